@@ -1,0 +1,130 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct CPU statement of the BFS kNN construction of
+arXiv 2509.19703 (GUMAP steps C0/C1 of Alg. 1, PartialBFS of Alg. 4 in
+Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1).  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
+it.  It shares no code with the GPU library and the GPU library never calls
+it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
+moves numpy arrays in and out.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, EINVAL, ERANGE, ENOMEM = 0, -1, -3, -4
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", src, "-o", tmp,
+                               "-lm", "-lpthread"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.oracle_bfs_dist.argtypes = [i32, vp, vp, i32, vp]
+        lib.oracle_knn_build.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, ctypes.c_int]
+        lib.oracle_knn_partial.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, ctypes.c_int]
+        lib.oracle_membership.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.c_int]
+        for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _csr(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    return rp, ci
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int):
+        super().__init__("oracle status %d" % status)
+        self.status = status
+
+
+def bfs_dist(g, s: int) -> np.ndarray:
+    """Hop distance from ``s`` to every vertex (-1 = unreachable)."""
+    rp, ci = _csr(g)
+    dist = np.empty(g.n, dtype=np.int32)
+    st = _load().oracle_bfs_dist(g.n, _ptr(rp), _ptr(ci), int(s), _ptr(dist))
+    if st:
+        raise OracleError(st)
+    return dist
+
+
+def knn_build(g, k: int, sources=None, hop_matrix: bool = False, threads: int | None = None):
+    """All-source (or listed-source) BFS + (hop, id) kNN.
+
+    Returns ``(ids int32[rows,k], hops uint8[rows,k], hop_matrix uint8[rows,n] or None)``.
+    """
+    rp, ci = _csr(g)
+    src = None if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    rows = g.n if src is None else int(src.shape[0])
+    ids = np.empty((rows, k), dtype=np.int32)
+    hops = np.empty((rows, k), dtype=np.uint8)
+    hm = np.empty((rows, g.n), dtype=np.uint8) if hop_matrix else None
+    st = _load().oracle_knn_build(g.n, _ptr(rp), _ptr(ci), int(k), _ptr(src), rows,
+                                  _ptr(ids), _ptr(hops), _ptr(hm), int(threads or default_threads()))
+    if st:
+        raise OracleError(st)
+    return ids, hops, hm
+
+
+def knn_partial(g, k: int, sources=None, threads: int | None = None):
+    """Truncated BFS kNN (PartialBFS).  Returns ``(ids, hops)``."""
+    rp, ci = _csr(g)
+    src = None if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    rows = g.n if src is None else int(src.shape[0])
+    ids = np.empty((rows, k), dtype=np.int32)
+    hops = np.empty((rows, k), dtype=np.uint8)
+    st = _load().oracle_knn_partial(g.n, _ptr(rp), _ptr(ci), int(k), _ptr(src), rows,
+                                    _ptr(ids), _ptr(hops), int(threads or default_threads()))
+    if st:
+        raise OracleError(st)
+    return ids, hops
+
+
+def membership(hops: np.ndarray, k: int | None = None, threads: int | None = None):
+    """FP64 rho/sigma bisection.  Returns ``(weights f32[rows,k], rho f32[rows], sigma f32[rows])``."""
+    hops = np.ascontiguousarray(hops, dtype=np.uint8)
+    rows, kk = hops.shape
+    k = kk if k is None else k
+    assert k == kk
+    w = np.empty((rows, k), dtype=np.float32)
+    rho = np.empty(rows, dtype=np.float32)
+    sigma = np.empty(rows, dtype=np.float32)
+    st = _load().oracle_membership(rows, int(k), _ptr(hops), _ptr(w), _ptr(rho), _ptr(sigma),
+                                   int(threads or default_threads()))
+    if st:
+        raise OracleError(st)
+    return w, rho, sigma

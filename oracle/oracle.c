@@ -1,0 +1,393 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU statement of what the GPU library
+ * computes.  Only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg may load it.  It shares no code, header, table or helper with the GPU
+ * path, and the GPU path never calls it.
+ *
+ * Contents (paper: arXiv 2509.19703, "Fast UMAP-based graph drawing"):
+ *   oracle_bfs_dist      one-source queue BFS hop distances
+ *                        (Sec. 3.1, Alg. 1, step C0: shortest paths of G)
+ *   oracle_knn_build     all-source hops + k nearest by (hop, id)
+ *                        (Sec. 3.1, Alg. 1, steps C0 and C1)
+ *   oracle_knn_partial   truncated BFS that stops at the level completing k
+ *                        other vertices (Sec. 3.3.1, Alg. 4 PartialBFS)
+ *   oracle_membership    UMAP fuzzy membership rho, sigma and weights in FP64
+ *                        (Sec. 2.1, high-dimensional similarity h_ij)
+ *
+ * Readings where the paper is silent or garbled (each is listed with its
+ * justification in the design notes):
+ *   - true hop distances: the source is at hop 0, its neighbours at hop 1;
+ *   - a kNN row lists k OTHER vertices (the source itself is excluded);
+ *   - ties at equal hop are broken by ascending vertex id (the paper breaks
+ *     them at random, which is not reproducible);
+ *   - a level is a set (a vertex enters a level once);
+ *   - unreachable vertices (the paper's "infinite" distance, Sec. 3.2) are
+ *     never neighbours; missing slots are padded with id -1 and hop 255;
+ *   - hop values are uint8, 255 meaning unreachable; a finite hop above 254
+ *     cannot be stored in a hop matrix (status -3);
+ *   - h_ij = exp(-(d_ij - rho_i) / sigma_i) (the printed sign is a typo) with
+ *     sigma_i solving sum_j h_ij = log2(k) over the row's valid entries, k the
+ *     requested neighbourhood size; rows with no root take the limits
+ *     described at oracle_membership.
+ *
+ * Threads: rows are independent; `nthreads` worker threads take rows from a
+ * shared counter.  This parallelism does not change any result.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ERANGE (-3)
+#define ORACLE_ENOMEM (-4)
+
+/* ------------------------------------------------------------------------
+ * One-source BFS (FIFO queue).  dist[v] = number of edges on a shortest
+ * path from s to v, or -1 if v is not reachable.  Repeated entries and
+ * self-loops in the adjacency are harmless: a vertex is labelled only the
+ * first time it is seen.
+ * ---------------------------------------------------------------------- */
+int oracle_bfs_dist(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                    int32_t s, int32_t *dist)
+{
+    if (n < 0 || s < 0 || s >= n) return ORACLE_EINVAL;
+    int32_t *queue = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!queue) return ORACLE_ENOMEM;
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    int32_t head = 0, tail = 0;
+    dist[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t w = col_idx[e];
+            if (dist[w] < 0) {
+                dist[w] = dist[u] + 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    free(queue);
+    return ORACLE_OK;
+}
+
+/* --------------------------------------------------------- thread pool -- */
+
+typedef struct {
+    int64_t next;          /* next row to take */
+    int64_t count;         /* rows in total */
+    pthread_mutex_t lock;
+    int status;            /* first non-OK status seen */
+    void *job;
+    int (*row_fn)(void *job, int64_t row, void *scratch);
+    size_t scratch_bytes;
+} pool_t;
+
+static void *pool_worker(void *arg)
+{
+    pool_t *p = (pool_t *)arg;
+    void *scratch = p->scratch_bytes ? calloc(1, p->scratch_bytes) : NULL;
+    if (p->scratch_bytes && !scratch) {
+        pthread_mutex_lock(&p->lock);
+        if (p->status == ORACLE_OK) p->status = ORACLE_ENOMEM;
+        pthread_mutex_unlock(&p->lock);
+        return NULL;
+    }
+    for (;;) {
+        pthread_mutex_lock(&p->lock);
+        int64_t row = p->next++;
+        pthread_mutex_unlock(&p->lock);
+        if (row >= p->count) break;
+        int st = p->row_fn(p->job, row, scratch);
+        if (st != ORACLE_OK) {
+            pthread_mutex_lock(&p->lock);
+            if (p->status == ORACLE_OK) p->status = st;
+            pthread_mutex_unlock(&p->lock);
+        }
+    }
+    free(scratch);
+    return NULL;
+}
+
+static int run_rows(int64_t count, int nthreads, void *job,
+                    int (*row_fn)(void *, int64_t, void *), size_t scratch_bytes)
+{
+    pool_t p;
+    p.next = 0;
+    p.count = count;
+    pthread_mutex_init(&p.lock, NULL);
+    p.status = ORACLE_OK;
+    p.job = job;
+    p.row_fn = row_fn;
+    p.scratch_bytes = scratch_bytes;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t)
+        if (pthread_create(&th[started], NULL, pool_worker, &p) == 0) ++started;
+    pool_worker(&p);
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&p.lock);
+    return p.status;
+}
+
+/* ------------------------------------------------------------ kNN build --
+ * Alg. 1 C0 then C1 for each requested source s:
+ *   1. dist = BFS hop distances from s;
+ *   2. the pairs (dist[v], v) with v != s and v reachable, sorted
+ *      lexicographically; the first min(k, count) of them form the row;
+ *   3. remaining slots are padded with (id -1, hop 255).
+ * If hop_matrix is not NULL, row r of it (n bytes) receives dist from
+ * sources[r] with 255 for unreachable; a finite distance above 254 makes the
+ * call fail with ORACLE_ERANGE.
+ * ---------------------------------------------------------------------- */
+
+typedef struct { int32_t hop, id; } pair_t;
+
+static int cmp_pair(const void *a, const void *b)
+{
+    const pair_t *x = (const pair_t *)a, *y = (const pair_t *)b;
+    if (x->hop != y->hop) return (x->hop > y->hop) - (x->hop < y->hop);
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr, *col_idx;
+    int32_t k;
+    const int32_t *sources;
+    int32_t *ids;
+    uint8_t *hops;
+    uint8_t *hop_matrix;
+} build_job;
+
+static int build_row(void *jp, int64_t r, void *scratch)
+{
+    build_job *j = (build_job *)jp;
+    int32_t n = j->n;
+    int32_t s = j->sources ? j->sources[r] : (int32_t)r;
+    int32_t *dist = (int32_t *)scratch;
+    pair_t *pairs = (pair_t *)(dist + n);
+    int st = oracle_bfs_dist(n, j->row_ptr, j->col_idx, s, dist);
+    if (st != ORACLE_OK) return st;
+    int32_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (v == s || dist[v] < 0) continue;
+        pairs[cnt].hop = dist[v];
+        pairs[cnt].id = v;
+        ++cnt;
+    }
+    qsort(pairs, (size_t)cnt, sizeof(pair_t), cmp_pair);
+    int32_t *ids = j->ids + r * (int64_t)j->k;
+    uint8_t *hops = j->hops + r * (int64_t)j->k;
+    for (int32_t i = 0; i < j->k; ++i) {
+        if (i < cnt) {
+            ids[i] = pairs[i].id;
+            hops[i] = (uint8_t)(pairs[i].hop > 254 ? 255 : pairs[i].hop);
+        } else {
+            ids[i] = -1;
+            hops[i] = 255;
+        }
+    }
+    if (j->hop_matrix) {
+        uint8_t *row = j->hop_matrix + r * (int64_t)n;
+        for (int32_t v = 0; v < n; ++v) {
+            if (dist[v] < 0) row[v] = 255;
+            else if (dist[v] > 254) return ORACLE_ERANGE;
+            else row[v] = (uint8_t)dist[v];
+        }
+    }
+    return ORACLE_OK;
+}
+
+int oracle_knn_build(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
+                     const int32_t *sources, int32_t n_sources, int32_t *ids, uint8_t *hops,
+                     uint8_t *hop_matrix, int nthreads)
+{
+    if (n < 0 || k < 1 || !ids || !hops) return ORACLE_EINVAL;
+    int64_t rows = sources ? n_sources : n;
+    if (rows < 0) return ORACLE_EINVAL;
+    if (sources)
+        for (int64_t r = 0; r < rows; ++r)
+            if (sources[r] < 0 || sources[r] >= n) return ORACLE_EINVAL;
+    build_job j = {n, row_ptr, col_idx, k, sources, ids, hops, hop_matrix};
+    size_t scratch = (size_t)(n > 0 ? n : 1) * (sizeof(int32_t) + sizeof(pair_t));
+    return run_rows(rows, nthreads, &j, build_row, scratch);
+}
+
+/* ---------------------------------------------------------- PartialBFS --
+ * Alg. 4, per source v: BFS one level at a time.  Level h+1 is the set of
+ * vertices adjacent to level h that no earlier level contains.  Let c be the
+ * number of other vertices already taken.  If c + |level| >= k, the level is
+ * sorted by id and its first k - c members are taken, and the search stops;
+ * otherwise the whole level is taken (in id order) and the search goes on.
+ * The search also stops when a level comes out empty (the component of v has
+ * fewer than k + 1 vertices); the row is then padded.
+ * Each row is therefore sorted by (hop, id), hops 1..h.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr, *col_idx;
+    int32_t k;
+    const int32_t *sources;
+    int32_t *ids;
+    uint8_t *hops;
+} partial_job;
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static int partial_row(void *jp, int64_t r, void *scratch)
+{
+    partial_job *j = (partial_job *)jp;
+    int32_t n = j->n, k = j->k;
+    int32_t v = j->sources ? j->sources[r] : (int32_t)r;
+    int32_t *seen = (int32_t *)scratch;   /* n entries: 0 = not seen, else level + 1 */
+    int32_t *cur = seen + n;              /* current level   */
+    int32_t *nxt = cur + n;               /* next level      */
+    int32_t *touched = nxt + n;           /* vertices marked, cleared again at the end */
+    int32_t ntouched = 0;
+    int32_t *ids = j->ids + r * (int64_t)k;
+    uint8_t *hops = j->hops + r * (int64_t)k;
+
+    seen[v] = 1;
+    touched[ntouched++] = v;
+    int32_t ncur = 1, taken = 0, h = 0;
+    cur[0] = v;
+    while (taken < k && ncur > 0) {
+        ++h;
+        int32_t nnext = 0;
+        for (int32_t i = 0; i < ncur; ++i) {
+            int32_t u = cur[i];
+            for (int32_t e = j->row_ptr[u]; e < j->row_ptr[u + 1]; ++e) {
+                int32_t w = j->col_idx[e];
+                if (seen[w] == 0) {
+                    seen[w] = h + 1;
+                    touched[ntouched++] = w;
+                    nxt[nnext++] = w;
+                }
+            }
+        }
+        qsort(nxt, (size_t)nnext, sizeof(int32_t), cmp_i32);
+        int32_t take = nnext < k - taken ? nnext : k - taken;
+        for (int32_t i = 0; i < take; ++i) {
+            ids[taken + i] = nxt[i];
+            hops[taken + i] = (uint8_t)(h > 254 ? 255 : h);
+        }
+        taken += take;
+        memcpy(cur, nxt, (size_t)nnext * sizeof(int32_t));
+        ncur = nnext;
+    }
+    for (int32_t i = taken; i < k; ++i) {
+        ids[i] = -1;
+        hops[i] = 255;
+    }
+    for (int32_t i = 0; i < ntouched; ++i) seen[touched[i]] = 0;
+    return ORACLE_OK;
+}
+
+int oracle_knn_partial(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t k,
+                       const int32_t *sources, int32_t n_sources, int32_t *ids, uint8_t *hops,
+                       int nthreads)
+{
+    if (n < 0 || k < 1 || !ids || !hops) return ORACLE_EINVAL;
+    int64_t rows = sources ? n_sources : n;
+    if (rows < 0) return ORACLE_EINVAL;
+    if (sources)
+        for (int64_t r = 0; r < rows; ++r)
+            if (sources[r] < 0 || sources[r] >= n) return ORACLE_EINVAL;
+    partial_job j = {n, row_ptr, col_idx, k, sources, ids, hops};
+    size_t scratch = (size_t)(n > 0 ? n : 1) * 4 * sizeof(int32_t);
+    return run_rows(rows, nthreads, &j, partial_row, scratch);
+}
+
+/* ---------------------------------------------------------- membership --
+ * Sec. 2.1: h_j = exp(-(d_j - rho) / sigma) over the row's K valid entries
+ * (hop != 255), rho = the hop of the nearest neighbour (the row's first
+ * entry), sigma chosen so that f(sigma) = sum_j exp(-(d_j - rho)/sigma)
+ * equals T = log2(k).  f rises from c0 = #{j : d_j = rho} (sigma -> 0+) to K
+ * (sigma -> infinity), so:
+ *   K = 0          rho = 0, sigma = 0, every weight 0;
+ *   c0 >= T        no root; sigma -> 0+ limit: sigma = 0, weight 1 where
+ *                  d_j = rho and 0 elsewhere;
+ *   K <= T         no root (or a root at infinity): sigma = +inf, weights 1;
+ *   otherwise      bisection on sigma in double precision: bracket [0, hi]
+ *                  with hi doubled from 1 until f(hi) >= T, then halve the
+ *                  bracket (f(mid) < T moves lo up, else hi down) until mid
+ *                  equals an end point or 2000 steps; sigma = hi.
+ * Padding slots get weight 0.  rho and sigma are returned as float, the
+ * weights as float(exp(-(d_j - rho)/sigma)) computed in double.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t k;
+    const uint8_t *hops;
+    float *weights, *rho, *sigma;
+} memb_job;
+
+static double memb_f(const uint8_t *h, int32_t K, double rho, double sigma)
+{
+    double s = 0.0;
+    for (int32_t j = 0; j < K; ++j) s += exp(-((double)h[j] - rho) / sigma);
+    return s;
+}
+
+static int memb_row(void *jp, int64_t r, void *scratch)
+{
+    (void)scratch;
+    memb_job *j = (memb_job *)jp;
+    int32_t k = j->k;
+    const uint8_t *h = j->hops + r * (int64_t)k;
+    float *w = j->weights + r * (int64_t)k;
+    int32_t K = 0;
+    while (K < k && h[K] != 255) ++K;
+    double rho = 0.0, sigma = 0.0;
+    if (K == 0) {
+        for (int32_t i = 0; i < k; ++i) w[i] = 0.0f;
+    } else {
+        rho = (double)h[0];
+        double T = log2((double)k);
+        int32_t c0 = 0;
+        for (int32_t i = 0; i < K; ++i) c0 += (h[i] == h[0]);
+        if ((double)c0 >= T) {
+            sigma = 0.0;
+            for (int32_t i = 0; i < K; ++i) w[i] = (h[i] == h[0]) ? 1.0f : 0.0f;
+        } else if ((double)K <= T) {
+            sigma = INFINITY;
+            for (int32_t i = 0; i < K; ++i) w[i] = 1.0f;
+        } else {
+            double lo = 0.0, hi = 1.0;
+            while (memb_f(h, K, rho, hi) < T) hi *= 2.0;
+            for (int it = 0; it < 2000; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid == lo || mid == hi) break;
+                if (memb_f(h, K, rho, mid) < T) lo = mid;
+                else hi = mid;
+            }
+            sigma = hi;
+            for (int32_t i = 0; i < K; ++i) w[i] = (float)exp(-((double)h[i] - rho) / sigma);
+        }
+        for (int32_t i = K; i < k; ++i) w[i] = 0.0f;
+    }
+    if (j->rho) j->rho[r] = (float)rho;
+    if (j->sigma) j->sigma[r] = (float)sigma;
+    return ORACLE_OK;
+}
+
+int oracle_membership(int64_t rows, int32_t k, const uint8_t *hops, float *weights,
+                      float *rho, float *sigma, int nthreads)
+{
+    if (rows < 0 || k < 1 || !hops || !weights) return ORACLE_EINVAL;
+    memb_job j = {k, hops, weights, rho, sigma};
+    return run_rows(rows, nthreads, &j, memb_row, 0);
+}

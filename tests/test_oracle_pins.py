@@ -1,0 +1,426 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Every check here is independent of the oracle's own code path: Floyd-Warshall
+and networkx for hop distances, closed forms for structured graphs, the BFS
+certificate, a separate statement of Alg. 4 for the truncated search, the
+companion-matrix roots of the membership polynomial, closed-form bandwidths,
+and a hand-worked example under tests/golden/.
+"""
+import math
+import os
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ helpers
+
+def floyd_warshall(g):
+    n = g.n
+    INF = 10**9
+    d = np.full((n, n), INF, dtype=np.int64)
+    np.fill_diagonal(d, 0)
+    for v in range(n):
+        for w in g.neighbors(v):
+            if w != v:
+                d[v, w] = 1
+    for m in range(n):
+        d = np.minimum(d, d[:, m:m + 1] + d[m:m + 1, :])
+    return np.where(d >= INF, 255, d).astype(np.int64)
+
+
+def to_nx(g):
+    h = nx.Graph()
+    h.add_nodes_from(range(g.n))
+    for v in range(g.n):
+        for w in g.neighbors(v):
+            if w != v:
+                h.add_edge(v, int(w))
+    return h
+
+
+def knn_from_dist(dist_row, s, k):
+    """k smallest (hop, id), v != s, reachable; padded -- from a distance row
+    obtained independently of the oracle."""
+    cand = [(int(dist_row[v]), v) for v in range(len(dist_row)) if v != s and 0 <= dist_row[v] < 255]
+    cand.sort()
+    ids = [v for _, v in cand[:k]] + [-1] * max(0, k - len(cand))
+    hops = [h for h, _ in cand[:k]] + [255] * max(0, k - len(cand))
+    return np.array(ids, dtype=np.int32), np.array(hops, dtype=np.uint8)
+
+
+def small_graph_family(count, seed0=11):
+    """Seeded small graphs: sparse/dense/disconnected/isolated, n <= 40."""
+    out = []
+    for i in range(count):
+        u = G.uniform(G.mix_seed(seed0, i), 2)
+        n = 1 + int(u[0] * 40)
+        p = [0.02, 0.05, 0.1, 0.2, 0.5, 0.9][i % 6]
+        out.append(G.tiny_random(n, p, G.mix_seed(seed0 + 1, i)))
+    return out
+
+
+# ------------------------------------------------------------ P-APSP pins
+
+def test_apsp_matches_floyd_warshall_and_networkx():
+    graphs = small_graph_family(1000)
+    graphs += [G.path(1), G.empty(5), G.star(7), G.cycle(9), G.complete(6)]
+    checked_nx = 0
+    for g in graphs:
+        ids, hops, hm = O.knn_build(g, 3, hop_matrix=True, threads=1)
+        fw = floyd_warshall(g)
+        assert np.array_equal(hm.astype(np.int64), fw), g.name
+        if checked_nx < 150:
+            ref = dict(nx.all_pairs_shortest_path_length(to_nx(g)))
+            for s in range(g.n):
+                row = np.full(g.n, 255)
+                for t, d in ref[s].items():
+                    row[t] = d
+                assert np.array_equal(hm[s].astype(np.int64), row)
+            checked_nx += 1
+
+
+def test_apsp_symmetric_on_random_graphs():
+    for i in range(20):
+        g = G.er(60, 0.05, 900 + i)
+        _, _, hm = O.knn_build(g, 5, hop_matrix=True)
+        assert np.array_equal(hm, hm.T)
+
+
+# ---------------------------------------------------------- P-closed pins
+
+def test_closed_forms_hops():
+    g = G.grid_2d(32, 32)
+    _, _, hm = O.knn_build(g, 15, hop_matrix=True)
+    r, c = np.divmod(np.arange(1024), 32)
+    expect = np.abs(r[:, None] - r[None, :]) + np.abs(c[:, None] - c[None, :])
+    assert np.array_equal(hm.astype(np.int64), expect)
+
+    g = G.complete(20)
+    _, _, hm = O.knn_build(g, 5, hop_matrix=True)
+    assert np.array_equal(hm.astype(np.int64), 1 - np.eye(20, dtype=np.int64))
+
+    n = 200
+    _, _, hm = O.knn_build(G.path(n), 5, hop_matrix=True)
+    i = np.arange(n)
+    assert np.array_equal(hm.astype(np.int64), np.abs(i[:, None] - i[None, :]))
+
+    n = 101
+    _, _, hm = O.knn_build(G.cycle(n), 5, hop_matrix=True)
+    dd = np.abs(i[:n, None] - i[None, :n])
+    assert np.array_equal(hm.astype(np.int64), np.minimum(dd, n - dd))
+
+    _, _, hm = O.knn_build(G.star(30), 5, hop_matrix=True)
+    expect = np.full((31, 31), 2)
+    expect[0, :] = 1
+    expect[:, 0] = 1
+    np.fill_diagonal(expect, 0)
+    assert np.array_equal(hm.astype(np.int64), expect)
+
+    d = 7
+    _, _, hm = O.knn_build(G.hypercube(d), 5, hop_matrix=True)
+    v = np.arange(1 << d)
+    x = v[:, None] ^ v[None, :]
+    pc = np.zeros_like(x)
+    for b in range(d):
+        pc += (x >> b) & 1
+    assert np.array_equal(hm.astype(np.int64), pc)
+
+    a, b = 6, 9
+    _, _, hm = O.knn_build(G.complete_bipartite(a, b), 4, hop_matrix=True)
+    side = np.arange(a + b) >= a
+    expect = np.where(side[:, None] == side[None, :], 2, 1)
+    np.fill_diagonal(expect, 0)
+    assert np.array_equal(hm.astype(np.int64), expect)
+
+
+def test_hop_range_limit():
+    """A finite hop above 254 cannot be stored in the uint8 hop matrix."""
+    _, _, hm = O.knn_build(G.path(255), 3, hop_matrix=True)
+    assert hm.max() == 254
+    with pytest.raises(O.OracleError) as e:
+        O.knn_build(G.path(256), 3, hop_matrix=True)
+    assert e.value.status == O.ERANGE
+    ids, hops, _ = O.knn_build(G.path(400), 3)          # kNN alone is fine
+    assert hops.max() <= 3
+
+
+# ------------------------------------------------------------ P-cert pins
+
+def bfs_certificate(g, s, dist):
+    """Graph500-style check that ``dist`` are BFS hop distances from s."""
+    assert dist[s] == 0
+    src = np.repeat(np.arange(g.n), g.degrees())
+    dst = g.col_idx
+    ds, dd = dist[src], dist[dst]
+    reached_s, reached_d = ds >= 0, dd >= 0
+    assert np.all(reached_s == reached_d), "edge joins reached and unreached"
+    both = reached_s & reached_d
+    assert np.all(np.abs(ds[both] - dd[both]) <= 1)
+    # every reached v != s has a neighbour one hop closer
+    has_parent = np.zeros(g.n, dtype=bool)
+    has_parent[src[both & (dd == ds - 1)]] = True
+    reached = dist >= 0
+    reached[s] = False
+    assert np.all(has_parent[reached])
+
+
+def test_bfs_certificate_on_generated_families():
+    gs = [G.ba(3000, 4, 5), G.rgg(3000, 8, 6), G.sbm(3000, 10, 7), G.er(2000, 0.004, 8),
+          G.grid_2d(20, 50)]
+    for g in gs:
+        for s in [0, g.n // 3, g.n - 1]:
+            bfs_certificate(g, s, O.bfs_dist(g, s))
+
+
+# ------------------------------------------------------------- P-knn pins
+
+def test_knn_grid_closed_form():
+    g = G.grid_2d(32, 32)
+    ids, hops, _ = O.knn_build(g, 15)
+    pids, phops = O.knn_partial(g, 15)
+    for r in range(32):
+        for c in range(32):
+            s = 32 * r + c
+            rr, cc = np.divmod(np.arange(1024), 32)
+            dist = np.abs(rr - r) + np.abs(cc - c)
+            e_ids, e_hops = knn_from_dist(dist, s, 15)
+            assert np.array_equal(ids[s], e_ids) and np.array_equal(hops[s], e_hops)
+            assert np.array_equal(pids[s], e_ids) and np.array_equal(phops[s], e_hops)
+    # interior row: 4 at hop 1, 8 at hop 2, then the three smallest hop-3 ids
+    r, c = 10, 17
+    s = 32 * r + c
+    assert list(hops[s]) == [1] * 4 + [2] * 8 + [3] * 3
+    assert list(ids[s][12:]) == [32 * (r - 3) + c, 32 * (r - 2) + c - 1, 32 * (r - 2) + c + 1]
+    # boundary row (0, c): the radius-3 ball has exactly 15 other vertices
+    s = 9
+    assert list(hops[s]) == [1] * 3 + [2] * 5 + [3] * 7
+
+
+def test_knn_star_complete_dense():
+    g = G.star(40)
+    ids, hops, _ = O.knn_build(g, 15)
+    assert list(ids[0]) == list(range(1, 16)) and list(hops[0]) == [1] * 15
+    assert list(ids[7]) == [0] + [1, 2, 3, 4, 5, 6] + list(range(8, 16)) and list(hops[7]) == [1] + [2] * 14
+    ids, hops, _ = O.knn_build(G.complete(30), 15)
+    for v in (0, 13, 29):
+        assert list(ids[v]) == [u for u in range(30) if u != v][:15]
+    g = G.er(2048, 1.0 / 8.0, 77)         # diameter 2: kNN = 15 smallest neighbours
+    ids, hops, _ = O.knn_build(g, 15, sources=np.arange(0, 2048, 97))
+    for r, s in enumerate(range(0, 2048, 97)):
+        assert list(ids[r]) == list(g.neighbors(s)[:15]) and list(hops[r]) == [1] * 15
+
+
+def test_knn_invariants_against_networkx():
+    """Sorted, distinct, not self, hops are true distances, complete below the
+    last level, minimal ids at the last level -- distances from networkx."""
+    for i in range(40):
+        g = G.tiny_random(30 + i, [0.04, 0.08, 0.15][i % 3], 3000 + i)
+        k = [1, 2, 5, 15, 40][i % 5]
+        ids, hops, _ = O.knn_build(g, k)
+        pids, phops = O.knn_partial(g, k)
+        assert np.array_equal(ids, pids) and np.array_equal(hops, phops)
+        ref = dict(nx.all_pairs_shortest_path_length(to_nx(g)))
+        for s in range(g.n):
+            row = np.full(g.n, 255)
+            for t, d in ref[s].items():
+                row[t] = d
+            e_ids, e_hops = knn_from_dist(row, s, k)
+            assert np.array_equal(ids[s], e_ids) and np.array_equal(hops[s], e_hops)
+            valid = ids[s] >= 0
+            vi = ids[s][valid]
+            assert s not in vi and len(set(vi)) == len(vi)
+            assert all(row[v] == h for v, h in zip(vi, hops[s][valid]))
+            if valid.all():
+                hl = hops[s][-1]
+                inside = set(np.nonzero((row < hl) & (np.arange(g.n) != s))[0])
+                assert inside <= set(vi)
+                chosen_last = [v for v, h in zip(vi, hops[s]) if h == hl]
+                others = [v for v in np.nonzero(row == hl)[0] if v not in chosen_last]
+                assert not others or min(others) > max(chosen_last)
+
+
+# ------------------------------------------------- P-eq and P-alg4 pins
+
+def partial_bfs_alg4(g, k, v):
+    """Alg. 4 (Sec. 3.3.1) restated with the readings: source at distance 0,
+    a level is a set, stop when the frontier empties.  Tie order is whatever
+    adjacency order gives; only the hop multiset is compared."""
+    visited, tovisit, dist, S = [], [v], 0, {}
+    while len(visited) <= k and tovisit:
+        newvisit = []
+        for u in tovisit:
+            visited.append(u)
+            S[u] = dist
+            if len(visited) > k:
+                break
+            for w in g.neighbors(u):
+                w = int(w)
+                if w not in visited and w not in tovisit and w not in newvisit:
+                    newvisit.append(w)
+        tovisit = newvisit
+        dist += 1
+    return sorted(d for u, d in S.items() if u != v)
+
+
+def test_partial_equals_build_and_alg4_multisets():
+    gs = [G.ba(800, 3, 21), G.rgg(800, 6, 22), G.sbm(800, 6, 23), G.grid_2d(15, 20),
+          G.star(25), G.disjoint_union([G.path(4), G.cycle(7), G.complete(3), G.empty(2)])]
+    for g in gs:
+        for k in (1, 4, 15, 30):
+            ids, hops, _ = O.knn_build(g, k)
+            pids, phops = O.knn_partial(g, k)
+            assert np.array_equal(ids, pids) and np.array_equal(hops, phops)
+            for v in range(0, g.n, max(1, g.n // 60)):
+                ms = partial_bfs_alg4(g, k, v)
+                got = sorted(int(h) for h in phops[v] if h != 255)
+                assert got == ms, (g.name, k, v)
+
+
+def test_partial_on_dirty_input_equals_clean():
+    g = G.ba(500, 3, 41)
+    d = G.dirty(g, 42)
+    for k in (3, 15):
+        a = O.knn_partial(g, k)
+        b = O.knn_partial(d, k)
+        c = O.knn_build(d, k)[:2]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+
+
+def test_padding_small_components_and_isolated():
+    g = G.disjoint_union([G.path(3), G.empty(1), G.complete(5)])
+    ids, hops, _ = O.knn_build(g, 6)
+    assert list(ids[0]) == [1, 2, -1, -1, -1, -1] and list(hops[0]) == [1, 2, 255, 255, 255, 255]
+    assert list(ids[3]) == [-1] * 6 and list(hops[3]) == [255] * 6
+    assert list(ids[4]) == [5, 6, 7, 8, -1, -1]
+    pids, phops = O.knn_partial(g, 6)
+    assert np.array_equal(ids, pids) and np.array_equal(hops, phops)
+    ids, hops, _ = O.knn_build(G.path(1), 4)
+    assert list(ids[0]) == [-1] * 4
+
+
+# ------------------------------------------------------- membership pins
+
+def _poly_root(row, k):
+    """Root in (0, 1) of sum_h c_h x^h = log2 k (companion-matrix eigenvalues)."""
+    h = np.array([x for x in row if x != 255], dtype=np.int64)
+    d = h - h[0]
+    c = np.bincount(d).astype(np.float64)
+    coeffs = c[::-1].copy()
+    coeffs[-1] -= math.log2(k)
+    roots = np.roots(coeffs)
+    real = [r.real for r in roots if abs(r.imag) < 1e-9 and 0 < r.real < 1]
+    assert len(real) == 1
+    return real[0]
+
+
+def test_membership_matches_polynomial_roots():
+    rng = np.random.default_rng(5)
+    rows = []
+    for k in (5, 10, 15, 30, 100, 254):
+        for _ in range(60):
+            K = int(rng.integers(1, k + 1))
+            inc = rng.integers(0, 3, size=K)
+            inc[0] = rng.integers(1, 3)
+            h = np.minimum(np.cumsum(inc), 250).astype(np.uint8)
+            rows.append((k, np.concatenate([h, np.full(k - K, 255, np.uint8)])))
+    checked = 0
+    for k, row in rows:
+        w, rho, sigma = O.membership(row[None, :], k)
+        K = int((row != 255).sum())
+        T = math.log2(k)
+        c0 = int((row[:K] == row[0]).sum())
+        assert rho[0] == float(row[0])
+        if c0 >= T:
+            assert sigma[0] == 0.0
+            assert list(w[0][:K]) == [1.0 if x == row[0] else 0.0 for x in row[:K]]
+        elif K <= T:
+            assert math.isinf(sigma[0]) and np.all(w[0][:K] == 1.0)
+        else:
+            x = _poly_root(row, k)
+            assert abs(math.exp(-1.0 / float(sigma[0])) - x) <= 1e-6 * x + 1e-12
+            d = row[:K].astype(np.float64) - row[0]
+            ref = x ** d
+            assert np.all(np.abs(w[0][:K] - ref) <= 1e-6 * ref + 1e-30)
+            assert w[0][0] == 1.0
+            # sum equals log2 k to double precision before the float cast
+            sig64 = -1.0 / math.log(x)
+            assert abs(np.exp(-d / sig64).sum() - T) < 1e-12
+            checked += 1
+        assert np.all(w[0][K:] == 0.0)
+    assert checked > 50
+
+
+def test_membership_closed_form_bandwidths():
+    T = math.log2(15)
+    g = G.grid_2d(32, 32)
+    ids, hops, _ = O.knn_build(g, 15)
+    w, rho, sigma = O.membership(hops)
+    xb = (-5 + math.sqrt(25 + 28 * (T - 3))) / 14          # 3 + 5x + 7x^2 = log2 15
+    s = 9                                                 # boundary row (0, 9)
+    assert abs(sigma[s] - (-1 / math.log(xb))) < 1e-6
+    assert np.allclose(w[s], [1] * 3 + [xb] * 5 + [xb * xb] * 7, rtol=1e-6)
+    corner = np.roots([1, 5, 4, 3, 2 - T])              # 2 + 3x + 4x^2 + 5x^3 + x^4
+    xc = [r.real for r in corner if abs(r.imag) < 1e-12 and 0 < r.real < 1][0]
+    assert abs(xc - 0.367225) < 1e-6
+    assert abs(math.exp(-1 / sigma[0]) - xc) < 1e-6
+    interior = 32 * 10 + 17                              # 4 at hop 1 >= log2 15: degenerate
+    assert sigma[interior] == 0 and list(w[interior]) == [1.0] * 4 + [0.0] * 11
+    ids, hops, _ = O.knn_build(G.star(40), 15)           # leaf: 1 + 14x = log2 15
+    w, rho, sigma = O.membership(hops)
+    xs = (T - 1) / 14
+    assert abs(sigma[5] - (-1 / math.log(xs))) < 1e-6
+    assert sigma[0] == 0 and np.all(w[0] == 1.0)           # hub: 15 at hop 1
+    # path endpoint: geometric series (1 - x^15)/(1 - x) = log2 15
+    ids, hops, _ = O.knn_build(G.path(40), 15)
+    w, rho, sigma = O.membership(hops)
+    x = math.exp(-1 / float(sigma[0]))
+    assert abs((1 - x**15) / (1 - x) - T) < 1e-5
+
+
+def test_membership_degenerate_and_empty_rows():
+    rows = np.array([[255] * 4, [1, 1, 2, 2], [1, 2, 255, 255], [3, 3, 3, 3]], dtype=np.uint8)
+    w, rho, sigma = O.membership(rows)
+    assert list(w[0]) == [0] * 4 and rho[0] == 0 and sigma[0] == 0
+    assert list(w[1]) == [1, 1, 0, 0] and sigma[1] == 0              # c0 = 2 >= log2 4
+    assert list(w[2]) == [1, 1, 0, 0] and math.isinf(sigma[2])        # K = 2 <= 2
+    assert list(w[3]) == [1, 1, 1, 1] and rho[3] == 3 and sigma[3] == 0
+
+
+# ------------------------------------------------------------ golden pin
+
+def _golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *rest = line.split()
+            vals[key] = [float(x) for x in rest]
+    return vals
+
+
+def test_hand_worked_example():
+    gv = _golden("hand_worked_7v.txt")
+    e = np.array(gv["edges"], dtype=np.int64).reshape(-1, 2)
+    g = G.from_edges(7, e)
+    s = int(gv["source"][0])
+    for k in (3, 4, 5, 8):
+        ids, hops, _ = O.knn_build(g, k, sources=[s])
+        pids, phops = O.knn_partial(g, k, sources=[s])
+        assert list(ids[0]) == [int(x) for x in gv["k%d_ids" % k]]
+        assert list(hops[0]) == [int(x) for x in gv["k%d_hops" % k]]
+        assert np.array_equal(ids, pids) and np.array_equal(hops, phops)
+        if "k%d_sigma" % k in gv:
+            w, rho, sigma = O.membership(hops, k)
+            assert rho[0] == 1.0
+            assert abs(sigma[0] - gv["k%d_sigma" % k][0]) <= 1e-6 * max(1.0, gv["k%d_sigma" % k][0])
+            assert np.allclose(w[0], gv["k%d_weights" % k], rtol=1e-6, atol=0)
