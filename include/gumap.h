@@ -1,0 +1,227 @@
+/*
+ * gumap -- BFS-based graph-theoretic kNN construction of the GUMAP family
+ * (arXiv 2509.19703) on one AMD MI355X (gfx950).
+ *
+ * What it computes (paper sections):
+ *   - all-source BFS hop distances of an undirected unweighted graph
+ *     (Sec. 3.1, Alg. 1 step C0, "AllPairsShortestPath");
+ *   - the kNN graph of those distances (Alg. 1 step C1), each row the k
+ *     nearest OTHER vertices ordered by (hop, vertex id);
+ *   - the truncated partial BFS that stops once k other vertices are
+ *     reached (Sec. 3.3.1, Alg. 4 "PartialBFS"), whose rows are identical
+ *     to those of the full construction under the (hop, id) order;
+ *   - the UMAP fuzzy-membership weights of a kNN row (Sec. 2.1):
+ *     w_j = exp(-(d_j - rho) / sigma), rho = hop of the nearest neighbour,
+ *     sigma solving sum_j w_j = log2(k).
+ *
+ * Conventions shared by every call
+ *   - Graphs are CSR with int32 row_ptr[n+1] and col_idx[nnz], both in
+ *     device memory.  The graph is read as the undirected edge set
+ *     {u, col_idx[e]}: repeated entries and self-loops are ignored and rows
+ *     may be in any order unless the caller sets GUMAP_CSR_SORTED.  The
+ *     caller guarantees a well-formed, symmetric CSR unless it sets
+ *     GUMAP_VALIDATE, in which case a malformed one returns GUMAP_EGRAPH.
+ *   - Output rows are k entries wide, row-major, sorted by (hop, id)
+ *     ascending; a row with fewer than k reachable other vertices is
+ *     padded with id -1, hop 255 and weight 0.
+ *   - Hops are uint8; 255 means unreachable (the paper's "infinite"
+ *     distance for disconnected pairs, Sec. 3.2).
+ *   - Pointers to arrays are device pointers owned by the caller; the
+ *     library owns its scratch memory (cached per device, grow-only).
+ *   - Calls are host-synchronous: they return after `stream` has finished
+ *     the work (0 selects the null stream).  Calls from several host
+ *     threads are serialised.
+ *   - Every call returns a status code; on failure gumap_last_error() holds
+ *     a message for the calling thread.
+ */
+#ifndef GUMAP_H
+#define GUMAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define GUMAP_OK 0
+#define GUMAP_PENDING 1      /* served job still running (gumap_poll only) */
+#define GUMAP_EINVAL (-1)    /* bad argument: null pointer, n < 0, k outside [1, 254], bad source id */
+#define GUMAP_EGRAPH (-2)    /* GUMAP_VALIDATE: malformed or asymmetric CSR */
+#define GUMAP_ERANGE (-3)    /* hop_matrix requested and a finite hop exceeds 254 */
+#define GUMAP_ENOMEM (-4)    /* device or host allocation failed */
+#define GUMAP_EDEVICE (-5)   /* HIP runtime error */
+#define GUMAP_E2BIG (-6)     /* served job larger than the server's memory budget */
+#define GUMAP_ENOTFOUND (-7) /* unknown or released ticket */
+
+/* Graph flags. */
+#define GUMAP_CSR_SORTED 1u  /* caller asserts: rows sorted ascending, no repeats, no self-loops */
+#define GUMAP_VALIDATE 2u    /* check the CSR on the device; malformed -> GUMAP_EGRAPH */
+
+#define GUMAP_MAX_K 254
+
+typedef struct gumap_graph {
+    int32_t n;              /* vertices, >= 0 */
+    int32_t nnz;            /* col_idx entries, >= 0 */
+    const int32_t *row_ptr; /* device, n + 1 entries; row_ptr[0] = 0, row_ptr[n] = nnz */
+    const int32_t *col_idx; /* device, nnz entries in [0, n) */
+    uint32_t flags;         /* GUMAP_CSR_SORTED | GUMAP_VALIDATE */
+} gumap_graph;
+
+/*
+ * GUMAP steps C0 + C1 (Sec. 3.1, Alg. 1): BFS hop distances from each source
+ * and the (hop, id)-ordered k nearest other vertices of each source.
+ *   sources    device int32[n_sources] vertex ids, or NULL for all n vertices
+ *              in order (n_sources is then ignored).  Repeats are allowed.
+ *   nbr_ids    device int32[rows * k], rows = n_sources (or n)
+ *   nbr_hops   device uint8[rows * k]
+ *   hop_matrix device uint8[rows * n] or NULL; row r receives the hop from
+ *              source r to every vertex (0 at the source, 255 unreachable).
+ * Errors: GUMAP_EINVAL (arguments, a source id outside [0, n)),
+ *         GUMAP_EGRAPH, GUMAP_ERANGE (only with hop_matrix), GUMAP_ENOMEM,
+ *         GUMAP_EDEVICE.  On error the outputs are unspecified.
+ */
+int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
+                    int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream);
+
+/*
+ * SL-/SSSL-GUMAP steps C0 + C1 (Sec. 3.3.1, Alg. 4 PartialBFS): for every
+ * vertex v, a BFS that stops at the level completing k other vertices; the
+ * row holds all earlier levels and the smallest ids of that last level.
+ * Rows are identical to gumap_knn_build's for sources = all vertices.
+ *   nbr_ids  device int32[n * k];  nbr_hops device uint8[n * k]
+ * Errors: GUMAP_EINVAL, GUMAP_EGRAPH, GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_knn_partial(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                      hipStream_t stream);
+
+/*
+ * UMAP fuzzy membership of kNN rows (Sec. 2.1): per row with K valid
+ * entries (hop != 255) sorted ascending, rho = the first hop and sigma
+ * solves sum_j exp(-(h_j - rho)/sigma) = log2(k), k the row width.
+ * Rows without a root take the limits: K = 0 -> rho = sigma = 0, weights 0;
+ * #{h_j = rho} >= log2 k -> sigma = 0, weight 1 at h_j = rho and 0 beyond;
+ * K <= log2 k -> sigma = +inf, weights 1.  The root is found in double
+ * precision; weights, rho and sigma are written as float.
+ *   nbr_hops device uint8[rows * k] (as written by the kNN calls)
+ *   weights  device float[rows * k];  rho, sigma device float[rows] or NULL
+ * Errors: GUMAP_EINVAL, GUMAP_EDEVICE.
+ */
+int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *weights, float *rho,
+                     float *sigma, hipStream_t stream);
+
+/*
+ * Many graphs at once (partial BFS + membership fused, one persistent
+ * launch over all vertices of all graphs).
+ * Packing: graph i has n_i = vtx_offset[i+1] - vtx_offset[i] vertices and
+ * its own local CSR: row_ptr[vtx_offset[i] + i .. vtx_offset[i+1] + i]
+ * (n_i + 1 entries, starting at 0) and col_idx[edge_offset[i] ..
+ * edge_offset[i+1]) holding local ids in [0, n_i).  Output row of vertex v of
+ * graph i is vtx_offset[i] + v; ids in it are local to graph i.
+ */
+typedef struct gumap_batch {
+    int32_t n_graphs;
+    int64_t total_vertices;     /* vtx_offset[n_graphs] (host copy) */
+    int64_t total_nnz;          /* edge_offset[n_graphs] (host copy) */
+    const int64_t *vtx_offset;  /* device, n_graphs + 1 */
+    const int64_t *edge_offset; /* device, n_graphs + 1 */
+    const int32_t *row_ptr;     /* device, total_vertices + n_graphs */
+    const int32_t *col_idx;     /* device, total_nnz */
+    uint32_t flags;             /* GUMAP_CSR_SORTED | GUMAP_VALIDATE */
+} gumap_batch;
+
+/*
+ * Rows of every graph of the batch: nbr_ids/nbr_hops as gumap_knn_partial,
+ * weights/rho/sigma as gumap_membership (weights, rho, sigma may be NULL to
+ * skip membership).  All outputs are device arrays indexed by packed row.
+ * Errors: GUMAP_EINVAL, GUMAP_EGRAPH, GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_knn_partial_batch(const gumap_batch *b, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                            float *weights, float *rho, float *sigma, hipStream_t stream);
+
+/*
+ * Captured form of gumap_knn_partial_batch for repeated calls on the same
+ * packed batch and output buffers: the launch sequence is recorded once into
+ * a HIP graph and replayed.  The batch arrays and outputs must stay valid and
+ * unchanged in size until gumap_batch_plan_destroy.  The batch must be
+ * canonical (GUMAP_CSR_SORTED).  Replays give the same results as the plain
+ * call.
+ */
+typedef struct gumap_batch_plan gumap_batch_plan;
+int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                            float *weights, float *rho, float *sigma, hipStream_t stream,
+                            gumap_batch_plan **plan);
+int gumap_batch_plan_launch(gumap_batch_plan *plan, hipStream_t stream); /* host-synchronous */
+void gumap_batch_plan_destroy(gumap_batch_plan *plan);
+
+/* ----------------------------------------------------------- serving --- */
+
+/*
+ * A request loop that takes layout-preparation jobs (one host CSR graph +
+ * k) as they arrive, keeps their CSR and results resident in device memory
+ * while they run, admits them first-come-first-served under a byte budget,
+ * and runs the admitted jobs' rows together (continuous batching: jobs that
+ * arrive while others run join the next device iteration).  Each job's
+ * result is the same as gumap_knn_partial + gumap_membership on its graph.
+ */
+typedef struct gumap_server gumap_server;
+
+typedef struct gumap_job {
+    int32_t n, nnz;
+    const int32_t *row_ptr;  /* HOST, n + 1; copied before gumap_submit returns */
+    const int32_t *col_idx;  /* HOST, nnz */
+    int32_t k;               /* 1..254 */
+    int32_t want_weights;    /* nonzero: also weights, rho, sigma */
+    uint32_t flags;          /* GUMAP_CSR_SORTED | GUMAP_VALIDATE */
+} gumap_job;
+
+typedef struct gumap_result {
+    int32_t status;          /* GUMAP_OK or the job's error */
+    int32_t n, k;
+    const int32_t *nbr_ids;  /* HOST, n * k; owned by the server until gumap_release */
+    const uint8_t *nbr_hops; /* HOST, n * k */
+    const float *weights;    /* HOST, n * k, or NULL */
+    const float *rho;        /* HOST, n, or NULL */
+    const float *sigma;      /* HOST, n, or NULL */
+    uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns; /* steady clock */
+} gumap_result;
+
+typedef struct gumap_server_stats {
+    uint64_t submitted, completed, failed, iterations;
+    uint64_t queued, running;          /* jobs now waiting / admitted */
+    uint64_t resident_bytes, peak_resident_bytes, budget_bytes;
+} gumap_server_stats;
+
+/* Server flag: run the scheduler without a device (results are zeros); for
+ * testing admission and ordering logic on machines without a GPU. */
+#define GUMAP_SERVER_NO_DEVICE 1u
+
+/* hbm_budget_bytes: device bytes the resident jobs may hold together;
+ * max_slots: jobs admitted at once (0 = no limit). */
+gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, uint32_t flags,
+                                  int *status);
+/* Copies the job and returns a ticket.  GUMAP_E2BIG if it can never fit. */
+int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket);
+/* GUMAP_PENDING while the job runs, else fills *out and returns its status. */
+int gumap_poll(gumap_server *s, uint64_t ticket, gumap_result *out);
+/* Blocks until the job ends (or timeout_ms elapses: GUMAP_PENDING; < 0 = forever). */
+int gumap_wait(gumap_server *s, uint64_t ticket, int64_t timeout_ms, gumap_result *out);
+/* Frees a finished job's host results.  GUMAP_ENOTFOUND if unknown/released,
+ * GUMAP_PENDING if still running. */
+int gumap_release(gumap_server *s, uint64_t ticket);
+int gumap_server_get_stats(gumap_server *s, gumap_server_stats *out);
+/* Stops the scheduler; jobs still queued or running end with GUMAP_EDEVICE
+ * status semantics are not observable afterwards (the server is gone). */
+void gumap_server_destroy(gumap_server *s);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *gumap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GUMAP_H */

@@ -1,0 +1,391 @@
+"""Python binding of libgumap (the HIP/gfx950 BFS-kNN library).
+
+Argument marshalling only: every step runs in the library's kernels.  The
+functions named ``gumap_*`` mirror the C entry points of ``include/gumap.h``
+one to one and take torch device tensors (or None) where the C call takes
+device pointers; the lower-case helpers allocate the outputs and return
+them.  Importing this package never touches the GPU; the library must have
+been built (``__graft_entry__.build()``) or the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgumap.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gumap.h")
+
+OK, PENDING = 0, 1
+EINVAL, EGRAPH, ERANGE, ENOMEM, EDEVICE, E2BIG, ENOTFOUND = -1, -2, -3, -4, -5, -6, -7
+CSR_SORTED, VALIDATE = 1, 2
+MAX_K = 254
+SERVER_NO_DEVICE = 1
+
+_STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "EGRAPH", -3: "ERANGE", -4: "ENOMEM",
+                 -5: "EDEVICE", -6: "E2BIG", -7: "ENOTFOUND"}
+
+
+class GumapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class gumap_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class gumap_batch(ctypes.Structure):
+    _fields_ = [("n_graphs", ctypes.c_int32), ("total_vertices", ctypes.c_int64),
+                ("total_nnz", ctypes.c_int64), ("vtx_offset", ctypes.c_void_p),
+                ("edge_offset", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class gumap_job(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("k", ctypes.c_int32), ("want_weights", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class gumap_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("nbr_ids", ctypes.c_void_p), ("nbr_hops", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("rho", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("t_submit_ns", ctypes.c_uint64),
+                ("t_admit_ns", ctypes.c_uint64), ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class gumap_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("iterations", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("running", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("peak_resident_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64)]
+
+
+def _hip_runtimes() -> list[str]:
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgumap.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+    # first makes the dynamic loader resolve libgumap's libamdhip64.so.7 to that
+    # same copy, so device pointers and streams are shared by one runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); import torch before loading libgumap"
+                          % ", ".join(runtimes))
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    G = ctypes.POINTER(gumap_graph)
+    B = ctypes.POINTER(gumap_batch)
+    lib.gumap_knn_build.argtypes = [G, i32, vp, i32, vp, vp, vp, vp]
+    lib.gumap_knn_partial.argtypes = [G, i32, vp, vp, vp]
+    lib.gumap_membership.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+    lib.gumap_knn_partial_batch.argtypes = [B, i32, vp, vp, vp, vp, vp, vp]
+    lib.gumap_batch_plan_create.argtypes = [B, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.gumap_batch_plan_launch.argtypes = [vp, vp]
+    lib.gumap_batch_plan_destroy.argtypes = [vp]
+    lib.gumap_batch_plan_destroy.restype = None
+    for f in (lib.gumap_knn_build, lib.gumap_knn_partial, lib.gumap_membership,
+              lib.gumap_knn_partial_batch, lib.gumap_batch_plan_create, lib.gumap_batch_plan_launch):
+        f.restype = ctypes.c_int
+    lib.gumap_last_error.argtypes = []
+    lib.gumap_last_error.restype = ctypes.c_char_p
+    if hasattr(lib, "gumap_server_create"):
+        lib.gumap_server_create.argtypes = [ctypes.c_size_t, i32, u32, ctypes.POINTER(ctypes.c_int)]
+        lib.gumap_server_create.restype = vp
+        lib.gumap_submit.argtypes = [vp, ctypes.POINTER(gumap_job), ctypes.POINTER(ctypes.c_uint64)]
+        lib.gumap_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(gumap_result)]
+        lib.gumap_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(gumap_result)]
+        lib.gumap_release.argtypes = [vp, ctypes.c_uint64]
+        lib.gumap_server_get_stats.argtypes = [vp, ctypes.POINTER(gumap_server_stats)]
+        lib.gumap_server_destroy.argtypes = [vp]
+        lib.gumap_server_destroy.restype = None
+        for f in (lib.gumap_submit, lib.gumap_poll, lib.gumap_wait, lib.gumap_release,
+                  lib.gumap_server_get_stats):
+            f.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.gumap_last_error().decode()
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise GumapError(status, last_error())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_graph(row_ptr, col_idx, n: int | None = None, flags: int = 0) -> gumap_graph:
+    """gumap_graph over torch int32 device tensors (kept alive by the caller)."""
+    n = int(row_ptr.shape[0]) - 1 if n is None else n
+    nnz = int(col_idx.shape[0])
+    return gumap_graph(n, nnz, _ptr(row_ptr) if n > 0 or row_ptr is not None else None,
+                       _ptr(col_idx) if nnz > 0 else None, flags)
+
+
+# ------------------------------------------------- mirrors of the C calls ---
+
+def gumap_knn_build(graph: gumap_graph, k: int, sources, n_sources: int, nbr_ids, nbr_hops,
+                    hop_matrix=None, stream=None) -> int:
+    return _check(lib.gumap_knn_build(ctypes.byref(graph), k, _ptr(sources), n_sources, _ptr(nbr_ids),
+                                      _ptr(nbr_hops), _ptr(hop_matrix), _stream(stream)))
+
+
+def gumap_knn_partial(graph: gumap_graph, k: int, nbr_ids, nbr_hops, stream=None) -> int:
+    return _check(lib.gumap_knn_partial(ctypes.byref(graph), k, _ptr(nbr_ids), _ptr(nbr_hops),
+                                        _stream(stream)))
+
+
+def gumap_membership(rows: int, k: int, nbr_hops, weights, rho=None, sigma=None, stream=None) -> int:
+    return _check(lib.gumap_membership(rows, k, _ptr(nbr_hops), _ptr(weights), _ptr(rho), _ptr(sigma),
+                                       _stream(stream)))
+
+
+def gumap_knn_partial_batch(batch: gumap_batch, k: int, nbr_ids, nbr_hops, weights=None, rho=None,
+                            sigma=None, stream=None) -> int:
+    return _check(lib.gumap_knn_partial_batch(ctypes.byref(batch), k, _ptr(nbr_ids), _ptr(nbr_hops),
+                                              _ptr(weights), _ptr(rho), _ptr(sigma), _stream(stream)))
+
+
+# ------------------------------------------------------ allocating helpers ---
+
+def _torch():
+    import torch
+    return torch
+
+
+def knn_build(row_ptr, col_idx, k: int, sources=None, hop_matrix: bool = False, flags: int = 0,
+              stream=None):
+    """All-source (or listed-source) BFS kNN.  Returns (ids, hops, hop_matrix or None)."""
+    torch = _torch()
+    dev = row_ptr.device
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    rows = g.n if sources is None else int(sources.shape[0])
+    ids = torch.empty((rows, k), dtype=torch.int32, device=dev)
+    hops = torch.empty((rows, k), dtype=torch.uint8, device=dev)
+    hm = torch.empty((rows, g.n), dtype=torch.uint8, device=dev) if hop_matrix else None
+    gumap_knn_build(g, k, sources, rows if sources is not None else 0, ids, hops, hm, stream)
+    return ids, hops, hm
+
+
+def knn_partial(row_ptr, col_idx, k: int, flags: int = 0, stream=None):
+    """Truncated partial BFS kNN from every vertex.  Returns (ids, hops)."""
+    torch = _torch()
+    dev = row_ptr.device
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    ids = torch.empty((g.n, k), dtype=torch.int32, device=dev)
+    hops = torch.empty((g.n, k), dtype=torch.uint8, device=dev)
+    gumap_knn_partial(g, k, ids, hops, stream)
+    return ids, hops
+
+
+def membership(hops, stream=None):
+    """Fuzzy-membership weights of kNN rows.  Returns (weights, rho, sigma)."""
+    torch = _torch()
+    rows, k = hops.shape
+    w = torch.empty((rows, k), dtype=torch.float32, device=hops.device)
+    rho = torch.empty(rows, dtype=torch.float32, device=hops.device)
+    sigma = torch.empty(rows, dtype=torch.float32, device=hops.device)
+    gumap_membership(rows, k, hops, w, rho, sigma, stream)
+    return w, rho, sigma
+
+
+class PackedBatch:
+    """Graphs packed in the batch layout of include/gumap.h, resident on a device."""
+
+    def __init__(self, graphs, device="cuda", flags: int = CSR_SORTED):
+        import numpy as np
+        torch = _torch()
+        ns = np.array([g.n for g in graphs], dtype=np.int64)
+        es = np.array([g.nnz for g in graphs], dtype=np.int64)
+        voff = np.zeros(len(graphs) + 1, dtype=np.int64)
+        eoff = np.zeros(len(graphs) + 1, dtype=np.int64)
+        np.cumsum(ns, out=voff[1:])
+        np.cumsum(es, out=eoff[1:])
+        rp = np.concatenate([g.row_ptr for g in graphs]) if graphs else np.zeros(0, np.int32)
+        col = np.concatenate([g.col_idx for g in graphs]) if graphs else np.zeros(0, np.int32)
+        self.n_graphs = len(graphs)
+        self.vtx_offset_host = voff
+        self.edge_offset_host = eoff
+        self.vtx_offset = torch.from_numpy(voff).to(device)
+        self.edge_offset = torch.from_numpy(eoff).to(device)
+        self.row_ptr = torch.from_numpy(rp.astype(np.int32)).to(device)
+        self.col_idx = torch.from_numpy(col.astype(np.int32)).to(device)
+        self.flags = flags
+
+    @property
+    def total_vertices(self) -> int:
+        return int(self.vtx_offset_host[-1])
+
+    @property
+    def total_nnz(self) -> int:
+        return int(self.edge_offset_host[-1])
+
+    def struct(self) -> gumap_batch:
+        return gumap_batch(self.n_graphs, self.total_vertices, self.total_nnz, _ptr(self.vtx_offset),
+                           _ptr(self.edge_offset), _ptr(self.row_ptr),
+                           _ptr(self.col_idx) if self.total_nnz else None, self.flags)
+
+
+def knn_partial_batch(batch: PackedBatch, k: int, weights: bool = True, stream=None):
+    """Batched partial BFS (+ membership).  Returns (ids, hops, weights, rho, sigma)."""
+    torch = _torch()
+    dev = batch.row_ptr.device
+    rows = batch.total_vertices
+    ids = torch.empty((rows, k), dtype=torch.int32, device=dev)
+    hops = torch.empty((rows, k), dtype=torch.uint8, device=dev)
+    w = torch.empty((rows, k), dtype=torch.float32, device=dev) if weights else None
+    rho = torch.empty(rows, dtype=torch.float32, device=dev) if weights else None
+    sigma = torch.empty(rows, dtype=torch.float32, device=dev) if weights else None
+    b = batch.struct()
+    gumap_knn_partial_batch(b, k, ids, hops, w, rho, sigma, stream)
+    return ids, hops, w, rho, sigma
+
+
+class BatchPlan:
+    """Captured (HIP graph) form of knn_partial_batch on fixed buffers."""
+
+    def __init__(self, batch: PackedBatch, k: int, weights: bool = True, stream=None):
+        torch = _torch()
+        dev = batch.row_ptr.device
+        rows = batch.total_vertices
+        self.batch = batch
+        self.ids = torch.empty((rows, k), dtype=torch.int32, device=dev)
+        self.hops = torch.empty((rows, k), dtype=torch.uint8, device=dev)
+        self.weights = torch.empty((rows, k), dtype=torch.float32, device=dev) if weights else None
+        self.rho = torch.empty(rows, dtype=torch.float32, device=dev) if weights else None
+        self.sigma = torch.empty(rows, dtype=torch.float32, device=dev) if weights else None
+        self._b = batch.struct()
+        h = ctypes.c_void_p()
+        _check(lib.gumap_batch_plan_create(ctypes.byref(self._b), k, _ptr(self.ids), _ptr(self.hops),
+                                           _ptr(self.weights), _ptr(self.rho), _ptr(self.sigma),
+                                           _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib.gumap_batch_plan_launch(self._h, _stream(stream)))
+        return self.ids, self.hops, self.weights, self.rho, self.sigma
+
+    def close(self):
+        if self._h:
+            lib.gumap_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ serving ---
+
+class Server:
+    """Request loop of include/gumap.h (gumap_server_*): submit host CSR jobs,
+    poll or wait for their results.  Results are returned as numpy copies."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 0, flags: int = 0):
+        st = ctypes.c_int(0)
+        h = lib.gumap_server_create(hbm_budget_bytes, max_slots, flags, ctypes.byref(st))
+        if not h:
+            raise GumapError(st.value, last_error())
+        self._h = ctypes.c_void_p(h)
+        self._keep = {}
+
+    def submit(self, row_ptr, col_idx, k: int, want_weights: bool = True, flags: int = CSR_SORTED) -> int:
+        import numpy as np
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        n = int(rp.shape[0]) - 1
+        job = gumap_job(n, int(ci.shape[0]), rp.ctypes.data if rp.size else None,
+                        ci.ctypes.data if ci.size else None, k, 1 if want_weights else 0, flags)
+        t = ctypes.c_uint64(0)
+        _check(lib.gumap_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
+        return int(t.value)
+
+    @staticmethod
+    def _unpack(r: gumap_result) -> dict:
+        import numpy as np
+        n, k = r.n, r.k
+        out = {"status": r.status, "n": n, "k": k, "t_submit_ns": r.t_submit_ns, "t_admit_ns": r.t_admit_ns,
+               "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns}
+
+        def arr(ptr, count, ctype, dtype):
+            if not ptr or count == 0:
+                return np.zeros(count, dtype=dtype) if ptr else None
+            buf = (ctype * count).from_address(ptr)
+            return np.frombuffer(buf, dtype=dtype).copy()
+
+        out["ids"] = arr(r.nbr_ids, n * k, ctypes.c_int32, np.int32)
+        out["hops"] = arr(r.nbr_hops, n * k, ctypes.c_uint8, np.uint8)
+        out["weights"] = arr(r.weights, n * k, ctypes.c_float, np.float32)
+        out["rho"] = arr(r.rho, n, ctypes.c_float, np.float32)
+        out["sigma"] = arr(r.sigma, n, ctypes.c_float, np.float32)
+        for key in ("ids", "hops", "weights"):
+            if out[key] is not None:
+                out[key] = out[key].reshape(n, k)
+        return out
+
+    def poll(self, ticket: int):
+        r = gumap_result()
+        st = lib.gumap_poll(self._h, ticket, ctypes.byref(r))
+        if st == PENDING:
+            return None
+        if st < 0 and st != r.status:
+            raise GumapError(st, last_error())
+        return self._unpack(r)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = gumap_result()
+        st = lib.gumap_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
+        if st == PENDING:
+            return None
+        if st < 0 and st != r.status:
+            raise GumapError(st, last_error())
+        return self._unpack(r)
+
+    def release(self, ticket: int) -> int:
+        return _check(lib.gumap_release(self._h, ticket))
+
+    def stats(self) -> dict:
+        s = gumap_server_stats()
+        _check(lib.gumap_server_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_}
+
+    def close(self):
+        if self._h:
+            lib.gumap_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

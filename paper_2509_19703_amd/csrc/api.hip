@@ -1,0 +1,709 @@
+// C-ABI of libgumap: argument checks, scratch management and the launch
+// sequences of the plain calls (gumap_knn_build, gumap_knn_partial,
+// gumap_membership) and of the batched call and its captured plan.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gumap.h"
+#include "kernels.h"
+#include "runtime.h"
+#include "util.h"
+
+namespace gm {
+
+// ------------------------------------------------------------ errors ---
+static thread_local std::string t_error;
+
+int set_error(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_error = buf;
+    return status;
+}
+
+void clear_error() { t_error.clear(); }
+const char *last_error() { return t_error.c_str(); }
+
+int hip_status(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GUMAP_OK;
+    if (e == hipErrorOutOfMemory) return set_error(GUMAP_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return set_error(GUMAP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// --------------------------------------------------------- scratch -----
+std::mutex &api_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
+namespace {
+
+struct DeviceScratch {
+    void *ptr[kScratchSlots] = {};
+    size_t size[kScratchSlots] = {};
+    void *host = nullptr;
+    size_t host_size = 0;
+};
+
+DeviceScratch &scratch_of(int dev)
+{
+    static DeviceScratch per_dev[64];
+    return per_dev[dev & 63];
+}
+
+}  // namespace
+
+int scratch_get(int slot, size_t bytes, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    DeviceScratch &d = scratch_of(dev);
+    if (bytes == 0) bytes = 256;
+    if (d.size[slot] < bytes) {
+        if (d.ptr[slot]) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(d.ptr[slot]);
+            d.ptr[slot] = nullptr;
+            d.size[slot] = 0;
+        }
+        size_t want = bytes + bytes / 8;
+        e = hipMalloc(&d.ptr[slot], want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            d.ptr[slot] = nullptr;
+            return set_error(GUMAP_ENOMEM, "device scratch of %zu bytes: %s", want, hipGetErrorString(e));
+        }
+        d.size[slot] = want;
+    }
+    *out = d.ptr[slot];
+    return GUMAP_OK;
+}
+
+int host_scratch_get(size_t bytes, void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    DeviceScratch &d = scratch_of(dev);
+    if (bytes == 0) bytes = 256;
+    if (d.host_size < bytes) {
+        if (d.host) (void)hipHostFree(d.host);
+        d.host = nullptr;
+        d.host_size = 0;
+        e = hipHostMalloc(&d.host, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            d.host = nullptr;
+            return set_error(GUMAP_ENOMEM, "pinned host scratch of %zu bytes", bytes);
+        }
+        d.host_size = bytes;
+    }
+    *out = d.host;
+    return GUMAP_OK;
+}
+
+size_t env_size(const char *name, size_t dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    char *end = nullptr;
+    unsigned long long x = strtoull(v, &end, 10);
+    return end && end != v ? (size_t)x : dflt;
+}
+
+// Reads a device int flag (after the stream drains).
+int read_flag(const int *dflag, int *out, hipStream_t s)
+{
+    void *h = nullptr;
+    int st = host_scratch_get(64, &h);
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(h, dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "reading device flag");
+    *out = *(int *)h;
+    return GUMAP_OK;
+}
+
+// ------------------------------------------------------- CSR ingest ----
+int prepare_graph(const gumap_graph *g, hipStream_t s, CanonCsr *out)
+{
+    const int32_t n = g->n, nnz = g->nnz;
+    out->n = n;
+    out->row_ptr = g->row_ptr;
+    out->col = g->col_idx;
+    if (n == 0) return GUMAP_OK;
+    int *err = nullptr;
+    int st;
+    if (g->flags & GUMAP_VALIDATE) {
+        st = scratch_get(kSlotFlags, 256, (void **)&err);
+        if (st) return st;
+        hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess) e = launch_validate_structure(n, nnz, g->row_ptr, g->col_idx, err, s);
+        if (e != hipSuccess) return hip_status(e, "validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "malformed CSR (check bits 0x%x)", bad);
+    }
+    if (!(g->flags & GUMAP_CSR_SORTED)) {
+        int32_t *rp = nullptr, *col = nullptr;
+        void *tmp = nullptr;
+        if ((st = scratch_get(kSlotCanonRp, (size_t)(n + 1) * sizeof(int32_t), (void **)&rp))) return st;
+        if ((st = scratch_get(kSlotCanonCol, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t), (void **)&col))) return st;
+        if ((st = scratch_get(kSlotCanonTmp, canon_scratch_bytes(n, nnz), &tmp))) return st;
+        hipError_t e = launch_canonicalize(n, nnz, g->row_ptr, g->col_idx, rp, col, tmp, s);
+        if (e != hipSuccess) return hip_status(e, "canonicalize");
+        out->row_ptr = rp;
+        out->col = col;
+    }
+    if (g->flags & GUMAP_VALIDATE) {
+        hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess && (g->flags & GUMAP_CSR_SORTED)) e = check_sorted(n, out->row_ptr, out->col, err, s);
+        if (e == hipSuccess) e = launch_check_symmetric(n, out->row_ptr, out->col, err, s);
+        if (e != hipSuccess) return hip_status(e, "validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "%s", (bad & 32) ? "rows not sorted/unique or self-loop under GUMAP_CSR_SORTED"
+                                                                 : "CSR is not symmetric");
+    }
+    return GUMAP_OK;
+}
+
+int check_graph_args(const gumap_graph *g)
+{
+    if (!g) return set_error(GUMAP_EINVAL, "graph is NULL");
+    if (g->n < 0 || g->nnz < 0) return set_error(GUMAP_EINVAL, "negative n or nnz");
+    if (g->n > 0 && !g->row_ptr) return set_error(GUMAP_EINVAL, "row_ptr is NULL");
+    if (g->nnz > 0 && !g->col_idx) return set_error(GUMAP_EINVAL, "col_idx is NULL");
+    if (g->flags & ~(GUMAP_CSR_SORTED | GUMAP_VALIDATE)) return set_error(GUMAP_EINVAL, "unknown flags");
+    return GUMAP_OK;
+}
+
+int check_k(int32_t k)
+{
+    if (k < 1 || k > GUMAP_MAX_K) return set_error(GUMAP_EINVAL, "k = %d outside [1, %d]", k, GUMAP_MAX_K);
+    return GUMAP_OK;
+}
+
+// On failure, let work already enqueued drain so the call stays host-synchronous.
+int settle(int status, hipStream_t s)
+{
+    if (status != GUMAP_OK && status != GUMAP_EINVAL) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+    }
+    return status;
+}
+
+int finish(hipStream_t s, const char *what)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    return hip_status(e, what);
+}
+
+// ----------------------------------------------------- all-source BFS --
+namespace {
+
+int bit_length(int x)
+{
+    int b = 0;
+    while (x > 0) { ++b; x >>= 1; }
+    return b;
+}
+
+int choose_words(int32_t n_uniq)
+{
+    size_t forced = env_size("GUMAP_FORCE_WORDS", 0);
+    if (forced == 1 || forced == 2 || forced == 4 || forced == 8) return (int)forced;
+    int need = (n_uniq + 63) / 64;
+    int w = 1;
+    while (w < need && w < 8) w <<= 1;
+    return w;
+}
+
+}  // namespace
+
+int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
+              int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if ((st = check_k(k))) return st;
+    if (sources && n_sources < 0) return set_error(GUMAP_EINVAL, "n_sources < 0");
+    const int32_t n = g->n;
+    const int64_t rows = sources ? n_sources : n;
+    if (rows > 0 && (!ids || !hops)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (rows == 0) return GUMAP_OK;
+    if (n == 0) return set_error(GUMAP_EINVAL, "source id outside [0, 0)");
+
+    // sources -> sorted unique slots
+    std::vector<int32_t> h_usrc;
+    std::vector<int64_t> h_slot_row;
+    std::vector<int64_t> dup_pairs;  // (dst row, src row)
+    const bool all_sources = sources == nullptr;
+    if (!all_sources) {
+        std::vector<int32_t> h_src((size_t)rows);
+        hipError_t e = hipMemcpyAsync(h_src.data(), sources, (size_t)rows * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "reading sources");
+        std::vector<int64_t> order((size_t)rows);
+        for (int64_t r = 0; r < rows; ++r) {
+            if (h_src[r] < 0 || h_src[r] >= n)
+                return set_error(GUMAP_EINVAL, "source %lld = %d outside [0, %d)", (long long)r, h_src[r], n);
+            order[r] = r;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return h_src[a] < h_src[b]; });
+        for (int64_t i = 0; i < rows; ++i) {
+            int64_t r = order[i];
+            if (!h_usrc.empty() && h_usrc.back() == h_src[r]) {
+                dup_pairs.push_back(r);
+                dup_pairs.push_back(h_slot_row.back());
+            } else {
+                h_usrc.push_back(h_src[r]);
+                h_slot_row.push_back(r);
+            }
+        }
+    }
+    const int32_t n_uniq = all_sources ? n : (int32_t)h_usrc.size();
+
+    CanonCsr c;
+    if ((st = prepare_graph(g, s, &c))) return st;
+
+    int32_t *usrc = nullptr, *slot_of = nullptr;
+    int64_t *slot_row = nullptr, *dup_dev = nullptr;
+    if ((st = scratch_get(kSlotUsrc, (size_t)n_uniq * sizeof(int32_t), (void **)&usrc))) return st;
+    if ((st = scratch_get(kSlotSlotOf, (size_t)n * sizeof(int32_t), (void **)&slot_of))) return st;
+    if ((st = scratch_get(kSlotSlotRow, (size_t)n_uniq * sizeof(int64_t), (void **)&slot_row))) return st;
+    hipError_t e = hipSuccess;
+    if (all_sources) {
+        e = iota_i32(usrc, n, s);
+        if (e == hipSuccess) e = iota_i32(slot_of, n, s);
+        if (e == hipSuccess) e = iota_i64(slot_row, n, 0, s);
+    } else {
+        e = hipMemcpyAsync(usrc, h_usrc.data(), (size_t)n_uniq * sizeof(int32_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot_row, h_slot_row.data(), (size_t)n_uniq * sizeof(int64_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = fill_i32(slot_of, n, -1, s);
+        if (e == hipSuccess) e = scatter_slots(usrc, n_uniq, slot_of, s);
+        if (e == hipSuccess && !dup_pairs.empty()) {
+            if ((st = scratch_get(kSlotDup, dup_pairs.size() * sizeof(int64_t), (void **)&dup_dev))) return st;
+            e = hipMemcpyAsync(dup_dev, dup_pairs.data(), dup_pairs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+        }
+    }
+    if (e != hipSuccess) return hip_status(e, "source setup");
+
+    const int words = choose_words(n_uniq);
+    const int W = 64 * words;
+    const int32_t groups_total = (n_uniq + W - 1) / W;
+    const int L_cap = hop_matrix ? 255 : k;
+    const int planes_alloc = hop_matrix ? 8 : bit_length(k);
+    const size_t arr_per_group = (size_t)n * words;  // uint64 per array per group
+    const size_t bytes_per_group = (3 + (size_t)planes_alloc) * arr_per_group * 8 +
+                                   (hop_matrix ? 0 : (size_t)W * n) + (size_t)W * 16 * 4 +
+                                   (size_t)(L_cap + 2) * 8;
+    const size_t budget = env_size("GUMAP_BFS_BUDGET_MB", 8192) << 20;
+    int32_t groups_round = (int32_t)std::max<size_t>(1, std::min<size_t>(groups_total, budget / std::max<size_t>(1, bytes_per_group)));
+
+    uint64_t *state = nullptr;
+    uint8_t *hop_scratch = nullptr;
+    unsigned long long *stats = nullptr;
+    unsigned int *lvl_cnt = nullptr;
+    int64_t *local_rows = nullptr;
+    const size_t arr_round = arr_per_group * groups_round;
+    if ((st = scratch_get(kSlotBfsState, (3 + (size_t)planes_alloc) * arr_round * 8, (void **)&state))) return st;
+    if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * groups_round * 8, (void **)&stats))) return st;
+    if ((st = scratch_get(kSlotLvlCnt, (size_t)groups_round * W * 16 * 4, (void **)&lvl_cnt))) return st;
+    if (!hop_matrix) {
+        if ((st = scratch_get(kSlotHopRows, (size_t)groups_round * W * n, (void **)&hop_scratch))) return st;
+        if ((st = scratch_get(kSlotLocalRows, (size_t)groups_round * W * sizeof(int64_t), (void **)&local_rows))) return st;
+        if ((e = iota_i64(local_rows, (int64_t)groups_round * W, 0, s)) != hipSuccess) return hip_status(e, "iota");
+    }
+    void *hstats_v = nullptr;
+    if ((st = host_scratch_get((size_t)(L_cap + 2) * groups_round * 8, &hstats_v))) return st;
+    unsigned long long *hstats = (unsigned long long *)hstats_v;
+
+    for (int32_t gs = 0; gs < groups_total; gs += groups_round) {
+        MsbfsArgs a;
+        a.n = n;
+        a.row_ptr = c.row_ptr;
+        a.col = c.col;
+        a.words = words;
+        a.groups = std::min(groups_round, groups_total - gs);
+        a.slot0 = gs * W;
+        a.n_slots = std::min<int32_t>(a.groups * W, n_uniq - a.slot0);
+        a.usrc = usrc;
+        a.n_usrc = n_uniq;
+        a.slot_of = slot_of;
+        const size_t arr = arr_per_group * a.groups;
+        a.front[0] = state;
+        a.front[1] = state + arr;
+        a.visited = state + 2 * arr;
+        a.planes = state + 3 * arr;
+        a.plane_stride = arr;
+        a.stats = stats;
+        a.stats_groups = a.groups;
+        e = hipMemsetAsync(a.front[1], 0, 2 * arr * 8, s);  // front[1] and visited
+        if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * a.groups * 8, s);
+        if (e == hipSuccess) e = hipMemsetAsync(lvl_cnt, 0, (size_t)a.n_slots * 16 * 4, s);
+        if (e == hipSuccess) e = launch_msbfs_init(a, s);
+        if (e != hipSuccess) return hip_status(e, "bfs init");
+
+        int L = 1, last_level = 0, chunk = 4;
+        bool done = false, range_error = false;
+        while (!done) {
+            const int first = L;
+            for (int c2 = 0; c2 < chunk && L <= L_cap; ++c2, ++L) {
+                const int hop = L - 1;   // committed by this launch
+                if (hop >= 1 && (hop & (hop - 1)) == 0) {
+                    int b = bit_length(hop) - 1;
+                    if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
+                    if (e != hipSuccess) return hip_status(e, "plane clear");
+                }
+                if ((e = launch_msbfs_level(a, L, false, s)) != hipSuccess) return hip_status(e, "bfs level");
+            }
+            e = hipMemcpyAsync(hstats + (size_t)first * a.groups, stats + (size_t)first * a.groups,
+                               (size_t)(L - first) * a.groups * 8, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_status(e, "bfs stats");
+            for (int lv = first; lv < L && !done; ++lv) {
+                bool any = false;
+                for (int q = 0; q < a.groups; ++q) any |= hstats[(size_t)lv * a.groups + q] != 0;
+                if (!any) {
+                    done = true;
+                    last_level = lv - 1;
+                } else if (hop_matrix && lv == 255) {
+                    range_error = true;
+                    done = true;
+                }
+            }
+            if (!done && L > L_cap) {
+                // level L_cap found vertices; commit them without searching further
+                const int hop = L_cap;
+                if ((hop & (hop - 1)) == 0) {
+                    int b = bit_length(hop) - 1;
+                    if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
+                    if (e != hipSuccess) return hip_status(e, "plane clear");
+                }
+                if ((e = launch_msbfs_level(a, L_cap + 1, true, s)) != hipSuccess) return hip_status(e, "bfs commit");
+                last_level = L_cap;
+                done = true;
+            }
+            chunk = std::max(4, L / 2);
+        }
+        if (range_error)
+            return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
+        const int planes_used = bit_length(last_level);
+        uint8_t *hop_out = hop_matrix ? hop_matrix : hop_scratch;
+        const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
+        e = launch_msbfs_hops_counted(a, planes_used, hop_out, hop_rows_of, n, lvl_cnt, s);
+        if (e == hipSuccess)
+            e = launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
+                                          slot_row + a.slot0, lvl_cnt, ids, hops, s);
+        if (e != hipSuccess) return hip_status(e, "hop rows / selection");
+    }
+    if (!dup_pairs.empty()) {
+        e = launch_copy_rows((int32_t)(dup_pairs.size() / 2), dup_dev, k, n, ids, hops, hop_matrix, s);
+        if (e != hipSuccess) return hip_status(e, "repeated sources");
+    }
+    return finish(s, "gumap_knn_build");
+}
+
+// --------------------------------------------------------- partial BFS --
+int knn_partial(const gumap_graph *g, int32_t k, int32_t *ids, uint8_t *hops, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if ((st = check_k(k))) return st;
+    if (g->n > 0 && (!ids || !hops)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (g->n == 0) return GUMAP_OK;
+    CanonCsr c;
+    if ((st = prepare_graph(g, s, &c))) return st;
+    PartialArgs a{};
+    a.k = k;
+    a.n = c.n;
+    a.row_ptr = c.row_ptr;
+    a.col = c.col;
+    a.ids = ids;
+    a.hops = hops;
+    hipError_t e = launch_partial_bfs(a, s);
+    if (e != hipSuccess) return hip_status(e, "partial bfs");
+    return finish(s, "gumap_knn_partial");
+}
+
+int membership(int32_t rows, int32_t k, const uint8_t *hops, float *w, float *rho, float *sigma,
+               hipStream_t s)
+{
+    int st;
+    if (rows < 0) return set_error(GUMAP_EINVAL, "rows < 0");
+    if ((st = check_k(k))) return st;
+    if (rows == 0) return GUMAP_OK;
+    if (!hops || !w) return set_error(GUMAP_EINVAL, "hops or weights is NULL");
+    hipError_t e = launch_membership(rows, k, hops, w, rho, sigma, s);
+    if (e != hipSuccess) return hip_status(e, "membership");
+    return finish(s, "gumap_membership");
+}
+
+// ------------------------------------------------------------ batches --
+int check_batch_args(const gumap_batch *b, int32_t k)
+{
+    if (!b) return set_error(GUMAP_EINVAL, "batch is NULL");
+    if (b->n_graphs < 0 || b->total_vertices < 0 || b->total_nnz < 0)
+        return set_error(GUMAP_EINVAL, "negative batch sizes");
+    if (b->total_vertices >= (int64_t)INT32_MAX || b->total_nnz >= (int64_t)INT32_MAX)
+        return set_error(GUMAP_EINVAL, "batch exceeds int32 vertex or edge positions");
+    if (b->n_graphs > 0 && (!b->vtx_offset || !b->edge_offset || !b->row_ptr))
+        return set_error(GUMAP_EINVAL, "batch array is NULL");
+    if (b->total_nnz > 0 && !b->col_idx) return set_error(GUMAP_EINVAL, "col_idx is NULL");
+    if (b->flags & ~(GUMAP_CSR_SORTED | GUMAP_VALIDATE)) return set_error(GUMAP_EINVAL, "unknown flags");
+    return check_k(k);
+}
+
+// Brings a batch to canonical packed form (validating if asked).  out may
+// alias the caller's arrays when nothing had to change.
+int prepare_batch(const gumap_batch *b, hipStream_t s, gumap_batch *out)
+{
+    *out = *b;
+    int st;
+    if (b->n_graphs == 0 || b->total_vertices == 0) return GUMAP_OK;
+    const bool validate = (b->flags & GUMAP_VALIDATE) != 0;
+    if (validate) {
+        std::vector<int64_t> hv(b->n_graphs + 1), he(b->n_graphs + 1);
+        hipError_t e = hipMemcpyAsync(hv.data(), b->vtx_offset, hv.size() * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(he.data(), b->edge_offset, he.size() * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "reading batch offsets");
+        if (hv[0] != 0 || he[0] != 0 || hv.back() != b->total_vertices || he.back() != b->total_nnz)
+            return set_error(GUMAP_EGRAPH, "batch offsets inconsistent with the totals");
+        for (int32_t i = 0; i < b->n_graphs; ++i)
+            if (hv[i] > hv[i + 1] || he[i] > he[i + 1]) return set_error(GUMAP_EGRAPH, "batch offsets not monotone");
+        int *err = nullptr;
+        if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+        e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess)
+            e = validate_batch(b->n_graphs, b->vtx_offset, b->edge_offset, b->row_ptr, b->col_idx,
+                               b->total_vertices, b->total_nnz, err, s);
+        if (e != hipSuccess) return hip_status(e, "batch validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "malformed batch CSR (check bits 0x%x)", bad);
+    }
+    if ((b->flags & GUMAP_CSR_SORTED) && !validate) return GUMAP_OK;
+    // Disjoint-union CSR, canonicalised (or checked), and back to packed form.
+    const int32_t nv = (int32_t)b->total_vertices, ne = (int32_t)b->total_nnz;
+    int32_t *urp = nullptr, *ucol = nullptr;
+    if ((st = scratch_get(kSlotUnionRp, (size_t)(nv + 1) * 4, (void **)&urp))) return st;
+    if ((st = scratch_get(kSlotUnionCol, (size_t)(ne > 0 ? ne : 1) * 4, (void **)&ucol))) return st;
+    hipError_t e = batch_to_union(b->n_graphs, b->vtx_offset, b->edge_offset, b->row_ptr, b->col_idx,
+                                  b->total_vertices, b->total_nnz, urp, ucol, s);
+    if (e != hipSuccess) return hip_status(e, "batch union");
+    gumap_graph ug{nv, ne, urp, ucol, b->flags & GUMAP_CSR_SORTED};
+    CanonCsr c;
+    if ((st = prepare_graph(&ug, s, &c))) return st;
+    if (validate) {
+        int *err = nullptr;
+        if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+        e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess && (b->flags & GUMAP_CSR_SORTED)) e = check_sorted(nv, c.row_ptr, c.col, err, s);
+        if (e == hipSuccess) e = launch_check_symmetric(nv, c.row_ptr, c.col, err, s);
+        if (e != hipSuccess) return hip_status(e, "batch validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "batch graph not sorted/symmetric (check bits 0x%x)", bad);
+        if (b->flags & GUMAP_CSR_SORTED) return GUMAP_OK;
+    }
+    // canonical union -> packed
+    int32_t total_canon = 0;
+    e = hipMemcpyAsync(&total_canon, c.row_ptr + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "batch canonical size");
+    int64_t *eoff = nullptr;
+    int32_t *rp = nullptr, *col = nullptr;
+    if ((st = scratch_get(kSlotBatchEoff, (size_t)(b->n_graphs + 1) * 8, (void **)&eoff))) return st;
+    if ((st = scratch_get(kSlotBatchRp, (size_t)(nv + b->n_graphs) * 4, (void **)&rp))) return st;
+    if ((st = scratch_get(kSlotBatchCol, (size_t)(total_canon > 0 ? total_canon : 1) * 4, (void **)&col))) return st;
+    e = union_to_batch(b->n_graphs, b->vtx_offset, c.row_ptr, c.col, nv, total_canon, eoff, rp, col, s);
+    if (e != hipSuccess) return hip_status(e, "batch repack");
+    out->edge_offset = eoff;
+    out->row_ptr = rp;
+    out->col_idx = col;
+    out->total_nnz = total_canon;
+    out->flags = GUMAP_CSR_SORTED;
+    return GUMAP_OK;
+}
+
+int batch_enqueue(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, float *w, float *rho,
+                  float *sigma, hipStream_t s)
+{
+    unsigned long long *counter = nullptr;
+    int st;
+    if ((st = scratch_get(kSlotCounter, 256, (void **)&counter))) return st;
+    BatchArgs a{};
+    a.k = k;
+    a.n_graphs = b->n_graphs;
+    a.total_vertices = b->total_vertices;
+    a.vtx_offset = b->vtx_offset;
+    a.edge_offset = b->edge_offset;
+    a.row_ptr = b->row_ptr;
+    a.col = b->col_idx;
+    a.ids = ids;
+    a.hops = hops;
+    a.weights = w;
+    a.rho = rho;
+    a.sigma = sigma;
+    a.work_counter = counter;
+    a.chunk = (int32_t)std::min<size_t>(batch_chunk_rows(k), std::max<size_t>(1, env_size("GUMAP_BATCH_CHUNK", 64)));
+    a.waves_per_block = 4;
+    int64_t maxb = partial_batch_max_blocks();
+    int64_t want = (b->total_vertices + 4 * a.chunk - 1) / (4 * a.chunk);
+    a.blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(maxb, want));
+    hipError_t e = launch_batch_reset(counter, s);
+    if (e == hipSuccess) e = launch_partial_batch(a, s);
+    return hip_status(e, "batch launch");
+}
+
+int knn_partial_batch(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, float *w, float *rho,
+                      float *sigma, hipStream_t s)
+{
+    int st;
+    if ((st = check_batch_args(b, k))) return st;
+    if (b->total_vertices > 0 && (!ids || !hops)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (b->total_vertices == 0) return GUMAP_OK;
+    gumap_batch cb;
+    if ((st = prepare_batch(b, s, &cb))) return st;
+    if ((st = batch_enqueue(&cb, k, ids, hops, w, rho, sigma, s))) return st;
+    return finish(s, "gumap_knn_partial_batch");
+}
+
+}  // namespace gm
+
+// ================================================================ C-ABI ===
+
+struct gumap_batch_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t rows = 0;
+};
+
+extern "C" {
+
+const char *gumap_last_error(void) { return gm::last_error(); }
+
+int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
+                    int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::knn_build(g, k, sources, n_sources, nbr_ids, nbr_hops, hop_matrix, stream), stream);
+}
+
+int gumap_knn_partial(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                      hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::knn_partial(g, k, nbr_ids, nbr_hops, stream), stream);
+}
+
+int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *weights, float *rho,
+                     float *sigma, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::membership(rows, k, nbr_hops, weights, rho, sigma, stream), stream);
+}
+
+int gumap_knn_partial_batch(const gumap_batch *b, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                            float *weights, float *rho, float *sigma, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::knn_partial_batch(b, k, nbr_ids, nbr_hops, weights, rho, sigma, stream), stream);
+}
+
+int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                            float *weights, float *rho, float *sigma, hipStream_t stream,
+                            gumap_batch_plan **plan)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    int st;
+    if (!plan) return gm::set_error(GUMAP_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if ((st = gm::check_batch_args(b, k))) return st;
+    if (!(b->flags & GUMAP_CSR_SORTED))
+        return gm::set_error(GUMAP_EINVAL, "a captured plan needs a canonical batch (GUMAP_CSR_SORTED)");
+    if (b->total_vertices > 0 && (!nbr_ids || !nbr_hops)) return gm::set_error(GUMAP_EINVAL, "output pointer is NULL");
+    gumap_batch cb;
+    if ((st = gm::prepare_batch(b, stream, &cb))) return st;  // validation only
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return gm::hip_status(e, "plan");
+    // make sure the scratch the launches use exists before capture
+    unsigned long long *counter = nullptr;
+    if ((st = gm::scratch_get(gm::kSlotCounter, 256, (void **)&counter))) return st;
+    gumap_batch_plan *p = new gumap_batch_plan();
+    p->rows = b->total_vertices;
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return gm::hip_status(e, "capture stream");
+    }
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = gm::batch_enqueue(&cb, k, nbr_ids, nbr_hops, weights, rho, sigma, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &p->graph);
+        if (st == GUMAP_OK && e2 != hipSuccess) st = gm::hip_status(e2, "end capture");
+    } else {
+        st = gm::hip_status(e, "begin capture");
+    }
+    if (st == GUMAP_OK) {
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = gm::hip_status(e, "graph instantiate");
+    }
+    (void)hipStreamDestroy(cap);
+    if (st != GUMAP_OK) {
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        delete p;
+        return st;
+    }
+    *plan = p;
+    return GUMAP_OK;
+}
+
+int gumap_batch_plan_launch(gumap_batch_plan *plan, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    if (!plan) return gm::set_error(GUMAP_EINVAL, "plan is NULL");
+    if (plan->rows == 0) return GUMAP_OK;
+    hipError_t e = hipGraphLaunch(plan->exec, stream);
+    if (e != hipSuccess) return gm::hip_status(e, "graph launch");
+    return gm::finish(stream, "gumap_batch_plan_launch");
+}
+
+void gumap_batch_plan_destroy(gumap_batch_plan *plan)
+{
+    if (!plan) return;
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+}
+
+}  // extern "C"

@@ -1,0 +1,452 @@
+// CSR ingest: structural validation, symmetry check, canonicalisation
+// (rows sorted ascending, repeats and self-loops removed) and the exclusive
+// scan used to rebuild row pointers.  The kNN results depend only on the
+// undirected edge set; a canonical adjacency is what lets the partial BFS
+// merge sorted neighbour lists and stop early.
+#include "device.h"
+#include "kernels.h"
+
+namespace gm {
+
+namespace {
+
+constexpr int kSmallRow = 64;      // one wave, registers
+constexpr int kMidRow = 1024;      // one wave, LDS
+constexpr int kBigRow = 32768;     // one workgroup, LDS
+constexpr int kCanonBlock = 256;   // 4 waves
+constexpr int kBigBlock = 1024;
+constexpr int kHugeBlocks = 32;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void validate_structure_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr,
+                                          const int32_t *__restrict__ col, int *err)
+{
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    if (tid == 0) {
+        if (row_ptr[0] != 0) bad |= 1;
+        if (row_ptr[n] != nnz) bad |= 4;
+    }
+    for (int64_t v = tid; v < n; v += stride) {
+        int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        if (a > b || a < 0 || b > nnz) bad |= 2;
+    }
+    for (int64_t e = tid; e < nnz; e += stride) {
+        int32_t w = col[e];
+        if (w < 0 || w >= n) bad |= 8;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// One wave per row u: every neighbour w must list u (canonical rows).
+__global__ void check_symmetric_kernel(int32_t n, const int32_t *__restrict__ row_ptr,
+                                       const int32_t *__restrict__ col, int *err)
+{
+    const int waves = blockDim.x / GM_WAVE;
+    int64_t u = (int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE;
+    int64_t wstride = (int64_t)gridDim.x * waves;
+    for (; u < n; u += wstride) {
+        int32_t a = row_ptr[u], b = row_ptr[u + 1];
+        int bad = 0;
+        for (int32_t e = a + lane(); e < b; e += GM_WAVE) {
+            int32_t w = col[e];
+            int32_t wa = row_ptr[w], wb = row_ptr[w + 1];
+            int32_t p = lower_bound(col, wa, wb, (int)u);
+            if (p >= wb || col[p] != u) bad = 16;
+        }
+        if (__ballot(bad != 0)) {
+            if (lane() == 0) atomicOr(err, 16);
+        }
+    }
+}
+
+// Sorts the row of vertex v into tmp[a, a + unique) and records the count.
+// Rows longer than kMidRow are queued for the workgroup kernels.
+__global__ void __launch_bounds__(kCanonBlock)
+canon_rows_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, int32_t *big_list,
+                  int32_t *big_count, int32_t *huge_list, int32_t *huge_count)
+{
+    __shared__ int32_t lds[kCanonBlock / GM_WAVE][kMidRow];
+    const int wid = threadIdx.x / GM_WAVE;
+    const int l = lane();
+    int32_t *buf = lds[wid];
+    const int waves = blockDim.x / GM_WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * waves + wid; v < n; v += (int64_t)gridDim.x * waves) {
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        const int32_t d = b - a;
+        if (d > kMidRow) {
+            if (l == 0) {
+                if (d > kBigRow) huge_list[atomicAdd(huge_count, 1)] = (int32_t)v;
+                else big_list[atomicAdd(big_count, 1)] = (int32_t)v;
+            }
+            continue;
+        }
+        if (d <= kSmallRow) {
+            int x = l < d ? col[a + l] : GM_INF_ID;
+            // bitonic sort across the 64 lanes, ascending
+#pragma unroll
+            for (int kk = 2; kk <= GM_WAVE; kk <<= 1) {
+#pragma unroll
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    int p = __shfl_xor(x, j, GM_WAVE);
+                    bool up = (l & kk) == 0;
+                    bool low = (l & j) == 0;
+                    x = (low == up) ? min(x, p) : max(x, p);
+                }
+            }
+            int prev = __shfl_up(x, 1, GM_WAVE);
+            bool keep = x != GM_INF_ID && x != (int)v && (l == 0 || x != prev);
+            unsigned long long m = __ballot(keep);
+            if (keep) tmp[a + lanes_below(m)] = x;
+            if (l == 0) cnt[v] = __popcll(m);
+            continue;
+        }
+        // 64 < d <= 1024: bitonic sort in this wave's LDS slice
+        int P = 128;
+        while (P < d) P <<= 1;
+        for (int i = l; i < P; i += GM_WAVE) buf[i] = i < d ? col[a + i] : GM_INF_ID;
+        wave_sync();
+        for (int kk = 2; kk <= P; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = l; i < P; i += GM_WAVE) {
+                    int q = i ^ j;
+                    if (q > i) {
+                        int x = buf[i], y = buf[q];
+                        bool up = (i & kk) == 0;
+                        if ((x > y) == up) { buf[i] = y; buf[q] = x; }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        int base = 0;
+        for (int c = 0; c < P; c += GM_WAVE) {
+            int i = c + l;
+            int x = buf[i];
+            bool keep = x != GM_INF_ID && x != (int)v && (i == 0 || x != buf[i - 1]);
+            unsigned long long m = __ballot(keep);
+            if (keep) tmp[a + base + lanes_below(m)] = x;
+            base += __popcll(m);
+        }
+        if (l == 0) cnt[v] = base;
+        wave_sync();
+    }
+}
+
+// One workgroup per queued row of length (kMidRow, kBigRow].
+__global__ void __launch_bounds__(kBigBlock)
+canon_big_kernel(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                 int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, const int32_t *big_list,
+                 const int32_t *big_count)
+{
+    extern __shared__ int32_t sbuf[];  // kBigRow ints + 32 ints of wave counts
+    int32_t *wcnt = sbuf + kBigRow;
+    const int nbig = *big_count;
+    const int t = threadIdx.x, l = lane(), wid = t / GM_WAVE;
+    for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
+        const int32_t v = big_list[r];
+        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
+        int P = 2048;
+        while (P < d) P <<= 1;
+        for (int i = t; i < P; i += blockDim.x) sbuf[i] = i < d ? col[a + i] : GM_INF_ID;
+        __syncthreads();
+        for (int kk = 2; kk <= P; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int i = t; i < P; i += blockDim.x) {
+                    int q = i ^ j;
+                    if (q > i) {
+                        int x = sbuf[i], y = sbuf[q];
+                        bool up = (i & kk) == 0;
+                        if ((x > y) == up) { sbuf[i] = y; sbuf[q] = x; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        int base = 0;
+        for (int c = 0; c < P; c += blockDim.x) {
+            int i = c + t;
+            int x = sbuf[i];
+            bool keep = x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1]);
+            unsigned long long m = __ballot(keep);
+            if (l == 0) wcnt[wid] = __popcll(m);
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int w = 0; w < (int)(blockDim.x / GM_WAVE); ++w) {
+                int cw = wcnt[w];
+                if (w < wid) before += cw;
+                total += cw;
+            }
+            if (keep) tmp[a + base + before + lanes_below(m)] = x;
+            base += total;
+            __syncthreads();
+        }
+        if (t == 0) cnt[v] = base;
+        __syncthreads();
+    }
+}
+
+// Rows longer than kBigRow: mark neighbours in a bitmap of n bits (one bitmap
+// per workgroup, in scratch), then emit the set bits in order.
+__global__ void __launch_bounds__(kBigBlock)
+canon_huge_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, const int32_t *huge_list,
+                  const int32_t *huge_count, uint32_t *bitmaps)
+{
+    __shared__ int32_t part[kBigBlock];
+    const int nhuge = *huge_count;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    const int t = threadIdx.x;
+    for (int r = blockIdx.x; r < nhuge; r += gridDim.x) {
+        const int32_t v = huge_list[r];
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        for (int64_t i = t; i < words; i += blockDim.x) bm[i] = 0u;
+        __threadfence();
+        __syncthreads();
+        for (int32_t e = a + t; e < b; e += blockDim.x) {
+            int32_t w = col[e];
+            if (w != v) atomicOr(&bm[w >> 5], 1u << (w & 31));
+        }
+        __threadfence();
+        __syncthreads();
+        // contiguous word range per thread
+        const int64_t per = (words + blockDim.x - 1) / blockDim.x;
+        const int64_t w0 = min(words, (int64_t)t * per), w1 = min(words, w0 + per);
+        int mine = 0;
+        for (int64_t i = w0; i < w1; ++i)
+            mine += __popc(__hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        part[t] = mine;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+            int x = t >= o ? part[t - o] : 0;
+            __syncthreads();
+            part[t] += x;
+            __syncthreads();
+        }
+        int pos = part[t] - mine;
+        for (int64_t i = w0; i < w1; ++i) {
+            uint32_t bits = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (bits) {
+                int bit = __ffs(bits) - 1;
+                bits &= bits - 1;
+                tmp[a + pos++] = (int32_t)(i * 32 + bit);
+            }
+        }
+        if (t == blockDim.x - 1) cnt[v] = part[t];
+        __syncthreads();
+    }
+}
+
+__global__ void canon_copy_kernel(int32_t n, const int32_t *__restrict__ row_ptr_in,
+                                  const int32_t *__restrict__ tmp, const int32_t *__restrict__ row_ptr_out,
+                                  int32_t *__restrict__ col_out)
+{
+    const int waves = blockDim.x / GM_WAVE;
+    for (int64_t v = (int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE; v < n;
+         v += (int64_t)gridDim.x * waves) {
+        const int32_t a = row_ptr_in[v], o = row_ptr_out[v], c = row_ptr_out[v + 1] - o;
+        for (int32_t i = lane(); i < c; i += GM_WAVE) col_out[o + i] = tmp[a + i];
+    }
+}
+
+// ------------------------------------------------------ exclusive scan ---
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ int block_excl_scan(int x, int *sh, int *total)
+{
+    // sh: kScanBlock / 64 ints
+    const int l = lane(), wid = threadIdx.x / GM_WAVE;
+    int inc = wave_incl_scan(x);
+    if (l == GM_WAVE - 1) sh[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < kScanBlock / GM_WAVE; ++w) {
+        int s = sh[w];
+        if (w < wid) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+scan_tile_sums_kernel(const int32_t *__restrict__ in, int64_t len, int32_t *__restrict__ sums)
+{
+    __shared__ int sh[kScanBlock / GM_WAVE];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < len) s += in[base + i];
+    int total;
+    block_excl_scan(s, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the tile sums in place, carrying across chunks.
+__global__ void __launch_bounds__(kScanBlock)
+scan_sums_kernel(int32_t *sums, int64_t ntiles)
+{
+    __shared__ int sh[kScanBlock / GM_WAVE];
+    int carry = 0;
+    for (int64_t c = 0; c < ntiles; c += kScanBlock) {
+        int64_t i = c + threadIdx.x;
+        int x = i < ntiles ? sums[i] : 0;
+        int total;
+        int ex = block_excl_scan(x, sh, &total);
+        if (i < ntiles) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock)
+scan_apply_kernel(const int32_t *__restrict__ in, int64_t len, const int32_t *__restrict__ sums,
+                  int32_t *__restrict__ out)
+{
+    __shared__ int sh[kScanBlock / GM_WAVE];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int vals[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        vals[i] = base + i < len ? in[base + i] : 0;
+        s += vals[i];
+    }
+    int total;
+    int ex = block_excl_scan(s, sh, &total) + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < len) out[base + i] = ex;
+        ex += vals[i];
+    }
+    if (base < len && base + kScanItems >= len) out[len] = ex;  // thread holding the last item
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t count, int32_t value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+int grid_for(int64_t items, int per_block, int cap = 65536)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+hipError_t launch_validate_structure(int32_t n, int32_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, int *err, hipStream_t s)
+{
+    int64_t items = (int64_t)n > nnz ? n : nnz;
+    hipLaunchKernelGGL(validate_structure_kernel, dim3(grid_for(items, 256, 8192)), dim3(256), 0, s,
+                       n, nnz, row_ptr, col_idx, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_symmetric(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                  int *err, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_symmetric_kernel, dim3(grid_for(n, 4, 16384)), dim3(256), 0, s, n,
+                       row_ptr, col_idx, err);
+    return hipGetLastError();
+}
+
+size_t exclusive_scan_scratch_bytes(int64_t len)
+{
+    int64_t tiles = (len + kScanTile - 1) / kScanTile;
+    return align256((size_t)(tiles + 1) * sizeof(int32_t));
+}
+
+hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t len, void *scratch,
+                                 hipStream_t s)
+{
+    if (len <= 0) {
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, out, (int64_t)1, 0);
+        return hipGetLastError();
+    }
+    int64_t tiles = (len + kScanTile - 1) / kScanTile;
+    int32_t *sums = (int32_t *)scratch;
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, in, len, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanBlock), 0, s, sums, tiles);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, in, len, sums, out);
+    return hipGetLastError();
+}
+
+size_t canon_scratch_bytes(int32_t n, int32_t nnz)
+{
+    size_t b = 0;
+    b += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));  // tmp
+    b += align256((size_t)(n + 1) * sizeof(int32_t));              // cnt
+    b += align256((size_t)(n + 1) * sizeof(int32_t));              // big list
+    b += align256((size_t)(n + 1) * sizeof(int32_t));              // huge list
+    b += align256(2 * sizeof(int32_t));                            // counters
+    b += align256((size_t)kHugeBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));
+    b += exclusive_scan_scratch_bytes(n);
+    return b;
+}
+
+hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, int32_t *out_row_ptr, int32_t *out_col,
+                               void *scratch, hipStream_t s)
+{
+    char *p = (char *)scratch;
+    int32_t *tmp = (int32_t *)p;      p += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    int32_t *cnt = (int32_t *)p;      p += align256((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *big = (int32_t *)p;      p += align256((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *huge = (int32_t *)p;     p += align256((size_t)(n + 1) * sizeof(int32_t));
+    int32_t *counters = (int32_t *)p; p += align256(2 * sizeof(int32_t));
+    uint32_t *bitmaps = (uint32_t *)p; p += align256((size_t)kHugeBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));
+    void *scan_scratch = p;
+    if (n <= 0) {
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, out_row_ptr, (int64_t)1, 0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)2, 0);
+    hipLaunchKernelGGL(canon_rows_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 32768)),
+                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, tmp, cnt, big, counters, huge,
+                       counters + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t big_lds = (kBigRow + 32) * sizeof(int32_t);
+    static bool lds_set = false;
+    if (!lds_set) {
+        e = hipFuncSetAttribute((const void *)canon_big_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)big_lds);
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
+    hipLaunchKernelGGL(canon_big_kernel, dim3(512), dim3(kBigBlock), big_lds, s, row_ptr, col_idx,
+                       tmp, cnt, big, counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(canon_huge_kernel, dim3(kHugeBlocks), dim3(kBigBlock), 0, s, n, row_ptr,
+                       col_idx, tmp, cnt, huge, counters + 1, bitmaps);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_exclusive_scan(cnt, out_row_ptr, n, scan_scratch, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(canon_copy_kernel, dim3(grid_for(n, 4, 32768)), dim3(256), 0, s, n, row_ptr,
+                       tmp, out_row_ptr, out_col);
+    return hipGetLastError();
+}
+
+}  // namespace gm

@@ -1,0 +1,153 @@
+// Internal launchers of the gfx950 kernels (host side).  Every launcher
+// enqueues on `stream` and returns the launch status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gm {
+
+// ----------------------------------------------------------------- CSR ---
+// Structural check of an input CSR.  Sets bits in *err (device int):
+//   1 row_ptr[0] != 0, 2 row_ptr not monotone or outside [0, nnz],
+//   4 row_ptr[n] != nnz, 8 col_idx entry outside [0, n).
+hipError_t launch_validate_structure(int32_t n, int32_t nnz, const int32_t *row_ptr,
+                                     const int32_t *col_idx, int *err, hipStream_t s);
+// Symmetry check of a canonical CSR: bit 16 in *err if some (u, w) lacks (w, u).
+hipError_t launch_check_symmetric(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                  int *err, hipStream_t s);
+
+// Scratch needed by launch_canonicalize for a graph of this size (bytes).
+size_t canon_scratch_bytes(int32_t n, int32_t nnz);
+// Canonical CSR (rows sorted, unique, no self-loops) of an arbitrary one.
+// out_row_ptr: n + 1 entries; out_col: nnz entries (capacity).  The number of
+// kept entries ends up in out_row_ptr[n].
+hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, int32_t *out_row_ptr, int32_t *out_col,
+                               void *scratch, hipStream_t s);
+
+// Exclusive prefix sum of int32 `in` (len values) into `out` (len + 1 values,
+// out[len] = total).  scratch: exclusive_scan_scratch_bytes(len).
+size_t exclusive_scan_scratch_bytes(int64_t len);
+hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t len, void *scratch,
+                                 hipStream_t s);
+
+// ------------------------------------------------------ all-source BFS ---
+// Multi-source bit-parallel BFS over groups of W = 64 * words sources.
+// Layout of every state array: [group][vertex][word] of uint64.
+struct MsbfsArgs {
+    int32_t n;
+    const int32_t *row_ptr;   // canonical CSR
+    const int32_t *col;
+    int32_t words;            // 64-bit words per vertex per group (1, 2, 4 or 8)
+    int32_t groups;           // groups in this round
+    int32_t slot0;            // first global slot of this round
+    int32_t n_slots;          // slots in this round (<= groups * 64 * words)
+    const int32_t *usrc;      // sorted unique sources, indexed by global slot
+    int32_t n_usrc;           // total slots
+    const int32_t *slot_of;   // vertex -> global slot or -1
+    uint64_t *front[2];       // rotating frontier / next arrays
+    uint64_t *visited;
+    uint64_t *planes;         // 8 bit-planes of the discovery level, plane-major
+    size_t plane_stride;      // uint64 elements per plane (= groups * n * words)
+    unsigned long long *stats; // [level][group] new bits found at that level
+    int32_t stats_groups;     // row length of stats
+};
+hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
+// One BFS level: commit the previous level's frontier, then find level `level`.
+// commit_only: only commit (used after the last level the caller wants).
+hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s);
+// Hop rows of this round's slots: hop_out + slot_row[slot] * row_stride
+// receives the n hop bytes of that slot (planes_used bit-planes committed).
+hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
+                             const int64_t *slot_row, int64_t row_stride, hipStream_t s);
+// Same, also accumulating per-slot counts of vertices at hops 1..16 into
+// lvl_cnt[local_slot * 16 + h - 1] (zeroed by the caller).
+hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
+                                     const int64_t *slot_row, int64_t row_stride,
+                                     unsigned int *lvl_cnt, hipStream_t s);
+
+// ------------------------------------------------------- kNN selection ---
+// Rows: for r in [0, rows): hop row hop_rows + row_of[r] * row_stride (n bytes),
+// source vertex src_of[r]; writes ids/hops rows out_row[r].
+hipError_t launch_knn_select(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
+                             const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
+                             const int64_t *out_row, int32_t *ids, uint8_t *hops, hipStream_t s);
+// Same, with per-row counts of vertices at hops 1..16 (lvl_cnt[r * 16 + h - 1])
+// from launch_msbfs_hops_counted; used when k <= 16.
+hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
+                                     const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
+                                     const int64_t *out_row, const unsigned int *lvl_cnt,
+                                     int32_t *ids, uint8_t *hops, hipStream_t s);
+
+// Copy output rows src_row -> dst_row for repeated sources (pairs on device).
+hipError_t launch_copy_rows(int32_t pairs, const int64_t *dst_src, int32_t k, int32_t n,
+                            int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s);
+
+// ---------------------------------------------------------- partial BFS ---
+struct PartialArgs {
+    int32_t k;
+    // single graph
+    int32_t n;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    // outputs (rows indexed by vertex)
+    int32_t *ids;
+    uint8_t *hops;
+    float *weights;           // optional fused membership (may be NULL)
+    float *rho;
+    float *sigma;
+};
+hipError_t launch_partial_bfs(const PartialArgs &a, hipStream_t s);
+
+// Batched form: packed graphs, persistent waves pulling vertex chunks.
+struct BatchArgs {
+    int32_t k;
+    int32_t n_graphs;
+    int64_t total_vertices;
+    const int64_t *vtx_offset;
+    const int64_t *edge_offset;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    int32_t *ids;
+    uint8_t *hops;
+    float *weights;
+    float *rho;
+    float *sigma;
+    unsigned long long *work_counter;  // zeroed by launch_batch_reset
+    int32_t chunk;            // vertices taken per grab (<= batch_chunk_rows(k))
+    int32_t waves_per_block;
+    int32_t blocks;
+};
+hipError_t launch_batch_reset(unsigned long long *counter, hipStream_t s);
+hipError_t launch_partial_batch(const BatchArgs &a, hipStream_t s);
+// Largest chunk (rows per grab) the batch/jobs kernels accept for this k.
+int batch_chunk_rows(int k);
+
+// Served form: resident jobs and the chunks of rows of one device iteration.
+struct DevJob {
+    const int32_t *row_ptr;   // canonical CSR of the job
+    const int32_t *col;
+    int32_t n, k;
+    int32_t *ids;
+    uint8_t *hops;
+    float *weights;           // NULL: no membership
+    float *rho;
+    float *sigma;
+};
+struct JobChunk {
+    int32_t job;              // index into the job table
+    int32_t begin, end;       // rows [begin, end), end - begin <= batch_chunk_rows(k)
+    int32_t pad;
+};
+hipError_t launch_partial_jobs(const DevJob *jobs, const JobChunk *chunks, int32_t n_chunks, int max_k,
+                               unsigned long long *counter, int blocks, hipStream_t s);
+// Co-resident blocks of the batch kernel on the current device.
+int partial_batch_max_blocks();
+
+// ----------------------------------------------------------- membership ---
+hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,
+                             float *rho, float *sigma, hipStream_t s);
+
+}  // namespace gm

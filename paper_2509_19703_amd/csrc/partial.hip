@@ -1,0 +1,337 @@
+// Truncated partial BFS (SL-/SSSL-GUMAP steps C0 + C1, Sec. 3.3.1, Alg. 4)
+// and the UMAP membership kernels (Sec. 2.1).
+//
+// One wavefront per source v.  Level h+1 of the BFS consists of the
+// neighbours of level h not seen before.  Adjacency rows are sorted, so the
+// level can be produced in ascending id order by a k-way merge of the sorted
+// rows of level h (one row head per lane, wave-wide minimum per step): every
+// value comes out once, values already seen (v and the earlier levels, at
+// most k + 1 of them, held one per lane) are skipped, and the merge stops the
+// moment the k-th neighbour is taken.  Levels before the last therefore come
+// out complete and in id order, and the last one contributes exactly its
+// smallest ids -- the (hop, id) order -- while each neighbour row is read at
+// most (needed + seen) entries deep, however large its degree.
+#include "device.h"
+#include "kernels.h"
+#include "membership.h"
+
+namespace gm {
+
+namespace {
+
+constexpr int kPartialWaves = 4;
+constexpr int kMaxRow = 256;     // k <= 254 picks; frontier and seen sets < 256
+constexpr int kStashBytes = 2048; // hops of one chunk kept for the fused membership
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct WaveLds {
+    int32_t fa[kMaxRow];      // current level (frontier)
+    int32_t fb[kMaxRow];      // level being built
+    int32_t seen[kMaxRow];    // v and all completed levels
+    int32_t row_ids[kMaxRow];
+    uint8_t row_hops[kMaxRow];
+};
+
+// NQ: 64-entry chunks needed for k + 1 seen vertices (1, 2 or 4).
+// Leaves the row (ids, hops, padded) in s.row_ids / s.row_hops.
+template <int NQ>
+__device__ void partial_row(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            int32_t v, int k, WaveLds &s)
+{
+    const int l = lane();
+    if (l == 0) {
+        s.fa[0] = v;
+        s.seen[0] = v;
+    }
+    wave_sync();
+    int nf = 1, nseen = 1, taken = 0, h = 0;
+    int32_t *fa = s.fa, *fb = s.fb;
+    while (taken < k && nf > 0) {
+        ++h;
+        int32_t p[NQ], e[NQ], hv[NQ], sv[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int j = l + 64 * q;
+            hv[q] = GM_INF_ID;
+            p[q] = 0;
+            e[q] = 0;
+            if (j < nf) {
+                const int32_t u = fa[j];
+                p[q] = rp[u];
+                e[q] = rp[u + 1];
+                if (p[q] < e[q]) hv[q] = col[p[q]];
+            }
+            sv[q] = j < nseen ? s.seen[j] : -1;
+        }
+        int nnew = 0;
+        for (;;) {
+            int mine = hv[0];
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) mine = min(mine, hv[q]);
+            const int m = wave_min(mine);
+            if (m == GM_INF_ID) break;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (hv[q] == m) {
+                    ++p[q];
+                    hv[q] = p[q] < e[q] ? col[p[q]] : GM_INF_ID;
+                }
+            }
+            bool hit = false;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) hit |= (sv[q] == m);
+            if (__ballot(hit) == 0ull) {
+                if (l == 0) {
+                    fb[nnew] = m;
+                    s.row_ids[taken] = m;
+                    s.row_hops[taken] = (uint8_t)h;
+                }
+                ++nnew;
+                ++taken;
+                if (taken == k) break;
+            }
+        }
+        wave_sync();
+        for (int j = l; j < nnew; j += 64) s.seen[nseen + j] = fb[j];
+        nseen += nnew;
+        int32_t *t = fa;
+        fa = fb;
+        fb = t;
+        nf = nnew;
+        wave_sync();
+    }
+    for (int i = taken + l; i < k; i += 64) {
+        s.row_ids[i] = -1;
+        s.row_hops[i] = 255;
+    }
+    wave_sync();
+}
+
+template <int NQ>
+__global__ void __launch_bounds__(kPartialWaves * GM_WAVE)
+partial_bfs_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int k,
+                   int32_t *__restrict__ ids, uint8_t *__restrict__ hops)
+{
+    __shared__ WaveLds lds[kPartialWaves];
+    const int wid = threadIdx.x / GM_WAVE, l = lane();
+    WaveLds &s = lds[wid];
+    for (int64_t v = (int64_t)blockIdx.x * kPartialWaves + wid; v < n;
+         v += (int64_t)gridDim.x * kPartialWaves) {
+        partial_row<NQ>(rp, col, (int32_t)v, k, s);
+        const int64_t o = v * k;
+        for (int i = l; i < k; i += 64) {
+            ids[o + i] = s.row_ids[i];
+            hops[o + i] = s.row_hops[i];
+        }
+        wave_sync();
+    }
+}
+
+// Rows [begin, end) of one graph (begin..end at most kStashBytes / k rows):
+// partial BFS per row, rows written out, and, when weights are wanted, the
+// membership of the chunk's rows computed one row per lane from the hops
+// kept in LDS.  Output row of local vertex v is out_row0 + (v - begin).
+template <int NQ>
+__device__ void chunk_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int k,
+                           int32_t begin, int32_t end, int64_t out_row0, int32_t *ids, uint8_t *hops,
+                           float *weights, float *rho, float *sigma, WaveLds &s, uint8_t *stash)
+{
+    const int l = lane();
+    for (int32_t v = begin; v < end; ++v) {
+        partial_row<NQ>(rp, col, v, k, s);
+        const int slot = v - begin;
+        const int64_t o = (out_row0 + slot) * k;
+        for (int i = l; i < k; i += 64) {
+            ids[o + i] = s.row_ids[i];
+            hops[o + i] = s.row_hops[i];
+            stash[slot * k + i] = s.row_hops[i];
+        }
+        wave_sync();
+    }
+    if (weights && l < end - begin) {
+        const uint8_t *hrow = stash + l * k;
+        const int64_t r = out_row0 + l;
+        membership_row([&](int j) { return (int)hrow[j]; }, k, weights + r * k, rho ? rho + r : nullptr,
+                       sigma ? sigma + r : nullptr);
+    }
+    wave_sync();
+}
+
+// Batched persistent form: waves take chunks of packed vertices from a device
+// counter (a chunk may span several graphs).
+template <int NQ>
+__global__ void __launch_bounds__(kPartialWaves * GM_WAVE)
+partial_batch_kernel(BatchArgs a)
+{
+    __shared__ WaveLds lds[kPartialWaves];
+    __shared__ uint8_t stash[kPartialWaves][kStashBytes];
+    const int wid = threadIdx.x / GM_WAVE, l = lane();
+    WaveLds &s = lds[wid];
+    for (;;) {
+        unsigned long long start = 0;
+        if (l == 0) start = atomicAdd(a.work_counter, (unsigned long long)a.chunk);
+        start = __shfl(start, 0, GM_WAVE);
+        if ((int64_t)start >= a.total_vertices) break;
+        const int64_t end = min((int64_t)start + a.chunk, a.total_vertices);
+        // graph of the first vertex: last g with vtx_offset[g] <= start
+        int lo = 0, hi = a.n_graphs;   // vtx_offset[lo] <= start < vtx_offset[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.vtx_offset[mid] <= (int64_t)start) lo = mid;
+            else hi = mid;
+        }
+        int64_t gi = (int64_t)start;
+        for (int g = lo; gi < end; ++g) {
+            const int64_t voff = a.vtx_offset[g], vend = a.vtx_offset[g + 1];
+            if (vend <= gi) continue;
+            const int64_t stop = min(end, vend);
+            chunk_rows<NQ>(a.row_ptr + voff + g, a.col + a.edge_offset[g], a.k, (int32_t)(gi - voff),
+                           (int32_t)(stop - voff), gi, a.ids, a.hops, a.weights, a.rho, a.sigma, s,
+                           stash[wid]);
+            gi = stop;
+        }
+    }
+}
+
+// Served form: an explicit list of (job, first row, end row) chunks over a
+// table of resident jobs.
+template <int NQ>
+__global__ void __launch_bounds__(kPartialWaves * GM_WAVE)
+partial_jobs_kernel(const DevJob *__restrict__ jobs, const JobChunk *__restrict__ chunks, int32_t n_chunks,
+                    unsigned long long *counter)
+{
+    __shared__ WaveLds lds[kPartialWaves];
+    __shared__ uint8_t stash[kPartialWaves][kStashBytes];
+    const int wid = threadIdx.x / GM_WAVE, l = lane();
+    WaveLds &s = lds[wid];
+    for (;;) {
+        unsigned long long c = 0;
+        if (l == 0) c = atomicAdd(counter, 1ull);
+        c = __shfl(c, 0, GM_WAVE);
+        if ((int64_t)c >= n_chunks) break;
+        const JobChunk ch = chunks[c];
+        const DevJob &j = jobs[ch.job];
+        chunk_rows<NQ>(j.row_ptr, j.col, j.k, ch.begin, ch.end, ch.begin, j.ids, j.hops, j.weights, j.rho,
+                       j.sigma, s, stash[wid]);
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
+
+__global__ void membership_kernel(int32_t rows, int32_t k, const uint8_t *__restrict__ hops,
+                                  float *__restrict__ weights, float *__restrict__ rho,
+                                  float *__restrict__ sigma)
+{
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t *h = hops + r * k;
+        membership_row([&](int j) { return (int)h[j]; }, k, weights + r * k, rho ? rho + r : nullptr,
+                       sigma ? sigma + r : nullptr);
+    }
+}
+
+int nq_for(int k) { return k + 1 <= 64 ? 1 : (k + 1 <= 128 ? 2 : 4); }
+
+}  // namespace
+
+hipError_t launch_partial_bfs(const PartialArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    int64_t blocks64 = ((int64_t)a.n + kPartialWaves - 1) / kPartialWaves;
+    int blocks = (int)(blocks64 > 1048576 ? 1048576 : blocks64);
+    switch (nq_for(a.k)) {
+    case 1:
+        hipLaunchKernelGGL(partial_bfs_kernel<1>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s,
+                           a.n, a.row_ptr, a.col, a.k, a.ids, a.hops);
+        break;
+    case 2:
+        hipLaunchKernelGGL(partial_bfs_kernel<2>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s,
+                           a.n, a.row_ptr, a.col, a.k, a.ids, a.hops);
+        break;
+    default:
+        hipLaunchKernelGGL(partial_bfs_kernel<4>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s,
+                           a.n, a.row_ptr, a.col, a.k, a.ids, a.hops);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(unsigned long long *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+int batch_chunk_rows(int k)
+{
+    int c = kStashBytes / k;
+    return c > 64 ? 64 : (c < 1 ? 1 : c);
+}
+
+hipError_t launch_partial_batch(const BatchArgs &a, hipStream_t s)
+{
+    if (a.total_vertices <= 0) return hipSuccess;
+    if (a.chunk < 1 || a.chunk > batch_chunk_rows(a.k)) return hipErrorInvalidValue;
+    switch (nq_for(a.k)) {
+    case 1:
+        hipLaunchKernelGGL(partial_batch_kernel<1>, dim3(a.blocks), dim3(kPartialWaves * GM_WAVE), 0, s, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL(partial_batch_kernel<2>, dim3(a.blocks), dim3(kPartialWaves * GM_WAVE), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(partial_batch_kernel<4>, dim3(a.blocks), dim3(kPartialWaves * GM_WAVE), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_partial_jobs(const DevJob *jobs, const JobChunk *chunks, int32_t n_chunks, int max_k,
+                               unsigned long long *counter, int blocks, hipStream_t s)
+{
+    if (n_chunks <= 0) return hipSuccess;
+    switch (nq_for(max_k)) {
+    case 1:
+        hipLaunchKernelGGL(partial_jobs_kernel<1>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s, jobs,
+                           chunks, n_chunks, counter);
+        break;
+    case 2:
+        hipLaunchKernelGGL(partial_jobs_kernel<2>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s, jobs,
+                           chunks, n_chunks, counter);
+        break;
+    default:
+        hipLaunchKernelGGL(partial_jobs_kernel<4>, dim3(blocks), dim3(kPartialWaves * GM_WAVE), 0, s, jobs,
+                           chunks, n_chunks, counter);
+        break;
+    }
+    return hipGetLastError();
+}
+
+int partial_batch_max_blocks()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, partial_batch_kernel<1>,
+                                                     kPartialWaves * GM_WAVE, 0) != hipSuccess || per < 1)
+        per = 4;
+    return cus * per;
+}
+
+hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,
+                             float *rho, float *sigma, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    int blocks = (rows + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(membership_kernel, dim3(blocks), dim3(256), 0, s, rows, k, hops, weights, rho, sigma);
+    return hipGetLastError();
+}
+
+}  // namespace gm

@@ -1,0 +1,29 @@
+// Helper launchers used by the host orchestration (enqueue only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gm {
+
+hipError_t fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+hipError_t iota_i32(int32_t *p, int64_t count, hipStream_t s);
+hipError_t iota_i64(int64_t *p, int64_t count, int64_t start, hipStream_t s);
+// slot_of[usrc[i]] = i
+hipError_t scatter_slots(const int32_t *usrc, int32_t count, int32_t *slot_of, hipStream_t s);
+// bit 32 in *err unless every row is strictly increasing without self-loops
+hipError_t check_sorted(int32_t n, const int32_t *rp, const int32_t *col, int *err, hipStream_t s);
+// bits 128/256 in *err for malformed row pointers / ids of a packed batch whose
+// offsets are already known to be monotone and consistent with the totals
+hipError_t validate_batch(int32_t n_graphs, const int64_t *voff, const int64_t *eoff, const int32_t *rp,
+                          const int32_t *col, int64_t total_v, int64_t total_e, int *err, hipStream_t s);
+// packed per-graph CSR -> one CSR of the disjoint union (global ids)
+hipError_t batch_to_union(int32_t n_graphs, const int64_t *voff, const int64_t *eoff, const int32_t *rp,
+                          const int32_t *col, int64_t total_v, int64_t total_e, int32_t *urp,
+                          int32_t *ucol, hipStream_t s);
+// union CSR -> packed per-graph CSR with new edge offsets
+hipError_t union_to_batch(int32_t n_graphs, const int64_t *voff, const int32_t *urp, const int32_t *ucol,
+                          int64_t total_v, int64_t total_e_canon, int64_t *eoff_out, int32_t *rp_out,
+                          int32_t *col_out, hipStream_t s);
+
+}  // namespace gm

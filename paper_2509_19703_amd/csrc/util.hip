@@ -1,0 +1,221 @@
+// Small helper kernels of the host orchestration: fills, slot maps, checks
+// of sorted input, and the conversions between the packed per-graph batch
+// layout and one disjoint-union CSR.
+#include "device.h"
+#include "util.h"
+
+namespace gm {
+
+namespace {
+
+int blocks_for(int64_t items, int threads = 256, int cap = 65536)
+{
+    int64_t b = (items + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+#define GRID_STRIDE(i, count)                                                              \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (count);         \
+         i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void fill_i32_k(int32_t *p, int64_t count, int32_t v) { GRID_STRIDE(i, count) p[i] = v; }
+__global__ void iota_i32_k(int32_t *p, int64_t count) { GRID_STRIDE(i, count) p[i] = (int32_t)i; }
+__global__ void iota_i64_k(int64_t *p, int64_t count, int64_t start) { GRID_STRIDE(i, count) p[i] = start + i; }
+__global__ void scatter_slots_k(const int32_t *usrc, int32_t count, int32_t *slot_of)
+{
+    GRID_STRIDE(i, count) slot_of[usrc[i]] = (int32_t)i;
+}
+
+// Rows strictly increasing, no self-loops (bit 32 of *err otherwise).
+__global__ void check_sorted_k(int32_t n, const int32_t *rp, const int32_t *col, int *err)
+{
+    int bad = 0;
+    GRID_STRIDE(v, (int64_t)n)
+    {
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            if (col[e] == v) bad = 32;
+            if (e > rp[v] && col[e] <= col[e - 1]) bad = 32;
+        }
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__device__ __forceinline__ int graph_of(const int64_t *off, int32_t n_graphs, int64_t x)
+{
+    // last g with off[g] <= x (off[0] = 0 <= x < off[n_graphs])
+    int lo = 0, hi = n_graphs;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Packed batch structure (offsets already checked on the host): local row
+// pointers consistent and local ids in range.  Bits: 128 row pointers, 256 ids.
+__global__ void validate_batch_k(int32_t n_graphs, const int64_t *voff, const int64_t *eoff,
+                                 const int32_t *rp, const int32_t *col, int64_t total_v,
+                                 int64_t total_e, int *err)
+{
+    int bad = 0;
+    GRID_STRIDE(i, total_v + n_graphs)
+    {
+        // entry i of the packed row pointers belongs to graph g with
+        // voff[g] + g <= i <= voff[g + 1] + g
+        int lo = 0, hi = n_graphs;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (voff[mid] + mid <= i) lo = mid;
+            else hi = mid;
+        }
+        const int g = lo;
+        const int64_t local = i - (voff[g] + g);
+        const int64_t ng = voff[g + 1] - voff[g], ne = eoff[g + 1] - eoff[g];
+        const int32_t x = rp[i];
+        if (local == 0 && x != 0) bad |= 128;
+        if (local == ng && x != ne) bad |= 128;
+        if (x < 0 || x > ne) bad |= 128;
+        if (local < ng && rp[i + 1] < x) bad |= 128;
+    }
+    GRID_STRIDE(e, total_e)
+    {
+        const int g = graph_of(eoff, n_graphs, e);
+        const int64_t ng = voff[g + 1] - voff[g];
+        if (col[e] < 0 || col[e] >= ng) bad |= 256;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void batch_to_union_rp_k(int32_t n_graphs, const int64_t *voff, const int64_t *eoff,
+                                    const int32_t *rp, int64_t total_v, int64_t total_e, int32_t *urp)
+{
+    GRID_STRIDE(i, total_v + 1)
+    {
+        if (i == total_v) {
+            urp[i] = (int32_t)total_e;
+        } else {
+            const int g = graph_of(voff, n_graphs, i);
+            urp[i] = (int32_t)(eoff[g] + rp[i + g]);
+        }
+    }
+}
+
+__global__ void batch_to_union_col_k(int32_t n_graphs, const int64_t *voff, const int64_t *eoff,
+                                     const int32_t *col, int64_t total_e, int32_t *ucol)
+{
+    GRID_STRIDE(e, total_e)
+    {
+        const int g = graph_of(eoff, n_graphs, e);
+        ucol[e] = (int32_t)(col[e] + voff[g]);
+    }
+}
+
+__global__ void union_edge_offsets_k(int32_t n_graphs, const int64_t *voff, const int32_t *urp,
+                                     int64_t *eoff_out)
+{
+    GRID_STRIDE(g, (int64_t)n_graphs + 1) eoff_out[g] = urp[voff[g]];
+}
+
+__global__ void union_to_batch_rp_k(int32_t n_graphs, const int64_t *voff, const int64_t *eoff,
+                                    const int32_t *urp, int64_t total_v, int32_t *rp)
+{
+    GRID_STRIDE(i, total_v + n_graphs)
+    {
+        int lo = 0, hi = n_graphs;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (voff[mid] + mid <= i) lo = mid;
+            else hi = mid;
+        }
+        const int g = lo;
+        const int64_t uv = i - g;   // union row index (the terminal entry maps to voff[g+1])
+        rp[i] = (int32_t)(urp[uv] - eoff[g]);
+    }
+}
+
+__global__ void union_to_batch_col_k(int32_t n_graphs, const int64_t *voff, const int64_t *eoff,
+                                     const int32_t *ucol, int64_t total_e, int32_t *col)
+{
+    GRID_STRIDE(e, total_e)
+    {
+        const int g = graph_of(eoff, n_graphs, e);
+        col[e] = (int32_t)(ucol[e] - voff[g]);
+    }
+}
+
+}  // namespace
+
+hipError_t fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_k, dim3(blocks_for(count)), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t iota_i32(int32_t *p, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_i32_k, dim3(blocks_for(count)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t iota_i64(int64_t *p, int64_t count, int64_t start, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_i64_k, dim3(blocks_for(count)), dim3(256), 0, s, p, count, start);
+    return hipGetLastError();
+}
+
+hipError_t scatter_slots(const int32_t *usrc, int32_t count, int32_t *slot_of, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_slots_k, dim3(blocks_for(count)), dim3(256), 0, s, usrc, count, slot_of);
+    return hipGetLastError();
+}
+
+hipError_t check_sorted(int32_t n, const int32_t *rp, const int32_t *col, int *err, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(check_sorted_k, dim3(blocks_for(n)), dim3(256), 0, s, n, rp, col, err);
+    return hipGetLastError();
+}
+
+hipError_t validate_batch(int32_t n_graphs, const int64_t *voff, const int64_t *eoff, const int32_t *rp,
+                          const int32_t *col, int64_t total_v, int64_t total_e, int *err, hipStream_t s)
+{
+    int64_t items = total_v + n_graphs > total_e ? total_v + n_graphs : total_e;
+    hipLaunchKernelGGL(validate_batch_k, dim3(blocks_for(items, 256, 16384)), dim3(256), 0, s,
+                       n_graphs, voff, eoff, rp, col, total_v, total_e, err);
+    return hipGetLastError();
+}
+
+hipError_t batch_to_union(int32_t n_graphs, const int64_t *voff, const int64_t *eoff, const int32_t *rp,
+                          const int32_t *col, int64_t total_v, int64_t total_e, int32_t *urp,
+                          int32_t *ucol, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_to_union_rp_k, dim3(blocks_for(total_v + 1)), dim3(256), 0, s, n_graphs,
+                       voff, eoff, rp, total_v, total_e, urp);
+    if (total_e > 0)
+        hipLaunchKernelGGL(batch_to_union_col_k, dim3(blocks_for(total_e)), dim3(256), 0, s, n_graphs,
+                           voff, eoff, col, total_e, ucol);
+    return hipGetLastError();
+}
+
+hipError_t union_to_batch(int32_t n_graphs, const int64_t *voff, const int32_t *urp, const int32_t *ucol,
+                          int64_t total_v, int64_t total_e_canon, int64_t *eoff_out, int32_t *rp_out,
+                          int32_t *col_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(union_edge_offsets_k, dim3(blocks_for((int64_t)n_graphs + 1)), dim3(256), 0, s,
+                       n_graphs, voff, urp, eoff_out);
+    hipLaunchKernelGGL(union_to_batch_rp_k, dim3(blocks_for(total_v + n_graphs)), dim3(256), 0, s,
+                       n_graphs, voff, eoff_out, urp, total_v, rp_out);
+    if (total_e_canon > 0)
+        hipLaunchKernelGGL(union_to_batch_col_k, dim3(blocks_for(total_e_canon)), dim3(256), 0, s,
+                           n_graphs, voff, eoff_out, ucol, total_e_canon, col_out);
+    return hipGetLastError();
+}
+
+}  // namespace gm

@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host (no GPU needed: these paths return before any device
+call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gumap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gumap_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(gumap):
+    names = declared_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(gumap.lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(gumap):
+    assert ctypes.sizeof(gumap.gumap_graph) == 32
+    assert ctypes.sizeof(gumap.gumap_batch) == 64
+
+
+def test_host_side_argument_errors(gumap):
+    lib = gumap.lib
+    g = gumap.gumap_graph(4, 0, None, None, 0)
+    # NULL graph
+    assert lib.gumap_knn_build(None, 5, None, 0, None, None, None, None) == gumap.EINVAL
+    assert "NULL" in gumap.last_error()
+    # k outside [1, 254]
+    for k in (0, -3, 255, 1000):
+        assert lib.gumap_knn_partial(ctypes.byref(g), k, None, None, None) == gumap.EINVAL
+    # row_ptr missing for n > 0
+    assert lib.gumap_knn_partial(ctypes.byref(g), 5, None, None, None) == gumap.EINVAL
+    bad = gumap.gumap_graph(-1, 0, None, None, 0)
+    assert lib.gumap_knn_partial(ctypes.byref(bad), 5, None, None, None) == gumap.EINVAL
+    unknown = gumap.gumap_graph(0, 0, None, None, 0x80)
+    assert lib.gumap_knn_partial(ctypes.byref(unknown), 5, None, None, None) == gumap.EINVAL
+    # empty graph is a successful no-op
+    empty = gumap.gumap_graph(0, 0, None, None, 0)
+    assert lib.gumap_knn_partial(ctypes.byref(empty), 5, None, None, None) == gumap.OK
+    assert lib.gumap_knn_build(ctypes.byref(empty), 5, None, 0, None, None, None, None) == gumap.OK
+    # membership: negative rows, bad k, zero rows
+    assert lib.gumap_membership(-1, 5, None, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_membership(3, 0, None, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_membership(0, 5, None, None, None, None, None) == gumap.OK
+    assert lib.gumap_membership(3, 5, None, None, None, None, None) == gumap.EINVAL
+    # batch
+    assert lib.gumap_knn_partial_batch(None, 5, None, None, None, None, None, None) == gumap.EINVAL
+    b = gumap.gumap_batch(0, 0, 0, None, None, None, None, 0)
+    assert lib.gumap_knn_partial_batch(ctypes.byref(b), 5, None, None, None, None, None, None) == gumap.OK
+    assert lib.gumap_knn_partial_batch(ctypes.byref(b), 0, None, None, None, None, None, None) == gumap.EINVAL
+    plan = ctypes.c_void_p()
+    unsorted = gumap.gumap_batch(0, 0, 0, None, None, None, None, 0)
+    assert lib.gumap_batch_plan_create(ctypes.byref(unsorted), 5, None, None, None, None, None, None,
+                                       ctypes.byref(plan)) == gumap.EINVAL
+
+
+def test_python_names_mirror_c_entry_points(gumap):
+    for name in ("gumap_knn_build", "gumap_knn_partial", "gumap_membership", "gumap_knn_partial_batch"):
+        assert callable(getattr(gumap, name))

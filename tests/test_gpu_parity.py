@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Bit-exact on neighbour ids, hops and hop matrices; weights within 1e-5
+relative (2^-126 absolute floor), rho bit-exact, sigma within 1e-5.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_util import assert_weights_close, first_mismatch, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs_small():
+    return [
+        ("grid32", G.grid_2d(32, 32)),
+        ("ba2000", G.ba(2000, 4, 11)),
+        ("rgg2000", G.rgg(2000, 8, 12)),
+        ("sbm2000", G.sbm(2000, 12, 13)),
+        ("er600", G.er(600, 0.1, 14)),
+        ("star300", G.star(300)),
+        ("complete40", G.complete(40)),
+        ("path200", G.path(200)),
+        ("union", G.disjoint_union([G.path(5), G.complete(4), G.empty(3), G.cycle(9), G.star(20)])),
+        ("hypercube8", G.hypercube(8)),
+        ("single", G.empty(1)),
+    ]
+
+
+def _check_build(gm, g, k, sources=None, hop_matrix=True, flags=0, dirty=False):
+    import torch
+    gi = G.dirty(g, 99) if dirty else g
+    rp, ci = to_dev(gi)
+    src_t = None if sources is None else torch.from_numpy(np.asarray(sources, np.int32)).cuda()
+    print("build n=%d k=%d rows=%s hm=%s flags=%d" % (g.n, k, "all" if sources is None else len(sources),
+                                                       hop_matrix, flags), flush=True)
+    ids, hops, hm = gm.knn_build(rp, ci, k, sources=src_t, hop_matrix=hop_matrix,
+                                 flags=flags | (0 if dirty else gm.CSR_SORTED))
+    oi, oh, ohm = O.knn_build(g, k, sources=sources, hop_matrix=hop_matrix)
+    assert np.array_equal(ids.cpu().numpy(), oi), first_mismatch(ids.cpu().numpy(), oi)
+    assert np.array_equal(hops.cpu().numpy(), oh), first_mismatch(hops.cpu().numpy(), oh)
+    if hop_matrix:
+        assert np.array_equal(hm.cpu().numpy(), ohm), first_mismatch(hm.cpu().numpy(), ohm)
+    return oi, oh
+
+
+@pytest.mark.parametrize("name,g", _graphs_small(), ids=[n for n, _ in _graphs_small()])
+def test_build_all_sources_small(gumap, name, g):
+    _check_build(gumap, g, 15)
+
+
+@pytest.mark.parametrize("name,g", _graphs_small(), ids=[n for n, _ in _graphs_small()])
+def test_partial_and_membership_small(gumap, name, g):
+    rp, ci = to_dev(g)
+    for k in (1, 15, 30):
+        print("partial", name, k, flush=True)
+        ids, hops = gumap.knn_partial(rp, ci, k, flags=gumap.CSR_SORTED)
+        oi, oh = O.knn_partial(g, k)
+        assert np.array_equal(ids.cpu().numpy(), oi), first_mismatch(ids.cpu().numpy(), oi)
+        assert np.array_equal(hops.cpu().numpy(), oh)
+        w, rho, sigma = gumap.membership(hops)
+        ow, orho, osig = O.membership(oh)
+        assert_weights_close(w.cpu().numpy(), ow, rho.cpu().numpy(), orho, sigma.cpu().numpy(), osig)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 17, 30, 63, 64, 100, 254])
+def test_k_range(gumap, k):
+    g = G.ba(1500, 3, 21)
+    _check_build(gumap, g, k, hop_matrix=False)
+    rp, ci = to_dev(g)
+    ids, hops = gumap.knn_partial(rp, ci, k, flags=gumap.CSR_SORTED)
+    oi, oh = O.knn_partial(g, k)
+    assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+    w, rho, sigma = gumap.membership(hops)
+    ow, orho, osig = O.membership(oh)
+    assert_weights_close(w.cpu().numpy(), ow, rho.cpu().numpy(), orho, sigma.cpu().numpy(), osig)
+
+
+@pytest.mark.parametrize("words", [1, 2, 4, 8])
+def test_bitset_width_invariance(gumap, words, monkeypatch):
+    monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+    for g in (G.rgg(3000, 6, 31), G.grid_2d(20, 37)):
+        _check_build(gumap, g, 15, hop_matrix=True)
+        src = G.sample_sources(g.n, 700, 32)
+        _check_build(gumap, g, 10, sources=src, hop_matrix=False)
+
+
+def test_sources_with_repeats_and_order(gumap):
+    g = G.sbm(2500, 10, 41)
+    src = np.concatenate([G.sample_sources(g.n, 300, 42), [5, 5, 17, 2499, 0, 17]]).astype(np.int32)
+    _check_build(gumap, g, 15, sources=src, hop_matrix=True)
+    _check_build(gumap, g, 15, sources=src[::-1].copy(), hop_matrix=False)
+
+
+def test_dirty_input_canonicalised(gumap):
+    for g in (G.ba(3000, 5, 51), G.grid_2d(16, 16), G.star(1500), G.complete(70)):
+        _check_build(gumap, g, 15, dirty=True, hop_matrix=True)
+        d = G.dirty(g, 52)
+        rp, ci = to_dev(d)
+        ids, hops = gumap.knn_partial(rp, ci, 15)
+        oi, oh = O.knn_partial(g, 15)
+        assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+
+
+def test_long_rows_canonicalised(gumap):
+    # rows above 1,024 and above 32,768 entries go through the workgroup and bitmap paths
+    g = G.disjoint_union([G.star(40000), G.star(5000), G.complete(30)])
+    d = G.dirty(g, 61)
+    rp, ci = to_dev(d)
+    ids, hops = gumap.knn_partial(rp, ci, 15, flags=gumap.VALIDATE)
+    oi, oh = O.knn_partial(g, 15)
+    assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+
+
+def test_hop_range_error(gumap):
+    import torch
+    g = G.path(300)
+    rp, ci = to_dev(g)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_build(rp, ci, 5, hop_matrix=True, flags=gumap.CSR_SORTED)
+    assert e.value.status == gumap.ERANGE
+    _check_build(gumap, g, 5, hop_matrix=False)
+    _check_build(gumap, G.path(255), 5, hop_matrix=True)
+    torch.cuda.synchronize()
+
+
+def test_validation_errors(gumap):
+    import torch
+    dev = "cuda"
+    # asymmetric: 0 -> 1 only
+    rp = torch.tensor([0, 1, 1], dtype=torch.int32, device=dev)
+    ci = torch.tensor([1], dtype=torch.int32, device=dev)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_partial(rp, ci, 3, flags=gumap.VALIDATE)
+    assert e.value.status == gumap.EGRAPH
+    # id out of range
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    ci = torch.tensor([1, 7], dtype=torch.int32, device=dev)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_build(rp, ci, 3, flags=gumap.VALIDATE)
+    assert e.value.status == gumap.EGRAPH
+    # row_ptr not monotone
+    rp = torch.tensor([0, 2, 1, 2], dtype=torch.int32, device=dev)
+    ci = torch.tensor([1, 2], dtype=torch.int32, device=dev)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_partial(rp, ci, 3, flags=gumap.VALIDATE)
+    assert e.value.status == gumap.EGRAPH
+    # claims sorted but is not
+    g = G.dirty(G.grid_2d(5, 5), 3)
+    rp, ci = to_dev(g)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_partial(rp, ci, 3, flags=gumap.VALIDATE | gumap.CSR_SORTED)
+    assert e.value.status == gumap.EGRAPH
+    # bad source id
+    g = G.grid_2d(5, 5)
+    rp, ci = to_dev(g)
+    with pytest.raises(gumap.GumapError) as e:
+        gumap.knn_build(rp, ci, 3, sources=torch.tensor([0, 25], dtype=torch.int32, device=dev))
+    assert e.value.status == gumap.EINVAL
+    # the library keeps working after errors
+    _check_build(gumap, g, 4)
+
+
+def test_ba100k_full_partial_and_sampled_build(gumap):
+    """The BA workload at full size: partial BFS from all 100,000 vertices and
+    the all-source BFS from the 4,096 sampled sources, against the oracle."""
+    g = G.config_ba()
+    src = G.config_ba_sources()
+    rp, ci = to_dev(g)
+    import torch
+    print("ba100k partial", flush=True)
+    ids, hops = gumap.knn_partial(rp, ci, 15, flags=gumap.CSR_SORTED)
+    oi, oh = O.knn_partial(g, 15)
+    assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+    w, rho, sigma = gumap.membership(hops)
+    ow, orho, osig = O.membership(oh)
+    assert_weights_close(w.cpu().numpy(), ow, rho.cpu().numpy(), orho, sigma.cpu().numpy(), osig)
+    print("ba100k build", flush=True)
+    src_t = torch.from_numpy(src).cuda()
+    bids, bhops, hm = gumap.knn_build(rp, ci, 15, sources=src_t, hop_matrix=True, flags=gumap.CSR_SORTED)
+    assert np.array_equal(bids.cpu().numpy(), oi[src]) and np.array_equal(bhops.cpu().numpy(), oh[src])
+    pick = np.arange(0, len(src), 64)
+    _, _, ohm = O.knn_build(g, 15, sources=src[pick], hop_matrix=True)
+    assert np.array_equal(hm[torch.from_numpy(pick).cuda()].cpu().numpy(), ohm)
+
+
+def test_er16k_all_sources_closed_form(gumap):
+    """Dense ER workload at full size: diameter 2, so every hop row is 1 on the
+    adjacency and 2 elsewhere, and the kNN row is the first 15 neighbours."""
+    import torch
+    g = G.config_er()
+    rp, ci = to_dev(g)
+    print("er16k build", flush=True)
+    ids, hops, hm = gumap.knn_build(rp, ci, 15, hop_matrix=True, flags=gumap.CSR_SORTED)
+    n = g.n
+    deg = g.degrees()
+    # closed form per row, checked on the device to keep host memory small
+    adj = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    src = torch.from_numpy(np.repeat(np.arange(n), deg)).cuda().long()
+    dst = torch.from_numpy(g.col_idx).cuda().long()
+    adj[src, dst] = 1
+    expect = 2 - adj
+    expect.fill_diagonal_(0)
+    assert torch.equal(hm, expect)
+    first15 = np.stack([g.neighbors(v)[:15] for v in range(n)])
+    assert np.array_equal(ids.cpu().numpy(), first15)
+    assert np.all(hops.cpu().numpy() == 1)
+    pick = G.sample_sources(n, 32, 71)
+    oi, oh, ohm = O.knn_build(g, 15, sources=pick, hop_matrix=True)
+    assert np.array_equal(hm[torch.from_numpy(pick).cuda().long()].cpu().numpy(), ohm)
+    w, rho, sigma = gumap.membership(hops)
+    assert torch.all(w == 1.0) and torch.all(sigma == 0.0)
+
+
+def test_build_equals_partial(gumap):
+    for g in (G.ba(4000, 4, 81), G.rgg(4000, 10, 82), G.grid_2d(40, 40)):
+        rp, ci = to_dev(g)
+        for k in (5, 15, 40):
+            ids, hops, _ = gumap.knn_build(rp, ci, k, flags=gumap.CSR_SORTED)
+            pids, phops = gumap.knn_partial(rp, ci, k, flags=gumap.CSR_SORTED)
+            assert np.array_equal(ids.cpu().numpy(), pids.cpu().numpy())
+            assert np.array_equal(hops.cpu().numpy(), phops.cpu().numpy())
