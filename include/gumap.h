@@ -72,6 +72,20 @@ typedef struct gumap_graph {
 } gumap_graph;
 
 /*
+ * CSR ingest.  The input of every method step is an undirected unweighted
+ * graph G = (V, E) (Sec. 3.1, Alg. 1 input); this writes the canonical CSR
+ * of its edge set: rows sorted ascending, repeated entries and self-loops
+ * removed.  The other calls do this themselves unless GUMAP_CSR_SORTED is
+ * set; calling it once lets a caller pass the result with that flag.
+ *   out_row_ptr device int32[n + 1]; out_col_idx device int32[g->nnz]
+ *   (capacity); *out_nnz (host) receives the kept entry count.
+ * Errors: GUMAP_EINVAL, GUMAP_EGRAPH (with GUMAP_VALIDATE), GUMAP_ENOMEM,
+ *         GUMAP_EDEVICE.
+ */
+int gumap_csr_canonicalize(const gumap_graph *g, int32_t *out_row_ptr, int32_t *out_col_idx,
+                           int32_t *out_nnz, hipStream_t stream);
+
+/*
  * GUMAP steps C0 + C1 (Sec. 3.1, Alg. 1): BFS hop distances from each source
  * and the (hop, id)-ordered k nearest other vertices of each source.
  *   sources    device int32[n_sources] vertex ids, or NULL for all n vertices

@@ -1,0 +1,38 @@
+/*
+ * gumap kernel timing (instrumentation of the library's own launches; not a
+ * step of the method).
+ *
+ * When enabled, every kernel launch the library makes is bracketed by two
+ * HIP events recorded on the stream the kernel is launched on, and tagged
+ * with the algorithmic bytes that launch moves (the bytes its traversal
+ * must read and write, computed from the sizes and from the device-side
+ * work counters of the BFS levels).  Timings are resolved when a call
+ * returns, so they cover exactly the calls made while enabled.  Not thread
+ * safe against concurrent library calls from several threads.
+ */
+#ifndef GUMAP_PROFILE_H
+#define GUMAP_PROFILE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Starts (on != 0) or stops recording.  Recording adds two event records per launch. */
+void gumap_profile_enable(int on);
+/* Drops everything recorded so far. */
+void gumap_profile_reset(void);
+/* Number of distinct kernels recorded. */
+int gumap_profile_count(void);
+/* Entry i (0 <= i < count): kernel name (owned by the library), number of
+ * launches, total elapsed milliseconds and total algorithmic bytes.
+ * Returns 0, or -1 if i is out of range. */
+int gumap_profile_entry(int i, const char **name, int64_t *launches, double *total_ms,
+                        double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GUMAP_PROFILE_H */

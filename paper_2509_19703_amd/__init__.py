@@ -87,6 +87,8 @@ def _load() -> ctypes.CDLL:
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     G = ctypes.POINTER(gumap_graph)
     B = ctypes.POINTER(gumap_batch)
+    lib.gumap_csr_canonicalize.argtypes = [G, vp, vp, ctypes.POINTER(i32), vp]
+    lib.gumap_csr_canonicalize.restype = ctypes.c_int
     lib.gumap_knn_build.argtypes = [G, i32, vp, i32, vp, vp, vp, vp]
     lib.gumap_knn_partial.argtypes = [G, i32, vp, vp, vp]
     lib.gumap_membership.argtypes = [i32, i32, vp, vp, vp, vp, vp]
@@ -98,6 +100,15 @@ def _load() -> ctypes.CDLL:
     for f in (lib.gumap_knn_build, lib.gumap_knn_partial, lib.gumap_membership,
               lib.gumap_knn_partial_batch, lib.gumap_batch_plan_create, lib.gumap_batch_plan_launch):
         f.restype = ctypes.c_int
+    lib.gumap_profile_enable.argtypes = [ctypes.c_int]
+    lib.gumap_profile_enable.restype = None
+    lib.gumap_profile_reset.argtypes = []
+    lib.gumap_profile_reset.restype = None
+    lib.gumap_profile_count.argtypes = []
+    lib.gumap_profile_count.restype = ctypes.c_int
+    lib.gumap_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.gumap_profile_entry.restype = ctypes.c_int
     lib.gumap_last_error.argtypes = []
     lib.gumap_last_error.restype = ctypes.c_char_p
     if hasattr(lib, "gumap_server_create"):
@@ -117,6 +128,29 @@ def _load() -> ctypes.CDLL:
 
 
 lib = _load()
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record HIP-event timings of the library's kernel launches (gumap_profile.h)."""
+    lib.gumap_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    lib.gumap_profile_reset()
+
+
+def profile_entries() -> dict:
+    """{kernel: {"launches", "total_ms", "alg_bytes"}} recorded so far."""
+    out = {}
+    for i in range(lib.gumap_profile_count()):
+        name = ctypes.c_char_p()
+        launches = ctypes.c_int64()
+        ms = ctypes.c_double()
+        b = ctypes.c_double()
+        if lib.gumap_profile_entry(i, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms),
+                                   ctypes.byref(b)) == 0:
+            out[name.value.decode()] = {"launches": launches.value, "total_ms": ms.value, "alg_bytes": b.value}
+    return out
 
 
 def last_error() -> str:
@@ -152,6 +186,13 @@ def make_graph(row_ptr, col_idx, n: int | None = None, flags: int = 0) -> gumap_
 
 # ------------------------------------------------- mirrors of the C calls ---
 
+def gumap_csr_canonicalize(graph: gumap_graph, out_row_ptr, out_col_idx, stream=None) -> int:
+    """Returns the kept entry count (the C call's *out_nnz)."""
+    nnz = ctypes.c_int32(0)
+    _check(lib.gumap_csr_canonicalize(ctypes.byref(graph), _ptr(out_row_ptr), _ptr(out_col_idx),
+                                      ctypes.byref(nnz), _stream(stream)))
+    return int(nnz.value)
+
 def gumap_knn_build(graph: gumap_graph, k: int, sources, n_sources: int, nbr_ids, nbr_hops,
                     hop_matrix=None, stream=None) -> int:
     return _check(lib.gumap_knn_build(ctypes.byref(graph), k, _ptr(sources), n_sources, _ptr(nbr_ids),
@@ -179,6 +220,16 @@ def gumap_knn_partial_batch(batch: gumap_batch, k: int, nbr_ids, nbr_hops, weigh
 def _torch():
     import torch
     return torch
+
+
+def csr_canonicalize(row_ptr, col_idx, flags: int = 0, stream=None):
+    """Canonical CSR (sorted rows, no repeats or self-loops).  Returns (row_ptr, col_idx)."""
+    torch = _torch()
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    out_rp = torch.empty(g.n + 1, dtype=torch.int32, device=row_ptr.device)
+    out_col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=row_ptr.device)
+    nnz = gumap_csr_canonicalize(g, out_rp, out_col, stream)
+    return out_rp, out_col[:nnz]
 
 
 def knn_build(row_ptr, col_idx, k: int, sources=None, hop_matrix: bool = False, flags: int = 0,

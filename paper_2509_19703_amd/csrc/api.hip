@@ -14,6 +14,7 @@
 
 #include "../../include/gumap.h"
 #include "kernels.h"
+#include "profile.h"
 #include "runtime.h"
 #include "util.h"
 
@@ -213,8 +214,17 @@ int finish(hipStream_t s, const char *what)
 {
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipGetLastError();
+    if (prof_on()) prof_resolve();
     return hip_status(e, what);
 }
+
+// Launch `call` between profiler marks (no-op marks when profiling is off).
+#define GM_PROF(name, bytes, call)                 \
+    do {                                          \
+        const int mark_ = prof_begin((name), s);  \
+        e = (call);                               \
+        prof_end(mark_, s, (double)(bytes));      \
+    } while (0)
 
 // ----------------------------------------------------- all-source BFS --
 namespace {
@@ -324,18 +334,33 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     unsigned long long *stats = nullptr;
     unsigned int *lvl_cnt = nullptr;
     int64_t *local_rows = nullptr;
+    int32_t *heavy = nullptr;
+    const int SF = msbfs_stat_fields(), SP = msbfs_stat_spread();
+    const size_t stats_per_level = (size_t)groups_round * SP * SF;   // u64 per level
     const size_t arr_round = arr_per_group * groups_round;
     if ((st = scratch_get(kSlotBfsState, (3 + (size_t)planes_alloc) * arr_round * 8, (void **)&state))) return st;
-    if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * groups_round * 8, (void **)&stats))) return st;
+    if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * stats_per_level * 8, (void **)&stats))) return st;
     if ((st = scratch_get(kSlotLvlCnt, (size_t)groups_round * W * 16 * 4, (void **)&lvl_cnt))) return st;
+    if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
     if (!hop_matrix) {
         if ((st = scratch_get(kSlotHopRows, (size_t)groups_round * W * n, (void **)&hop_scratch))) return st;
         if ((st = scratch_get(kSlotLocalRows, (size_t)groups_round * W * sizeof(int64_t), (void **)&local_rows))) return st;
         if ((e = iota_i64(local_rows, (int64_t)groups_round * W, 0, s)) != hipSuccess) return hip_status(e, "iota");
     }
     void *hstats_v = nullptr;
-    if ((st = host_scratch_get((size_t)(L_cap + 2) * groups_round * 8, &hstats_v))) return st;
+    if ((st = host_scratch_get((size_t)(L_cap + 2) * stats_per_level * 8 + 256, &hstats_v))) return st;
     unsigned long long *hstats = (unsigned long long *)hstats_v;
+    // vertices of high degree get a whole wave per level
+    int32_t n_heavy = 0;
+    {
+        int32_t *count = heavy + n;
+        e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
+        if (e == hipSuccess) e = launch_heavy_list(n, c.row_ptr, heavy, count, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hstats, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "heavy vertices");
+        n_heavy = *(int32_t *)hstats;
+    }
 
     for (int32_t gs = 0; gs < groups_total; gs += groups_round) {
         MsbfsArgs a;
@@ -349,6 +374,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.usrc = usrc;
         a.n_usrc = n_uniq;
         a.slot_of = slot_of;
+        a.heavy = heavy;
+        a.n_heavy = n_heavy;
         const size_t arr = arr_per_group * a.groups;
         a.front[0] = state;
         a.front[1] = state + arr;
@@ -357,11 +384,40 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.plane_stride = arr;
         a.stats = stats;
         a.stats_groups = a.groups;
+        const size_t spl = (size_t)a.groups * SP * SF;   // u64 per level this round
         e = hipMemsetAsync(a.front[1], 0, 2 * arr * 8, s);  // front[1] and visited
-        if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * a.groups * 8, s);
+        if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * spl * 8, s);
         if (e == hipSuccess) e = hipMemsetAsync(lvl_cnt, 0, (size_t)a.n_slots * 16 * 4, s);
         if (e == hipSuccess) e = launch_msbfs_init(a, s);
         if (e != hipSuccess) return hip_status(e, "bfs init");
+
+        // sum over spread slots of one field for (level, group)
+        auto level_sum = [&](int lv, int q, int field) {
+            unsigned long long t = 0;
+            const unsigned long long *p = hstats + (size_t)lv * spl + (size_t)q * SP * SF;
+            for (int i = 0; i < SP; ++i) t += p[(size_t)i * SF + field];
+            return t;
+        };
+        std::vector<int> marks(L_cap + 3, -1);
+        std::vector<char> ran(L_cap + 3, 0);
+        // algorithmic bytes of one level launch, from its counters
+        auto level_bytes = [&](int lv, bool commit_only) {
+            double b = 0.0;
+            const int hop = lv - 1;
+            const int pc = __builtin_popcount((unsigned)(hop > 0 ? hop : 0));
+            for (int q = 0; q < a.groups; ++q) {
+                const bool active = lv == 1 || level_sum(lv - 1, q, 0) != 0;
+                if (!active) continue;
+                // row pointers, frontier + visited reads, next-frontier writes
+                b += 8.0 * n + (commit_only ? 16.0 : 24.0) * (double)n * words;
+                // committed words: visited write + plane read-modify-write per set hop bit
+                const double commits = (double)level_sum(lv, q, 3);
+                b += 8.0 * commits + 16.0 * commits * pc;
+                // neighbour frontier words gathered and adjacency entries read
+                b += 8.0 * (double)level_sum(lv, q, 1) + 4.0 * (double)level_sum(lv, q, 2);
+            }
+            return b;
+        };
 
         int L = 1, last_level = 0, chunk = 4;
         bool done = false, range_error = false;
@@ -374,15 +430,20 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
                     if (e != hipSuccess) return hip_status(e, "plane clear");
                 }
-                if ((e = launch_msbfs_level(a, L, false, s)) != hipSuccess) return hip_status(e, "bfs level");
+                marks[L] = prof_begin("msbfs_level", s);
+                e = launch_msbfs_level(a, L, false, s);
+                prof_end(marks[L], s, 0.0);
+                ran[L] = 1;
+                if (e != hipSuccess) return hip_status(e, "bfs level");
             }
-            e = hipMemcpyAsync(hstats + (size_t)first * a.groups, stats + (size_t)first * a.groups,
-                               (size_t)(L - first) * a.groups * 8, hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(hstats + (size_t)first * spl, stats + (size_t)first * spl,
+                               (size_t)(L - first) * spl * 8, hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_status(e, "bfs stats");
+            for (int lv = first; lv < L; ++lv) prof_set_bytes(marks[lv], level_bytes(lv, false));
             for (int lv = first; lv < L && !done; ++lv) {
                 bool any = false;
-                for (int q = 0; q < a.groups; ++q) any |= hstats[(size_t)lv * a.groups + q] != 0;
+                for (int q = 0; q < a.groups; ++q) any |= level_sum(lv, q, 0) != 0;
                 if (!any) {
                     done = true;
                     last_level = lv - 1;
@@ -399,7 +460,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
                     if (e != hipSuccess) return hip_status(e, "plane clear");
                 }
-                if ((e = launch_msbfs_level(a, L_cap + 1, true, s)) != hipSuccess) return hip_status(e, "bfs commit");
+                const int mk = prof_begin("msbfs_level", s);
+                e = launch_msbfs_level(a, L_cap + 1, true, s);
+                // commit-only: reads front + visited, writes the committed words
+                prof_end(mk, s, (double)a.groups * (8.0 * n + 16.0 * (double)n * words));
+                if (e != hipSuccess) return hip_status(e, "bfs commit");
                 last_level = L_cap;
                 done = true;
             }
@@ -410,10 +475,13 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         const int planes_used = bit_length(last_level);
         uint8_t *hop_out = hop_matrix ? hop_matrix : hop_scratch;
         const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
-        e = launch_msbfs_hops_counted(a, planes_used, hop_out, hop_rows_of, n, lvl_cnt, s);
+        const double hop_bytes = (double)(planes_used + 1) * (double)arr * 8.0 + (double)a.n_slots * n;
+        GM_PROF("msbfs_hops", hop_bytes,
+                launch_msbfs_hops_counted(a, planes_used, hop_out, hop_rows_of, n, lvl_cnt, s));
         if (e == hipSuccess)
-            e = launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                          slot_row + a.slot0, lvl_cnt, ids, hops, s);
+            GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
+                    launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
+                                              slot_row + a.slot0, lvl_cnt, ids, hops, s));
         if (e != hipSuccess) return hip_status(e, "hop rows / selection");
     }
     if (!dup_pairs.empty()) {
@@ -421,6 +489,56 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e != hipSuccess) return hip_status(e, "repeated sources");
     }
     return finish(s, "gumap_knn_build");
+}
+
+// ------------------------------------------------------- canonical CSR --
+int csr_canonicalize(const gumap_graph *g, int32_t *out_rp, int32_t *out_col, int32_t *out_nnz, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if (!out_nnz || !out_rp || (g->nnz > 0 && !out_col)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (g->n == 0) {
+        *out_nnz = 0;
+        hipError_t e = hipMemsetAsync(out_rp, 0, sizeof(int32_t), s);
+        if (e != hipSuccess) return hip_status(e, "canonicalize");
+        return finish(s, "gumap_csr_canonicalize");
+    }
+    if (g->flags & GUMAP_VALIDATE) {
+        gumap_graph v = *g;
+        v.flags = GUMAP_VALIDATE | GUMAP_CSR_SORTED;   // structural checks only here
+        int *err = nullptr;
+        if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+        hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess) e = launch_validate_structure(g->n, g->nnz, g->row_ptr, g->col_idx, err, s);
+        if (e != hipSuccess) return hip_status(e, "validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "malformed CSR (check bits 0x%x)", bad);
+        (void)v;
+    }
+    void *tmp = nullptr;
+    if ((st = scratch_get(kSlotCanonTmp, canon_scratch_bytes(g->n, g->nnz), &tmp))) return st;
+    hipError_t e;
+    GM_PROF("canonicalize", 2.0 * ((double)g->n * 4 + (double)g->nnz * 4),
+            launch_canonicalize(g->n, g->nnz, g->row_ptr, g->col_idx, out_rp, out_col, tmp, s));
+    if (e != hipSuccess) return hip_status(e, "canonicalize");
+    if (g->flags & GUMAP_VALIDATE) {
+        int *err = nullptr;
+        if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+        e = hipMemsetAsync(err, 0, sizeof(int), s);
+        if (e == hipSuccess) e = launch_check_symmetric(g->n, out_rp, out_col, err, s);
+        if (e != hipSuccess) return hip_status(e, "validate");
+        int bad = 0;
+        if ((st = read_flag(err, &bad, s))) return st;
+        if (bad) return set_error(GUMAP_EGRAPH, "CSR is not symmetric");
+    }
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    e = hipMemcpyAsync(h, out_rp + g->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_status(e, "canonicalize");
+    if ((st = finish(s, "gumap_csr_canonicalize"))) return st;
+    *out_nnz = *(int32_t *)h;
+    return GUMAP_OK;
 }
 
 // --------------------------------------------------------- partial BFS --
@@ -440,7 +558,8 @@ int knn_partial(const gumap_graph *g, int32_t k, int32_t *ids, uint8_t *hops, hi
     a.col = c.col;
     a.ids = ids;
     a.hops = hops;
-    hipError_t e = launch_partial_bfs(a, s);
+    hipError_t e;
+    GM_PROF("partial_bfs", (double)c.n * (8.0 + 5.0 * k), launch_partial_bfs(a, s));
     if (e != hipSuccess) return hip_status(e, "partial bfs");
     return finish(s, "gumap_knn_partial");
 }
@@ -453,7 +572,9 @@ int membership(int32_t rows, int32_t k, const uint8_t *hops, float *w, float *rh
     if ((st = check_k(k))) return st;
     if (rows == 0) return GUMAP_OK;
     if (!hops || !w) return set_error(GUMAP_EINVAL, "hops or weights is NULL");
-    hipError_t e = launch_membership(rows, k, hops, w, rho, sigma, s);
+    hipError_t e;
+    GM_PROF("membership", (double)rows * k * 5.0 + (double)rows * 8.0 * (rho && sigma ? 1 : 0),
+            launch_membership(rows, k, hops, w, rho, sigma, s));
     if (e != hipSuccess) return hip_status(e, "membership");
     return finish(s, "gumap_membership");
 }
@@ -602,6 +723,14 @@ struct gumap_batch_plan {
 extern "C" {
 
 const char *gumap_last_error(void) { return gm::last_error(); }
+
+int gumap_csr_canonicalize(const gumap_graph *g, int32_t *out_row_ptr, int32_t *out_col_idx,
+                           int32_t *out_nnz, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::csr_canonicalize(g, out_row_ptr, out_col_idx, out_nnz, stream), stream);
+}
 
 int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
                     int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream)

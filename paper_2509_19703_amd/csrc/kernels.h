@@ -51,9 +51,18 @@ struct MsbfsArgs {
     uint64_t *visited;
     uint64_t *planes;         // 8 bit-planes of the discovery level, plane-major
     size_t plane_stride;      // uint64 elements per plane (= groups * n * words)
-    unsigned long long *stats; // [level][group] new bits found at that level
-    int32_t stats_groups;     // row length of stats
+    unsigned long long *stats; // [level][group][spread][field] counters of each level
+    int32_t stats_groups;     // groups per stats level
+    const int32_t *heavy;     // vertices of degree above msbfs_heavy_degree()
+    int32_t n_heavy;
 };
+// Layout of the level counters: stats[((level * groups + g) * spread + slot) * fields + field]
+// with fields {new bits, frontier words gathered, adjacency entries read,
+// frontier words committed}; a level's value is the sum over the spread slots.
+int msbfs_stat_fields();
+int msbfs_stat_spread();
+int msbfs_heavy_degree();
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t *heavy, int32_t *count, hipStream_t s);
 hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).

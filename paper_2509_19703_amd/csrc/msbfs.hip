@@ -19,6 +19,8 @@
 // butterflies, and counts how many vertices each source reached at hops
 // 1..16 (used by the kNN selection to find its last level without a
 // separate pass).
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -27,9 +29,13 @@ namespace gm {
 namespace {
 
 constexpr int kLevelBlock = 256;
+constexpr int kHeavyDeg = 64;      // above this degree a vertex gets a whole wave
 constexpr int kHopTilesPerWave = 16;
 constexpr int kHopWaves = 4;
 constexpr int kCountLevels = 16;
+constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
+constexpr int kStatFields = 4;
+enum { kFieldNewBits = 0, kFieldGathers = 1, kFieldCols = 2, kFieldCommits = 3 };
 
 __device__ __forceinline__ uint64_t word_valid_mask(int32_t n_slots, int32_t local_slot0)
 {
@@ -51,62 +57,172 @@ __global__ void msbfs_init_kernel(MsbfsArgs a)
     atomicOr((unsigned long long *)&a.front[1][idx], 1ull << bit);
 }
 
-__global__ void __launch_bounds__(kLevelBlock)
-msbfs_level_kernel(MsbfsArgs a, int level, int commit_only)
+struct Counters {
+    unsigned long long v[kStatFields];
+};
+
+// Commit of the previous level's frontier word of (vertex, word) at `me`.
+__device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, size_t me, Counters &c)
 {
+    const uint64_t f = a.front[level & 1][me];
+    uint64_t vis = a.visited[me];
+    if (f) {
+        vis |= f;
+        a.visited[me] = vis;
+        const int hop = level - 1;
+        for (int b = 0; b < 8; ++b)
+            if ((hop >> b) & 1) a.planes[(size_t)b * a.plane_stride + me] |= f;
+        c.v[kFieldCommits] += 1;
+    }
+    return vis;
+}
+
+template <int WORDS>
+__global__ void __launch_bounds__(kLevelBlock)
+msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks)
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    constexpr int G = GM_WAVE / WORDS;            // neighbour lanes per word in a heavy wave
+    __shared__ unsigned long long red[kLevelBlock / GM_WAVE][kStatFields];
     const int32_t g = blockIdx.y;
-    if (level >= 2 && a.stats[(size_t)(level - 1) * a.stats_groups + g] == 0ull) return;
-    const int lw = __ffs(a.words) - 1;                        // log2(words)
-    const int64_t idx = (int64_t)blockIdx.x * kLevelBlock + threadIdx.x;
-    const int64_t items = (int64_t)a.n << lw;
-    uint64_t nw = 0;
-    if (idx < items) {
-        const int32_t v = (int32_t)(idx >> lw);
-        const int32_t w = (int32_t)(idx & (a.words - 1));
-        const size_t gbase = (size_t)g * a.n * a.words + w;  // + vertex * words
-        const size_t me = gbase + ((size_t)v << lw);
-        const uint64_t *__restrict__ fr = a.front[level & 1];
-        uint64_t f = fr[me];
-        uint64_t vis = a.visited[me];
-        if (f) {
-            vis |= f;
-            a.visited[me] = vis;
-            const int hop = level - 1;
-            for (int b = 0; b < 8; ++b)
-                if ((hop >> b) & 1) a.planes[(size_t)b * a.plane_stride + me] |= f;
-        }
-        if (!commit_only) {
-            const int32_t ls0 = g * 64 * a.words + 64 * w;    // local slot of bit 0
-            const uint64_t unv = ~vis & word_valid_mask(a.n_slots, ls0);
-            if (unv) {
-                const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
-                uint64_t acc = 0;
-                if (level == 1) {
-                    const int32_t gs0 = a.slot0 + ls0;
-                    const int32_t gl = min(gs0 + 63, a.slot0 + a.n_slots - 1);
-                    const int32_t lo = a.usrc[gs0], hi = a.usrc[gl];
-                    for (int32_t e = lower_bound(a.col, e0, e1, lo); e < e1; ++e) {
-                        const int32_t u = a.col[e];
-                        if (u > hi) break;
-                        const int32_t s = a.slot_of[u];
-                        if (s >= 0) acc |= 1ull << (s - gs0);
+    const int l = lane(), wid = threadIdx.x / GM_WAVE;
+    if (level >= 2) {
+        // previous level found nothing for this group: nothing to commit or search
+        const unsigned long long x =
+            a.stats[(((size_t)(level - 1) * a.stats_groups + g) * kSpread + l) * kStatFields + kFieldNewBits];
+        if (__ballot(x != 0ull) == 0ull) return;
+    }
+    Counters c{};
+    const size_t gbase = (size_t)g * a.n * WORDS;
+    const uint64_t *__restrict__ fr = a.front[level & 1];
+    if ((int)blockIdx.x < light_blocks) {
+        // one thread per (vertex, word); vertices of degree > kHeavyDeg are left
+        // to the heavy waves (except at level 1, where all are done here)
+        const int64_t idx = (int64_t)blockIdx.x * kLevelBlock + threadIdx.x;
+        const int32_t v = (int32_t)(idx >> LW);
+        const int w = (int)(idx & (WORDS - 1));
+        int cols = 0;
+        if (v < a.n) {
+            const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+            if (level == 1 || e1 - e0 <= kHeavyDeg) {
+                const size_t me = gbase + ((size_t)v << LW) + w;
+                const uint64_t vis = commit_word(a, level, me, c);
+                if (!commit_only) {
+                    const int32_t ls0 = g * 64 * WORDS + 64 * w;
+                    const uint64_t unv = ~vis & word_valid_mask(a.n_slots, ls0);
+                    uint64_t acc = 0;
+                    if (unv) {
+                        if (level == 1) {
+                            const int32_t gs0 = a.slot0 + ls0;
+                            const int32_t gl = min(gs0 + 63, a.slot0 + a.n_slots - 1);
+                            const int32_t lo = a.usrc[gs0], hi = a.usrc[gl];
+                            int32_t lo_e = e0, hi_e = e1;
+                            while (lo_e < hi_e) {
+                                const int32_t mid = (lo_e + hi_e) >> 1;
+                                ++cols;
+                                if (a.col[mid] < lo) lo_e = mid + 1;
+                                else hi_e = mid;
+                            }
+                            for (int32_t e = lo_e; e < e1; ++e) {
+                                const int32_t u = a.col[e];
+                                ++cols;
+                                if (u > hi) break;
+                                const int32_t s = a.slot_of[u];
+                                if (s >= 0) acc |= 1ull << (s - gs0);
+                            }
+                        } else {
+                            for (int32_t e = e0; e < e1; e += 4) {
+                                // four independent neighbour loads in flight
+                                const int32_t u0 = a.col[e];
+                                const int32_t u1 = e + 1 < e1 ? a.col[e + 1] : -1;
+                                const int32_t u2 = e + 2 < e1 ? a.col[e + 2] : -1;
+                                const int32_t u3 = e + 3 < e1 ? a.col[e + 3] : -1;
+                                uint64_t x = fr[gbase + ((size_t)u0 << LW) + w];
+                                if (u1 >= 0) x |= fr[gbase + ((size_t)u1 << LW) + w];
+                                if (u2 >= 0) x |= fr[gbase + ((size_t)u2 << LW) + w];
+                                if (u3 >= 0) x |= fr[gbase + ((size_t)u3 << LW) + w];
+                                const int got = min(4, e1 - e);
+                                cols += got;
+                                c.v[kFieldGathers] += got;
+                                acc |= x;
+                                if ((acc & unv) == unv) break;
+                            }
+                        }
                     }
-                } else {
-                    for (int32_t e = e0; e < e1; ++e) {
-                        const int32_t u = a.col[e];
-                        acc |= fr[gbase + ((size_t)u << lw)];
-                        if ((acc & unv) == unv) break;
+                    const uint64_t nw = acc & unv;
+                    a.front[(level + 1) & 1][me] = nw;
+                    c.v[kFieldNewBits] += __popcll(nw);
+                }
+            }
+        }
+        // adjacency entries are shared by the word threads of a vertex: count the longest scan once
+#pragma unroll
+        for (int o = 1; o < WORDS; o <<= 1) cols = max(cols, __shfl_xor(cols, o, GM_WAVE));
+        if (w == 0) c.v[kFieldCols] += cols;
+    } else if (level >= 2) {
+        // one wave per heavy vertex: lane = (neighbour group, word)
+        const int32_t hidx = ((int)blockIdx.x - light_blocks) * (kLevelBlock / GM_WAVE) + wid;
+        if (hidx < a.n_heavy) {
+            const int32_t v = a.heavy[hidx];
+            const int w = l & (WORDS - 1), grp = l >> LW;
+            const size_t me = gbase + ((size_t)v << LW) + w;
+            uint64_t vis = 0;
+            if (grp == 0) vis = commit_word(a, level, me, c);
+            vis = __shfl(vis, w, GM_WAVE);
+            if (!commit_only) {
+                const int32_t ls0 = g * 64 * WORDS + 64 * w;
+                const uint64_t unv = ~vis & word_valid_mask(a.n_slots, ls0);
+                uint64_t redv = 0;
+                if (__ballot(unv != 0ull)) {
+                    const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+                    uint64_t acc = 0;
+                    for (int32_t base = e0; base < e1; base += 4 * G) {
+                        int got = 0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int32_t e = base + grp + G * i;
+                            if (e < e1) {
+                                acc |= fr[gbase + ((size_t)a.col[e] << LW) + w];
+                                ++got;
+                            }
+                        }
+                        c.v[kFieldGathers] += got;
+                        if (w == 0) c.v[kFieldCols] += got;
+                        redv = acc;
+#pragma unroll
+                        for (int o = WORDS; o < GM_WAVE; o <<= 1) redv |= __shfl_xor(redv, o, GM_WAVE);
+                        if (__ballot((redv & unv) != unv) == 0ull) break;
                     }
                 }
-                nw = acc & unv;
+                const uint64_t nw = redv & unv;
+                if (grp == 0) {
+                    a.front[(level + 1) & 1][me] = nw;
+                    c.v[kFieldNewBits] += __popcll(nw);
+                }
             }
-            a.front[(level + 1) & 1][me] = nw;
         }
     }
-    if (!commit_only) {
-        unsigned long long c = wave_sum_u64((unsigned long long)__popcll(nw));
-        if (lane() == 0 && c) atomicAdd(&a.stats[(size_t)level * a.stats_groups + g], c);
+    // block totals -> one atomic per field into a spread slot
+#pragma unroll
+    for (int f = 0; f < kStatFields; ++f) {
+        const unsigned long long t = wave_sum_u64(c.v[f]);
+        if (l == 0) red[wid][f] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < kStatFields) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kLevelBlock / GM_WAVE; ++q) t += red[q][threadIdx.x];
+        if (t)
+            atomicAdd(&a.stats[(((size_t)level * a.stats_groups + g) * kSpread + (blockIdx.x & (kSpread - 1))) *
+                                   kStatFields + threadIdx.x],
+                      t);
+    }
+}
+
+__global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t *heavy, int32_t *count)
+{
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        if (rp[v + 1] - rp[v] > kHeavyDeg) heavy[atomicAdd(count, 1)] = (int32_t)v;
 }
 
 // Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
@@ -236,10 +352,31 @@ hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s)
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s)
 {
     const int64_t items = (int64_t)a.n * a.words;
-    dim3 grid((unsigned)((items + kLevelBlock - 1) / kLevelBlock), (unsigned)a.groups);
-    hipLaunchKernelGGL(msbfs_level_kernel, grid, dim3(kLevelBlock), 0, s, a, level, commit_only ? 1 : 0);
+    const int light = (int)((items + kLevelBlock - 1) / kLevelBlock);
+    const int heavy = level >= 2 ? (a.n_heavy + kLevelBlock / GM_WAVE - 1) / (kLevelBlock / GM_WAVE) : 0;
+    dim3 grid((unsigned)(light + heavy), (unsigned)a.groups);
+    const int co = commit_only ? 1 : 0;
+    switch (a.words) {
+    case 1: hipLaunchKernelGGL(msbfs_level_kernel<1>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
+    case 2: hipLaunchKernelGGL(msbfs_level_kernel<2>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
+    case 4: hipLaunchKernelGGL(msbfs_level_kernel<4>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
+    case 8: hipLaunchKernelGGL(msbfs_level_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
+
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t *heavy, int32_t *count, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>(4096, ((int64_t)n + 255) / 256);
+    hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, heavy, count);
+    return hipGetLastError();
+}
+
+int msbfs_stat_fields() { return kStatFields; }
+int msbfs_stat_spread() { return kSpread; }
+int msbfs_heavy_degree() { return kHeavyDeg; }
 
 hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                                      const int64_t *slot_row, int64_t row_stride,

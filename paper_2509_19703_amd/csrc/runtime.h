@@ -33,6 +33,7 @@ enum ScratchSlot {
     kSlotBatchRp,
     kSlotBatchCol,
     kSlotCounter,
+    kSlotHeavy,
     kScratchSlots
 };
 
