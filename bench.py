@@ -38,6 +38,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-parity", action="store_true")
     p.add_argument("--cpu-sample-sources", type=int, default=1024)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    p.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                   help="turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of this bench and of "
+                        "--calibrate-copy) into the traffic file and exit")
+    p.add_argument("--traffic-kernel", default="msbfs_level_kernel")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_ba100k.json"),
                    help="HBM bytes per launch of the dominant kernel measured with rocprofv3 counters")
     return p.parse_args()
@@ -45,6 +51,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.traffic_from:
+        write_traffic(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -54,6 +63,19 @@ def main():
 
     import graphgen as G
     import paper_2509_19703_amd as gm
+
+    if args.calibrate_copy:
+        n_bytes = 1 << 30
+        a = torch.empty(n_bytes // 4, dtype=torch.int32, device="cuda")
+        b_ = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n_bytes,
+                          "bytes_written_per_copy": n_bytes, "copies": 3}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -156,6 +178,42 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, src, k, m, args.cpu_sample_sources)
     print(json.dumps(out), flush=True)
+
+
+def _counter_avg_kib(run_dir: str, kernel_substr: str):
+    """Average counter value (KiB) per dispatch of the kernels whose name contains kernel_substr."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(run_dir, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise FileNotFoundError("no rocprofv3 database under %s" % run_dir)
+    con = sqlite3.connect(dbs[0])
+    rows = con.execute("select kernel_name, value from counters_collection").fetchall()
+    vals = [v for name, v in rows if kernel_substr in name]
+    return (sum(vals) / len(vals) if vals else None), len(vals)
+
+
+def write_traffic(args):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE,
+    each scaled by the reading of the same counter for a plain 1 GiB copy."""
+    fetch, nf = _counter_avg_kib(args.traffic_from[0], args.traffic_kernel)
+    write, nw = _counter_avg_kib(args.traffic_from[1], args.traffic_kernel)
+    cf, _ = _counter_avg_kib(args.traffic_from[2], "copyBuffer")
+    cw, _ = _counter_avg_kib(args.traffic_from[3], "copyBuffer")
+    gib_kib = float(1 << 20)
+    f_fetch = cf / gib_kib          # counter KiB per KiB the copy must read
+    f_write = cw / gib_kib
+    read_b = fetch * 1024.0 / f_fetch
+    write_b = write * 1024.0 / f_write
+    name = {"msbfs_level_kernel": "msbfs_level"}.get(args.traffic_kernel, args.traffic_kernel)
+    out = {"kernel": name, "counter_kernel": args.traffic_kernel, "source_sha": kernel_source_sha(),
+           "fetch_kib_per_launch": fetch, "write_kib_per_launch": write, "launches": [nf, nw],
+           "copy_fetch_factor": f_fetch, "copy_write_factor": f_write,
+           "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+           "hbm_bytes_per_launch": read_b + write_b}
+    with open(args.traffic_json, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def kernel_source_sha() -> str:

@@ -324,8 +324,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const int planes_alloc = hop_matrix ? 8 : bit_length(k);
     const size_t arr_per_group = (size_t)n * words;  // uint64 per array per group
     const size_t bytes_per_group = (3 + (size_t)planes_alloc) * arr_per_group * 8 +
-                                   (hop_matrix ? 0 : (size_t)W * n) + (size_t)W * 16 * 4 +
-                                   (size_t)(L_cap + 2) * 8;
+                                   (hop_matrix ? 0 : (size_t)W * n) + (size_t)W * msbfs_hop_chunks(n) * 16 * 4 +
+                                   (size_t)(L_cap + 2) * msbfs_stat_spread() * msbfs_stat_fields() * 8;
     const size_t budget = env_size("GUMAP_BFS_BUDGET_MB", 8192) << 20;
     int32_t groups_round = (int32_t)std::max<size_t>(1, std::min<size_t>(groups_total, budget / std::max<size_t>(1, bytes_per_group)));
 
@@ -340,7 +340,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const size_t arr_round = arr_per_group * groups_round;
     if ((st = scratch_get(kSlotBfsState, (3 + (size_t)planes_alloc) * arr_round * 8, (void **)&state))) return st;
     if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * stats_per_level * 8, (void **)&stats))) return st;
-    if ((st = scratch_get(kSlotLvlCnt, (size_t)groups_round * W * 16 * 4, (void **)&lvl_cnt))) return st;
+    const int32_t hop_chunks = msbfs_hop_chunks(n);
+    if ((st = scratch_get(kSlotLvlCnt, (size_t)groups_round * W * hop_chunks * 16 * 4, (void **)&lvl_cnt))) return st;
     if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
     if (!hop_matrix) {
         if ((st = scratch_get(kSlotHopRows, (size_t)groups_round * W * n, (void **)&hop_scratch))) return st;
@@ -376,6 +377,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.slot_of = slot_of;
         a.heavy = heavy;
         a.n_heavy = n_heavy;
+        a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
+        a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
         const size_t arr = arr_per_group * a.groups;
         a.front[0] = state;
         a.front[1] = state + arr;
@@ -387,7 +390,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         const size_t spl = (size_t)a.groups * SP * SF;   // u64 per level this round
         e = hipMemsetAsync(a.front[1], 0, 2 * arr * 8, s);  // front[1] and visited
         if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * spl * 8, s);
-        if (e == hipSuccess) e = hipMemsetAsync(lvl_cnt, 0, (size_t)a.n_slots * 16 * 4, s);
         if (e == hipSuccess) e = launch_msbfs_init(a, s);
         if (e != hipSuccess) return hip_status(e, "bfs init");
 
@@ -481,7 +483,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e == hipSuccess)
             GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
                     launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                              slot_row + a.slot0, lvl_cnt, ids, hops, s));
+                                              slot_row + a.slot0, lvl_cnt, hop_chunks, ids, hops, s));
         if (e != hipSuccess) return hip_status(e, "hop rows / selection");
     }
     if (!dup_pairs.empty()) {

@@ -55,6 +55,8 @@ struct MsbfsArgs {
     int32_t stats_groups;     // groups per stats level
     const int32_t *heavy;     // vertices of degree above msbfs_heavy_degree()
     int32_t n_heavy;
+    int32_t xcd_map;          // keep each group on one XCD when groups % 8 == 0
+    int32_t hops_variant;     // hop-row writer: tiles per step / store kind (tuning)
 };
 // Layout of the level counters: stats[((level * groups + g) * spread + slot) * fields + field]
 // with fields {new bits, frontier words gathered, adjacency entries read,
@@ -71,11 +73,13 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
 // receives the n hop bytes of that slot (planes_used bit-planes committed).
 hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                              const int64_t *slot_row, int64_t row_stride, hipStream_t s);
-// Same, also accumulating per-slot counts of vertices at hops 1..16 into
-// lvl_cnt[local_slot * 16 + h - 1] (zeroed by the caller).
+// Same, also writing per-slot counts of vertices at hops 1..16, one partial
+// count per block of vertex tiles: part[(local_slot * chunks + c) * 16 + h - 1]
+// with chunks = msbfs_hop_chunks(n).
+int msbfs_hop_chunks(int32_t n);
 hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                                      const int64_t *slot_row, int64_t row_stride,
-                                     unsigned int *lvl_cnt, hipStream_t s);
+                                     unsigned int *part, hipStream_t s);
 
 // ------------------------------------------------------- kNN selection ---
 // Rows: for r in [0, rows): hop row hop_rows + row_of[r] * row_stride (n bytes),
@@ -83,11 +87,11 @@ hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_
 hipError_t launch_knn_select(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
                              const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
                              const int64_t *out_row, int32_t *ids, uint8_t *hops, hipStream_t s);
-// Same, with per-row counts of vertices at hops 1..16 (lvl_cnt[r * 16 + h - 1])
-// from launch_msbfs_hops_counted; used when k <= 16.
+// Same, with the per-block counts of vertices at hops 1..16 written by
+// launch_msbfs_hops_counted (part, `chunks` blocks per row); used when k <= 16.
 hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
                                      const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
-                                     const int64_t *out_row, const unsigned int *lvl_cnt,
+                                     const int64_t *out_row, const unsigned int *part, int32_t chunks,
                                      int32_t *ids, uint8_t *hops, hipStream_t s);
 
 // Copy output rows src_row -> dst_row for repeated sources (pairs on device).

@@ -8,7 +8,8 @@
 // counts come either from the BFS transpose (hops 1..16) or from a histogram
 // pass of this kernel.  One streaming pass over the row in id order then
 // writes the taken entries straight to their (hop, id) position and stops as
-// soon as all of them are found.
+// soon as all of them are found.  Bytes are classified four at a time with
+// SWAR compares; only lanes holding a taken entry walk their bytes.
 #include "device.h"
 #include "kernels.h"
 
@@ -18,7 +19,7 @@ namespace {
 
 constexpr int kCountLevels = 16;
 constexpr int kSelWaves = 4;
-#define GUMAP_MAX_K_INTERNAL 254
+constexpr int kMaxK = 254;
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -27,111 +28,161 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Loads the 16 hop bytes of lane-chunk starting at vertex `v` (bytes past n
-// read as 255, i.e. skipped).
-__device__ __forceinline__ void load16(const uint8_t *row, int32_t n, int32_t v, bool aligned,
-                                       uint32_t q[4])
+__device__ __noinline__ uint4 load16_slow(const uint8_t *row, int32_t n, int32_t v)
 {
-    if (aligned && v + 16 <= n) {
-        uint4 x = *(const uint4 *)(row + v);
-        q[0] = x.x; q[1] = x.y; q[2] = x.z; q[3] = x.w;
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t w = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int32_t id = v + 4 * i + j;
-                uint32_t b = id < n ? row[id] : 255u;
-                w |= b << (8 * j);
-            }
-            q[i] = w;
+    uint32_t q[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll 1
+    for (int i = 0; i < 16; ++i) {
+        const int32_t id = v + i;
+        if (id < n) {
+            const uint32_t b = row[id];
+            const int sh = 8 * (i & 3);
+            const uint32_t m = ~(0xFFu << sh);
+            if ((i >> 2) == 0) q[0] = (q[0] & m) | (b << sh);
+            else if ((i >> 2) == 1) q[1] = (q[1] & m) | (b << sh);
+            else if ((i >> 2) == 2) q[2] = (q[2] & m) | (b << sh);
+            else q[3] = (q[3] & m) | (b << sh);
         }
     }
+    return make_uint4(q[0], q[1], q[2], q[3]);
 }
 
-// Selection pass shared by both kernels.  cnt_lds[h] (h = 1..hmax) holds the
-// per-hop counts; got/base are per-wave LDS scratch of 256 ints each.
-__device__ void select_row(const uint8_t *row, int32_t n, int32_t k, int32_t src,
-                           const unsigned int *cnt_lds, int hmax, int *got, int *base,
-                           int32_t *ids_out, uint8_t *hops_out)
+// Loads the 16 hop bytes starting at vertex `v` (bytes past n read as 255).
+__device__ __forceinline__ uint4 load16(const uint8_t *row, int32_t n, int32_t v, bool aligned)
+{
+    if (aligned && v + 16 <= n) return *(const uint4 *)(row + v);
+    return load16_slow(row, n, v);
+}
+
+// High bit of each byte set where the byte is zero.
+__device__ __forceinline__ uint32_t zero_hi(uint32_t y)
+{
+    const uint32_t t = (y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    return ~(t | y | 0x7F7F7F7Fu);
+}
+
+// High bit of each byte set where the byte is >= c (1 <= c <= 128).
+__device__ __forceinline__ uint32_t ge_hi(uint32_t x, uint32_t c)
+{
+    return (x | ((x | 0x80808080u) - c * 0x01010101u)) & 0x80808080u;
+}
+
+struct Classes {
+    uint32_t lt[4], eq[4];   // high-bit masks: 1 <= b < h*, b == h*
+};
+
+__device__ __forceinline__ Classes classify(uint4 q, int hstar, bool swar)
+{
+    Classes c;
+    const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t x = qq[i];
+        if (swar) {
+            c.eq[i] = zero_hi(x ^ ((uint32_t)hstar * 0x01010101u));
+            c.lt[i] = ~ge_hi(x, (uint32_t)hstar) & ~zero_hi(x) & 0x80808080u;
+        } else {
+            uint32_t lt = 0, eq = 0;
+#pragma unroll 1
+            for (int j = 0; j < 4; ++j) {
+                const int b = (x >> (8 * j)) & 0xFF;
+                if (b >= 1 && b < hstar && b <= 254) lt |= 0x80u << (8 * j);
+                if (b == hstar) eq |= 0x80u << (8 * j);
+            }
+            c.lt[i] = lt;
+            c.eq[i] = eq;
+        }
+    }
+    return c;
+}
+
+// Selection pass.  cnt[h] (h = 1..hmax) holds the per-hop counts; got/base
+// are per-wave LDS scratch of 256 ints each.
+__device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsigned int *cnt, int hmax,
+                           int *got, int *base, int32_t *ids_out, uint8_t *hops_out)
 {
     const int l = lane();
-    // last hop and how many to take at it
     int c = 0, hstar = hmax + 1, need = 0;
     for (int h = 1; h <= hmax; ++h) {
-        int ch = (int)cnt_lds[h];
-        if (c + ch >= k) { hstar = h; need = k - c; break; }
+        const int ch = (int)cnt[h];
+        if (c + ch >= k) {
+            hstar = h;
+            need = k - c;
+            break;
+        }
         c += ch;
     }
     const int c_less = c;
-    // output offset of each hop below h*
     if (l == 0) {
         int acc = 0;
         for (int h = 1; h < hstar && h <= hmax; ++h) {
             base[h] = acc;
             got[h] = 0;
-            acc += (int)cnt_lds[h];
+            acc += (int)cnt[h];
         }
     }
     wave_sync();
     const bool aligned = (((uintptr_t)row) & 15) == 0;
+    const bool swar = hstar <= 128;
     int found_lt = 0, found_eq = 0;
     if (c_less > 0 || need > 0) {
+        uint4 q = load16(row, n, 16 * l, aligned);
         for (int32_t vb = 0; vb < n; vb += 16 * GM_WAVE) {
             const int32_t v = vb + 16 * l;
-            uint32_t q[4];
-            load16(row, n, v, aligned, q);
-            int n_lt = 0, n_eq = 0;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                int b = (q[i >> 2] >> (8 * (i & 3))) & 0xFF;
-                n_lt += (b >= 1 && b < hstar && b <= 254);
-                n_eq += (b == hstar);
-            }
+            const uint4 qn = load16(row, n, v + 16 * GM_WAVE, aligned);   // next chunk in flight
+            const Classes cl = classify(q, hstar, swar);
+            const int n_lt = __popc(cl.lt[0]) + __popc(cl.lt[1]) + __popc(cl.lt[2]) + __popc(cl.lt[3]);
+            const int n_eq = __popc(cl.eq[0]) + __popc(cl.eq[1]) + __popc(cl.eq[2]) + __popc(cl.eq[3]);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
             unsigned long long lt_mask = __ballot(n_lt > 0);
-            while (lt_mask) {
-                const int L = __ffsll((long long)lt_mask) - 1;
-                lt_mask &= lt_mask - 1;
-                if (l == L) {
+            if (lt_mask) {
+                found_lt += wave_sum(n_lt);
+                while (lt_mask) {
+                    const int L = __ffsll((long long)lt_mask) - 1;
+                    lt_mask &= lt_mask - 1;
+                    if (l == L) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        int b = (q[i >> 2] >> (8 * (i & 3))) & 0xFF;
-                        if (b >= 1 && b < hstar && b <= 254) {
-                            int pos = base[b] + got[b];
-                            got[b] = got[b] + 1;
-                            if (pos < c_less) {
-                                ids_out[pos] = v + i;
-                                hops_out[pos] = (uint8_t)b;
+                        for (int i = 0; i < 4; ++i) {
+                            uint32_t mk = cl.lt[i];
+                            while (mk) {
+                                const int bit = __ffs(mk) - 1;
+                                mk &= mk - 1;
+                                const int j = bit >> 3;
+                                const int b = (qq[i] >> (8 * j)) & 0xFF;
+                                const int pos = base[b] + got[b];
+                                got[b] = got[b] + 1;
+                                if (pos < c_less) {
+                                    ids_out[pos] = v + 4 * i + j;
+                                    hops_out[pos] = (uint8_t)b;
+                                }
                             }
                         }
                     }
+                    wave_sync();
                 }
-                wave_sync();
             }
-            if (need > 0) {
+            if (found_eq < need) {
                 const int incl = wave_incl_scan(n_eq);
                 int rank = found_eq + incl - n_eq;
                 if (n_eq > 0 && rank < need) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        int b = (q[i >> 2] >> (8 * (i & 3))) & 0xFF;
-                        if (b == hstar) {
-                            if (rank < need) {
-                                ids_out[c_less + rank] = v + i;
-                                hops_out[c_less + rank] = (uint8_t)b;
-                            }
+                    for (int i = 0; i < 4; ++i) {
+                        uint32_t mk = cl.eq[i];
+                        while (mk && rank < need) {
+                            const int bit = __ffs(mk) - 1;
+                            mk &= mk - 1;
+                            ids_out[c_less + rank] = v + 4 * i + (bit >> 3);
+                            hops_out[c_less + rank] = (uint8_t)hstar;
                             ++rank;
                         }
                     }
                 }
                 found_eq += __shfl(incl, GM_WAVE - 1, GM_WAVE);
             }
-            found_lt += wave_sum(n_lt);
             if (found_lt >= c_less && found_eq >= need) break;
+            q = qn;
         }
     }
-    (void)src;
     const int K = c_less + (need < found_eq ? need : found_eq);
     for (int i = K + l; i < k; i += GM_WAVE) {
         ids_out[i] = -1;
@@ -143,20 +194,25 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, int32_t src
 __global__ void __launch_bounds__(kSelWaves * GM_WAVE)
 knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__restrict__ hop_rows,
                           const int64_t *__restrict__ row_of, int64_t row_stride,
-                          const int32_t *__restrict__ src_of, const int64_t *__restrict__ out_row,
-                          const unsigned int *__restrict__ lvl_cnt, int32_t *__restrict__ ids,
-                          uint8_t *__restrict__ hops)
+                          const int64_t *__restrict__ out_row, const unsigned int *__restrict__ part,
+                          int32_t chunks, int32_t *__restrict__ ids, uint8_t *__restrict__ hops)
 {
     __shared__ unsigned int cnt[kSelWaves][kCountLevels + 2];
-    __shared__ int got[kSelWaves][256];
-    __shared__ int base[kSelWaves][256];
+    __shared__ int got[kSelWaves][kCountLevels + 2];
+    __shared__ int base[kSelWaves][kCountLevels + 2];
     const int wid = threadIdx.x / GM_WAVE, l = lane();
     for (int32_t r = blockIdx.x * kSelWaves + wid; r < rows; r += gridDim.x * kSelWaves) {
-        if (l < kCountLevels) cnt[wid][l + 1] = lvl_cnt[(size_t)r * kCountLevels + l];
+        // sum the per-block partial counts: lane = (chunk phase, level)
+        const int h = l & 15;
+        unsigned int sum = 0;
+        for (int32_t cc = l >> 4; cc < chunks; cc += 4) sum += part[((size_t)r * chunks + cc) * kCountLevels + h];
+        sum += __shfl_xor(sum, 16, GM_WAVE);
+        sum += __shfl_xor(sum, 32, GM_WAVE);
+        if (l < kCountLevels) cnt[wid][l + 1] = sum;
         wave_sync();
         const uint8_t *row = hop_rows + row_of[r] * row_stride;
         const int64_t o = out_row[r] * (int64_t)k;
-        select_row(row, n, k, src_of[r], cnt[wid], kCountLevels, got[wid], base[wid], ids + o, hops + o);
+        select_row(row, n, k, cnt[wid], kCountLevels, got[wid], base[wid], ids + o, hops + o);
         wave_sync();
     }
 }
@@ -165,8 +221,8 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
 __global__ void __launch_bounds__(GM_WAVE)
 knn_select_hist_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__restrict__ hop_rows,
                        const int64_t *__restrict__ row_of, int64_t row_stride,
-                       const int32_t *__restrict__ src_of, const int64_t *__restrict__ out_row,
-                       int32_t *__restrict__ ids, uint8_t *__restrict__ hops)
+                       const int64_t *__restrict__ out_row, int32_t *__restrict__ ids,
+                       uint8_t *__restrict__ hops)
 {
     extern __shared__ unsigned int bins[];  // [(k + 1)][64] then cnt[256]
     unsigned int *cnt = bins + (size_t)(k + 1) * GM_WAVE;
@@ -179,11 +235,11 @@ knn_select_hist_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__rest
         const uint8_t *row = hop_rows + row_of[r] * row_stride;
         const bool aligned = (((uintptr_t)row) & 15) == 0;
         for (int32_t vb = 0; vb < n; vb += 16 * GM_WAVE) {
-            uint32_t q[4];
-            load16(row, n, vb + 16 * l, aligned, q);
-#pragma unroll
+            const uint4 q = load16(row, n, vb + 16 * l, aligned);
+            const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll 1
             for (int i = 0; i < 16; ++i) {
-                int b = (q[i >> 2] >> (8 * (i & 3))) & 0xFF;
+                const int b = (qq[i >> 2] >> (8 * (i & 3))) & 0xFF;
                 if (b >= 1 && b <= k) bins[b * GM_WAVE + l] += 1;
             }
         }
@@ -195,7 +251,7 @@ knn_select_hist_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__rest
         }
         wave_sync();
         const int64_t o = out_row[r] * (int64_t)k;
-        select_row(row, n, k, src_of[r], cnt, k, got, base, ids + o, hops + o);
+        select_row(row, n, k, cnt, k, got, base, ids + o, hops + o);
         wave_sync();
     }
 }
@@ -219,28 +275,29 @@ __global__ void copy_rows_kernel(int32_t pairs, const int64_t *__restrict__ dst_
 
 hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
                                      const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
-                                     const int64_t *out_row, const unsigned int *lvl_cnt,
+                                     const int64_t *out_row, const unsigned int *part, int32_t chunks,
                                      int32_t *ids, uint8_t *hops, hipStream_t s)
 {
+    (void)src_of;
     if (rows <= 0) return hipSuccess;
-    if (lvl_cnt && k <= kCountLevels) {
+    if (part && k <= kCountLevels) {
         int blocks = (rows + kSelWaves - 1) / kSelWaves;
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(knn_select_counted_kernel, dim3(blocks), dim3(kSelWaves * GM_WAVE), 0, s,
-                           n, k, rows, hop_rows, row_of, row_stride, src_of, out_row, lvl_cnt, ids, hops);
+        hipLaunchKernelGGL(knn_select_counted_kernel, dim3(blocks), dim3(kSelWaves * GM_WAVE), 0, s, n, k,
+                           rows, hop_rows, row_of, row_stride, out_row, part, chunks, ids, hops);
     } else {
-        size_t lds = ((size_t)(k + 1) * GM_WAVE + 256) * sizeof(unsigned int);
+        const size_t lds = ((size_t)(k + 1) * GM_WAVE + 256) * sizeof(unsigned int);
         static bool lds_set = false;
         if (!lds_set) {
             hipError_t e = hipFuncSetAttribute((const void *)knn_select_hist_kernel,
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(((size_t)(GUMAP_MAX_K_INTERNAL + 1) * GM_WAVE + 256) * sizeof(unsigned int)));
+                                               (int)(((size_t)(kMaxK + 1) * GM_WAVE + 256) * sizeof(unsigned int)));
             if (e != hipSuccess) return e;
             lds_set = true;
         }
-        int blocks = rows > 65536 ? 65536 : rows;
-        hipLaunchKernelGGL(knn_select_hist_kernel, dim3(blocks), dim3(GM_WAVE), lds, s, n, k, rows,
-                           hop_rows, row_of, row_stride, src_of, out_row, ids, hops);
+        const int blocks = rows > 65536 ? 65536 : rows;
+        hipLaunchKernelGGL(knn_select_hist_kernel, dim3(blocks), dim3(GM_WAVE), lds, s, n, k, rows, hop_rows,
+                           row_of, row_stride, out_row, ids, hops);
     }
     return hipGetLastError();
 }
@@ -249,8 +306,8 @@ hipError_t launch_knn_select(int32_t n, int32_t k, int32_t rows, const uint8_t *
                              const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
                              const int64_t *out_row, int32_t *ids, uint8_t *hops, hipStream_t s)
 {
-    return launch_knn_select_counted(n, k, rows, hop_rows, row_of, row_stride, src_of, out_row,
-                                     nullptr, ids, hops, s);
+    return launch_knn_select_counted(n, k, rows, hop_rows, row_of, row_stride, src_of, out_row, nullptr, 0,
+                                     ids, hops, s);
 }
 
 hipError_t launch_copy_rows(int32_t pairs, const int64_t *dst_src, int32_t k, int32_t n,

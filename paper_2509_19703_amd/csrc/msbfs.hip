@@ -28,10 +28,11 @@ namespace gm {
 
 namespace {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kLevelBlock = 256;
 constexpr int kHeavyDeg = 64;      // above this degree a vertex gets a whole wave
 constexpr int kHopTilesPerWave = 16;
-constexpr int kHopWaves = 4;
 constexpr int kCountLevels = 16;
 constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
 constexpr int kStatFields = 4;
@@ -79,12 +80,23 @@ __device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, s
 
 template <int WORDS>
 __global__ void __launch_bounds__(kLevelBlock)
-msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks)
+msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, int per_group, int xcd_map)
 {
     constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
     constexpr int G = GM_WAVE / WORDS;            // neighbour lanes per word in a heavy wave
     __shared__ unsigned long long red[kLevelBlock / GM_WAVE][kStatFields];
-    const int32_t g = blockIdx.y;
+    // Workgroups are handed to the 8 XCDs round-robin by linear id.  With
+    // xcd_map, group g runs only on XCD g % 8, so its frontier stays in that
+    // XCD's L2 instead of being cached by all of them.
+    int32_t g, vb;
+    if (xcd_map) {
+        const int32_t xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+        g = xcd + 8 * (j / per_group);
+        vb = j % per_group;
+    } else {
+        g = blockIdx.x / per_group;
+        vb = blockIdx.x % per_group;
+    }
     const int l = lane(), wid = threadIdx.x / GM_WAVE;
     if (level >= 2) {
         // previous level found nothing for this group: nothing to commit or search
@@ -95,10 +107,10 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks)
     Counters c{};
     const size_t gbase = (size_t)g * a.n * WORDS;
     const uint64_t *__restrict__ fr = a.front[level & 1];
-    if ((int)blockIdx.x < light_blocks) {
+    if (vb < light_blocks) {
         // one thread per (vertex, word); vertices of degree > kHeavyDeg are left
         // to the heavy waves (except at level 1, where all are done here)
-        const int64_t idx = (int64_t)blockIdx.x * kLevelBlock + threadIdx.x;
+        const int64_t idx = (int64_t)vb * kLevelBlock + threadIdx.x;
         const int32_t v = (int32_t)(idx >> LW);
         const int w = (int)(idx & (WORDS - 1));
         int cols = 0;
@@ -161,7 +173,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks)
         if (w == 0) c.v[kFieldCols] += cols;
     } else if (level >= 2) {
         // one wave per heavy vertex: lane = (neighbour group, word)
-        const int32_t hidx = ((int)blockIdx.x - light_blocks) * (kLevelBlock / GM_WAVE) + wid;
+        const int32_t hidx = (vb - light_blocks) * (kLevelBlock / GM_WAVE) + wid;
         if (hidx < a.n_heavy) {
             const int32_t v = a.heavy[hidx];
             const int w = l & (WORDS - 1), grp = l >> LW;
@@ -213,7 +225,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks)
         unsigned long long t = 0;
         for (int q = 0; q < kLevelBlock / GM_WAVE; ++q) t += red[q][threadIdx.x];
         if (t)
-            atomicAdd(&a.stats[(((size_t)level * a.stats_groups + g) * kSpread + (blockIdx.x & (kSpread - 1))) *
+            atomicAdd(&a.stats[(((size_t)level * a.stats_groups + g) * kSpread + (vb & (kSpread - 1))) *
                                    kStatFields + threadIdx.x],
                       t);
     }
@@ -251,93 +263,108 @@ __device__ __forceinline__ uint64_t spread8(uint64_t bits8)
     return t;
 }
 
-// Block: kHopWaves waves on one (group, word); each wave walks vertex tiles of
-// 64.  Lane j ends with the hop bytes of slot (group, word, j) for the tile.
-__global__ void __launch_bounds__(kHopWaves * GM_WAVE)
+// Block: one wave per word of a group, all on the same vertex tiles, so the
+// waves of a block together read whole 64-byte state rows.  Wave w walks
+// kHopTilesPerWave tiles of 64 vertices; lane j ends with the hop bytes of
+// slot (group, w, j) for the tile and writes them (64 bytes) to its row.
+// Per-slot counts of vertices at hops 1..16 are written per block (no
+// atomics) to part[(slot * chunks + block) * 16 + h - 1].
+template <int WORDS, int STEP, bool NT>
+__global__ void __launch_bounds__(WORDS * GM_WAVE)
 msbfs_hops_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
-                  const int64_t *__restrict__ slot_row, int64_t row_stride,
-                  unsigned int *__restrict__ lvl_cnt)
+                  const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part)
 {
-    __shared__ unsigned int red[kHopWaves][kCountLevels][GM_WAVE];
-    const int wid = threadIdx.x / GM_WAVE, l = lane();
-    const int32_t gw = blockIdx.y;                 // group * words + word
-    const int32_t g = gw / a.words, w = gw % a.words;
-    const int lw = __ffs(a.words) - 1;
-    const int32_t local_slot = g * 64 * a.words + 64 * w + l;
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const int w = threadIdx.x / GM_WAVE, l = lane();
+    const int32_t g = blockIdx.y;
+    const int32_t local_slot = g * 64 * WORDS + 64 * w + l;
     const bool slot_ok = local_slot < a.n_slots;
     const int64_t row = slot_ok ? slot_row[local_slot] : 0;
     const int32_t ntiles = (a.n + 63) / 64;
-    const size_t gbase = (size_t)g * a.n * a.words + w;
+    const size_t gbase = (size_t)g * a.n * WORDS + w;
     unsigned int cnt[kCountLevels];
 #pragma unroll
     for (int h = 0; h < kCountLevels; ++h) cnt[h] = 0;
 
-    const int32_t t0 = blockIdx.x * (kHopWaves * kHopTilesPerWave);
-    for (int it = 0; it < kHopTilesPerWave; ++it) {
-        const int32_t tile = t0 + it * kHopWaves + wid;
-        if (tile >= ntiles) break;
-        const int32_t v0 = tile * 64;
-        const int32_t v = v0 + l;
-        const size_t me = gbase + ((size_t)v << lw);
-        uint64_t vis = v < a.n ? a.visited[me] : 0ull;
-        uint64_t pl[8];
+    // tiles of 64 vertices, STEP at a time: each lane then writes 64 * STEP
+    // contiguous bytes of its row per step
+    const int32_t t_begin = blockIdx.x * kHopTilesPerWave;
+    const int32_t t_end = min(ntiles, t_begin + kHopTilesPerWave);
+    for (int32_t tile = t_begin; tile < t_end; tile += STEP) {
+        uint64_t outw[STEP][8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) pl[b] = (b < planes_used && v < a.n) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
-        vis = transpose64(vis);
+        for (int half = 0; half < STEP; ++half) {
+            const int32_t v = (tile + half) * 64 + l;
+            const bool in = v < a.n && tile + half < t_end;
+            const size_t me = gbase + ((size_t)v << LW);
+            uint64_t vis = in ? a.visited[me] : 0ull;
+            uint64_t pl[8];
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
-            if (b < planes_used) pl[b] = transpose64(pl[b]);
-        // counts of vertices at hops 1..16 (planes 5.. must be clear)
-        uint64_t high = 0;
+            for (int b = 0; b < 8; ++b) pl[b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
+            vis = transpose64(vis);
 #pragma unroll
-        for (int b = 5; b < 8; ++b) high |= pl[b];
-        const uint64_t low_ok = vis & ~high;
+            for (int b = 0; b < 8; ++b)
+                if (b < planes_used) pl[b] = transpose64(pl[b]);
+            // counts of vertices at hops 1..16 (planes 5.. must be clear)
+            uint64_t high = 0;
 #pragma unroll
-        for (int h = 1; h <= kCountLevels; ++h) {
-            uint64_t m = low_ok;
+            for (int b = 5; b < 8; ++b) high |= pl[b];
+            const uint64_t low_ok = vis & ~high;
 #pragma unroll
-            for (int b = 0; b < 5; ++b) m &= ((h >> b) & 1) ? pl[b] : ~pl[b];
-            cnt[h - 1] += __popcll(m);
-        }
-        if (slot_ok) {
-            uint8_t *dst = hop_out + row * row_stride + v0;
-            const int valid = min(64, a.n - v0);
-            uint64_t outw[8];
+            for (int h = 1; h <= kCountLevels; ++h) {
+                uint64_t m = low_ok;
+#pragma unroll
+                for (int b = 0; b < 5; ++b) m &= ((h >> b) & 1) ? pl[b] : ~pl[b];
+                cnt[h - 1] += __popcll(m);
+            }
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 uint64_t by = spread8(~vis >> (8 * c)) * 0xFFull;
 #pragma unroll
-                for (int b = 0; b < 8; ++b) by |= spread8(pl[b] >> (8 * c)) << b;
-                outw[c] = by;
+                for (int b = 0; b < 8; ++b)
+                    if (b < planes_used) by |= spread8(pl[b] >> (8 * c)) << b;
+                outw[half][c] = by;
             }
-            if (valid == 64 && (((uintptr_t)dst) & 15) == 0) {
-                uint4 *d4 = (uint4 *)dst;
+        }
+        if (slot_ok) {
+            const int32_t v0 = tile * 64;
+            uint8_t *dst = hop_out + row * row_stride + v0;
+            const int valid = min(min(64 * STEP, a.n - v0), (t_end - tile) * 64);
+            if (valid == 64 * STEP && (((uintptr_t)dst) & 15) == 0) {
+                u32x4 *d4 = (u32x4 *)dst;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    uint4 q;
-                    q.x = (uint32_t)outw[2 * c];
-                    q.y = (uint32_t)(outw[2 * c] >> 32);
-                    q.z = (uint32_t)outw[2 * c + 1];
-                    q.w = (uint32_t)(outw[2 * c + 1] >> 32);
-                    d4[c] = q;
+                for (int c = 0; c < 4 * STEP; ++c) {
+                    const uint64_t lo = outw[c >> 2][(2 * c) & 7], hi = outw[c >> 2][(2 * c + 1) & 7];
+                    u32x4 q = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+                    if (NT) __builtin_nontemporal_store(q, d4 + c);
+                    else d4[c] = q;
                 }
             } else {
-                for (int i = 0; i < valid; ++i) dst[i] = (uint8_t)(outw[i >> 3] >> (8 * (i & 7)));
+                for (int i = 0; i < valid; ++i) dst[i] = (uint8_t)(outw[i >> 6][(i >> 3) & 7] >> (8 * (i & 7)));
             }
         }
     }
-    if (lvl_cnt) {
+    if (part && slot_ok) {
+        uint4 *p = (uint4 *)(part + ((size_t)local_slot * gridDim.x + blockIdx.x) * kCountLevels);
 #pragma unroll
-        for (int h = 0; h < kCountLevels; ++h) red[wid][h][l] = cnt[h];
-        __syncthreads();
-        if (wid == 0 && slot_ok) {
-            for (int h = 0; h < kCountLevels; ++h) {
-                unsigned int s = 0;
-                for (int q = 0; q < kHopWaves; ++q) s += red[q][h][l];
-                if (s) atomicAdd(&lvl_cnt[(size_t)local_slot * kCountLevels + h], s);
-            }
-        }
+        for (int q = 0; q < kCountLevels / 4; ++q) p[q] = make_uint4(cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]);
     }
+}
+
+template <int WORDS>
+hipError_t launch_hops_words(dim3 grid, int variant, const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
+                             const int64_t *slot_row, int64_t row_stride, unsigned int *part, hipStream_t s)
+{
+    dim3 block(WORDS * GM_WAVE);
+    if (variant == 1)
+        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+    else if (variant == 2)
+        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, true>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+    else if (variant == 3)
+        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 1, true>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+    else
+        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 1, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -354,13 +381,15 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
     const int64_t items = (int64_t)a.n * a.words;
     const int light = (int)((items + kLevelBlock - 1) / kLevelBlock);
     const int heavy = level >= 2 ? (a.n_heavy + kLevelBlock / GM_WAVE - 1) / (kLevelBlock / GM_WAVE) : 0;
-    dim3 grid((unsigned)(light + heavy), (unsigned)a.groups);
+    const int per_group = light + heavy;
+    const int xcd = (a.xcd_map && a.groups % 8 == 0) ? 1 : 0;
+    dim3 grid((unsigned)((int64_t)per_group * a.groups));
     const int co = commit_only ? 1 : 0;
     switch (a.words) {
-    case 1: hipLaunchKernelGGL(msbfs_level_kernel<1>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
-    case 2: hipLaunchKernelGGL(msbfs_level_kernel<2>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
-    case 4: hipLaunchKernelGGL(msbfs_level_kernel<4>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
-    case 8: hipLaunchKernelGGL(msbfs_level_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, co, light); break;
+    case 1: hipLaunchKernelGGL(msbfs_level_kernel<1>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
+    case 2: hipLaunchKernelGGL(msbfs_level_kernel<2>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
+    case 4: hipLaunchKernelGGL(msbfs_level_kernel<4>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
+    case 8: hipLaunchKernelGGL(msbfs_level_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -378,16 +407,21 @@ int msbfs_stat_fields() { return kStatFields; }
 int msbfs_stat_spread() { return kSpread; }
 int msbfs_heavy_degree() { return kHeavyDeg; }
 
+int msbfs_hop_chunks(int32_t n) { return ((n + 63) / 64 + kHopTilesPerWave - 1) / kHopTilesPerWave; }
+
 hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                                      const int64_t *slot_row, int64_t row_stride,
-                                     unsigned int *lvl_cnt, hipStream_t s)
+                                     unsigned int *part, hipStream_t s)
 {
-    const int32_t ntiles = (a.n + 63) / 64;
-    const int32_t per_block = kHopWaves * kHopTilesPerWave;
-    dim3 grid((unsigned)((ntiles + per_block - 1) / per_block), (unsigned)(a.groups * a.words));
-    hipLaunchKernelGGL(msbfs_hops_kernel, grid, dim3(kHopWaves * GM_WAVE), 0, s, a, planes_used,
-                       hop_out, slot_row, row_stride, lvl_cnt);
-    return hipGetLastError();
+    dim3 grid((unsigned)msbfs_hop_chunks(a.n), (unsigned)a.groups);
+    const int variant = a.hops_variant;
+    switch (a.words) {
+    case 1: return launch_hops_words<1>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
+    case 2: return launch_hops_words<2>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
+    case 4: return launch_hops_words<4>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
+    case 8: return launch_hops_words<8>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
