@@ -31,6 +31,11 @@ METRIC = "GTEPS + kNN graphs/sec vs plain; p50/p99 served latency, bit-exact"
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve"])
+    p.add_argument("--batch-graphs", type=int, default=2048)
+    p.add_argument("--serve-jobs", type=int, default=1024)
+    p.add_argument("--serve-pool", type=int, default=64)
+    p.add_argument("--serve-budget-gb", type=float, default=64.0)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--k", type=int, default=15)
@@ -63,6 +68,13 @@ def main():
 
     import graphgen as G
     import paper_2509_19703_amd as gm
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload in ("grid", "er"):
+        return bench_allsource(args)
 
     if args.calibrate_copy:
         n_bytes = 1 << 30
@@ -177,6 +189,305 @@ def main():
         out["parity_sampled_bit_exact"] = bool(ok)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, src, k, m, args.cpu_sample_sources)
+    print(json.dumps(out), flush=True)
+
+
+def _profiled(gm, fn, steps):
+    """Runs fn() `steps` times with the launch profiler on; returns (s per step, entries)."""
+    import torch
+    gm.profile_reset()
+    gm.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    gm.profile_enable(False)
+    return dt, gm.profile_entries()
+
+
+def _roofline(prof, steps):
+    dom = max(prof, key=lambda kname: prof[kname]["total_ms"])
+    d = prof[dom]
+    achieved = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": d["launches"],
+            "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
+            "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]}, \
+        {kname: v["total_ms"] / steps for kname, v in prof.items()}
+
+
+def bench_allsource(args):
+    """Plain GUMAP C0 + C1 on one graph: all-source BFS with the uint8 hop
+    matrix, (hop, id) kNN and membership (32x32 grid or dense ER)."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    k = args.k
+    g = G.config_grid() if args.workload == "grid" else G.config_er()
+    n, m = g.n, g.m
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    hops = torch.empty((n, k), dtype=torch.uint8, device="cuda")
+    hm = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    w = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    rho = torch.empty(n, dtype=torch.float32, device="cuda")
+    sigma = torch.empty(n, dtype=torch.float32, device="cuda")
+    gg = gm.make_graph(rp, ci, flags=gm.CSR_SORTED)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        gm.gumap_knn_build(gg, k, None, 0, ids, hops, hm, stream)
+        gm.gumap_membership(n, k, hops, w, rho, sigma, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dt, prof = _profiled(gm, step, args.steps)
+    roof, kms = _roofline(prof, args.steps)
+    out = {"metric": METRIC, "value": n * m / dt / 1e9, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "%s: all-source BFS with uint8 hop matrix, (hop,id) kNN k=%d, FP32 membership"
+                                  % (g.name or args.workload, k), "n": n, "m": m, "k": k},
+           "roofline": roof, "kernels_ms_per_step": kms}
+    if not args.no_parity:
+        import oracle as O
+        pick = np.arange(0, n, max(1, n // 64))
+        oi, oh, ohm = O.knn_build(g, k, sources=pick, hop_matrix=True)
+        pt = torch.from_numpy(pick).cuda()
+        out["parity_sampled_bit_exact"] = bool(np.array_equal(ids[pt].cpu().numpy(), oi)
+                                               and np.array_equal(hops[pt].cpu().numpy(), oh)
+                                               and np.array_equal(hm[pt].cpu().numpy(), ohm))
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        sub = np.arange(0, n, max(1, n // (n if n <= 2048 else 256)))
+        t0 = time.perf_counter()
+        _, oh, _ = O.knn_build(g, k, sources=sub, hop_matrix=True, threads=threads)
+        t_b = (time.perf_counter() - t0) * n / len(sub)
+        t = t_b
+        out["cpu_baseline"] = {"value": n * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+                               "sample": "oracle all-source BFS + kNN from %d of %d sources, scaled" % (len(sub), n)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Many uneven graphs: partial BFS kNN + membership for every vertex of
+    every graph, as one persistent launch (captured plan) against the plain
+    per-graph loop (two synchronous calls per graph)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    k = args.k
+    t0 = time.perf_counter()
+    graphs = G.config_batch_graphs(args.batch_graphs)
+    t_gen = time.perf_counter() - t0
+    pb = gm.PackedBatch(graphs)
+    rows = pb.total_vertices
+    voff, eoff = pb.vtx_offset_host, pb.edge_offset_host
+    ids = torch.empty((rows, k), dtype=torch.int32, device="cuda")
+    hops = torch.empty((rows, k), dtype=torch.uint8, device="cuda")
+    w = torch.empty((rows, k), dtype=torch.float32, device="cuda")
+    rho = torch.empty(rows, dtype=torch.float32, device="cuda")
+    sigma = torch.empty(rows, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    # plain per-graph loop, arguments prepared up front
+    plain_args = []
+    for i, g in enumerate(graphs):
+        gg = gm.gumap_graph(g.n, g.nnz, ctypes.c_void_p(pb.row_ptr.data_ptr() + 4 * int(voff[i] + i)),
+                            ctypes.c_void_p(pb.col_idx.data_ptr() + 4 * int(eoff[i])) if g.nnz else None,
+                            gm.CSR_SORTED)
+        r0 = int(voff[i])
+        plain_args.append((gg, g.n, ctypes.c_void_p(ids.data_ptr() + 4 * r0 * k),
+                           ctypes.c_void_p(hops.data_ptr() + r0 * k), ctypes.c_void_p(w.data_ptr() + 4 * r0 * k),
+                           ctypes.c_void_p(rho.data_ptr() + 4 * r0), ctypes.c_void_p(sigma.data_ptr() + 4 * r0)))
+    lib = gm.lib
+
+    def plain():
+        for gg, n, pi, ph, pw, pr, ps in plain_args:
+            st = lib.gumap_knn_partial(ctypes.byref(gg), k, pi, ph, sp)
+            st |= lib.gumap_membership(n, k, ph, pw, pr, ps, sp)
+            if st:
+                raise gm.GumapError(st, gm.last_error())
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ref = [t.cpu().numpy() for t in (ids, hops, w, rho, sigma)]
+    for t in (ids, hops, w, rho, sigma):
+        t.zero_()
+    b = pb.struct()
+
+    def batched():
+        gm.gumap_knn_partial_batch(b, k, ids, hops, w, rho, sigma, stream)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    dt_batch, prof = _profiled(gm, batched, args.steps)
+    roof, kms = _roofline(prof, args.steps)
+    same_plain = all(np.array_equal(a, t.cpu().numpy()) for a, t in zip(ref, (ids, hops, w, rho, sigma)))
+    plan = gm.BatchPlan(pb, k)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    dt_plan = (time.perf_counter() - t0) / args.steps
+    same_plan = all(np.array_equal(a, t.cpu().numpy()) for a, t in
+                    zip(ref, (plan.ids, plan.hops, plan.weights, plan.rho, plan.sigma)))
+    ng = len(graphs)
+    best = min(dt_batch, dt_plan)
+    out = {"metric": METRIC, "value": ng / best, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": best * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8+f64", "data": "synthetic",
+           "config": {"workload": "batch%d: %d graphs, n log-uniform [256, 16384], mean degree U[4, 32], "
+                                  "BA/RGG/SBM thirds; partial BFS kNN k=%d + FP32 membership for all %d rows"
+                                  % (ng, ng, k, rows), "graphs": ng, "rows": rows, "nnz": pb.total_nnz, "k": k},
+           "graphs_per_s_plain_loop": ng / t_plain, "speedup_vs_plain": t_plain / best,
+           "ms_batched_call": dt_batch * 1e3, "ms_plan_replay": dt_plan * 1e3, "ms_plain_loop": t_plain * 1e3,
+           "rows_per_s": rows / best, "roofline": roof, "kernels_ms_per_step": kms,
+           "batched_equals_plain": bool(same_plain), "plan_equals_plain": bool(same_plan),
+           "host_generation_s": t_gen}
+    if not args.no_parity:
+        import oracle as O
+        ok = True
+        for i in range(0, ng, max(1, ng // 24)):
+            oi, oh = O.knn_partial(graphs[i], k)
+            r0, r1 = int(voff[i]), int(voff[i + 1])
+            ok = ok and np.array_equal(ref[0][r0:r1], oi) and np.array_equal(ref[1][r0:r1], oh)
+        out["parity_sampled_bit_exact"] = bool(ok)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        pick = list(range(0, ng, 8))
+        t0 = time.perf_counter()
+        for i in pick:
+            _, oh = O.knn_partial(graphs[i], k, threads=threads)
+            O.membership(oh, k, threads=threads)
+        t = (time.perf_counter() - t0) * ng / len(pick)
+        out["cpu_baseline"] = {"value": ng / t, "unit": "graphs/s", "cores": threads, "kind": "oracle",
+                               "sample": "oracle partial BFS + membership on %d of the %d graphs, scaled"
+                                         % (len(pick), ng)}
+    print(json.dumps(out), flush=True)
+
+
+def _gen_job_graph(job):
+    import graphgen as G
+    g = G.stream_job_graph(job)
+    return g.n, g.row_ptr, g.col_idx
+
+
+def bench_serve(args):
+    """Served request stream: jobs (graph + k) arrive by a Poisson process at
+    0.8 x the measured saturation rate; latency submit -> done per job."""
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    jobs = G.config_stream_jobs(args.serve_jobs)
+    pool_n = min(args.serve_pool, len(jobs))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        graphs = pool.map(_gen_job_graph, jobs[:pool_n])
+    t_gen = time.perf_counter() - t0
+    gk = [(graphs[i % pool_n], jobs[i]["k"]) for i in range(len(jobs))]
+    budget = int(args.serve_budget_gb * (1 << 30))
+    warm = max(1, len(jobs) // 8)
+    server = gm.Server(budget)
+    # saturation: everything submitted at once
+    t0 = time.perf_counter()
+    tk = [server.submit(rp, ci, k) for (n, rp, ci), k in gk[:warm * 2]]
+    for t in tk:
+        server.wait(t)
+        server.release(t)
+    sat_rate = len(tk) / (time.perf_counter() - t0)
+    rate = 0.8 * sat_rate
+    # Poisson arrivals at `rate`
+    gaps = -np.log1p(-G.uniform(G.BASE_SEED + 200, len(jobs))) / rate
+    arrivals = np.cumsum(gaps)
+    tickets = [None] * len(jobs)
+
+    def submitter():
+        start = time.perf_counter()
+        for i, ((n, rp, ci), k) in enumerate(gk):
+            delay = arrivals[i] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = server.submit(rp, ci, k)
+
+    th = threading.Thread(target=submitter)
+    t_start = time.perf_counter()
+    th.start()
+    lat = []
+    first_done = last_done = None
+    for i in range(len(jobs)):
+        while tickets[i] is None:
+            time.sleep(0.0002)
+        r = server.wait(tickets[i])
+        if r["status"] != gm.OK:
+            raise RuntimeError("job %d failed: %d" % (i, r["status"]))
+        if i >= warm:
+            lat.append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
+            first_done = r["t_submit_ns"] if first_done is None else first_done
+            last_done = r["t_done_ns"]
+        if i == 3 and not args.no_parity:
+            keep = r
+        server.release(tickets[i])
+    th.join()
+    t_total = time.perf_counter() - t_start
+    stats = server.stats()
+    lat = np.array(lat)
+    measured = len(jobs) - warm
+    out = {"metric": METRIC, "value": measured / ((last_done - first_done) / 1e9), "unit": "graphs/s",
+           "n_gpus": 1, "steps": len(jobs), "warmup": warm, "ms_per_step": float(np.mean(lat)),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8+f64",
+           "data": "synthetic",
+           "config": {"workload": "stream: %d jobs (first %d warm-up), Poisson arrivals at 0.8x saturation "
+                                  "(%.1f jobs/s), graphs BA/RGG/SBM n log-uniform [1e3, 2e5], degree U[4, 64], "
+                                  "k in {10, 15, 30}; %d distinct graphs reused round-robin; budget %.0f GB"
+                                  % (len(jobs), warm, rate, pool_n, args.serve_budget_gb),
+                      "jobs": len(jobs), "rate_jobs_per_s": rate, "budget_bytes": budget},
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "saturation_graphs_per_s": sat_rate, "iterations": stats["iterations"],
+           "peak_resident_bytes": stats["peak_resident_bytes"], "wall_s": t_total, "host_generation_s": t_gen}
+    # plain loop on the same GPU: copy in, two synchronous calls, copy out, per job
+    plain = gk[:min(64, len(gk))]
+    t0 = time.perf_counter()
+    for (n, rp, ci), k in plain:
+        drp = torch.from_numpy(rp).cuda()
+        dci = torch.from_numpy(ci).cuda()
+        i_, h_ = gm.knn_partial(drp, dci, k, flags=gm.CSR_SORTED)
+        w_, r_, s_ = gm.membership(h_)
+        i_.cpu(), h_.cpu(), w_.cpu(), r_.cpu(), s_.cpu()
+    t_plain = (time.perf_counter() - t0) / len(plain)
+    out["graphs_per_s_plain_loop"] = 1.0 / t_plain
+    out["speedup_vs_plain"] = out["saturation_graphs_per_s"] * t_plain
+    if not args.no_parity:
+        import oracle as O
+        (n, rp, ci), k = gk[3]
+        g = G.CSR(n, rp, ci)
+        oi, oh = O.knn_partial(g, k)
+        out["parity_sampled_bit_exact"] = bool(np.array_equal(keep["ids"], oi) and np.array_equal(keep["hops"], oh))
+    server.close()
     print(json.dumps(out), flush=True)
 
 

@@ -695,7 +695,9 @@ int batch_enqueue(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, 
     int64_t want = (b->total_vertices + 4 * a.chunk - 1) / (4 * a.chunk);
     a.blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(maxb, want));
     hipError_t e = launch_batch_reset(counter, s);
-    if (e == hipSuccess) e = launch_partial_batch(a, s);
+    if (e == hipSuccess)
+        GM_PROF("partial_batch", (double)b->total_vertices * (8.0 + 5.0 * k + (w ? 4.0 * k + 8.0 : 0.0)),
+                launch_partial_batch(a, s));
     return hip_status(e, "batch launch");
 }
 

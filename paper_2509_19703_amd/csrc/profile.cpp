@@ -62,6 +62,11 @@ int prof_begin(const char *name, hipStream_t s)
 {
     Profiler &p = prof();
     if (!p.on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return -1;   // never record profiling events into a captured graph
+    }
     std::lock_guard<std::mutex> lk(p.mu);
     Pending x;
     x.name = name;

@@ -227,3 +227,18 @@ def test_build_equals_partial(gumap):
             pids, phops = gumap.knn_partial(rp, ci, k, flags=gumap.CSR_SORTED)
             assert np.array_equal(ids.cpu().numpy(), pids.cpu().numpy())
             assert np.array_equal(hops.cpu().numpy(), phops.cpu().numpy())
+
+
+@pytest.mark.parametrize("lanes", ["0", "16", "32", "64"])
+def test_partial_lane_width_invariance(gumap, lanes, monkeypatch):
+    """The register-resident search (16/32/64 lanes per source) and the
+    one-wave LDS form give identical rows."""
+    monkeypatch.setenv("GUMAP_PARTIAL_LANES", lanes)
+    for g in (G.ba(3000, 4, 91), G.rgg(3000, 7, 92), G.star(600),
+              G.disjoint_union([G.path(3), G.empty(2), G.complete(20)])):
+        rp, ci = to_dev(g)
+        for k in (1, 5, 15, 31, 63):
+            ids, hops = gumap.knn_partial(rp, ci, k, flags=gumap.CSR_SORTED)
+            oi, oh = O.knn_partial(g, k)
+            assert np.array_equal(ids.cpu().numpy(), oi), (lanes, k, first_mismatch(ids.cpu().numpy(), oi))
+            assert np.array_equal(hops.cpu().numpy(), oh)
