@@ -214,7 +214,9 @@ typedef struct gumap_server_stats {
 #define GUMAP_SERVER_NO_DEVICE 1u
 
 /* hbm_budget_bytes: device bytes the resident jobs may hold together;
- * max_slots: jobs admitted at once (0 = no limit). */
+ * max_slots: jobs admitted at once (0 = no limit).  Job inputs and results
+ * are staged in a pinned host pool (GUMAP_SERVE_HOST_POOL_MB, default 4096);
+ * when it is full, pageable host memory is used instead. */
 gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, uint32_t flags,
                                   int *status);
 /* Copies the job and returns a ticket.  GUMAP_E2BIG if it can never fit. */

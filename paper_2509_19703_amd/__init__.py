@@ -404,23 +404,29 @@ class Server:
                 out[key] = out[key].reshape(n, k)
         return out
 
-    def poll(self, ticket: int):
+    @staticmethod
+    def _times(r: gumap_result) -> dict:
+        return {"status": r.status, "n": r.n, "k": r.k, "t_submit_ns": r.t_submit_ns,
+                "t_admit_ns": r.t_admit_ns, "t_start_ns": r.t_start_ns, "t_done_ns": r.t_done_ns}
+
+    def poll(self, ticket: int, copy_results: bool = True):
         r = gumap_result()
         st = lib.gumap_poll(self._h, ticket, ctypes.byref(r))
         if st == PENDING:
             return None
         if st < 0 and st != r.status:
             raise GumapError(st, last_error())
-        return self._unpack(r)
+        return self._unpack(r) if copy_results else self._times(r)
 
-    def wait(self, ticket: int, timeout_ms: int = -1):
+    def wait(self, ticket: int, timeout_ms: int = -1, copy_results: bool = True):
+        """Blocks until the job ends; with copy_results=False only status and timestamps."""
         r = gumap_result()
         st = lib.gumap_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
         if st == PENDING:
             return None
         if st < 0 and st != r.status:
             raise GumapError(st, last_error())
-        return self._unpack(r)
+        return self._unpack(r) if copy_results else self._times(r)
 
     def release(self, ticket: int) -> int:
         return _check(lib.gumap_release(self._h, ticket))

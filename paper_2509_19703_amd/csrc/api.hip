@@ -353,10 +353,18 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     unsigned long long *hstats = (unsigned long long *)hstats_v;
     // vertices of high degree get a whole wave per level
     int32_t n_heavy = 0;
+    int32_t nnz_canon = g->nnz;
+    if (!(g->flags & GUMAP_CSR_SORTED)) {
+        e = hipMemcpyAsync(hstats, c.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "canonical size");
+        nnz_canon = *(int32_t *)hstats;
+    }
+    const int32_t heavy_deg = (int32_t)env_size("GUMAP_HEAVY_DEGREE", (size_t)msbfs_heavy_degree(n, nnz_canon));
     {
         int32_t *count = heavy + n;
         e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
-        if (e == hipSuccess) e = launch_heavy_list(n, c.row_ptr, heavy, count, s);
+        if (e == hipSuccess) e = launch_heavy_list(n, c.row_ptr, heavy_deg, heavy, count, s);
         if (e == hipSuccess) e = hipMemcpyAsync(hstats, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_status(e, "heavy vertices");
@@ -377,6 +385,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.slot_of = slot_of;
         a.heavy = heavy;
         a.n_heavy = n_heavy;
+        a.heavy_deg = heavy_deg;
         a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
         a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
         const size_t arr = arr_per_group * a.groups;
@@ -410,8 +419,10 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             for (int q = 0; q < a.groups; ++q) {
                 const bool active = lv == 1 || level_sum(lv - 1, q, 0) != 0;
                 if (!active) continue;
-                // row pointers, frontier + visited reads, next-frontier writes
-                b += 8.0 * n + (commit_only ? 16.0 : 24.0) * (double)n * words;
+                // row pointers, frontier + visited reads, next-frontier writes (none when
+                // the launch only committed: no search and nothing found)
+                const bool searched = !commit_only && (level_sum(lv, q, 0) != 0 || level_sum(lv, q, 1) != 0);
+                b += 8.0 * n + (searched ? 24.0 : 16.0) * (double)n * words;
                 // committed words: visited write + plane read-modify-write per set hop bit
                 const double commits = (double)level_sum(lv, q, 3);
                 b += 8.0 * commits + 16.0 * commits * pc;

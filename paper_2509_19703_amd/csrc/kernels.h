@@ -53,8 +53,9 @@ struct MsbfsArgs {
     size_t plane_stride;      // uint64 elements per plane (= groups * n * words)
     unsigned long long *stats; // [level][group][spread][field] counters of each level
     int32_t stats_groups;     // groups per stats level
-    const int32_t *heavy;     // vertices of degree above msbfs_heavy_degree()
+    const int32_t *heavy;     // vertices of degree above heavy_deg
     int32_t n_heavy;
+    int32_t heavy_deg;
     int32_t xcd_map;          // keep each group on one XCD when groups % 8 == 0
     int32_t hops_variant;     // hop-row writer: tiles per step / store kind (tuning)
 };
@@ -63,8 +64,9 @@ struct MsbfsArgs {
 // frontier words committed}; a level's value is the sum over the spread slots.
 int msbfs_stat_fields();
 int msbfs_stat_spread();
-int msbfs_heavy_degree();
-hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t *heavy, int32_t *count, hipStream_t s);
+int msbfs_heavy_degree(int32_t n, int32_t nnz);
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t heavy_deg, int32_t *heavy, int32_t *count,
+                             hipStream_t s);
 hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).

@@ -31,7 +31,7 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevelBlock = 256;
-constexpr int kHeavyDeg = 64;      // above this degree a vertex gets a whole wave
+constexpr int kFullCheckLevels = 32;  // levels up to which a finished group is detected
 constexpr int kHopTilesPerWave = 16;
 constexpr int kCountLevels = 16;
 constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
@@ -104,21 +104,32 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
             a.stats[(((size_t)(level - 1) * a.stats_groups + g) * kSpread + l) * kStatFields + kFieldNewBits];
         if (__ballot(x != 0ull) == 0ull) return;
     }
+    if (level >= 2 && level <= kFullCheckLevels) {
+        // every source of the group has reached every other vertex by level - 1
+        // (counts of finished launches only): only the commit is left
+        unsigned long long got = 0;
+        for (int lv = 1; lv < level; ++lv)
+            got += a.stats[(((size_t)lv * a.stats_groups + g) * kSpread + l) * kStatFields + kFieldNewBits];
+        got = wave_sum_u64(got);
+        const int32_t in_group = min(64 * WORDS, a.n_slots - g * 64 * WORDS);
+        if (got == (unsigned long long)(a.n - 1) * (unsigned long long)in_group) commit_only = 1;
+    }
     Counters c{};
     const size_t gbase = (size_t)g * a.n * WORDS;
     const uint64_t *__restrict__ fr = a.front[level & 1];
     if (vb < light_blocks) {
-        // one thread per (vertex, word); vertices of degree > kHeavyDeg are left
-        // to the heavy waves (except at level 1, where all are done here)
+        // one thread per (vertex, word): commit for every vertex; the search
+        // of vertices of degree > heavy_deg is left to the heavy waves (except
+        // at level 1, where all are searched here)
         const int64_t idx = (int64_t)vb * kLevelBlock + threadIdx.x;
         const int32_t v = (int32_t)(idx >> LW);
         const int w = (int)(idx & (WORDS - 1));
         int cols = 0;
         if (v < a.n) {
             const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
-            if (level == 1 || e1 - e0 <= kHeavyDeg) {
-                const size_t me = gbase + ((size_t)v << LW) + w;
-                const uint64_t vis = commit_word(a, level, me, c);
+            const size_t me = gbase + ((size_t)v << LW) + w;
+            const uint64_t vis = commit_word(a, level, me, c);
+            if (level == 1 || e1 - e0 <= a.heavy_deg) {
                 if (!commit_only) {
                     const int32_t ls0 = g * 64 * WORDS + 64 * w;
                     const uint64_t unv = ~vis & word_valid_mask(a.n_slots, ls0);
@@ -178,8 +189,10 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
             const int32_t v = a.heavy[hidx];
             const int w = l & (WORDS - 1), grp = l >> LW;
             const size_t me = gbase + ((size_t)v << LW) + w;
+            // the light threads commit this vertex in the same launch; visited
+            // | frontier is the committed value whichever of the two is read
             uint64_t vis = 0;
-            if (grp == 0) vis = commit_word(a, level, me, c);
+            if (grp == 0) vis = a.visited[me] | fr[me];
             vis = __shfl(vis, w, GM_WAVE);
             if (!commit_only) {
                 const int32_t ls0 = g * 64 * WORDS + 64 * w;
@@ -231,10 +244,11 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     }
 }
 
-__global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t *heavy, int32_t *count)
+__global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t heavy_deg, int32_t *heavy,
+                                  int32_t *count)
 {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        if (rp[v + 1] - rp[v] > kHeavyDeg) heavy[atomicAdd(count, 1)] = (int32_t)v;
+        if (rp[v + 1] - rp[v] > heavy_deg) heavy[atomicAdd(count, 1)] = (int32_t)v;
 }
 
 // Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
@@ -395,17 +409,26 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
     return hipGetLastError();
 }
 
-hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t *heavy, int32_t *count, hipStream_t s)
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t heavy_deg, int32_t *heavy, int32_t *count,
+                             hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>(4096, ((int64_t)n + 255) / 256);
-    hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, heavy, count);
+    hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, heavy_deg, heavy, count);
     return hipGetLastError();
 }
 
 int msbfs_stat_fields() { return kStatFields; }
 int msbfs_stat_spread() { return kSpread; }
-int msbfs_heavy_degree() { return kHeavyDeg; }
+// Degree above which a vertex is searched by a whole wave: hubs well above
+// the mean degree (a lone thread would walk their rows serially while the
+// rest of its wave waits); dense graphs with an even degree keep one thread
+// per vertex word, which stops early.
+int msbfs_heavy_degree(int32_t n, int32_t nnz)
+{
+    const int64_t mean = n > 0 ? (int64_t)nnz / n : 0;
+    return (int)std::max<int64_t>(64, 8 * mean);
+}
 
 int msbfs_hop_chunks(int32_t n) { return ((n + 63) / 64 + kHopTilesPerWave - 1) / kHopTilesPerWave; }
 

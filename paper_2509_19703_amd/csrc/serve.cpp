@@ -1,23 +1,31 @@
 // Request server: continuous batching of layout-preparation jobs
-// (partial-BFS kNN + membership per job graph) on one device.
+// (partial-BFS kNN + membership of one graph per job) on one device.
 //
-// Jobs arrive through gumap_submit with host CSR arrays, which are copied at
-// once.  A scheduler thread admits queued jobs first-come-first-served while
-// their device bytes fit the budget (and a slot is free), copies their CSR
-// into a device slab that was reserved once at creation, and runs device
-// iterations: each iteration is one launch of the jobs kernel over a list of
-// row chunks taken from every admitted job that still has rows to do, up to
-// a row budget per iteration, oldest job first.  Jobs admitted while an
-// iteration runs join the next one.  When all rows of a job are done its
-// results are copied to host buffers, its slab space is returned and it is
-// marked done.  Every row of a job is computed by the same per-row code
-// whatever else shares the launch, so a result does not depend on the mix.
+// gumap_submit copies a job's host CSR into pinned host memory (a pool
+// reserved at creation; pageable memory if the pool is full) and queues it.
+// A scheduler thread runs a pipeline on three streams:
+//   admission   queued jobs are admitted first-come-first-served while their
+//               device bytes fit the budget, a slot is free and their result
+//               fits the pinned result pool; the CSR is uploaded (and, if the
+//               job is not canonical, canonicalised) on the copy stream and an
+//               event marks the upload;
+//   iterations  one launch of the jobs kernel over row chunks taken from
+//               every admitted job with rows left (oldest job first, up to a
+//               row budget); the compute stream waits for the uploads of the
+//               jobs it includes, and up to two iterations are in flight, so
+//               jobs that arrive while one runs join the next;
+//   retirement  when the iteration holding a job's last rows completes, its
+//               results are copied to pinned host memory on a third stream;
+//               when that copy completes the job is done and its device space
+//               is returned.
+// Every row of a job is computed by the same per-row code whatever shares the
+// launch, so a result does not depend on the mix of jobs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -41,17 +49,22 @@ uint64_t now_ns()
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// First-fit allocator over [0, capacity) of the slab.
+// First-fit allocator over [0, capacity).
 class SlabAllocator {
 public:
-    explicit SlabAllocator(size_t capacity) { if (capacity) free_[0] = capacity; }
+    explicit SlabAllocator(size_t capacity = 0) { reset(capacity); }
+    void reset(size_t capacity)
+    {
+        free_.clear();
+        if (capacity) free_[0] = capacity;
+    }
     bool alloc(size_t bytes, size_t *off)
     {
-        bytes = align_up(bytes, 256);
+        bytes = align_up(bytes ? bytes : 1, 256);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
             if (it->second >= bytes) {
                 *off = it->first;
-                size_t rest = it->second - bytes, start = it->first + bytes;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
                 free_.erase(it);
                 if (rest) free_[start] = rest;
                 return true;
@@ -61,7 +74,7 @@ public:
     }
     void release(size_t off, size_t bytes)
     {
-        bytes = align_up(bytes, 256);
+        bytes = align_up(bytes ? bytes : 1, 256);
         auto it = free_.emplace(off, bytes).first;
         auto next = std::next(it);
         if (next != free_.end() && it->first + it->second == next->first) {
@@ -81,7 +94,7 @@ private:
     std::map<size_t, size_t> free_;
 };
 
-enum JobState { kQueued, kRunning, kDone };
+enum JobState { kQueued, kAdmitted, kDownloading, kDone };
 
 struct Job {
     uint64_t ticket = 0;
@@ -90,27 +103,74 @@ struct Job {
     int32_t n = 0, nnz = 0, k = 0;
     bool weights = false;
     uint32_t flags = 0;
-    std::vector<int32_t> h_rp, h_col;                 // host input copy
-    std::vector<int32_t> r_ids;                       // host results
-    std::vector<uint8_t> r_hops;
-    std::vector<float> r_w, r_rho, r_sigma;
+    // host input: pinned pool slice, or pageable copy when the pool was full
+    int32_t *in_rp = nullptr, *in_col = nullptr;
+    size_t in_off = 0, in_bytes = 0;
+    bool in_pinned = false;
+    std::vector<int32_t> pg_rp, pg_col;
+    // host results (pinned pool slice, or pageable memory when the pool is full)
+    size_t out_off = 0, out_bytes = 0;
+    bool out_pinned = false;
+    std::vector<char> pg_out;
+    int32_t *r_ids = nullptr;
+    uint8_t *r_hops = nullptr;
+    float *r_w = nullptr, *r_rho = nullptr, *r_sigma = nullptr;
+    // device
     size_t bytes = 0, slab_off = 0;
-    int32_t next_row = 0, rows_done = 0;              // scheduling progress
     gm::DevJob dev{};
+    hipEvent_t up_done = nullptr, down_done = nullptr;
+    bool waited = false;           // compute stream already waits for the upload
+    bool input_freed = false;
+    int32_t next_row = 0;
+    int64_t last_iter = -1;
     uint64_t t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
 };
 
-// Device bytes a job holds while resident.
-size_t job_bytes(int32_t n, int32_t nnz, int32_t k, bool weights, bool sorted)
+size_t job_device_bytes(int32_t n, int32_t nnz, int32_t k, bool weights, bool needs_canon)
 {
     size_t b = align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)std::max(nnz, 1) * 4, 256);
     b += align_up((size_t)n * k * 4, 256) + align_up((size_t)n * k, 256);
     if (weights) b += align_up((size_t)n * k * 4, 256) + 2 * align_up((size_t)n * 4, 256);
-    if (!sorted) {
+    if (needs_canon) {
         b += align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)std::max(nnz, 1) * 4, 256);
         b += align_up(gm::canon_scratch_bytes(n, nnz), 256) + 512;
     }
     return b;
+}
+
+size_t job_result_bytes(int32_t n, int32_t k, bool weights)
+{
+    size_t b = align_up((size_t)n * k * 4, 256) + align_up((size_t)n * k, 256);
+    if (weights) b += align_up((size_t)n * k * 4, 256) + 2 * align_up((size_t)n * 4, 256);
+    return b;
+}
+
+size_t job_input_bytes(int32_t n, int32_t nnz)
+{
+    return align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)std::max(nnz, 1) * 4, 256);
+}
+
+constexpr int kInFlight = 2;
+
+// memcpy split over a few threads: one thread does not reach the host's
+// memory bandwidth for the multi-megabyte CSR copies made at submission.
+void parallel_copy(void *dst, const void *src, size_t bytes)
+{
+    constexpr size_t kMin = 4u << 20;
+    const int parts = (int)std::min<size_t>(8, std::max<size_t>(1, bytes / kMin));
+    if (parts <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t per = align_up((bytes + parts - 1) / parts, 4096);
+    std::vector<std::thread> th;
+    for (int p = 1; p < parts; ++p) {
+        const size_t off = per * p;
+        if (off >= bytes) break;
+        th.emplace_back([=] { std::memcpy((char *)dst + off, (const char *)src + off, std::min(per, bytes - off)); });
+    }
+    std::memcpy(dst, src, std::min(per, bytes));
+    for (auto &t : th) t.join();
 }
 
 }  // namespace
@@ -120,15 +180,19 @@ struct gumap_server {
     int32_t max_slots = 0;
     bool no_device = false;
     int device = 0;
-    char *slab = nullptr;
-    SlabAllocator alloc{0};
-    hipStream_t compute = nullptr, copy = nullptr;
-    hipEvent_t iter_done = nullptr;
-    gm::DevJob *d_jobs = nullptr;            // job table of the running iteration
-    gm::JobChunk *d_chunks = nullptr;
-    unsigned long long *d_counter = nullptr;
-    gm::DevJob *h_jobs = nullptr;            // pinned staging
-    gm::JobChunk *h_chunks = nullptr;
+    char *slab = nullptr;               // device
+    SlabAllocator alloc;
+    char *host_pool = nullptr;          // pinned (or plain memory without a device)
+    size_t host_pool_bytes = 0;
+    SlabAllocator host_alloc;
+    hipStream_t compute = nullptr, copy = nullptr, d2h = nullptr;
+    // per in-flight iteration slot
+    hipEvent_t iter_done[kInFlight] = {};
+    gm::DevJob *d_jobs[kInFlight] = {};
+    gm::JobChunk *d_chunks[kInFlight] = {};
+    unsigned long long *d_counter[kInFlight] = {};
+    gm::DevJob *h_jobs[kInFlight] = {};
+    gm::JobChunk *h_chunks[kInFlight] = {};
     int32_t table_cap = 0, chunk_cap = 0;
     int64_t iter_rows = 0;
     int blocks = 0;
@@ -136,39 +200,81 @@ struct gumap_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Job>> queue;               // waiting for admission
-    std::vector<std::shared_ptr<Job>> running;            // admitted, rows pending or in flight
+    std::vector<std::shared_ptr<Job>> admitted;           // resident, rows left or in flight
+    std::vector<std::shared_ptr<Job>> downloading;
     std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool kick = false;                 // a submission or a released result may unblock admission
     std::thread worker;
     gumap_server_stats stats{};
     size_t resident = 0;
-    std::string fatal;
+
+    struct Flight {
+        int64_t iter;
+        int slot;
+        std::vector<std::shared_ptr<Job>> finishing;   // jobs whose last rows are in it
+    };
+    std::deque<Flight> flights;
+    int64_t iter_count = 0;
 
     void run();
-    bool admit_locked(std::vector<std::shared_ptr<Job>> &admitted);
-    int stage_job(Job &j);
-    void finish_job(const std::shared_ptr<Job> &j, int status);
+    int stage(Job &j);
+    void finish_locked(const std::shared_ptr<Job> &j, int status);
+    void free_input_locked(Job &j);
+    bool launch_iteration();
+    bool retire_iterations();
+    bool poll_downloads();
 };
 
-int gumap_server::stage_job(Job &j)
+void gumap_server::free_input_locked(Job &j)
 {
-    // called without the lock; j is owned by the scheduler while running
+    if (j.input_freed) return;
+    if (j.in_pinned) host_alloc.release(j.in_off, j.in_bytes);
+    j.pg_rp.clear();
+    j.pg_rp.shrink_to_fit();
+    j.pg_col.clear();
+    j.pg_col.shrink_to_fit();
+    j.in_rp = j.in_col = nullptr;
+    j.input_freed = true;
+}
+
+void gumap_server::finish_locked(const std::shared_ptr<Job> &j, int status)
+{
+    j->status = status;
+    j->state = kDone;
+    j->t_done = now_ns();
+    resident -= j->bytes;
+    alloc.release(j->slab_off, j->bytes);
+    free_input_locked(*j);
+    if (status != GUMAP_OK && j->out_pinned) {
+        host_alloc.release(j->out_off, j->out_bytes);
+        j->out_pinned = false;
+    }
+    if (j->up_done) (void)hipEventDestroy(j->up_done);
+    if (j->down_done) (void)hipEventDestroy(j->down_done);
+    j->up_done = j->down_done = nullptr;
+    if (status == GUMAP_OK) stats.completed++;
+    else stats.failed++;
+    cv_done.notify_all();
+}
+
+// Upload (and canonicalise / validate) an admitted job.  Scheduler thread.
+int gumap_server::stage(Job &j)
+{
     if (no_device) return GUMAP_OK;
-    hipError_t e = hipSuccess;
     char *base = slab + j.slab_off;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base + off;
-        off += align_up(bytes, 256);
+        off += align_up(bytes ? bytes : 1, 256);
         return p;
     };
     int32_t *rp = (int32_t *)take((size_t)(j.n + 1) * 4);
     int32_t *col = (int32_t *)take((size_t)std::max(j.nnz, 1) * 4);
     j.dev.ids = (int32_t *)take((size_t)j.n * j.k * 4);
     j.dev.hops = (uint8_t *)take((size_t)j.n * j.k);
-    j.dev.weights = nullptr;
-    j.dev.rho = j.dev.sigma = nullptr;
+    j.dev.weights = j.dev.rho = j.dev.sigma = nullptr;
     if (j.weights) {
         j.dev.weights = (float *)take((size_t)j.n * j.k * 4);
         j.dev.rho = (float *)take((size_t)j.n * 4);
@@ -176,17 +282,19 @@ int gumap_server::stage_job(Job &j)
     }
     j.dev.n = j.n;
     j.dev.k = j.k;
-    e = hipMemcpyAsync(rp, j.h_rp.data(), (size_t)(j.n + 1) * 4, hipMemcpyHostToDevice, copy);
-    if (e == hipSuccess && j.nnz)
-        e = hipMemcpyAsync(col, j.h_col.data(), (size_t)j.nnz * 4, hipMemcpyHostToDevice, copy);
-    if (e != hipSuccess) return gm::hip_status(e, "job upload");
     j.dev.row_ptr = rp;
     j.dev.col = col;
+    hipError_t e = hipEventCreateWithFlags(&j.up_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&j.down_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpyAsync(rp, j.in_rp, (size_t)(j.n + 1) * 4, hipMemcpyHostToDevice, copy);
+    if (e == hipSuccess && j.nnz)
+        e = hipMemcpyAsync(col, j.in_col, (size_t)j.nnz * 4, hipMemcpyHostToDevice, copy);
+    if (e != hipSuccess) return gm::hip_status(e, "job upload");
     if (!(j.flags & GUMAP_CSR_SORTED) || (j.flags & GUMAP_VALIDATE)) {
         int32_t *crp = (int32_t *)take((size_t)(j.n + 1) * 4);
         int32_t *ccol = (int32_t *)take((size_t)std::max(j.nnz, 1) * 4);
         void *scratch = take(gm::canon_scratch_bytes(j.n, j.nnz));
-        int *err = (int *)scratch;  // structural check uses the first word of the canon scratch
+        int *err = (int *)take(256);
         if (j.flags & GUMAP_VALIDATE) {
             e = hipMemsetAsync(err, 0, sizeof(int), copy);
             if (e == hipSuccess) e = gm::launch_validate_structure(j.n, j.nnz, rp, col, err, copy);
@@ -203,183 +311,242 @@ int gumap_server::stage_job(Job &j)
             j.dev.col = ccol;
         }
         if (j.flags & GUMAP_VALIDATE) {
-            // symmetry (and order, when claimed) of the canonical rows
-            int *err2 = (int *)(base + off);
-            (void)take(256);
-            e = hipMemsetAsync(err2, 0, sizeof(int), copy);
-            if (e == hipSuccess) e = gm::launch_check_symmetric(j.n, j.dev.row_ptr, j.dev.col, err2, copy);
+            e = hipMemsetAsync(err, 0, sizeof(int), copy);
+            if (e == hipSuccess) e = gm::launch_check_symmetric(j.n, j.dev.row_ptr, j.dev.col, err, copy);
             int bad = 0;
-            if (e == hipSuccess) e = hipMemcpyAsync(&bad, err2, sizeof(int), hipMemcpyDeviceToHost, copy);
+            if (e == hipSuccess) e = hipMemcpyAsync(&bad, err, sizeof(int), hipMemcpyDeviceToHost, copy);
             if (e == hipSuccess) e = hipStreamSynchronize(copy);
             if (e != hipSuccess) return gm::hip_status(e, "job validate");
             if (bad) return gm::set_error(GUMAP_EGRAPH, "CSR is not symmetric");
         }
     }
-    return GUMAP_OK;
+    e = hipEventRecord(j.up_done, copy);
+    return gm::hip_status(e, "job upload event");
 }
 
-bool gumap_server::admit_locked(std::vector<std::shared_ptr<Job>> &admitted)
+// Enqueue one iteration if a slot is free and rows are waiting.
+bool gumap_server::launch_iteration()
 {
-    bool any = false;
-    while (!queue.empty()) {
-        auto &j = queue.front();
-        if (max_slots > 0 && (int32_t)running.size() + (int32_t)admitted.size() >= max_slots) break;
-        size_t off = 0;
-        if (resident + j->bytes > budget || !alloc.alloc(j->bytes, &off)) break;  // FIFO: no overtaking
-        j->slab_off = off;
-        resident += j->bytes;
-        stats.peak_resident_bytes = std::max<uint64_t>(stats.peak_resident_bytes, resident);
-        j->state = kRunning;
-        j->t_admit = now_ns();
-        admitted.push_back(j);
-        queue.pop_front();
-        any = true;
+    if ((int)flights.size() >= kInFlight) return false;
+    const int slot = (int)(iter_count % kInFlight);
+    std::vector<std::shared_ptr<Job>> table;
+    std::vector<gm::JobChunk> chunks;
+    Flight fl;
+    fl.iter = iter_count;
+    fl.slot = slot;
+    int max_k = 1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        int64_t rows_left = iter_rows;
+        for (auto &j : admitted) {
+            if (j->next_row >= j->n && j->n > 0) continue;
+            if (j->last_iter >= 0 && j->n == 0) continue;
+            if (rows_left <= 0 || (int32_t)table.size() >= table_cap) break;
+            const int32_t job_idx = (int32_t)table.size();
+            const int32_t step = gm::batch_chunk_rows(j->k);
+            int32_t r = j->next_row;
+            while (r < j->n && rows_left > 0 && (int32_t)chunks.size() < chunk_cap) {
+                const int32_t e = std::min(j->n, r + step);
+                chunks.push_back(gm::JobChunk{job_idx, r, e, 0});
+                rows_left -= e - r;
+                r = e;
+            }
+            if (r == j->next_row && j->n > 0) break;
+            if (j->t_start == 0) j->t_start = now_ns();
+            table.push_back(j);
+            max_k = std::max(max_k, j->k);
+            j->next_row = r;
+            j->last_iter = iter_count;
+            if (r >= j->n) fl.finishing.push_back(j);
+        }
+        if (table.empty()) return false;
+        stats.iterations++;
     }
-    return any;
+    if (!no_device) {
+        hipError_t e = hipSuccess;
+        for (auto &j : table) {
+            if (!j->waited) {
+                e = hipStreamWaitEvent(compute, j->up_done, 0);
+                j->waited = true;
+                if (e != hipSuccess) break;
+            }
+        }
+        for (size_t i = 0; i < table.size(); ++i) h_jobs[slot][i] = table[i]->dev;
+        std::copy(chunks.begin(), chunks.end(), h_chunks[slot]);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_jobs[slot], h_jobs[slot], table.size() * sizeof(gm::DevJob), hipMemcpyHostToDevice, compute);
+        if (e == hipSuccess && !chunks.empty())
+            e = hipMemcpyAsync(d_chunks[slot], h_chunks[slot], chunks.size() * sizeof(gm::JobChunk),
+                               hipMemcpyHostToDevice, compute);
+        if (e == hipSuccess) e = gm::launch_batch_reset(d_counter[slot], compute);
+        if (e == hipSuccess)
+            e = gm::launch_partial_jobs(d_jobs[slot], d_chunks[slot], (int32_t)chunks.size(), max_k,
+                                        d_counter[slot], blocks, compute);
+        if (e == hipSuccess) e = hipEventRecord(iter_done[slot], compute);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto &j : table)
+                if (j->state == kAdmitted) {
+                    admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
+                    finish_locked(j, GUMAP_EDEVICE);
+                }
+            (void)hipGetLastError();
+            return false;
+        }
+    }
+    flights.push_back(std::move(fl));
+    ++iter_count;
+    return true;
 }
 
-void gumap_server::finish_job(const std::shared_ptr<Job> &j, int status)
+// Completed iterations: start the result downloads of jobs they finished.
+bool gumap_server::retire_iterations()
 {
-    // lock held by caller
-    j->status = status;
-    j->state = kDone;
-    j->t_done = now_ns();
-    resident -= j->bytes;
-    alloc.release(j->slab_off, j->bytes);
-    j->h_rp.clear();
-    j->h_rp.shrink_to_fit();
-    j->h_col.clear();
-    j->h_col.shrink_to_fit();
-    if (status == GUMAP_OK) stats.completed++;
-    else stats.failed++;
-    cv_done.notify_all();
+    bool progress = false;
+    while (!flights.empty()) {
+        Flight &fl = flights.front();
+        if (!no_device) {
+            hipError_t q = hipEventQuery(iter_done[fl.slot]);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) (void)hipGetLastError();
+        }
+        for (auto &j : fl.finishing) {
+            if (j->last_iter != fl.iter || j->state != kAdmitted) continue;
+            const size_t nk = (size_t)j->n * j->k;
+            hipError_t e = hipSuccess;
+            if (!no_device && j->n > 0) {
+                e = hipMemcpyAsync(j->r_ids, j->dev.ids, nk * 4, hipMemcpyDeviceToHost, d2h);
+                if (e == hipSuccess) e = hipMemcpyAsync(j->r_hops, j->dev.hops, nk, hipMemcpyDeviceToHost, d2h);
+                if (e == hipSuccess && j->weights) {
+                    e = hipMemcpyAsync(j->r_w, j->dev.weights, nk * 4, hipMemcpyDeviceToHost, d2h);
+                    if (e == hipSuccess) e = hipMemcpyAsync(j->r_rho, j->dev.rho, (size_t)j->n * 4, hipMemcpyDeviceToHost, d2h);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(j->r_sigma, j->dev.sigma, (size_t)j->n * 4, hipMemcpyDeviceToHost, d2h);
+                }
+            }
+            if (e == hipSuccess && !no_device) e = hipEventRecord(j->down_done, d2h);
+            std::lock_guard<std::mutex> lk(mu);
+            admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                finish_locked(j, GUMAP_EDEVICE);
+            } else {
+                j->state = kDownloading;
+                downloading.push_back(j);
+            }
+        }
+        flights.pop_front();
+        progress = true;
+    }
+    return progress;
+}
+
+bool gumap_server::poll_downloads()
+{
+    bool progress = false;
+    std::lock_guard<std::mutex> lk(mu);
+    for (size_t i = 0; i < downloading.size();) {
+        auto j = downloading[i];
+        bool ready = true;
+        if (!no_device) {
+            hipError_t q = hipEventQuery(j->down_done);
+            if (q == hipErrorNotReady) ready = false;
+            else if (q != hipSuccess) (void)hipGetLastError();
+        }
+        if (!ready) {
+            ++i;
+            continue;
+        }
+        downloading.erase(downloading.begin() + (long)i);
+        finish_locked(j, GUMAP_OK);
+        progress = true;
+    }
+    // inputs of uploaded jobs go back to the pool
+    for (auto &j : admitted) {
+        if (j->input_freed || !j->up_done) continue;
+        if (hipEventQuery(j->up_done) == hipSuccess) free_input_locked(*j);
+        else (void)hipGetLastError();
+    }
+    return progress;
 }
 
 void gumap_server::run()
 {
     if (!no_device) (void)hipSetDevice(device);
-    bool iteration_running = false;
     for (;;) {
-        std::vector<std::shared_ptr<Job>> admitted;
+        std::vector<std::shared_ptr<Job>> fresh;
         {
             std::unique_lock<std::mutex> lk(mu);
-            if (!iteration_running) {
-                cv_work.wait_for(lk, std::chrono::milliseconds(2), [&] {
-                    return stop || !queue.empty() || !running.empty();
-                });
+            const bool busy = !flights.empty() || !downloading.empty();
+            if (!busy && !stop) cv_work.wait_for(lk, std::chrono::milliseconds(2), [&] { return stop || kick; });
+            kick = false;
+            if (stop && flights.empty() && downloading.empty()) break;
+            // admission: first come first served, no overtaking
+            while (!stop && !queue.empty()) {
+                auto &j = queue.front();
+                if (max_slots > 0 && (int32_t)admitted.size() >= max_slots) break;
+                size_t off = 0, hoff = 0;
+                if (resident + j->bytes > budget) break;
+                if (!alloc.alloc(j->bytes, &off)) break;
+                j->slab_off = off;
+                char *hb;
+                if (host_alloc.alloc(j->out_bytes, &hoff)) {
+                    j->out_pinned = true;
+                    j->out_off = hoff;
+                    hb = host_pool + hoff;
+                } else {
+                    j->pg_out.assign(j->out_bytes, 0);
+                    hb = j->pg_out.data();
+                }
+                char *const out_base = hb;
+                const size_t nk = (size_t)j->n * j->k;
+                j->r_ids = (int32_t *)hb;
+                hb += align_up(nk * 4, 256);
+                j->r_hops = (uint8_t *)hb;
+                hb += align_up(nk, 256);
+                if (j->weights) {
+                    j->r_w = (float *)hb;
+                    hb += align_up(nk * 4, 256);
+                    j->r_rho = (float *)hb;
+                    hb += align_up((size_t)j->n * 4, 256);
+                    j->r_sigma = (float *)hb;
+                }
+                if (no_device) std::memset(out_base, 0, j->out_bytes);
+                resident += j->bytes;
+                stats.peak_resident_bytes = std::max<uint64_t>(stats.peak_resident_bytes, resident);
+                j->state = kAdmitted;
+                j->t_admit = now_ns();
+                fresh.push_back(j);
+                queue.pop_front();
             }
-            if (stop && !iteration_running) break;
-            admit_locked(admitted);
         }
-        // stage admitted jobs (uploads overlap the running iteration)
-        for (auto &j : admitted) {
-            int st = stage_job(*j);
+        for (auto &j : fresh) {
+            const int st = stage(*j);
             std::lock_guard<std::mutex> lk(mu);
             if (st != GUMAP_OK) {
-                finish_job(j, st);
+                (void)hipGetLastError();
+                finish_locked(j, st);
             } else {
-                running.push_back(j);
+                admitted.push_back(j);
             }
         }
-        if (iteration_running) {
-            if (!no_device) {
-                hipError_t q = hipEventQuery(iter_done);
-                if (q == hipErrorNotReady) {
-                    std::this_thread::sleep_for(std::chrono::microseconds(50));
-                    continue;
-                }
-                if (q != hipSuccess) {
-                    std::lock_guard<std::mutex> lk(mu);
-                    fatal = hipGetErrorString(q);
-                    for (auto &j : running) finish_job(j, GUMAP_EDEVICE);
-                    running.clear();
-                    iteration_running = false;
-                    continue;
-                }
-            }
-            iteration_running = false;
-        }
-        // No iteration is in flight now: every scheduled row is complete, so
-        // jobs whose rows were all scheduled are finished.
-        std::vector<std::shared_ptr<Job>> finished;
+        bool progress = !fresh.empty();
+        progress |= retire_iterations();
+        progress |= poll_downloads();
+        bool stopping;
         {
             std::lock_guard<std::mutex> lk(mu);
-            for (auto &j : running)
-                if (j->rows_done >= j->n) finished.push_back(j);
+            stopping = stop;
         }
-        for (auto &j : finished) {
-            int st = GUMAP_OK;
-            size_t nk = (size_t)j->n * j->k;
-            j->r_ids.resize(nk);
-            j->r_hops.resize(nk);
-            if (j->weights) {
-                j->r_w.resize(nk);
-                j->r_rho.resize(j->n);
-                j->r_sigma.resize(j->n);
-            }
-            if (!no_device && j->n > 0) {
-                hipError_t e = hipMemcpyAsync(j->r_ids.data(), j->dev.ids, nk * 4, hipMemcpyDeviceToHost, copy);
-                if (e == hipSuccess) e = hipMemcpyAsync(j->r_hops.data(), j->dev.hops, nk, hipMemcpyDeviceToHost, copy);
-                if (e == hipSuccess && j->weights) {
-                    e = hipMemcpyAsync(j->r_w.data(), j->dev.weights, nk * 4, hipMemcpyDeviceToHost, copy);
-                    if (e == hipSuccess) e = hipMemcpyAsync(j->r_rho.data(), j->dev.rho, (size_t)j->n * 4, hipMemcpyDeviceToHost, copy);
-                    if (e == hipSuccess) e = hipMemcpyAsync(j->r_sigma.data(), j->dev.sigma, (size_t)j->n * 4, hipMemcpyDeviceToHost, copy);
-                }
-                if (e == hipSuccess) e = hipStreamSynchronize(copy);
-                if (e != hipSuccess) st = gm::hip_status(e, "job download");
-            }
-            std::lock_guard<std::mutex> lk(mu);
-            running.erase(std::remove(running.begin(), running.end(), j), running.end());
-            finish_job(j, st);
-        }
-        // next iteration: chunks from every running job with rows left
-        std::vector<std::shared_ptr<Job>> table;
-        std::vector<gm::JobChunk> chunks;
-        int max_k = 1;
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            int64_t rows_left = iter_rows;
-            for (auto &j : running) {
-                if (j->next_row >= j->n || rows_left <= 0) continue;
-                if ((int32_t)table.size() >= table_cap) break;
-                const int32_t job_idx = (int32_t)table.size();
-                const int32_t step = gm::batch_chunk_rows(j->k);
-                int32_t r = j->next_row;
-                while (r < j->n && rows_left > 0 && (int32_t)chunks.size() < chunk_cap) {
-                    int32_t e = std::min(j->n, r + step);
-                    chunks.push_back(gm::JobChunk{job_idx, r, e, 0});
-                    rows_left -= e - r;
-                    r = e;
-                }
-                if (r == j->next_row) break;
-                if (j->t_start == 0) j->t_start = now_ns();
-                table.push_back(j);
-                max_k = std::max(max_k, j->k);
-                j->rows_done += r - j->next_row;   // counted done once this iteration completes
-                j->next_row = r;
-            }
-            if (!chunks.empty()) stats.iterations++;
-        }
-        if (chunks.empty()) continue;
-        if (!no_device) {
-            for (size_t i = 0; i < table.size(); ++i) h_jobs[i] = table[i]->dev;
-            std::copy(chunks.begin(), chunks.end(), h_chunks);
-            hipError_t e = hipStreamSynchronize(copy);   // staged uploads must land first
-            if (e == hipSuccess) e = hipMemcpyAsync(d_jobs, h_jobs, table.size() * sizeof(gm::DevJob), hipMemcpyHostToDevice, compute);
-            if (e == hipSuccess) e = hipMemcpyAsync(d_chunks, h_chunks, chunks.size() * sizeof(gm::JobChunk), hipMemcpyHostToDevice, compute);
-            if (e == hipSuccess) e = gm::launch_batch_reset(d_counter, compute);
-            if (e == hipSuccess)
-                e = gm::launch_partial_jobs(d_jobs, d_chunks, (int32_t)chunks.size(), max_k, d_counter, blocks, compute);
-            if (e == hipSuccess) e = hipEventRecord(iter_done, compute);
-            if (e != hipSuccess) {
-                std::lock_guard<std::mutex> lk(mu);
-                fatal = hipGetErrorString(e);
-                for (auto &j : running) finish_job(j, GUMAP_EDEVICE);
-                running.clear();
-                continue;
-            }
-        }
-        iteration_running = true;
+        if (!stopping)
+            while (launch_iteration()) progress = true;
+        if (!progress && (!flights.empty() || !downloading.empty()))
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    if (!no_device) {
+        (void)hipStreamSynchronize(compute);
+        (void)hipStreamSynchronize(copy);
+        (void)hipStreamSynchronize(d2h);
     }
 }
 
@@ -398,38 +565,41 @@ gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->no_device = (flags & GUMAP_SERVER_NO_DEVICE) != 0;
-    s->alloc = SlabAllocator(hbm_budget_bytes);
+    s->alloc.reset(hbm_budget_bytes);
     s->stats.budget_bytes = hbm_budget_bytes;
     s->iter_rows = (int64_t)gm::env_size("GUMAP_SERVE_ITER_ROWS", 1 << 20);
     s->table_cap = 4096;
     s->chunk_cap = (int32_t)std::min<int64_t>(1 << 22, s->iter_rows + s->table_cap);
-    if (!s->no_device) {
-        hipError_t e = hipGetDevice(&s->device);
+    s->host_pool_bytes = gm::env_size("GUMAP_SERVE_HOST_POOL_MB", s->no_device ? 256 : 4096) << 20;
+    s->host_alloc.reset(s->host_pool_bytes);
+    hipError_t e = hipSuccess;
+    if (s->no_device) {
+        s->host_pool = (char *)malloc(s->host_pool_bytes);
+        if (!s->host_pool) e = hipErrorOutOfMemory;
+    } else {
+        e = hipGetDevice(&s->device);
         if (e == hipSuccess) e = hipMalloc((void **)&s->slab, hbm_budget_bytes);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->host_pool, s->host_pool_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->iter_done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc((void **)&s->d_jobs, (size_t)s->table_cap * sizeof(gm::DevJob));
-        if (e == hipSuccess) e = hipMalloc((void **)&s->d_chunks, (size_t)s->chunk_cap * sizeof(gm::JobChunk));
-        if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, 256);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_jobs, (size_t)s->table_cap * sizeof(gm::DevJob), hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_chunks, (size_t)s->chunk_cap * sizeof(gm::JobChunk), hipHostMallocDefault);
-        if (e != hipSuccess) {
-            int st = gm::hip_status(e, "server setup");
-            (void)hipGetLastError();
-            if (s->slab) (void)hipFree(s->slab);
-            if (s->d_jobs) (void)hipFree(s->d_jobs);
-            if (s->d_chunks) (void)hipFree(s->d_chunks);
-            if (s->d_counter) (void)hipFree(s->d_counter);
-            if (s->h_jobs) (void)hipHostFree(s->h_jobs);
-            if (s->h_chunks) (void)hipHostFree(s->h_chunks);
-            if (s->iter_done) (void)hipEventDestroy(s->iter_done);
-            if (s->compute) (void)hipStreamDestroy(s->compute);
-            if (s->copy) (void)hipStreamDestroy(s->copy);
-            delete s;
-            return fail(st);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->d2h, hipStreamNonBlocking);
+        for (int i = 0; i < kInFlight && e == hipSuccess; ++i) {
+            e = hipEventCreateWithFlags(&s->iter_done[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipMalloc((void **)&s->d_jobs[i], (size_t)s->table_cap * sizeof(gm::DevJob));
+            if (e == hipSuccess) e = hipMalloc((void **)&s->d_chunks[i], (size_t)s->chunk_cap * sizeof(gm::JobChunk));
+            if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter[i], 256);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void **)&s->h_jobs[i], (size_t)s->table_cap * sizeof(gm::DevJob), hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void **)&s->h_chunks[i], (size_t)s->chunk_cap * sizeof(gm::JobChunk), hipHostMallocDefault);
         }
-        s->blocks = gm::partial_batch_max_blocks();
+        if (e == hipSuccess) s->blocks = gm::partial_batch_max_blocks();
+    }
+    if (e != hipSuccess) {
+        const int st = gm::hip_status(e, "server setup");
+        (void)hipGetLastError();
+        gumap_server_destroy(s);
+        return fail(st);
     }
     s->worker = std::thread([s] { s->run(); });
     if (status) *status = GUMAP_OK;
@@ -452,12 +622,28 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
     j->weights = job->want_weights != 0;
     j->flags = job->flags;
     const bool needs_canon = !(job->flags & GUMAP_CSR_SORTED) || (job->flags & GUMAP_VALIDATE);
-    j->bytes = job_bytes(j->n, j->nnz, j->k, j->weights, !needs_canon);
+    j->bytes = job_device_bytes(j->n, j->nnz, j->k, j->weights, needs_canon);
+    j->out_bytes = job_result_bytes(j->n, j->k, j->weights);
     if (j->bytes > s->budget)
         return gm::set_error(GUMAP_E2BIG, "job needs %zu device bytes, budget is %zu", j->bytes, s->budget);
-    j->h_rp.assign(job->row_ptr, job->row_ptr + (job->n > 0 ? job->n + 1 : 0));
-    if (job->n == 0) j->h_rp.assign(1, 0);
-    if (job->nnz) j->h_col.assign(job->col_idx, job->col_idx + job->nnz);
+    // copy the CSR now: into the pinned pool when it has room, else pageable memory
+    j->in_bytes = job_input_bytes(j->n, j->nnz);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        j->in_pinned = s->host_alloc.alloc(j->in_bytes, &j->in_off);
+    }
+    if (j->in_pinned) {
+        j->in_rp = (int32_t *)(s->host_pool + j->in_off);
+        j->in_col = (int32_t *)(s->host_pool + j->in_off + align_up((size_t)(j->n + 1) * 4, 256));
+    } else {
+        j->pg_rp.resize((size_t)j->n + 1);
+        j->pg_col.resize((size_t)std::max(j->nnz, 1));
+        j->in_rp = j->pg_rp.data();
+        j->in_col = j->pg_col.data();
+    }
+    if (j->n > 0) parallel_copy(j->in_rp, job->row_ptr, (size_t)(j->n + 1) * 4);
+    else j->in_rp[0] = 0;
+    if (j->nnz > 0) parallel_copy(j->in_col, job->col_idx, (size_t)j->nnz * 4);
     j->t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     j->ticket = s->next_ticket++;
@@ -465,6 +651,7 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
     s->queue.push_back(j);
     s->stats.submitted++;
     *ticket = j->ticket;
+    s->kick = true;
     s->cv_work.notify_one();
     return GUMAP_OK;
 }
@@ -475,11 +662,11 @@ static void fill_result(const Job &j, gumap_result *out)
     out->n = j.n;
     out->k = j.k;
     const bool ok = j.status == GUMAP_OK;
-    out->nbr_ids = ok ? j.r_ids.data() : nullptr;
-    out->nbr_hops = ok ? j.r_hops.data() : nullptr;
-    out->weights = ok && j.weights ? j.r_w.data() : nullptr;
-    out->rho = ok && j.weights ? j.r_rho.data() : nullptr;
-    out->sigma = ok && j.weights ? j.r_sigma.data() : nullptr;
+    out->nbr_ids = ok ? j.r_ids : nullptr;
+    out->nbr_hops = ok ? j.r_hops : nullptr;
+    out->weights = ok && j.weights ? j.r_w : nullptr;
+    out->rho = ok && j.weights ? j.r_rho : nullptr;
+    out->sigma = ok && j.weights ? j.r_sigma : nullptr;
     out->t_submit_ns = j.t_submit;
     out->t_admit_ns = j.t_admit;
     out->t_start_ns = j.t_start;
@@ -518,7 +705,12 @@ int gumap_release(gumap_server *s, uint64_t ticket)
     auto it = s->jobs.find(ticket);
     if (it == s->jobs.end()) return gm::set_error(GUMAP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     if (it->second->state != kDone) return GUMAP_PENDING;
+    Job &j = *it->second;
+    if (j.out_pinned) s->host_alloc.release(j.out_off, j.out_bytes);
+    j.out_pinned = false;
     s->jobs.erase(it);
+    s->kick = true;
+    s->cv_work.notify_one();   // result space freed: admission may proceed
     return GUMAP_OK;
 }
 
@@ -528,7 +720,7 @@ int gumap_server_get_stats(gumap_server *s, gumap_server_stats *out)
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
     out->queued = s->queue.size();
-    out->running = s->running.size();
+    out->running = s->admitted.size() + s->downloading.size();
     out->resident_bytes = s->resident;
     return GUMAP_OK;
 }
@@ -542,18 +734,35 @@ void gumap_server_destroy(gumap_server *s)
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    if (!s->no_device) {
-        (void)hipStreamSynchronize(s->compute);
-        (void)hipStreamSynchronize(s->copy);
-        (void)hipFree(s->slab);
-        (void)hipFree(s->d_jobs);
-        (void)hipFree(s->d_chunks);
-        (void)hipFree(s->d_counter);
-        (void)hipHostFree(s->h_jobs);
-        (void)hipHostFree(s->h_chunks);
-        (void)hipEventDestroy(s->iter_done);
-        (void)hipStreamDestroy(s->compute);
-        (void)hipStreamDestroy(s->copy);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &kv : s->jobs) {
+            Job &j = *kv.second;
+            if (j.up_done) (void)hipEventDestroy(j.up_done);
+            if (j.down_done) (void)hipEventDestroy(j.down_done);
+            j.up_done = j.down_done = nullptr;
+        }
+        s->jobs.clear();
+        s->queue.clear();
+        s->admitted.clear();
+        s->downloading.clear();
+    }
+    if (s->no_device) {
+        free(s->host_pool);
+    } else {
+        if (s->slab) (void)hipFree(s->slab);
+        if (s->host_pool) (void)hipHostFree(s->host_pool);
+        for (int i = 0; i < kInFlight; ++i) {
+            if (s->d_jobs[i]) (void)hipFree(s->d_jobs[i]);
+            if (s->d_chunks[i]) (void)hipFree(s->d_chunks[i]);
+            if (s->d_counter[i]) (void)hipFree(s->d_counter[i]);
+            if (s->h_jobs[i]) (void)hipHostFree(s->h_jobs[i]);
+            if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
+            if (s->iter_done[i]) (void)hipEventDestroy(s->iter_done[i]);
+        }
+        if (s->compute) (void)hipStreamDestroy(s->compute);
+        if (s->copy) (void)hipStreamDestroy(s->copy);
+        if (s->d2h) (void)hipStreamDestroy(s->d2h);
     }
     delete s;
 }
