@@ -413,8 +413,12 @@ def bench_serve(args):
     budget = int(args.serve_budget_gb * (1 << 30))
     warm = max(1, len(jobs) // 8)
     server = gm.Server(budget)
-    # saturation: everything submitted at once; rate from the server's own clock
-    tk = [server.submit(rp, ci, k) for (n, rp, ci), k in gk[:warm * 2]]
+    # warm-up burst (first launches load code objects), then saturation:
+    # everything submitted at once; rate from the server's own clock
+    for t in [server.submit(rp, ci, k) for (n, rp, ci), k in gk[:warm]]:
+        server.wait(t, copy_results=False)
+        server.release(t)
+    tk = [server.submit(rp, ci, k) for (n, rp, ci), k in gk[warm:warm * 3]]
     t_first = t_last = None
     for t in tk:
         r = server.wait(t, copy_results=False)
@@ -481,6 +485,16 @@ def bench_serve(args):
         w_, r_, s_ = gm.membership(h_)
         i_.cpu(), h_.cpu(), w_.cpu(), r_.cpu(), s_.cpu()
     t_plain = (time.perf_counter() - t0) / len(plain)
+    # the same plain calls with the graphs already resident and the results
+    # left on the device: what the per-graph launches cost without transfers
+    resident = [(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), k) for (n, rp, ci), k in plain]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for drp, dci, k in resident:
+        i_, h_ = gm.knn_partial(drp, dci, k, flags=gm.CSR_SORTED)
+        gm.membership(h_)
+    torch.cuda.synchronize()
+    out["graphs_per_s_plain_loop_resident"] = len(plain) / (time.perf_counter() - t0)
     out["graphs_per_s_plain_loop"] = 1.0 / t_plain
     out["speedup_vs_plain"] = out["saturation_graphs_per_s"] * t_plain
     if not args.no_parity:

@@ -3,13 +3,16 @@
 // that sum_j h_ij = log2 k).  One thread per row.
 //
 // Hops are integers, so with x = exp(-1/sigma) the row's sum is the
-// polynomial P(x) = sum_j x^(h_j - rho), increasing on (0, 1) from
-// c0 = #{h_j = rho} to K (the valid entries).  The root of P(x) = log2 k is
-// bisected directly in x in double precision (Horner-free incremental powers
-// over the sorted row, no exp per step); sigma = -1/ln x and w_j = x^(h_j-rho).
-// Rows without a root take the limits: K = 0 -> all zero; c0 >= log2 k ->
-// sigma = 0, weights 1 at rho and 0 beyond; K <= log2 k -> sigma = +inf,
-// weights 1.
+// polynomial P(x) = sum_d c_d x^d over the counts c_d of entries at hop
+// rho + d, increasing and convex on (0, 1) from c_0 to K (the valid
+// entries).  The root of P(x) = log2 k is found in double precision by
+// Newton's method started at x = 1: on a convex increasing function the
+// iterates decrease monotonically onto the root, and the loop ends when
+// rounding stops the decrease.  Rows whose hops span more than kMembLevels
+// levels keep the counts implicit and bisect in x instead.  Then
+// sigma = -1/ln x and w_j = x^(h_j - rho).  Rows without a root take the
+// limits: K = 0 -> all zero; c_0 >= log2 k -> sigma = 0, weights 1 at rho
+// and 0 beyond; K <= log2 k -> sigma = +inf, weights 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +20,8 @@
 #include <stdint.h>
 
 namespace gm {
+
+constexpr int kMembLevels = 16;
 
 template <typename HopAt>
 __device__ __forceinline__ double membership_poly(HopAt hop_at, int K, int rho, double x)
@@ -37,18 +42,28 @@ template <typename HopAt>
 __device__ __forceinline__ void membership_row(HopAt hop_at, int k, float *w, float *rho_out,
                                                float *sigma_out)
 {
-    int K = 0;
-    while (K < k && hop_at(K) != 255) ++K;
-    if (K == 0) {
+    const int rho = k > 0 ? hop_at(0) : 255;
+    if (rho == 255) {
         for (int j = 0; j < k; ++j) w[j] = 0.0f;
         if (rho_out) *rho_out = 0.0f;
         if (sigma_out) *sigma_out = 0.0f;
         return;
     }
-    const int rho = hop_at(0);
+    // counts per level above rho (one pass over the row), as 8-bit fields
+    // (a count is at most k <= 254) of two words: levels 0..7 and 8..15
+    uint64_t lo8 = 0, hi8 = 0;
+    int K = 0;
+    bool wide = false;
+    for (; K < k; ++K) {
+        const int h = hop_at(K);
+        if (h == 255) break;
+        const int d = h - rho;
+        if (d < 8) lo8 += 1ull << (8 * d);
+        else if (d < kMembLevels) hi8 += 1ull << (8 * (d - 8));
+        else wide = true;
+    }
+    const int c0 = (int)(lo8 & 0xFF);
     const double T = log2((double)k);
-    int c0 = 0;
-    for (int j = 0; j < K; ++j) c0 += (hop_at(j) == rho);
     float sigma;
     if ((double)c0 >= T) {
         sigma = 0.0f;
@@ -57,14 +72,34 @@ __device__ __forceinline__ void membership_row(HopAt hop_at, int k, float *w, fl
         sigma = INFINITY;
         for (int j = 0; j < K; ++j) w[j] = 1.0f;
     } else {
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 2000; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid == lo || mid == hi) break;
-            if (membership_poly(hop_at, K, rho, mid) < T) lo = mid;
-            else hi = mid;
+        double x = 1.0;
+        if (!wide) {
+            double cnt[kMembLevels];
+#pragma unroll
+            for (int d = 0; d < kMembLevels; ++d)
+                cnt[d] = (double)(((d < 8 ? lo8 : hi8) >> (8 * (d & 7))) & 0xFF);
+            for (int it = 0; it < 1000; ++it) {
+                double p = cnt[kMembLevels - 1], dp = 0.0;
+#pragma unroll
+                for (int d = kMembLevels - 2; d >= 0; --d) {
+                    dp = fma(dp, x, p);
+                    p = fma(p, x, cnt[d]);
+                }
+                const double xn = x - (p - T) / dp;
+                if (!(xn < x)) break;
+                x = xn > 0.0 ? xn : 0.5 * x;
+            }
+        } else {
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 2000; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                if (mid == lo || mid == hi) break;
+                if (membership_poly(hop_at, K, rho, mid) < T) lo = mid;
+                else hi = mid;
+            }
+            x = hi;
         }
-        const double lx = log(hi);
+        const double lx = log(x);
         sigma = (float)(-1.0 / lx);
         for (int j = 0; j < K; ++j) w[j] = (float)exp((double)(hop_at(j) - rho) * lx);
     }

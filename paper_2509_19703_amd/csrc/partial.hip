@@ -48,12 +48,19 @@ __device__ void partial_row(const int32_t *__restrict__ rp, const int32_t *__res
                             int32_t v, int k, WaveLds &s)
 {
     const int l = lane();
-    if (l == 0) {
-        s.fa[0] = v;
-        s.seen[0] = v;
+    // level 1: the first min(deg, k) entries of v's sorted row
+    const int32_t e0 = rp[v], e1 = rp[v + 1];
+    const int t1 = min(e1 - e0, k);
+    if (l == 0) s.seen[0] = v;
+    for (int i = l; i < t1; i += 64) {
+        const int32_t u = col[e0 + i];
+        s.fa[i] = u;
+        s.seen[1 + i] = u;
+        s.row_ids[i] = u;
+        s.row_hops[i] = 1;
     }
     wave_sync();
-    int nf = 1, nseen = 1, taken = 0, h = 0;
+    int nf = t1, nseen = 1 + t1, taken = t1, h = 1;
     int32_t *fa = s.fa, *fb = s.fb;
     while (taken < k && nf > 0) {
         ++h;
@@ -145,11 +152,22 @@ __device__ void partial_rows(const int32_t *__restrict__ rp, const int32_t *__re
     const int rl = l & (ROW - 1);
     const int rb = l & ~(ROW - 1);
     const unsigned long long gmask = ROW == 64 ? ~0ull : (((1ull << ROW) - 1ull) << rb);
-    int32_t sv = rl == 0 ? v : -1;
-    int32_t fr = rl == 0 ? v : -1;
-    my_id = -1;
-    my_hop = 255;
-    int taken = 0, nf = v >= 0 ? 1 : 0, nseen = 1, h = 0;
+    // Level 1 is the sorted row of v itself: its first min(deg, k) entries,
+    // read in one coalesced load (rows hold no self-loop).
+    int32_t e0 = 0, e1 = 0;
+    if (v >= 0) {
+        e0 = rp[v];
+        e1 = rp[v + 1];
+    }
+    const int t1 = min(e1 - e0, k);
+    const int32_t x = rl < t1 ? col[e0 + rl] : -1;
+    my_id = rl < t1 ? x : -1;
+    my_hop = rl < t1 ? 1 : 255;
+    // seen set: v in lane 0, level 1 in lanes 1..t1; the frontier is level 1
+    const int32_t up = __shfl(x, rb + (rl > 0 ? rl - 1 : 0), GM_WAVE);
+    int32_t sv = rl == 0 ? v : (rl - 1 < t1 ? up : -1);
+    int32_t fr = x;
+    int taken = t1, nf = t1, nseen = 1 + t1, h = 1;
     for (;;) {
         const bool go = taken < k && nf > 0;
         if (__ballot(go) == 0ull) break;

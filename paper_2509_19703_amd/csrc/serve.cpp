@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -96,6 +97,42 @@ private:
 
 enum JobState { kQueued, kAdmitted, kDownloading, kDone };
 
+// An event shared by the jobs whose copies it follows: one record per batch
+// of uploads or downloads instead of one per job (records interleaved with
+// every copy slow down uploads that overlap downloads in the other direction).
+struct SharedEvent {
+    hipEvent_t ev = nullptr;
+    ~SharedEvent()
+    {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+typedef std::shared_ptr<SharedEvent> EventRef;
+
+// Records a fresh event on `s`; null on failure.
+EventRef record_event(hipStream_t s)
+{
+    auto r = std::make_shared<SharedEvent>();
+    if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(r->ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return r;
+}
+
+// hipEventQuery, asked once per event within one pass over many jobs.
+struct QueryCache {
+    std::map<SharedEvent *, bool> seen;
+    bool done(const EventRef &r)
+    {
+        auto it = seen.find(r.get());
+        if (it != seen.end()) return it->second;
+        const hipError_t q = hipEventQuery(r->ev);
+        if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
+        return seen[r.get()] = (q != hipErrorNotReady);
+    }
+};
+
 struct Job {
     uint64_t ticket = 0;
     JobState state = kQueued;
@@ -118,7 +155,7 @@ struct Job {
     // device
     size_t bytes = 0, slab_off = 0;
     gm::DevJob dev{};
-    hipEvent_t up_done = nullptr, down_done = nullptr;
+    EventRef up_done, down_done;   // upload and result download complete
     bool waited = false;           // compute stream already waits for the upload
     bool input_freed = false;
     int32_t next_row = 0;
@@ -152,26 +189,119 @@ size_t job_input_bytes(int32_t n, int32_t nnz)
 
 constexpr int kInFlight = 2;
 
-// memcpy split over a few threads: one thread does not reach the host's
-// memory bandwidth for the multi-megabyte CSR copies made at submission.
-void parallel_copy(void *dst, const void *src, size_t bytes)
-{
-    constexpr size_t kMin = 4u << 20;
-    const int parts = (int)std::min<size_t>(8, std::max<size_t>(1, bytes / kMin));
-    if (parts <= 1) {
-        std::memcpy(dst, src, bytes);
-        return;
+// Host copies of submitted CSRs, split into 1 MiB parts over a few
+// persistent threads plus the caller: one thread reaches only a fraction of
+// the host's memory bandwidth on multi-megabyte copies from cold memory.
+// Parts are claimed with a compare-and-swap on (generation, index), so a
+// worker that wakes late never takes a part of a later copy.
+class CopyPool {
+public:
+    explicit CopyPool(int workers)
+    {
+        for (int i = 0; i < workers; ++i) th_.emplace_back([this] { work(); });
     }
-    const size_t per = align_up((bytes + parts - 1) / parts, 4096);
-    std::vector<std::thread> th;
-    for (int p = 1; p < parts; ++p) {
-        const size_t off = per * p;
-        if (off >= bytes) break;
-        th.emplace_back([=] { std::memcpy((char *)dst + off, (const char *)src + off, std::min(per, bytes - off)); });
+    ~CopyPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
     }
-    std::memcpy(dst, src, std::min(per, bytes));
-    for (auto &t : th) t.join();
-}
+    void copy(void *dst, const void *src, size_t bytes)
+    {
+        if (th_.empty() || bytes < 2 * kPart) {
+            std::memcpy(dst, src, bytes);
+            return;
+        }
+        std::lock_guard<std::mutex> call(call_mu_);   // one copy at a time
+        uint32_t gen;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            dst_ = (char *)dst;
+            src_ = (const char *)src;
+            bytes_ = bytes;
+            parts_ = (uint32_t)((bytes + kPart - 1) / kPart);
+            gen = ++gen_;
+            done_.store(0);
+            next_.store((uint64_t)gen << 32);
+        }
+        cv_.notify_all();
+        run_parts(gen, (char *)dst, (const char *)src, bytes, parts_);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return done_.load() == parts_; });
+    }
+
+    // memset split over as many threads as the pool holds
+    void fill(void *dst, int value, size_t bytes)
+    {
+        const size_t parts = (bytes + kPart * 16 - 1) / (kPart * 16);
+        std::vector<std::thread> th;
+        std::atomic<size_t> next{0};
+        auto run = [&] {
+            for (size_t i; (i = next.fetch_add(1)) < parts;) {
+                const size_t off = i * kPart * 16;
+                std::memset((char *)dst + off, value, std::min(kPart * 16, bytes - off));
+            }
+        };
+        for (size_t i = 0; i < th_.size(); ++i) th.emplace_back(run);
+        run();
+        for (auto &t : th) t.join();
+    }
+
+private:
+    static constexpr size_t kPart = 1u << 20;
+
+    void run_parts(uint32_t gen, char *dst, const char *src, size_t bytes, uint32_t parts)
+    {
+        for (;;) {
+            uint64_t v = next_.load();
+            for (;;) {
+                if ((uint32_t)(v >> 32) != gen || (uint32_t)v >= parts) return;
+                if (next_.compare_exchange_weak(v, v + 1)) break;
+            }
+            const size_t off = (size_t)(uint32_t)v * kPart;
+            std::memcpy(dst + off, src + off, std::min(kPart, bytes - off));
+            if (done_.fetch_add(1) + 1 == parts) {
+                std::lock_guard<std::mutex> lk(mu_);
+                done_cv_.notify_all();
+            }
+        }
+    }
+    void work()
+    {
+        uint32_t seen = 0;
+        for (;;) {
+            uint32_t gen, parts;
+            char *dst;
+            const char *src;
+            size_t bytes;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen = gen_;
+                dst = dst_;
+                src = src_;
+                bytes = bytes_;
+                parts = parts_;
+            }
+            run_parts(gen, dst, src, bytes, parts);
+        }
+    }
+
+    std::mutex call_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    std::vector<std::thread> th_;
+    char *dst_ = nullptr;
+    const char *src_ = nullptr;
+    size_t bytes_ = 0;
+    uint32_t parts_ = 0, gen_ = 0;
+    std::atomic<uint64_t> next_{0};
+    std::atomic<uint32_t> done_{0};
+    bool stop_ = false;
+};
 
 }  // namespace
 
@@ -185,9 +315,9 @@ struct gumap_server {
     char *host_pool = nullptr;          // pinned (or plain memory without a device)
     size_t host_pool_bytes = 0;
     SlabAllocator host_alloc;
-    hipStream_t compute = nullptr, copy = nullptr, d2h = nullptr;
+    hipStream_t compute = nullptr, copy = nullptr, d2h = nullptr, meta = nullptr;
     // per in-flight iteration slot
-    hipEvent_t iter_done[kInFlight] = {};
+    hipEvent_t iter_done[kInFlight] = {}, table_done[kInFlight] = {};
     gm::DevJob *d_jobs[kInFlight] = {};
     gm::JobChunk *d_chunks[kInFlight] = {};
     unsigned long long *d_counter[kInFlight] = {};
@@ -207,6 +337,7 @@ struct gumap_server {
     bool stop = false;
     bool kick = false;                 // a submission or a released result may unblock admission
     std::thread worker;
+    std::unique_ptr<CopyPool> copier;
     gumap_server_stats stats{};
     size_t resident = 0;
 
@@ -251,9 +382,8 @@ void gumap_server::finish_locked(const std::shared_ptr<Job> &j, int status)
         host_alloc.release(j->out_off, j->out_bytes);
         j->out_pinned = false;
     }
-    if (j->up_done) (void)hipEventDestroy(j->up_done);
-    if (j->down_done) (void)hipEventDestroy(j->down_done);
-    j->up_done = j->down_done = nullptr;
+    j->up_done.reset();
+    j->down_done.reset();
     if (status == GUMAP_OK) stats.completed++;
     else stats.failed++;
     cv_done.notify_all();
@@ -280,15 +410,25 @@ int gumap_server::stage(Job &j)
         j.dev.rho = (float *)take((size_t)j.n * 4);
         j.dev.sigma = (float *)take((size_t)j.n * 4);
     }
+    // results come back in one copy: the host result region mirrors this layout
+    if (j.n > 0 && ((char *)j.dev.hops - (char *)j.dev.ids != (char *)j.r_hops - (char *)j.r_ids ||
+                    (j.weights && (char *)j.dev.sigma - (char *)j.dev.ids != (char *)j.r_sigma - (char *)j.r_ids)))
+        return gm::set_error(GUMAP_EINVAL, "internal: result layouts differ");
     j.dev.n = j.n;
     j.dev.k = j.k;
     j.dev.row_ptr = rp;
     j.dev.col = col;
-    hipError_t e = hipEventCreateWithFlags(&j.up_done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&j.down_done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMemcpyAsync(rp, j.in_rp, (size_t)(j.n + 1) * 4, hipMemcpyHostToDevice, copy);
-    if (e == hipSuccess && j.nnz)
-        e = hipMemcpyAsync(col, j.in_col, (size_t)j.nnz * 4, hipMemcpyHostToDevice, copy);
+    hipError_t e = hipSuccess;
+    if (j.in_pinned) {
+        // the pinned slice has the device layout (row_ptr, then col_idx at the
+        // next 256-byte boundary): one copy
+        const size_t bytes = align_up((size_t)(j.n + 1) * 4, 256) + (size_t)j.nnz * 4;
+        if (e == hipSuccess) e = hipMemcpyAsync(rp, j.in_rp, bytes, hipMemcpyHostToDevice, copy);
+    } else {
+        if (e == hipSuccess) e = hipMemcpyAsync(rp, j.in_rp, (size_t)(j.n + 1) * 4, hipMemcpyHostToDevice, copy);
+        if (e == hipSuccess && j.nnz)
+            e = hipMemcpyAsync(col, j.in_col, (size_t)j.nnz * 4, hipMemcpyHostToDevice, copy);
+    }
     if (e != hipSuccess) return gm::hip_status(e, "job upload");
     if (!(j.flags & GUMAP_CSR_SORTED) || (j.flags & GUMAP_VALIDATE)) {
         int32_t *crp = (int32_t *)take((size_t)(j.n + 1) * 4);
@@ -320,8 +460,7 @@ int gumap_server::stage(Job &j)
             if (bad) return gm::set_error(GUMAP_EGRAPH, "CSR is not symmetric");
         }
     }
-    e = hipEventRecord(j.up_done, copy);
-    return gm::hip_status(e, "job upload event");
+    return GUMAP_OK;
 }
 
 // Enqueue one iteration if a slot is free and rows are waiting.
@@ -364,20 +503,27 @@ bool gumap_server::launch_iteration()
     }
     if (!no_device) {
         hipError_t e = hipSuccess;
+        SharedEvent *last = nullptr;
         for (auto &j : table) {
             if (!j->waited) {
-                e = hipStreamWaitEvent(compute, j->up_done, 0);
+                if (j->up_done.get() != last) e = hipStreamWaitEvent(compute, j->up_done->ev, 0);
+                last = j->up_done.get();
                 j->waited = true;
                 if (e != hipSuccess) break;
             }
         }
         for (size_t i = 0; i < table.size(); ++i) h_jobs[slot][i] = table[i]->dev;
         std::copy(chunks.begin(), chunks.end(), h_chunks[slot]);
+        // the iteration's tables go up on a stream of their own: a copy
+        // queued behind the running kernel on the compute stream would hold
+        // up the job uploads that share its copy engine
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_jobs[slot], h_jobs[slot], table.size() * sizeof(gm::DevJob), hipMemcpyHostToDevice, compute);
+            e = hipMemcpyAsync(d_jobs[slot], h_jobs[slot], table.size() * sizeof(gm::DevJob), hipMemcpyHostToDevice, meta);
         if (e == hipSuccess && !chunks.empty())
             e = hipMemcpyAsync(d_chunks[slot], h_chunks[slot], chunks.size() * sizeof(gm::JobChunk),
-                               hipMemcpyHostToDevice, compute);
+                               hipMemcpyHostToDevice, meta);
+        if (e == hipSuccess) e = hipEventRecord(table_done[slot], meta);
+        if (e == hipSuccess) e = hipStreamWaitEvent(compute, table_done[slot], 0);
         if (e == hipSuccess) e = gm::launch_batch_reset(d_counter[slot], compute);
         if (e == hipSuccess)
             e = gm::launch_partial_jobs(d_jobs[slot], d_chunks[slot], (int32_t)chunks.size(), max_k,
@@ -402,7 +548,8 @@ bool gumap_server::launch_iteration()
 // Completed iterations: start the result downloads of jobs they finished.
 bool gumap_server::retire_iterations()
 {
-    bool progress = false;
+    std::vector<std::shared_ptr<Job>> started, failed;
+    bool popped = false;
     while (!flights.empty()) {
         Flight &fl = flights.front();
         if (!no_device) {
@@ -415,59 +562,70 @@ bool gumap_server::retire_iterations()
             const size_t nk = (size_t)j->n * j->k;
             hipError_t e = hipSuccess;
             if (!no_device && j->n > 0) {
-                e = hipMemcpyAsync(j->r_ids, j->dev.ids, nk * 4, hipMemcpyDeviceToHost, d2h);
-                if (e == hipSuccess) e = hipMemcpyAsync(j->r_hops, j->dev.hops, nk, hipMemcpyDeviceToHost, d2h);
-                if (e == hipSuccess && j->weights) {
-                    e = hipMemcpyAsync(j->r_w, j->dev.weights, nk * 4, hipMemcpyDeviceToHost, d2h);
-                    if (e == hipSuccess) e = hipMemcpyAsync(j->r_rho, j->dev.rho, (size_t)j->n * 4, hipMemcpyDeviceToHost, d2h);
-                    if (e == hipSuccess)
-                        e = hipMemcpyAsync(j->r_sigma, j->dev.sigma, (size_t)j->n * 4, hipMemcpyDeviceToHost, d2h);
-                }
+                // host and device result regions share one layout (ids, hops,
+                // weights, rho, sigma at 256-byte boundaries): one copy
+                const size_t bytes = j->weights ? (size_t)((char *)j->r_sigma - (char *)j->r_ids) + (size_t)j->n * 4
+                                                : (size_t)((char *)j->r_hops - (char *)j->r_ids) + nk;
+                // issued as a one-row 2D copy: some HIP runtimes run linear
+                // device-to-host copies as shader blits, which stall the DMA
+                // engine carrying the uploads; the 2D form goes to DMA, so
+                // downloads and uploads overlap on the full-duplex link
+                e = hipMemcpy2DAsync(j->r_ids, bytes, j->dev.ids, bytes, bytes, 1, hipMemcpyDeviceToHost, d2h);
             }
-            if (e == hipSuccess && !no_device) e = hipEventRecord(j->down_done, d2h);
-            std::lock_guard<std::mutex> lk(mu);
-            admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
             if (e != hipSuccess) {
                 (void)hipGetLastError();
-                finish_locked(j, GUMAP_EDEVICE);
+                failed.push_back(j);
             } else {
-                j->state = kDownloading;
-                downloading.push_back(j);
+                started.push_back(j);
             }
         }
         flights.pop_front();
-        progress = true;
+        popped = true;
     }
-    return progress;
+    if (started.empty() && failed.empty()) return popped;
+    EventRef ev;
+    if (!no_device && !started.empty()) {
+        ev = record_event(d2h);
+        if (!ev) {
+            failed.insert(failed.end(), started.begin(), started.end());
+            started.clear();
+        }
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &j : failed) {
+        admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
+        finish_locked(j, GUMAP_EDEVICE);
+    }
+    for (auto &j : started) {
+        admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
+        j->down_done = ev;
+        j->state = kDownloading;
+        downloading.push_back(j);
+    }
+    return true;
 }
 
 bool gumap_server::poll_downloads()
 {
-    bool progress = false;
-    std::lock_guard<std::mutex> lk(mu);
-    for (size_t i = 0; i < downloading.size();) {
-        auto j = downloading[i];
-        bool ready = true;
-        if (!no_device) {
-            hipError_t q = hipEventQuery(j->down_done);
-            if (q == hipErrorNotReady) ready = false;
-            else if (q != hipSuccess) (void)hipGetLastError();
-        }
-        if (!ready) {
-            ++i;
-            continue;
-        }
-        downloading.erase(downloading.begin() + (long)i);
-        finish_locked(j, GUMAP_OK);
-        progress = true;
-    }
-    // inputs of uploaded jobs go back to the pool
+    // events are queried without the lock (only this thread changes the
+    // admitted and downloading lists), so submissions are not held up
+    std::vector<std::shared_ptr<Job>> ready, uploaded;
+    QueryCache qc;
+    for (auto &j : downloading)
+        if (no_device || !j->down_done || qc.done(j->down_done)) ready.push_back(j);
     for (auto &j : admitted) {
         if (j->input_freed || !j->up_done) continue;
-        if (hipEventQuery(j->up_done) == hipSuccess) free_input_locked(*j);
-        else (void)hipGetLastError();
+        if (qc.done(j->up_done)) uploaded.push_back(j);
     }
-    return progress;
+    if (ready.empty() && uploaded.empty()) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &j : ready) {
+        downloading.erase(std::find(downloading.begin(), downloading.end(), j));
+        finish_locked(j, GUMAP_OK);
+    }
+    // inputs of uploaded jobs go back to the pool
+    for (auto &j : uploaded) free_input_locked(*j);
+    return !ready.empty();
 }
 
 void gumap_server::run()
@@ -520,13 +678,29 @@ void gumap_server::run()
                 queue.pop_front();
             }
         }
+        std::vector<std::shared_ptr<Job>> staged;
         for (auto &j : fresh) {
             const int st = stage(*j);
+            if (st == GUMAP_OK) {
+                staged.push_back(j);
+                continue;
+            }
+            (void)hipGetLastError();
             std::lock_guard<std::mutex> lk(mu);
-            if (st != GUMAP_OK) {
-                (void)hipGetLastError();
-                finish_locked(j, st);
-            } else {
+            finish_locked(j, st);
+        }
+        if (!staged.empty()) {
+            // one event marks the uploads of the whole batch
+            EventRef up = no_device ? nullptr : record_event(copy);
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto &j : staged) {
+                if (!no_device && !up) {
+                    gm::set_error(GUMAP_EDEVICE, "upload event");
+                    finish_locked(j, GUMAP_EDEVICE);
+                    continue;
+                }
+                j->up_done = up;
+                if (no_device) j->waited = true;
                 admitted.push_back(j);
             }
         }
@@ -547,6 +721,7 @@ void gumap_server::run()
         (void)hipStreamSynchronize(compute);
         (void)hipStreamSynchronize(copy);
         (void)hipStreamSynchronize(d2h);
+        (void)hipStreamSynchronize(meta);
     }
 }
 
@@ -583,8 +758,10 @@ gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->d2h, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->meta, hipStreamNonBlocking);
         for (int i = 0; i < kInFlight && e == hipSuccess; ++i) {
             e = hipEventCreateWithFlags(&s->iter_done[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->table_done[i], hipEventDisableTiming);
             if (e == hipSuccess) e = hipMalloc((void **)&s->d_jobs[i], (size_t)s->table_cap * sizeof(gm::DevJob));
             if (e == hipSuccess) e = hipMalloc((void **)&s->d_chunks[i], (size_t)s->chunk_cap * sizeof(gm::JobChunk));
             if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter[i], 256);
@@ -600,6 +777,15 @@ gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
         (void)hipGetLastError();
         gumap_server_destroy(s);
         return fail(st);
+    }
+    {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int def = std::max(0, std::min(7, hw / 2 - 1));
+        s->copier.reset(new CopyPool((int)std::min<size_t>(31, gm::env_size("GUMAP_SERVE_COPY_THREADS", (size_t)def))));
+        // the first CPU write to each page of pinned memory is about ten
+        // times slower than later ones: touch the whole pool now, so that
+        // submissions copy at full speed
+        s->copier->fill(s->host_pool, 0, s->host_pool_bytes);
     }
     s->worker = std::thread([s] { s->run(); });
     if (status) *status = GUMAP_OK;
@@ -641,9 +827,9 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
         j->in_rp = j->pg_rp.data();
         j->in_col = j->pg_col.data();
     }
-    if (j->n > 0) parallel_copy(j->in_rp, job->row_ptr, (size_t)(j->n + 1) * 4);
+    if (j->n > 0) s->copier->copy(j->in_rp, job->row_ptr, (size_t)(j->n + 1) * 4);
     else j->in_rp[0] = 0;
-    if (j->nnz > 0) parallel_copy(j->in_col, job->col_idx, (size_t)j->nnz * 4);
+    if (j->nnz > 0) s->copier->copy(j->in_col, job->col_idx, (size_t)j->nnz * 4);
     j->t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     j->ticket = s->next_ticket++;
@@ -738,9 +924,8 @@ void gumap_server_destroy(gumap_server *s)
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &kv : s->jobs) {
             Job &j = *kv.second;
-            if (j.up_done) (void)hipEventDestroy(j.up_done);
-            if (j.down_done) (void)hipEventDestroy(j.down_done);
-            j.up_done = j.down_done = nullptr;
+            j.up_done.reset();
+            j.down_done.reset();
         }
         s->jobs.clear();
         s->queue.clear();
@@ -759,10 +944,12 @@ void gumap_server_destroy(gumap_server *s)
             if (s->h_jobs[i]) (void)hipHostFree(s->h_jobs[i]);
             if (s->h_chunks[i]) (void)hipHostFree(s->h_chunks[i]);
             if (s->iter_done[i]) (void)hipEventDestroy(s->iter_done[i]);
+            if (s->table_done[i]) (void)hipEventDestroy(s->table_done[i]);
         }
         if (s->compute) (void)hipStreamDestroy(s->compute);
         if (s->copy) (void)hipStreamDestroy(s->copy);
         if (s->d2h) (void)hipStreamDestroy(s->d2h);
+        if (s->meta) (void)hipStreamDestroy(s->meta);
     }
     delete s;
 }

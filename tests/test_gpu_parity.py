@@ -242,3 +242,33 @@ def test_partial_lane_width_invariance(gumap, lanes, monkeypatch):
             oi, oh = O.knn_partial(g, k)
             assert np.array_equal(ids.cpu().numpy(), oi), (lanes, k, first_mismatch(ids.cpu().numpy(), oi))
             assert np.array_equal(hops.cpu().numpy(), oh)
+
+
+def _synthetic_hop_rows(rows, k, seed):
+    """Sorted hop rows with 255 padding: the valid count K, rho and the spread
+    of levels above rho vary per row (spreads past 16 levels included)."""
+    rng = np.random.default_rng(seed)
+    out = np.full((rows, k), 255, dtype=np.uint8)
+    for r in range(rows):
+        K = int(rng.integers(0, k + 1)) if r % 4 else k
+        rho = int(rng.integers(1, 4))
+        p_step = (0.05, 0.2, 0.5, 0.9)[r % 4]
+        if K == 0:
+            continue
+        steps = rng.random(K) < p_step
+        steps[0] = False
+        h = rho + np.cumsum(steps)
+        out[r, :K] = np.minimum(h, 254)
+    return out
+
+
+@pytest.mark.parametrize("k", [2, 3, 10, 15, 16, 30, 64, 100, 254])
+def test_membership_synthetic_rows(gumap, k):
+    """Membership of rows of every shape (degenerate low and high, narrow and
+    wide level spreads, padding) against the oracle's bisection."""
+    import torch
+    oh = _synthetic_hop_rows(3000, k, 900 + k)
+    hops = torch.from_numpy(oh).cuda()
+    w, rho, sigma = gumap.membership(hops)
+    ow, orho, osig = O.membership(oh)
+    assert_weights_close(w.cpu().numpy(), ow, rho.cpu().numpy(), orho, sigma.cpu().numpy(), osig)
