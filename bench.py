@@ -544,12 +544,12 @@ def write_traffic(args):
 
 
 def kernel_source_sha() -> str:
-    """Hash of the HIP sources, so stored counter readings go stale when a kernel changes."""
-    import glob
+    """Hash of the sources of the BFS level kernel (the one the stored counter
+    readings are for), so they go stale when that kernel changes."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2509_19703_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for name in ("msbfs.hip", "kernels.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_2509_19703_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
