@@ -360,6 +360,7 @@ def bench_batch(args):
                                   % (ng, ng, k, rows), "graphs": ng, "rows": rows, "nnz": pb.total_nnz, "k": k},
            "graphs_per_s_plain_loop": ng / t_plain, "speedup_vs_plain": t_plain / best,
            "ms_batched_call": dt_batch * 1e3, "ms_plan_replay": dt_plan * 1e3, "ms_plain_loop": t_plain * 1e3,
+           "plan_autotune": plan.tuning(),
            "rows_per_s": rows / best, "roofline": roof, "kernels_ms_per_step": kms,
            "batched_equals_plain": bool(same_plain), "plan_equals_plain": bool(same_plan),
            "host_generation_s": t_gen}

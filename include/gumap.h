@@ -163,6 +163,12 @@ int gumap_knn_partial_batch(const gumap_batch *b, int32_t k, int32_t *nbr_ids, u
  * unchanged in size until gumap_batch_plan_destroy.  The batch must be
  * canonical (GUMAP_CSR_SORTED).  Replays give the same results as the plain
  * call.
+ * Before capture the launch is autotuned on this batch: every candidate
+ * (lanes per source in {16, 32, 64} where k + 1 fits, or one wave per source;
+ * rows per work grab in {16, 32, 64}; half or all of the resident-workgroup
+ * grid) is timed (one warm-up and two timed launches, writing the outputs),
+ * and the fastest is recorded.  Every candidate computes the same rows.
+ * Setting the environment variable GUMAP_PLAN_TUNE=0 skips the tuning.
  */
 typedef struct gumap_batch_plan gumap_batch_plan;
 int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
@@ -170,6 +176,18 @@ int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, u
                             gumap_batch_plan **plan);
 int gumap_batch_plan_launch(gumap_batch_plan *plan, hipStream_t stream); /* host-synchronous */
 void gumap_batch_plan_destroy(gumap_batch_plan *plan);
+
+/* What the autotuner of gumap_batch_plan_create picked (all zero when it did
+ * not run).  Errors: GUMAP_EINVAL for a NULL argument. */
+typedef struct gumap_batch_tuning {
+    int32_t lanes;      /* lanes per source: 16, 32, 64; -1 one wave per source; 0 default */
+    int32_t chunk;      /* rows per work grab */
+    int32_t blocks;     /* persistent workgroups */
+    int32_t candidates; /* configurations timed */
+    float best_ms;      /* one launch with the pick */
+    float default_ms;   /* one launch with the defaults of gumap_knn_partial_batch */
+} gumap_batch_tuning;
+int gumap_batch_plan_tuning(const gumap_batch_plan *plan, gumap_batch_tuning *out);
 
 /* ----------------------------------------------------------- serving --- */
 

@@ -37,6 +37,11 @@ class gumap_graph(ctypes.Structure):
                 ("col_idx", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
+class gumap_batch_tuning(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("chunk", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
+
+
 class gumap_batch(ctypes.Structure):
     _fields_ = [("n_graphs", ctypes.c_int32), ("total_vertices", ctypes.c_int64),
                 ("total_nnz", ctypes.c_int64), ("vtx_offset", ctypes.c_void_p),
@@ -97,6 +102,8 @@ def _load() -> ctypes.CDLL:
     lib.gumap_batch_plan_launch.argtypes = [vp, vp]
     lib.gumap_batch_plan_destroy.argtypes = [vp]
     lib.gumap_batch_plan_destroy.restype = None
+    lib.gumap_batch_plan_tuning.argtypes = [vp, ctypes.POINTER(gumap_batch_tuning)]
+    lib.gumap_batch_plan_tuning.restype = ctypes.c_int
     for f in (lib.gumap_knn_build, lib.gumap_knn_partial, lib.gumap_membership,
               lib.gumap_knn_partial_batch, lib.gumap_batch_plan_create, lib.gumap_batch_plan_launch):
         f.restype = ctypes.c_int
@@ -343,6 +350,12 @@ class BatchPlan:
     def launch(self, stream=None):
         _check(lib.gumap_batch_plan_launch(self._h, _stream(stream)))
         return self.ids, self.hops, self.weights, self.rho, self.sigma
+
+    def tuning(self) -> dict:
+        t = gumap_batch_tuning()
+        _check(lib.gumap_batch_plan_tuning(self._h, ctypes.byref(t)))
+        return {"lanes": t.lanes, "chunk": t.chunk, "blocks": t.blocks, "candidates": t.candidates,
+                "best_ms": t.best_ms, "default_ms": t.default_ms}
 
     def close(self):
         if self._h:

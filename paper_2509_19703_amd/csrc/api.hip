@@ -681,7 +681,7 @@ int prepare_batch(const gumap_batch *b, hipStream_t s, gumap_batch *out)
 }
 
 int batch_enqueue(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, float *w, float *rho,
-                  float *sigma, hipStream_t s)
+                  float *sigma, hipStream_t s, const BatchTune *t)
 {
     unsigned long long *counter = nullptr;
     int st;
@@ -701,8 +701,10 @@ int batch_enqueue(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, 
     a.sigma = sigma;
     a.work_counter = counter;
     a.chunk = (int32_t)std::min<size_t>(batch_chunk_rows(k), std::max<size_t>(1, env_size("GUMAP_BATCH_CHUNK", 64)));
+    if (t && t->chunk > 0) a.chunk = std::min(t->chunk, batch_chunk_rows(k));
+    a.lanes = t ? t->lanes : 0;
     a.waves_per_block = 4;
-    int64_t maxb = partial_batch_max_blocks();
+    int64_t maxb = t && t->blocks > 0 ? t->blocks : partial_batch_max_blocks();
     int64_t want = (b->total_vertices + 4 * a.chunk - 1) / (4 * a.chunk);
     a.blocks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(maxb, want));
     hipError_t e = launch_batch_reset(counter, s);
@@ -725,6 +727,72 @@ int knn_partial_batch(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *ho
     return finish(s, "gumap_knn_partial_batch");
 }
 
+// Autotuner of the batch launch: times every (lanes per source, rows per
+// grab, grid size) candidate on the batch itself -- one warm-up launch, then
+// the mean of two -- and keeps the fastest.  Every candidate computes the same
+// rows, so the pick changes only the time.
+int tune_batch(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, float *w, float *rho, float *sigma,
+               hipStream_t s, BatchTune *best, gumap_batch_tuning *info)
+{
+    *best = BatchTune{};
+    info->lanes = 0;
+    info->chunk = 0;
+    info->blocks = 0;
+    info->candidates = 0;
+    info->best_ms = info->default_ms = 0.0f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_status(e, "tuning events");
+    auto time_one = [&](const BatchTune *t, float *ms) -> int {
+        int st = batch_enqueue(b, k, ids, hops, w, rho, sigma, s, t);
+        if (st) return st;
+        hipError_t x = hipEventRecord(e0, s);
+        for (int r = 0; r < 2 && x == hipSuccess && st == GUMAP_OK; ++r)
+            st = batch_enqueue(b, k, ids, hops, w, rho, sigma, s, t);
+        if (st) return st;
+        if (x == hipSuccess) x = hipEventRecord(e1, s);
+        if (x == hipSuccess) x = hipEventSynchronize(e1);
+        if (x == hipSuccess) x = hipEventElapsedTime(ms, e0, e1);
+        if (x != hipSuccess) return hip_status(x, "tuning launch");
+        *ms *= 0.5f;
+        return GUMAP_OK;
+    };
+    int st = time_one(nullptr, &info->default_ms);
+    float best_ms = info->default_ms;
+    int32_t lane_opts[4];
+    const int nl = partial_lane_options(k, lane_opts);
+    const int32_t maxb = partial_batch_max_blocks();
+    const int32_t chunk_max = batch_chunk_rows(k);
+    for (int li = 0; li < nl && st == GUMAP_OK; ++li) {
+        for (int32_t chunk : {16, 32, 64}) {
+            if (chunk > chunk_max && chunk != 16) continue;
+            for (int32_t blocks : {maxb / 2, maxb}) {
+                BatchTune t;
+                t.lanes = lane_opts[li];
+                t.chunk = std::min(chunk, chunk_max);
+                t.blocks = std::max(1, blocks);
+                float ms = 0.0f;
+                if ((st = time_one(&t, &ms))) break;
+                ++info->candidates;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    *best = t;
+                }
+            }
+            if (st) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    info->best_ms = best_ms;
+    info->lanes = best->lanes;
+    info->chunk = best->chunk;
+    info->blocks = best->blocks;
+    return GUMAP_OK;
+}
+
 }  // namespace gm
 
 // ================================================================ C-ABI ===
@@ -733,6 +801,7 @@ struct gumap_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int64_t rows = 0;
+    gumap_batch_tuning tuning{};
 };
 
 extern "C" {
@@ -801,6 +870,13 @@ int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, u
     if ((st = gm::scratch_get(gm::kSlotCounter, 256, (void **)&counter))) return st;
     gumap_batch_plan *p = new gumap_batch_plan();
     p->rows = b->total_vertices;
+    gm::BatchTune tune;
+    if (b->total_vertices > 0 && gm::env_size("GUMAP_PLAN_TUNE", 1) != 0) {
+        if ((st = gm::tune_batch(&cb, k, nbr_ids, nbr_hops, weights, rho, sigma, stream, &tune, &p->tuning))) {
+            delete p;
+            return st;
+        }
+    }
     hipStream_t cap = nullptr;
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -809,7 +885,7 @@ int gumap_batch_plan_create(const gumap_batch *b, int32_t k, int32_t *nbr_ids, u
     }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = gm::batch_enqueue(&cb, k, nbr_ids, nbr_hops, weights, rho, sigma, cap);
+        st = gm::batch_enqueue(&cb, k, nbr_ids, nbr_hops, weights, rho, sigma, cap, &tune);
         hipError_t e2 = hipStreamEndCapture(cap, &p->graph);
         if (st == GUMAP_OK && e2 != hipSuccess) st = gm::hip_status(e2, "end capture");
     } else {
@@ -839,6 +915,14 @@ int gumap_batch_plan_launch(gumap_batch_plan *plan, hipStream_t stream)
     hipError_t e = hipGraphLaunch(plan->exec, stream);
     if (e != hipSuccess) return gm::hip_status(e, "graph launch");
     return gm::finish(stream, "gumap_batch_plan_launch");
+}
+
+int gumap_batch_plan_tuning(const gumap_batch_plan *plan, gumap_batch_tuning *out)
+{
+    gm::clear_error();
+    if (!plan || !out) return gm::set_error(GUMAP_EINVAL, "NULL argument");
+    *out = plan->tuning;
+    return GUMAP_OK;
 }
 
 void gumap_batch_plan_destroy(gumap_batch_plan *plan)

@@ -134,11 +134,15 @@ struct BatchArgs {
     int32_t chunk;            // vertices taken per grab (<= batch_chunk_rows(k))
     int32_t waves_per_block;
     int32_t blocks;
+    int32_t lanes;            // lanes per source: 16, 32 or 64 (k + 1 <= lanes), -1 a wave with LDS state, 0 automatic
 };
 hipError_t launch_batch_reset(unsigned long long *counter, hipStream_t s);
 hipError_t launch_partial_batch(const BatchArgs &a, hipStream_t s);
 // Largest chunk (rows per grab) the batch/jobs kernels accept for this k.
 int batch_chunk_rows(int k);
+// Lanes-per-source settings valid for this k (16, 32, 64 where k + 1 fits, and
+// -1 for the LDS form); returns how many were written to out (at most 4).
+int partial_lane_options(int k, int32_t *out);
 
 // Served form: resident jobs and the chunks of rows of one device iteration.
 struct DevJob {

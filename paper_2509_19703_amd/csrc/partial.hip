@@ -450,11 +450,22 @@ int batch_chunk_rows(int k)
 #define GM_BATCH_LAUNCH(NQ_, ROW_) \
     hipLaunchKernelGGL((partial_batch_kernel<NQ_, ROW_>), dim3(a.blocks), dim3(kPartialWaves * GM_WAVE), 0, s, a)
 
+int partial_lane_options(int k, int32_t *out)
+{
+    int c = 0;
+    for (int l : {16, 32, 64})
+        if (k + 1 <= l) out[c++] = l;
+    out[c++] = -1;
+    return c;
+}
+
 hipError_t launch_partial_batch(const BatchArgs &a, hipStream_t s)
 {
     if (a.total_vertices <= 0) return hipSuccess;
     if (a.chunk < 1 || a.chunk > batch_chunk_rows(a.k)) return hipErrorInvalidValue;
-    const int lanes = lanes_for(a.k);
+    if (a.lanes > 0 && (a.k + 1 > a.lanes || (a.lanes != 16 && a.lanes != 32 && a.lanes != 64)))
+        return hipErrorInvalidValue;
+    const int lanes = a.lanes == 0 ? lanes_for(a.k) : (a.lanes < 0 ? 0 : a.lanes);
     if (lanes == 16) GM_BATCH_LAUNCH(1, 16);
     else if (lanes == 32) GM_BATCH_LAUNCH(1, 32);
     else if (lanes == 64) GM_BATCH_LAUNCH(1, 64);

@@ -58,9 +58,14 @@ int check_k(int32_t k);
 int prepare_graph(const gumap_graph *g, hipStream_t s, CanonCsr *out);
 int check_batch_args(const gumap_batch *b, int32_t k);
 int prepare_batch(const gumap_batch *b, hipStream_t s, gumap_batch *out);
+// Launch configuration of the batch kernel; zero fields take the defaults.
+struct BatchTune {
+    int32_t lanes = 0, chunk = 0, blocks = 0;
+};
 // Enqueues the batched partial BFS (+ membership when w != NULL) of a
-// canonical packed batch; no synchronisation.
+// canonical packed batch with configuration t (NULL: defaults); no
+// synchronisation.
 int batch_enqueue(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, float *w, float *rho,
-                  float *sigma, hipStream_t s);
+                  float *sigma, hipStream_t s, const BatchTune *t = nullptr);
 
 }  // namespace gm

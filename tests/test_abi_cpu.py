@@ -27,6 +27,7 @@ def test_library_exports_every_declared_symbol(gumap):
 def test_struct_layouts_match_header(gumap):
     assert ctypes.sizeof(gumap.gumap_graph) == 32
     assert ctypes.sizeof(gumap.gumap_batch) == 64
+    assert ctypes.sizeof(gumap.gumap_batch_tuning) == 24
 
 
 def test_host_side_argument_errors(gumap):
@@ -62,6 +63,7 @@ def test_host_side_argument_errors(gumap):
     unsorted = gumap.gumap_batch(0, 0, 0, None, None, None, None, 0)
     assert lib.gumap_batch_plan_create(ctypes.byref(unsorted), 5, None, None, None, None, None, None,
                                        ctypes.byref(plan)) == gumap.EINVAL
+    assert lib.gumap_batch_plan_tuning(None, None) == gumap.EINVAL
 
 
 def test_python_names_mirror_c_entry_points(gumap):

@@ -98,6 +98,43 @@ def test_plan_replays_match_plain(gumap):
     plan.close()
 
 
+@pytest.mark.parametrize("k", [15, 40])
+def test_plan_autotuner_pick_is_valid(gumap, k):
+    """The tuner times every candidate on the batch; its pick is a valid
+    configuration, no slower than the defaults, and the plan built with it
+    gives the oracle's rows."""
+    graphs = _mix(30, n_hi=3000, seed=G.BASE_SEED + 57 + k)
+    pb = gumap.PackedBatch(graphs)
+    plan = gumap.BatchPlan(pb, k)
+    t = plan.tuning()
+    valid_lanes = [l for l in (16, 32, 64) if k + 1 <= l] + [-1, 0]
+    assert t["lanes"] in valid_lanes
+    assert t["candidates"] >= 2 * len(valid_lanes) - 2
+    assert 0 < t["best_ms"] <= t["default_ms"]
+    ids, hops, w, rho, sigma = [x.cpu().numpy() for x in plan.launch()]
+    plan.close()
+    off = 0
+    for g in graphs:
+        oi, oh = O.knn_partial(g, k)
+        assert np.array_equal(ids[off:off + g.n], oi) and np.array_equal(hops[off:off + g.n], oh)
+        ow, orho, osig = O.membership(oh)
+        assert_weights_close(w[off:off + g.n], ow, rho[off:off + g.n], orho, sigma[off:off + g.n], osig)
+        off += g.n
+
+
+@pytest.mark.parametrize("lanes,chunk", [("16", "16"), ("32", "64"), ("64", "32"), ("0", "8")])
+def test_batch_launch_shape_invariance(gumap, monkeypatch, lanes, chunk):
+    """Lanes per source and rows per grab change only the speed."""
+    graphs = _mix(24, n_hi=2000, seed=G.BASE_SEED + 59)
+    pb = gumap.PackedBatch(graphs)
+    ref = [t.cpu().numpy() for t in gumap.knn_partial_batch(pb, 15)]
+    monkeypatch.setenv("GUMAP_PARTIAL_LANES", lanes)
+    monkeypatch.setenv("GUMAP_BATCH_CHUNK", chunk)
+    got = [t.cpu().numpy() for t in gumap.knn_partial_batch(pb, 15)]
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
 def test_server_results_match_oracle_and_alone(gumap):
     jobs = G.config_stream_jobs(24, n_lo=200, n_hi=6000, d_lo=4, d_hi=40)
     graphs = [G.stream_job_graph(j) for j in jobs]
