@@ -2,7 +2,8 @@
 
 Plain, slow, obviously correct CPU statement of the BFS kNN construction of
 arXiv 2509.19703 (GUMAP steps C0/C1 of Alg. 1, PartialBFS of Alg. 4 in
-Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1).  Only ``tests/``,
+Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1) and of the drawing
+quality metrics of Sec. 5.1 computed on the same BFS.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
 it.  It shares no code with the GPU library and the GPU library never calls
 it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
@@ -46,7 +47,9 @@ def _load():
         lib.oracle_knn_build.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, vp, ctypes.c_int]
         lib.oracle_knn_partial.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, ctypes.c_int]
         lib.oracle_membership.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.c_int]
-        for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership):
+        lib.oracle_stress.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
+        for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership,
+                  lib.oracle_stress):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -128,3 +131,26 @@ def membership(hops: np.ndarray, k: int | None = None, threads: int | None = Non
     if st:
         raise OracleError(st)
     return w, rho, sigma
+
+
+def stress_rows(g, xy: np.ndarray, sources=None, threads: int | None = None):
+    """Per-source stress sums and pair counts (Sec. 5.1 aggregated stress).
+
+    ``xy`` is float32 [n, 2].  Returns ``(row_sum float64[rows], row_pairs int64[rows])``."""
+    rp, ci = _csr(g)
+    xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(g.n, 2)
+    src = None if sources is None else np.ascontiguousarray(sources, dtype=np.int32)
+    rows = g.n if src is None else int(src.shape[0])
+    row_sum = np.empty(rows, dtype=np.float64)
+    row_pairs = np.empty(rows, dtype=np.int64)
+    st = _load().oracle_stress(g.n, _ptr(rp), _ptr(ci), _ptr(xy), _ptr(src), rows, _ptr(row_sum),
+                               _ptr(row_pairs), int(threads or default_threads()))
+    if st:
+        raise OracleError(st)
+    return row_sum, row_pairs
+
+
+def stress(g, xy: np.ndarray, sources=None, threads: int | None = None):
+    """Aggregated stress: ``(sum, pairs)``; the metric is ``sum / pairs``."""
+    row_sum, row_pairs = stress_rows(g, xy, sources, threads)
+    return float(row_sum.sum()), int(row_pairs.sum())

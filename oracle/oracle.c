@@ -15,6 +15,8 @@
  *                        other vertices (Sec. 3.3.1, Alg. 4 PartialBFS)
  *   oracle_membership    UMAP fuzzy membership rho, sigma and weights in FP64
  *                        (Sec. 2.1, high-dimensional similarity h_ij)
+ *   oracle_stress        aggregated stress of a drawing against hop
+ *                        distances (Sec. 5.1, quality metrics)
  *
  * Readings where the paper is silent or garbled (each is listed with its
  * justification in the design notes):
@@ -30,7 +32,12 @@
  *   - h_ij = exp(-(d_ij - rho_i) / sigma_i) (the printed sign is a typo) with
  *     sigma_i solving sum_j h_ij = log2(k) over the row's valid entries, k the
  *     requested neighbourhood size; rows with no root take the limits
- *     described at oracle_membership.
+ *     described at oracle_membership;
+ *   - stress sums over ordered pairs of distinct vertices that are connected
+ *     (the paper evaluates on connected graphs, where these are all n^2 - n
+ *     pairs), the graph distance being the hop count, the drawing distance
+ *     the Euclidean one in FP64 of float coordinates; the sum and the number
+ *     of pairs are returned, stress = sum / pairs.
  *
  * Threads: rows are independent; `nthreads` worker threads take rows from a
  * shared counter.  This parallelism does not change any result.
@@ -390,4 +397,54 @@ int oracle_membership(int64_t rows, int32_t k, const uint8_t *hops, float *weigh
     if (rows < 0 || k < 1 || !hops || !weights) return ORACLE_EINVAL;
     memb_job j = {k, hops, weights, rho, sigma};
     return run_rows(rows, nthreads, &j, memb_row, 0);
+}
+
+/* ------------------------------------------------------------------------
+ * Aggregated stress (Sec. 5.1): for each listed source s and every vertex
+ * v != s reachable from s, ((d(s,v) - |X_s - X_v|) / d(s,v))^2, with d the
+ * BFS hop distance and |.| the Euclidean distance of the drawing (xy holds
+ * x, y per vertex as float; the arithmetic is FP64).  Per-source sums and
+ * pair counts go to row_sum[r] / row_pairs[r]; the caller adds them up.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n;
+    const int32_t *row_ptr, *col_idx, *src;
+    const float *xy;
+    double *row_sum;
+    int64_t *row_pairs;
+} stress_job_t;
+
+static int stress_row(void *jp, int64_t r, void *scratch)
+{
+    stress_job_t *j = (stress_job_t *)jp;
+    int32_t *dist = (int32_t *)scratch;
+    const int32_t s = j->src ? j->src[r] : (int32_t)r;
+    int st = oracle_bfs_dist(j->n, j->row_ptr, j->col_idx, s, dist);
+    if (st != ORACLE_OK) return st;
+    double sum = 0.0;
+    int64_t pairs = 0;
+    const double xs = (double)j->xy[2 * (size_t)s], ys = (double)j->xy[2 * (size_t)s + 1];
+    for (int32_t v = 0; v < j->n; ++v) {
+        if (v == s || dist[v] < 0) continue;
+        const double dx = xs - (double)j->xy[2 * (size_t)v];
+        const double dy = ys - (double)j->xy[2 * (size_t)v + 1];
+        const double e = sqrt(dx * dx + dy * dy);
+        const double d = (double)dist[v];
+        const double t = (d - e) / d;
+        sum += t * t;
+        ++pairs;
+    }
+    j->row_sum[r] = sum;
+    j->row_pairs[r] = pairs;
+    return ORACLE_OK;
+}
+
+int oracle_stress(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const float *xy,
+                  const int32_t *sources, int64_t rows, double *row_sum, int64_t *row_pairs, int nthreads)
+{
+    if (n < 0 || rows < 0) return ORACLE_EINVAL;
+    for (int64_t r = 0; sources && r < rows; ++r)
+        if (sources[r] < 0 || sources[r] >= n) return ORACLE_EINVAL;
+    stress_job_t j = {n, row_ptr, col_idx, sources, xy, row_sum, row_pairs};
+    return run_rows(rows, nthreads, &j, stress_row, (size_t)(n > 0 ? n : 1) * sizeof(int32_t));
 }

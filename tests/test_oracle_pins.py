@@ -424,3 +424,84 @@ def test_hand_worked_example():
             assert rho[0] == 1.0
             assert abs(sigma[0] - gv["k%d_sigma" % k][0]) <= 1e-6 * max(1.0, gv["k%d_sigma" % k][0])
             assert np.allclose(w[0], gv["k%d_weights" % k], rtol=1e-6, atol=0)
+
+
+# ----------------------------------------------------- stress (Sec. 5.1) --
+
+def _line_layout(n, scale=1.0):
+    return np.stack([scale * np.arange(n), np.zeros(n)], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("c", [1.0, 2.0, 0.5, 0.25])
+def test_stress_scaled_path_closed_form(c):
+    """A path drawn on a line with spacing c: every pair contributes
+    ((d - c d) / d)^2 = (1 - c)^2, over all n(n-1) ordered pairs."""
+    n = 37
+    s, pairs = O.stress(G.path(n), _line_layout(n, c))
+    assert pairs == n * (n - 1)
+    assert s == pytest.approx((1 - c) ** 2 * pairs, rel=1e-12, abs=1e-12)
+
+
+def test_stress_collapsed_complete_graph():
+    """Every vertex at one point: each pair at hop 1 contributes 1."""
+    n = 12
+    s, pairs = O.stress(G.complete(n), np.zeros((n, 2), dtype=np.float32))
+    assert pairs == n * (n - 1) and s == pytest.approx(pairs, rel=1e-15)
+
+
+def test_stress_grid_in_its_own_coordinates():
+    """Grid drawn at its lattice points: hop distance |dx| + |dy| against the
+    Euclidean sqrt(dx^2 + dy^2), summed over the (w - |dx|)(h - |dy|) ordered
+    pairs with each offset."""
+    w, h = 9, 6
+    g = G.grid_2d(h, w)   # h rows of w columns, id = row * w + column
+    xy = np.array([[v % w, v // w] for v in range(g.n)], dtype=np.float32)
+    expect = 0.0
+    for dx in range(-(w - 1), w):
+        for dy in range(-(h - 1), h):
+            if dx == 0 and dy == 0:
+                continue
+            d = abs(dx) + abs(dy)
+            e = math.hypot(dx, dy)
+            expect += (w - abs(dx)) * (h - abs(dy)) * ((d - e) / d) ** 2
+    s, pairs = O.stress(g, xy)
+    assert pairs == g.n * (g.n - 1)
+    assert s == pytest.approx(expect, rel=1e-12)
+
+
+def test_stress_disconnected_pairs_and_sources():
+    """Only connected pairs count; a source subset sums its own rows."""
+    a, b = G.path(7), G.cycle(5)
+    g = G.disjoint_union([a, b])
+    rng = np.random.default_rng(3)
+    xy = rng.normal(size=(g.n, 2)).astype(np.float32)
+    s, pairs = O.stress(g, xy)
+    sa, pa = O.stress(a, xy[:7])
+    sb, pb = O.stress(b, xy[7:])
+    assert pairs == 7 * 6 + 5 * 4 == pa + pb
+    assert s == pytest.approx(sa + sb, rel=1e-12)
+    rows, rpairs = O.stress_rows(g, xy)
+    src = np.array([0, 3, 9, 3], dtype=np.int32)
+    s2, p2 = O.stress(g, xy, sources=src)
+    assert p2 == int(rpairs[src].sum()) and s2 == pytest.approx(float(rows[src].sum()), rel=1e-12)
+
+
+def test_stress_brute_force_tiny_graphs():
+    """Floyd-Warshall distances and the metric written out pair by pair."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    for seed in range(5):
+        g = G.tiny_random(14, 0.25, seed)
+        rng = np.random.default_rng(100 + seed)
+        xy = (rng.random((g.n, 2)) * 5).astype(np.float32)
+        adj = csr_matrix((np.ones(len(g.col_idx)), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+        d = shortest_path(adj, unweighted=True, directed=False)
+        tot, cnt = 0.0, 0
+        for i in range(g.n):
+            for j in range(g.n):
+                if i != j and np.isfinite(d[i, j]):
+                    e = math.dist(xy[i].astype(np.float64), xy[j].astype(np.float64))
+                    tot += ((d[i, j] - e) / d[i, j]) ** 2
+                    cnt += 1
+        s, pairs = O.stress(g, xy)
+        assert pairs == cnt and s == pytest.approx(tot, rel=1e-12, abs=1e-12)
