@@ -77,11 +77,21 @@ hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_o
                              const int64_t *slot_row, int64_t row_stride, hipStream_t s);
 // Same, also writing per-slot counts of vertices at hops 1..16, one partial
 // count per block of vertex tiles: part[(local_slot * chunks + c) * 16 + h - 1]
-// with chunks = msbfs_hop_chunks(n).
-int msbfs_hop_chunks(int32_t n);
+// with chunks = msbfs_hop_chunks(n, groups).
+int msbfs_hop_chunks(int32_t n, int32_t groups);
 hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                                      const int64_t *slot_row, int64_t row_stride,
                                      unsigned int *part, hipStream_t s);
+// Aggregated stress of a drawing over the round's hop rows, fused into the
+// transpose (no rows written): per (local slot, block c) the FP64 sum of
+// ((h - |X_s - X_v|) / h)^2 over v with 1 <= h <= 254 and the number of such
+// v, at [local_slot * chunks + c] with chunks = msbfs_hop_chunks(n, groups).
+struct StressArgs {
+    const float2 *xy;          // drawing, one (x, y) per vertex
+    double *part_sum;
+    unsigned int *part_pairs;
+};
+hipError_t launch_msbfs_stress(const MsbfsArgs &a, int planes_used, const StressArgs &sa, hipStream_t s);
 
 // ------------------------------------------------------- kNN selection ---
 // Rows: for r in [0, rows): hop row hop_rows + row_of[r] * row_stride (n bytes),

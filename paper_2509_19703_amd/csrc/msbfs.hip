@@ -20,6 +20,7 @@
 // 1..16 (used by the kNN selection to find its last level without a
 // separate pass).
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
 #include "kernels.h"
@@ -32,7 +33,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevelBlock = 256;
 constexpr int kFullCheckLevels = 32;  // levels up to which a finished group is detected
-constexpr int kHopTilesPerWave = 16;
 constexpr int kCountLevels = 16;
 constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
 constexpr int kStatFields = 4;
@@ -279,7 +279,7 @@ __device__ __forceinline__ uint64_t spread8(uint64_t bits8)
 
 // Block: one wave per word of a group, all on the same vertex tiles, so the
 // waves of a block together read whole 64-byte state rows.  Wave w walks
-// kHopTilesPerWave tiles of 64 vertices; lane j ends with the hop bytes of
+// the block's share of the 64-vertex tiles; lane j ends with the hop bytes of
 // slot (group, w, j) for the tile and writes them (64 bytes) to its row.
 // Per-slot counts of vertices at hops 1..16 are written per block (no
 // atomics) to part[(slot * chunks + block) * 16 + h - 1].
@@ -301,9 +301,9 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
     for (int h = 0; h < kCountLevels; ++h) cnt[h] = 0;
 
     // tiles of 64 vertices, STEP at a time: each lane then writes 64 * STEP
-    // contiguous bytes of its row per step
-    const int32_t t_begin = blockIdx.x * kHopTilesPerWave;
-    const int32_t t_end = min(ntiles, t_begin + kHopTilesPerWave);
+    // contiguous bytes of its row per step; block x of a group takes tiles [x * ntiles / chunks, (x + 1) * ntiles / chunks)
+    const int32_t t_begin = (int32_t)((int64_t)blockIdx.x * ntiles / gridDim.x);
+    const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     for (int32_t tile = t_begin; tile < t_end; tile += STEP) {
         uint64_t outw[STEP][8];
 #pragma unroll
@@ -365,17 +365,164 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
     }
 }
 
+// The same transpose with the stores staged in LDS: each wave leaves the hop
+// bytes of its 64 sources for TILES 64-vertex tiles (64 * TILES bytes per
+// source) in LDS, and the whole block then writes the rows out as whole
+// segments (8 * TILES threads per row), instead of 16 bytes into 64
+// different rows per store.  Needs rows aligned to 8 * TILES bytes.
+// With STRESS the staged bytes are not stored: each row's stress terms
+// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 5.1) are summed in
+// FP64 instead, one partial sum and pair count per (slot, block).
+template <int WORDS, int TILES, bool STRESS>
+__global__ void __launch_bounds__(WORDS * GM_WAVE)
+msbfs_hops_staged_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
+                         const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part,
+                         StressArgs sa)
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    constexpr int ROWS = WORDS * GM_WAVE;        // sources of the group = rows staged
+    constexpr int SEG = 64 * TILES;              // bytes per row per step
+    constexpr int UNIT = 8 * TILES;              // bytes per store: 8 or 16
+    constexpr int PITCH = SEG + UNIT;            // padded against bank conflicts, UNIT-aligned
+    typedef typename std::conditional<TILES == 2, u32x4, uint64_t>::type unit_t;
+    __shared__ __align__(16) uint8_t stage[ROWS * PITCH];
+    __shared__ int64_t row_base[ROWS];
+    const int w = threadIdx.x / GM_WAVE, l = lane();
+    const int32_t g = blockIdx.y;
+    const int32_t local_slot = g * ROWS + 64 * w + l;
+    const bool slot_ok = local_slot < a.n_slots;
+    // store / stress rows of this thread: r = threadIdx.x / 8 + it * ROWS / 8
+    constexpr int ITS = 8;
+    double st_sum[ITS];
+    unsigned int st_cnt[ITS];
+    float2 st_xy[ITS];
+    if (STRESS) {
+#pragma unroll
+        for (int it = 0; it < ITS; ++it) {
+            st_sum[it] = 0.0;
+            st_cnt[it] = 0;
+            const int32_t ls = g * ROWS + (threadIdx.x >> 3) + it * (ROWS >> 3);
+            st_xy[it] = ls < a.n_slots ? sa.xy[a.usrc[a.slot0 + ls]] : make_float2(0.0f, 0.0f);
+        }
+    } else {
+        row_base[threadIdx.x] = slot_ok ? slot_row[local_slot] * row_stride : -1;
+    }
+    const int32_t ntiles = (a.n + 63) / 64;
+    const size_t gbase = (size_t)g * a.n * WORDS + w;
+    unsigned int cnt[kCountLevels];
+#pragma unroll
+    for (int h = 0; h < kCountLevels; ++h) cnt[h] = 0;
+    // block x of a group takes tiles [x * ntiles / chunks, (x + 1) * ntiles / chunks)
+    const int32_t t_begin = (int32_t)((int64_t)blockIdx.x * ntiles / gridDim.x);
+    const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
+    for (int32_t tile = t_begin; tile < t_end; tile += TILES) {
+#pragma unroll
+        for (int half = 0; half < TILES; ++half) {
+            const int32_t v = (tile + half) * 64 + l;
+            const bool in = v < a.n && tile + half < t_end;
+            const size_t me = gbase + ((size_t)v << LW);
+            uint64_t vis = in ? a.visited[me] : 0ull;
+            uint64_t pl[8];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) pl[b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
+            vis = transpose64(vis);
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b < planes_used) pl[b] = transpose64(pl[b]);
+            uint64_t high = 0;
+#pragma unroll
+            for (int b = 5; b < 8; ++b) high |= pl[b];
+            const uint64_t low_ok = vis & ~high;
+#pragma unroll
+            for (int h = 1; h <= kCountLevels; ++h) {
+                uint64_t m = low_ok;
+#pragma unroll
+                for (int b = 0; b < 5; ++b) m &= ((h >> b) & 1) ? pl[b] : ~pl[b];
+                cnt[h - 1] += __popcll(m);
+            }
+            uint64_t *dst = (uint64_t *)(stage + (size_t)(64 * w + l) * PITCH + 64 * half);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                uint64_t by = spread8(~vis >> (8 * c)) * 0xFFull;
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (b < planes_used) by |= spread8(pl[b] >> (8 * c)) << b;
+                dst[c] = by;
+            }
+        }
+        __syncthreads();
+        // rows out: 8 threads per row, UNIT bytes each
+        const int32_t v0 = tile * 64;
+        const int valid = min(SEG, min(a.n - v0, (t_end - tile) * 64));
+#pragma unroll
+        for (int it = 0; it < ITS; ++it) {
+            const int q = threadIdx.x + it * ROWS;
+            const int r = q >> 3, off = (q & 7) * UNIT;
+            const uint8_t *src = stage + (size_t)r * PITCH + off;
+            if (STRESS) {
+                if (g * ROWS + r >= a.n_slots) continue;
+                const double xs = (double)st_xy[it].x, ys = (double)st_xy[it].y;
+                for (int i = 0; i < UNIT && off + i < valid; ++i) {
+                    const int h = src[i];
+                    if (h == 0 || h == 255) continue;
+                    const float2 p = sa.xy[v0 + off + i];
+                    const double dx = xs - (double)p.x, dy = ys - (double)p.y;
+                    const double d = (double)h;
+                    const double t = (d - sqrt(dx * dx + dy * dy)) / d;
+                    st_sum[it] += t * t;
+                    st_cnt[it] += 1;
+                }
+            } else {
+                const int64_t base = row_base[r];
+                if (base < 0 || off >= valid) continue;
+                uint8_t *dstp = hop_out + base + v0 + off;
+                if (off + UNIT <= valid) {
+                    *(unit_t *)dstp = *(const unit_t *)src;
+                } else {
+                    for (int i = 0; off + i < valid; ++i) dstp[i] = src[i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (STRESS) {
+        // the 8 threads of a row are adjacent lanes: reduce, then one writes
+#pragma unroll
+        for (int it = 0; it < ITS; ++it) {
+            double v = st_sum[it];
+            unsigned int c = st_cnt[it];
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                v += __shfl_xor(v, o, GM_WAVE);
+                c += __shfl_xor(c, o, GM_WAVE);
+            }
+            const int32_t ls = g * ROWS + (threadIdx.x >> 3) + it * (ROWS >> 3);
+            if ((threadIdx.x & 7) == 0 && ls < a.n_slots) {
+                sa.part_sum[(size_t)ls * gridDim.x + blockIdx.x] = v;
+                sa.part_pairs[(size_t)ls * gridDim.x + blockIdx.x] = c;
+            }
+        }
+    } else if (part && slot_ok) {
+        uint4 *p = (uint4 *)(part + ((size_t)local_slot * gridDim.x + blockIdx.x) * kCountLevels);
+#pragma unroll
+        for (int q = 0; q < kCountLevels / 4; ++q) p[q] = make_uint4(cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]);
+    }
+}
+
 template <int WORDS>
 hipError_t launch_hops_words(dim3 grid, int variant, const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                              const int64_t *slot_row, int64_t row_stride, unsigned int *part, hipStream_t s)
 {
     dim3 block(WORDS * GM_WAVE);
-    if (variant == 1)
-        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+    const bool a16 = (row_stride % 16) == 0 && (((uintptr_t)hop_out) & 15) == 0;
+    const bool a8 = (row_stride % 8) == 0 && (((uintptr_t)hop_out) & 7) == 0;
+    const StressArgs none{};
+    if (variant == 0 && a16)
+        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+    else if ((variant == 0 || variant == 3) && a8)
+        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 1, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
     else if (variant == 2)
-        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, true>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
-    else if (variant == 3)
-        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 1, true>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
+        hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
     else
         hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 1, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
     return hipGetLastError();
@@ -430,13 +577,30 @@ int msbfs_heavy_degree(int32_t n, int32_t nnz)
     return (int)std::max<int64_t>(64, 8 * mean);
 }
 
-int msbfs_hop_chunks(int32_t n) { return ((n + 63) / 64 + kHopTilesPerWave - 1) / kHopTilesPerWave; }
+// Blocks per group of the hop-row transpose: about two resident blocks per
+// compute unit over all groups, each taking an equal share of the tiles (at
+// least two).
+int msbfs_hop_chunks(int32_t n, int32_t groups)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            (void)hipGetLastError();
+            cus = 256;
+        }
+    }
+    const int32_t ntiles = (n + 63) / 64;
+    const int32_t per_group = std::max(1, 2 * cus / std::max(1, groups));
+    return std::max(1, std::min(per_group, (ntiles + 1) / 2));
+}
 
 hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
                                      const int64_t *slot_row, int64_t row_stride,
                                      unsigned int *part, hipStream_t s)
 {
-    dim3 grid((unsigned)msbfs_hop_chunks(a.n), (unsigned)a.groups);
+    dim3 grid((unsigned)msbfs_hop_chunks(a.n, a.groups), (unsigned)a.groups);
     const int variant = a.hops_variant;
     switch (a.words) {
     case 1: return launch_hops_words<1>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
@@ -445,6 +609,19 @@ hipError_t launch_msbfs_hops_counted(const MsbfsArgs &a, int planes_used, uint8_
     case 8: return launch_hops_words<8>(grid, variant, a, planes_used, hop_out, slot_row, row_stride, part, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_msbfs_stress(const MsbfsArgs &a, int planes_used, const StressArgs &sa, hipStream_t s)
+{
+    dim3 grid((unsigned)msbfs_hop_chunks(a.n, a.groups), (unsigned)a.groups);
+    switch (a.words) {
+    case 1: hipLaunchKernelGGL((msbfs_hops_staged_kernel<1, 2, true>), grid, dim3(64), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
+    case 2: hipLaunchKernelGGL((msbfs_hops_staged_kernel<2, 2, true>), grid, dim3(128), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
+    case 4: hipLaunchKernelGGL((msbfs_hops_staged_kernel<4, 2, true>), grid, dim3(256), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
+    case 8: hipLaunchKernelGGL((msbfs_hops_staged_kernel<8, 2, true>), grid, dim3(512), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,
