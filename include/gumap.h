@@ -102,6 +102,26 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
                     int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream);
 
 /*
+ * Aggregated stress of a drawing (Sec. 5.1 quality metrics): the sum over
+ * ordered pairs (s, v), s in `sources` (every vertex when sources is NULL;
+ * a source listed twice counts twice) and v != s reachable from s, of
+ * ((d(s,v) - |X_s - X_v|) / d(s,v))^2, with d the hop distance of the graph
+ * and |.| the Euclidean distance of the drawing, computed in FP64, plus the
+ * number of such pairs.  The metric is *sum / *pairs (the paper's 1/(n^2-n)
+ * normalisation on a connected graph).  Runs the all-source BFS of
+ * gumap_knn_build and folds the terms into its hop-row pass; no hop rows are
+ * written.
+ *   xy       device float[2 * n]: x and y of vertex v at xy[2v], xy[2v + 1]
+ *   sources  device int32[n_sources] or NULL
+ *   sum      host double (out);  pairs  host int64 (out)
+ * Errors: GUMAP_EINVAL (NULL pointer, bad source id), GUMAP_EGRAPH (with
+ * GUMAP_VALIDATE), GUMAP_ERANGE (a finite hop distance above 254),
+ * GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_t n_sources,
+                 double *sum, int64_t *pairs, hipStream_t stream);
+
+/*
  * SL-/SSSL-GUMAP steps C0 + C1 (Sec. 3.3.1, Alg. 4 PartialBFS): for every
  * vertex v, a BFS that stops at the level completing k other vertices; the
  * row holds all earlier levels and the smallest ids of that last level.

@@ -96,6 +96,8 @@ def _load() -> ctypes.CDLL:
     lib.gumap_csr_canonicalize.restype = ctypes.c_int
     lib.gumap_knn_build.argtypes = [G, i32, vp, i32, vp, vp, vp, vp]
     lib.gumap_knn_partial.argtypes = [G, i32, vp, vp, vp]
+    lib.gumap_stress.argtypes = [G, vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]
+    lib.gumap_stress.restype = ctypes.c_int
     lib.gumap_membership.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     lib.gumap_knn_partial_batch.argtypes = [B, i32, vp, vp, vp, vp, vp, vp]
     lib.gumap_batch_plan_create.argtypes = [B, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -262,6 +264,25 @@ def knn_partial(row_ptr, col_idx, k: int, flags: int = 0, stream=None):
     hops = torch.empty((g.n, k), dtype=torch.uint8, device=dev)
     gumap_knn_partial(g, k, ids, hops, stream)
     return ids, hops
+
+
+def gumap_stress(g, xy, sources, n_sources, stream=None):
+    """C-ABI gumap_stress; returns (sum, pairs)."""
+    out_sum = ctypes.c_double(0.0)
+    out_pairs = ctypes.c_int64(0)
+    _check(lib.gumap_stress(ctypes.byref(g), _ptr(xy), _ptr(sources), int(n_sources), ctypes.byref(out_sum),
+                            ctypes.byref(out_pairs), _stream(stream)))
+    return out_sum.value, out_pairs.value
+
+
+def stress(row_ptr, col_idx, xy, sources=None, flags: int = 0, stream=None):
+    """Aggregated stress of the drawing xy (device float32 [n, 2]) over hop
+    distances.  Returns (sum, pairs); the metric is sum / pairs."""
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    if sources is not None and int(sources.shape[0]) == 0:
+        return 0.0, 0   # an empty list, not NULL (= every vertex)
+    n_src = 0 if sources is None else int(sources.shape[0])
+    return gumap_stress(g, xy.contiguous(), sources, n_src, stream)
 
 
 def membership(hops, stream=None):

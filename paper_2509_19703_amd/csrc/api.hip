@@ -248,8 +248,17 @@ int choose_words(int32_t n_uniq)
 
 }  // namespace
 
+// The all-source BFS in rounds of source groups, each round's hop rows going
+// to the kNN selection (and the hop matrix), or, with so, only into the
+// stress sums of a drawing.
+struct StressOut {
+    const float *xy = nullptr;
+    double sum = 0.0;
+    int64_t pairs = 0;
+};
+
 int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
-              int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s)
+              int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s, StressOut *so = nullptr)
 {
     int st;
     if ((st = check_graph_args(g))) return st;
@@ -257,7 +266,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     if (sources && n_sources < 0) return set_error(GUMAP_EINVAL, "n_sources < 0");
     const int32_t n = g->n;
     const int64_t rows = sources ? n_sources : n;
-    if (rows > 0 && (!ids || !hops)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (!so && rows > 0 && (!ids || !hops)) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    if (so && n > 0 && !so->xy) return set_error(GUMAP_EINVAL, "coordinates pointer is NULL");
     if (rows == 0) return GUMAP_OK;
     if (n == 0) return set_error(GUMAP_EINVAL, "source id outside [0, 0)");
 
@@ -265,6 +275,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     std::vector<int32_t> h_usrc;
     std::vector<int64_t> h_slot_row;
     std::vector<int64_t> dup_pairs;  // (dst row, src row)
+    std::vector<int32_t> h_mult;     // times each unique source is listed
     const bool all_sources = sources == nullptr;
     if (!all_sources) {
         std::vector<int32_t> h_src((size_t)rows);
@@ -283,9 +294,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if (!h_usrc.empty() && h_usrc.back() == h_src[r]) {
                 dup_pairs.push_back(r);
                 dup_pairs.push_back(h_slot_row.back());
+                ++h_mult.back();
             } else {
                 h_usrc.push_back(h_src[r]);
                 h_slot_row.push_back(r);
+                h_mult.push_back(1);
             }
         }
     }
@@ -320,11 +333,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const int words = choose_words(n_uniq);
     const int W = 64 * words;
     const int32_t groups_total = (n_uniq + W - 1) / W;
-    const int L_cap = hop_matrix ? 255 : k;
-    const int planes_alloc = hop_matrix ? 8 : bit_length(k);
+    const bool full_hops = hop_matrix != nullptr || so != nullptr;   // every finite hop <= 254 is needed
+    const int L_cap = full_hops ? 255 : k;
+    const int planes_alloc = full_hops ? 8 : bit_length(k);
     const size_t arr_per_group = (size_t)n * words;  // uint64 per array per group
     const size_t bytes_per_group = (3 + (size_t)planes_alloc) * arr_per_group * 8 +
-                                   (hop_matrix ? 0 : (size_t)W * n) + (size_t)W * msbfs_hop_chunks(n) * 16 * 4 +
+                                   (full_hops ? 0 : (size_t)W * n) + (size_t)W * msbfs_hop_chunks(n, 1) * 16 * 4 +
                                    (size_t)(L_cap + 2) * msbfs_stat_spread() * msbfs_stat_fields() * 8;
     const size_t budget = env_size("GUMAP_BFS_BUDGET_MB", 8192) << 20;
     int32_t groups_round = (int32_t)std::max<size_t>(1, std::min<size_t>(groups_total, budget / std::max<size_t>(1, bytes_per_group)));
@@ -340,10 +354,14 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const size_t arr_round = arr_per_group * groups_round;
     if ((st = scratch_get(kSlotBfsState, (3 + (size_t)planes_alloc) * arr_round * 8, (void **)&state))) return st;
     if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * stats_per_level * 8, (void **)&stats))) return st;
-    const int32_t hop_chunks = msbfs_hop_chunks(n);
-    if ((st = scratch_get(kSlotLvlCnt, (size_t)groups_round * W * hop_chunks * 16 * 4, (void **)&lvl_cnt))) return st;
+    // hop counts per (slot, transpose block); rounds with fewer groups use more blocks per group
+    const size_t lvl_cnt_bytes = std::max((size_t)groups_round * msbfs_hop_chunks(n, groups_round),
+                                          (size_t)((groups_total - 1) % groups_round + 1) *
+                                              msbfs_hop_chunks(n, (groups_total - 1) % groups_round + 1)) *
+                                 W * 16 * 4;
+    if ((st = scratch_get(kSlotLvlCnt, lvl_cnt_bytes, (void **)&lvl_cnt))) return st;
     if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
-    if (!hop_matrix) {
+    if (!full_hops) {
         if ((st = scratch_get(kSlotHopRows, (size_t)groups_round * W * n, (void **)&hop_scratch))) return st;
         if ((st = scratch_get(kSlotLocalRows, (size_t)groups_round * W * sizeof(int64_t), (void **)&local_rows))) return st;
         if ((e = iota_i64(local_rows, (int64_t)groups_round * W, 0, s)) != hipSuccess) return hip_status(e, "iota");
@@ -460,7 +478,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if (!any) {
                     done = true;
                     last_level = lv - 1;
-                } else if (hop_matrix && lv == 255) {
+                } else if (full_hops && lv == 255) {
                     range_error = true;
                     done = true;
                 }
@@ -486,6 +504,37 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (range_error)
             return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
         const int planes_used = bit_length(last_level);
+        if (so) {
+            // stress terms of this round's rows, fused into the transpose
+            const int32_t chunks = msbfs_hop_chunks(n, a.groups);
+            const size_t parts = (size_t)a.n_slots * chunks;
+            StressArgs sa;
+            sa.xy = (const float2 *)so->xy;
+            if ((st = scratch_get(kSlotStressSum, parts * sizeof(double), (void **)&sa.part_sum))) return st;
+            if ((st = scratch_get(kSlotStressPairs, parts * sizeof(unsigned int), (void **)&sa.part_pairs))) return st;
+            GM_PROF("msbfs_stress", (double)(planes_used + 1) * (double)arr * 8.0 + 8.0 * (double)n,
+                    launch_msbfs_stress(a, planes_used, sa, s));
+            if (e != hipSuccess) return hip_status(e, "stress");
+            std::vector<double> hsum(parts);
+            std::vector<unsigned int> hpairs(parts);
+            e = hipMemcpyAsync(hsum.data(), sa.part_sum, parts * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hpairs.data(), sa.part_pairs, parts * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_status(e, "stress sums");
+            for (int32_t ls = 0; ls < a.n_slots; ++ls) {
+                double rs = 0.0;
+                int64_t rp = 0;
+                for (int32_t c2 = 0; c2 < chunks; ++c2) {
+                    rs += hsum[(size_t)ls * chunks + c2];
+                    rp += hpairs[(size_t)ls * chunks + c2];
+                }
+                const int64_t m = all_sources ? 1 : h_mult[(size_t)a.slot0 + ls];
+                so->sum += rs * (double)m;
+                so->pairs += rp * m;
+            }
+            continue;
+        }
         uint8_t *hop_out = hop_matrix ? hop_matrix : hop_scratch;
         const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
         const double hop_bytes = (double)(planes_used + 1) * (double)arr * 8.0 + (double)a.n_slots * n;
@@ -494,14 +543,28 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e == hipSuccess)
             GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
                     launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                              slot_row + a.slot0, lvl_cnt, hop_chunks, ids, hops, s));
+                                              slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups), ids,
+                                              hops, s));
         if (e != hipSuccess) return hip_status(e, "hop rows / selection");
     }
-    if (!dup_pairs.empty()) {
+    if (!so && !dup_pairs.empty()) {
         e = launch_copy_rows((int32_t)(dup_pairs.size() / 2), dup_dev, k, n, ids, hops, hop_matrix, s);
         if (e != hipSuccess) return hip_status(e, "repeated sources");
     }
     return finish(s, "gumap_knn_build");
+}
+
+int stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_t n_sources, double *sum,
+           int64_t *pairs, hipStream_t s)
+{
+    if (!sum || !pairs) return set_error(GUMAP_EINVAL, "output pointer is NULL");
+    StressOut so;
+    so.xy = xy;
+    int st = knn_build(g, 1, sources, n_sources, nullptr, nullptr, nullptr, s, &so);
+    if (st) return st;
+    *sum = so.sum;
+    *pairs = so.pairs;
+    return GUMAP_OK;
 }
 
 // ------------------------------------------------------- canonical CSR --
@@ -822,6 +885,14 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
     return gm::settle(gm::knn_build(g, k, sources, n_sources, nbr_ids, nbr_hops, hop_matrix, stream), stream);
+}
+
+int gumap_stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_t n_sources, double *sum,
+                 int64_t *pairs, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::stress(g, xy, sources, n_sources, sum, pairs, stream), stream);
 }
 
 int gumap_knn_partial(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,

@@ -34,6 +34,8 @@ enum ScratchSlot {
     kSlotBatchCol,
     kSlotCounter,
     kSlotHeavy,
+    kSlotStressSum,
+    kSlotStressPairs,
     kScratchSlots
 };
 
