@@ -31,7 +31,7 @@ METRIC = "GTEPS + kNN graphs/sec vs plain; p50/p99 served latency, bit-exact"
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve"])
+    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress"])
     p.add_argument("--batch-graphs", type=int, default=2048)
     p.add_argument("--serve-jobs", type=int, default=1024)
     p.add_argument("--serve-pool", type=int, default=64)
@@ -75,6 +75,8 @@ def main():
         return bench_serve(args)
     if args.workload in ("grid", "er"):
         return bench_allsource(args)
+    if args.workload == "stress":
+        return bench_stress(args)
 
     if args.calibrate_copy:
         n_bytes = 1 << 30
@@ -272,6 +274,62 @@ def bench_allsource(args):
         t = t_b
         out["cpu_baseline"] = {"value": n * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
                                "sample": "oracle all-source BFS + kNN from %d of %d sources, scaled" % (len(sub), n)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_stress(args):
+    """Aggregated stress (Sec. 5.1) of a seeded random drawing of the BA graph
+    over all ordered vertex pairs: the all-source BFS from every vertex with
+    the stress terms folded into its hop-row pass."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    g = G.config_ba()
+    n, m = g.n, g.m
+    xy = (G.uniform(G.BASE_SEED + 300, 2 * n).reshape(n, 2) * 100.0).astype(np.float32)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    dxy = torch.from_numpy(xy).cuda()
+    gg = gm.make_graph(rp, ci, flags=gm.CSR_SORTED)
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def step():
+        res["v"] = gm.gumap_stress(gg, dxy, None, 0, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    dt, prof = _profiled(gm, step, steps)
+    roof, kms = _roofline(prof, steps)
+    total, pairs = res["v"]
+    out = {"metric": METRIC, "value": n * m / dt / 1e9, "unit": "GTEPS", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8+f64", "data": "synthetic",
+           "config": {"workload": "stress: BA n=%d m=%d, seeded uniform drawing in [0, 100)^2; aggregated stress "
+                                  "over all ordered pairs (all-source BFS, terms in FP64)" % (n, m),
+                      "n": n, "m": m},
+           "stress": total / pairs, "pairs": pairs, "pairs_per_s": pairs / dt,
+           "roofline": roof, "kernels_ms_per_step": kms}
+    if not args.no_parity:
+        import oracle as O
+        pick = G.sample_sources(n, 64, G.BASE_SEED + 301)
+        gs, gp = gm.gumap_stress(gg, dxy, torch.from_numpy(pick).cuda(), len(pick), stream)
+        os_, op = O.stress(g, xy, sources=pick)
+        out["parity_sampled_pairs_exact"] = bool(gp == op)
+        out["parity_sampled_sum_rel_diff"] = abs(gs - os_) / abs(os_)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        sub = G.sample_sources(n, 256, G.BASE_SEED + 302)
+        t0 = time.perf_counter()
+        O.stress(g, xy, sources=sub, threads=threads)
+        t = (time.perf_counter() - t0) * n / len(sub)
+        out["cpu_baseline"] = {"value": n * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+                               "sample": "oracle stress rows of 256 of the %d sources, scaled" % n}
     print(json.dumps(out), flush=True)
 
 

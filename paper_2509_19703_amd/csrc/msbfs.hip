@@ -396,7 +396,9 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop
     double st_sum[ITS];
     unsigned int st_cnt[ITS];
     float2 st_xy[ITS];
+    __shared__ double rinv[STRESS ? 256 : 1];   // 1 / h for the stress terms
     if (STRESS) {
+        for (int h = threadIdx.x; h < 256; h += blockDim.x) rinv[h] = h ? 1.0 / (double)h : 0.0;
 #pragma unroll
         for (int it = 0; it < ITS; ++it) {
             st_sum[it] = 0.0;
@@ -454,6 +456,14 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop
         // rows out: 8 threads per row, UNIT bytes each
         const int32_t v0 = tile * 64;
         const int valid = min(SEG, min(a.n - v0, (t_end - tile) * 64));
+        // a thread's UNIT vertices (offset (threadIdx.x & 7) * UNIT) are the
+        // same for all its rows: their coordinates are loaded once
+        float2 pv[STRESS ? UNIT : 1];
+        if (STRESS) {
+            const int off = (threadIdx.x & 7) * UNIT;
+#pragma unroll
+            for (int i = 0; i < UNIT; ++i) pv[i] = off + i < valid ? sa.xy[v0 + off + i] : make_float2(0.0f, 0.0f);
+        }
 #pragma unroll
         for (int it = 0; it < ITS; ++it) {
             const int q = threadIdx.x + it * ROWS;
@@ -462,13 +472,13 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop
             if (STRESS) {
                 if (g * ROWS + r >= a.n_slots) continue;
                 const double xs = (double)st_xy[it].x, ys = (double)st_xy[it].y;
-                for (int i = 0; i < UNIT && off + i < valid; ++i) {
+#pragma unroll
+                for (int i = 0; i < UNIT; ++i) {
                     const int h = src[i];
-                    if (h == 0 || h == 255) continue;
-                    const float2 p = sa.xy[v0 + off + i];
-                    const double dx = xs - (double)p.x, dy = ys - (double)p.y;
-                    const double d = (double)h;
-                    const double t = (d - sqrt(dx * dx + dy * dy)) / d;
+                    if (off + i >= valid || h == 0 || h == 255) continue;
+                    const double dx = xs - (double)pv[i].x, dy = ys - (double)pv[i].y;
+                    // (h - e) / h = 1 - e / h
+                    const double t = 1.0 - sqrt(dx * dx + dy * dy) * rinv[h];
                     st_sum[it] += t * t;
                     st_cnt[it] += 1;
                 }
