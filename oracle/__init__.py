@@ -48,8 +48,9 @@ def _load():
         lib.oracle_knn_partial.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, ctypes.c_int]
         lib.oracle_membership.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.c_int]
         lib.oracle_stress.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
+        lib.oracle_neighborhood.argtypes = [i32, vp, vp, vp, i32, vp, vp, ctypes.c_int]
         for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership,
-                  lib.oracle_stress):
+                  lib.oracle_stress, lib.oracle_neighborhood):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -154,3 +155,24 @@ def stress(g, xy: np.ndarray, sources=None, threads: int | None = None):
     """Aggregated stress: ``(sum, pairs)``; the metric is ``sum / pairs``."""
     row_sum, row_pairs = stress_rows(g, xy, sources, threads)
     return float(row_sum.sum()), int(row_pairs.sum())
+
+
+def neighborhood_scores(g, xy: np.ndarray, r: int = 2, threads: int | None = None):
+    """Per-vertex neighbourhood preservation (Sec. 5.1): ``(score float64[n]
+    (NaN where the graph ball is empty), ball int32[n])``."""
+    rp, ci = _csr(g)
+    xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(g.n, 2)
+    score = np.empty(g.n, dtype=np.float64)
+    ball = np.empty(g.n, dtype=np.int32)
+    st = _load().oracle_neighborhood(g.n, _ptr(rp), _ptr(ci), _ptr(xy), int(r), _ptr(score), _ptr(ball),
+                                     int(threads or default_threads()))
+    if st:
+        raise OracleError(st)
+    return score, ball
+
+
+def neighborhood_preservation(g, xy: np.ndarray, r: int = 2, threads: int | None = None):
+    """``(sum of defined scores, number of defined scores)``."""
+    score, _ = neighborhood_scores(g, xy, r, threads)
+    ok = ~np.isnan(score)
+    return float(score[ok].sum()), int(ok.sum())

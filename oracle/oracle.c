@@ -17,6 +17,8 @@
  *                        (Sec. 2.1, high-dimensional similarity h_ij)
  *   oracle_stress        aggregated stress of a drawing against hop
  *                        distances (Sec. 5.1, quality metrics)
+ *   oracle_neighborhood  neighbourhood preservation of a drawing, per vertex
+ *                        (Sec. 5.1, quality metrics)
  *
  * Readings where the paper is silent or garbled (each is listed with its
  * justification in the design notes):
@@ -37,7 +39,13 @@
  *     (the paper evaluates on connected graphs, where these are all n^2 - n
  *     pairs), the graph distance being the hop count, the drawing distance
  *     the Euclidean one in FP64 of float coordinates; the sum and the number
- *     of pairs are returned, stress = sum / pairs.
+ *     of pairs are returned, stress = sum / pairs;
+ *   - neighbourhood preservation: N_G(v, r) holds the vertices u != v at hop
+ *     distance 1..r; N_D(v, r) the |N_G(v, r)| vertices u != v nearest to v in
+ *     the drawing, ordered by squared Euclidean distance (FP64, computed as
+ *     dx*dx + dy*dy without fused multiply-add) and then by id; a vertex's
+ *     score is |N_G & N_D| / |N_G | N_D|, undefined (NaN) when N_G is empty;
+ *     the metric sums the defined scores.
  *
  * Threads: rows are independent; `nthreads` worker threads take rows from a
  * shared counter.  This parallelism does not change any result.
@@ -447,4 +455,77 @@ int oracle_stress(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, con
         if (sources[r] < 0 || sources[r] >= n) return ORACLE_EINVAL;
     stress_job_t j = {n, row_ptr, col_idx, sources, xy, row_sum, row_pairs};
     return run_rows(rows, nthreads, &j, stress_row, (size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+}
+
+/* ------------------------------------------------------------------------
+ * Neighbourhood preservation (Sec. 5.1): per vertex v, the Jaccard index of
+ * its graph ball N_G(v, r) (hops 1..r) and the same number of nearest
+ * vertices in the drawing, ranked by (squared distance, id).  score[v] is
+ * NaN when the ball is empty; ball[v] receives |N_G(v, r)|.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double d2;
+    int32_t id;
+} np_key_t;
+
+static int cmp_np_key(const void *a, const void *b)
+{
+    const np_key_t *x = (const np_key_t *)a, *y = (const np_key_t *)b;
+    if (x->d2 < y->d2) return -1;
+    if (x->d2 > y->d2) return 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+typedef struct {
+    int32_t n, r;
+    const int32_t *row_ptr, *col_idx;
+    const float *xy;
+    double *score;
+    int32_t *ball;
+} np_job_t;
+
+static int np_row(void *jp, int64_t row, void *scratch)
+{
+    np_job_t *j = (np_job_t *)jp;
+    const int32_t n = j->n, v = (int32_t)row;
+    int32_t *dist = (int32_t *)scratch;
+    np_key_t *keys = (np_key_t *)(dist + n);
+    char *in_ball = (char *)(keys + n);
+    int st = oracle_bfs_dist(n, j->row_ptr, j->col_idx, v, dist);
+    if (st != ORACLE_OK) return st;
+    int32_t K = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        in_ball[u] = (u != v && dist[u] >= 1 && dist[u] <= j->r);
+        K += in_ball[u];
+    }
+    j->ball[v] = K;
+    if (K == 0) {
+        j->score[v] = NAN;
+        return ORACLE_OK;
+    }
+    const double xv = (double)j->xy[2 * (size_t)v], yv = (double)j->xy[2 * (size_t)v + 1];
+    int32_t m = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        if (u == v) continue;
+        const double dx = (double)j->xy[2 * (size_t)u] - xv;
+        const double dy = (double)j->xy[2 * (size_t)u + 1] - yv;
+        const double sx = dx * dx, sy = dy * dy;
+        keys[m].d2 = sx + sy;
+        keys[m].id = u;
+        ++m;
+    }
+    qsort(keys, (size_t)m, sizeof(np_key_t), cmp_np_key);
+    int32_t common = 0;
+    for (int32_t i = 0; i < K; ++i) common += in_ball[keys[i].id];
+    j->score[v] = (double)common / (double)(2 * K - common);
+    return ORACLE_OK;
+}
+
+int oracle_neighborhood(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const float *xy, int32_t r,
+                        double *score, int32_t *ball, int nthreads)
+{
+    if (n < 0 || r < 1) return ORACLE_EINVAL;
+    np_job_t j = {n, r, row_ptr, col_idx, xy, score, ball};
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    return run_rows(n, nthreads, &j, np_row, nn * (sizeof(int32_t) + sizeof(np_key_t) + 1));
 }

@@ -505,3 +505,61 @@ def test_stress_brute_force_tiny_graphs():
                     cnt += 1
         s, pairs = O.stress(g, xy)
         assert pairs == cnt and s == pytest.approx(tot, rel=1e-12, abs=1e-12)
+
+
+# ---------------------------------------- neighbourhood preservation (Sec. 5.1) --
+
+def test_neighborhood_line_and_lattice_drawings_score_one():
+    """A path on a line and a grid at its lattice points keep every graph ball
+    (r = 1, 2) as the nearest points of the drawing, ties included whole."""
+    n = 23
+    s, c = O.neighborhood_preservation(G.path(n), np.stack([np.arange(n), np.zeros(n)], 1))
+    assert (s, c) == (float(n), n)
+    g = G.grid_2d(7, 11)
+    xy = np.array([[v % 11, v // 11] for v in range(g.n)], dtype=np.float32)
+    for r in (1, 2):
+        score, ball = O.neighborhood_scores(g, xy, r)
+        assert np.all(score == 1.0)
+        assert ball.max() == (4 if r == 1 else 12)
+
+
+def test_neighborhood_collapsed_cycle_tie_rule():
+    """Every vertex of C_n at one point: all distances tie, so N_D(v) is the K
+    smallest ids other than v; the score follows from the two sets."""
+    n = 12
+    score, ball = O.neighborhood_scores(G.cycle(n), np.zeros((n, 2), dtype=np.float32), 2)
+    for v in range(n):
+        ng = {(v + d) % n for d in (-2, -1, 1, 2)}
+        nd = set([u for u in range(n) if u != v][:4])
+        assert ball[v] == 4
+        assert score[v] == len(ng & nd) / len(ng | nd)
+
+
+def test_neighborhood_isolated_vertices_undefined():
+    g = G.disjoint_union([G.path(4), G.empty(3)])
+    xy = np.random.default_rng(0).random((g.n, 2)).astype(np.float32)
+    score, ball = O.neighborhood_scores(g, xy)
+    assert np.all(np.isnan(score[4:])) and np.all(ball[4:] == 0)
+    s, c = O.neighborhood_preservation(g, xy)
+    assert c == 4 and s == pytest.approx(float(score[:4].sum()))
+
+
+def test_neighborhood_brute_force_tiny_graphs():
+    """networkx balls and a lexicographic sort of (squared distance, id)."""
+    for seed in range(6):
+        g = G.tiny_random(25, 0.12, 300 + seed)
+        rng = np.random.default_rng(400 + seed)
+        xy = np.round(rng.random((g.n, 2)) * 4).astype(np.float32)   # many exact ties
+        nxg = to_nx(g)
+        score, ball = O.neighborhood_scores(g, xy, 2)
+        for v in range(g.n):
+            ng = set(nx.single_source_shortest_path_length(nxg, v, cutoff=2)) - {v}
+            assert ball[v] == len(ng)
+            if not ng:
+                assert np.isnan(score[v])
+                continue
+            others = np.array([u for u in range(g.n) if u != v])
+            d2 = ((xy[others].astype(np.float64) - xy[v].astype(np.float64)) ** 2).sum(1)
+            order = np.lexsort((others, d2))
+            nd = set(others[order[:len(ng)]].tolist())
+            assert score[v] == len(ng & nd) / len(ng | nd)
