@@ -31,7 +31,7 @@ METRIC = "GTEPS + kNN graphs/sec vs plain; p50/p99 served latency, bit-exact"
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress"])
+    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress", "neighborhood"])
     p.add_argument("--batch-graphs", type=int, default=2048)
     p.add_argument("--serve-jobs", type=int, default=1024)
     p.add_argument("--serve-pool", type=int, default=64)
@@ -77,6 +77,8 @@ def main():
         return bench_allsource(args)
     if args.workload == "stress":
         return bench_stress(args)
+    if args.workload == "neighborhood":
+        return bench_neighborhood(args)
 
     if args.calibrate_copy:
         n_bytes = 1 << 30
@@ -208,9 +210,21 @@ def _profiled(gm, fn, steps):
     return dt, gm.profile_entries()
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
 def _roofline(prof, steps):
     dom = max(prof, key=lambda kname: prof[kname]["total_ms"])
     d = prof[dom]
+    if dom == "neighborhood":
+        # FP64 distance arithmetic against the vector FP64 peak; the counter
+        # holds FP64 operations, not bytes
+        achieved = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e12
+        return {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "launches": d["launches"],
+                "avg_launch_us": d["total_ms"] * 1e3 / d["launches"],
+                "alg_flops_per_launch": d["alg_bytes"] / d["launches"]}, \
+            {kname: v["total_ms"] / steps for kname, v in prof.items()}
     achieved = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": d["launches"],
@@ -330,6 +344,65 @@ def bench_stress(args):
         t = (time.perf_counter() - t0) * n / len(sub)
         out["cpu_baseline"] = {"value": n * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
                                "sample": "oracle stress rows of 256 of the %d sources, scaled" % n}
+    print(json.dumps(out), flush=True)
+
+
+def bench_neighborhood(args):
+    """Neighbourhood preservation (Sec. 5.1, r = 2) of a seeded random drawing
+    of the BA graph, scored for its 4,096 sampled vertices."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    g = G.config_ba()
+    n, m = g.n, g.m
+    verts = G.config_ba_sources()
+    xy = (G.uniform(G.BASE_SEED + 300, 2 * n).reshape(n, 2) * 100.0).astype(np.float32)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    dxy = torch.from_numpy(xy).cuda()
+    dv = torch.from_numpy(verts).cuda()
+    gg = gm.make_graph(rp, ci, flags=gm.CSR_SORTED)
+    score = torch.empty(len(verts), dtype=torch.float64, device="cuda")
+    ball = torch.empty(len(verts), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        gm.gumap_neighborhood(gg, dxy, 2, dv, len(verts), score, ball, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    dt, prof = _profiled(gm, step, steps)
+    roof, kms = _roofline(prof, steps)
+    sc = score.cpu().numpy()
+    ok = ~np.isnan(sc)
+    out = {"metric": METRIC, "value": len(verts) / dt, "unit": "scored vertices/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "neighborhood: BA n=%d m=%d, seeded uniform drawing in [0, 100)^2; "
+                                  "neighbourhood preservation r=2 of the %d sampled vertices" % (n, m, len(verts)),
+                      "n": n, "m": m, "vertices": len(verts), "r": 2},
+           "np_mean": float(sc[ok].mean()), "np_sum": float(sc[ok].sum()), "mean_ball": float(ball.float().mean()),
+           "roofline": roof, "kernels_ms_per_step": kms}
+    if not args.no_parity:
+        import oracle as O
+        pick = np.arange(0, len(verts), 64)
+        osc, oball = O.neighborhood_scores(g, xy, 2, vertices=verts[pick])
+        out["parity_sampled_bit_exact"] = bool(np.array_equal(sc[pick], osc, equal_nan=True)
+                                               and np.array_equal(ball.cpu().numpy()[pick], oball))
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        sub = verts[:256]
+        t0 = time.perf_counter()
+        O.neighborhood_scores(g, xy, 2, vertices=sub, threads=threads)
+        t = (time.perf_counter() - t0) * len(verts) / len(sub)
+        out["cpu_baseline"] = {"value": len(verts) / t, "unit": "scored vertices/s", "cores": threads,
+                               "kind": "oracle", "sample": "oracle scores of 256 of the %d vertices, scaled"
+                               % len(verts)}
     print(json.dumps(out), flush=True)
 
 

@@ -122,6 +122,27 @@ int gumap_stress(const gumap_graph *g, const float *xy, const int32_t *sources, 
                  double *sum, int64_t *pairs, hipStream_t stream);
 
 /*
+ * Neighbourhood preservation of a drawing (Sec. 5.1 quality metrics), per
+ * vertex: the Jaccard index |N_G & N_D| / |N_G | N_D| of the graph ball
+ * N_G(v, r) (vertices u != v within r hops) and N_D(v, r), the |N_G(v, r)|
+ * vertices u != v nearest to v in the drawing, ranked by squared Euclidean
+ * distance (FP64, dx*dx + dy*dy without fused multiply-add) and then by id.
+ * The paper's metric is the sum of the scores (r = 2).
+ *   xy        device float[2 * n] (x, y of each vertex)
+ *   r         1 or 2
+ *   vertices  device int32[n_vertices] or NULL (every vertex, n_vertices ignored)
+ *   score     device double[rows]: the score of each listed vertex, NaN when
+ *             its ball is empty
+ *   ball      device int32[rows] or NULL: |N_G(v, r)|
+ * Each vertex costs a few passes over all n vertices of the drawing; n is
+ * limited to about 1.2 million (the ball is a bit set in LDS).
+ * Errors: GUMAP_EINVAL (NULL pointer, r, vertex id, n too large),
+ * GUMAP_EGRAPH (with GUMAP_VALIDATE), GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_neighborhood(const gumap_graph *g, const float *xy, int32_t r, const int32_t *vertices,
+                       int32_t n_vertices, double *score, int32_t *ball, hipStream_t stream);
+
+/*
  * SL-/SSSL-GUMAP steps C0 + C1 (Sec. 3.3.1, Alg. 4 PartialBFS): for every
  * vertex v, a BFS that stops at the level completing k other vertices; the
  * row holds all earlier levels and the smallest ids of that last level.

@@ -48,7 +48,7 @@ def _load():
         lib.oracle_knn_partial.argtypes = [i32, vp, vp, i32, vp, i32, vp, vp, ctypes.c_int]
         lib.oracle_membership.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.c_int]
         lib.oracle_stress.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
-        lib.oracle_neighborhood.argtypes = [i32, vp, vp, vp, i32, vp, vp, ctypes.c_int]
+        lib.oracle_neighborhood.argtypes = [i32, vp, vp, vp, i32, vp, i64, vp, vp, ctypes.c_int]
         for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership,
                   lib.oracle_stress, lib.oracle_neighborhood):
             f.restype = ctypes.c_int
@@ -157,15 +157,18 @@ def stress(g, xy: np.ndarray, sources=None, threads: int | None = None):
     return float(row_sum.sum()), int(row_pairs.sum())
 
 
-def neighborhood_scores(g, xy: np.ndarray, r: int = 2, threads: int | None = None):
-    """Per-vertex neighbourhood preservation (Sec. 5.1): ``(score float64[n]
-    (NaN where the graph ball is empty), ball int32[n])``."""
+def neighborhood_scores(g, xy: np.ndarray, r: int = 2, vertices=None, threads: int | None = None):
+    """Per-vertex neighbourhood preservation (Sec. 5.1) of the listed vertices
+    (all when None): ``(score float64[rows] (NaN where the graph ball is
+    empty), ball int32[rows])``."""
     rp, ci = _csr(g)
     xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(g.n, 2)
-    score = np.empty(g.n, dtype=np.float64)
-    ball = np.empty(g.n, dtype=np.int32)
-    st = _load().oracle_neighborhood(g.n, _ptr(rp), _ptr(ci), _ptr(xy), int(r), _ptr(score), _ptr(ball),
-                                     int(threads or default_threads()))
+    vt = None if vertices is None else np.ascontiguousarray(vertices, dtype=np.int32)
+    rows = g.n if vt is None else int(vt.shape[0])
+    score = np.empty(rows, dtype=np.float64)
+    ball = np.empty(rows, dtype=np.int32)
+    st = _load().oracle_neighborhood(g.n, _ptr(rp), _ptr(ci), _ptr(xy), int(r), _ptr(vt), rows, _ptr(score),
+                                     _ptr(ball), int(threads or default_threads()))
     if st:
         raise OracleError(st)
     return score, ball
@@ -173,6 +176,6 @@ def neighborhood_scores(g, xy: np.ndarray, r: int = 2, threads: int | None = Non
 
 def neighborhood_preservation(g, xy: np.ndarray, r: int = 2, threads: int | None = None):
     """``(sum of defined scores, number of defined scores)``."""
-    score, _ = neighborhood_scores(g, xy, r, threads)
+    score, _ = neighborhood_scores(g, xy, r, threads=threads)
     ok = ~np.isnan(score)
     return float(score[ok].sum()), int(ok.sum())

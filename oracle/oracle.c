@@ -480,6 +480,7 @@ typedef struct {
     int32_t n, r;
     const int32_t *row_ptr, *col_idx;
     const float *xy;
+    const int32_t *verts;
     double *score;
     int32_t *ball;
 } np_job_t;
@@ -487,7 +488,7 @@ typedef struct {
 static int np_row(void *jp, int64_t row, void *scratch)
 {
     np_job_t *j = (np_job_t *)jp;
-    const int32_t n = j->n, v = (int32_t)row;
+    const int32_t n = j->n, v = j->verts ? j->verts[row] : (int32_t)row;
     int32_t *dist = (int32_t *)scratch;
     np_key_t *keys = (np_key_t *)(dist + n);
     char *in_ball = (char *)(keys + n);
@@ -498,9 +499,9 @@ static int np_row(void *jp, int64_t row, void *scratch)
         in_ball[u] = (u != v && dist[u] >= 1 && dist[u] <= j->r);
         K += in_ball[u];
     }
-    j->ball[v] = K;
+    j->ball[row] = K;
     if (K == 0) {
-        j->score[v] = NAN;
+        j->score[row] = NAN;
         return ORACLE_OK;
     }
     const double xv = (double)j->xy[2 * (size_t)v], yv = (double)j->xy[2 * (size_t)v + 1];
@@ -517,15 +518,17 @@ static int np_row(void *jp, int64_t row, void *scratch)
     qsort(keys, (size_t)m, sizeof(np_key_t), cmp_np_key);
     int32_t common = 0;
     for (int32_t i = 0; i < K; ++i) common += in_ball[keys[i].id];
-    j->score[v] = (double)common / (double)(2 * K - common);
+    j->score[row] = (double)common / (double)(2 * K - common);
     return ORACLE_OK;
 }
 
 int oracle_neighborhood(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const float *xy, int32_t r,
-                        double *score, int32_t *ball, int nthreads)
+                        const int32_t *verts, int64_t rows, double *score, int32_t *ball, int nthreads)
 {
-    if (n < 0 || r < 1) return ORACLE_EINVAL;
-    np_job_t j = {n, r, row_ptr, col_idx, xy, score, ball};
+    if (n < 0 || r < 1 || rows < 0) return ORACLE_EINVAL;
+    for (int64_t i = 0; verts && i < rows; ++i)
+        if (verts[i] < 0 || verts[i] >= n) return ORACLE_EINVAL;
+    np_job_t j = {n, r, row_ptr, col_idx, xy, verts, score, ball};
     const size_t nn = (size_t)(n > 0 ? n : 1);
-    return run_rows(n, nthreads, &j, np_row, nn * (sizeof(int32_t) + sizeof(np_key_t) + 1));
+    return run_rows(verts ? rows : n, nthreads, &j, np_row, nn * (sizeof(int32_t) + sizeof(np_key_t) + 1));
 }

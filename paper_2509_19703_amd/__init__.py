@@ -98,6 +98,8 @@ def _load() -> ctypes.CDLL:
     lib.gumap_knn_partial.argtypes = [G, i32, vp, vp, vp]
     lib.gumap_stress.argtypes = [G, vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]
     lib.gumap_stress.restype = ctypes.c_int
+    lib.gumap_neighborhood.argtypes = [G, vp, i32, vp, i32, vp, vp, vp]
+    lib.gumap_neighborhood.restype = ctypes.c_int
     lib.gumap_membership.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     lib.gumap_knn_partial_batch.argtypes = [B, i32, vp, vp, vp, vp, vp, vp]
     lib.gumap_batch_plan_create.argtypes = [B, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -283,6 +285,24 @@ def stress(row_ptr, col_idx, xy, sources=None, flags: int = 0, stream=None):
         return 0.0, 0   # an empty list, not NULL (= every vertex)
     n_src = 0 if sources is None else int(sources.shape[0])
     return gumap_stress(g, xy.contiguous(), sources, n_src, stream)
+
+
+def gumap_neighborhood(g, xy, r, vertices, n_vertices, score, ball=None, stream=None) -> int:
+    return _check(lib.gumap_neighborhood(ctypes.byref(g), _ptr(xy), int(r), _ptr(vertices), int(n_vertices),
+                                         _ptr(score), _ptr(ball), _stream(stream)))
+
+
+def neighborhood(row_ptr, col_idx, xy, r: int = 2, vertices=None, flags: int = 0, stream=None):
+    """Per-vertex neighbourhood preservation of the drawing xy (device
+    float32 [n, 2]).  Returns (score float64 [rows], ball int32 [rows])."""
+    torch = _torch()
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    rows = g.n if vertices is None else int(vertices.shape[0])
+    score = torch.empty(rows, dtype=torch.float64, device=row_ptr.device)
+    ball = torch.empty(rows, dtype=torch.int32, device=row_ptr.device)
+    if rows:
+        gumap_neighborhood(g, xy.contiguous(), r, vertices, rows, score, ball, stream)
+    return score, ball
 
 
 def membership(hops, stream=None):

@@ -567,6 +567,52 @@ int stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_
     return GUMAP_OK;
 }
 
+int neighborhood(const gumap_graph *g, const float *xy, int32_t r, const int32_t *verts, int32_t n_verts,
+                 double *score, int32_t *ball, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if (r != 1 && r != 2) return set_error(GUMAP_EINVAL, "r = %d: only 1 and 2 are supported", r);
+    if (verts && n_verts < 0) return set_error(GUMAP_EINVAL, "n_vertices < 0");
+    const int32_t n = g->n;
+    const int64_t rows = verts ? n_verts : n;
+    if (rows == 0) return GUMAP_OK;
+    if (!xy || !score) return set_error(GUMAP_EINVAL, "NULL coordinates or output pointer");
+    if (neighborhood_lds_bytes(n) > 144 * 1024)
+        return set_error(GUMAP_EINVAL, "n = %d exceeds the ball set the kernel keeps in LDS", n);
+    if (verts) {
+        std::vector<int32_t> h((size_t)rows);
+        hipError_t e = hipMemcpyAsync(h.data(), verts, (size_t)rows * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "reading vertices");
+        for (int64_t i = 0; i < rows; ++i)
+            if (h[i] < 0 || h[i] >= n) return set_error(GUMAP_EINVAL, "vertex %d outside [0, %d)", h[i], n);
+    }
+    CanonCsr c;
+    if ((st = prepare_graph(g, s, &c))) return st;
+    // when launches are timed, count the work: 5 FP64 operations per squared
+    // distance (2 differences, 2 products, 1 sum); the kernel is ALU-bound
+    unsigned long long *evals = nullptr;
+    hipError_t e = hipSuccess;
+    if (prof_on()) {
+        if ((st = scratch_get(kSlotEvals, 256, (void **)&evals))) return st;
+        e = hipMemsetAsync(evals, 0, sizeof(unsigned long long), s);
+        if (e != hipSuccess) return hip_status(e, "counter");
+    }
+    const int mark = prof_begin("neighborhood", s);
+    e = launch_neighborhood(n, c.row_ptr, c.col, xy, r, verts, (int32_t)rows, score, ball, evals, s);
+    prof_end(mark, s, 0.0);
+    if (e != hipSuccess) return hip_status(e, "neighbourhood preservation");
+    if (evals) {
+        unsigned long long h = 0;
+        e = hipMemcpyAsync(&h, evals, sizeof(h), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "counter");
+        prof_set_bytes(mark, 5.0 * (double)h);
+    }
+    return finish(s, "gumap_neighborhood");
+}
+
 // ------------------------------------------------------- canonical CSR --
 int csr_canonicalize(const gumap_graph *g, int32_t *out_rp, int32_t *out_col, int32_t *out_nnz, hipStream_t s)
 {
@@ -885,6 +931,14 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
     return gm::settle(gm::knn_build(g, k, sources, n_sources, nbr_ids, nbr_hops, hop_matrix, stream), stream);
+}
+
+int gumap_neighborhood(const gumap_graph *g, const float *xy, int32_t r, const int32_t *vertices,
+                       int32_t n_vertices, double *score, int32_t *ball, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::neighborhood(g, xy, r, vertices, n_vertices, score, ball, stream), stream);
 }
 
 int gumap_stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_t n_sources, double *sum,

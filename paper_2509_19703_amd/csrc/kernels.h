@@ -93,6 +93,17 @@ struct StressArgs {
 };
 hipError_t launch_msbfs_stress(const MsbfsArgs &a, int planes_used, const StressArgs &sa, hipStream_t s);
 
+// ------------------------------------------------ drawing quality metrics ---
+// Neighbourhood preservation (r = 1 or 2) of the drawing xy (x, y per vertex)
+// for the listed vertices (all when verts is NULL): score[i] (FP64, NaN for
+// an empty ball) and, when ball is not NULL, ball[i] = |N_G(v, r)|.  The
+// kernel keeps an n-bit set in LDS: neighborhood_lds_bytes(n) dynamic bytes.
+// evals (optional, device) accumulates the squared distances evaluated.
+size_t neighborhood_lds_bytes(int32_t n);
+hipError_t launch_neighborhood(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *xy, int r,
+                               const int32_t *verts, int32_t n_verts, double *score, int32_t *ball,
+                               unsigned long long *evals, hipStream_t s);
+
 // ------------------------------------------------------- kNN selection ---
 // Rows: for r in [0, rows): hop row hop_rows + row_of[r] * row_stride (n bytes),
 // source vertex src_of[r]; writes ids/hops rows out_row[r].

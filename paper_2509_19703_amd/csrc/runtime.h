@@ -36,6 +36,7 @@ enum ScratchSlot {
     kSlotHeavy,
     kSlotStressSum,
     kSlotStressPairs,
+    kSlotEvals,
     kScratchSlots
 };
 

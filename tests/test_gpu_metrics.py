@@ -110,3 +110,68 @@ def test_stress_ba100k_sampled_sources(gumap):
     src = G.config_ba_sources()[::16].copy()
     print("ba100k stress", len(src), flush=True)
     _check(gumap, g, _layout(g.n, 61, scale=100.0), sources=src)
+
+
+# ------------------------------------------------ neighbourhood preservation --
+
+def _np_check(gumap, g, xy, r=2, vertices=None, flags=None):
+    import torch
+    rp, ci = to_dev(g)
+    dxy = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.float32)).cuda()
+    vt = None if vertices is None else torch.from_numpy(np.asarray(vertices, dtype=np.int32)).cuda()
+    score, ball = gumap.neighborhood(rp, ci, dxy, r=r, vertices=vt,
+                                     flags=gumap.CSR_SORTED if flags is None else flags)
+    oscore, oball = O.neighborhood_scores(g, xy, r, vertices=vertices)
+    score, ball = score.cpu().numpy(), ball.cpu().numpy()
+    assert np.array_equal(ball, oball)
+    # integer counts decide every score: equal to the last bit (NaN where undefined)
+    assert np.array_equal(np.isnan(score), np.isnan(oscore))
+    ok = ~np.isnan(oscore)
+    assert np.array_equal(score[ok], oscore[ok]), np.flatnonzero(score[ok] != oscore[ok])[:5]
+    return score
+
+
+@pytest.mark.parametrize("name,g", _family(), ids=[n for n, _ in _family()])
+def test_neighborhood_random_drawings(gumap, name, g):
+    print("neighborhood", name, g.n, flush=True)
+    _np_check(gumap, g, _layout(g.n, 71))
+    # coarse integer coordinates: many exact distance ties, decided by id
+    _np_check(gumap, g, np.floor(_layout(g.n, 72, scale=6.0)), r=1)
+
+
+def test_neighborhood_lattice_and_collapsed(gumap):
+    g = G.grid_2d(20, 33)
+    xy = np.array([[v % 33, v // 33] for v in range(g.n)], dtype=np.float32)
+    assert np.all(_np_check(gumap, g, xy) == 1.0)
+    c = G.cycle(300)
+    _np_check(gumap, c, np.zeros((c.n, 2), dtype=np.float32))
+    _np_check(gumap, G.complete(50), _layout(50, 73))
+
+
+def test_neighborhood_vertices_and_unsorted(gumap):
+    g = G.rgg(5000, 9, 81)
+    verts = np.concatenate([G.sample_sources(g.n, 400, 82), [7, 7, 4999, 0]]).astype(np.int32)
+    _np_check(gumap, g, _layout(g.n, 83), vertices=verts)
+    d = G.dirty(G.sbm(2500, 8, 84), 85)
+    _np_check(gumap, d, _layout(d.n, 86), flags=0)
+
+
+def test_neighborhood_errors(gumap):
+    import torch
+    g = G.path(10)
+    rp, ci = to_dev(g)
+    gr = gumap.make_graph(rp, ci, flags=gumap.CSR_SORTED)
+    xy = torch.zeros((10, 2), dtype=torch.float32, device="cuda")
+    out = torch.empty(10, dtype=torch.float64, device="cuda")
+    for r, x, verts, nv in ((3, xy, None, 0), (2, None, None, 0),
+                            (2, xy, torch.tensor([1, 10], dtype=torch.int32, device="cuda"), 2)):
+        with pytest.raises(gumap.GumapError) as ei:
+            gumap.gumap_neighborhood(gr, x, r, verts, nv, out)
+        assert ei.value.status == gumap.EINVAL
+
+
+def test_neighborhood_ba100k_sampled(gumap):
+    g = G.config_ba()
+    verts = G.config_ba_sources()[::16].copy()
+    print("ba100k neighborhood", len(verts), flush=True)
+    _np_check(gumap, g, _layout(g.n, 91, scale=100.0), vertices=verts)

@@ -542,6 +542,8 @@ def test_neighborhood_isolated_vertices_undefined():
     assert np.all(np.isnan(score[4:])) and np.all(ball[4:] == 0)
     s, c = O.neighborhood_preservation(g, xy)
     assert c == 4 and s == pytest.approx(float(score[:4].sum()))
+    sub, subball = O.neighborhood_scores(g, xy, vertices=[2, 5, 2])
+    assert np.array_equal(subball, ball[[2, 5, 2]]) and sub[0] == score[2] and sub[2] == score[2]
 
 
 def test_neighborhood_brute_force_tiny_graphs():
