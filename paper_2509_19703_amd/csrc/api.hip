@@ -271,64 +271,63 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     if (rows == 0) return GUMAP_OK;
     if (n == 0) return set_error(GUMAP_EINVAL, "source id outside [0, 0)");
 
-    // sources -> sorted unique slots
-    std::vector<int32_t> h_usrc;
-    std::vector<int64_t> h_slot_row;
-    std::vector<int64_t> dup_pairs;  // (dst row, src row)
-    std::vector<int32_t> h_mult;     // times each unique source is listed
+    // sources -> sorted unique slots, on the device; one synchronisation below
+    // reads the number of unique sources, a range flag and the heavy-vertex
+    // list size together
     const bool all_sources = sources == nullptr;
-    if (!all_sources) {
-        std::vector<int32_t> h_src((size_t)rows);
-        hipError_t e = hipMemcpyAsync(h_src.data(), sources, (size_t)rows * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_status(e, "reading sources");
-        std::vector<int64_t> order((size_t)rows);
-        for (int64_t r = 0; r < rows; ++r) {
-            if (h_src[r] < 0 || h_src[r] >= n)
-                return set_error(GUMAP_EINVAL, "source %lld = %d outside [0, %d)", (long long)r, h_src[r], n);
-            order[r] = r;
-        }
-        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return h_src[a] < h_src[b]; });
-        for (int64_t i = 0; i < rows; ++i) {
-            int64_t r = order[i];
-            if (!h_usrc.empty() && h_usrc.back() == h_src[r]) {
-                dup_pairs.push_back(r);
-                dup_pairs.push_back(h_slot_row.back());
-                ++h_mult.back();
-            } else {
-                h_usrc.push_back(h_src[r]);
-                h_slot_row.push_back(r);
-                h_mult.push_back(1);
-            }
-        }
-    }
-    const int32_t n_uniq = all_sources ? n : (int32_t)h_usrc.size();
-
     CanonCsr c;
     if ((st = prepare_graph(g, s, &c))) return st;
-
-    int32_t *usrc = nullptr, *slot_of = nullptr;
-    int64_t *slot_row = nullptr, *dup_dev = nullptr;
-    if ((st = scratch_get(kSlotUsrc, (size_t)n_uniq * sizeof(int32_t), (void **)&usrc))) return st;
+    int32_t *usrc = nullptr, *slot_of = nullptr, *first_row = nullptr, *info = nullptr, *mult = nullptr;
+    int32_t *heavy = nullptr;
+    int64_t *slot_row = nullptr;
+    if ((st = scratch_get(kSlotUsrc, (size_t)n * sizeof(int32_t), (void **)&usrc))) return st;
     if ((st = scratch_get(kSlotSlotOf, (size_t)n * sizeof(int32_t), (void **)&slot_of))) return st;
-    if ((st = scratch_get(kSlotSlotRow, (size_t)n_uniq * sizeof(int64_t), (void **)&slot_row))) return st;
-    hipError_t e = hipSuccess;
+    if ((st = scratch_get(kSlotSlotRow, (size_t)n * sizeof(int64_t), (void **)&slot_row))) return st;
+    if ((st = scratch_get(kSlotInfo, 256, (void **)&info))) return st;
+    if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
+    hipError_t e = hipMemsetAsync(info, 0, 8 * sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_status(e, "source setup");
     if (all_sources) {
         e = iota_i32(usrc, n, s);
         if (e == hipSuccess) e = iota_i32(slot_of, n, s);
         if (e == hipSuccess) e = iota_i64(slot_row, n, 0, s);
     } else {
-        e = hipMemcpyAsync(usrc, h_usrc.data(), (size_t)n_uniq * sizeof(int32_t), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(slot_row, h_slot_row.data(), (size_t)n_uniq * sizeof(int64_t), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = fill_i32(slot_of, n, -1, s);
-        if (e == hipSuccess) e = scatter_slots(usrc, n_uniq, slot_of, s);
-        if (e == hipSuccess && !dup_pairs.empty()) {
-            if ((st = scratch_get(kSlotDup, dup_pairs.size() * sizeof(int64_t), (void **)&dup_dev))) return st;
-            e = hipMemcpyAsync(dup_dev, dup_pairs.data(), dup_pairs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+        int32_t *count = nullptr, *marks = nullptr, *pos = nullptr;
+        void *scan_tmp = nullptr;
+        if ((st = scratch_get(kSlotFirst, (size_t)n * sizeof(int32_t), (void **)&first_row))) return st;
+        if ((st = scratch_get(kSlotMarks, (size_t)n * sizeof(int32_t), (void **)&marks))) return st;
+        if ((st = scratch_get(kSlotPos, (size_t)(n + 1) * sizeof(int32_t), (void **)&pos))) return st;
+        if ((st = scratch_get(kSlotScanTmp, exclusive_scan_scratch_bytes(n), &scan_tmp))) return st;
+        if (so) {
+            if ((st = scratch_get(kSlotCount, (size_t)n * sizeof(int32_t), (void **)&count))) return st;
+            if ((st = scratch_get(kSlotMult, (size_t)n * sizeof(int32_t), (void **)&mult))) return st;
         }
+        e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of, mult,
+                            info, s);
     }
+    // vertices of high degree get a whole wave per level
+    if (e == hipSuccess)
+        e = launch_heavy_list(n, c.row_ptr, (int32_t)env_size("GUMAP_HEAVY_DEGREE", 0), heavy, info, s);
     if (e != hipSuccess) return hip_status(e, "source setup");
+    int32_t hinfo[8];
+    {
+        void *hv = nullptr;
+        if ((st = host_scratch_get(256, &hv))) return st;
+        e = hipMemcpyAsync(hv, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "source setup");
+        std::memcpy(hinfo, hv, sizeof(hinfo));
+    }
+    if (hinfo[0] & 1) return set_error(GUMAP_EINVAL, "a source id is outside [0, %d)", n);
+    const int32_t n_uniq = all_sources ? n : hinfo[3];
+    const int32_t n_heavy = hinfo[1], heavy_deg = hinfo[2];
+    std::vector<int32_t> h_mult;     // times each unique source is listed (stress only)
+    if (mult && n_uniq > 0) {
+        h_mult.resize((size_t)n_uniq);
+        e = hipMemcpyAsync(h_mult.data(), mult, (size_t)n_uniq * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "source multiplicities");
+    }
 
     const int words = choose_words(n_uniq);
     const int W = 64 * words;
@@ -348,7 +347,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     unsigned long long *stats = nullptr;
     unsigned int *lvl_cnt = nullptr;
     int64_t *local_rows = nullptr;
-    int32_t *heavy = nullptr;
     const int SF = msbfs_stat_fields(), SP = msbfs_stat_spread();
     const size_t stats_per_level = (size_t)groups_round * SP * SF;   // u64 per level
     const size_t arr_round = arr_per_group * groups_round;
@@ -360,7 +358,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                                               msbfs_hop_chunks(n, (groups_total - 1) % groups_round + 1)) *
                                  W * 16 * 4;
     if ((st = scratch_get(kSlotLvlCnt, lvl_cnt_bytes, (void **)&lvl_cnt))) return st;
-    if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
     if (!full_hops) {
         if ((st = scratch_get(kSlotHopRows, (size_t)groups_round * W * n, (void **)&hop_scratch))) return st;
         if ((st = scratch_get(kSlotLocalRows, (size_t)groups_round * W * sizeof(int64_t), (void **)&local_rows))) return st;
@@ -369,26 +366,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     void *hstats_v = nullptr;
     if ((st = host_scratch_get((size_t)(L_cap + 2) * stats_per_level * 8 + 256, &hstats_v))) return st;
     unsigned long long *hstats = (unsigned long long *)hstats_v;
-    // vertices of high degree get a whole wave per level
-    int32_t n_heavy = 0;
-    int32_t nnz_canon = g->nnz;
-    if (!(g->flags & GUMAP_CSR_SORTED)) {
-        e = hipMemcpyAsync(hstats, c.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_status(e, "canonical size");
-        nnz_canon = *(int32_t *)hstats;
-    }
-    const int32_t heavy_deg = (int32_t)env_size("GUMAP_HEAVY_DEGREE", (size_t)msbfs_heavy_degree(n, nnz_canon));
-    {
-        int32_t *count = heavy + n;
-        e = hipMemsetAsync(count, 0, sizeof(int32_t), s);
-        if (e == hipSuccess) e = launch_heavy_list(n, c.row_ptr, heavy_deg, heavy, count, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(hstats, count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_status(e, "heavy vertices");
-        n_heavy = *(int32_t *)hstats;
-    }
-
     for (int32_t gs = 0; gs < groups_total; gs += groups_round) {
         MsbfsArgs a;
         a.n = n;
@@ -450,7 +427,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             return b;
         };
 
-        int L = 1, last_level = 0, chunk = 4;
+        // levels launched between reads of the counters: the first batch covers
+        // about 1.5x the depth a graph of this mean degree reaches (a level
+        // launched past the end returns at once); later batches grow
+        const double mean_deg = std::max(2.0, (double)g->nnz / std::max(1, n));
+        int L = 1, last_level = 0;
+        int chunk = (int)std::min(16.0, std::max(4.0, std::ceil(1.5 * std::log((double)n) / std::log(mean_deg)) + 2));
         bool done = false, range_error = false;
         while (!done) {
             const int first = L;
@@ -499,7 +481,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 last_level = L_cap;
                 done = true;
             }
-            chunk = std::max(4, L / 2);
+            chunk = std::max(8, L / 2);
         }
         if (range_error)
             return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
@@ -547,8 +529,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                                               hops, s));
         if (e != hipSuccess) return hip_status(e, "hop rows / selection");
     }
-    if (!so && !dup_pairs.empty()) {
-        e = launch_copy_rows((int32_t)(dup_pairs.size() / 2), dup_dev, k, n, ids, hops, hop_matrix, s);
+    if (!so && !all_sources && n_uniq < rows) {
+        e = copy_dup_rows(sources, rows, first_row, k, n, ids, hops, hop_matrix, s);
         if (e != hipSuccess) return hip_status(e, "repeated sources");
     }
     return finish(s, "gumap_knn_build");

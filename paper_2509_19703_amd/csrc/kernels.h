@@ -64,8 +64,9 @@ struct MsbfsArgs {
 // frontier words committed}; a level's value is the sum over the spread slots.
 int msbfs_stat_fields();
 int msbfs_stat_spread();
-int msbfs_heavy_degree(int32_t n, int32_t nnz);
-hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t heavy_deg, int32_t *heavy, int32_t *count,
+// heavy[0 .. info[1]) = vertices of degree above the threshold info[2]
+// (forced if > 0, else max(64, 8 * mean degree)); info[1] must be zero.
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, int32_t *heavy, int32_t *info,
                              hipStream_t s);
 hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.

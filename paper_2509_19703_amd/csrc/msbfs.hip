@@ -244,11 +244,18 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     }
 }
 
-__global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t heavy_deg, int32_t *heavy,
-                                  int32_t *count)
+// Degree above which a vertex is searched by a whole wave: hubs well above
+// the mean degree (a lone thread would walk their rows serially while the
+// rest of its wave waits); dense graphs with an even degree keep one thread
+// per vertex word, which stops early.  info[1] = count, info[2] = threshold.
+__global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t forced, int32_t *heavy,
+                                  int32_t *info)
 {
+    const int32_t mean = n > 0 ? rp[n] / n : 0;
+    const int32_t thr = forced > 0 ? forced : max(64, 8 * mean);
+    if (blockIdx.x == 0 && threadIdx.x == 0) info[2] = thr;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        if (rp[v + 1] - rp[v] > heavy_deg) heavy[atomicAdd(count, 1)] = (int32_t)v;
+        if (rp[v + 1] - rp[v] > thr) heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
 }
 
 // Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
@@ -566,26 +573,17 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
     return hipGetLastError();
 }
 
-hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t heavy_deg, int32_t *heavy, int32_t *count,
+hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, int32_t *heavy, int32_t *info,
                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>(4096, ((int64_t)n + 255) / 256);
-    hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, heavy_deg, heavy, count);
+    hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, forced, heavy, info);
     return hipGetLastError();
 }
 
 int msbfs_stat_fields() { return kStatFields; }
 int msbfs_stat_spread() { return kSpread; }
-// Degree above which a vertex is searched by a whole wave: hubs well above
-// the mean degree (a lone thread would walk their rows serially while the
-// rest of its wave waits); dense graphs with an even degree keep one thread
-// per vertex word, which stops early.
-int msbfs_heavy_degree(int32_t n, int32_t nnz)
-{
-    const int64_t mean = n > 0 ? (int64_t)nnz / n : 0;
-    return (int)std::max<int64_t>(64, 8 * mean);
-}
 
 // Blocks per group of the hop-row transpose: about two resident blocks per
 // compute unit over all groups, each taking an equal share of the tiles (at

@@ -37,6 +37,13 @@ enum ScratchSlot {
     kSlotStressSum,
     kSlotStressPairs,
     kSlotEvals,
+    kSlotInfo,
+    kSlotFirst,
+    kSlotMarks,
+    kSlotPos,
+    kSlotScanTmp,
+    kSlotCount,
+    kSlotMult,
     kScratchSlots
 };
 

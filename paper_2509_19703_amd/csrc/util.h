@@ -11,6 +11,19 @@ hipError_t iota_i32(int32_t *p, int64_t count, hipStream_t s);
 hipError_t iota_i64(int64_t *p, int64_t count, int64_t start, hipStream_t s);
 // slot_of[usrc[i]] = i
 hipError_t scatter_slots(const int32_t *usrc, int32_t count, int32_t *slot_of, hipStream_t s);
+// Listed sources src[rows] -> sorted unique sources on the device:
+// first[v] = first row naming v (INT32_MAX if none), usrc[slot] (ascending),
+// slot_row[slot] = first row, slot_of[v] (-1 if not a source), and, when
+// count and mult are not NULL, mult[slot] = times listed; info[0] gets bit 1
+// for an id outside [0, n), info[3] the number of unique sources.  marks,
+// pos (n + 1) and scan_tmp (exclusive_scan_scratch_bytes(n)) are scratch.
+hipError_t prepare_sources(const int32_t *src, int64_t rows, int32_t n, int32_t *first, int32_t *count,
+                           int32_t *marks, int32_t *pos, void *scan_tmp, int32_t *usrc, int64_t *slot_row,
+                           int32_t *slot_of, int32_t *mult, int32_t *info, hipStream_t s);
+// Rows r with first[src[r]] != r copy row first[src[r]] of ids/hops (k wide)
+// and of the hop matrix (n wide, when not NULL).
+hipError_t copy_dup_rows(const int32_t *src, int64_t rows, const int32_t *first, int32_t k, int32_t n, int32_t *ids,
+                         uint8_t *hops, uint8_t *hop_matrix, hipStream_t s);
 // bit 32 in *err unless every row is strictly increasing without self-loops
 hipError_t check_sorted(int32_t n, const int32_t *rp, const int32_t *col, int *err, hipStream_t s);
 // bits 128/256 in *err for malformed row pointers / ids of a packed batch whose

@@ -3,6 +3,10 @@
 // layout and one disjoint-union CSR.
 #include "device.h"
 #include "util.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <climits>
 
 namespace gm {
 
@@ -26,6 +30,63 @@ __global__ void iota_i64_k(int64_t *p, int64_t count, int64_t start) { GRID_STRI
 __global__ void scatter_slots_k(const int32_t *usrc, int32_t count, int32_t *slot_of)
 {
     GRID_STRIDE(i, count) slot_of[usrc[i]] = (int32_t)i;
+}
+
+// Listed sources: first row of each vertex (atomic minimum), times listed,
+// bit 1 of info[0] for an id outside [0, n).
+__global__ void source_first_k(const int32_t *src, int64_t rows, int32_t n, int32_t *first, int32_t *count,
+                               int32_t *info)
+{
+    GRID_STRIDE(r, rows)
+    {
+        const int32_t v = src[r];
+        if (v < 0 || v >= n) {
+            atomicOr(&info[0], 1);
+            continue;
+        }
+        atomicMin(&first[v], (int32_t)r);
+        if (count) atomicAdd(&count[v], 1);
+    }
+}
+
+__global__ void source_marks_k(int32_t n, const int32_t *first, int32_t *marks)
+{
+    GRID_STRIDE(v, (int64_t)n) marks[v] = first[v] != INT32_MAX ? 1 : 0;
+}
+
+// Unique sources in ascending id order: slot = exclusive prefix of the marks.
+__global__ void source_slots_k(int32_t n, const int32_t *first, const int32_t *pos, const int32_t *count,
+                               int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) info[3] = pos[n];
+    GRID_STRIDE(v, (int64_t)n)
+    {
+        if (first[v] != INT32_MAX) {
+            const int32_t s = pos[v];
+            usrc[s] = (int32_t)v;
+            slot_row[s] = first[v];
+            slot_of[v] = s;
+            if (mult) mult[s] = count[v];
+        } else {
+            slot_of[v] = -1;
+        }
+    }
+}
+
+// Rows naming a source listed earlier copy that row's results.
+__global__ void copy_dup_rows_k(const int32_t *src, int64_t rows, const int32_t *first, int32_t k, int32_t n,
+                                int32_t *ids, uint8_t *hops, uint8_t *hop_matrix)
+{
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int64_t f = first[src[r]];
+        if (f == r) continue;
+        for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            ids[r * k + i] = ids[f * k + i];
+            hops[r * k + i] = hops[f * k + i];
+        }
+        if (hop_matrix)
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) hop_matrix[r * (int64_t)n + i] = hop_matrix[f * (int64_t)n + i];
+    }
 }
 
 // Rows strictly increasing, no self-loops (bit 32 of *err otherwise).
@@ -215,6 +276,32 @@ hipError_t union_to_batch(int32_t n_graphs, const int64_t *voff, const int32_t *
     if (total_e_canon > 0)
         hipLaunchKernelGGL(union_to_batch_col_k, dim3(blocks_for(total_e_canon)), dim3(256), 0, s,
                            n_graphs, voff, eoff_out, ucol, total_e_canon, col_out);
+    return hipGetLastError();
+}
+
+hipError_t prepare_sources(const int32_t *src, int64_t rows, int32_t n, int32_t *first, int32_t *count,
+                           int32_t *marks, int32_t *pos, void *scan_tmp, int32_t *usrc, int64_t *slot_row,
+                           int32_t *slot_of, int32_t *mult, int32_t *info, hipStream_t s)
+{
+    hipError_t e = fill_i32(first, n, INT32_MAX, s);
+    if (e == hipSuccess && count) e = fill_i32(count, n, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(source_first_k, dim3(blocks_for(rows)), dim3(256), 0, s, src, rows, n, first, count, info);
+    hipLaunchKernelGGL(source_marks_k, dim3(blocks_for(n)), dim3(256), 0, s, n, first, marks);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_exclusive_scan(marks, pos, n, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(source_slots_k, dim3(blocks_for(n)), dim3(256), 0, s, n, first, pos, count, usrc, slot_row,
+                       slot_of, mult, info);
+    return hipGetLastError();
+}
+
+hipError_t copy_dup_rows(const int32_t *src, int64_t rows, const int32_t *first, int32_t k, int32_t n, int32_t *ids,
+                         uint8_t *hops, uint8_t *hop_matrix, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_dup_rows_k, dim3((unsigned)std::min<int64_t>(rows, 4096)), dim3(256), 0, s, src, rows,
+                       first, k, n, ids, hops, hop_matrix);
     return hipGetLastError();
 }
 
