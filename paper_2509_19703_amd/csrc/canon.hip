@@ -11,18 +11,11 @@ namespace gm {
 namespace {
 
 constexpr int kSmallRow = 64;      // one wave, registers
-constexpr int kMidRow = 1024;      // one wave, LDS
+constexpr int kMidRow = 1024;      // one wave, registers
 constexpr int kBigRow = 32768;     // one workgroup, LDS
 constexpr int kCanonBlock = 256;   // 4 waves
 constexpr int kBigBlock = 1024;
 constexpr int kHugeBlocks = 32;
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __global__ void validate_structure_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col, int *err)
@@ -67,77 +60,160 @@ __global__ void check_symmetric_kernel(int32_t n, const int32_t *__restrict__ ro
     }
 }
 
-// Sorts the row of vertex v into tmp[a, a + unique) and records the count.
-// Rows longer than kMidRow are queued for the workgroup kernels.
+constexpr int kTinyRow = 16;       // four rows per wave, 16 lanes each
+
+// Bitonic sort of one row of 64 * R entries (padding GM_INF_ID) held in
+// registers: element i = lane + 64 * r sits in register r of lane i % 64.
+// Compare-exchange distances below 64 cross lanes (shuffles), larger ones
+// stay within a lane.  Unique entries other than v go to tmp[a, ...) in
+// order and their count to cnt[v].
+template <int R>
+__device__ __forceinline__ void wave_sort_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
+                                              int32_t *__restrict__ tmp, int32_t *__restrict__ cnt)
+{
+    constexpr int P = GM_WAVE * R;
+    const int l = lane();
+    int x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = l + GM_WAVE * r;
+        x[r] = i < d ? col[a + i] : GM_INF_ID;
+    }
+#pragma unroll
+    for (int kk = 2; kk <= P; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= GM_WAVE) {
+                const int q = j / GM_WAVE;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((r & q) == 0) {
+                        const int i = l + GM_WAVE * r;
+                        const bool up = (i & kk) == 0;
+                        const int lo = min(x[r], x[r | q]), hi = max(x[r], x[r | q]);
+                        x[r] = up ? lo : hi;
+                        x[r | q] = up ? hi : lo;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = l + GM_WAVE * r;
+                    const int p = __shfl_xor(x[r], j, GM_WAVE);
+                    const bool up = (i & kk) == 0;
+                    const bool low = (i & j) == 0;
+                    x[r] = (low == up) ? min(x[r], p) : max(x[r], p);
+                }
+            }
+        }
+    }
+    int base = 0, carry = GM_INF_ID;   // carry: last element of the previous register
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int prev = __shfl_up(x[r], 1, GM_WAVE);
+        if (l == 0) prev = carry;
+        const bool keep = x[r] != GM_INF_ID && x[r] != (int)v && (r + l == 0 || x[r] != prev);
+        const unsigned long long m = __ballot(keep);
+        if (keep) tmp[a + base + lanes_below(m)] = x[r];
+        base += __popcll(m);
+        carry = __shfl(x[r], GM_WAVE - 1, GM_WAVE);
+    }
+    if (l == 0) cnt[v] = base;
+}
+
+// Sorts row v (a = its first entry, d its length, kTinyRow < d) into
+// tmp[a, a + unique) and records the count; rows longer than kMidRow are
+// queued for the workgroup kernels.
+__device__ __forceinline__ void canon_one_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
+                              int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, int32_t *big_list,
+                              int32_t *big_count, int32_t *huge_list, int32_t *huge_count)
+{
+    const int l = lane();
+    if (d > kMidRow) {
+        if (l == 0) {
+            if (d > kBigRow) huge_list[atomicAdd(huge_count, 1)] = (int32_t)v;
+            else big_list[atomicAdd(big_count, 1)] = (int32_t)v;
+        }
+        return;
+    }
+    if (d <= kSmallRow) {
+        int x = l < d ? col[a + l] : GM_INF_ID;
+        // bitonic sort across the 64 lanes, ascending
+#pragma unroll
+        for (int kk = 2; kk <= GM_WAVE; kk <<= 1) {
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                int p = __shfl_xor(x, j, GM_WAVE);
+                bool up = (l & kk) == 0;
+                bool low = (l & j) == 0;
+                x = (low == up) ? min(x, p) : max(x, p);
+            }
+        }
+        int prev = __shfl_up(x, 1, GM_WAVE);
+        bool keep = x != GM_INF_ID && x != (int)v && (l == 0 || x != prev);
+        unsigned long long m = __ballot(keep);
+        if (keep) tmp[a + lanes_below(m)] = x;
+        if (l == 0) cnt[v] = __popcll(m);
+        return;
+    }
+    // 64 < d <= 1024: bitonic sort in registers, R = 2..16 per lane
+    if (d <= 128) wave_sort_row<2>(v, a, d, col, tmp, cnt);
+    else if (d <= 256) wave_sort_row<4>(v, a, d, col, tmp, cnt);
+    else if (d <= 512) wave_sort_row<8>(v, a, d, col, tmp, cnt);
+    else wave_sort_row<16>(v, a, d, col, tmp, cnt);
+}
+
+// Rows of length <= 16, four per wave: one 16-lane segment each, bitonic
+// sort within the segment.  Longer rows are left to canon_rows_kernel.
+__global__ void __launch_bounds__(kCanonBlock)
+canon_tiny_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt)
+{
+    const int l = lane();
+    const int seg = l >> 4, sl = l & (kTinyRow - 1);
+    const int64_t waves = blockDim.x / GM_WAVE;
+    for (int64_t v0 = ((int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE) * 4; v0 < n;
+         v0 += (int64_t)gridDim.x * waves * 4) {
+        const int64_t v = v0 + seg;
+        int32_t a = 0, d = 0;
+        if (v < n) {
+            a = row_ptr[v];
+            d = row_ptr[v + 1] - a;
+        }
+        const bool tiny = v < n && d <= kTinyRow;
+        int x = (tiny && sl < d) ? col[a + sl] : GM_INF_ID;
+#pragma unroll
+        for (int kk = 2; kk <= kTinyRow; kk <<= 1) {
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                int p = __shfl_xor(x, j, GM_WAVE);
+                bool up = (sl & kk) == 0;
+                bool low = (sl & j) == 0;
+                x = (low == up) ? min(x, p) : max(x, p);
+            }
+        }
+        const int prev = __shfl_up(x, 1, GM_WAVE);
+        const bool keep = tiny && x != GM_INF_ID && x != (int)v && (sl == 0 || x != prev);
+        const unsigned long long m = __ballot(keep);
+        const unsigned long long segm = 0xFFFFull << (16 * seg);
+        if (keep) tmp[a + __popcll(m & segm & ((1ull << l) - 1ull))] = x;
+        if (tiny && sl == 0) cnt[v] = __popcll(m & segm);
+    }
+}
+
+// Rows longer than 16, one wave each (see canon_one_row); rows longer than
+// kMidRow are queued for the workgroup kernels.
 __global__ void __launch_bounds__(kCanonBlock)
 canon_rows_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                   int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, int32_t *big_list,
                   int32_t *big_count, int32_t *huge_list, int32_t *huge_count)
 {
-    __shared__ int32_t lds[kCanonBlock / GM_WAVE][kMidRow];
     const int wid = threadIdx.x / GM_WAVE;
-    const int l = lane();
-    int32_t *buf = lds[wid];
     const int waves = blockDim.x / GM_WAVE;
     for (int64_t v = (int64_t)blockIdx.x * waves + wid; v < n; v += (int64_t)gridDim.x * waves) {
-        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        const int32_t d = b - a;
-        if (d > kMidRow) {
-            if (l == 0) {
-                if (d > kBigRow) huge_list[atomicAdd(huge_count, 1)] = (int32_t)v;
-                else big_list[atomicAdd(big_count, 1)] = (int32_t)v;
-            }
-            continue;
-        }
-        if (d <= kSmallRow) {
-            int x = l < d ? col[a + l] : GM_INF_ID;
-            // bitonic sort across the 64 lanes, ascending
-#pragma unroll
-            for (int kk = 2; kk <= GM_WAVE; kk <<= 1) {
-#pragma unroll
-                for (int j = kk >> 1; j > 0; j >>= 1) {
-                    int p = __shfl_xor(x, j, GM_WAVE);
-                    bool up = (l & kk) == 0;
-                    bool low = (l & j) == 0;
-                    x = (low == up) ? min(x, p) : max(x, p);
-                }
-            }
-            int prev = __shfl_up(x, 1, GM_WAVE);
-            bool keep = x != GM_INF_ID && x != (int)v && (l == 0 || x != prev);
-            unsigned long long m = __ballot(keep);
-            if (keep) tmp[a + lanes_below(m)] = x;
-            if (l == 0) cnt[v] = __popcll(m);
-            continue;
-        }
-        // 64 < d <= 1024: bitonic sort in this wave's LDS slice
-        int P = 128;
-        while (P < d) P <<= 1;
-        for (int i = l; i < P; i += GM_WAVE) buf[i] = i < d ? col[a + i] : GM_INF_ID;
-        wave_sync();
-        for (int kk = 2; kk <= P; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int i = l; i < P; i += GM_WAVE) {
-                    int q = i ^ j;
-                    if (q > i) {
-                        int x = buf[i], y = buf[q];
-                        bool up = (i & kk) == 0;
-                        if ((x > y) == up) { buf[i] = y; buf[q] = x; }
-                    }
-                }
-                wave_sync();
-            }
-        }
-        int base = 0;
-        for (int c = 0; c < P; c += GM_WAVE) {
-            int i = c + l;
-            int x = buf[i];
-            bool keep = x != GM_INF_ID && x != (int)v && (i == 0 || x != buf[i - 1]);
-            unsigned long long m = __ballot(keep);
-            if (keep) tmp[a + base + lanes_below(m)] = x;
-            base += __popcll(m);
-        }
-        if (l == 0) cnt[v] = base;
-        wave_sync();
+        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
+        if (d <= kTinyRow) continue;
+        canon_one_row(v, a, d, col, tmp, cnt, big_list, big_count, huge_list, huge_count);
     }
 }
 
@@ -421,6 +497,8 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)2, 0);
+    hipLaunchKernelGGL(canon_tiny_kernel, dim3(grid_for((n + 3) / 4, kCanonBlock / GM_WAVE, 32768)),
+                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, tmp, cnt);
     hipLaunchKernelGGL(canon_rows_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 32768)),
                        dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, tmp, cnt, big, counters, huge,
                        counters + 1);
