@@ -32,6 +32,14 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevelBlock = 256;
+#ifndef GM_GATHER_BATCH
+#define GM_GATHER_BATCH 8
+#endif
+constexpr int kGatherBatch = GM_GATHER_BATCH;   // neighbour loads in flight per thread
+#ifndef GM_HEAVY_BATCH
+#define GM_HEAVY_BATCH 4
+#endif
+constexpr int kHeavyBatch = GM_HEAVY_BATCH;     // neighbour loads in flight per heavy-wave lane
 constexpr int kFullCheckLevels = 32;  // levels up to which a finished group is detected
 constexpr int kCountLevels = 16;
 constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
@@ -117,17 +125,27 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     Counters c{};
     const size_t gbase = (size_t)g * a.n * WORDS;
     const uint64_t *__restrict__ fr = a.front[level & 1];
-    if (vb < light_blocks) {
+    // heavy-vertex waves come first in launch order: the longest rows start
+    // early instead of forming the tail of the level
+    const int heavy_blocks = per_group - light_blocks;
+    if (vb >= heavy_blocks) {
+        const int32_t lb = vb - heavy_blocks;
         // one thread per (vertex, word): commit for every vertex; the search
         // of vertices of degree > heavy_deg is left to the heavy waves (except
         // at level 1, where all are searched here)
-        const int64_t idx = (int64_t)vb * kLevelBlock + threadIdx.x;
+        const int64_t idx = (int64_t)lb * kLevelBlock + threadIdx.x;
         const int32_t v = (int32_t)(idx >> LW);
         const int w = (int)(idx & (WORDS - 1));
         int cols = 0;
         if (v < a.n) {
             const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
             const size_t me = gbase + ((size_t)v << LW) + w;
+            // the first batch of neighbour ids is read before the commit, so
+            // that its latency overlaps the commit's loads
+            const bool search = level >= 2 && !commit_only && e1 - e0 <= a.heavy_deg;
+            int32_t u0[kGatherBatch];
+#pragma unroll
+            for (int i = 0; i < kGatherBatch; ++i) u0[i] = search && e0 + i < e1 ? a.col[e0 + i] : -1;
             const uint64_t vis = commit_word(a, level, me, c);
             if (level == 1 || e1 - e0 <= a.heavy_deg) {
                 if (!commit_only) {
@@ -154,17 +172,17 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                                 if (s >= 0) acc |= 1ull << (s - gs0);
                             }
                         } else {
-                            for (int32_t e = e0; e < e1; e += 4) {
-                                // four independent neighbour loads in flight
-                                const int32_t u0 = a.col[e];
-                                const int32_t u1 = e + 1 < e1 ? a.col[e + 1] : -1;
-                                const int32_t u2 = e + 2 < e1 ? a.col[e + 2] : -1;
-                                const int32_t u3 = e + 3 < e1 ? a.col[e + 3] : -1;
-                                uint64_t x = fr[gbase + ((size_t)u0 << LW) + w];
-                                if (u1 >= 0) x |= fr[gbase + ((size_t)u1 << LW) + w];
-                                if (u2 >= 0) x |= fr[gbase + ((size_t)u2 << LW) + w];
-                                if (u3 >= 0) x |= fr[gbase + ((size_t)u3 << LW) + w];
-                                const int got = min(4, e1 - e);
+                            for (int32_t e = e0; e < e1; e += kGatherBatch) {
+                                // kGatherBatch independent neighbour loads in flight
+                                int32_t u[kGatherBatch];
+#pragma unroll
+                                for (int i = 0; i < kGatherBatch; ++i)
+                                    u[i] = e == e0 ? u0[i] : (e + i < e1 ? a.col[e + i] : -1);
+                                uint64_t x = 0;
+#pragma unroll
+                                for (int i = 0; i < kGatherBatch; ++i)
+                                    if (u[i] >= 0) x |= fr[gbase + ((size_t)u[i] << LW) + w];
+                                const int got = min(kGatherBatch, e1 - e);
                                 cols += got;
                                 c.v[kFieldGathers] += got;
                                 acc |= x;
@@ -184,7 +202,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
         if (w == 0) c.v[kFieldCols] += cols;
     } else if (level >= 2) {
         // one wave per heavy vertex: lane = (neighbour group, word)
-        const int32_t hidx = (vb - light_blocks) * (kLevelBlock / GM_WAVE) + wid;
+        const int32_t hidx = vb * (kLevelBlock / GM_WAVE) + wid;
         if (hidx < a.n_heavy) {
             const int32_t v = a.heavy[hidx];
             const int w = l & (WORDS - 1), grp = l >> LW;
@@ -201,10 +219,10 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                 if (__ballot(unv != 0ull)) {
                     const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
                     uint64_t acc = 0;
-                    for (int32_t base = e0; base < e1; base += 4 * G) {
+                    for (int32_t base = e0; base < e1; base += kHeavyBatch * G) {
                         int got = 0;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
+                        for (int i = 0; i < kHeavyBatch; ++i) {
                             const int32_t e = base + grp + G * i;
                             if (e < e1) {
                                 acc |= fr[gbase + ((size_t)a.col[e] << LW) + w];
