@@ -329,7 +329,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e != hipSuccess) return hip_status(e, "source multiplicities");
     }
 
-    const int words = choose_words(n_uniq);
+    // small graphs: every level of a group in one workgroup with its state in
+    // LDS (one 64-source word per vertex), instead of one launch per level
+    const bool fused = env_size("GUMAP_FUSED", 1) != 0 && env_size("GUMAP_FORCE_WORDS", 0) == 0 &&
+                       msbfs_fused_lds_bytes(n) <= 144 * 1024;
+    const int words = fused ? 1 : choose_words(n_uniq);
     const int W = 64 * words;
     const int32_t groups_total = (n_uniq + W - 1) / W;
     const bool full_hops = hop_matrix != nullptr || so != nullptr;   // every finite hop <= 254 is needed
@@ -392,6 +396,29 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.stats = stats;
         a.stats_groups = a.groups;
         const size_t spl = (size_t)a.groups * SP * SF;   // u64 per level this round
+        int last_level = 0;
+        bool range_error = false;
+        if (fused) {
+            int32_t *gout = nullptr;
+            void *hg = nullptr;
+            if ((st = scratch_get(kSlotGroupOut, (size_t)a.groups * 2 * sizeof(int32_t), (void **)&gout))) return st;
+            if ((st = host_scratch_get((size_t)a.groups * 2 * sizeof(int32_t) + 256, &hg))) return st;
+            e = hipMemsetAsync(a.planes, 0, (size_t)planes_alloc * arr * 8, s);
+            const int mark = prof_begin("msbfs_level", s);
+            if (e == hipSuccess) e = launch_msbfs_fused(a, L_cap, full_hops, gout, s);
+            prof_end(mark, s, 0.0);
+            if (e == hipSuccess) e = hipMemcpyAsync(hg, gout, (size_t)a.groups * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_status(e, "bfs (fused)");
+            const int32_t *hgo = (const int32_t *)hg;
+            for (int32_t q = 0; q < a.groups; ++q) {
+                last_level = std::max(last_level, (int)hgo[2 * q]);
+                range_error |= hgo[2 * q + 1] != 0;
+            }
+            // per level and group: row pointers and adjacency (read at most
+            // once each) and the three LDS state words per vertex
+            prof_set_bytes(mark, (double)(last_level + 1) * a.groups * (8.0 * n + 4.0 * g->nnz + 24.0 * n));
+        } else {
         e = hipMemsetAsync(a.front[1], 0, 2 * arr * 8, s);  // front[1] and visited
         if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * spl * 8, s);
         if (e == hipSuccess) e = launch_msbfs_init(a, s);
@@ -431,9 +458,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         // about 1.5x the depth a graph of this mean degree reaches (a level
         // launched past the end returns at once); later batches grow
         const double mean_deg = std::max(2.0, (double)g->nnz / std::max(1, n));
-        int L = 1, last_level = 0;
+        int L = 1;
         int chunk = (int)std::min(16.0, std::max(4.0, std::ceil(1.5 * std::log((double)n) / std::log(mean_deg)) + 2));
-        bool done = false, range_error = false;
+        bool done = false;
         while (!done) {
             const int first = L;
             for (int c2 = 0; c2 < chunk && L <= L_cap; ++c2, ++L) {
@@ -483,6 +510,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             chunk = std::max(8, L / 2);
         }
+        }   // per-level launches
         if (range_error)
             return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
         const int planes_used = bit_length(last_level);

@@ -69,6 +69,12 @@ int msbfs_stat_spread();
 hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, int32_t *heavy, int32_t *info,
                              hipStream_t s);
 hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
+// Small graphs (words == 1, msbfs_fused_lds_bytes(n) of LDS): every level of
+// each group in one workgroup, replacing init + the per-level launches; the
+// planes must be zero beforehand.  group_out[2g] = last level with new
+// vertices, group_out[2g + 1] = hop-range flag.
+size_t msbfs_fused_lds_bytes(int32_t n);
+hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t *group_out, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s);

@@ -32,6 +32,7 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevelBlock = 256;
+constexpr int kFusedBlock = 1024;
 #ifndef GM_GATHER_BATCH
 #define GM_GATHER_BATCH 8
 #endif
@@ -259,6 +260,78 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
             atomicAdd(&a.stats[(((size_t)level * a.stats_groups + g) * kSpread + (vb & (kSpread - 1))) *
                                    kStatFields + threadIdx.x],
                       t);
+    }
+}
+
+// Small graphs: all levels of one group in one workgroup, the frontier and
+// visited words (one 64-source word per vertex) in LDS, the bit-planes in
+// global memory for the hop-row transpose.  Same levels, commits and stop
+// rules as the one-launch-per-level path; per group, group_out[2g] = last
+// level that found vertices and group_out[2g + 1] = 1 if a hop above 254
+// was found while every finite hop is needed.
+__global__ void __launch_bounds__(kFusedBlock)
+msbfs_fused_kernel(MsbfsArgs a, int L_cap, int full_hops, int32_t *group_out)
+{
+    extern __shared__ uint64_t fsm[];
+    const int32_t n = a.n, g = blockIdx.x;
+    uint64_t *front0 = fsm, *front1 = fsm + n, *vis = fsm + 2 * (size_t)n;
+    __shared__ unsigned long long red[kFusedBlock / GM_WAVE];
+    const uint64_t valid = word_valid_mask(a.n_slots, g * 64);
+    for (int32_t v = threadIdx.x; v < n; v += kFusedBlock) {
+        const int32_t sl = a.slot_of[v];
+        front1[v] = (sl >= a.slot0 + g * 64 && sl < a.slot0 + g * 64 + 64) ? 1ull << (sl - a.slot0 - g * 64) : 0ull;
+        front0[v] = 0ull;
+        vis[v] = 0ull;
+    }
+    __syncthreads();
+    const size_t gbase = (size_t)g * n;
+    int last = 0, range = 0;
+    for (int L = 1;; ++L) {
+        uint64_t *cur = (L & 1) ? front1 : front0, *nxt = (L & 1) ? front0 : front1;
+        const bool search = L <= L_cap;
+        unsigned long long found = 0;
+        for (int32_t v = threadIdx.x; v < n; v += kFusedBlock) {
+            const uint64_t f = cur[v];
+            uint64_t vv = vis[v];
+            if (f) {
+                vv |= f;
+                vis[v] = vv;
+                const int hop = L - 1;
+                for (int b = 0; b < 8; ++b)
+                    if ((hop >> b) & 1) a.planes[(size_t)b * a.plane_stride + gbase + v] |= f;
+            }
+            if (!search) continue;
+            const uint64_t unv = ~vv & valid;
+            uint64_t acc = 0;
+            if (unv) {
+                for (int32_t e = a.row_ptr[v]; e < a.row_ptr[v + 1]; ++e) {
+                    acc |= cur[a.col[e]];
+                    if ((acc & unv) == unv) break;
+                }
+            }
+            const uint64_t nw = acc & unv;
+            nxt[v] = nw;
+            found += __popcll(nw);
+        }
+        found = wave_sum_u64(found);
+        if (lane() == 0) red[threadIdx.x / GM_WAVE] = found;
+        __syncthreads();
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int q = 0; q < kFusedBlock / GM_WAVE; ++q) tot += red[q];
+        __syncthreads();
+        if (!search) break;                  // the commit-only step after the hop cap
+        if (tot == 0) break;                 // level L found nothing: hop L-1 was the last
+        last = L;
+        if (full_hops && L == 255) {
+            range = 1;
+            break;
+        }
+    }
+    for (int32_t v = threadIdx.x; v < n; v += kFusedBlock) a.visited[gbase + v] = vis[v];
+    if (threadIdx.x == 0) {
+        group_out[2 * g] = last;
+        group_out[2 * g + 1] = range;
     }
 }
 
@@ -588,6 +661,24 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
     case 8: hipLaunchKernelGGL(msbfs_level_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+size_t msbfs_fused_lds_bytes(int32_t n) { return 3 * (size_t)n * sizeof(uint64_t); }
+
+hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t *group_out, hipStream_t s)
+{
+    if (a.words != 1 || a.groups <= 0) return hipErrorInvalidValue;
+    const size_t lds = msbfs_fused_lds_bytes(a.n);
+    static size_t lds_set = 0;
+    if (lds > 48 * 1024 && lds > lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)msbfs_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set = lds;
+    }
+    hipLaunchKernelGGL(msbfs_fused_kernel, dim3(a.groups), dim3(kFusedBlock), lds, s, a, L_cap, full_hops ? 1 : 0,
+                       group_out);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ enum ScratchSlot {
     kSlotScanTmp,
     kSlotCount,
     kSlotMult,
+    kSlotGroupOut,
     kScratchSlots
 };
 
