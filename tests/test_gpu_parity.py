@@ -272,3 +272,37 @@ def test_membership_synthetic_rows(gumap, k):
     w, rho, sigma = gumap.membership(hops)
     ow, orho, osig = O.membership(oh)
     assert_weights_close(w.cpu().numpy(), ow, rho.cpu().numpy(), orho, sigma.cpu().numpy(), osig)
+
+
+@pytest.mark.parametrize("name,g", [("grid", G.grid_2d(40, 37)), ("ba", G.ba(3000, 3, 95)),
+                                    ("union", G.disjoint_union([G.path(90), G.star(30), G.empty(4)]))])
+def test_fused_small_graph_path_equals_per_level(gumap, monkeypatch, name, g):
+    """The one-launch small-graph BFS and the per-level launches give the
+    same rows and hop matrices (with and without the hop cap of k)."""
+    import torch
+    rp, ci = to_dev(g)
+    src = torch.from_numpy(G.sample_sources(g.n, min(g.n, 700), 96)).cuda()
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("GUMAP_FUSED", fused)
+        a = gumap.knn_build(rp, ci, 15, hop_matrix=True, flags=gumap.CSR_SORTED)
+        b = gumap.knn_build(rp, ci, 6, sources=src, hop_matrix=False, flags=gumap.CSR_SORTED)
+        out[fused] = [t.cpu().numpy() for t in a if t is not None] + [t.cpu().numpy() for t in b[:2]]
+    for x, y in zip(out["1"], out["0"]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n,fused", [(300, "1"), (300, "0"), (7000, "1")])
+def test_hop_range_error_both_paths(gumap, monkeypatch, n, fused):
+    """A hop above 254 in a requested hop matrix is ERANGE on the one-launch
+    path (n = 300), the per-level path (forced off, and n = 7000 above the
+    one-launch LDS limit)."""
+    import torch
+    monkeypatch.setenv("GUMAP_FUSED", fused)
+    g = G.path(n)
+    rp, ci = to_dev(g)
+    src = None if n < 1000 else torch.arange(8, dtype=torch.int32).cuda()
+    print("range n=%d fused=%s" % (n, fused), flush=True)
+    with pytest.raises(gumap.GumapError) as ei:
+        gumap.knn_build(rp, ci, 3, sources=src, hop_matrix=True, flags=gumap.CSR_SORTED)
+    assert ei.value.status == gumap.ERANGE
