@@ -3,7 +3,9 @@
 Plain, slow, obviously correct CPU statement of the BFS kNN construction of
 arXiv 2509.19703 (GUMAP steps C0/C1 of Alg. 1, PartialBFS of Alg. 4 in
 Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1) and of the drawing
-quality metrics of Sec. 5.1 computed on the same BFS.  Only ``tests/``,
+quality metrics of Sec. 5.1 computed on the same BFS, and of the layout step C2
+that follows (fuzzy union of the kNN weights, edge shuffle and the sliding
+window GradSample of Alg. 5).  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
 it.  It shares no code with the GPU library and the GPU library never calls
 it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
@@ -49,6 +51,15 @@ def _load():
         lib.oracle_membership.argtypes = [i64, i32, vp, vp, vp, vp, ctypes.c_int]
         lib.oracle_stress.argtypes = [i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
         lib.oracle_neighborhood.argtypes = [i32, vp, vp, vp, i32, vp, i64, vp, vp, ctypes.c_int]
+        lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_splitmix64.restype = ctypes.c_uint64
+        lib.oracle_fuzzy_union.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, vp]
+        lib.oracle_edge_shuffle.argtypes = [i32, vp, vp, vp, ctypes.c_uint64, vp, vp, vp]
+        d = ctypes.c_double
+        lib.oracle_grad_sample.argtypes = [i32, i64, vp, vp, vp, vp, d, d, d, d, i64, i32, i32, ctypes.c_uint64,
+                                           i32, i32, vp]
+        for f in (lib.oracle_fuzzy_union, lib.oracle_edge_shuffle, lib.oracle_grad_sample):
+            f.restype = ctypes.c_int
         for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership,
                   lib.oracle_stress, lib.oracle_neighborhood):
             f.restype = ctypes.c_int
@@ -179,3 +190,68 @@ def neighborhood_preservation(g, xy: np.ndarray, r: int = 2, threads: int | None
     score, _ = neighborhood_scores(g, xy, r, threads=threads)
     ok = ~np.isnan(score)
     return float(score[ok].sum()), int(ok.sum())
+
+
+# ---------------------------------------------------------------- layout C2 --
+def splitmix64(seed: int, i: int) -> int:
+    """The i-th output (i >= 1) of SplitMix64 seeded with ``seed``."""
+    return int(_load().oracle_splitmix64(ctypes.c_uint64(seed & (2**64 - 1)), ctypes.c_uint64(i & (2**64 - 1))))
+
+
+def fuzzy_union(ids: np.ndarray, weights: np.ndarray):
+    """Symmetric fuzzy union of directed kNN weights.
+
+    ``ids`` int32[n, k], ``weights`` float32[n, k] -> ``(row_ptr int32[n+1],
+    col int32[nnz], val float32[nnz])`` with ascending columns per row."""
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    n, k = ids.shape
+    cap = max(1, 2 * n * k)
+    rp = np.empty(n + 1, dtype=np.int32)
+    col = np.empty(cap, dtype=np.int32)
+    val = np.empty(cap, dtype=np.float32)
+    nnz = np.zeros(1, dtype=np.int64)
+    st = _load().oracle_fuzzy_union(n, k, _ptr(ids), _ptr(w), _ptr(rp), _ptr(col), _ptr(val), cap, _ptr(nnz))
+    if st:
+        raise OracleError(st)
+    m = int(nnz[0])
+    return rp, col[:m].copy(), val[:m].copy()
+
+
+def edge_shuffle(row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray, seed: int):
+    """E_k in shuffled order: ``(head int32[m], tail int32[m], w float32[m])``."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float32)
+    n = rp.shape[0] - 1
+    m = int(rp[-1])
+    head = np.empty(max(m, 1), dtype=np.int32)
+    tail = np.empty(max(m, 1), dtype=np.int32)
+    w = np.empty(max(m, 1), dtype=np.float32)
+    st = _load().oracle_edge_shuffle(n, _ptr(rp), _ptr(col), _ptr(val), ctypes.c_uint64(seed & (2**64 - 1)),
+                                     _ptr(head), _ptr(tail), _ptr(w))
+    if st:
+        raise OracleError(st)
+    return head[:m], tail[:m], w[:m]
+
+
+def grad_sample(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, gamma: float = 1.0,
+                alpha0: float = 1.0, window: int, neg: int = 5, t: int, seed: int, it_begin: int = 0,
+                it_end: int | None = None, visits: bool = False):
+    """GradSample (Alg. 5) iterations [it_begin, it_end) of a run of ``t``.
+
+    Returns the new float32[n, 2] drawing (and the per-position visit counts
+    when ``visits``)."""
+    head = np.ascontiguousarray(head, dtype=np.int32)
+    tail = np.ascontiguousarray(tail, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    out = np.ascontiguousarray(np.array(xy, dtype=np.float32).reshape(n, 2))
+    m = int(head.shape[0])
+    vis = np.zeros(max(m, 1), dtype=np.int32) if visits else None
+    it_end = t if it_end is None else it_end
+    st = _load().oracle_grad_sample(int(n), m, _ptr(head), _ptr(tail), _ptr(w), _ptr(out), float(a), float(b),
+                                    float(gamma), float(alpha0), int(window), int(neg), int(t),
+                                    ctypes.c_uint64(seed & (2**64 - 1)), int(it_begin), int(it_end), _ptr(vis))
+    if st:
+        raise OracleError(st)
+    return (out, vis[:m]) if visits else out

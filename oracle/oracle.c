@@ -19,6 +19,12 @@
  *                        distances (Sec. 5.1, quality metrics)
  *   oracle_neighborhood  neighbourhood preservation of a drawing, per vertex
  *                        (Sec. 5.1, quality metrics)
+ *   oracle_splitmix64    the SplitMix64 generator (published definition)
+ *   oracle_fuzzy_union   symmetric fuzzy union of the kNN membership weights
+ *                        (UMAP's graph symmetrisation before step C2)
+ *   oracle_edge_shuffle  shuffled edge array E_k (Alg. 5, first step)
+ *   oracle_grad_sample   sliding-window gradient iterations of the layout
+ *                        (Alg. 5 GradSample, cost C of Sec. 2.1)
  *
  * Readings where the paper is silent or garbled (each is listed with its
  * justification in the design notes):
@@ -45,7 +51,12 @@
  *     the drawing, ordered by squared Euclidean distance (FP64, computed as
  *     dx*dx + dy*dy without fused multiply-add) and then by id; a vertex's
  *     score is |N_G & N_D| / |N_G | N_D|, undefined (NaN) when N_G is empty;
- *     the metric sums the defined scores.
+ *     the metric sums the defined scores;
+ *   - layout step: the readings are stated at each function below (fuzzy
+ *     union as in UMAP, E_k holding both directions of each edge, windows
+ *     of s consecutive positions, synchronous update of a window in fixed
+ *     point, UMAP's attractive and negative-sample moves scaled by the edge
+ *     weight, learning rate alpha0 (1 - it / t)).
  *
  * Threads: rows are independent; `nthreads` worker threads take rows from a
  * shared counter.  This parallelism does not change any result.
@@ -531,4 +542,234 @@ int oracle_neighborhood(int32_t n, const int32_t *row_ptr, const int32_t *col_id
     np_job_t j = {n, r, row_ptr, col_idx, xy, verts, score, ball};
     const size_t nn = (size_t)(n > 0 ? n : 1);
     return run_rows(verts ? rows : n, nthreads, &j, np_row, nn * (sizeof(int32_t) + sizeof(np_key_t) + 1));
+}
+
+/* ========================================================================
+ * Layout step C2 of SL-GUMAP (Sec. 2.1 cost C, Sec. 3.3 Alg. 3 and Alg. 5
+ * GradSample), after the kNN graph and its membership weights.
+ * ====================================================================== */
+
+/* ------------------------------------------------------------------------
+ * SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the i-th output (i >= 1) of the stream seeded
+ * with `seed` mixes seed + i * 0x9E3779B97F4A7C15 by two xor-shift-multiply
+ * rounds and a final xor-shift.
+ * ---------------------------------------------------------------------- */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------------
+ * Fuzzy union of the directed kNN membership graph (UMAP's symmetrisation,
+ * which the paper inherits from its UMAP implementation, Sec. 4.1): with
+ * A[i][j] = weight of j in row i (0 when j is not in row i), the symmetric
+ * graph has U[i][j] = A[i][j] + A[j][i] - A[i][j] * A[j][i] for every pair
+ * where this is positive.  Evaluated in FP64 as (a + b) - a * b without
+ * fused multiply-add and rounded to float.
+ * Output: CSR with n = rows, columns ascending in each row; `cap` entries
+ * of capacity (2 * rows * k always suffices); *nnz receives the count.
+ * ---------------------------------------------------------------------- */
+typedef struct { int32_t r, c; } rc_t;
+
+static int cmp_rc(const void *a, const void *b)
+{
+    const rc_t *x = (const rc_t *)a, *y = (const rc_t *)b;
+    if (x->r != y->r) return (x->r > y->r) - (x->r < y->r);
+    return (x->c > y->c) - (x->c < y->c);
+}
+
+static double knn_weight(int32_t k, const int32_t *ids, const float *w, int32_t i, int32_t j)
+{
+    for (int32_t q = 0; q < k; ++q)
+        if (ids[(size_t)i * k + q] == j) return (double)w[(size_t)i * k + q];
+    return 0.0;
+}
+
+int oracle_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *w, int32_t *row_ptr,
+                       int32_t *col, float *val, int64_t cap, int64_t *nnz)
+{
+    if (rows < 0 || k < 1 || !row_ptr || !nnz) return ORACLE_EINVAL;
+    const size_t cells = (size_t)rows * (size_t)k;
+    rc_t *cand = (rc_t *)malloc((2 * cells + 1) * sizeof(rc_t));
+    if (!cand) return ORACLE_ENOMEM;
+    size_t m = 0;
+    for (int32_t i = 0; i < rows; ++i)
+        for (int32_t q = 0; q < k; ++q) {
+            const int32_t j = ids[(size_t)i * k + q];
+            if (j < 0) continue;
+            if (j >= rows || j == i) { free(cand); return ORACLE_EINVAL; }
+            cand[m].r = i; cand[m].c = j; ++m;
+            cand[m].r = j; cand[m].c = i; ++m;
+        }
+    qsort(cand, m, sizeof(rc_t), cmp_rc);
+    int64_t out = 0;
+    for (int32_t i = 0; i <= rows; ++i) row_ptr[i] = 0;
+    for (size_t e = 0; e < m; ++e) {
+        if (e > 0 && cand[e].r == cand[e - 1].r && cand[e].c == cand[e - 1].c) continue;
+        const double a = knn_weight(k, ids, w, cand[e].r, cand[e].c);
+        const double b = knn_weight(k, ids, w, cand[e].c, cand[e].r);
+        const double s = a + b;
+        const double p = a * b;
+        const double u = s - p;
+        if (!(u > 0.0)) continue;
+        if (out >= cap) { free(cand); return ORACLE_ERANGE; }
+        col[out] = cand[e].c;
+        val[out] = (float)u;
+        ++out;
+        ++row_ptr[cand[e].r + 1];
+    }
+    for (int32_t i = 0; i < rows; ++i) row_ptr[i + 1] += row_ptr[i];
+    *nnz = out;
+    free(cand);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Shuffle of the edge array E_k (Alg. 5, first step): E_k lists every
+ * stored entry (i, j, U[i][j]) of the symmetric graph, so each undirected
+ * edge appears once per direction, as in the positive-sample arrays of
+ * UMAP's optimiser.  Entry e (CSR order) gets the key
+ * splitmix64(seed, e + 1); the shuffled order sorts by (key, e).
+ * ---------------------------------------------------------------------- */
+typedef struct { uint64_t key; int64_t e; } shuf_t;
+
+static int cmp_shuf(const void *a, const void *b)
+{
+    const shuf_t *x = (const shuf_t *)a, *y = (const shuf_t *)b;
+    if (x->key != y->key) return (x->key > y->key) - (x->key < y->key);
+    return (x->e > y->e) - (x->e < y->e);
+}
+
+int oracle_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, uint64_t seed,
+                        int32_t *head, int32_t *tail, float *w)
+{
+    if (n < 0 || !row_ptr) return ORACLE_EINVAL;
+    const int64_t m = row_ptr[n];
+    shuf_t *ks = (shuf_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(shuf_t));
+    int32_t *row_of = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    if (!ks || !row_of) { free(ks); free(row_of); return ORACLE_ENOMEM; }
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) row_of[e] = i;
+    for (int64_t e = 0; e < m; ++e) {
+        ks[e].key = oracle_splitmix64(seed, (uint64_t)e + 1);
+        ks[e].e = e;
+    }
+    qsort(ks, (size_t)m, sizeof(shuf_t), cmp_shuf);
+    for (int64_t p = 0; p < m; ++p) {
+        head[p] = row_of[ks[p].e];
+        tail[p] = col[ks[p].e];
+        w[p] = val[ks[p].e];
+    }
+    free(ks);
+    free(row_of);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * GradSample (Alg. 5) on a 2-D drawing.  Positions are held in fixed point
+ * P = round(X * 2^32) (int64 per coordinate, round half to even), so that
+ * the sum of the moves of a window does not depend on their order.
+ *
+ * s = window (edges per iteration, 1 <= s <= m).  Iteration it in
+ * [it_begin, it_end) of a run of t iterations:
+ *   lr = alpha0 * (1 - it / t)      (UMAP's linear learning-rate decay)
+ *   the window holds the array positions (it * s + l) mod m, l = 0..s-1,
+ *   i.e. consecutive windows slide over the shuffled array without gaps;
+ *   every move of the window is computed from the positions at the start of
+ *   the window and the moves are added afterwards (synchronous window).
+ * For the window entry (a, b, h) at position l:
+ *   D = X_a - X_b, d2 = Dx*Dx + Dy*Dy, T = d2^beta;
+ *   attraction (gradient of h * log(1 + alpha_ab * d^(2 beta)), the
+ *   attractive part of the cross-entropy C of Sec. 2.1 with
+ *   w = 1 / (1 + alpha_ab * d^(2 beta))):
+ *     c = -2 alpha_ab beta T / (d2 (1 + alpha_ab T)) if d2 > 0 else 0,
+ *     g = clip(c * D, -4, 4) per coordinate,
+ *     X_a += lr * h * g,  X_b -= lr * h * g;
+ *   repulsion (negative sampling of UMAP's optimiser, neg samples): the
+ *   q-th sample is vertex v = splitmix64(seed, ((it * s + l) * neg + q) + 1)
+ *   mod n; v == a is skipped; with E = X_a - X_v, e2 = |E|^2, T = e2^beta:
+ *     c = 2 gamma beta / ((0.001 + e2) (1 + alpha_ab T)),
+ *     g = clip(c * E, -4, 4) if e2 > 0, else 4 in each coordinate,
+ *     X_a += lr * h * g.
+ * Each move lr * h * g is rounded to the fixed-point grid on its own.
+ * The FP64 expressions are evaluated in exactly the order written, without
+ * fused multiply-add.  visits (optional) counts how often each array
+ * position was processed.
+ * ---------------------------------------------------------------------- */
+static double clip4(double v)
+{
+    return v > 4.0 ? 4.0 : (v < -4.0 ? -4.0 : v);
+}
+
+int oracle_grad_sample(int32_t n, int64_t m, const int32_t *head, const int32_t *tail, const float *w, float *xy,
+                       double alpha_ab, double beta, double gamma, double alpha0, int64_t s, int32_t neg,
+                       int32_t t, uint64_t seed, int32_t it_begin, int32_t it_end, int32_t *visits)
+{
+    if (n < 0 || m < 0 || neg < 0 || t < 1 || it_begin < 0 || it_end > t || it_begin > it_end) return ORACLE_EINVAL;
+    if (m == 0 || n == 0 || it_begin == it_end) return ORACLE_OK;
+    if (s < 1 || s > m) return ORACLE_EINVAL;
+    const double scale = 4294967296.0, inv = 1.0 / 4294967296.0;
+    int64_t *P = (int64_t *)malloc((size_t)n * 2 * sizeof(int64_t));
+    int64_t *acc = (int64_t *)calloc((size_t)n * 2, sizeof(int64_t));
+    if (!P || !acc) { free(P); free(acc); return ORACLE_ENOMEM; }
+    for (size_t i = 0; i < (size_t)n * 2; ++i) P[i] = llrint((double)xy[i] * scale);
+    for (int64_t e = 0; e < m; ++e)
+        if (head[e] < 0 || head[e] >= n || tail[e] < 0 || tail[e] >= n) { free(P); free(acc); return ORACLE_EINVAL; }
+    for (int32_t it = it_begin; it < it_end; ++it) {
+        const double lr = alpha0 * (1.0 - (double)it / (double)t);
+        const int64_t j0 = (int64_t)(((__int128)it * s) % m);
+        for (int64_t l = 0; l < s; ++l) {
+            const int64_t p = (j0 + l) % m;
+            if (visits) ++visits[p];
+            const int32_t a = head[p], b = tail[p];
+            const double lh = lr * (double)w[p];
+            const double ax = (double)P[2 * (size_t)a] * inv, ay = (double)P[2 * (size_t)a + 1] * inv;
+            const double bx = (double)P[2 * (size_t)b] * inv, by = (double)P[2 * (size_t)b + 1] * inv;
+            const double dx = ax - bx, dy = ay - by;
+            const double sx = dx * dx, sy = dy * dy;
+            const double d2 = sx + sy;
+            if (d2 > 0.0) {
+                const double T = pow(d2, beta);
+                const double num = -2.0 * alpha_ab * beta * T;
+                const double den = d2 * (1.0 + alpha_ab * T);
+                const double c = num / den;
+                const int64_t qx = llrint(lh * clip4(c * dx) * scale);
+                const int64_t qy = llrint(lh * clip4(c * dy) * scale);
+                acc[2 * (size_t)a] += qx; acc[2 * (size_t)a + 1] += qy;
+                acc[2 * (size_t)b] -= qx; acc[2 * (size_t)b + 1] -= qy;
+            }
+            for (int32_t q = 0; q < neg; ++q) {
+                const uint64_t idx = ((uint64_t)it * (uint64_t)s + (uint64_t)l) * (uint64_t)neg + (uint64_t)q;
+                const int32_t v = (int32_t)(oracle_splitmix64(seed, idx + 1) % (uint64_t)n);
+                if (v == a) continue;
+                const double vx = (double)P[2 * (size_t)v] * inv, vy = (double)P[2 * (size_t)v + 1] * inv;
+                const double ex = ax - vx, ey = ay - vy;
+                const double tx = ex * ex, ty = ey * ey;
+                const double e2 = tx + ty;
+                double gx = 4.0, gy = 4.0;
+                if (e2 > 0.0) {
+                    const double T = pow(e2, beta);
+                    const double num = 2.0 * gamma * beta;
+                    const double den = (0.001 + e2) * (1.0 + alpha_ab * T);
+                    const double c = num / den;
+                    gx = clip4(c * ex);
+                    gy = clip4(c * ey);
+                }
+                acc[2 * (size_t)a] += llrint(lh * gx * scale);
+                acc[2 * (size_t)a + 1] += llrint(lh * gy * scale);
+            }
+        }
+        for (size_t i = 0; i < (size_t)n * 2; ++i) {
+            P[i] += acc[i];
+            acc[i] = 0;
+        }
+    }
+    for (size_t i = 0; i < (size_t)n * 2; ++i) xy[i] = (float)((double)P[i] * inv);
+    free(P);
+    free(acc);
+    return ORACLE_OK;
 }

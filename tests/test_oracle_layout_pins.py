@@ -1,0 +1,262 @@
+"""Pins of the oracle's layout step (C2 of Sec. 2.1, GradSample of Alg. 5).
+
+Each check compares the oracle with something other than itself: the
+generator's published reference outputs, the fuzzy union written as a
+probability (1 - (1 - a)(1 - b)) on dense matrices, finite differences of
+the UMAP cross-entropy terms, the closed-form window schedule, and the
+independence of a synchronous window from the order of its edges.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+A_UMAP, B_UMAP = 1.5769434603113077, 0.8950608781227859
+
+
+def test_splitmix64_reference_outputs():
+    lines = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+             if l.strip() and not l.startswith("#")]
+    seed = int(lines[0][1])
+    for i, v in lines[1:]:
+        assert O.splitmix64(seed, int(i)) == int(v)
+
+
+def test_umap_default_curve_parameters():
+    """alpha, beta are UMAP's least-squares fit of 1 / (1 + a x^(2b)) to the
+    target curve of min_dist 0.1, spread 1 (1 below min_dist, exp decay
+    above)."""
+    from scipy.optimize import curve_fit
+    x = np.linspace(0, 3.0, 300)
+    y = np.where(x < 0.1, 1.0, np.exp(-(x - 0.1) / 1.0))
+    (a, b), _ = curve_fit(lambda x, a, b: 1.0 / (1.0 + a * x ** (2 * b)), x, y)
+    assert abs(a - A_UMAP) < 1e-3 and abs(b - B_UMAP) < 1e-3
+
+
+def _random_knn(n, k, seed, binary=False, zero_frac=0.2):
+    rng = np.random.default_rng(seed)
+    ids = np.full((n, k), -1, np.int32)
+    w = np.zeros((n, k), np.float32)
+    for i in range(n):
+        cnt = rng.integers(0, k + 1)
+        others = rng.permutation(np.delete(np.arange(n), i))[:cnt]
+        ids[i, :cnt] = others
+        w[i, :cnt] = 1.0 if binary else rng.uniform(0.0, 1.0, cnt).astype(np.float32)
+        w[i, :cnt][rng.uniform(size=cnt) < zero_frac] = 0.0
+    return ids, w
+
+
+def _dense(rp, col, val, n):
+    d = np.zeros((n, n))
+    for i in range(n):
+        d[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    return d
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fuzzy_union_is_probabilistic_or(seed):
+    n, k = 60, 7
+    ids, w = _random_knn(n, k, seed)
+    A = np.zeros((n, n))
+    for i in range(n):
+        for q in range(k):
+            if ids[i, q] >= 0:
+                A[i, ids[i, q]] = w[i, q]
+    U = 1.0 - (1.0 - A) * (1.0 - A.T)
+    rp, col, val = O.fuzzy_union(ids, w)
+    assert rp[0] == 0 and rp[-1] == len(col)
+    for i in range(n):
+        c = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(c) > 0)
+        assert np.array_equal(c, np.nonzero(U[i] > 0)[0])
+    D = _dense(rp, col, val, n)
+    assert np.allclose(D, U.astype(np.float32), rtol=2e-7, atol=0)
+    assert np.array_equal(D, D.T)
+    assert np.all(D >= np.maximum(A, A.T).astype(np.float32) - 1e-7)
+
+
+def test_fuzzy_union_binary_weights_is_or_of_patterns():
+    ids, w = _random_knn(50, 5, 9, binary=True, zero_frac=0.0)
+    rp, col, val = O.fuzzy_union(ids, w)
+    pat = np.zeros((50, 50), bool)
+    for i in range(50):
+        pat[i, ids[i][ids[i] >= 0]] = True
+    pat |= pat.T
+    assert np.array_equal(_dense(rp, col, val, 50) > 0, pat) and np.all(val == 1.0)
+
+
+def test_fuzzy_union_rejects_self_and_out_of_range():
+    ids = np.array([[1, 0], [0, -1]], np.int32)
+    with pytest.raises(O.OracleError):
+        O.fuzzy_union(ids, np.ones((2, 2), np.float32))
+    with pytest.raises(O.OracleError):
+        O.fuzzy_union(np.array([[2]], np.int32), np.ones((1, 1), np.float32))
+
+
+def test_edge_shuffle_is_the_keyed_permutation():
+    ids, w = _random_knn(80, 6, 4)
+    rp, col, val = O.fuzzy_union(ids, w)
+    seed = 0xC0FFEE
+    head, tail, ws = O.edge_shuffle(rp, col, val, seed)
+    m = len(col)
+    rows = np.repeat(np.arange(80), np.diff(rp))
+    keys = np.array([O.splitmix64(seed, e + 1) for e in range(m)], dtype=np.uint64)
+    order = np.lexsort((np.arange(m), keys))
+    assert np.array_equal(head, rows[order]) and np.array_equal(tail, col[order]) and np.array_equal(ws, val[order])
+
+
+def _two(xa, xb, h=1.0):
+    return np.array([0], np.int32), np.array([1], np.int32), np.array([h], np.float32), \
+        np.array([xa, xb], np.float32)
+
+
+def _attr_cost(xa, xb):
+    d2 = (xa[0] - xb[0]) ** 2 + (xa[1] - xb[1]) ** 2
+    return np.log1p(A_UMAP * d2 ** B_UMAP)
+
+
+def _rep_cost(xa, xb):
+    d2 = (xa[0] - xb[0]) ** 2 + (xa[1] - xb[1]) ** 2
+    return -np.log1p(-1.0 / (1.0 + A_UMAP * d2 ** B_UMAP))
+
+
+def _num_grad(f, xa, xb, eps=1e-6):
+    g = np.zeros(2)
+    for d in range(2):
+        p, q = np.array(xa, float), np.array(xa, float)
+        p[d] += eps
+        q[d] -= eps
+        g[d] = (f(p, xb) - f(q, xb)) / (2 * eps)
+    return g
+
+
+@pytest.mark.parametrize("xa,xb", [((0.5, 0.25), (-0.3, 0.1)), ((1.0, -2.0), (0.25, 0.5)),
+                                   ((0.0, 0.0), (3.0, 4.0))])
+def test_attraction_is_the_cross_entropy_gradient(xa, xb):
+    """With no negative samples one window moves a by -lr h grad_a of
+    h log(1 + a d^(2b)) and b by the opposite amount."""
+    h, lr = 0.7, 0.01
+    head, tail, w, xy = _two(xa, xb, h)
+    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=0, t=1, seed=1)
+    g = _num_grad(_attr_cost, np.array(xy[0], float), np.array(xy[1], float))
+    da = out[0].astype(float) - xy[0]
+    db = out[1].astype(float) - xy[1]
+    assert np.allclose(da, -lr * h * g, rtol=2e-4, atol=2e-8)
+    assert np.allclose(db, lr * h * g, rtol=2e-4, atol=2e-8)
+
+
+def test_repulsion_is_the_cross_entropy_gradient():
+    """Negative samples that hit b push a along -grad_a of gamma * (-log(1 - w))
+    (up to UMAP's 0.001 regulariser of d^2); samples hitting a are skipped."""
+    h, lr, gamma, neg, seed = 0.6, 0.01, 1.3, 40, 77
+    xa, xb = (0.5, 1.0), (2.5, 3.0)
+    head, tail, w, xy = _two(xa, xb, h)
+    kw = dict(a=A_UMAP, b=B_UMAP, gamma=gamma, alpha0=lr, window=1, t=1, seed=seed)
+    base = O.grad_sample(2, head, tail, w, xy, neg=0, **kw)
+    out = O.grad_sample(2, head, tail, w, xy, neg=neg, **kw)
+    hits = sum(O.splitmix64(seed, q + 1) % 2 == 1 for q in range(neg))
+    assert 0 < hits < neg
+    g = _num_grad(_rep_cost, np.array(xy[0], float), np.array(xy[1], float))
+    rep = out[0].astype(float) - base[0]
+    assert np.allclose(rep, -lr * h * gamma * hits * g, rtol=3e-4)
+    assert np.array_equal(out[1], base[1])
+
+
+def test_repulsion_clip_and_coincident_points():
+    h, lr, neg, seed = 1.0, 0.5, 16, 5
+    hits = sum(O.splitmix64(seed, q + 1) % 2 == 1 for q in range(neg))
+    head, tail, w, xy = _two((0.25, 0.5), (0.25, 0.5), h)      # coincident: +4 per coordinate
+    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=neg, t=1, seed=seed)
+    assert np.allclose(out[0] - xy[0], lr * h * 4.0 * hits, rtol=1e-6)
+    head, tail, w, xy = _two((0.26, 0.5), (0.25, 0.49), h)     # close: clipped at 4
+    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=neg, t=1, seed=seed)
+    base = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=0, t=1, seed=seed)
+    assert np.allclose(out[0].astype(float) - base[0], lr * h * 4.0 * hits, rtol=1e-5)
+
+
+@pytest.mark.parametrize("m,s,t", [(37, 5, 20), (10, 10, 3), (11, 1, 25), (64, 63, 7)])
+def test_window_schedule_closed_form(m, s, t):
+    rng = np.random.default_rng(m)
+    head = rng.integers(0, 20, m).astype(np.int32)
+    tail = ((head + 1 + rng.integers(0, 18, m)) % 20).astype(np.int32)
+    xy = rng.uniform(-5, 5, (20, 2)).astype(np.float32)
+    _, vis = O.grad_sample(20, head, tail, np.ones(m, np.float32), xy, a=A_UMAP, b=B_UMAP, window=s, neg=2, t=t,
+                           seed=3, visits=True)
+    x = np.arange(t * s) % m
+    assert np.array_equal(vis, np.bincount(x, minlength=m))
+
+
+def test_learning_rate_decays_linearly():
+    """Per-iteration move of a far-apart pair (attraction nearly constant) is
+    alpha0 (1 - it / t) times the first."""
+    head, tail, w, xy = _two((0.0, 0.0), (30.0, 40.0))
+    t = 8
+    moves = []
+    for it in range(t):
+        out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=1.0, window=1, neg=0, t=t, seed=1,
+                            it_begin=it, it_end=it + 1)
+        moves.append(float(out[0, 0]) - float(xy[0, 0]))
+    assert np.allclose(np.array(moves) / moves[0], 1.0 - np.arange(t) / t, rtol=1e-4)
+
+
+def test_synchronous_window_ignores_edge_order():
+    """One window over all edges (s = m, no negatives): permuting the edge
+    array leaves the result bit-identical, and each window equals the sum of
+    the single-edge moves."""
+    g = G.grid_2d(6, 7)
+    rng = np.random.default_rng(2)
+    head = np.repeat(np.arange(g.n), np.diff(g.row_ptr)).astype(np.int32)
+    tail = g.col_idx.astype(np.int32)
+    w = rng.uniform(0.2, 1.0, len(tail)).astype(np.float32)
+    xy = rng.uniform(-3, 3, (g.n, 2)).astype(np.float32)
+    m = len(tail)
+    kw = dict(a=A_UMAP, b=B_UMAP, alpha0=0.3, window=m, neg=0, t=4, seed=1)
+    r1 = O.grad_sample(g.n, head, tail, w, xy, **kw)
+    p = rng.permutation(m)
+    r2 = O.grad_sample(g.n, head[p], tail[p], w[p], xy, **kw)
+    assert np.array_equal(r1, r2)
+    one = O.grad_sample(g.n, head, tail, w, xy, **dict(kw, t=1))
+    acc = np.zeros((g.n, 2))
+    for e in range(m):
+        single = O.grad_sample(g.n, head[e:e + 1], tail[e:e + 1], w[e:e + 1], xy, **dict(kw, window=1, t=1))
+        acc += single.astype(float) - xy
+    assert np.allclose(one.astype(float) - xy, acc, atol=1e-6)
+
+
+def test_attraction_lowers_the_cost():
+    """Without negative samples and with a small rate the attractive cost
+    sum_e h log(1 + a d^(2b)) falls at every window."""
+    g = G.grid_2d(8, 8)
+    ids, hops = O.knn_partial(g, 15)
+    w, _, _ = O.membership(hops)
+    rp, col, val = O.fuzzy_union(ids, w)
+    head, tail, ws = O.edge_shuffle(rp, col, val, 11)
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(-4, 4, (g.n, 2)).astype(np.float32)
+
+    def cost(x):
+        d2 = ((x[head].astype(float) - x[tail]) ** 2).sum(1)
+        return float((ws * np.log1p(A_UMAP * d2 ** B_UMAP)).sum())
+
+    s = int(len(head) ** 0.9)
+    prev = cost(xy)
+    for it in range(10):
+        xy = O.grad_sample(g.n, head, tail, ws, xy, a=A_UMAP, b=B_UMAP, alpha0=0.02, window=s, neg=0, t=10, seed=1,
+                           it_begin=it, it_end=it + 1)
+        c = cost(xy)
+        assert c < prev
+        prev = c
+
+
+def test_grad_sample_argument_errors():
+    head, tail, w, xy = _two((0, 0), (1, 1))
+    with pytest.raises(O.OracleError):
+        O.grad_sample(2, head, tail, w, xy, a=1, b=1, window=2, t=1, seed=0)
+    with pytest.raises(O.OracleError):
+        O.grad_sample(2, head, np.array([2], np.int32), w, xy, a=1, b=1, window=1, t=1, seed=0)
+    out = O.grad_sample(2, head, tail, w, xy, a=1, b=1, window=1, t=3, seed=0, it_begin=2, it_end=2)
+    assert np.array_equal(out, xy)
