@@ -169,6 +169,91 @@ int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *we
                      float *sigma, hipStream_t stream);
 
 /*
+ * Layout step C2 (Sec. 2.1 cost C; Sec. 3.3, Alg. 3 and Alg. 5 GradSample).
+ *
+ * gumap_fuzzy_union: the symmetric graph of UMAP's fuzzy union of a
+ * directed kNN membership graph.  With A[i][j] the weight of j in row i
+ * (0 when absent), U[i][j] = A[i][j] + A[j][i] - A[i][j] * A[j][i],
+ * evaluated in FP64 as (a + b) - a * b and rounded to float; entries with
+ * U = 0 are dropped.
+ *   rows, k   the kNN has rows x k cells (rows = number of vertices)
+ *   ids       device int32[rows * k]: neighbour ids; a negative id marks an
+ *             empty slot (gumap_knn_partial pads with -1)
+ *   weights   device float[rows * k] (gumap_membership's output)
+ *   row_ptr   device int32[rows + 1] (out);  col device int32[cap],
+ *   val       device float[cap] (out): columns ascending within a row
+ *   cap       capacity of col / val; 2 * rows * k always suffices
+ *   nnz       host int64 (out): stored entries
+ * Errors: GUMAP_EINVAL (NULL pointer, rows < 0, k outside [1, 254],
+ * 2 * rows * k >= 2^31, an id at or above rows, or equal to its row),
+ * GUMAP_ERANGE (more than cap entries: *nnz holds the count needed),
+ * GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *weights, int32_t *row_ptr,
+                      int32_t *col, float *val, int64_t cap, int64_t *nnz, hipStream_t stream);
+
+/*
+ * gumap_edge_shuffle: the edge array E_k of Alg. 5 in shuffled order.  E_k
+ * lists every stored entry (i, j, w) of a symmetric CSR (so each undirected
+ * edge once per direction); entry e (CSR order) gets the key
+ * SplitMix64(seed, e + 1) (the (e + 1)-th output of the generator seeded
+ * with `seed`) and the array is ordered by (key, e).
+ *   n, row_ptr, col, val   device CSR (gumap_fuzzy_union's output)
+ *   m                      number of entries, must equal row_ptr[n]
+ *   head, tail             device int32[m] (out): the entry's row and column
+ *   w                      device float[m] (out): its weight
+ * Errors: GUMAP_EINVAL (NULL pointer, n < 0, m != row_ptr[n], m >= 2^31),
+ * GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, int64_t m,
+                       uint64_t seed, int32_t *head, int32_t *tail, float *w, hipStream_t stream);
+
+/* Parameters of gumap_grad_sample. */
+typedef struct {
+    double alpha;      /* low-dimensional similarity 1 / (1 + alpha d^(2 beta)) */
+    double beta;
+    double gamma;      /* weight of the repulsive (negative-sample) moves */
+    double alpha0;     /* learning rate of iteration 0; iteration it uses alpha0 (1 - it / t) */
+    double samp;       /* window = floor(m^samp) when window is 0 (the paper uses 0.9) */
+    int64_t window;    /* edges per iteration s, 1 <= s <= m; 0 = from samp */
+    int32_t neg;       /* negative samples per edge (>= 0) */
+    int32_t t;         /* iterations of the whole run (>= 1) */
+    uint64_t seed;     /* seed of the negative samples */
+} gumap_layout_params;
+
+/*
+ * gumap_grad_sample: iterations [it_begin, it_end) of a t-iteration
+ * GradSample run on a 2-D drawing.  Iteration it processes the entries at
+ * positions (it * s + l) mod m, l = 0..s-1, of the shuffled edge array
+ * (consecutive windows slide without gaps or overlap) at learning rate
+ * lr = alpha0 (1 - it / t).  For entry (a, b, h), with D = X_a - X_b,
+ * d2 = |D|^2 and T = d2^beta:
+ *   attraction   g = clip(c D, -4, 4), c = -2 alpha beta T / (d2 (1 + alpha T))
+ *                (0 when d2 = 0); X_a += lr h g, X_b -= lr h g;
+ *   repulsion    for q < neg: v = SplitMix64(seed, (it s + l) neg + q + 1) mod n,
+ *                skipped when v = a; with E = X_a - X_v, e2 = |E|^2:
+ *                g = clip(c E, -4, 4), c = 2 gamma beta / ((0.001 + e2)(1 + alpha e2^beta)),
+ *                or g = (4, 4) when e2 = 0; X_a += lr h g.
+ * All moves of an iteration are computed from the positions at its start
+ * and added afterwards (a synchronous window).  Positions are kept in fixed
+ * point (round(X * 2^32) in int64) during the call and every move is rounded
+ * to that grid, so results do not depend on thread scheduling; xy is read at
+ * the start and written at the end.  FP64 arithmetic throughout.  Splitting
+ * a run into several calls over consecutive iteration ranges gives the
+ * same drawing as one call, up to the rounding of xy to float between calls.
+ *   n               vertices;  xy device float[2 n] (in/out): x, y of vertex v
+ *                   at xy[2v], xy[2v + 1], each of magnitude below 2^20
+ *   m, head, tail, w  the shuffled edge array (gumap_edge_shuffle's output)
+ *   p               parameters (host)
+ * Errors: GUMAP_EINVAL (NULL pointer, n < 0, m < 0, m > 0 with n = 0,
+ * window outside [1, m], neg < 0, t < 1, iteration range outside [0, t],
+ * an endpoint outside [0, n), a coordinate out of range), GUMAP_ENOMEM,
+ * GUMAP_EDEVICE.
+ */
+int gumap_grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int32_t *tail, const float *w,
+                      const gumap_layout_params *p, int32_t it_begin, int32_t it_end, hipStream_t stream);
+
+/*
  * Many graphs at once (partial BFS + membership fused, one persistent
  * launch over all vertices of all graphs).
  * Packing: graph i has n_i = vtx_offset[i+1] - vtx_offset[i] vertices and

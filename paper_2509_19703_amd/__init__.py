@@ -42,6 +42,18 @@ class gumap_batch_tuning(ctypes.Structure):
                 ("candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
 
 
+class gumap_layout_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("alpha0", ctypes.c_double), ("samp", ctypes.c_double), ("window", ctypes.c_int64),
+                ("neg", ctypes.c_int32), ("t", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+# UMAP's curve parameters for min_dist 0.1 and spread 1 (its default fit of
+# 1 / (1 + a d^(2b)) to the target membership curve of the drawing).
+UMAP_A = 1.5769434603113077
+UMAP_B = 0.8950608781227859
+
+
 class gumap_batch(ctypes.Structure):
     _fields_ = [("n_graphs", ctypes.c_int32), ("total_vertices", ctypes.c_int64),
                 ("total_nnz", ctypes.c_int64), ("vtx_offset", ctypes.c_void_p),
@@ -101,6 +113,11 @@ def _load() -> ctypes.CDLL:
     lib.gumap_neighborhood.argtypes = [G, vp, i32, vp, i32, vp, vp, vp]
     lib.gumap_neighborhood.restype = ctypes.c_int
     lib.gumap_membership.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+    lib.gumap_fuzzy_union.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
+    lib.gumap_edge_shuffle.argtypes = [i32, vp, vp, vp, i64, ctypes.c_uint64, vp, vp, vp, vp]
+    lib.gumap_grad_sample.argtypes = [i32, vp, i64, vp, vp, vp, ctypes.POINTER(gumap_layout_params), i32, i32, vp]
+    for f in (lib.gumap_fuzzy_union, lib.gumap_edge_shuffle, lib.gumap_grad_sample):
+        f.restype = ctypes.c_int
     lib.gumap_knn_partial_batch.argtypes = [B, i32, vp, vp, vp, vp, vp, vp]
     lib.gumap_batch_plan_create.argtypes = [B, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.gumap_batch_plan_launch.argtypes = [vp, vp]
@@ -314,6 +331,72 @@ def membership(hops, stream=None):
     sigma = torch.empty(rows, dtype=torch.float32, device=hops.device)
     gumap_membership(rows, k, hops, w, rho, sigma, stream)
     return w, rho, sigma
+
+
+# ------------------------------------------------------- layout step C2 --
+def gumap_fuzzy_union(rows, k, ids, weights, row_ptr, col, val, cap, stream=None) -> int:
+    """C-ABI gumap_fuzzy_union; returns the entry count."""
+    nnz = ctypes.c_int64(0)
+    st = lib.gumap_fuzzy_union(int(rows), int(k), _ptr(ids), _ptr(weights), _ptr(row_ptr), _ptr(col), _ptr(val),
+                               int(cap), ctypes.byref(nnz), _stream(stream))
+    _check(st)
+    return nnz.value
+
+
+def fuzzy_union(ids, weights, stream=None):
+    """Symmetric fuzzy union of a directed kNN membership graph (ids int32
+    [n, k], weights float32 [n, k] on the device).  Returns (row_ptr, col, val)."""
+    torch = _torch()
+    rows, k = ids.shape
+    dev = ids.device
+    cap = 2 * rows * k
+    row_ptr = torch.empty(rows + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+    m = gumap_fuzzy_union(rows, k, ids.contiguous(), weights.contiguous(), row_ptr, col, val, cap, stream)
+    return row_ptr, col[:m], val[:m]
+
+
+def gumap_edge_shuffle(n, row_ptr, col, val, m, seed, head, tail, w, stream=None) -> int:
+    return _check(lib.gumap_edge_shuffle(int(n), _ptr(row_ptr), _ptr(col), _ptr(val), int(m),
+                                         ctypes.c_uint64(int(seed) & (2**64 - 1)), _ptr(head), _ptr(tail), _ptr(w),
+                                         _stream(stream)))
+
+
+def edge_shuffle(row_ptr, col, val, seed: int, stream=None):
+    """The edge array E_k of a symmetric CSR in shuffled order: (head, tail, w)."""
+    torch = _torch()
+    n = int(row_ptr.shape[0]) - 1
+    m = int(col.shape[0])
+    dev = row_ptr.device
+    head = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    tail = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    w = torch.empty(max(m, 1), dtype=torch.float32, device=dev)
+    gumap_edge_shuffle(n, row_ptr, col, val, m, seed, head, tail, w, stream)
+    return head[:m], tail[:m], w[:m]
+
+
+def layout_params(*, a: float = UMAP_A, b: float = UMAP_B, gamma: float = 1.0, alpha0: float = 1.0,
+                  samp: float = 0.9, window: int = 0, neg: int = 5, t: int = 200, seed: int = 0):
+    return gumap_layout_params(float(a), float(b), float(gamma), float(alpha0), float(samp), int(window), int(neg),
+                               int(t), int(seed) & (2**64 - 1))
+
+
+def gumap_grad_sample(n, xy, m, head, tail, w, params, it_begin, it_end, stream=None) -> int:
+    return _check(lib.gumap_grad_sample(int(n), _ptr(xy), int(m), _ptr(head), _ptr(tail), _ptr(w),
+                                        ctypes.byref(params), int(it_begin), int(it_end), _stream(stream)))
+
+
+def grad_sample(xy, head, tail, w, params=None, it_begin: int = 0, it_end=None, stream=None, **kw):
+    """GradSample iterations [it_begin, it_end) of a t-iteration run, in
+    place on xy (device float32 [n, 2]).  params: layout_params(...) or its
+    keyword arguments."""
+    p = params if params is not None else layout_params(**kw)
+    n = int(xy.shape[0])
+    it_end = p.t if it_end is None else it_end
+    assert xy.is_contiguous() and xy.dtype.itemsize == 4
+    gumap_grad_sample(n, xy, int(head.shape[0]), head, tail, w, p, it_begin, it_end, stream)
+    return xy
 
 
 class PackedBatch:

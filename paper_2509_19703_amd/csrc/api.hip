@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -912,6 +913,137 @@ int tune_batch(const gumap_batch *b, int32_t k, int32_t *ids, uint8_t *hops, flo
     return GUMAP_OK;
 }
 
+// ---------------------------------------------------- layout step (C2) --
+int fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *w, int32_t *row_ptr, int32_t *col,
+                float *val, int64_t cap, int64_t *nnz, hipStream_t s)
+{
+    int st;
+    if (!nnz) return set_error(GUMAP_EINVAL, "nnz is NULL");
+    *nnz = 0;
+    if (rows < 0) return set_error(GUMAP_EINVAL, "rows < 0");
+    if ((st = check_k(k))) return st;
+    if (!row_ptr) return set_error(GUMAP_EINVAL, "row_ptr is NULL");
+    if (rows == 0) {
+        hipError_t e = hipMemsetAsync(row_ptr, 0, sizeof(int32_t), s);
+        if (e != hipSuccess) return hip_status(e, "fuzzy union");
+        return finish(s, "gumap_fuzzy_union");
+    }
+    if (!ids || !w) return set_error(GUMAP_EINVAL, "ids or weights is NULL");
+    if (cap < 0 || (cap > 0 && (!col || !val))) return set_error(GUMAP_EINVAL, "col or val is NULL");
+    if (2 * (int64_t)rows * k >= (int64_t)INT32_MAX) return set_error(GUMAP_EINVAL, "2 * rows * k >= 2^31");
+    size_t tmp = 0;
+    void *scratch = nullptr;
+    char *flags = nullptr;
+    if ((st = scratch_get(kSlotUnion, union_scratch_bytes(rows, k, &tmp), &scratch))) return st;
+    if ((st = scratch_get(kSlotFlags, 256, (void **)&flags))) return st;
+    int *err = (int *)flags;
+    int64_t *dnnz = (int64_t *)(flags + 8);
+    hipError_t e = hipMemsetAsync(flags, 0, 16, s);
+    if (e != hipSuccess) return hip_status(e, "fuzzy union");
+    GM_PROF("fuzzy_union", (double)rows * k * (4.0 + 4.0 + 4.0 * k) + 2.0 * rows * k * 8.0,
+            launch_fuzzy_union(rows, k, ids, w, row_ptr, col, val, cap, dnnz, err, scratch, s));
+    if (e != hipSuccess) return hip_status(e, "fuzzy union");
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    e = hipMemcpyAsync(h, flags, 16, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_status(e, "fuzzy union");
+    if ((st = finish(s, "gumap_fuzzy_union"))) return st;
+    const int bad = *(int *)h;
+    const int64_t count = *(int64_t *)((char *)h + 8);
+    if (bad) return set_error(GUMAP_EINVAL, "a neighbour id is outside [-1, rows) or equals its row");
+    *nnz = count;
+    if (count == 0) {
+        e = hipMemsetAsync(row_ptr, 0, (size_t)(rows + 1) * sizeof(int32_t), s);
+        if (e != hipSuccess) return hip_status(e, "fuzzy union");
+        if ((st = finish(s, "gumap_fuzzy_union"))) return st;
+    }
+    if (count > cap) return set_error(GUMAP_ERANGE, "fuzzy union has %lld entries, capacity %lld",
+                                      (long long)count, (long long)cap);
+    return GUMAP_OK;
+}
+
+int edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, int64_t m, uint64_t seed,
+                 int32_t *head, int32_t *tail, float *w, hipStream_t s)
+{
+    int st;
+    if (n < 0 || m < 0) return set_error(GUMAP_EINVAL, "n < 0 or m < 0");
+    if (m >= (int64_t)INT32_MAX) return set_error(GUMAP_EINVAL, "m >= 2^31");
+    if (!row_ptr) return set_error(GUMAP_EINVAL, "row_ptr is NULL");
+    if (m > 0 && (!col || !val || !head || !tail || !w)) return set_error(GUMAP_EINVAL, "NULL array");
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    hipError_t e = hipMemcpyAsync(h, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_status(e, "edge shuffle");
+    if ((st = finish(s, "gumap_edge_shuffle"))) return st;
+    if ((int64_t)*(int32_t *)h != m) return set_error(GUMAP_EINVAL, "m (%lld) != row_ptr[n] (%d)", (long long)m,
+                                                       *(int32_t *)h);
+    if (m == 0) return GUMAP_OK;
+    size_t tmp = 0;
+    void *scratch = nullptr;
+    if ((st = scratch_get(kSlotShuffle, shuffle_scratch_bytes(m, &tmp), &scratch))) return st;
+    GM_PROF("edge_shuffle", (double)m * (4.0 + 4.0 + 4.0 + 12.0) + (double)m * 12.0 * 2.0,
+            launch_edge_shuffle(n, m, row_ptr, col, val, seed, head, tail, w, scratch, s));
+    if (e != hipSuccess) return hip_status(e, "edge shuffle");
+    return finish(s, "gumap_edge_shuffle");
+}
+
+int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int32_t *tail, const float *w,
+                const gumap_layout_params *p, int32_t it_begin, int32_t it_end, hipStream_t s)
+{
+    int st;
+    if (!p) return set_error(GUMAP_EINVAL, "params is NULL");
+    if (n < 0 || m < 0) return set_error(GUMAP_EINVAL, "n < 0 or m < 0");
+    if (m > 0 && n == 0) return set_error(GUMAP_EINVAL, "edges without vertices");
+    if (p->neg < 0 || p->t < 1) return set_error(GUMAP_EINVAL, "neg < 0 or t < 1");
+    if (it_begin < 0 || it_end > p->t || it_begin > it_end)
+        return set_error(GUMAP_EINVAL, "iteration range [%d, %d) outside [0, %d]", it_begin, it_end, p->t);
+    if (!(p->beta > 0.0) || !(p->alpha > 0.0) || !(p->samp > 0.0 || p->window > 0))
+        return set_error(GUMAP_EINVAL, "alpha, beta must be positive; samp or window must be set");
+    if (n == 0 || m == 0 || it_begin == it_end) return GUMAP_OK;
+    if (!xy || !head || !tail || !w) return set_error(GUMAP_EINVAL, "NULL array");
+    int64_t win = p->window;
+    if (win == 0) win = (int64_t)floor(pow((double)m, p->samp));
+    if (win < 1 || win > m) return set_error(GUMAP_EINVAL, "window %lld outside [1, m = %lld]", (long long)win,
+                                             (long long)m);
+    long long *pos = nullptr;
+    int *err = nullptr;
+    if ((st = scratch_get(kSlotLayoutPos, (size_t)n * 6 * sizeof(long long), (void **)&pos))) return st;
+    if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+    long long *B[3] = {pos, pos + 2 * (size_t)n, pos + 4 * (size_t)n};
+    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_edge_check(n, m, head, tail, err, s);
+    if (e == hipSuccess) e = launch_layout_init(n, xy, B[0], B[1], err, s);
+    if (e != hipSuccess) return hip_status(e, "grad sample");
+    int bad = 0;
+    if ((st = read_flag(err, &bad, s))) return st;
+    if (bad & 1) return set_error(GUMAP_EINVAL, "an edge endpoint is outside [0, n)");
+    if (bad & 2) return set_error(GUMAP_EINVAL, "a coordinate is not finite or not below 2^20 in magnitude");
+    LayoutArgs g{};
+    g.n = n;
+    g.m = m;
+    g.s = win;
+    g.head = head;
+    g.tail = tail;
+    g.w = w;
+    g.alpha = p->alpha;
+    g.beta = p->beta;
+    g.att_num = (-2.0 * p->alpha) * p->beta;
+    g.rep_num = (2.0 * p->gamma) * p->beta;
+    g.neg = p->neg;
+    g.seed = p->seed;
+    int cur = 0;
+    for (int32_t it = it_begin; it < it_end; ++it) {
+        const double lr = p->alpha0 * (1.0 - (double)it / (double)p->t);
+        GM_PROF("grad_window", (double)win * (12.0 + 16.0 + 8.0 * p->neg + 32.0) + (double)n * 48.0,
+                launch_grad_window(g, it, lr, B[cur], B[(cur + 1) % 3], B[(cur + 2) % 3], s));
+        if (e != hipSuccess) return hip_status(e, "grad sample");
+        cur = (cur + 1) % 3;
+    }
+    e = launch_layout_out(n, B[cur], xy, s);
+    if (e != hipSuccess) return hip_status(e, "grad sample");
+    return finish(s, "gumap_grad_sample");
+}
+
 }  // namespace gm
 
 // ================================================================ C-ABI ===
@@ -965,6 +1097,30 @@ int gumap_knn_partial(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
     return gm::settle(gm::knn_partial(g, k, nbr_ids, nbr_hops, stream), stream);
+}
+
+int gumap_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *weights, int32_t *row_ptr,
+                      int32_t *col, float *val, int64_t cap, int64_t *nnz, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::fuzzy_union(rows, k, ids, weights, row_ptr, col, val, cap, nnz, stream), stream);
+}
+
+int gumap_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, int64_t m,
+                       uint64_t seed, int32_t *head, int32_t *tail, float *w, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::edge_shuffle(n, row_ptr, col, val, m, seed, head, tail, w, stream), stream);
+}
+
+int gumap_grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int32_t *tail, const float *w,
+                      const gumap_layout_params *p, int32_t it_begin, int32_t it_end, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::grad_sample(n, xy, m, head, tail, w, p, it_begin, it_end, stream), stream);
 }
 
 int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *weights, float *rho,

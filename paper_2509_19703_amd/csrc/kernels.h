@@ -193,6 +193,46 @@ hipError_t launch_partial_jobs(const DevJob *jobs, const JobChunk *chunks, int32
 // Co-resident blocks of the batch kernel on the current device.
 int partial_batch_max_blocks();
 
+// ---------------------------------------------------- layout step (C2) ---
+// Fuzzy union of a directed kNN membership graph (rows x k cells) into a
+// symmetric CSR; *nnz (device) receives the entry count, entries beyond
+// `cap` are not stored.  err (device) gets bit 1 for an id out of range or
+// equal to its row.  scratch: union_scratch_bytes(rows, k, &tmp).
+size_t union_scratch_bytes(int32_t rows, int32_t k, size_t *sort_tmp);
+hipError_t launch_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *w, int32_t *row_ptr,
+                              int32_t *col, float *val, int64_t cap, int64_t *nnz, int *err, void *scratch,
+                              hipStream_t s);
+// E_k of a CSR (m = row_ptr[n] entries) ordered by (SplitMix64 key of the
+// entry position, position).  scratch: shuffle_scratch_bytes(m, &tmp).
+size_t shuffle_scratch_bytes(int64_t m, size_t *sort_tmp);
+hipError_t launch_edge_shuffle(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *val,
+                               uint64_t seed, int32_t *head, int32_t *tail, float *w, void *scratch, hipStream_t s);
+// GradSample windows over a shuffled edge array.  Positions are fixed point
+// (int64, 2^-32 units) in three rotating buffers of 2 n values.
+constexpr double kLayoutCoordLimit = 1048576.0;   // |coordinate| < 2^20 keeps P * 2^-32 exact in FP64
+struct LayoutArgs {
+    int32_t n;
+    int64_t m;                // edges in the array
+    int64_t s;                // window (edges per iteration), 1 <= s <= m
+    const int32_t *head;
+    const int32_t *tail;
+    const float *w;
+    double alpha, beta;       // curve w = 1 / (1 + alpha d^(2 beta))
+    double att_num;           // (-2 alpha) beta
+    double rep_num;           // (2 gamma) beta
+    int32_t neg;              // negative samples per edge
+    uint64_t seed;            // seed of the negative samples
+};
+// err bit 1: head or tail outside [0, n).
+hipError_t launch_edge_check(int32_t n, int64_t m, const int32_t *head, const int32_t *tail, int *err, hipStream_t s);
+// p0 = round(xy * 2^32), p1 = 0; err bit 2: a coordinate not finite or not below 2^20 in magnitude.
+hipError_t launch_layout_init(int32_t n, const float *xy, long long *p0, long long *p1, int *err, hipStream_t s);
+hipError_t launch_layout_out(int32_t n, const long long *p, float *xy, hipStream_t s);
+// Iteration `it` at learning rate lr: reads R, accumulates into N (zero on
+// entry), clears Z.
+hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
+                              long long *Z, hipStream_t s);
+
 // ----------------------------------------------------------- membership ---
 hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,
                              float *rho, float *sigma, hipStream_t s);

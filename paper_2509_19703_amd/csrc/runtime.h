@@ -45,6 +45,9 @@ enum ScratchSlot {
     kSlotCount,
     kSlotMult,
     kSlotGroupOut,
+    kSlotUnion,
+    kSlotShuffle,
+    kSlotLayoutPos,
     kScratchSlots
 };
 

@@ -33,3 +33,19 @@ def assert_weights_close(w_gpu, w_ref, rho_gpu=None, rho_ref=None, sig_gpu=None,
 def first_mismatch(a, b):
     idx = np.argwhere(np.asarray(a) != np.asarray(b))
     return None if idx.size == 0 else idx[0].tolist()
+
+
+def random_knn(n, k, seed, binary=False, zero_frac=0.2, fill=None):
+    """Seeded synthetic kNN rows: ids int32 [n, k] (distinct, never the row
+    itself, -1 padding at the end of short rows) and weights float32 [n, k]
+    in [0, 1] with a share of exact zeros (or all ones when binary)."""
+    rng = np.random.default_rng(seed)
+    ids = np.full((n, k), -1, np.int32)
+    w = np.zeros((n, k), np.float32)
+    for i in range(n):
+        cnt = min(n - 1, k if fill == "full" else int(rng.integers(0, k + 1)))
+        others = rng.permutation(np.delete(np.arange(n), i))[:cnt]
+        ids[i, :cnt] = others
+        w[i, :cnt] = 1.0 if binary else rng.uniform(0.0, 1.0, cnt).astype(np.float32)
+        w[i, :cnt][rng.uniform(size=cnt) < zero_frac] = 0.0
+    return ids, w

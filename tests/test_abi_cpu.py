@@ -28,6 +28,7 @@ def test_struct_layouts_match_header(gumap):
     assert ctypes.sizeof(gumap.gumap_graph) == 32
     assert ctypes.sizeof(gumap.gumap_batch) == 64
     assert ctypes.sizeof(gumap.gumap_batch_tuning) == 24
+    assert ctypes.sizeof(gumap.gumap_layout_params) == 64
 
 
 def test_host_side_argument_errors(gumap):
@@ -66,6 +67,33 @@ def test_host_side_argument_errors(gumap):
     assert lib.gumap_batch_plan_tuning(None, None) == gumap.EINVAL
 
 
+def test_layout_entry_points_reject_bad_arguments(gumap):
+    lib = gumap.lib
+    nnz = ctypes.c_int64(7)
+    assert lib.gumap_fuzzy_union(4, 5, None, None, None, None, None, 0, None, None) == gumap.EINVAL
+    assert lib.gumap_fuzzy_union(-1, 5, None, None, None, None, None, 0, ctypes.byref(nnz), None) == gumap.EINVAL
+    assert nnz.value == 0
+    assert lib.gumap_fuzzy_union(4, 0, None, None, None, None, None, 0, ctypes.byref(nnz), None) == gumap.EINVAL
+    assert lib.gumap_fuzzy_union(4, 255, None, None, None, None, None, 0, ctypes.byref(nnz), None) == gumap.EINVAL
+    assert lib.gumap_fuzzy_union(0, 5, None, None, None, None, None, 0, ctypes.byref(nnz), None) == gumap.EINVAL
+    assert lib.gumap_edge_shuffle(-1, None, None, None, 0, 0, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_edge_shuffle(3, None, None, None, 0, 0, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_edge_shuffle(3, None, None, None, 2**31, 0, None, None, None, None) == gumap.EINVAL
+    p = gumap.layout_params(t=10)
+    assert lib.gumap_grad_sample(2, None, 1, None, None, None, None, 0, 1, None) == gumap.EINVAL
+    assert lib.gumap_grad_sample(0, None, 0, None, None, None, ctypes.byref(p), 0, 10, None) == gumap.OK
+    assert lib.gumap_grad_sample(0, None, 3, None, None, None, ctypes.byref(p), 0, 10, None) == gumap.EINVAL
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(p), 0, 11, None) == gumap.EINVAL
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(p), 5, 4, None) == gumap.EINVAL
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(p), 4, 4, None) == gumap.OK
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(p), 0, 4, None) == gumap.EINVAL
+    bad = gumap.layout_params(t=0)
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(bad), 0, 0, None) == gumap.EINVAL
+    neg = gumap.layout_params(neg=-1)
+    assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(neg), 0, 1, None) == gumap.EINVAL
+
+
 def test_python_names_mirror_c_entry_points(gumap):
-    for name in ("gumap_knn_build", "gumap_knn_partial", "gumap_membership", "gumap_knn_partial_batch"):
+    for name in ("gumap_knn_build", "gumap_knn_partial", "gumap_membership", "gumap_knn_partial_batch",
+                 "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample"):
         assert callable(getattr(gumap, name))

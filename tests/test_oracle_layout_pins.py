@@ -14,6 +14,10 @@ import pytest
 import graphgen as G
 import oracle as O
 
+import sys
+sys.path.insert(0, os.path.dirname(__file__))
+from gpu_util import random_knn  # noqa: E402
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 A_UMAP, B_UMAP = 1.5769434603113077, 0.8950608781227859
 
@@ -38,16 +42,7 @@ def test_umap_default_curve_parameters():
 
 
 def _random_knn(n, k, seed, binary=False, zero_frac=0.2):
-    rng = np.random.default_rng(seed)
-    ids = np.full((n, k), -1, np.int32)
-    w = np.zeros((n, k), np.float32)
-    for i in range(n):
-        cnt = rng.integers(0, k + 1)
-        others = rng.permutation(np.delete(np.arange(n), i))[:cnt]
-        ids[i, :cnt] = others
-        w[i, :cnt] = 1.0 if binary else rng.uniform(0.0, 1.0, cnt).astype(np.float32)
-        w[i, :cnt][rng.uniform(size=cnt) < zero_frac] = 0.0
-    return ids, w
+    return random_knn(n, k, seed, binary=binary, zero_frac=zero_frac)
 
 
 def _dense(rp, col, val, n):
