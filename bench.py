@@ -31,7 +31,9 @@ METRIC = "GTEPS + kNN graphs/sec vs plain; p50/p99 served latency, bit-exact"
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress", "neighborhood"])
+    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress", "neighborhood",
+                                                             "layout"])
+    p.add_argument("--layout-iters", type=int, default=200)
     p.add_argument("--batch-graphs", type=int, default=2048)
     p.add_argument("--serve-jobs", type=int, default=1024)
     p.add_argument("--serve-pool", type=int, default=64)
@@ -79,6 +81,8 @@ def main():
         return bench_stress(args)
     if args.workload == "neighborhood":
         return bench_neighborhood(args)
+    if args.workload == "layout":
+        return bench_layout(args)
 
     if args.calibrate_copy:
         n_bytes = 1 << 30
@@ -403,6 +407,104 @@ def bench_neighborhood(args):
         out["cpu_baseline"] = {"value": len(verts) / t, "unit": "scored vertices/s", "cores": threads,
                                "kind": "oracle", "sample": "oracle scores of 256 of the %d vertices, scaled"
                                % len(verts)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_layout(args):
+    """SL-GUMAP's layout run on the BA graph (Alg. 3): partial BFS kNN and
+    membership (k = 15), fuzzy union, shuffle of E_k and t GradSample
+    iterations (Alg. 5, window floor(|E_k|^0.9), 5 negative samples per
+    edge) from a seeded uniform drawing (the paper starts from a spectral
+    layout; the drawing here is an input)."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    g = G.config_ba()
+    n, m_g, k, t = g.n, g.m, args.k, args.layout_iters
+    xy0 = ((G.uniform(G.BASE_SEED + 400, 2 * n).reshape(n, 2) - 0.5) * 20.0).astype(np.float32)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    gg = gm.make_graph(rp, ci, flags=gm.CSR_SORTED)
+    stream = torch.cuda.current_stream()
+    ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    hops = torch.empty((n, k), dtype=torch.uint8, device="cuda")
+    w = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    urp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    ucol = torch.empty(2 * n * k, dtype=torch.int32, device="cuda")
+    uval = torch.empty(2 * n * k, dtype=torch.float32, device="cuda")
+    head = torch.empty(2 * n * k, dtype=torch.int32, device="cuda")
+    tail = torch.empty(2 * n * k, dtype=torch.int32, device="cuda")
+    ew = torch.empty(2 * n * k, dtype=torch.float32, device="cuda")
+    xy0_d = torch.from_numpy(xy0).cuda()
+    xy = torch.empty_like(xy0_d)
+    seed_shuffle, seed_neg = G.BASE_SEED + 401, G.BASE_SEED + 402
+    res = {}
+
+    def step():
+        gm.gumap_knn_partial(gg, k, ids, hops, stream)
+        gm.gumap_membership(n, k, hops, w, None, None, stream)
+        mm = gm.gumap_fuzzy_union(n, k, ids, w, urp, ucol, uval, 2 * n * k, stream)
+        gm.gumap_edge_shuffle(n, urp, ucol, uval, mm, seed_shuffle, head, tail, ew, stream)
+        xy.copy_(xy0_d)
+        p = gm.layout_params(t=t, neg=5, samp=0.9, seed=seed_neg)
+        gm.gumap_grad_sample(n, xy, mm, head, tail, ew, p, 0, t, stream)
+        res["m"] = mm
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    dt, prof = _profiled(gm, step, steps)
+    roof, kms = _roofline(prof, steps)
+    mm = res["m"]
+    s_win = int(np.floor(mm ** 0.9))
+    samples = t * s_win
+    out = {"metric": METRIC, "value": samples / dt, "unit": "edge samples/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (2^-32 fixed-point positions)", "data": "synthetic",
+           "config": {"workload": "layout: BA n=%d m=%d; partial BFS kNN k=%d + membership + fuzzy union + "
+                                  "shuffle + %d GradSample iterations (window floor(|E_k|^0.9), 5 negative "
+                                  "samples) from a seeded uniform drawing in [-10, 10)^2" % (n, m_g, k, t),
+                      "n": n, "m": m_g, "k": k, "edges_Ek": mm, "window": s_win, "iterations": t},
+           "window_ms": kms.get("grad_window", 0.0) / t, "roofline": roof, "kernels_ms_per_step": kms}
+    out_xy = xy.cpu().numpy()
+    # quality of the drawing against the start (neighbourhood preservation, r = 2, sampled vertices)
+    verts = torch.from_numpy(G.config_ba_sources()).cuda()
+    sc1, _ = gm.neighborhood(rp, ci, xy, 2, verts, flags=gm.CSR_SORTED)
+    sc0, _ = gm.neighborhood(rp, ci, xy0_d, 2, verts, flags=gm.CSR_SORTED)
+    out["np_mean_start"] = float(torch.nanmean(sc0))
+    out["np_mean_layout"] = float(torch.nanmean(sc1))
+    if not args.no_parity or not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        t0 = time.perf_counter()
+        oi, oh = O.knn_partial(g, k, threads=threads)
+        ow, _, _ = O.membership(oh, threads=threads)
+        orp, ocol, oval = O.fuzzy_union(oi, ow)
+        eh, et, ew_ = O.edge_shuffle(orp, ocol, oval, seed_shuffle)
+        t_prep = time.perf_counter() - t0
+        few = 5
+        t0 = time.perf_counter()
+        oxy = O.grad_sample(n, eh, et, ew_, xy0, a=gm.UMAP_A, b=gm.UMAP_B, window=s_win, neg=5, t=t,
+                            seed=seed_neg, it_begin=0, it_end=few)
+        t_win = (time.perf_counter() - t0) / few
+        if not args.no_parity:
+            chk = xy0_d.clone()
+            p = gm.layout_params(t=t, neg=5, samp=0.9, seed=seed_neg)
+            gm.gumap_grad_sample(n, chk, mm, head, tail, ew, p, 0, few, stream)
+            out["parity_sampled_bit_exact"] = bool(
+                len(ocol) == mm and np.array_equal(head[:mm].cpu().numpy(), eh)
+                and np.array_equal(tail[:mm].cpu().numpy(), et) and np.array_equal(chk.cpu().numpy(), oxy))
+            out["parity_sample"] = "union + shuffled E_k, and the drawing after the first %d iterations" % few
+        if not args.no_cpu_baseline:
+            est = t_prep + t * t_win
+            out["cpu_baseline"] = {"value": samples / est, "unit": "edge samples/s", "cores": threads,
+                                   "kind": "oracle",
+                                   "sample": "oracle kNN/membership/union/shuffle in full (%d threads) and %d of %d "
+                                             "GradSample iterations (one thread), scaled; run estimate %.1f s"
+                                             % (threads, few, t, est)}
     print(json.dumps(out), flush=True)
 
 

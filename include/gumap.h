@@ -245,7 +245,7 @@ typedef struct {
  *                   at xy[2v], xy[2v + 1], each of magnitude below 2^20
  *   m, head, tail, w  the shuffled edge array (gumap_edge_shuffle's output)
  *   p               parameters (host)
- * Errors: GUMAP_EINVAL (NULL pointer, n < 0, m < 0, m > 0 with n = 0,
+ * Errors: GUMAP_EINVAL (NULL pointer, n < 0, m < 0, m >= 2^30, m > 0 with n = 0,
  * window outside [1, m], neg < 0, t < 1, iteration range outside [0, t],
  * an endpoint outside [0, n), a coordinate out of range), GUMAP_ENOMEM,
  * GUMAP_EDEVICE.

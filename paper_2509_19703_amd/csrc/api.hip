@@ -994,6 +994,7 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
     if (!p) return set_error(GUMAP_EINVAL, "params is NULL");
     if (n < 0 || m < 0) return set_error(GUMAP_EINVAL, "n < 0 or m < 0");
     if (m > 0 && n == 0) return set_error(GUMAP_EINVAL, "edges without vertices");
+    if (m >= ((int64_t)1 << 30)) return set_error(GUMAP_EINVAL, "m >= 2^30");
     if (p->neg < 0 || p->t < 1) return set_error(GUMAP_EINVAL, "neg < 0 or t < 1");
     if (it_begin < 0 || it_end > p->t || it_begin > it_end)
         return set_error(GUMAP_EINVAL, "iteration range [%d, %d) outside [0, %d]", it_begin, it_end, p->t);
@@ -1007,9 +1008,19 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
                                              (long long)m);
     long long *pos = nullptr;
     int *err = nullptr;
-    if ((st = scratch_get(kSlotLayoutPos, (size_t)n * 6 * sizeof(long long), (void **)&pos))) return st;
+    void *sort_scratch = nullptr;
+    char *inc = nullptr;
+    size_t sort_tmp = 0;
+    const size_t rec_bytes = (((size_t)(2 * m) * sizeof(uint32_t)) + 255) & ~(size_t)255;
+    void *moves = nullptr;
+    if ((st = scratch_get(kSlotLayoutMoves, (size_t)m * 32, &moves))) return st;
+    const size_t off_bytes = ((size_t)(n + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t heavy_bytes = ((size_t)n * sizeof(int32_t) + 255) & ~(size_t)255;
+    if ((st = scratch_get(kSlotLayoutPos, (size_t)n * 4 * sizeof(long long), (void **)&pos))) return st;
+    if ((st = scratch_get(kSlotLayoutSort, incidence_scratch_bytes(n, m, &sort_tmp), &sort_scratch))) return st;
+    if ((st = scratch_get(kSlotLayoutRec, rec_bytes + off_bytes + heavy_bytes + 256, (void **)&inc))) return st;
     if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
-    long long *B[3] = {pos, pos + 2 * (size_t)n, pos + 4 * (size_t)n};
+    long long *B[2] = {pos, pos + 2 * (size_t)n};
     hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
     if (e == hipSuccess) e = launch_edge_check(n, m, head, tail, err, s);
     if (e == hipSuccess) e = launch_layout_init(n, xy, B[0], B[1], err, s);
@@ -1031,13 +1042,26 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
     g.rep_num = (2.0 * p->gamma) * p->beta;
     g.neg = p->neg;
     g.seed = p->seed;
+    GM_PROF("layout_incidence", (double)m * 2.0 * (4.0 + 4.0) * 4.0 + (double)m * 2.0 * 16.0,
+            launch_layout_incidence(g, sort_scratch, (int32_t *)(inc + rec_bytes),
+                                    (uint32_t *)inc, (int32_t *)(inc + rec_bytes + off_bytes),
+                                    (int32_t *)(inc + rec_bytes + off_bytes + heavy_bytes), s));
+    if (e != hipSuccess) return hip_status(e, "grad sample");
+    int n_heavy = 0;   // one block per heavy vertex in every window
+    if ((st = read_flag((const int *)(inc + rec_bytes + off_bytes + heavy_bytes), &n_heavy, s))) return st;
+    g.heavy_blocks = n_heavy;
     int cur = 0;
     for (int32_t it = it_begin; it < it_end; ++it) {
         const double lr = p->alpha0 * (1.0 - (double)it / (double)p->t);
-        GM_PROF("grad_window", (double)win * (12.0 + 16.0 + 8.0 * p->neg + 32.0) + (double)n * 48.0,
-                launch_grad_window(g, it, lr, B[cur], B[(cur + 1) % 3], B[(cur + 2) % 3], s));
+        // moves: the window's entries (12 B) and the positions of their
+        // endpoints and negative samples, 32 B of moves stored; gather: every
+        // incidence code and offset, the stored moves read back, positions in
+        // and out
+        GM_PROF("grad_window", (double)win * (12.0 + 32.0 + 16.0 * p->neg + 32.0) + (double)m * 2.0 * 4.0 +
+                                   (double)n * (8.0 + 32.0) + (double)win * 32.0,
+                launch_grad_window(g, it, lr, B[cur], B[cur ^ 1], moves, s));
         if (e != hipSuccess) return hip_status(e, "grad sample");
-        cur = (cur + 1) % 3;
+        cur ^= 1;
     }
     e = launch_layout_out(n, B[cur], xy, s);
     if (e != hipSuccess) return hip_status(e, "grad sample");

@@ -208,8 +208,9 @@ size_t shuffle_scratch_bytes(int64_t m, size_t *sort_tmp);
 hipError_t launch_edge_shuffle(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, const float *val,
                                uint64_t seed, int32_t *head, int32_t *tail, float *w, void *scratch, hipStream_t s);
 // GradSample windows over a shuffled edge array.  Positions are fixed point
-// (int64, 2^-32 units) in three rotating buffers of 2 n values.
+// (int64, 2^-32 units) in two alternating buffers of 2 n values.
 constexpr double kLayoutCoordLimit = 1048576.0;   // |coordinate| < 2^20 keeps P * 2^-32 exact in FP64
+constexpr int kLayoutHeavyInc = 64;               // incidences above which a vertex gets a whole wave
 struct LayoutArgs {
     int32_t n;
     int64_t m;                // edges in the array
@@ -222,16 +223,28 @@ struct LayoutArgs {
     double rep_num;           // (2 gamma) beta
     int32_t neg;              // negative samples per edge
     uint64_t seed;            // seed of the negative samples
+    // incidence lists (launch_layout_incidence)
+    const int32_t *off;       // n + 1 offsets into rec
+    const uint32_t *code;     // position << 1 | role (0 head, 1 tail) of each incidence, 2 m codes
+    const int32_t *heavy;     // vertices with more than kLayoutHeavyInc incidences
+    const int32_t *n_heavy;   // their count (device)
+    int32_t heavy_blocks;     // blocks of the window launch given to heavy vertices
 };
 // err bit 1: head or tail outside [0, n).
 hipError_t launch_edge_check(int32_t n, int64_t m, const int32_t *head, const int32_t *tail, int *err, hipStream_t s);
 // p0 = round(xy * 2^32), p1 = 0; err bit 2: a coordinate not finite or not below 2^20 in magnitude.
 hipError_t launch_layout_init(int32_t n, const float *xy, long long *p0, long long *p1, int *err, hipStream_t s);
 hipError_t launch_layout_out(int32_t n, const long long *p, float *xy, hipStream_t s);
-// Iteration `it` at learning rate lr: reads R, accumulates into N (zero on
-// entry), clears Z.
+// Incidence lists of g's edge array (fills g.off, g.code, g.heavy, g.n_heavy;
+// the caller sets g.heavy_blocks, normally to the heavy count read back).  off: n + 1 ints, code: 2 m codes, heavy: n ints,
+// n_heavy: one int; scratch: incidence_scratch_bytes(n, m, &tmp).
+size_t incidence_scratch_bytes(int32_t n, int64_t m, size_t *sort_tmp);
+hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, uint32_t *code, int32_t *heavy,
+                                   int32_t *n_heavy, hipStream_t s);
+// Iteration `it` at learning rate lr: reads the positions R, writes N;
+// moves: 32 bytes per array position (m entries).
 hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
-                              long long *Z, hipStream_t s);
+                              void *moves, hipStream_t s);
 
 // ----------------------------------------------------------- membership ---
 hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,

@@ -6,13 +6,17 @@
 // Union and shuffle are sorts: every directed kNN cell emits at most two
 // (row, col) keys with their union weight, one radix sort orders them and a
 // segment pass writes the CSR; the shuffle sorts the entries by a
-// SplitMix64 key of their position.  A GradSample window is one launch: a
-// thread per window entry computes the attractive move and its negative
-// samples from the positions at the start of the window and adds the
-// rounded moves to the next positions with 64-bit integer atomics (fixed
-// point, 2^-32 units), so the window's result does not depend on the order
-// in which the moves land.  Positions rotate through three buffers: the one
-// read, the one accumulated into, and the one cleared for the next window.
+// SplitMix64 key of their position.  GradSample first sorts the 2m
+// incidences (each array entry at its head and at its tail) by vertex.  A
+// window is then two launches: a thread per window entry computes the
+// entry's moves from the positions at the start of the window and stores
+// them at the entry's array position; a thread per vertex (a wave for a
+// vertex with many incidences) adds up the stored moves of its incidences
+// that lie in the window and writes its next position once.  Positions are
+// fixed point (int64, 2^-32 units) and moves are summed as integers, so the
+// result does not depend on the order of the sum, and no atomics are needed
+// (device-wide 64-bit atomics on one address serialise, and a high-degree
+// vertex receives thousands of moves per window).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 #include <math.h>
@@ -61,15 +65,19 @@ union_emit_kernel(int32_t rows, int32_t k, const int32_t *__restrict__ ids, cons
                 atomicOr(err, 1);
             } else {
                 const double a = (double)w[e];
-                double b = 0.0;
-                bool found = false;
+                // find i in row j, eight independent loads per round
                 const int32_t *rj = ids + (int64_t)j * k;
-                for (int32_t q = 0; q < k; ++q)
-                    if (rj[q] == i) {
-                        b = (double)w[(int64_t)j * k + q];
-                        found = true;
-                        break;
-                    }
+                int32_t at = -1;
+                for (int32_t q0 = 0; q0 < k && at < 0; q0 += 8) {
+                    int32_t c[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) c[u] = q0 + u < k ? rj[q0 + u] : -1;
+#pragma unroll
+                    for (int u = 7; u >= 0; --u)
+                        if (c[u] == i) at = q0 + u;
+                }
+                const bool found = at >= 0;
+                const double b = found ? (double)w[(int64_t)j * k + at] : 0.0;
                 const double s = a + b;
                 const double p = a * b;
                 const double u = s - p;
@@ -182,67 +190,210 @@ fix_out_kernel(int32_t n, const long long *__restrict__ p, float *__restrict__ x
         xy[i] = (float)((double)p[i] * kFixInv);
 }
 
-// One window: entries at array positions (j0 + l) mod m, l in [0, s).
-// R: positions at the start of the window (read only); N: next positions,
-// all zero on entry, receiving R and every move; Z: cleared for the window
-// after this one.
+// ------------------------------------------------- incidence lists --
+// Every array position p contributes two incidences: at head[p] (role 0)
+// and at tail[p] (role 1).  Sorted by vertex, code[i] = p << 1 | role and
+// off[v] .. off[v + 1] delimit vertex v's codes.
 __global__ void __launch_bounds__(kLayoutBlock)
-grad_window_kernel(LayoutArgs g, int64_t j0, int32_t it, double lr, const long long *__restrict__ R,
-                   unsigned long long *__restrict__ N, long long *__restrict__ Z)
+incidence_keys_kernel(int64_t m, const int32_t *__restrict__ head, const int32_t *__restrict__ tail,
+                      uint32_t *__restrict__ keys, uint32_t *__restrict__ codes)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i >> 1;
+        keys[i] = (uint32_t)((i & 1) ? tail[p] : head[p]);
+        codes[i] = (uint32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(kLayoutBlock)
+incidence_rows_kernel(int32_t n, int64_t total, const uint32_t *__restrict__ keys, int32_t *__restrict__ off)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)keys[i];
+        const int32_t prev = i == 0 ? -1 : (int32_t)keys[i - 1];
+        for (int32_t x = prev + 1; x <= v; ++x) off[x] = (int32_t)i;
+        if (i + 1 == total)
+            for (int32_t x = v + 1; x <= n; ++x) off[x] = (int32_t)total;
+    }
+}
+
+__global__ void __launch_bounds__(kLayoutBlock)
+incidence_heavy_kernel(int32_t n, const int32_t *__restrict__ off, int32_t *__restrict__ heavy,
+                       int32_t *__restrict__ n_heavy)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (off[v + 1] - off[v] > kLayoutHeavyInc) heavy[atomicAdd(n_heavy, 1)] = v;
+}
+
+// ---------------------------------------------------------- one window --
+__device__ __forceinline__ void attract(const LayoutArgs &g, double lh, double dx, double dy, long long &qx,
+                                        long long &qy)
 {
 #pragma clang fp contract(off)
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t v = tid; v < g.n; v += stride) {
-        atomicAdd(N + 2 * v, (unsigned long long)R[2 * v]);
-        atomicAdd(N + 2 * v + 1, (unsigned long long)R[2 * v + 1]);
-        Z[2 * v] = 0;
-        Z[2 * v + 1] = 0;
+    const double sx = dx * dx, sy = dy * dy;
+    const double d2 = sx + sy;
+    qx = 0;
+    qy = 0;
+    if (d2 > 0.0) {
+        const double T = pow(d2, g.beta);
+        const double num = g.att_num * T;
+        const double den = d2 * (1.0 + g.alpha * T);
+        const double c = num / den;
+        qx = llrint(lh * clip4(c * dx) * kFix);
+        qy = llrint(lh * clip4(c * dy) * kFix);
     }
-    for (int64_t l = tid; l < g.s; l += stride) {
+}
+
+__device__ __forceinline__ void repel(const LayoutArgs &g, double lh, double ex, double ey, long long &hx,
+                                      long long &hy)
+{
+#pragma clang fp contract(off)
+    const double tx = ex * ex, ty = ey * ey;
+    const double e2 = tx + ty;
+    double gx = 4.0, gy = 4.0;
+    if (e2 > 0.0) {
+        const double T = pow(e2, g.beta);
+        const double den = (0.001 + e2) * (1.0 + g.alpha * T);
+        const double c = g.rep_num / den;
+        gx = clip4(c * ex);
+        gy = clip4(c * ey);
+    }
+    hx += llrint(lh * gx * kFix);
+    hy += llrint(lh * gy * kFix);
+}
+
+__device__ __forceinline__ double fix_to_f64(long long v) { return (double)v * kFixInv; }
+
+// Phase 1, a thread per window entry (a, b, h) at position p: the head's
+// move (attraction plus negative samples) and the attraction alone, rounded
+// to the fixed-point grid, stored at mv[p] = {head x, head y, att x, att y};
+// the tail receives -att.  The positions of up to kNegBatch negative samples
+// are loaded before any of them is used.
+constexpr int kNegBatch = 8;
+
+__global__ void __launch_bounds__(kLayoutBlock)
+grad_moves_kernel(LayoutArgs g, int64_t j0, int32_t it, double lr, const longlong2 *__restrict__ R,
+                  longlong2 *__restrict__ mv)
+{
+#pragma clang fp contract(off)
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < g.s; l += (int64_t)gridDim.x * blockDim.x) {
         int64_t p = j0 + l;
         if (p >= g.m) p -= g.m;
         const int32_t a = g.head[p], b = g.tail[p];
         const double lh = lr * (double)g.w[p];
-        const double ax = (double)R[2 * (int64_t)a] * kFixInv, ay = (double)R[2 * (int64_t)a + 1] * kFixInv;
-        const double bx = (double)R[2 * (int64_t)b] * kFixInv, by = (double)R[2 * (int64_t)b + 1] * kFixInv;
-        const double dx = ax - bx, dy = ay - by;
-        const double sx = dx * dx, sy = dy * dy;
-        const double d2 = sx + sy;
-        long long qax = 0, qay = 0;
-        if (d2 > 0.0) {
-            const double T = pow(d2, g.beta);
-            const double num = g.att_num * T;
-            const double den = d2 * (1.0 + g.alpha * T);
-            const double c = num / den;
-            const long long qx = llrint(lh * clip4(c * dx) * kFix);
-            const long long qy = llrint(lh * clip4(c * dy) * kFix);
-            qax = qx;
-            qay = qy;
-            atomicAdd(N + 2 * (int64_t)b, (unsigned long long)(-qx));
-            atomicAdd(N + 2 * (int64_t)b + 1, (unsigned long long)(-qy));
-        }
+        const longlong2 ra = R[a], rb = R[b];
+        const double ax = fix_to_f64(ra.x), ay = fix_to_f64(ra.y);
+        long long qx, qy;
+        attract(g, lh, ax - fix_to_f64(rb.x), ay - fix_to_f64(rb.y), qx, qy);
+        long long hx = qx, hy = qy;
         const uint64_t base = ((uint64_t)it * (uint64_t)g.s + (uint64_t)l) * (uint64_t)g.neg;
-        for (int32_t q = 0; q < g.neg; ++q) {
-            const int32_t v = (int32_t)(splitmix64(g.seed, base + (uint64_t)q + 1) % (uint64_t)g.n);
-            if (v == a) continue;
-            const double vx = (double)R[2 * (int64_t)v] * kFixInv, vy = (double)R[2 * (int64_t)v + 1] * kFixInv;
-            const double ex = ax - vx, ey = ay - vy;
-            const double tx = ex * ex, ty = ey * ey;
-            const double e2 = tx + ty;
-            double gx = 4.0, gy = 4.0;
-            if (e2 > 0.0) {
-                const double T = pow(e2, g.beta);
-                const double den = (0.001 + e2) * (1.0 + g.alpha * T);
-                const double c = g.rep_num / den;
-                gx = clip4(c * ex);
-                gy = clip4(c * ey);
-            }
-            qax += llrint(lh * gx * kFix);
-            qay += llrint(lh * gy * kFix);
+        for (int32_t q0 = 0; q0 < g.neg; q0 += kNegBatch) {
+            int32_t vq[kNegBatch];
+            longlong2 rq[kNegBatch];
+#pragma unroll
+            for (int u = 0; u < kNegBatch; ++u)
+                vq[u] = q0 + u < g.neg ? (int32_t)(splitmix64(g.seed, base + (uint64_t)(q0 + u) + 1) % (uint64_t)g.n)
+                                       : a;
+#pragma unroll
+            for (int u = 0; u < kNegBatch; ++u) rq[u] = vq[u] != a ? R[vq[u]] : ra;
+#pragma unroll
+            for (int u = 0; u < kNegBatch; ++u)
+                if (vq[u] != a) repel(g, lh, ax - fix_to_f64(rq[u].x), ay - fix_to_f64(rq[u].y), hx, hy);
         }
-        if (qax) atomicAdd(N + 2 * (int64_t)a, (unsigned long long)qax);
-        if (qay) atomicAdd(N + 2 * (int64_t)a + 1, (unsigned long long)qay);
+        mv[2 * p] = make_longlong2(hx, hy);
+        mv[2 * p + 1] = make_longlong2(qx, qy);
+    }
+}
+
+// Adds the stored moves of the incidences codes[i], i in [i0, i1) stepping by
+// `step`, that lie in the window (kGatherLoads codes in flight per round).
+constexpr int kGatherLoads = 4;
+
+__device__ __forceinline__ void gather_range(const LayoutArgs &g, int64_t j0, const longlong2 *__restrict__ mv,
+                                             int32_t i0, int32_t i1, int32_t step, long long &ax, long long &ay)
+{
+    for (int32_t i = i0; i < i1; i += kGatherLoads * step) {
+        uint32_t c[kGatherLoads];
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; ++u) c[u] = i + u * step < i1 ? g.code[i + u * step] : 0xFFFFFFFFu;
+        longlong2 t[kGatherLoads];
+        bool in[kGatherLoads];
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; ++u) {
+            int64_t l = (int64_t)(c[u] >> 1) - j0;
+            if (l < 0) l += g.m;
+            in[u] = c[u] != 0xFFFFFFFFu && l < g.s;
+            t[u] = in[u] ? mv[2 * (int64_t)(c[u] >> 1) + (c[u] & 1)] : make_longlong2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherLoads; ++u) {
+            if (c[u] & 1) {
+                ax -= t[u].x;
+                ay -= t[u].y;
+            } else {
+                ax += t[u].x;
+                ay += t[u].y;
+            }
+        }
+    }
+}
+
+// Phase 2: N[v] = R[v] + the moves of v's incidences in the window.  Blocks
+// [0, heavy_blocks) take the heavy vertices (more than kLayoutHeavyInc
+// incidences), one block each when heavy_blocks equals their count; the
+// other blocks give kGatherTeam lanes to each remaining vertex.
+constexpr int kGatherTeam = 8;
+
+__global__ void __launch_bounds__(kLayoutBlock)
+grad_gather_kernel(LayoutArgs g, int64_t j0, const longlong2 *__restrict__ mv, const longlong2 *__restrict__ R,
+                   longlong2 *__restrict__ N)
+{
+    if ((int)blockIdx.x < g.heavy_blocks) {
+        __shared__ long long part[2][kLayoutBlock / 64];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        const int32_t cnt = *g.n_heavy;
+        for (int32_t h = blockIdx.x; h < cnt; h += g.heavy_blocks) {
+            const int32_t v = g.heavy[h];
+            long long ax = 0, ay = 0;
+            gather_range(g, j0, mv, g.off[v] + (int32_t)threadIdx.x, g.off[v + 1], kLayoutBlock, ax, ay);
+            for (int o = 32; o > 0; o >>= 1) {
+                ax += __shfl_xor(ax, o);
+                ay += __shfl_xor(ay, o);
+            }
+            if (lane == 0) {
+                part[0][wid] = ax;
+                part[1][wid] = ay;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                long long sx = 0, sy = 0;
+                for (int w = 0; w < kLayoutBlock / 64; ++w) {
+                    sx += part[0][w];
+                    sy += part[1][w];
+                }
+                const longlong2 r = R[v];
+                N[v] = make_longlong2(r.x + sx, r.y + sy);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    const int32_t v = ((blockIdx.x - g.heavy_blocks) * kLayoutBlock + threadIdx.x) / kGatherTeam;
+    const int32_t t = threadIdx.x % kGatherTeam;
+    const bool valid = v < g.n;
+    const int32_t b = valid ? g.off[v] : 0, e = valid ? g.off[v + 1] : 0;
+    const bool mine = valid && e - b <= kLayoutHeavyInc;
+    long long ax = 0, ay = 0;
+    if (mine) gather_range(g, j0, mv, b + t, e, kGatherTeam, ax, ay);
+    for (int o = kGatherTeam / 2; o > 0; o >>= 1) {
+        ax += __shfl_xor(ax, o);
+        ay += __shfl_xor(ay, o);
+    }
+    if (mine && t == 0) {
+        const longlong2 r = R[v];
+        N[v] = make_longlong2(r.x + ax, r.y + ay);
     }
 }
 
@@ -359,13 +510,71 @@ hipError_t launch_layout_out(int32_t n, const long long *p, float *xy, hipStream
     return hipGetLastError();
 }
 
+size_t incidence_scratch_bytes(int32_t n, int64_t m, size_t *sort_tmp)
+{
+    size_t tmp = 0;
+    hipcub::DoubleBuffer<uint32_t> kb(nullptr, nullptr);
+    hipcub::DoubleBuffer<uint32_t> vb(nullptr, nullptr);
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)(2 * m), 0, bits, (hipStream_t)0);
+    tmp = (tmp + 255) & ~(size_t)255;
+    *sort_tmp = tmp;
+    const size_t t = (size_t)(2 * m);
+    return tmp + 3 * t * sizeof(uint32_t) + 1024;
+}
+
+hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, uint32_t *code, int32_t *heavy,
+                                   int32_t *n_heavy, hipStream_t s)
+{
+    size_t tmp = 0;
+    (void)incidence_scratch_bytes(g.n, g.m, &tmp);
+    const int64_t total = 2 * g.m;
+    char *p = (char *)scratch;
+    uint32_t *k0 = (uint32_t *)(p + tmp), *k1 = k0 + total, *c0 = k1 + total;
+    hipLaunchKernelGGL(incidence_keys_kernel, dim3(grid_for(total)), dim3(kLayoutBlock), 0, s, g.m, g.head, g.tail,
+                       k0, c0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)g.n) ++bits;
+    hipcub::DoubleBuffer<uint32_t> kb(k0, k1);
+    hipcub::DoubleBuffer<uint32_t> cb(c0, code);   // the sorted codes may end in either buffer
+    e = hipcub::DeviceRadixSort::SortPairs(p, tmp, kb, cb, (int)total, 0, bits, s);
+    if (e != hipSuccess) return e;
+    if (cb.Current() != code) {
+        e = hipMemcpyAsync(code, cb.Current(), (size_t)total * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(incidence_rows_kernel, dim3(grid_for(total)), dim3(kLayoutBlock), 0, s, g.n, total,
+                       (const uint32_t *)kb.Current(), off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = hipMemsetAsync(n_heavy, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(incidence_heavy_kernel, dim3(grid_for(g.n)), dim3(kLayoutBlock), 0, s, g.n, off, heavy,
+                       n_heavy);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    g.off = off;
+    g.code = code;
+    g.heavy = heavy;
+    g.n_heavy = n_heavy;
+    g.heavy_blocks = 0;   // set by the caller to the heavy count (one block each)
+    return hipSuccess;
+}
+
 hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
-                              long long *Z, hipStream_t s)
+                              void *moves, hipStream_t s)
 {
     const int64_t j0 = (int64_t)(((unsigned __int128)(uint64_t)it * (uint64_t)g.s) % (uint64_t)g.m);
-    const int64_t work = g.s > g.n ? g.s : g.n;
-    hipLaunchKernelGGL(grad_window_kernel, dim3(grid_for(work)), dim3(kLayoutBlock), 0, s, g, j0, it, lr, R,
-                       (unsigned long long *)N, Z);
+    longlong2 *mv = (longlong2 *)moves;
+    hipLaunchKernelGGL(grad_moves_kernel, dim3(grid_for(g.s)), dim3(kLayoutBlock), 0, s, g, j0, it, lr,
+                       (const longlong2 *)R, mv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t light_threads = (int64_t)g.n * kGatherTeam;
+    const int blocks = g.heavy_blocks + (int)((light_threads + kLayoutBlock - 1) / kLayoutBlock);
+    hipLaunchKernelGGL(grad_gather_kernel, dim3(blocks), dim3(kLayoutBlock), 0, s, g, j0, (const longlong2 *)mv,
+                       (const longlong2 *)R, (longlong2 *)N);
     return hipGetLastError();
 }
 

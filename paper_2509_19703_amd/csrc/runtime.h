@@ -48,6 +48,9 @@ enum ScratchSlot {
     kSlotUnion,
     kSlotShuffle,
     kSlotLayoutPos,
+    kSlotLayoutSort,
+    kSlotLayoutRec,
+    kSlotLayoutMoves,
     kScratchSlots
 };
 
