@@ -303,11 +303,15 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if ((st = scratch_get(kSlotCount, (size_t)n * sizeof(int32_t), (void **)&count))) return st;
             if ((st = scratch_get(kSlotMult, (size_t)n * sizeof(int32_t), (void **)&mult))) return st;
         }
-        e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of, mult,
-                            info, s);
+        if (sources_ranked_small(rows, n))
+            e = prepare_sources_small(sources, rows, n, c.row_ptr, (int32_t)env_size("GUMAP_HEAVY_DEGREE", 0), heavy,
+                                      first_row, count, usrc, slot_row, slot_of, mult, info, s);
+        else
+            e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of,
+                                mult, info, s);
     }
     // vertices of high degree get a whole wave per level
-    if (e == hipSuccess)
+    if (e == hipSuccess && (all_sources || !sources_ranked_small(rows, n)))
         e = launch_heavy_list(n, c.row_ptr, (int32_t)env_size("GUMAP_HEAVY_DEGREE", 0), heavy, info, s);
     if (e != hipSuccess) return hip_status(e, "source setup");
     int32_t hinfo[8];
@@ -373,6 +377,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     unsigned long long *hstats = (unsigned long long *)hstats_v;
     for (int32_t gs = 0; gs < groups_total; gs += groups_round) {
         MsbfsArgs a;
+        a.planes_dev = nullptr;
         a.n = n;
         a.row_ptr = c.row_ptr;
         a.col = c.col;
@@ -399,6 +404,10 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         const size_t spl = (size_t)a.groups * SP * SF;   // u64 per level this round
         int last_level = 0;
         bool range_error = false;
+        uint8_t *hop_out = hop_matrix ? hop_matrix : hop_scratch;
+        const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
+        bool spec_valid = false;    // hop rows and selection already launched for the complete BFS
+        int spec_hops_mark = -1;
         if (fused) {
             int32_t *gout = nullptr;
             void *hg = nullptr;
@@ -462,6 +471,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         int L = 1;
         int chunk = (int)std::min(16.0, std::max(4.0, std::ceil(1.5 * std::log((double)n) / std::log(mean_deg)) + 2));
         bool done = false;
+        // The transpose and the selection are launched right after each batch
+        // of levels, before the host has read the counters, with the plane
+        // count computed on the device; they stand when that batch completed
+        // the BFS (the usual case), and run again after further levels
+        // otherwise.  The host then waits once per round instead of twice.
+        int32_t *depth = info + 16;
         while (!done) {
             const int first = L;
             for (int c2 = 0; c2 < chunk && L <= L_cap; ++c2, ++L) {
@@ -479,6 +494,21 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             e = hipMemcpyAsync(hstats + (size_t)first * spl, stats + (size_t)first * spl,
                                (size_t)(L - first) * spl * 8, hipMemcpyDeviceToHost, s);
+            bool spec = false;
+            if (e == hipSuccess && !so) {
+                e = launch_msbfs_depth(a, first, L, depth, s);
+                a.planes_dev = depth;
+                spec_hops_mark = prof_begin("msbfs_hops", s);
+                if (e == hipSuccess) e = launch_msbfs_hops_counted(a, 8, hop_out, hop_rows_of, n, lvl_cnt, s);
+                prof_end(spec_hops_mark, s, 0.0);
+                a.planes_dev = nullptr;
+                if (e == hipSuccess)
+                    GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
+                            launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
+                                                      slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups), ids,
+                                                      hops, s));
+                spec = true;
+            }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_status(e, "bfs stats");
             for (int lv = first; lv < L; ++lv) prof_set_bytes(marks[lv], level_bytes(lv, false));
@@ -493,6 +523,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                     done = true;
                 }
             }
+            spec_valid = spec && done && !range_error;
             if (!done && L > L_cap) {
                 // level L_cap found vertices; commit them without searching further
                 const int hop = L_cap;
@@ -508,6 +539,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if (e != hipSuccess) return hip_status(e, "bfs commit");
                 last_level = L_cap;
                 done = true;
+                spec_valid = false;
             }
             chunk = std::max(8, L / 2);
         }
@@ -546,9 +578,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             continue;
         }
-        uint8_t *hop_out = hop_matrix ? hop_matrix : hop_scratch;
-        const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
         const double hop_bytes = (double)(planes_used + 1) * (double)arr * 8.0 + (double)a.n_slots * n;
+        if (spec_valid) {
+            prof_set_bytes(spec_hops_mark, hop_bytes);
+            continue;
+        }
         GM_PROF("msbfs_hops", hop_bytes,
                 launch_msbfs_hops_counted(a, planes_used, hop_out, hop_rows_of, n, lvl_cnt, s));
         if (e == hipSuccess)

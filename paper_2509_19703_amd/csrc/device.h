@@ -11,6 +11,14 @@ namespace gm {
 
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 
+// Degree above which a vertex gets a whole wave in the BFS level kernel:
+// `forced` if positive, else max(64, 8 * mean degree).
+__device__ __forceinline__ int32_t heavy_threshold(int32_t n, const int32_t *row_ptr, int32_t forced)
+{
+    const int32_t mean = n > 0 ? row_ptr[n] / n : 0;
+    return forced > 0 ? forced : max(64, 8 * mean);
+}
+
 __device__ __forceinline__ int wave_min(int v)
 {
 #pragma unroll

@@ -58,6 +58,7 @@ struct MsbfsArgs {
     int32_t heavy_deg;
     int32_t xcd_map;          // keep each group on one XCD when groups % 8 == 0
     int32_t hops_variant;     // hop-row writer: tiles per step / store kind (tuning)
+    const int32_t *planes_dev; // if not NULL: the transpose reads its plane count here (device)
 };
 // Layout of the level counters: stats[((level * groups + g) * spread + slot) * fields + field]
 // with fields {new bits, frontier words gathered, adjacency entries read,
@@ -78,6 +79,10 @@ hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s);
+// After levels [first, last) of a round: out[0] = bit_length of the last
+// level that found vertices (the plane count the transpose needs once the
+// BFS is complete), out[1] = 1 if level last - 1 still found vertices.
+hipError_t launch_msbfs_depth(const MsbfsArgs &a, int first, int last, int32_t *out, hipStream_t s);
 // Hop rows of this round's slots: hop_out + slot_row[slot] * row_stride
 // receives the n hop bytes of that slot (planes_used bit-planes committed).
 hipError_t launch_msbfs_hops(const MsbfsArgs &a, int planes_used, uint8_t *hop_out,

@@ -339,11 +339,44 @@ msbfs_fused_kernel(MsbfsArgs a, int L_cap, int full_hops, int32_t *group_out)
 // the mean degree (a lone thread would walk their rows serially while the
 // rest of its wave waits); dense graphs with an even degree keep one thread
 // per vertex word, which stops early.  info[1] = count, info[2] = threshold.
+// Plane count of the levels run so far: one block sums the new-vertex field
+// of every (level, group, spread slot) counter of levels [first, last).
+__global__ void __launch_bounds__(256)
+msbfs_depth_kernel(const unsigned long long *__restrict__ stats, int32_t groups, int first, int last,
+                   int32_t *__restrict__ out)
+{
+    __shared__ int found[256];
+    const int per_level = groups * kSpread;
+    for (int lv = first + (int)threadIdx.x; lv < last && lv < first + 256; lv += blockDim.x) found[lv - first] = 0;
+    __syncthreads();
+    for (int lv = first; lv < last && lv < first + 256; ++lv) {
+        unsigned long long t = 0;
+        for (int i = threadIdx.x; i < per_level; i += blockDim.x)
+            t |= stats[((size_t)lv * per_level + i) * kStatFields + 0];
+        if (t) found[lv - first] = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int last_found = first - 1;   // the level before the batch found vertices
+        bool more = true;
+        for (int lv = first; lv < last && lv < first + 256; ++lv) {
+            if (!found[lv - first]) {
+                more = false;
+                break;
+            }
+            last_found = lv;
+        }
+        int bits = 0;
+        while (bits < 31 && (1 << bits) <= last_found) ++bits;
+        out[0] = bits;
+        out[1] = more ? 1 : 0;
+    }
+}
+
 __global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t forced, int32_t *heavy,
                                   int32_t *info)
 {
-    const int32_t mean = n > 0 ? rp[n] / n : 0;
-    const int32_t thr = forced > 0 ? forced : max(64, 8 * mean);
+    const int32_t thr = heavy_threshold(n, rp, forced);
     if (blockIdx.x == 0 && threadIdx.x == 0) info[2] = thr;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         if (rp[v + 1] - rp[v] > thr) heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
@@ -383,10 +416,11 @@ __device__ __forceinline__ uint64_t spread8(uint64_t bits8)
 // atomics) to part[(slot * chunks + block) * 16 + h - 1].
 template <int WORDS, int STEP, bool NT>
 __global__ void __launch_bounds__(WORDS * GM_WAVE)
-msbfs_hops_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
+msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
                   const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part)
 {
     constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
     const int w = threadIdx.x / GM_WAVE, l = lane();
     const int32_t g = blockIdx.y;
     const int32_t local_slot = g * 64 * WORDS + 64 * w + l;
@@ -473,11 +507,12 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
 // FP64 instead, one partial sum and pair count per (slot, block).
 template <int WORDS, int TILES, bool STRESS>
 __global__ void __launch_bounds__(WORDS * GM_WAVE)
-msbfs_hops_staged_kernel(MsbfsArgs a, int planes_used, uint8_t *__restrict__ hop_out,
+msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
                          const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part,
                          StressArgs sa)
 {
     constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
     constexpr int ROWS = WORDS * GM_WAVE;        // sources of the group = rows staged
     constexpr int SEG = 64 * TILES;              // bytes per row per step
     constexpr int UNIT = 8 * TILES;              // bytes per store: 8 or 16
@@ -688,6 +723,13 @@ hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, 
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>(4096, ((int64_t)n + 255) / 256);
     hipLaunchKernelGGL(heavy_list_kernel, dim3(blocks), dim3(256), 0, s, n, row_ptr, forced, heavy, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_msbfs_depth(const MsbfsArgs &a, int first, int last, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(msbfs_depth_kernel, dim3(1), dim3(256), 0, s, (const unsigned long long *)a.stats,
+                       a.stats_groups, first, last, out);
     return hipGetLastError();
 }
 

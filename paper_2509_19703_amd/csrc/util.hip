@@ -73,6 +73,111 @@ __global__ void source_slots_k(int32_t n, const int32_t *first, const int32_t *p
     }
 }
 
+// Few listed sources on a small graph (at most kRankMax rows, kRankMaxN vertices).  First a pass over the
+// vertices: not a source yet (first = INT32_MAX, slot -1, count 0), and the
+// heavy-vertex list of the level kernel (info[1] entries, threshold info[2]).
+constexpr int kRankThreads = 1024;
+constexpr int kRankMax = 4096;
+
+__global__ void source_vertex_prep_k(int32_t n, const int32_t *__restrict__ rp, int32_t forced, int32_t *first,
+                                     int32_t *count, int32_t *slot_of, int32_t *heavy, int32_t *info)
+{
+    const int32_t thr = heavy_threshold(n, rp, forced);
+    if (blockIdx.x == 0 && threadIdx.x == 0) info[2] = thr;
+    GRID_STRIDE(v, (int64_t)n)
+    {
+        first[v] = INT32_MAX;
+        slot_of[v] = -1;
+        if (count) count[v] = 0;
+        if (rp[v + 1] - rp[v] > thr) heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
+    }
+}
+
+// Then one workgroup ranks the rows with an n-bit set of the listed vertices
+// in LDS: the slot of a listed vertex is the number of listed vertices with
+// a smaller id (word popcounts, prefix-summed); the first row and the times
+// listed of each slot are LDS atomics over the rows.  Same outputs as the
+// scan-based path for larger inputs.
+constexpr int kRankMaxN = 131072;
+constexpr int kRankWords = kRankMaxN / 64;
+
+__device__ __forceinline__ int32_t rank_of(const uint64_t *bits, const int32_t *prefix, int32_t v)
+{
+    const int w = v >> 6, b = v & 63;
+    return prefix[w] + __popcll(bits[w] & ((1ull << b) - 1ull));
+}
+
+__global__ void __launch_bounds__(kRankThreads)
+source_rank_small_k(const int32_t *__restrict__ src, int32_t rows, int32_t n, int32_t *first, int32_t *count,
+                    int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info)
+{
+    __shared__ uint64_t bits[kRankWords];
+    __shared__ int32_t prefix[kRankWords];
+    __shared__ int32_t first_row[kRankMax];
+    __shared__ int32_t times[kRankMax];
+    __shared__ int32_t wsum[kRankThreads / GM_WAVE];
+    const int t = threadIdx.x;
+    const int W = (n + 63) / 64;
+    for (int w = t; w < W; w += kRankThreads) bits[w] = 0;
+    __syncthreads();
+    for (int r = t; r < rows; r += kRankThreads) {
+        const int32_t v = src[r];
+        if (v < 0 || v >= n) atomicOr(&info[0], 1);
+        else atomicOr(&bits[v >> 6], 1ull << (v & 63));
+    }
+    __syncthreads();
+    // exclusive prefix of the word popcounts: thread t takes words [t * per, (t + 1) * per)
+    const int per = (W + kRankThreads - 1) / kRankThreads;
+    int local = 0;
+    for (int w = t * per; w < min(W, (t + 1) * per); ++w) local += __popcll(bits[w]);
+    int x = local;
+    for (int o = 1; o < GM_WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o, GM_WAVE);
+        if (lane() >= o) x += y;
+    }
+    if (lane() == GM_WAVE - 1) wsum[t / GM_WAVE] = x;
+    __syncthreads();
+    if (t == 0)
+        for (int w = 1; w < kRankThreads / GM_WAVE; ++w) wsum[w] += wsum[w - 1];
+    __syncthreads();
+    int run = x - local + (t >= GM_WAVE ? wsum[t / GM_WAVE - 1] : 0);
+    for (int w = t * per; w < min(W, (t + 1) * per); ++w) {
+        prefix[w] = run;
+        run += __popcll(bits[w]);
+    }
+    const int total = wsum[kRankThreads / GM_WAVE - 1];
+    for (int q = t; q < total; q += kRankThreads) {
+        first_row[q] = INT32_MAX;
+        times[q] = 0;
+    }
+    __syncthreads();
+    for (int r = t; r < rows; r += kRankThreads) {
+        const int32_t v = src[r];
+        if (v < 0 || v >= n) continue;
+        const int32_t q = rank_of(bits, prefix, v);
+        atomicMin(&first_row[q], r);
+        atomicAdd(&times[q], 1);
+    }
+    __syncthreads();
+    for (int w = t; w < W; w += kRankThreads) {
+        uint64_t m = bits[w];
+        int32_t q = prefix[w];
+        while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int32_t v = 64 * w + b;
+            usrc[q] = v;
+            slot_of[v] = q;
+            slot_row[q] = first_row[q];
+            first[v] = first_row[q];
+            if (mult) mult[q] = times[q];
+            if (count) count[v] = times[q];
+            ++q;
+        }
+    }
+    if (t == 0) info[3] = total;
+}
+
 // Rows naming a source listed earlier copy that row's results.
 __global__ void copy_dup_rows_k(const int32_t *src, int64_t rows, const int32_t *first, int32_t k, int32_t n,
                                 int32_t *ids, uint8_t *hops, uint8_t *hop_matrix)
@@ -276,6 +381,23 @@ hipError_t union_to_batch(int32_t n_graphs, const int64_t *voff, const int32_t *
     if (total_e_canon > 0)
         hipLaunchKernelGGL(union_to_batch_col_k, dim3(blocks_for(total_e_canon)), dim3(256), 0, s,
                            n_graphs, voff, eoff_out, ucol, total_e_canon, col_out);
+    return hipGetLastError();
+}
+
+bool sources_ranked_small(int64_t rows, int32_t n) { return rows <= kRankMax && n <= kRankMaxN; }
+
+hipError_t prepare_sources_small(const int32_t *src, int64_t rows, int32_t n, const int32_t *row_ptr,
+                                 int32_t heavy_forced, int32_t *heavy, int32_t *first, int32_t *count,
+                                 int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info,
+                                 hipStream_t s)
+{
+    if (!sources_ranked_small(rows, n)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(source_vertex_prep_k, dim3(blocks_for(n)), dim3(256), 0, s, n, row_ptr, heavy_forced, first,
+                       count, slot_of, heavy, info);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || rows <= 0) return e;
+    hipLaunchKernelGGL(source_rank_small_k, dim3(1), dim3(kRankThreads), 0, s, src, (int32_t)rows, n, first, count,
+                       usrc, slot_row, slot_of, mult, info);
     return hipGetLastError();
 }
 

@@ -306,3 +306,42 @@ def test_hop_range_error_both_paths(gumap, monkeypatch, n, fused):
     with pytest.raises(gumap.GumapError) as ei:
         gumap.knn_build(rp, ci, 3, sources=src, hop_matrix=True, flags=gumap.CSR_SORTED)
     assert ei.value.status == gumap.ERANGE
+
+
+@pytest.mark.parametrize("rows", [1, 2, 1023, 1024, 1025, 4096, 4097, 9000])
+def test_listed_sources_ranking_both_paths(gumap, rows):
+    """Listed sources with repeats in any order: up to 4,096 rows are ranked
+    by one workgroup, more by the scan path; both give the oracle's rows
+    (repeated sources copy their first row)."""
+    g = G.ba(3000, 3, 401)
+    rng = np.random.default_rng(rows)
+    src = rng.integers(0, g.n, rows).astype(np.int32)
+    if rows > 4:
+        src[rows // 2] = src[0]
+        src[-1] = src[1]
+    print("ranking rows=%d" % rows, flush=True)
+    _check_build(gumap, g, 7, sources=src, hop_matrix=rows <= 1025)
+
+
+@pytest.mark.parametrize("rows", [3, 4096, 5000])
+def test_stress_listed_sources_multiplicity_both_paths(gumap, rows):
+    """Stress over listed sources counts a repeated source once per listing,
+    on both ranking paths."""
+    import torch
+    g = G.ba(2500, 3, 402)
+    rng = np.random.default_rng(7 + rows)
+    src = rng.integers(0, g.n, rows).astype(np.int32)
+    src[-1] = src[0]
+    xy = rng.uniform(0, 50, (g.n, 2)).astype(np.float32)
+    rp, ci = to_dev(g)
+    gs, gp = gumap.stress(rp, ci, torch.from_numpy(xy).cuda(), torch.from_numpy(src).cuda(),
+                          flags=gumap.CSR_SORTED)
+    os_, op = O.stress(g, xy, sources=src)
+    assert gp == op and abs(gs - os_) <= 1e-9 * abs(os_)
+
+
+def test_listed_sources_ranking_large_graph(gumap):
+    """More than 131,072 vertices: listed sources take the scan path."""
+    g = G.ba(140000, 2, 403)
+    src = np.concatenate([G.sample_sources(g.n, 60, 404), [7, 7, 139999]]).astype(np.int32)
+    _check_build(gumap, g, 9, sources=src, hop_matrix=False)
