@@ -5,7 +5,8 @@ arXiv 2509.19703 (GUMAP steps C0/C1 of Alg. 1, PartialBFS of Alg. 4 in
 Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1) and of the drawing
 quality metrics of Sec. 5.1 computed on the same BFS, and of the layout step C2
 that follows (fuzzy union of the kNN weights, edge shuffle and the sliding
-window GradSample of Alg. 5).  Only ``tests/``,
+window GradSample of Alg. 5) and its spectral initial drawing (dense
+eigendecomposition, in this module).  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
 it.  It shares no code with the GPU library and the GPU library never calls
 it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
@@ -23,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-OK, EINVAL, ERANGE, ENOMEM = 0, -1, -3, -4
+OK, EINVAL, EGRAPH, ERANGE, ENOMEM = 0, -1, -2, -3, -4
 
 
 def build(force: bool = False) -> str:
@@ -255,3 +256,43 @@ def grad_sample(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, ga
     if st:
         raise OracleError(st)
     return (out, vis[:m]) if visits else out
+
+
+# ------------------------------------------------------ spectral layout ---
+def spectral_layout(n: int, row_ptr, col, val, dim: int = 2):
+    """Spectral initial drawing (Sec. 3.2: the layout starts from a spectral
+    layout, as in UMAP): the eigenvectors of the 2nd .. (dim+1)-th smallest
+    eigenvalues of the normalised Laplacian L = I - D^-1/2 W D^-1/2 of the
+    symmetric weighted graph W (FP64, dense numpy.linalg.eigh).  Each vector
+    has unit norm and the sign that makes positive its first entry (in index
+    order) of magnitude above half its largest (a rule that rounding cannot
+    flip, unlike "the largest entry" on symmetric graphs); the drawing is the
+    vectors
+    scaled by 10 / (largest magnitude over all coordinates), rounded to
+    float.  Returns (xy float32 [n, dim], eigenvalues float64 [dim]).
+    Raises OracleError(EGRAPH) for a vertex of zero degree or a disconnected
+    graph (second eigenvalue below 1e-10), EINVAL for n < dim + 1."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    c = np.asarray(col, dtype=np.int64)
+    w = np.asarray(val, dtype=np.float64)
+    if n < dim + 1:
+        raise OracleError(EINVAL)
+    W = np.zeros((n, n))
+    for i in range(n):
+        W[i, c[rp[i]:rp[i + 1]]] += w[rp[i]:rp[i + 1]]
+    d = W.sum(axis=1)
+    if np.any(d <= 0):
+        raise OracleError(EGRAPH)
+    s = 1.0 / np.sqrt(d)
+    L = np.eye(n) - (s[:, None] * W) * s[None, :]
+    evals, evecs = np.linalg.eigh(L)
+    if evals[1] < 1e-10:
+        raise OracleError(EGRAPH)
+    V = evecs[:, 1:dim + 1].copy()
+    for j in range(dim):
+        a = np.abs(V[:, j])
+        p = int(np.argmax(a > 0.5 * a.max()))
+        if V[p, j] < 0:
+            V[:, j] = -V[:, j]
+    scale = 10.0 / np.abs(V).max()
+    return (V * scale).astype(np.float32), evals[1:dim + 1].copy()
