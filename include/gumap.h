@@ -208,6 +208,42 @@ int gumap_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *
 int gumap_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, int64_t m,
                        uint64_t seed, int32_t *head, int32_t *tail, float *w, hipStream_t stream);
 
+/* Parameters of gumap_spectral_layout (zero fields take the defaults). */
+typedef struct {
+    int32_t max_steps;  /* Lanczos steps at most (default 600, never more than n - 1) */
+    int32_t pad;
+    double tol;         /* residual |A x - mu x| of each eigenvector (default 1e-6) */
+    uint64_t seed;      /* SplitMix64 seed of the starting vector */
+} gumap_spectral_params;
+
+/*
+ * gumap_spectral_layout: the spectral initial drawing of the layout step
+ * (the paper starts its layout from a spectral layout, Sec. 3.2, as UMAP
+ * does): the eigenvectors of the 2nd and 3rd smallest eigenvalues of the
+ * normalised Laplacian L = I - D^-1/2 W D^-1/2 of the symmetric weighted
+ * graph W (D: weighted degrees), each of unit norm with the sign that makes
+ * positive its first entry of magnitude above half its largest, the two
+ * scaled together so that the largest coordinate magnitude is 10.  Computed
+ * by Lanczos iteration with full reorthogonalisation in FP64 on the
+ * complement of the known eigenvector D^1/2 1, until both residuals are at
+ * most tol; the result approximates the exact eigenvectors to about
+ * tol / (eigenvalue gap).
+ *   n, row_ptr, col, val   device symmetric CSR with non-negative float weights
+ *                          (gumap_fuzzy_union's output), connected
+ *   params                 host, may be NULL (defaults)
+ *   xy                     device float[2 n] (out): x, y of vertex v at xy[2v], xy[2v + 1]
+ *   eigenvalues            host double[2] or NULL (out): the two eigenvalues of L
+ *   steps                  host int32 or NULL (out): Lanczos steps taken
+ * Scratch: (min(max_steps, n - 1) + 6) * n doubles of device memory.
+ * Errors: GUMAP_EINVAL (NULL pointer, n < 3, a weight negative or not
+ * finite), GUMAP_EGRAPH (a vertex of zero degree, or a disconnected graph:
+ * second eigenvalue below 1e-10), GUMAP_ERANGE (no convergence within
+ * max_steps), GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                          const gumap_spectral_params *params, float *xy, double *eigenvalues, int32_t *steps,
+                          hipStream_t stream);
+
 /* Parameters of gumap_grad_sample. */
 typedef struct {
     double alpha;      /* low-dimensional similarity 1 / (1 + alpha d^(2 beta)) */

@@ -48,6 +48,11 @@ class gumap_layout_params(ctypes.Structure):
                 ("neg", ctypes.c_int32), ("t", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
+class gumap_spectral_params(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int32), ("pad", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
 # UMAP's curve parameters for min_dist 0.1 and spread 1 (its default fit of
 # 1 / (1 + a d^(2b)) to the target membership curve of the drawing).
 UMAP_A = 1.5769434603113077
@@ -116,7 +121,9 @@ def _load() -> ctypes.CDLL:
     lib.gumap_fuzzy_union.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.gumap_edge_shuffle.argtypes = [i32, vp, vp, vp, i64, ctypes.c_uint64, vp, vp, vp, vp]
     lib.gumap_grad_sample.argtypes = [i32, vp, i64, vp, vp, vp, ctypes.POINTER(gumap_layout_params), i32, i32, vp]
-    for f in (lib.gumap_fuzzy_union, lib.gumap_edge_shuffle, lib.gumap_grad_sample):
+    lib.gumap_spectral_layout.argtypes = [i32, vp, vp, vp, ctypes.POINTER(gumap_spectral_params), vp,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), vp]
+    for f in (lib.gumap_fuzzy_union, lib.gumap_edge_shuffle, lib.gumap_grad_sample, lib.gumap_spectral_layout):
         f.restype = ctypes.c_int
     lib.gumap_knn_partial_batch.argtypes = [B, i32, vp, vp, vp, vp, vp, vp]
     lib.gumap_batch_plan_create.argtypes = [B, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -397,6 +404,27 @@ def grad_sample(xy, head, tail, w, params=None, it_begin: int = 0, it_end=None, 
     assert xy.is_contiguous() and xy.dtype.itemsize == 4
     gumap_grad_sample(n, xy, int(head.shape[0]), head, tail, w, p, it_begin, it_end, stream)
     return xy
+
+
+def gumap_spectral_layout(n, row_ptr, col, val, params, xy, stream=None):
+    """C-ABI gumap_spectral_layout; returns (eigenvalues (2,), Lanczos steps)."""
+    ev = (ctypes.c_double * 2)()
+    steps = ctypes.c_int32(0)
+    _check(lib.gumap_spectral_layout(int(n), _ptr(row_ptr), _ptr(col), _ptr(val),
+                                     ctypes.byref(params) if params is not None else None, _ptr(xy), ev,
+                                     ctypes.byref(steps), _stream(stream)))
+    return (ev[0], ev[1]), steps.value
+
+
+def spectral_layout(row_ptr, col, val, max_steps: int = 0, tol: float = 0.0, seed: int = 0, stream=None):
+    """Spectral initial drawing of a symmetric weighted CSR on the device.
+    Returns (xy float32 [n, 2], eigenvalues, steps)."""
+    torch = _torch()
+    n = int(row_ptr.shape[0]) - 1
+    xy = torch.empty((n, 2), dtype=torch.float32, device=row_ptr.device)
+    p = gumap_spectral_params(int(max_steps), 0, float(tol), int(seed) & (2**64 - 1))
+    ev, steps = gumap_spectral_layout(n, row_ptr, col, val, p, xy, stream)
+    return xy, ev, steps
 
 
 class PackedBatch:

@@ -1102,6 +1102,141 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
     return finish(s, "gumap_grad_sample");
 }
 
+// -------------------------------------------- spectral initial drawing --
+namespace {
+
+// One Lanczos run behind c0 deflated columns: steps until the largest Ritz
+// value's residual |beta_m z_m| is at most tol (or the Krylov space is
+// exhausted); then that Ritz vector into X[:, k].  *lambda = 1 - the Ritz value.
+int lanczos_run(const SpectralArgs &a, int c0, int jmax, double tol, uint64_t seed, double *svec, int k,
+                double *lambda, int *steps, hipStream_t s)
+{
+    int st;
+    hipError_t e = launch_lanczos_start(a, c0, seed, s);
+    if (e != hipSuccess) return hip_status(e, "lanczos start");
+    std::vector<double> ha((size_t)jmax + 2), hb((size_t)jmax + 2), ta, tb, zl;
+    int m = 0, top = 0;
+    bool converged = false;
+    for (int j = 1; j <= jmax; ++j) {
+        if ((e = launch_lanczos_step(a, c0, j, s)) != hipSuccess) return hip_status(e, "lanczos step");
+        if (j % 10 != 0 && j != jmax) continue;
+        e = hipMemcpyAsync(ha.data(), a.alpha, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hb.data(), a.beta, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "lanczos coefficients");
+        // the recurrence stops at the first zero beta (the Krylov space is exhausted)
+        m = j;
+        bool exhausted = false;
+        for (int q = 1; q <= j; ++q)
+            if (hb[q] == 0.0) {
+                m = q;
+                exhausted = true;
+                break;
+            }
+        ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
+        tb.assign(hb.begin() + 1, hb.begin() + m);
+        zl.assign((size_t)m, 0.0);
+        if (!tridiag_eigen(m, ta.data(), tb.data(), nullptr, zl.data()))
+            return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
+        top = 0;
+        for (int q = 1; q < m; ++q)
+            if (ta[q] > ta[top]) top = q;
+        if (exhausted || fabs(hb[m] * zl[top]) <= tol) {
+            converged = true;
+            break;
+        }
+    }
+    if (!converged)
+        return set_error(GUMAP_ERANGE, "the Lanczos iteration did not reach residual %g in %d steps", tol, jmax);
+    ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
+    tb.assign(hb.begin() + 1, hb.begin() + m);
+    std::vector<double> Z((size_t)m * m);
+    if (!tridiag_eigen(m, ta.data(), tb.data(), Z.data(), nullptr))
+        return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
+    top = 0;
+    for (int q = 1; q < m; ++q)
+        if (ta[q] > ta[top]) top = q;
+    std::vector<double> sv((size_t)m);
+    for (int c = 0; c < m; ++c) sv[c] = Z[(size_t)c * m + top];
+    e = hipMemcpyAsync(svec, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // sv lives in this frame
+    if (e == hipSuccess) e = launch_ritz_vector(a, c0, m, svec, k, s);
+    if (e != hipSuccess) return hip_status(e, "ritz vector");
+    *lambda = 1.0 - ta[top];
+    *steps += m;
+    (void)st;
+    return GUMAP_OK;
+}
+
+}  // namespace
+
+int spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                    const gumap_spectral_params *p, float *xy, double *eigenvalues, int32_t *steps, hipStream_t s)
+{
+    int st;
+    if (n < 3) return set_error(GUMAP_EINVAL, "n < 3 (two eigenvectors beyond the first need three vertices)");
+    if (!row_ptr || !col || !val || !xy) return set_error(GUMAP_EINVAL, "NULL array");
+    const int32_t max_steps = p && p->max_steps > 0 ? p->max_steps : 600;
+    const double tol = p && p->tol > 0.0 ? p->tol : 1e-6;
+    const uint64_t seed = p ? p->seed : 0;
+    // run 1 works in the complement of one column, run 2 of two
+    const int jmax = (int)std::min<int64_t>(max_steps, (int64_t)n - 1);
+    const int tiles = spectral_tiles(n);
+    const size_t cols = (size_t)jmax + 3;
+    const size_t ld = ((size_t)n + 31) & ~(size_t)31;
+    SpectralArgs a{};
+    a.n = n;
+    a.row_ptr = row_ptr;
+    a.col = col;
+    a.val = val;
+    a.ld = ld;
+    a.tiny = 1e-12;
+    double *base = nullptr;
+    const size_t doubles = cols * ld + 4 * ld + (size_t)tiles * (cols + 4) * 2 + 4 * cols + 16;
+    if ((st = scratch_get(kSlotSpectral, doubles * sizeof(double), (void **)&base))) return st;
+    double *q = base;
+    a.Q = q;            q += cols * ld;
+    a.sinv = q;         q += ld;
+    a.w = q;            q += ld;
+    a.X = q;            q += 2 * ld;
+    a.part = q;         q += (size_t)tiles * (cols + 4) * 2;
+    a.h = q;            q += cols;
+    a.hacc = q;         q += cols;
+    a.alpha = q;        q += cols;
+    a.beta = q;         q += cols;
+    a.scal = q;
+    double *svec = nullptr;
+    if ((st = scratch_get(kSlotSpectralVec, (size_t)cols * sizeof(double) + 256, (void **)&svec))) return st;
+    int *err = nullptr;
+    if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
+    int *first = err + 16;
+    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipMemsetAsync(first, 0x7f, 2 * sizeof(int), s);
+    if (e == hipSuccess) e = launch_spectral_setup(a, err, s);
+    if (e != hipSuccess) return hip_status(e, "spectral setup");
+    int bad = 0;
+    if ((st = read_flag(err, &bad, s))) return st;
+    if (bad & 2) return set_error(GUMAP_EINVAL, "a weight is negative or not finite");
+    if (bad & 1) return set_error(GUMAP_EGRAPH, "a vertex has zero degree (the graph is not connected)");
+    double lam[2] = {0.0, 0.0};
+    int total_steps = 0;
+    if ((st = lanczos_run(a, 1, std::min(jmax, n - 1), tol, seed, svec, 0, &lam[0], &total_steps, s))) return st;
+    if (lam[0] < 1e-10) return set_error(GUMAP_EGRAPH, "second eigenvalue %g: the graph is not connected", lam[0]);
+    e = launch_ritz_deflate(a, 0, 1, s);
+    if (e != hipSuccess) return hip_status(e, "deflation");
+    if ((st = lanczos_run(a, 2, std::min(jmax, n - 2), tol, seed + 1, svec, 1, &lam[1], &total_steps, s))) return st;
+    e = launch_spectral_finish(a, first, xy, s);
+    if (e != hipSuccess) return hip_status(e, "spectral finish");
+    if ((st = finish(s, "gumap_spectral_layout"))) return st;
+    if (eigenvalues) {
+        eigenvalues[0] = lam[0];
+        eigenvalues[1] = lam[1];
+    }
+    if (steps) *steps = total_steps;
+    return GUMAP_OK;
+}
+
 }  // namespace gm
 
 // ================================================================ C-ABI ===
@@ -1179,6 +1314,15 @@ int gumap_grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, cons
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
     return gm::settle(gm::grad_sample(n, xy, m, head, tail, w, p, it_begin, it_end, stream), stream);
+}
+
+int gumap_spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val,
+                          const gumap_spectral_params *params, float *xy, double *eigenvalues, int32_t *steps,
+                          hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::spectral_layout(n, row_ptr, col, val, params, xy, eigenvalues, steps, stream), stream);
 }
 
 int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *weights, float *rho,

@@ -251,6 +251,44 @@ hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, u
 hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
                               void *moves, hipStream_t s);
 
+// -------------------------------------------- spectral initial drawing ---
+// Lanczos iteration on A = D^-1/2 W D^-1/2 deflated by D^1/2 1 (FP64).
+struct SpectralArgs {
+    int32_t n;
+    const int32_t *row_ptr;   // symmetric weighted CSR
+    const int32_t *col;
+    const float *val;
+    double *sinv;             // n: 1 / sqrt(degree)
+    double *Q;                // column-major basis, ld doubles per column; column 0 = D^1/2 1 normalised
+    size_t ld;
+    double *w;                // n: work vector
+    double *part;             // spectral_tiles(n) x (columns + 2) partial sums
+    double *h, *hacc;         // projections of the current step (columns + 2)
+    double *alpha, *beta;     // recurrence coefficients, index = step (columns + 2)
+    double *scal;             // 8 scalars
+    double *X;                // 2 n: the two Ritz vectors, column-major
+    double tiny;              // norms at or below this count as zero (Krylov space exhausted)
+};
+int spectral_tiles(int32_t n);
+// Degrees (err bit 1: zero degree, bit 2: a weight negative or not finite)
+// and column 0 = D^1/2 1 normalised.
+hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, hipStream_t s);
+// Column c0: the first Lanczos vector, from a SplitMix64-seeded vector
+// orthogonalised against columns 0 .. c0 - 1.
+hipError_t launch_lanczos_start(const SpectralArgs &a, int c0, uint64_t seed, hipStream_t s);
+// Step j >= 1 (vector j in column c0 + j - 1): the next column, alpha[j] and
+// beta[j] (0 when the Krylov space is exhausted).
+hipError_t launch_lanczos_step(const SpectralArgs &a, int c0, int j, hipStream_t s);
+// X[:, k] = Q[:, c0 .. c0 + m) svec (svec: m doubles on the device).
+hipError_t launch_ritz_vector(const SpectralArgs &a, int c0, int m, const double *svec, int k, hipStream_t s);
+// Q[:, col] = X[:, k] normalised.
+hipError_t launch_ritz_deflate(const SpectralArgs &a, int k, int col, hipStream_t s);
+// The two columns of X normalised, signed and scaled into xy (float, x y
+// per vertex); first: two ints set to INT32_MAX beforehand.
+hipError_t launch_spectral_finish(const SpectralArgs &a, int *first, float *xy, hipStream_t s);
+// Host: eigen-decomposition of a symmetric tridiagonal matrix (see spectral.hip).
+bool tridiag_eigen(int m, double *a, double *b, double *Z, double *zlast);
+
 // ----------------------------------------------------------- membership ---
 hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,
                              float *rho, float *sigma, hipStream_t s);

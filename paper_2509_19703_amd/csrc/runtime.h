@@ -51,6 +51,8 @@ enum ScratchSlot {
     kSlotLayoutSort,
     kSlotLayoutRec,
     kSlotLayoutMoves,
+    kSlotSpectral,
+    kSlotSpectralVec,
     kScratchSlots
 };
 

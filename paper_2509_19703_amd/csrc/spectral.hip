@@ -1,0 +1,411 @@
+// Spectral initial drawing of the layout step (the drawing starts from a
+// spectral layout, Sec. 3.2, as UMAP starts its optimisation): the
+// eigenvectors of the 2nd and 3rd smallest eigenvalues of the normalised
+// Laplacian L = I - D^-1/2 W D^-1/2 of the symmetric weighted graph W.
+//
+// They are the eigenvectors of the two largest eigenvalues of
+// A = D^-1/2 W D^-1/2 on the complement of its top eigenvector D^1/2 1
+// (eigenvalue 1), found by Lanczos iteration in FP64: the Krylov basis Q is
+// kept whole (column-major, one column per step) behind the deflated
+// columns, and every new vector is orthogonalised against all of it twice
+// (classical Gram-Schmidt applied twice), which keeps Q orthonormal to
+// rounding and removes the deflated directions.  Two runs: the first, with
+// column 0 = D^1/2 1 normalised, converges the top eigenpair; the second
+// also deflates that eigenvector (column 1) and converges the next, so that
+// a repeated eigenvalue (a cycle's, a complete graph's) still yields two
+// orthogonal eigenvectors, which one Krylov sequence cannot.  The small tridiagonal matrix
+// of the recurrence is diagonalised on the host by implicit QR steps with
+// Wilkinson shifts.  Partial sums are reduced in a fixed order, so a run is
+// reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace gm {
+namespace {
+
+constexpr int kSpBlock = 256;
+constexpr int kSpTile = 4096;   // rows per partial sum
+
+__device__ __forceinline__ uint64_t sp_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)blockDim.x / 64; ++i) t += sh[i];
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+// sinv[v] = 1 / sqrt(d_v), u[v] = sqrt(d_v), d_v = sum of row v's weights;
+// err bit 1: a vertex of zero degree; bit 2: a weight negative or not finite.
+__global__ void __launch_bounds__(kSpBlock)
+sp_degree_kernel(int32_t n, const int32_t *__restrict__ rp, const float *__restrict__ val, double *__restrict__ sinv,
+                 double *__restrict__ u, int *__restrict__ err)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        double d = 0.0;
+        int bad = 0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const float x = val[e];
+            if (!(x >= 0.0f) || isinf(x)) bad = 2;
+            d += (double)x;
+        }
+        if (!(d > 0.0)) bad |= 1;
+        if (bad) atomicOr(err, bad);
+        sinv[v] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        u[v] = d > 0.0 ? sqrt(d) : 0.0;
+    }
+}
+
+// y = A x
+__global__ void __launch_bounds__(kSpBlock)
+sp_spmv_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+               const float *__restrict__ val, const double *__restrict__ sinv, const double *__restrict__ x,
+               double *__restrict__ y)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t c = col[e];
+            acc += (double)val[e] * (sinv[c] * x[c]);
+        }
+        y[v] = sinv[v] * acc;
+    }
+}
+
+// part[c * tiles + t] = sum over the rows of tile t of Q[:, c] * w
+__global__ void __launch_bounds__(kSpBlock)
+sp_gemvt_kernel(int32_t n, const double *__restrict__ Q, size_t ld, const double *__restrict__ w,
+                double *__restrict__ part, int tiles)
+{
+    __shared__ double sh[kSpBlock / 64];
+    const int c = blockIdx.y, t = blockIdx.x;
+    const int32_t r0 = t * kSpTile, r1 = min(n, r0 + kSpTile);
+    const double *q = Q + (size_t)c * ld;
+    double acc = 0.0;
+    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) acc += q[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(size_t)c * tiles + t] = s;
+}
+
+// h[c] = sum of the tiles' partials; hacc[c] = h[c] (first pass) or += h[c]
+// (second pass, which also stores *alpha_out = hacc[jcol])
+__global__ void __launch_bounds__(kSpBlock)
+sp_reduce_kernel(const double *__restrict__ part, int tiles, int ncols, double *__restrict__ h,
+                 double *__restrict__ hacc, int second, int jcol, double *__restrict__ alpha_out)
+{
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        double s = 0.0;
+        for (int t = 0; t < tiles; ++t) s += part[(size_t)c * tiles + t];
+        h[c] = s;
+        const double a = second ? hacc[c] + s : s;
+        hacc[c] = a;
+        if (second && c == jcol) *alpha_out = a;
+    }
+}
+
+// w -= Q[:, 0..ncols) h
+__global__ void __launch_bounds__(kSpBlock)
+sp_gemv_sub_kernel(int32_t n, const double *__restrict__ Q, size_t ld, int ncols, const double *__restrict__ h,
+                   double *__restrict__ w)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < ncols; ++c) acc += Q[(size_t)c * ld + i] * h[c];
+        w[i] -= acc;
+    }
+}
+
+__global__ void __launch_bounds__(kSpBlock)
+sp_sumsq_kernel(int32_t n, const double *__restrict__ w, double *__restrict__ part)
+{
+    __shared__ double sh[kSpBlock / 64];
+    const int32_t r0 = blockIdx.x * kSpTile, r1 = min(n, r0 + kSpTile);
+    double acc = 0.0;
+    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) acc += w[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[0] = sqrt(sum of the partials); below `tiny` it counts as zero (the
+// Krylov space is exhausted) and the next vector is zero.
+__global__ void sp_norm_kernel(const double *__restrict__ part, int tiles, double tiny, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += part[t];
+    const double r = sqrt(s);
+    out[0] = r > tiny ? r : 0.0;
+}
+
+__global__ void __launch_bounds__(kSpBlock)
+sp_scale_kernel(int32_t n, const double *w, const double *__restrict__ nrm, double *q)   // w may equal q
+{
+    const double r = nrm[0];
+    const double f = r > 0.0 ? 1.0 / r : 0.0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) q[i] = w[i] * f;
+}
+
+__global__ void __launch_bounds__(kSpBlock)
+sp_start_kernel(int32_t n, uint64_t seed, double *__restrict__ q)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        q[i] = (double)(sp_splitmix64(seed, (uint64_t)i + 1) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// x[i] = sum_c Q[i][c0 + c] s[c], c < m (a Ritz vector)
+__global__ void __launch_bounds__(kSpBlock)
+sp_ritz_kernel(int32_t n, const double *__restrict__ Q, size_t ld, int c0, int m, const double *__restrict__ s,
+               double *__restrict__ x)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int c = 0; c < m; ++c) a += Q[(size_t)(c0 + c) * ld + i] * s[c];
+        x[i] = a;
+    }
+}
+
+// Per tile and column: sum of squares and largest magnitude.
+__global__ void __launch_bounds__(kSpBlock)
+sp_stats_kernel(int32_t n, const double *__restrict__ X, double *__restrict__ part, int tiles)
+{
+    __shared__ double sh[kSpBlock / 64];
+    __shared__ double mx[kSpBlock];
+    const int k = blockIdx.y;
+    const double *x = X + (size_t)k * n;
+    const int32_t r0 = blockIdx.x * kSpTile, r1 = min(n, r0 + kSpTile);
+    double ss = 0.0, m = 0.0;
+    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        ss += x[i] * x[i];
+        m = fmax(m, fabs(x[i]));
+    }
+    const double s = block_sum(ss, sh);
+    mx[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[((size_t)k * tiles + blockIdx.x) * 2] = s;
+        part[((size_t)k * tiles + blockIdx.x) * 2 + 1] = mx[0];
+    }
+}
+
+// stat[k] = {norm, largest magnitude} of column k
+__global__ void sp_stats_reduce_kernel(const double *__restrict__ part, int tiles, double *__restrict__ stat)
+{
+    const int k = threadIdx.x;
+    if (k >= 2 || blockIdx.x != 0) return;
+    double s = 0.0, m = 0.0;
+    for (int t = 0; t < tiles; ++t) {
+        s += part[((size_t)k * tiles + t) * 2];
+        m = fmax(m, part[((size_t)k * tiles + t) * 2 + 1]);
+    }
+    stat[2 * k] = sqrt(s);
+    stat[2 * k + 1] = m;
+}
+
+// first[k] = the smallest index whose magnitude exceeds half the largest
+__global__ void __launch_bounds__(kSpBlock)
+sp_first_kernel(int32_t n, const double *__restrict__ X, const double *__restrict__ stat, int *__restrict__ first)
+{
+    const int k = blockIdx.y;
+    const double *x = X + (size_t)k * n;
+    const double thr = 0.5 * stat[2 * k + 1];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        if (fabs(x[i]) > thr) atomicMin(&first[k], i);
+}
+
+// xy[2 i + k] = sign_k x_k[i] / norm_k * 10 / max_k(largest_k / norm_k)
+__global__ void __launch_bounds__(kSpBlock)
+sp_finish_kernel(int32_t n, const double *__restrict__ X, const double *__restrict__ stat,
+                 const int *__restrict__ first, float *__restrict__ xy)
+{
+    if (!(stat[0] > 0.0) || !(stat[2] > 0.0)) {   // no Ritz vector (cannot happen after convergence)
+        for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n; i += gridDim.x * blockDim.x) xy[i] = 0.0f;
+        return;
+    }
+    const double m0 = stat[1] / stat[0], m1 = stat[3] / stat[2];
+    const double scale = 10.0 / fmax(m0, m1);
+    const int32_t p0 = first[0] < n ? first[0] : 0, p1 = first[1] < n ? first[1] : 0;
+    const double f0 = (X[p0] < 0.0 ? -scale : scale) / stat[0];
+    const double f1 = (X[(size_t)n + p1] < 0.0 ? -scale : scale) / stat[2];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        xy[2 * (size_t)i] = (float)(X[i] * f0);
+        xy[2 * (size_t)i + 1] = (float)(X[(size_t)n + i] * f1);
+    }
+}
+
+int sp_grid(int64_t work)
+{
+    int64_t b = (work + kSpBlock - 1) / kSpBlock;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+}  // namespace
+
+int spectral_tiles(int32_t n) { return (n + kSpTile - 1) / kSpTile; }
+
+hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, hipStream_t s)
+{
+    const int tiles = spectral_tiles(a.n);
+    hipLaunchKernelGGL(sp_degree_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.val, a.sinv,
+                       a.Q, err);
+    // column 0: D^1/2 1 normalised
+    hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, a.Q, a.part);
+    hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, 0.0, a.scal);
+    hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.scal, a.Q);
+    return hipGetLastError();
+}
+
+// Column c0 (the first Lanczos vector): a seeded vector orthogonalised twice
+// against columns 0 .. c0 - 1 and normalised.
+hipError_t launch_lanczos_start(const SpectralArgs &a, int c0, uint64_t seed, hipStream_t s)
+{
+    const int tiles = spectral_tiles(a.n);
+    hipLaunchKernelGGL(sp_start_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, seed, a.w);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, c0), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, a.w, a.part, tiles);
+        hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, c0, a.h, a.hacc, 0, -1,
+                           (double *)nullptr);
+        hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, c0, a.h,
+                           a.w);
+    }
+    hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, a.w, a.part);
+    hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, 0.0, a.scal);
+    hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.w, a.scal,
+                       a.Q + (size_t)c0 * a.ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_step(const SpectralArgs &a, int c0, int j, hipStream_t s)
+{
+    const int tiles = spectral_tiles(a.n);
+    const int cj = c0 + j - 1;   // column of Lanczos vector j
+    hipLaunchKernelGGL(sp_spmv_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.col, a.val, a.sinv,
+                       a.Q + (size_t)cj * a.ld, a.w);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, cj + 1), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, a.w, a.part,
+                           tiles);
+        hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, cj + 1, a.h, a.hacc, pass,
+                           cj, a.alpha + j);
+        hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, cj + 1, a.h,
+                           a.w);
+    }
+    hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, a.w, a.part);
+    hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, a.tiny, a.beta + j);
+    hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.w, a.beta + j,
+                       a.Q + (size_t)(cj + 1) * a.ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_ritz_vector(const SpectralArgs &a, int c0, int m, const double *svec, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(sp_ritz_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, c0, m, svec,
+                       a.X + (size_t)k * a.n);
+    return hipGetLastError();
+}
+
+// Column `col` = X[:, k] normalised (for the deflation of the second run).
+hipError_t launch_ritz_deflate(const SpectralArgs &a, int k, int col, hipStream_t s)
+{
+    const int tiles = spectral_tiles(a.n);
+    const double *x = a.X + (size_t)k * a.n;
+    hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, x, a.part);
+    hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, 0.0, a.scal);
+    hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, x, a.scal,
+                       a.Q + (size_t)col * a.ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectral_finish(const SpectralArgs &a, int *first, float *xy, hipStream_t s)
+{
+    const int tiles = spectral_tiles(a.n);
+    hipLaunchKernelGGL(sp_stats_kernel, dim3(tiles, 2), dim3(kSpBlock), 0, s, a.n, a.X, a.part, tiles);
+    hipLaunchKernelGGL(sp_stats_reduce_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, a.scal);
+    hipLaunchKernelGGL(sp_first_kernel, dim3(sp_grid(a.n), 2), dim3(kSpBlock), 0, s, a.n, a.X, a.scal, first);
+    hipLaunchKernelGGL(sp_finish_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.X, a.scal, first, xy);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ host side --
+// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal
+// a[0..m) and off-diagonal b[0..m-1) (b[i] couples i and i + 1) by implicit
+// QR steps with Wilkinson shifts (Golub and Van Loan, Matrix Computations,
+// the symmetric QR algorithm).  On return a holds the eigenvalues; if Z is
+// not NULL (m x m, row-major, set to the identity here) its columns are the
+// eigenvectors; if zlast is not NULL it receives the last row of that
+// matrix (only that row is updated, O(m) per rotation).
+bool tridiag_eigen(int m, double *a, double *b, double *Z, double *zlast)
+{
+    if (Z)
+        for (int i = 0; i < m; ++i)
+            for (int k = 0; k < m; ++k) Z[(size_t)i * m + k] = i == k ? 1.0 : 0.0;
+    if (zlast)
+        for (int k = 0; k < m; ++k) zlast[k] = k == m - 1 ? 1.0 : 0.0;
+    const double eps = 2.220446049250313e-16;
+    int hi = m - 1, iters = 0;
+    while (hi > 0) {
+        if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
+            b[hi - 1] = 0.0;
+            --hi;
+            iters = 0;
+            continue;
+        }
+        if (++iters > 60) return false;
+        int lo = hi - 1;
+        while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
+        // shift: the eigenvalue of the trailing 2 x 2 block closer to a[hi]
+        const double d = 0.5 * (a[hi - 1] - a[hi]);
+        const double bb = b[hi - 1] * b[hi - 1];
+        const double mu = a[hi] - bb / (d + (d >= 0.0 ? 1.0 : -1.0) * sqrt(d * d + bb));
+        double x = a[lo] - mu, z = b[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = hypot(x, z);
+            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
+            if (k > lo) b[k - 1] = r;
+            const double ak = a[k], ak1 = a[k + 1], bk = b[k];
+            a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
+            a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
+            b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
+            if (k + 1 < hi) {
+                x = b[k];
+                z = s * b[k + 1];
+                b[k + 1] *= c;
+            }
+            if (Z)
+                for (int i = 0; i < m; ++i) {
+                    const double zk = Z[(size_t)i * m + k], zk1 = Z[(size_t)i * m + k + 1];
+                    Z[(size_t)i * m + k] = c * zk + s * zk1;
+                    Z[(size_t)i * m + k + 1] = -s * zk + c * zk1;
+                }
+            if (zlast) {
+                const double zk = zlast[k], zk1 = zlast[k + 1];
+                zlast[k] = c * zk + s * zk1;
+                zlast[k + 1] = -s * zk + c * zk1;
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace gm

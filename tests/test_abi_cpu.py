@@ -29,6 +29,7 @@ def test_struct_layouts_match_header(gumap):
     assert ctypes.sizeof(gumap.gumap_batch) == 64
     assert ctypes.sizeof(gumap.gumap_batch_tuning) == 24
     assert ctypes.sizeof(gumap.gumap_layout_params) == 64
+    assert ctypes.sizeof(gumap.gumap_spectral_params) == 24
 
 
 def test_host_side_argument_errors(gumap):
@@ -93,7 +94,15 @@ def test_layout_entry_points_reject_bad_arguments(gumap):
     assert lib.gumap_grad_sample(2, None, 3, None, None, None, ctypes.byref(neg), 0, 1, None) == gumap.EINVAL
 
 
+def test_spectral_layout_rejects_bad_arguments(gumap):
+    lib = gumap.lib
+    assert lib.gumap_spectral_layout(2, None, None, None, None, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_spectral_layout(-5, None, None, None, None, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_spectral_layout(10, None, None, None, None, None, None, None, None) == gumap.EINVAL
+    assert "NULL" in gumap.last_error()
+
+
 def test_python_names_mirror_c_entry_points(gumap):
     for name in ("gumap_knn_build", "gumap_knn_partial", "gumap_membership", "gumap_knn_partial_batch",
-                 "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample"):
+                 "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample", "gumap_spectral_layout"):
         assert callable(getattr(gumap, name))
