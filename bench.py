@@ -412,10 +412,11 @@ def bench_neighborhood(args):
 
 def bench_layout(args):
     """SL-GUMAP's layout run on the BA graph (Alg. 3): partial BFS kNN and
-    membership (k = 15), fuzzy union, shuffle of E_k and t GradSample
-    iterations (Alg. 5, window floor(|E_k|^0.9), 5 negative samples per
-    edge) from a seeded uniform drawing (the paper starts from a spectral
-    layout; the drawing here is an input)."""
+    membership (k = 15), fuzzy union, the spectral initial drawing, shuffle
+    of E_k and t GradSample iterations (Alg. 5, window floor(|E_k|^0.9),
+    5 negative samples per edge).  GradSample's parity is checked from a
+    seeded uniform drawing (the oracle takes no input from the device), the
+    spectral drawing by its eigen-residual."""
     import numpy as np
     import torch
 
@@ -439,15 +440,19 @@ def bench_layout(args):
     ew = torch.empty(2 * n * k, dtype=torch.float32, device="cuda")
     xy0_d = torch.from_numpy(xy0).cuda()
     xy = torch.empty_like(xy0_d)
+    xy_init = torch.empty_like(xy0_d)
     seed_shuffle, seed_neg = G.BASE_SEED + 401, G.BASE_SEED + 402
     res = {}
+
+    sp_params = gm.gumap_spectral_params(0, 0, 0.0, G.BASE_SEED + 403)
 
     def step():
         gm.gumap_knn_partial(gg, k, ids, hops, stream)
         gm.gumap_membership(n, k, hops, w, None, None, stream)
         mm = gm.gumap_fuzzy_union(n, k, ids, w, urp, ucol, uval, 2 * n * k, stream)
+        res["ev"], res["sp_steps"] = gm.gumap_spectral_layout(n, urp, ucol, uval, sp_params, xy, stream)
+        xy_init.copy_(xy)
         gm.gumap_edge_shuffle(n, urp, ucol, uval, mm, seed_shuffle, head, tail, ew, stream)
-        xy.copy_(xy0_d)
         p = gm.layout_params(t=t, neg=5, samp=0.9, seed=seed_neg)
         gm.gumap_grad_sample(n, xy, mm, head, tail, ew, p, 0, t, stream)
         res["m"] = mm
@@ -465,17 +470,31 @@ def bench_layout(args):
            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64 (2^-32 fixed-point positions)", "data": "synthetic",
            "config": {"workload": "layout: BA n=%d m=%d; partial BFS kNN k=%d + membership + fuzzy union + "
-                                  "shuffle + %d GradSample iterations (window floor(|E_k|^0.9), 5 negative "
-                                  "samples) from a seeded uniform drawing in [-10, 10)^2" % (n, m_g, k, t),
+                                  "spectral initial drawing + shuffle + %d GradSample iterations (window "
+                                  "floor(|E_k|^0.9), 5 negative samples)" % (n, m_g, k, t),
                       "n": n, "m": m_g, "k": k, "edges_Ek": mm, "window": s_win, "iterations": t},
            "window_ms": kms.get("grad_window", 0.0) / t, "roofline": roof, "kernels_ms_per_step": kms}
-    out_xy = xy.cpu().numpy()
-    # quality of the drawing against the start (neighbourhood preservation, r = 2, sampled vertices)
+    out["spectral_eigenvalues"] = list(res["ev"])
+    out["spectral_lanczos_steps"] = res["sp_steps"]
+    # quality (neighbourhood preservation, r = 2, the 4,096 sampled vertices):
+    # a random drawing, the spectral drawing and the final layout
     verts = torch.from_numpy(G.config_ba_sources()).cuda()
-    sc1, _ = gm.neighborhood(rp, ci, xy, 2, verts, flags=gm.CSR_SORTED)
-    sc0, _ = gm.neighborhood(rp, ci, xy0_d, 2, verts, flags=gm.CSR_SORTED)
-    out["np_mean_start"] = float(torch.nanmean(sc0))
-    out["np_mean_layout"] = float(torch.nanmean(sc1))
+    for name, d in (("random", xy0_d), ("spectral", xy_init), ("layout", xy)):
+        sc, _ = gm.neighborhood(rp, ci, d, 2, verts, flags=gm.CSR_SORTED)
+        out["np_mean_" + name] = float(torch.nanmean(sc))
+    if not args.no_parity:
+        # the spectral drawing: eigen-residual of each coordinate vector (host sparse products)
+        import scipy.sparse as sp
+        mm = res["m"]
+        Wm = sp.csr_matrix((uval[:mm].cpu().numpy().astype(float), ucol[:mm].cpu().numpy(), urp.cpu().numpy()),
+                           shape=(n, n))
+        dg = np.asarray(Wm.sum(axis=1)).ravel()
+        sm = sp.diags(1 / np.sqrt(dg))
+        Lm = sp.identity(n) - sm @ Wm @ sm
+        p0 = xy_init.cpu().numpy().astype(float)
+        out["spectral_residuals"] = [float(np.linalg.norm(Lm @ (p0[:, c] / np.linalg.norm(p0[:, c]))
+                                                          - res["ev"][c] * p0[:, c] / np.linalg.norm(p0[:, c])))
+                                     for c in range(2)]
     if not args.no_parity or not args.no_cpu_baseline:
         import oracle as O
         threads = O.default_threads()
@@ -497,14 +516,16 @@ def bench_layout(args):
             out["parity_sampled_bit_exact"] = bool(
                 len(ocol) == mm and np.array_equal(head[:mm].cpu().numpy(), eh)
                 and np.array_equal(tail[:mm].cpu().numpy(), et) and np.array_equal(chk.cpu().numpy(), oxy))
-            out["parity_sample"] = "union + shuffled E_k, and the drawing after the first %d iterations" % few
+            out["parity_sample"] = ("union + shuffled E_k, and the drawing after the first %d iterations from a "
+                                    "seeded uniform drawing" % few)
         if not args.no_cpu_baseline:
             est = t_prep + t * t_win
             out["cpu_baseline"] = {"value": samples / est, "unit": "edge samples/s", "cores": threads,
                                    "kind": "oracle",
                                    "sample": "oracle kNN/membership/union/shuffle in full (%d threads) and %d of %d "
-                                             "GradSample iterations (one thread), scaled; run estimate %.1f s"
-                                             % (threads, few, t, est)}
+                                             "GradSample iterations (one thread), scaled; the spectral drawing is "
+                                             "left out (the oracle's dense eigendecomposition does not scale to "
+                                             "n = 100,000); run estimate %.1f s" % (threads, few, t, est)}
     print(json.dumps(out), flush=True)
 
 

@@ -212,7 +212,7 @@ int gumap_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, co
 typedef struct {
     int32_t max_steps;  /* Lanczos steps at most (default 600, never more than n - 1) */
     int32_t pad;
-    double tol;         /* residual |A x - mu x| of each eigenvector (default 1e-6) */
+    double tol;         /* residual |A x - mu x| of each eigenvector (default 1e-5) */
     uint64_t seed;      /* SplitMix64 seed of the starting vector */
 } gumap_spectral_params;
 

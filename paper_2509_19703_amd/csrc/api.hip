@@ -1108,8 +1108,8 @@ namespace {
 // One Lanczos run behind c0 deflated columns: steps until the largest Ritz
 // value's residual |beta_m z_m| is at most tol (or the Krylov space is
 // exhausted); then that Ritz vector into X[:, k].  *lambda = 1 - the Ritz value.
-int lanczos_run(const SpectralArgs &a, int c0, int jmax, double tol, uint64_t seed, double *svec, int k,
-                double *lambda, int *steps, hipStream_t s)
+int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol, uint64_t seed, double *svec,
+                int k, double *lambda, int *steps, hipStream_t s)
 {
     int st;
     hipError_t e = launch_lanczos_start(a, c0, seed, s);
@@ -1118,7 +1118,11 @@ int lanczos_run(const SpectralArgs &a, int c0, int jmax, double tol, uint64_t se
     int m = 0, top = 0;
     bool converged = false;
     for (int j = 1; j <= jmax; ++j) {
-        if ((e = launch_lanczos_step(a, c0, j, s)) != hipSuccess) return hip_status(e, "lanczos step");
+        // the sparse product (CSR, degree scales, the vector gathered), the
+        // local recurrence and one pass over the basis (projections, update)
+        GM_PROF("lanczos_step", (double)nnz * 24.0 + (double)a.n * 120.0 + 2.0 * (double)(c0 + j) * (double)a.n * 8.0,
+                launch_lanczos_step(a, c0, j, s));
+        if (e != hipSuccess) return hip_status(e, "lanczos step");
         if (j % 10 != 0 && j != jmax) continue;
         e = hipMemcpyAsync(ha.data(), a.alpha, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)
@@ -1178,7 +1182,7 @@ int spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const
     if (n < 3) return set_error(GUMAP_EINVAL, "n < 3 (two eigenvectors beyond the first need three vertices)");
     if (!row_ptr || !col || !val || !xy) return set_error(GUMAP_EINVAL, "NULL array");
     const int32_t max_steps = p && p->max_steps > 0 ? p->max_steps : 600;
-    const double tol = p && p->tol > 0.0 ? p->tol : 1e-6;
+    const double tol = p && p->tol > 0.0 ? p->tol : 1e-5;
     const uint64_t seed = p ? p->seed : 0;
     // run 1 works in the complement of one column, run 2 of two
     const int jmax = (int)std::min<int64_t>(max_steps, (int64_t)n - 1);
@@ -1207,25 +1211,41 @@ int spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const
     a.beta = q;         q += cols;
     a.scal = q;
     double *svec = nullptr;
-    if ((st = scratch_get(kSlotSpectralVec, (size_t)cols * sizeof(double) + 256, (void **)&svec))) return st;
+    if ((st = scratch_get(kSlotSpectralVec, (size_t)cols * sizeof(double) + 256 + (size_t)n * sizeof(int32_t),
+                          (void **)&svec)))
+        return st;
+    a.heavy = (int32_t *)(svec + cols + 32);
     int *err = nullptr;
     if ((st = scratch_get(kSlotFlags, 256, (void **)&err))) return st;
     int *first = err + 16;
-    hipError_t e = hipMemsetAsync(err, 0, sizeof(int), s);
+    // err[0]: flags, err[1]: entries (row_ptr[n]), err[2]: long rows
+    hipError_t e = hipMemsetAsync(err, 0, 3 * sizeof(int), s);
     if (e == hipSuccess) e = hipMemsetAsync(first, 0x7f, 2 * sizeof(int), s);
-    if (e == hipSuccess) e = launch_spectral_setup(a, err, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(err + 1, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_spectral_setup(a, err, err + 2, s);
     if (e != hipSuccess) return hip_status(e, "spectral setup");
-    int bad = 0;
-    if ((st = read_flag(err, &bad, s))) return st;
-    if (bad & 2) return set_error(GUMAP_EINVAL, "a weight is negative or not finite");
-    if (bad & 1) return set_error(GUMAP_EGRAPH, "a vertex has zero degree (the graph is not connected)");
+    int hflags[3];
+    {
+        void *hv = nullptr;
+        if ((st = host_scratch_get(64, &hv))) return st;
+        e = hipMemcpyAsync(hv, err, 3 * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "spectral setup");
+        std::memcpy(hflags, hv, sizeof(hflags));
+    }
+    if (hflags[0] & 2) return set_error(GUMAP_EINVAL, "a weight is negative or not finite");
+    if (hflags[0] & 1) return set_error(GUMAP_EGRAPH, "a vertex has zero degree (the graph is not connected)");
+    const int32_t nnz = hflags[1];   // for the profiler's byte counts
+    a.heavy_rows = hflags[2];
     double lam[2] = {0.0, 0.0};
     int total_steps = 0;
-    if ((st = lanczos_run(a, 1, std::min(jmax, n - 1), tol, seed, svec, 0, &lam[0], &total_steps, s))) return st;
+    if ((st = lanczos_run(a, nnz, 1, std::min(jmax, n - 1), tol, seed, svec, 0, &lam[0], &total_steps, s)))
+        return st;
     if (lam[0] < 1e-10) return set_error(GUMAP_EGRAPH, "second eigenvalue %g: the graph is not connected", lam[0]);
     e = launch_ritz_deflate(a, 0, 1, s);
     if (e != hipSuccess) return hip_status(e, "deflation");
-    if ((st = lanczos_run(a, 2, std::min(jmax, n - 2), tol, seed + 1, svec, 1, &lam[1], &total_steps, s))) return st;
+    if ((st = lanczos_run(a, nnz, 2, std::min(jmax, n - 2), tol, seed + 1, svec, 1, &lam[1], &total_steps, s)))
+        return st;
     e = launch_spectral_finish(a, first, xy, s);
     if (e != hipSuccess) return hip_status(e, "spectral finish");
     if ((st = finish(s, "gumap_spectral_layout"))) return st;

@@ -268,11 +268,14 @@ struct SpectralArgs {
     double *scal;             // 8 scalars
     double *X;                // 2 n: the two Ritz vectors, column-major
     double tiny;              // norms at or below this count as zero (Krylov space exhausted)
+    int32_t *heavy;           // n: rows with many entries (one block each in the sparse product)
+    int32_t heavy_rows;       // their count (read back after the setup)
 };
 int spectral_tiles(int32_t n);
-// Degrees (err bit 1: zero degree, bit 2: a weight negative or not finite)
-// and column 0 = D^1/2 1 normalised.
-hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, hipStream_t s);
+// Degrees (err bit 1: zero degree, bit 2: a weight negative or not finite),
+// column 0 = D^1/2 1 normalised, and the list of long rows (a.heavy,
+// *heavy_count entries; *heavy_count zero beforehand).
+hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, int32_t *heavy_count, hipStream_t s);
 // Column c0: the first Lanczos vector, from a SplitMix64-seeded vector
 // orthogonalised against columns 0 .. c0 - 1.
 hipError_t launch_lanczos_start(const SpectralArgs &a, int c0, uint64_t seed, hipStream_t s);

@@ -7,9 +7,10 @@
 // A = D^-1/2 W D^-1/2 on the complement of its top eigenvector D^1/2 1
 // (eigenvalue 1), found by Lanczos iteration in FP64: the Krylov basis Q is
 // kept whole (column-major, one column per step) behind the deflated
-// columns, and every new vector is orthogonalised against all of it twice
-// (classical Gram-Schmidt applied twice), which keeps Q orthonormal to
-// rounding and removes the deflated directions.  Two runs: the first, with
+// columns, and every new vector is orthogonalised against all of it once
+// after the three-term recurrence has removed the two large components
+// (one classical Gram-Schmidt pass then meets only rounding error), which
+// keeps Q orthonormal to rounding and removes the deflated directions.  Two runs: the first, with
 // column 0 = D^1/2 1 normalised, converges the top eigenpair; the second
 // also deflates that eigenvector (column 1) and converges the next, so that
 // a repeated eigenvalue (a cycle's, a complete graph's) still yields two
@@ -73,35 +74,92 @@ sp_degree_kernel(int32_t n, const int32_t *__restrict__ rp, const float *__restr
     }
 }
 
-// y = A x
+// Rows with more than kSpHeavyRow entries (listed once per call).
+constexpr int kSpHeavyRow = 128;
+constexpr int kSpTeam = 8;
+
+__global__ void __launch_bounds__(kSpBlock)
+sp_heavy_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t *__restrict__ heavy, int32_t *__restrict__ count)
+{
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (rp[v + 1] - rp[v] > kSpHeavyRow) heavy[atomicAdd(count, 1)] = v;
+}
+
+// y = A x: blocks [0, heavy_blocks) take one heavy row each (block-wide
+// sum), the others kSpTeam lanes per remaining row.
 __global__ void __launch_bounds__(kSpBlock)
 sp_spmv_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                const float *__restrict__ val, const double *__restrict__ sinv, const double *__restrict__ x,
-               double *__restrict__ y)
+               double *__restrict__ y, const int32_t *__restrict__ heavy, int heavy_blocks)
 {
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if ((int)blockIdx.x < heavy_blocks) {
+        __shared__ double sh[kSpBlock / 64];
+        const int32_t v = heavy[blockIdx.x];
         double acc = 0.0;
-        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        for (int32_t e = rp[v] + threadIdx.x; e < rp[v + 1]; e += blockDim.x) {
             const int32_t c = col[e];
             acc += (double)val[e] * (sinv[c] * x[c]);
         }
-        y[v] = sinv[v] * acc;
+        const double t = block_sum(acc, sh);
+        if (threadIdx.x == 0) y[v] = sinv[v] * t;
+        return;
+    }
+    const int32_t v = (int32_t)((((int64_t)blockIdx.x - heavy_blocks) * kSpBlock + threadIdx.x) / kSpTeam);
+    const int lane_t = threadIdx.x % kSpTeam;
+    const bool valid = v < n;
+    const int32_t b = valid ? rp[v] : 0, e1 = valid ? rp[v + 1] : 0;
+    const bool mine = valid && e1 - b <= kSpHeavyRow;
+    double acc = 0.0;
+    if (mine)
+        for (int32_t e = b + lane_t; e < e1; e += kSpTeam) {
+            const int32_t c = col[e];
+            acc += (double)val[e] * (sinv[c] * x[c]);
+        }
+    for (int o = kSpTeam / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (mine && lane_t == 0) y[v] = sinv[v] * acc;
+}
+
+// part[c * tiles + t] = sum over the rows of tile t of Q[:, c] * w, for
+// columns c0 .. c0 + kSpCols of block (t, cb) (c < ncols): w is read once
+// per column block
+constexpr int kSpCols = 8;
+
+__global__ void __launch_bounds__(kSpBlock)
+sp_gemvt_kernel(int32_t n, const double *__restrict__ Q, size_t ld, int ncols, const double *__restrict__ w,
+                double *__restrict__ part, int tiles)
+{
+    __shared__ double sh[kSpCols][kSpBlock / 64];
+    const int t = blockIdx.x, c0 = blockIdx.y * kSpCols;
+    const int32_t r0 = t * kSpTile, r1 = min(n, r0 + kSpTile);
+    double acc[kSpCols];
+#pragma unroll
+    for (int u = 0; u < kSpCols; ++u) acc[u] = 0.0;
+    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int u = 0; u < kSpCols; ++u)
+            if (c0 + u < ncols) acc[u] += Q[(size_t)(c0 + u) * ld + i] * wi;
+    }
+#pragma unroll
+    for (int u = 0; u < kSpCols; ++u) {
+        double v = acc[u];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[u][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kSpCols && c0 + (int)threadIdx.x < ncols) {
+        double v = 0.0;
+        for (int q = 0; q < kSpBlock / 64; ++q) v += sh[threadIdx.x][q];
+        part[(size_t)(c0 + threadIdx.x) * tiles + t] = v;
     }
 }
 
-// part[c * tiles + t] = sum over the rows of tile t of Q[:, c] * w
+// w -= coef[0] * q
 __global__ void __launch_bounds__(kSpBlock)
-sp_gemvt_kernel(int32_t n, const double *__restrict__ Q, size_t ld, const double *__restrict__ w,
-                double *__restrict__ part, int tiles)
+sp_axpy_kernel(int32_t n, const double *__restrict__ q, const double *__restrict__ coef, double *__restrict__ w)
 {
-    __shared__ double sh[kSpBlock / 64];
-    const int c = blockIdx.y, t = blockIdx.x;
-    const int32_t r0 = t * kSpTile, r1 = min(n, r0 + kSpTile);
-    const double *q = Q + (size_t)c * ld;
-    double acc = 0.0;
-    for (int32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) acc += q[i] * w[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[(size_t)c * tiles + t] = s;
+    const double f = coef[0];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] -= f * q[i];
 }
 
 // h[c] = sum of the tiles' partials; hacc[c] = h[c] (first pass) or += h[c]
@@ -117,6 +175,23 @@ sp_reduce_kernel(const double *__restrict__ part, int tiles, int ncols, double *
         const double a = second ? hacc[c] + s : s;
         hacc[c] = a;
         if (second && c == jcol) *alpha_out = a;
+    }
+}
+
+// The full pass of a Lanczos step: h[c] = sum of the partials for every
+// column; *alpha_out = the local alpha (h[0] on entry, from the projection
+// on q[j] alone) + the correction h[jcol].
+__global__ void __launch_bounds__(kSpBlock)
+sp_reduce_full_kernel(const double *__restrict__ part, int tiles, int ncols, double *__restrict__ h, int jcol,
+                      double *__restrict__ alpha_out)
+{
+    const double local = h[0];   // the local alpha, read before h is overwritten
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+        double s = 0.0;
+        for (int t = 0; t < tiles; ++t) s += part[(size_t)c * tiles + t];
+        h[c] = s;
+        if (c == jcol) *alpha_out = local + s;
     }
 }
 
@@ -265,9 +340,11 @@ int sp_grid(int64_t work)
 
 int spectral_tiles(int32_t n) { return (n + kSpTile - 1) / kSpTile; }
 
-hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, hipStream_t s)
+hipError_t launch_spectral_setup(const SpectralArgs &a, int *err, int32_t *heavy_count, hipStream_t s)
 {
     const int tiles = spectral_tiles(a.n);
+    hipLaunchKernelGGL(sp_heavy_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.heavy,
+                       heavy_count);
     hipLaunchKernelGGL(sp_degree_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.val, a.sinv,
                        a.Q, err);
     // column 0: D^1/2 1 normalised
@@ -284,7 +361,8 @@ hipError_t launch_lanczos_start(const SpectralArgs &a, int c0, uint64_t seed, hi
     const int tiles = spectral_tiles(a.n);
     hipLaunchKernelGGL(sp_start_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, seed, a.w);
     for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, c0), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, a.w, a.part, tiles);
+        hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, (c0 + kSpCols - 1) / kSpCols), dim3(kSpBlock), 0, s, a.n, a.Q,
+                           a.ld, c0, a.w, a.part, tiles);
         hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, c0, a.h, a.hacc, 0, -1,
                            (double *)nullptr);
         hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, c0, a.h,
@@ -301,16 +379,25 @@ hipError_t launch_lanczos_step(const SpectralArgs &a, int c0, int j, hipStream_t
 {
     const int tiles = spectral_tiles(a.n);
     const int cj = c0 + j - 1;   // column of Lanczos vector j
-    hipLaunchKernelGGL(sp_spmv_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.col, a.val, a.sinv,
-                       a.Q + (size_t)cj * a.ld, a.w);
-    for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, cj + 1), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, a.w, a.part,
-                           tiles);
-        hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, cj + 1, a.h, a.hacc, pass,
-                           cj, a.alpha + j);
-        hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, cj + 1, a.h,
+    const double *qj = a.Q + (size_t)cj * a.ld;
+    const int light_blocks = (int)(((int64_t)a.n * kSpTeam + kSpBlock - 1) / kSpBlock);
+    hipLaunchKernelGGL(sp_spmv_kernel, dim3(a.heavy_rows + light_blocks), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.col,
+                       a.val, a.sinv, qj, a.w, a.heavy, a.heavy_rows);
+    // the three-term recurrence first: w -= beta[j-1] q[j-1], then w -= alpha q[j]
+    // with alpha = q[j] . w; what remains along the basis is rounding error,
+    // which one full projection pass removes
+    if (j > 1)
+        hipLaunchKernelGGL(sp_axpy_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, qj - a.ld, a.beta + j - 1,
                            a.w);
-    }
+    hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, 1), dim3(kSpBlock), 0, s, a.n, qj, a.ld, 1, a.w, a.part, tiles);
+    hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, 1, a.h, a.hacc, 0, -1,
+                       (double *)nullptr);
+    hipLaunchKernelGGL(sp_axpy_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, qj, a.h, a.w);
+    hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, (cj + 1 + kSpCols - 1) / kSpCols), dim3(kSpBlock), 0, s, a.n, a.Q,
+                       a.ld, cj + 1, a.w, a.part, tiles);
+    hipLaunchKernelGGL(sp_reduce_full_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, cj + 1, a.h, cj,
+                       a.alpha + j);
+    hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, cj + 1, a.h, a.w);
     hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, a.w, a.part);
     hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, a.tiny, a.beta + j);
     hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.w, a.beta + j,

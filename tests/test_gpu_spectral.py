@@ -6,7 +6,7 @@ tol / gap (the tests ask for residual tol = 1e-10; gap = the distance from a
 wanted eigenvalue to the rest of the spectrum), then rounds to float after
 the scaling to 10: on the test graphs (gaps above 1e-3) coordinates agree to
 1e-5 absolute and eigenvalues to 1e-9.  At full size the spectrum's low end
-is clustered (the BA graph is an expander) and the default residual 1e-6 is
+is clustered (the BA graph is an expander) and the default residual 1e-5 is
 checked directly.  Where the second eigenvalue is
 double (a cycle) only the plane is unique: the drawing must be the same
 regular polygon.
@@ -140,7 +140,7 @@ def test_spectral_errors(gumap):
 
 def test_spectral_ba100k_union_graph(gumap):
     """Full size: the fuzzy-union graph of the BA n = 100,000 workload, at the
-    default residual 1e-6.  Checked on the host with sparse products: the
+    default residual 1e-5.  Checked on the host with sparse products: the
     eigen-equation of each (float) coordinate vector, orthogonality to
     D^1/2 1 and to each other, eigenvalues at the low end of the spectrum
     (a few Lanczos steps of scipy give a lower bound check), and the scale."""
@@ -164,9 +164,9 @@ def test_spectral_ba100k_union_graph(gumap):
         v = p[:, k] / np.linalg.norm(p[:, k])
         res = np.linalg.norm(L @ v - ev[k] * v)
         print("  residual", k, res, flush=True)
-        assert res < 2e-6
+        assert res < 2e-5
         assert abs(v @ np.sqrt(d)) / np.linalg.norm(np.sqrt(d)) < 1e-5
-        assert abs(v @ (L @ v) - ev[k]) < 1e-8
+        assert abs(v @ (L @ v) - ev[k]) < 1e-7
         vs.append(v)
     assert abs(vs[0] @ vs[1]) < 1e-5
     assert 0 < ev[0] <= ev[1] + 1e-9 < 1
