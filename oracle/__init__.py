@@ -6,7 +6,9 @@ Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1) and of the drawing
 quality metrics of Sec. 5.1 computed on the same BFS, and of the layout step C2
 that follows (fuzzy union of the kNN weights, edge shuffle and the sliding
 window GradSample of Alg. 5) and its spectral initial drawing (dense
-eigendecomposition, in this module).  Only ``tests/``,
+eigendecomposition, in this module), and the spectral sparsification
+front end (effective resistances by random projection and conjugate
+gradients, the maximum spanning forest and the top edges, in this module).  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
 it.  It shares no code with the GPU library and the GPU library never calls
 it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
@@ -296,3 +298,115 @@ def spectral_layout(n: int, row_ptr, col, val, dim: int = 2):
             V[:, j] = -V[:, j]
     scale = 10.0 / np.abs(V).max()
     return (V * scale).astype(np.float32), evals[1:dim + 1].copy()
+
+
+# ------------------------------------------------- spectral sparsification ---
+def undirected_edges(row_ptr, col):
+    """The edges (u, v), u < v, of a symmetric CSR in CSR order: (u, v) arrays."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    c = np.asarray(col, dtype=np.int64)
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    up = c > rows
+    return rows[up], c[up]
+
+
+def jl_signs(seed: int, q: int, m: int) -> np.ndarray:
+    """s[k, e] = +1 when bit 63 of SplitMix64(seed, k m + e + 1) is 0, else -1."""
+    s = np.empty((q, m), dtype=np.float64)
+    for k in range(q):
+        for e in range(m):
+            s[k, e] = -1.0 if (splitmix64(seed, k * m + e + 1) >> 63) else 1.0
+    return s
+
+
+def effective_resistance(n: int, row_ptr, col, q: int = 32, seed: int = 0, tol: float = 1e-10,
+                         max_iters: int = 2000, return_x: bool = False):
+    """Effective resistances of the edges of an unweighted graph (Sec. 3.2,
+    Alg. 2: the sparsifier ranks edges by effective resistance), estimated
+    as Spielman and Srivastava do: with random signs s_k (q vectors over the
+    edges), x_k solves L x_k = B^T s_k (B the edge-vertex incidence, L = D - W)
+    by conjugate gradients preconditioned with D, from x = 0, stopping when
+    |r| <= tol |b| (or after max_iters), and
+    R_e = (1/q) sum_k (x_k(u) - x_k(v))^2 for e = (u, v).
+    FP64, plain loops over the steps.  Returns (R float64[m], iterations)."""
+    u, v = undirected_edges(row_ptr, col)
+    m = len(u)
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    c = np.asarray(col, dtype=np.int64)
+    deg = np.diff(rp).astype(np.float64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+
+    def lap(x):   # L x for every column of x (n x q)
+        y = deg[:, None] * x
+        np.subtract.at(y, rows, x[c])
+        return y
+
+    S = jl_signs(seed, q, m)
+    B = np.zeros((n, q))
+    for k in range(q):
+        np.add.at(B[:, k], u, S[k])
+        np.subtract.at(B[:, k], v, S[k])
+    X = np.zeros((n, q))
+    its = 0
+    dinv = np.where(deg > 0, 1.0 / np.where(deg > 0, deg, 1.0), 0.0)
+    for k in range(q):
+        b = B[:, k]
+        bn = np.sqrt(b @ b)
+        x = np.zeros(n)
+        r = b.copy()
+        z = dinv * r
+        p = z.copy()
+        rz = r @ z
+        it = 0
+        while np.sqrt(r @ r) > tol * bn and it < max_iters:
+            Ap = lap(p[:, None])[:, 0]
+            a = rz / (p @ Ap)
+            x += a * p
+            r -= a * Ap
+            z = dinv * r
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+            it += 1
+        X[:, k] = x
+        its = max(its, it)
+    R = ((X[u] - X[v]) ** 2).sum(axis=1) / q
+    return (R, its, X, B) if return_x else (R, its)
+
+
+def sparsify_select(n: int, row_ptr, col, R, target: int | None = None):
+    """The sparsifier's edge choice (Sec. 3.2, Alg. 2): a maximum spanning
+    forest with the effective resistances as weights, then further edges in
+    decreasing resistance until `target` edges (default ceil(n ln n), at most
+    m).  Edges are ordered by (R descending, edge index ascending), so the
+    forest and the choice are unique.  Returns keep (bool [m])."""
+    u, v = undirected_edges(row_ptr, col)
+    m = len(u)
+    R = np.asarray(R, dtype=np.float64)
+    if target is None:
+        target = int(np.ceil(n * np.log(n))) if n > 1 else 0
+    target = min(target, m)
+    order = sorted(range(m), key=lambda e: (-R[e], e))
+    parent = list(range(n))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    keep = np.zeros(m, dtype=bool)
+    count = 0
+    for e in order:
+        a, b = find(int(u[e])), find(int(v[e]))
+        if a != b:
+            parent[a] = b
+            keep[e] = True
+            count += 1
+    for e in order:
+        if count >= target:
+            break
+        if not keep[e]:
+            keep[e] = True
+            count += 1
+    return keep
