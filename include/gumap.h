@@ -208,6 +208,48 @@ int gumap_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const float *
 int gumap_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val, int64_t m,
                        uint64_t seed, int32_t *head, int32_t *tail, float *w, hipStream_t stream);
 
+/*
+ * Spectral sparsification front end of SS-GUMAP / SSSL-GUMAP (Sec. 3.2,
+ * Alg. 2 and Alg. 6): rank the edges by effective resistance, keep a maximum
+ * spanning tree (forest) of the resistances and then the edges of highest
+ * resistance until about n log n edges.  The edges of a graph are its
+ * entries (u, v) with u < v, numbered in CSR order of the canonical CSR.
+ *
+ * gumap_effective_resistance: R_e of every edge of the (unweighted,
+ * symmetric) graph, estimated by random projection (Spielman and
+ * Srivastava): with q sign vectors s_k over the edges (s_k(e) = -1 when bit
+ * 63 of SplitMix64(seed, k m + e + 1) is set, else +1), x_k solves
+ * L x_k = B^T s_k (L = D - W, B the edge-vertex incidence) by conjugate
+ * gradients preconditioned with the degrees, from x = 0, each until
+ * |r| <= tol |b| or max_iters iterations; R_e = (1/q) sum_k (x_k(u) - x_k(v))^2.
+ * The estimate is unbiased with relative spread about sqrt(2 / q).  FP64.
+ *   q           sign vectors, 1 .. 1024 (n q < 2^31)
+ *   resistance  device double[g->nnz / 2] (out), indexed by edge
+ *   edges       host int64 or NULL (out): number of edges m
+ *   iterations  host int32 or NULL (out): CG iterations run (the slowest column)
+ * Errors: GUMAP_EINVAL (NULL pointer, q, tol <= 0, max_iters < 1),
+ * GUMAP_EGRAPH (malformed under GUMAP_VALIDATE; not symmetric or with
+ * self-loops after canonicalisation), GUMAP_ENOMEM, GUMAP_EDEVICE.
+ */
+int gumap_effective_resistance(const gumap_graph *g, int32_t q, uint64_t seed, double tol, int32_t max_iters,
+                               double *resistance, int64_t *edges, int32_t *iterations, hipStream_t stream);
+
+/*
+ * gumap_sparsify_select: the sparsified graph G' for given edge weights
+ * (the resistances): the maximum spanning forest in the order (resistance
+ * descending, edge index ascending), which makes it unique, then the
+ * further edges first in that order until `target` edges (target <= 0:
+ * ceil(n ln n); at most m; the forest is kept whole if it alone exceeds
+ * the target).
+ *   resistance   device double[m], non-negative (gumap_effective_resistance's output)
+ *   out_row_ptr  device int32[n + 1], out_col_idx device int32[g->nnz] (out):
+ *                the symmetric CSR of G', columns ascending
+ *   out_nnz      host int32 (out): entries of G' (twice its edges)
+ * Errors: as gumap_effective_resistance (NULL pointer, graph).
+ */
+int gumap_sparsify_select(const gumap_graph *g, const double *resistance, int64_t target, int32_t *out_row_ptr,
+                          int32_t *out_col_idx, int32_t *out_nnz, hipStream_t stream);
+
 /* Parameters of gumap_spectral_layout (zero fields take the defaults). */
 typedef struct {
     int32_t max_steps;  /* Lanczos steps at most (default 600, never more than n - 1) */

@@ -121,6 +121,11 @@ def _load() -> ctypes.CDLL:
     lib.gumap_fuzzy_union.argtypes = [i32, i32, vp, vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp]
     lib.gumap_edge_shuffle.argtypes = [i32, vp, vp, vp, i64, ctypes.c_uint64, vp, vp, vp, vp]
     lib.gumap_grad_sample.argtypes = [i32, vp, i64, vp, vp, vp, ctypes.POINTER(gumap_layout_params), i32, i32, vp]
+    lib.gumap_effective_resistance.argtypes = [G, i32, ctypes.c_uint64, ctypes.c_double, i32, vp,
+                                               ctypes.POINTER(i64), ctypes.POINTER(i32), vp]
+    lib.gumap_sparsify_select.argtypes = [G, vp, i64, vp, vp, ctypes.POINTER(i32), vp]
+    lib.gumap_effective_resistance.restype = ctypes.c_int
+    lib.gumap_sparsify_select.restype = ctypes.c_int
     lib.gumap_spectral_layout.argtypes = [i32, vp, vp, vp, ctypes.POINTER(gumap_spectral_params), vp,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), vp]
     for f in (lib.gumap_fuzzy_union, lib.gumap_edge_shuffle, lib.gumap_grad_sample, lib.gumap_spectral_layout):
@@ -425,6 +430,45 @@ def spectral_layout(row_ptr, col, val, max_steps: int = 0, tol: float = 0.0, see
     p = gumap_spectral_params(int(max_steps), 0, float(tol), int(seed) & (2**64 - 1))
     ev, steps = gumap_spectral_layout(n, row_ptr, col, val, p, xy, stream)
     return xy, ev, steps
+
+
+def gumap_effective_resistance(g, q, seed, tol, max_iters, resistance, stream=None):
+    """C-ABI gumap_effective_resistance; returns (edges, CG iterations)."""
+    m = ctypes.c_int64(0)
+    its = ctypes.c_int32(0)
+    _check(lib.gumap_effective_resistance(ctypes.byref(g), int(q), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                          float(tol), int(max_iters), _ptr(resistance), ctypes.byref(m),
+                                          ctypes.byref(its), _stream(stream)))
+    return m.value, its.value
+
+
+def effective_resistance(row_ptr, col_idx, q: int = 32, seed: int = 0, tol: float = 1e-10, max_iters: int = 2000,
+                         flags: int = 0, stream=None):
+    """Effective resistances of the edges (u < v, CSR order) of a symmetric
+    graph.  Returns (R float64 [m], CG iterations)."""
+    torch = _torch()
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    R = torch.empty(max(g.nnz // 2, 1), dtype=torch.float64, device=row_ptr.device)
+    m, its = gumap_effective_resistance(g, q, seed, tol, max_iters, R, stream)
+    return R[:m], its
+
+
+def gumap_sparsify_select(g, resistance, target, out_row_ptr, out_col_idx, stream=None) -> int:
+    """C-ABI gumap_sparsify_select; returns the entry count of G'."""
+    nnz = ctypes.c_int32(0)
+    _check(lib.gumap_sparsify_select(ctypes.byref(g), _ptr(resistance), int(target), _ptr(out_row_ptr),
+                                     _ptr(out_col_idx), ctypes.byref(nnz), _stream(stream)))
+    return nnz.value
+
+
+def sparsify_select(row_ptr, col_idx, resistance, target: int = 0, flags: int = 0, stream=None):
+    """The sparsified graph G' (symmetric CSR) for the given edge resistances."""
+    torch = _torch()
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    out_rp = torch.empty(g.n + 1, dtype=torch.int32, device=row_ptr.device)
+    out_col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=row_ptr.device)
+    nnz = gumap_sparsify_select(g, resistance, target, out_rp, out_col, stream)
+    return out_rp, out_col[:nnz]
 
 
 class PackedBatch:

@@ -1257,6 +1257,183 @@ int spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col, const
     return GUMAP_OK;
 }
 
+// ------------------------------------------------ spectral sparsification --
+namespace {
+
+// Scratch of the sparsifier for a canonical graph (n, nnz) and q columns.
+int sparsify_args(const CanonCsr &c, int32_t nnz, int32_t q, SparsifyArgs *a, void **scan_tmp)
+{
+    int st;
+    const int32_t n = c.n;
+    const int64_t m_max = (int64_t)nnz + 1;   // upper entries, whatever the input
+    const int tiles = sparsify_tiles(n);
+    const size_t nq = (size_t)n * (size_t)(q > 0 ? q : 1);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t bytes = 2 * al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + 2 * al((size_t)m_max * 4) +
+                   (q > 0 ? 6 * al(nq * 8) + al((size_t)tiles * q * 3 * 8) + al((size_t)q * 3 * 8) +
+                                al((size_t)q * 8 * 8) + al((size_t)q * 4) : 0) +
+                   al(256) + 3 * al((size_t)n * 4) + al((size_t)n * 8) + al((size_t)m_max) +
+                   al(exclusive_scan_scratch_bytes(n > 0 ? n : 1));
+    char *p = nullptr;
+    if ((st = scratch_get(kSlotSparsify, bytes, (void **)&p))) return st;
+    *a = SparsifyArgs{};
+    a->n = n;
+    a->row_ptr = c.row_ptr;
+    a->col = c.col;
+    a->upper = (int32_t *)p;            p += al((size_t)(n + 1) * 4);
+    a->eoff = (int32_t *)p;             p += al((size_t)(n + 1) * 4);
+    a->eid = (int32_t *)p;              p += al((size_t)nnz * 4);
+    a->eu = (int32_t *)p;               p += al((size_t)m_max * 4);
+    a->ev = (int32_t *)p;               p += al((size_t)m_max * 4);
+    if (q > 0) {
+        double **vecs[6] = {&a->B, &a->X, &a->Rv, &a->Z, &a->P, &a->AP};
+        for (double **v : vecs) {
+            *v = (double *)p;
+            p += al(nq * 8);
+        }
+        a->part = (double *)p;          p += al((size_t)tiles * q * 3 * 8);
+        a->sums = (double *)p;          p += al((size_t)q * 3 * 8);
+        a->st = (double *)p;            p += al((size_t)q * 8 * 8);
+        a->active = (int *)p;           p += al((size_t)q * 4);
+    }
+    a->n_active = (int *)p;             p += al(256);
+    a->comp = (int32_t *)p;             p += al((size_t)n * 4);
+    a->parent = (int32_t *)p;           p += al((size_t)n * 4);
+    a->bestE = (int32_t *)p;            p += al((size_t)n * 4);
+    a->bestR = (unsigned long long *)p; p += al((size_t)n * 8);
+    a->keep = (uint8_t *)p;             p += al((size_t)m_max);
+    *scan_tmp = p;
+    return GUMAP_OK;
+}
+
+// Canonical graph, its entry count and the edge ids; a->m read back.
+int sparsify_prepare(const gumap_graph *g, int32_t q, hipStream_t s, CanonCsr *c, SparsifyArgs *a, void **scan_tmp)
+{
+    int st;
+    if ((st = prepare_graph(g, s, c))) return st;
+    int32_t nnz = g->nnz;
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    hipError_t e = hipMemcpyAsync(h, c->row_ptr + c->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "sparsify setup");
+    nnz = *(int32_t *)h;
+    if ((st = sparsify_args(*c, nnz, q, a, scan_tmp))) return st;
+    e = launch_edge_ids(*a, *scan_tmp, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, a->eoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_status(e, "edge ids");
+    a->m = *(int32_t *)h;
+    // a symmetric graph without self-loops has exactly nnz / 2 edges
+    if (2 * a->m != (int64_t)nnz) return set_error(GUMAP_EGRAPH, "the graph is not symmetric or has self-loops");
+    return GUMAP_OK;
+}
+
+}  // namespace
+
+int effective_resistance(const gumap_graph *g, int32_t q, uint64_t seed, double tol, int32_t max_iters, double *R,
+                         int64_t *m_out, int32_t *iters_out, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if (q < 1 || q > 1024) return set_error(GUMAP_EINVAL, "q outside [1, 1024]");
+    if (!(tol > 0.0) || max_iters < 1) return set_error(GUMAP_EINVAL, "tol must be positive, max_iters >= 1");
+    if (m_out) *m_out = 0;
+    if (iters_out) *iters_out = 0;
+    if (g->n == 0 || g->nnz == 0) return GUMAP_OK;
+    if (!R) return set_error(GUMAP_EINVAL, "R is NULL");
+    if ((int64_t)g->n * q >= ((int64_t)1 << 31)) return set_error(GUMAP_EINVAL, "n * q >= 2^31");
+    CanonCsr c;
+    SparsifyArgs a;
+    void *scan_tmp = nullptr;
+    if ((st = sparsify_prepare(g, q, s, &c, &a, &scan_tmp))) return st;
+    if (m_out) *m_out = a.m;
+    if (a.m == 0) return GUMAP_OK;
+    hipError_t e;
+    GM_PROF("resistance_setup", (double)g->nnz * (4.0 + 4.0) * q + (double)g->n * q * 8.0 * 5.0,
+            launch_resistance_setup(a, q, seed, tol, s));
+    if (e != hipSuccess) return hip_status(e, "resistance setup");
+    int its = 0;
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    while (its < max_iters) {
+        const int batch = std::min(8, max_iters - its);
+        for (int b = 0; b < batch; ++b) {
+            // per iteration: the Laplacian product (rows and neighbour rows of
+            // q values), two passes of dot products, the updates
+            GM_PROF("cg_iteration", (double)(c.n + 1) * 4.0 + (double)g->nnz * (4.0 + 8.0 * q) +
+                                        (double)c.n * q * 8.0 * 12.0,
+                    launch_cg_iteration(a, q, tol, max_iters, s));
+            if (e != hipSuccess) return hip_status(e, "cg iteration");
+        }
+        its += batch;
+        e = hipMemcpyAsync(h, a.n_active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "cg state");
+        if (*(int *)h == 0) break;
+    }
+    GM_PROF("resistance_out", (double)a.m * (8.0 + 16.0 * q + 8.0), launch_resistance_out(a, q, R, s));
+    if (e != hipSuccess) return hip_status(e, "resistances");
+    std::vector<double> hst((size_t)q * 8);   // per column: iterations at [3]
+    e = hipMemcpyAsync(hst.data(), a.st, hst.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_status(e, "cg state");
+    if ((st = finish(s, "gumap_effective_resistance"))) return st;
+    int most = 0;
+    for (int k = 0; k < q; ++k) most = std::max(most, (int)hst[(size_t)k * 8 + 3]);
+    if (iters_out) *iters_out = most;
+    return GUMAP_OK;
+}
+
+int sparsify_select(const gumap_graph *g, const double *R, int64_t target, int32_t *out_row_ptr, int32_t *out_col,
+                    int32_t *out_nnz, hipStream_t s)
+{
+    int st;
+    if ((st = check_graph_args(g))) return st;
+    if (!out_nnz) return set_error(GUMAP_EINVAL, "out_nnz is NULL");
+    *out_nnz = 0;
+    if (g->n == 0) return GUMAP_OK;
+    if (!out_row_ptr || (g->nnz > 0 && (!R || !out_col))) return set_error(GUMAP_EINVAL, "NULL array");
+    CanonCsr c;
+    SparsifyArgs a;
+    void *scan_tmp = nullptr;
+    if ((st = sparsify_prepare(g, 0, s, &c, &a, &scan_tmp))) return st;
+    const int32_t n = c.n;
+    if (target <= 0) target = n > 1 ? (int64_t)ceil((double)n * log((double)n)) : 0;
+    if (target > a.m) target = a.m;
+    hipError_t e = launch_forest_init(a, s);
+    if (e != hipSuccess) return hip_status(e, "forest");
+    int64_t forest = 0;
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    for (int round = 0; round < 64 && a.m > 0; ++round) {
+        e = hipMemsetAsync(a.n_active, 0, sizeof(int), s);
+        if (e == hipSuccess) {
+            GM_PROF("forest_round", (double)a.m * (8.0 + 8.0 + 16.0) * 2.0 + (double)n * 40.0,
+                    launch_forest_round(a, R, a.n_active, s));
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h, a.n_active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e, "forest round");
+        const int added = *(int *)h;
+        forest += added;
+        if (added == 0) break;
+    }
+    const int64_t need = target - forest;
+    if (need > 0) {
+        size_t tmp = 0;
+        void *rank = nullptr;
+        if ((st = scratch_get(kSlotSparsifyRank, rank_scratch_bytes(a.m, &tmp), &rank))) return st;
+        GM_PROF("top_edges", (double)a.m * (8.0 + 12.0) * 8.0, launch_take_top(a, R, need, rank, s));
+        if (e != hipSuccess) return hip_status(e, "top edges");
+    }
+    e = launch_sparsified_csr(a, out_row_ptr, out_col, scan_tmp, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, out_row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_status(e, "sparsified csr");
+    if ((st = finish(s, "gumap_sparsify_select"))) return st;
+    *out_nnz = *(int32_t *)h;
+    return GUMAP_OK;
+}
+
 }  // namespace gm
 
 // ================================================================ C-ABI ===
@@ -1343,6 +1520,23 @@ int gumap_spectral_layout(int32_t n, const int32_t *row_ptr, const int32_t *col,
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
     return gm::settle(gm::spectral_layout(n, row_ptr, col, val, params, xy, eigenvalues, steps, stream), stream);
+}
+
+int gumap_effective_resistance(const gumap_graph *g, int32_t q, uint64_t seed, double tol, int32_t max_iters,
+                               double *resistance, int64_t *edges, int32_t *iterations, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::effective_resistance(g, q, seed, tol, max_iters, resistance, edges, iterations, stream),
+                      stream);
+}
+
+int gumap_sparsify_select(const gumap_graph *g, const double *resistance, int64_t target, int32_t *out_row_ptr,
+                          int32_t *out_col_idx, int32_t *out_nnz, hipStream_t stream)
+{
+    std::lock_guard<std::mutex> lock(gm::api_mutex());
+    gm::clear_error();
+    return gm::settle(gm::sparsify_select(g, resistance, target, out_row_ptr, out_col_idx, out_nnz, stream), stream);
 }
 
 int gumap_membership(int32_t rows, int32_t k, const uint8_t *nbr_hops, float *weights, float *rho,

@@ -292,6 +292,47 @@ hipError_t launch_spectral_finish(const SpectralArgs &a, int *first, float *xy, 
 // Host: eigen-decomposition of a symmetric tridiagonal matrix (see spectral.hip).
 bool tridiag_eigen(int m, double *a, double *b, double *Z, double *zlast);
 
+// ----------------------------------------------- spectral sparsification ---
+struct SparsifyArgs {
+    int32_t n;
+    int64_t m;                // undirected edges (read back after launch_edge_ids)
+    const int32_t *row_ptr;   // canonical symmetric CSR
+    const int32_t *col;
+    int32_t *upper;           // n + 1: edges per row (reused for output counts)
+    int32_t *eoff;            // n + 1: first edge of each row
+    int32_t *eid;             // nnz: edge of each entry (-1: self-loop or unmatched)
+    int32_t *eu, *ev;         // m: the edges (u < v) in CSR order
+    double *B, *X, *Rv, *Z, *P, *AP;   // n x q each, row-major
+    double *part;             // sparsify_tiles(n) x q x 3
+    double *sums;             // q x 3
+    double *st;               // q x 8: CG scalars per column
+    int *active;              // q: 1 running, 2 stopping now, 0 stopped
+    int *n_active;
+    int32_t *comp, *parent;   // n
+    int32_t *bestE;           // n
+    unsigned long long *bestR;  // n
+    uint8_t *keep;            // m
+};
+int sparsify_tiles(int32_t n);
+// upper, eoff (exclusive scan, scan_tmp: exclusive_scan_scratch_bytes(n)), eid, eu, ev.
+hipError_t launch_edge_ids(const SparsifyArgs &a, void *scan_tmp, hipStream_t s);
+// Right-hand sides B^T s_k (k < q, signs from SplitMix64(seed, k m + e + 1)),
+// CG start (x = 0) and the per-column state; active columns get 1.
+hipError_t launch_resistance_setup(const SparsifyArgs &a, int32_t q, uint64_t seed, double tol, hipStream_t s);
+// One preconditioned CG iteration of every active column; *n_active = columns still running.
+hipError_t launch_cg_iteration(const SparsifyArgs &a, int32_t q, double tol, int max_iters, hipStream_t s);
+hipError_t launch_resistance_out(const SparsifyArgs &a, int32_t q, double *R, hipStream_t s);
+// Maximum spanning forest by (R descending, edge ascending): init, then
+// rounds until a round adds no edge (*added: edges of the round, zero it first).
+hipError_t launch_forest_init(const SparsifyArgs &a, hipStream_t s);
+hipError_t launch_forest_round(const SparsifyArgs &a, const double *R, int *added, hipStream_t s);
+// The `need` best edges outside the forest join it (scratch: rank_scratch_bytes(m, &tmp)).
+size_t rank_scratch_bytes(int64_t m, size_t *sort_tmp);
+hipError_t launch_take_top(const SparsifyArgs &a, const double *R, int64_t need, void *scratch, hipStream_t s);
+// CSR of the kept edges (both directions, columns in the input order).
+hipError_t launch_sparsified_csr(const SparsifyArgs &a, int32_t *out_rp, int32_t *out_col, void *scan_tmp,
+                                 hipStream_t s);
+
 // ----------------------------------------------------------- membership ---
 hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float *weights,
                              float *rho, float *sigma, hipStream_t s);

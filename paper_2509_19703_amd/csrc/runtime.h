@@ -53,6 +53,8 @@ enum ScratchSlot {
     kSlotLayoutMoves,
     kSlotSpectral,
     kSlotSpectralVec,
+    kSlotSparsify,
+    kSlotSparsifyRank,
     kScratchSlots
 };
 

@@ -102,7 +102,28 @@ def test_spectral_layout_rejects_bad_arguments(gumap):
     assert "NULL" in gumap.last_error()
 
 
+def test_sparsify_entry_points_reject_bad_arguments(gumap):
+    lib = gumap.lib
+    g = gumap.gumap_graph(4, 6, None, None, 0)
+    m = ctypes.c_int64(5)
+    its = ctypes.c_int32(0)
+    nnz = ctypes.c_int32(3)
+    assert lib.gumap_effective_resistance(None, 8, 0, 1e-8, 10, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_effective_resistance(ctypes.byref(g), 0, 0, 1e-8, 10, None, ctypes.byref(m), None,
+                                          None) == gumap.EINVAL
+    assert lib.gumap_effective_resistance(ctypes.byref(g), 2000, 0, 1e-8, 10, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_effective_resistance(ctypes.byref(g), 8, 0, 0.0, 10, None, None, None, None) == gumap.EINVAL
+    empty = gumap.gumap_graph(0, 0, None, None, 0)
+    assert lib.gumap_effective_resistance(ctypes.byref(empty), 8, 0, 1e-8, 10, None, ctypes.byref(m),
+                                          ctypes.byref(its), None) == gumap.OK
+    assert m.value == 0
+    assert lib.gumap_sparsify_select(ctypes.byref(g), None, 0, None, None, None, None) == gumap.EINVAL
+    assert lib.gumap_sparsify_select(ctypes.byref(empty), None, 0, None, None, ctypes.byref(nnz), None) == gumap.OK
+    assert nnz.value == 0
+
+
 def test_python_names_mirror_c_entry_points(gumap):
     for name in ("gumap_knn_build", "gumap_knn_partial", "gumap_membership", "gumap_knn_partial_batch",
-                 "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample", "gumap_spectral_layout"):
+                 "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample", "gumap_spectral_layout",
+                 "gumap_effective_resistance", "gumap_sparsify_select"):
         assert callable(getattr(gumap, name))
