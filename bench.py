@@ -32,7 +32,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress", "neighborhood",
-                                                             "layout"])
+                                                             "layout", "sparsify"])
     p.add_argument("--layout-iters", type=int, default=200)
     p.add_argument("--batch-graphs", type=int, default=2048)
     p.add_argument("--serve-jobs", type=int, default=1024)
@@ -83,6 +83,8 @@ def main():
         return bench_neighborhood(args)
     if args.workload == "layout":
         return bench_layout(args)
+    if args.workload == "sparsify":
+        return bench_sparsify(args)
 
     if args.calibrate_copy:
         n_bytes = 1 << 30
@@ -526,6 +528,91 @@ def bench_layout(args):
                                              "GradSample iterations (one thread), scaled; the spectral drawing is "
                                              "left out (the oracle's dense eigendecomposition does not scale to "
                                              "n = 100,000); run estimate %.1f s" % (threads, few, t, est)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_sparsify(args):
+    """SS-GUMAP's front end on the dense ER graph G(16,384, 1/16) (the case
+    the paper sparsifies for, Sec. 3.2): effective resistances (32 random
+    projections, CG to 1e-8), the sparsified graph of ceil(n ln n) edges,
+    and GUMAP's all-source BFS kNN (hop matrix, k = 15) and membership on it,
+    against the same kNN on the whole graph."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
+    k = args.k
+    g = G.config_er()
+    n, m = g.n, g.m
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    gg = gm.make_graph(rp, ci, flags=gm.CSR_SORTED)
+    stream = torch.cuda.current_stream()
+    R = torch.empty(g.nnz // 2, dtype=torch.float64, device="cuda")
+    srp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    scol = torch.empty(g.nnz, dtype=torch.int32, device="cuda")
+    ids = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    hops = torch.empty((n, k), dtype=torch.uint8, device="cuda")
+    hm = torch.empty((n, n), dtype=torch.uint8, device="cuda")
+    w = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    res = {}
+
+    def sparsify():
+        res["m"], res["its"] = gm.gumap_effective_resistance(gg, 32, G.BASE_SEED + 500, 1e-8, 1000, R, stream)
+        res["snnz"] = gm.gumap_sparsify_select(gg, R, 0, srp, scol, stream)
+
+    def knn(graph):
+        gm.gumap_knn_build(graph, k, None, 0, ids, hops, hm, stream)
+        gm.gumap_membership(n, k, hops, w, None, None, stream)
+
+    def step():
+        sparsify()
+        knn(gm.gumap_graph(n, res["snnz"], gm._ptr(srp), gm._ptr(scol), gm.CSR_SORTED))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    dt, prof = _profiled(gm, step, steps)
+    roof, kms = _roofline(prof, steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        knn(gg)
+    torch.cuda.synchronize()
+    t_full = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sparsify()
+    torch.cuda.synchronize()
+    t_sp = (time.perf_counter() - t0) / steps
+    out = {"metric": METRIC, "value": m / t_sp / 1e9, "unit": "G input edges/s (sparsifier)", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 (resistances), u8 (hops)", "data": "synthetic",
+           "config": {"workload": "sparsify: ER G(%d, 1/16), m=%d; effective resistances (32 projections, CG to "
+                                  "1e-8) + spectral sparsification to ceil(n ln n) edges + all-source BFS kNN "
+                                  "k=%d with hop matrix + membership on the sparsified graph" % (n, m, k),
+                      "n": n, "m": m, "k": k},
+           "sparsified_edges": res["snnz"] // 2, "cg_iterations": res["its"], "sparsify_ms": t_sp * 1e3,
+           "ss_gumap_ms": dt * 1e3, "gumap_full_graph_ms": t_full * 1e3,
+           "roofline": roof, "kernels_ms_per_step": kms}
+    if not args.no_parity:
+        # Foster's theorem for the estimate, and the sparsified graph connected
+        import scipy.sparse as sp
+        from scipy.sparse.csgraph import connected_components
+        Rn = R[:res["m"]].cpu().numpy()
+        A = sp.csr_matrix((np.ones(res["snnz"]), scol[:res["snnz"]].cpu().numpy(), srp.cpu().numpy()), shape=(n, n))
+        out["resistance_sum_over_n_minus_1"] = float(Rn.sum() / (n - 1))
+        out["sparsified_connected"] = bool(connected_components(A)[0] == 1)
+    if not args.no_cpu_baseline:
+        import oracle as O
+        q = 1
+        t0 = time.perf_counter()
+        O.effective_resistance(n, g.row_ptr, g.col_idx, q=q, seed=G.BASE_SEED + 500, tol=1e-8, max_iters=1000)
+        t1 = (time.perf_counter() - t0) * 32 / q
+        out["cpu_baseline"] = {"value": m / t1 / 1e9, "unit": "G input edges/s (sparsifier)", "cores": 1,
+                               "kind": "oracle", "sample": "oracle resistances with 1 of the 32 projections "
+                               "(numpy, one thread), scaled to 32; selection not included"}
     print(json.dumps(out), flush=True)
 
 

@@ -1272,7 +1272,7 @@ int sparsify_args(const CanonCsr &c, int32_t nnz, int32_t q, SparsifyArgs *a, vo
     size_t bytes = 2 * al((size_t)(n + 1) * 4) + al((size_t)nnz * 4) + 2 * al((size_t)m_max * 4) +
                    (q > 0 ? 6 * al(nq * 8) + al((size_t)tiles * q * 3 * 8) + al((size_t)q * 3 * 8) +
                                 al((size_t)q * 8 * 8) + al((size_t)q * 4) : 0) +
-                   al(256) + 3 * al((size_t)n * 4) + al((size_t)n * 8) + al((size_t)m_max) +
+                   al(256) + 4 * al((size_t)n * 4) + 2 * al((size_t)n * 8) + al((size_t)m_max) +
                    al(exclusive_scan_scratch_bytes(n > 0 ? n : 1));
     char *p = nullptr;
     if ((st = scratch_get(kSlotSparsify, bytes, (void **)&p))) return st;
@@ -1301,6 +1301,8 @@ int sparsify_args(const CanonCsr &c, int32_t nnz, int32_t q, SparsifyArgs *a, vo
     a->parent = (int32_t *)p;           p += al((size_t)n * 4);
     a->bestE = (int32_t *)p;            p += al((size_t)n * 4);
     a->bestR = (unsigned long long *)p; p += al((size_t)n * 8);
+    a->vkey = (unsigned long long *)p;  p += al((size_t)n * 8);
+    a->ve = (int32_t *)p;               p += al((size_t)n * 4);
     a->keep = (uint8_t *)p;             p += al((size_t)m_max);
     *scan_tmp = p;
     return GUMAP_OK;
@@ -1319,7 +1321,9 @@ int sparsify_prepare(const gumap_graph *g, int32_t q, hipStream_t s, CanonCsr *c
     if (e != hipSuccess) return hip_status(e, "sparsify setup");
     nnz = *(int32_t *)h;
     if ((st = sparsify_args(*c, nnz, q, a, scan_tmp))) return st;
-    e = launch_edge_ids(*a, *scan_tmp, s);
+    // row pointers and columns, the binary searches of the lower entries, the ids and edges written
+    GM_PROF("edge_ids", (double)(c->n + 1) * 12.0 + (double)nnz * 4.0 * 12.0 + (double)nnz * 8.0,
+            launch_edge_ids(*a, *scan_tmp, s));
     if (e == hipSuccess) e = hipMemcpyAsync(h, a->eoff + c->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_status(e, "edge ids");
@@ -1408,7 +1412,8 @@ int sparsify_select(const gumap_graph *g, const double *R, int64_t target, int32
     for (int round = 0; round < 64 && a.m > 0; ++round) {
         e = hipMemsetAsync(a.n_active, 0, sizeof(int), s);
         if (e == hipSuccess) {
-            GM_PROF("forest_round", (double)a.m * (8.0 + 8.0 + 16.0) * 2.0 + (double)n * 40.0,
+            // every entry's edge id, neighbour label and resistance; per vertex its label, best and state
+            GM_PROF("forest_round", (double)(2 * a.m) * (4.0 + 4.0 + 4.0 + 8.0) + (double)n * 60.0,
                     launch_forest_round(a, R, a.n_active, s));
         }
         if (e == hipSuccess) e = hipMemcpyAsync(h, a.n_active, sizeof(int), hipMemcpyDeviceToHost, s);

@@ -311,6 +311,8 @@ struct SparsifyArgs {
     int32_t *comp, *parent;   // n
     int32_t *bestE;           // n
     unsigned long long *bestR;  // n
+    unsigned long long *vkey;   // n: each vertex's best edge key in a forest round
+    int32_t *ve;              // n: and that edge
     uint8_t *keep;            // m
 };
 int sparsify_tiles(int32_t n);

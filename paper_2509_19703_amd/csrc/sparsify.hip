@@ -15,8 +15,9 @@
 //
 // The spanning forest is Boruvka's: each component takes its best edge in
 // the order (resistance descending, edge index ascending), a total order,
-// so the forest is unique; components are hooked along the chosen edges and
-// the labels compressed, until no component gains an edge.  The remaining
+// so the forest is unique (found per vertex by a wave over its row, then one
+// atomic per vertex); components are hooked along the chosen edges and the
+// labels compressed, until no component gains an edge.  The remaining
 // edges are ranked by a stable radix sort on the resistance bits.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -65,15 +66,21 @@ __global__ void ss_upper_count_kernel(int32_t n, const int32_t *__restrict__ rp,
 }
 
 // eid[j] for every entry j = (u, w): the index of edge (min, max) in CSR
-// order of the upper entries; eu / ev list the edges.
-__global__ void ss_edge_ids_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                   const int32_t *__restrict__ eoff, int32_t *__restrict__ eid,
-                                   int32_t *__restrict__ eu, int32_t *__restrict__ ev)
+// order of the upper entries; eu / ev list the edges.  A wave per row, the
+// lanes striding over its entries (each lower entry searches row w for u).
+__global__ void __launch_bounds__(kSsBlock)
+ss_edge_ids_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                   const int32_t *__restrict__ eoff, int32_t *__restrict__ eid, int32_t *__restrict__ eu,
+                   int32_t *__restrict__ ev)
 {
-    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
-        const int32_t b = rp[u], e1 = rp[u + 1];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t uu = wave; uu < n; uu += waves) {
+        const int32_t u = (int32_t)uu;
+        const int32_t e1 = rp[u + 1];
         const int32_t first_up = e1 - (eoff[u + 1] - eoff[u]);
-        for (int32_t j = b; j < e1; ++j) {
+        for (int32_t j = rp[u] + lane; j < e1; j += 64) {
             const int32_t w = col[j];
             if (w == u) {   // a self-loop is not an edge
                 eid[j] = -1;
@@ -305,30 +312,56 @@ __global__ void ss_best_clear_kernel(int32_t n, unsigned long long *__restrict__
 // Non-negative doubles order as their bit patterns; +1 keeps 0 above "none".
 __device__ __forceinline__ unsigned long long r_key(double r) { return (unsigned long long)__double_as_longlong(r) + 1ull; }
 
+// Each vertex's best edge to another component, a wave per vertex (the
+// order: larger key first, then the smaller edge index); then one atomic
+// per vertex on its component instead of one per edge end, since late
+// rounds have few components and millions of edges between them.
 __global__ void __launch_bounds__(kSsBlock)
-ss_best_r_kernel(int64_t m, const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
-                 const int32_t *__restrict__ comp, const double *__restrict__ R, unsigned long long *__restrict__ bestR)
+ss_vertex_best_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                      const int32_t *__restrict__ eid, const int32_t *__restrict__ comp, const double *__restrict__ R,
+                      unsigned long long *__restrict__ vkey, int32_t *__restrict__ ve,
+                      unsigned long long *__restrict__ bestR)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = comp[eu[e]], b = comp[ev[e]];
-        if (a == b) continue;
-        const unsigned long long k = r_key(R[e]);
-        atomicMax(&bestR[a], k);
-        atomicMax(&bestR[b], k);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < n; v += waves) {
+        const int32_t c = comp[v];
+        unsigned long long key = 0ull;
+        int32_t e = INT32_MAX;
+        for (int32_t j = rp[v] + lane; j < rp[v + 1]; j += 64) {
+            const int32_t x = eid[j];
+            if (x < 0 || comp[col[j]] == c) continue;
+            const unsigned long long k = r_key(R[x]);
+            if (k > key || (k == key && x < e)) {
+                key = k;
+                e = x;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long k2 = __shfl_xor(key, o, 64);
+            const int32_t e2 = __shfl_xor(e, o, 64);
+            if (k2 > key || (k2 == key && e2 < e)) {
+                key = k2;
+                e = e2;
+            }
+        }
+        if (lane == 0) {
+            vkey[v] = key;
+            ve[v] = e;
+            if (key) atomicMax(&bestR[c], key);
+        }
     }
 }
 
 __global__ void __launch_bounds__(kSsBlock)
-ss_best_e_kernel(int64_t m, const int32_t *__restrict__ eu, const int32_t *__restrict__ ev,
-                 const int32_t *__restrict__ comp, const double *__restrict__ R,
-                 const unsigned long long *__restrict__ bestR, int32_t *__restrict__ bestE)
+ss_vertex_best_e_kernel(int32_t n, const int32_t *__restrict__ comp, const unsigned long long *__restrict__ vkey,
+                        const int32_t *__restrict__ ve, const unsigned long long *__restrict__ bestR,
+                        int32_t *__restrict__ bestE)
 {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = comp[eu[e]], b = comp[ev[e]];
-        if (a == b) continue;
-        const unsigned long long k = r_key(R[e]);
-        if (k == bestR[a]) atomicMin(&bestE[a], (int32_t)e);
-        if (k == bestR[b]) atomicMin(&bestE[b], (int32_t)e);
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int32_t c = comp[v];
+        if (vkey[v] && vkey[v] == bestR[c]) atomicMin(&bestE[c], ve[v]);
     }
 }
 
@@ -437,8 +470,8 @@ hipError_t launch_edge_ids(const SparsifyArgs &a, void *scan_tmp, hipStream_t s)
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_exclusive_scan(a.upper, a.eoff, a.n, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ss_edge_ids_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.row_ptr, a.col, a.eoff,
-                       a.eid, a.eu, a.ev);
+    hipLaunchKernelGGL(ss_edge_ids_kernel, dim3(ss_grid((int64_t)a.n * 64)), dim3(kSsBlock), 0, s, a.n, a.row_ptr,
+                       a.col, a.eoff, a.eid, a.eu, a.ev);
     return hipGetLastError();
 }
 
@@ -500,9 +533,9 @@ hipError_t launch_forest_init(const SparsifyArgs &a, hipStream_t s)
 hipError_t launch_forest_round(const SparsifyArgs &a, const double *R, int *added, hipStream_t s)
 {
     hipLaunchKernelGGL(ss_best_clear_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.bestR, a.bestE);
-    hipLaunchKernelGGL(ss_best_r_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, a.eu, a.ev, a.comp, R,
-                       a.bestR);
-    hipLaunchKernelGGL(ss_best_e_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, a.eu, a.ev, a.comp, R,
+    hipLaunchKernelGGL(ss_vertex_best_kernel, dim3(ss_grid((int64_t)a.n * 64)), dim3(kSsBlock), 0, s, a.n,
+                       a.row_ptr, a.col, a.eid, a.comp, R, a.vkey, a.ve, a.bestR);
+    hipLaunchKernelGGL(ss_vertex_best_e_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.comp, a.vkey, a.ve,
                        a.bestR, a.bestE);
     hipLaunchKernelGGL(ss_hook_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.eu, a.ev, a.comp, a.bestE,
                        a.parent, a.keep, added);
