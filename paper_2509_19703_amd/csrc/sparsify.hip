@@ -169,15 +169,25 @@ ss_dots_kernel(int32_t n, int32_t q, const double *__restrict__ A, const double 
     part[item * 3 + 2] = cc;
 }
 
-// Column sums of the partials (fixed order over the tiles) into sums[k * 3 + f].
-__global__ void ss_reduce_kernel(int32_t q, int tiles, const double *__restrict__ part, double *__restrict__ sums)
+// Column sums of the partials into sums[k * 3 + f]: a block per column, the
+// threads striding over the tiles, then a tree (a fixed order throughout).
+__global__ void __launch_bounds__(kSsBlock)
+ss_reduce_kernel(int32_t q, int tiles, const double *__restrict__ part, double *__restrict__ sums)
 {
-    for (int k = threadIdx.x; k < q; k += blockDim.x)
-        for (int f = 0; f < 3; ++f) {
-            double s = 0.0;
-            for (int t = 0; t < tiles; ++t) s += part[((int64_t)t * q + k) * 3 + f];
-            sums[k * 3 + f] = s;
-        }
+    __shared__ double sh[3][kSsBlock];
+    const int k = blockIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x)
+        for (int f = 0; f < 3; ++f) acc[f] += part[((int64_t)t * q + k) * 3 + f];
+    for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int f = 0; f < 3; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int f = 0; f < 3; ++f) sums[k * 3 + f] = sh[f][0];
 }
 
 // CG state per column k: st[k * 8 + .] = {rz, |b|, alpha, iterations}.
@@ -438,24 +448,41 @@ ss_take_kernel(int64_t m, const int32_t *__restrict__ order, const int32_t *__re
 }
 
 // ----------------------------------------------------------- output CSR --
-__global__ void ss_out_count_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ eid,
-                                    const uint8_t *__restrict__ keep, int32_t *__restrict__ cnt)
+// A wave per row: kept entries counted, then written in row order (the
+// lanes' ballot of kept entries gives each its place).
+__global__ void __launch_bounds__(kSsBlock)
+ss_out_count_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ eid,
+                    const uint8_t *__restrict__ keep, int32_t *__restrict__ cnt)
 {
-    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = wave; u < n; u += waves) {
         int32_t c = 0;
-        for (int32_t j = rp[u]; j < rp[u + 1]; ++j) c += eid[j] >= 0 ? keep[eid[j]] : 0;
-        cnt[u] = c;
+        for (int32_t j = rp[u] + lane; j < rp[u + 1]; j += 64) c += eid[j] >= 0 ? keep[eid[j]] : 0;
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0) cnt[u] = c;
     }
 }
 
-__global__ void ss_out_fill_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                   const int32_t *__restrict__ eid, const uint8_t *__restrict__ keep,
-                                   const int32_t *__restrict__ out_rp, int32_t *__restrict__ out_col)
+__global__ void __launch_bounds__(kSsBlock)
+ss_out_fill_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                   const int32_t *__restrict__ eid, const uint8_t *__restrict__ keep,
+                   const int32_t *__restrict__ out_rp, int32_t *__restrict__ out_col)
 {
-    for (int32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t u = wave; u < n; u += waves) {
         int32_t o = out_rp[u];
-        for (int32_t j = rp[u]; j < rp[u + 1]; ++j)
-            if (eid[j] >= 0 && keep[eid[j]]) out_col[o++] = col[j];
+        const int32_t e1 = rp[u + 1];
+        for (int32_t j0 = rp[u]; j0 < e1; j0 += 64) {
+            const int32_t j = j0 + lane;
+            const bool k = j < e1 && eid[j] >= 0 && keep[eid[j]];
+            const uint64_t mask = __ballot(k);
+            if (k) out_col[o + __popcll(mask & ((1ull << lane) - 1ull))] = col[j];
+            o += __popcll(mask);
+        }
     }
 }
 
@@ -486,7 +513,7 @@ hipError_t launch_resistance_setup(const SparsifyArgs &a, int32_t q, uint64_t se
     // r . z and b . b (r = b at the start)
     hipLaunchKernelGGL(ss_dots_kernel, dim3(ss_grid((int64_t)tiles * q)), dim3(kSsBlock), 0, s, a.n, q,
                        (const double *)nullptr, (const double *)nullptr, a.Rv, a.Z, a.part, tiles);
-    hipLaunchKernelGGL(ss_reduce_kernel, dim3(1), dim3(64), 0, s, q, tiles, a.part, a.sums);
+    hipLaunchKernelGGL(ss_reduce_kernel, dim3(q), dim3(kSsBlock), 0, s, q, tiles, a.part, a.sums);
     hipLaunchKernelGGL(ss_start_kernel, dim3(1), dim3(64), 0, s, q, a.sums, a.st, a.active, tol);
     return hipGetLastError();
 }
@@ -499,13 +526,13 @@ hipError_t launch_cg_iteration(const SparsifyArgs &a, int32_t q, double tol, int
                        a.active);
     hipLaunchKernelGGL(ss_dots_kernel, dim3(ss_grid((int64_t)tiles * q)), dim3(kSsBlock), 0, s, a.n, q, a.P, a.AP,
                        (const double *)nullptr, (const double *)nullptr, a.part, tiles);
-    hipLaunchKernelGGL(ss_reduce_kernel, dim3(1), dim3(64), 0, s, q, tiles, a.part, a.sums);
+    hipLaunchKernelGGL(ss_reduce_kernel, dim3(q), dim3(kSsBlock), 0, s, q, tiles, a.part, a.sums);
     hipLaunchKernelGGL(ss_alpha_kernel, dim3(1), dim3(64), 0, s, q, a.sums, a.st, a.active);
     hipLaunchKernelGGL(ss_update_kernel, dim3(ss_grid(nq)), dim3(kSsBlock), 0, s, a.n, q, a.row_ptr, a.st, a.active,
                        a.X, a.Rv, a.Z, a.P, a.AP);
     hipLaunchKernelGGL(ss_dots_kernel, dim3(ss_grid((int64_t)tiles * q)), dim3(kSsBlock), 0, s, a.n, q,
                        (const double *)nullptr, (const double *)nullptr, a.Rv, a.Z, a.part, tiles);
-    hipLaunchKernelGGL(ss_reduce_kernel, dim3(1), dim3(64), 0, s, q, tiles, a.part, a.sums);
+    hipLaunchKernelGGL(ss_reduce_kernel, dim3(q), dim3(kSsBlock), 0, s, q, tiles, a.part, a.sums);
     hipLaunchKernelGGL(ss_beta_kernel, dim3(1), dim3(64), 0, s, q, a.sums, a.st, a.active, tol, max_iters,
                        a.n_active);
     hipLaunchKernelGGL(ss_direction_kernel, dim3(ss_grid(nq)), dim3(kSsBlock), 0, s, a.n, q, a.st, a.active, a.Z,
@@ -586,13 +613,13 @@ hipError_t launch_take_top(const SparsifyArgs &a, const double *R, int64_t need,
 hipError_t launch_sparsified_csr(const SparsifyArgs &a, int32_t *out_rp, int32_t *out_col, void *scan_tmp,
                                  hipStream_t s)
 {
-    hipLaunchKernelGGL(ss_out_count_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.row_ptr, a.eid, a.keep,
-                       a.upper);
+    hipLaunchKernelGGL(ss_out_count_kernel, dim3(ss_grid((int64_t)a.n * 64)), dim3(kSsBlock), 0, s, a.n, a.row_ptr,
+                       a.eid, a.keep, a.upper);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_exclusive_scan(a.upper, out_rp, a.n, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ss_out_fill_kernel, dim3(ss_grid(a.n)), dim3(kSsBlock), 0, s, a.n, a.row_ptr, a.col, a.eid,
-                       a.keep, (const int32_t *)out_rp, out_col);
+    hipLaunchKernelGGL(ss_out_fill_kernel, dim3(ss_grid((int64_t)a.n * 64)), dim3(kSsBlock), 0, s, a.n, a.row_ptr,
+                       a.col, a.eid, a.keep, (const int32_t *)out_rp, out_col);
     return hipGetLastError();
 }
 
