@@ -1,6 +1,10 @@
 // C-ABI of libgumap: argument checks, scratch management and the launch
 // sequences of the plain calls (gumap_knn_build, gumap_knn_partial,
-// gumap_membership) and of the batched call and its captured plan.
+// gumap_membership), of the batched call and its captured plan, of the
+// drawing metrics (gumap_stress, gumap_neighborhood), of the layout step
+// (gumap_fuzzy_union, gumap_edge_shuffle, gumap_grad_sample,
+// gumap_spectral_layout) and of the sparsifier (gumap_effective_resistance,
+// gumap_sparsify_select).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1111,7 +1115,6 @@ namespace {
 int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol, uint64_t seed, double *svec,
                 int k, double *lambda, int *steps, hipStream_t s)
 {
-    int st;
     hipError_t e = launch_lanczos_start(a, c0, seed, s);
     if (e != hipSuccess) return hip_status(e, "lanczos start");
     std::vector<double> ha((size_t)jmax + 2), hb((size_t)jmax + 2), ta, tb, zl;
@@ -1169,7 +1172,6 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
     if (e != hipSuccess) return hip_status(e, "ritz vector");
     *lambda = 1.0 - ta[top];
     *steps += m;
-    (void)st;
     return GUMAP_OK;
 }
 
