@@ -237,3 +237,28 @@ def test_layout_pipeline_ba100k_sampled(gumap):
     gumap.grad_sample(got, head, tail, ws, it_begin=0, it_end=3, **kw)
     ref = O.grad_sample(g.n, oh_, ot_, ow_, xy, it_begin=0, it_end=3, **kw)
     _compare_xy(got.cpu().numpy(), ref, 3, "ba100k 3 windows")
+
+
+def test_layout_degenerate_inputs(gumap):
+    """One row (k = 1), a kNN with no entries, and edge arrays holding
+    self-loops (attraction 0, only negative samples move the head)."""
+    import torch
+    ids = np.array([[1], [0]], np.int32)
+    w = np.array([[0.5], [0.25]], np.float32)
+    rp, col, val = gumap.fuzzy_union(_dev(ids), _dev(w))
+    orp, ocol, oval = O.fuzzy_union(ids, w)
+    assert np.array_equal(rp.cpu().numpy(), orp) and np.array_equal(col.cpu().numpy(), ocol)
+    assert np.array_equal(val.cpu().numpy(), oval)
+    head = np.array([0, 1, 2, 2], np.int32)
+    tail = np.array([0, 3, 2, 1], np.int32)
+    ws = np.array([1.0, 0.5, 1.0, 0.75], np.float32)
+    xy = np.random.default_rng(4).uniform(-3, 3, (4, 2)).astype(np.float32)
+    kw = dict(a=gumap.UMAP_A, b=gumap.UMAP_B, window=3, neg=4, t=6, seed=9)
+    ref = O.grad_sample(4, head, tail, ws, xy, **kw)
+    got = _dev(xy.copy())
+    gumap.grad_sample(got, _dev(head), _dev(tail), _dev(ws), **kw)
+    assert np.array_equal(got.cpu().numpy(), ref)
+    one = torch.zeros((1, 2), dtype=torch.float32, device="cuda")
+    gumap.grad_sample(one, _dev(np.zeros(0, np.int32)), _dev(np.zeros(0, np.int32)), _dev(np.zeros(0, np.float32)),
+                      window=1, t=3)
+    assert float(one.abs().sum()) == 0.0

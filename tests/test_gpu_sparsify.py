@@ -128,3 +128,19 @@ def test_sparsify_pipeline_dense_er(gumap):
     assert (A != A.T).nnz == 0
     srp2, scol2 = gumap.sparsify_select(rp, ci, R, flags=gumap.CSR_SORTED)
     assert np.array_equal(scol.cpu().numpy(), scol2.cpu().numpy())
+
+
+def test_sparsify_degenerate_inputs(gumap):
+    """No edges at all, and a graph whose only edges form a tree (every edge
+    kept, resistance exactly 1)."""
+    g = G.empty(7)
+    R, its = gumap.effective_resistance(_dev(g.row_ptr), _dev(np.zeros(1, np.int32)), flags=gumap.CSR_SORTED)
+    assert R.numel() == 0 and its == 0
+    rp, col = gumap.sparsify_select(_dev(g.row_ptr), _dev(np.zeros(1, np.int32)), _dev(np.zeros(1)),
+                                    flags=gumap.CSR_SORTED)
+    assert col.numel() == 0 and int(rp.abs().sum()) == 0
+    g = G.star(25)
+    R, _ = gumap.effective_resistance(_dev(g.row_ptr), _dev(g.col_idx), q=4, flags=gumap.CSR_SORTED)
+    assert np.allclose(R.cpu().numpy(), 1.0, atol=1e-8)
+    rp, col = gumap.sparsify_select(_dev(g.row_ptr), _dev(g.col_idx), R, target=3, flags=gumap.CSR_SORTED)
+    assert np.array_equal(rp.cpu().numpy(), g.row_ptr) and np.array_equal(col.cpu().numpy(), g.col_idx)
