@@ -5,11 +5,13 @@
 // With c(h) = number of vertices at hop h, the last hop taken is the smallest
 // h* with c(1) + ... + c(h*) >= k.  Every vertex with hop < h* is taken and
 // the first k - (c(1) + ... + c(h*-1)) vertices at hop h* in id order.  The
-// counts come either from the BFS transpose (hops 1..16) or from a histogram
-// pass of this kernel.  One streaming pass over the row in id order then
-// writes the taken entries straight to their (hop, id) position and stops as
-// soon as all of them are found.  Bytes are classified four at a time with
-// SWAR compares; only lanes holding a taken entry walk their bytes.
+// counts come either from the BFS transpose (hops 1..16, per chunk of the row)
+// or from a histogram pass of this kernel.  One streaming pass over the row in
+// id order then writes the taken entries straight to their (hop, id) position
+// and stops as soon as all of them are found.  With per-chunk counts the pass
+// visits only the chunks that hold a vertex with hop < h* or one of the
+// needed vertices at hop h*.  Bytes are classified four at a time with SWAR
+// compares; only lanes holding a taken entry walk their bytes.
 #include "device.h"
 #include "kernels.h"
 
@@ -20,6 +22,7 @@ namespace {
 constexpr int kCountLevels = 16;
 constexpr int kSelWaves = 4;
 constexpr int kMaxK = 254;
+constexpr int kMaxChunks = 512;   // chunk list capacity per wave of the counted kernel
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -96,10 +99,21 @@ __device__ __forceinline__ Classes classify(uint4 q, int hstar, bool swar)
     return c;
 }
 
+// Vertex range [b, e) of chunk c when the row's 64-vertex tiles are split
+// into `chunks` equal shares (the partition of the BFS transpose).
+__device__ __forceinline__ void chunk_range(int32_t c, int32_t chunks, int32_t n, int32_t &b, int32_t &e)
+{
+    const int64_t ntiles = (n + 63) / 64;
+    b = (int32_t)(64 * ((int64_t)c * ntiles / chunks));
+    e = (int32_t)min<int64_t>(n, 64 * (((int64_t)c + 1) * ntiles / chunks));
+}
+
 // Selection pass.  cnt[h] (h = 1..hmax) holds the per-hop counts; got/base
-// are per-wave LDS scratch of 256 ints each.
+// are per-wave LDS scratch of 256 ints each.  The pass scans the chunks
+// list[0..nlist) in that (ascending) order, or the whole row if list is null.
 __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsigned int *cnt, int hmax,
-                           int *got, int *base, int32_t *ids_out, uint8_t *hops_out)
+                           const int32_t *list, int nlist, int32_t chunks, int *got, int *base,
+                           int32_t *ids_out, uint8_t *hops_out)
 {
     const int l = lane();
     int c = 0, hstar = hmax + 1, need = 0;
@@ -124,12 +138,28 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
     wave_sync();
     const bool aligned = (((uintptr_t)row) & 15) == 0;
     const bool swar = hstar <= 128;
+    if (!list) nlist = 1;
     int found_lt = 0, found_eq = 0;
-    if (c_less > 0 || need > 0) {
-        uint4 q = load16(row, n, 16 * l, aligned);
-        for (int32_t vb = 0; vb < n; vb += 16 * GM_WAVE) {
+    if ((c_less > 0 || need > 0) && nlist > 0) {
+        // lanes at or past the end of the current chunk read all-255 bytes
+        auto load = [&](int32_t v, int32_t e) {
+            return v < e ? load16(row, n, v, aligned) : make_uint4(~0u, ~0u, ~0u, ~0u);
+        };
+        int li = 0;
+        int32_t vb = 0, ce = n;
+        if (list) chunk_range(list[0], chunks, n, vb, ce);
+        uint4 q = load(vb + 16 * l, ce);
+        for (;;) {
+            // next position: the following 16 * 64 bytes of this chunk, else the next listed chunk
+            int nli = li;
+            int32_t nvb = vb + 16 * GM_WAVE, nce = ce;
+            if (nvb >= ce) {
+                ++nli;
+                if (nli < nlist) chunk_range(list[nli], chunks, n, nvb, nce);
+            }
+            const bool more = nli < nlist;
+            const uint4 qn = more ? load(nvb + 16 * l, nce) : make_uint4(~0u, ~0u, ~0u, ~0u);   // in flight
             const int32_t v = vb + 16 * l;
-            const uint4 qn = load16(row, n, v + 16 * GM_WAVE, aligned);   // next chunk in flight
             const Classes cl = classify(q, hstar, swar);
             const int n_lt = __popc(cl.lt[0]) + __popc(cl.lt[1]) + __popc(cl.lt[2]) + __popc(cl.lt[3]);
             const int n_eq = __popc(cl.eq[0]) + __popc(cl.eq[1]) + __popc(cl.eq[2]) + __popc(cl.eq[3]);
@@ -179,7 +209,10 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
                 }
                 found_eq += __shfl(incl, GM_WAVE - 1, GM_WAVE);
             }
-            if (found_lt >= c_less && found_eq >= need) break;
+            if ((found_lt >= c_less && found_eq >= need) || !more) break;
+            li = nli;
+            vb = nvb;
+            ce = nce;
             q = qn;
         }
     }
@@ -200,6 +233,7 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
     __shared__ unsigned int cnt[kSelWaves][kCountLevels + 2];
     __shared__ int got[kSelWaves][kCountLevels + 2];
     __shared__ int base[kSelWaves][kCountLevels + 2];
+    __shared__ int32_t list[kSelWaves][kMaxChunks];
     const int wid = threadIdx.x / GM_WAVE, l = lane();
     for (int32_t r = blockIdx.x * kSelWaves + wid; r < rows; r += gridDim.x * kSelWaves) {
         // sum the per-block partial counts: lane = (chunk phase, level)
@@ -210,9 +244,49 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
         sum += __shfl_xor(sum, 32, GM_WAVE);
         if (l < kCountLevels) cnt[wid][l + 1] = sum;
         wave_sync();
+        // last level h* and the number of its vertices taken (as in select_row)
+        int c = 0, hstar = kCountLevels + 1, need = 0;
+        for (int hh = 1; hh <= kCountLevels; ++hh) {
+            const int ch = (int)cnt[wid][hh];
+            if (c + ch >= k) {
+                hstar = hh;
+                need = k - c;
+                break;
+            }
+            c += ch;
+        }
+        // chunks holding a vertex with hop < h*, or one of the first `need`
+        // vertices at hop h* (eq counts scanned in chunk order), in order
+        int nlist = 0, eq_carry = 0;
+        for (int32_t c0 = 0; c0 < chunks; c0 += GM_WAVE) {
+            const int32_t cc = c0 + l;
+            int lt_c = 0, eq_c = 0;
+            if (cc < chunks) {
+                const uint4 *p = (const uint4 *)(part + ((size_t)r * chunks + cc) * kCountLevels);
+#pragma unroll
+                for (int i = 0; i < kCountLevels / 4; ++i) {
+                    const uint4 x = p[i];
+                    const unsigned int xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int hh = 4 * i + j + 1;
+                        if (hh < hstar) lt_c += (int)xs[j];
+                        else if (hh == hstar) eq_c = (int)xs[j];
+                    }
+                }
+            }
+            const int incl = wave_incl_scan(eq_c);
+            const bool needed = cc < chunks && (lt_c > 0 || (eq_c > 0 && eq_carry + incl - eq_c < need));
+            const unsigned long long mk = __ballot(needed);
+            if (needed) list[wid][nlist + lanes_below(mk)] = cc;
+            nlist += __popcll(mk);
+            eq_carry += __shfl(incl, GM_WAVE - 1, GM_WAVE);
+        }
+        wave_sync();
         const uint8_t *row = hop_rows + row_of[r] * row_stride;
         const int64_t o = out_row[r] * (int64_t)k;
-        select_row(row, n, k, cnt[wid], kCountLevels, got[wid], base[wid], ids + o, hops + o);
+        select_row(row, n, k, cnt[wid], kCountLevels, list[wid], nlist, chunks, got[wid], base[wid], ids + o,
+                   hops + o);
         wave_sync();
     }
 }
@@ -251,7 +325,7 @@ knn_select_hist_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__rest
         }
         wave_sync();
         const int64_t o = out_row[r] * (int64_t)k;
-        select_row(row, n, k, cnt, k, got, base, ids + o, hops + o);
+        select_row(row, n, k, cnt, k, nullptr, 0, 1, got, base, ids + o, hops + o);
         wave_sync();
     }
 }
@@ -280,7 +354,7 @@ hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const u
 {
     (void)src_of;
     if (rows <= 0) return hipSuccess;
-    if (part && k <= kCountLevels) {
+    if (part && k <= kCountLevels && chunks >= 1 && chunks <= kMaxChunks) {
         int blocks = (rows + kSelWaves - 1) / kSelWaves;
         if (blocks > 65536) blocks = 65536;
         hipLaunchKernelGGL(knn_select_counted_kernel, dim3(blocks), dim3(kSelWaves * GM_WAVE), 0, s, n, k,
