@@ -505,43 +505,29 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
 // With STRESS the staged bytes are not stored: each row's stress terms
 // ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 5.1) are summed in
 // FP64 instead, one partial sum and pair count per (slot, block).
-template <int WORDS, int TILES, bool STRESS>
-__global__ void __launch_bounds__(WORDS * GM_WAVE)
-msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
-                         const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part,
-                         StressArgs sa)
+constexpr int kStressIts = 8;   // rows per thread in the store / stress phase of the staged transpose
+
+// Body of the staged transpose for at most PL bit-planes.  With PL = 4 (every
+// hop <= 15, the usual depth) the visited and plane words of the next tiles
+// are loaded before the current tiles' rows are stored, so that the loads
+// overlap the stores; the 8-plane form would need too many registers for that.
+template <int WORDS, int TILES, bool STRESS, int PL>
+__device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_used, uint8_t *__restrict__ hop_out,
+                                                 unsigned int *__restrict__ part, const StressArgs &sa,
+                                                 uint8_t *stage, const int64_t *row_base, const double *rinv,
+                                                 double *st_sum, unsigned int *st_cnt, const float2 *st_xy)
 {
     constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
-    const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
     constexpr int ROWS = WORDS * GM_WAVE;        // sources of the group = rows staged
     constexpr int SEG = 64 * TILES;              // bytes per row per step
     constexpr int UNIT = 8 * TILES;              // bytes per store: 8 or 16
     constexpr int PITCH = SEG + UNIT;            // padded against bank conflicts, UNIT-aligned
+    constexpr bool PREFETCH = PL <= 4;
     typedef typename std::conditional<TILES == 2, u32x4, uint64_t>::type unit_t;
-    __shared__ __align__(16) uint8_t stage[ROWS * PITCH];
-    __shared__ int64_t row_base[ROWS];
     const int w = threadIdx.x / GM_WAVE, l = lane();
     const int32_t g = blockIdx.y;
     const int32_t local_slot = g * ROWS + 64 * w + l;
     const bool slot_ok = local_slot < a.n_slots;
-    // store / stress rows of this thread: r = threadIdx.x / 8 + it * ROWS / 8
-    constexpr int ITS = 8;
-    double st_sum[ITS];
-    unsigned int st_cnt[ITS];
-    float2 st_xy[ITS];
-    __shared__ double rinv[STRESS ? 256 : 1];   // 1 / h for the stress terms
-    if (STRESS) {
-        for (int h = threadIdx.x; h < 256; h += blockDim.x) rinv[h] = h ? 1.0 / (double)h : 0.0;
-#pragma unroll
-        for (int it = 0; it < ITS; ++it) {
-            st_sum[it] = 0.0;
-            st_cnt[it] = 0;
-            const int32_t ls = g * ROWS + (threadIdx.x >> 3) + it * (ROWS >> 3);
-            st_xy[it] = ls < a.n_slots ? sa.xy[a.usrc[a.slot0 + ls]] : make_float2(0.0f, 0.0f);
-        }
-    } else {
-        row_base[threadIdx.x] = slot_ok ? slot_row[local_slot] * row_stride : -1;
-    }
     const int32_t ntiles = (a.n + 63) / 64;
     const size_t gbase = (size_t)g * a.n * WORDS + w;
     unsigned int cnt[kCountLevels];
@@ -550,20 +536,28 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
     // block x of a group takes tiles [x * ntiles / chunks, (x + 1) * ntiles / chunks)
     const int32_t t_begin = (int32_t)((int64_t)blockIdx.x * ntiles / gridDim.x);
     const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
-    for (int32_t tile = t_begin; tile < t_end; tile += TILES) {
+    uint64_t wv[TILES], wp[TILES][PL];   // visited and plane words of the tiles being (or next to be) transposed
+    auto load_tiles = [&](int32_t tile) {
 #pragma unroll
         for (int half = 0; half < TILES; ++half) {
             const int32_t v = (tile + half) * 64 + l;
             const bool in = v < a.n && tile + half < t_end;
             const size_t me = gbase + ((size_t)v << LW);
-            uint64_t vis = in ? a.visited[me] : 0ull;
+            wv[half] = in ? a.visited[me] : 0ull;
+#pragma unroll
+            for (int b = 0; b < PL; ++b)
+                wp[half][b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
+        }
+    };
+    if (PREFETCH && t_begin < t_end) load_tiles(t_begin);
+    for (int32_t tile = t_begin; tile < t_end; tile += TILES) {
+        if (!PREFETCH) load_tiles(tile);
+#pragma unroll
+        for (int half = 0; half < TILES; ++half) {
+            const uint64_t vis = transpose64(wv[half]);
             uint64_t pl[8];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) pl[b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
-            vis = transpose64(vis);
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b < planes_used) pl[b] = transpose64(pl[b]);
+            for (int b = 0; b < 8; ++b) pl[b] = (b < PL && b < planes_used) ? transpose64(wp[half][b < PL ? b : 0]) : 0ull;
             uint64_t high = 0;
 #pragma unroll
             for (int b = 5; b < 8; ++b) high |= pl[b];
@@ -580,12 +574,13 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
             for (int c = 0; c < 8; ++c) {
                 uint64_t by = spread8(~vis >> (8 * c)) * 0xFFull;
 #pragma unroll
-                for (int b = 0; b < 8; ++b)
+                for (int b = 0; b < PL; ++b)
                     if (b < planes_used) by |= spread8(pl[b] >> (8 * c)) << b;
                 dst[c] = by;
             }
         }
         __syncthreads();
+        if (PREFETCH && tile + TILES < t_end) load_tiles(tile + TILES);
         // rows out: 8 threads per row, UNIT bytes each
         const int32_t v0 = tile * 64;
         const int valid = min(SEG, min(a.n - v0, (t_end - tile) * 64));
@@ -598,7 +593,7 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
             for (int i = 0; i < UNIT; ++i) pv[i] = off + i < valid ? sa.xy[v0 + off + i] : make_float2(0.0f, 0.0f);
         }
 #pragma unroll
-        for (int it = 0; it < ITS; ++it) {
+        for (int it = 0; it < kStressIts; ++it) {
             const int q = threadIdx.x + it * ROWS;
             const int r = q >> 3, off = (q & 7) * UNIT;
             const uint8_t *src = stage + (size_t)r * PITCH + off;
@@ -628,10 +623,61 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
         }
         __syncthreads();
     }
+    if (!STRESS && part && slot_ok) {
+        uint4 *p = (uint4 *)(part + ((size_t)local_slot * gridDim.x + blockIdx.x) * kCountLevels);
+#pragma unroll
+        for (int q = 0; q < kCountLevels / 4; ++q) p[q] = make_uint4(cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]);
+    }
+}
+
+// The same transpose with the stores staged in LDS: each wave leaves the hop
+// bytes of its 64 sources for TILES 64-vertex tiles (64 * TILES bytes per
+// source) in LDS, and the whole block then writes the rows out as whole
+// segments (8 * TILES threads per row), instead of 16 bytes into 64
+// different rows per store.  Needs rows aligned to 8 * TILES bytes.
+// With STRESS the staged bytes are not stored: each row's stress terms
+// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 5.1) are summed in
+// FP64 instead, one partial sum and pair count per (slot, block).
+template <int WORDS, int TILES, bool STRESS>
+__global__ void __launch_bounds__(WORDS * GM_WAVE)
+msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
+                         const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part,
+                         StressArgs sa)
+{
+    const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
+    constexpr int ROWS = WORDS * GM_WAVE;
+    constexpr int PITCH = 64 * TILES + 8 * TILES;
+    __shared__ __align__(16) uint8_t stage[ROWS * PITCH];
+    __shared__ int64_t row_base[ROWS];
+    __shared__ double rinv[STRESS ? 256 : 1];   // 1 / h for the stress terms
+    const int32_t g = blockIdx.y;
+    const int32_t local_slot = g * ROWS + threadIdx.x;
+    // store / stress rows of this thread: r = threadIdx.x / 8 + it * ROWS / 8
+    double st_sum[kStressIts];
+    unsigned int st_cnt[kStressIts];
+    float2 st_xy[kStressIts];
+    if (STRESS) {
+        for (int h = threadIdx.x; h < 256; h += blockDim.x) rinv[h] = h ? 1.0 / (double)h : 0.0;
+#pragma unroll
+        for (int it = 0; it < kStressIts; ++it) {
+            st_sum[it] = 0.0;
+            st_cnt[it] = 0;
+            const int32_t ls = g * ROWS + (threadIdx.x >> 3) + it * (ROWS >> 3);
+            st_xy[it] = ls < a.n_slots ? sa.xy[a.usrc[a.slot0 + ls]] : make_float2(0.0f, 0.0f);
+        }
+    } else {
+        row_base[threadIdx.x] = local_slot < a.n_slots ? slot_row[local_slot] * row_stride : -1;
+    }
+    if (planes_used <= 4)
+        hops_staged_body<WORDS, TILES, STRESS, 4>(a, planes_used, hop_out, part, sa, stage, row_base, rinv, st_sum,
+                                                  st_cnt, st_xy);
+    else
+        hops_staged_body<WORDS, TILES, STRESS, 8>(a, planes_used, hop_out, part, sa, stage, row_base, rinv, st_sum,
+                                                  st_cnt, st_xy);
     if (STRESS) {
         // the 8 threads of a row are adjacent lanes: reduce, then one writes
 #pragma unroll
-        for (int it = 0; it < ITS; ++it) {
+        for (int it = 0; it < kStressIts; ++it) {
             double v = st_sum[it];
             unsigned int c = st_cnt[it];
 #pragma unroll
@@ -645,10 +691,6 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
                 sa.part_pairs[(size_t)ls * gridDim.x + blockIdx.x] = c;
             }
         }
-    } else if (part && slot_ok) {
-        uint4 *p = (uint4 *)(part + ((size_t)local_slot * gridDim.x + blockIdx.x) * kCountLevels);
-#pragma unroll
-        for (int q = 0; q < kCountLevels / 4; ++q) p[q] = make_uint4(cnt[4 * q], cnt[4 * q + 1], cnt[4 * q + 2], cnt[4 * q + 3]);
     }
 }
 
