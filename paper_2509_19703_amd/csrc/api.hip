@@ -397,6 +397,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.heavy_deg = heavy_deg;
         a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
         a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
+        a.level_verts = (int32_t)env_size("GUMAP_LEVEL_VERTS", 2);
         const size_t arr = arr_per_group * a.groups;
         a.front[0] = state;
         a.front[1] = state + arr;

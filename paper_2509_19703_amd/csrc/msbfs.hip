@@ -71,11 +71,11 @@ struct Counters {
     unsigned long long v[kStatFields];
 };
 
-// Commit of the previous level's frontier word of (vertex, word) at `me`.
-__device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, size_t me, Counters &c)
+// Commit of the previous level's frontier word f of (vertex, word) at `me`,
+// whose visited word is vis; returns the new visited word.
+__device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, size_t me, uint64_t f, uint64_t vis,
+                                                Counters &c)
 {
-    const uint64_t f = a.front[level & 1][me];
-    uint64_t vis = a.visited[me];
     if (f) {
         vis |= f;
         a.visited[me] = vis;
@@ -87,7 +87,7 @@ __device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, s
     return vis;
 }
 
-template <int WORDS>
+template <int WORDS, int VERTS>
 __global__ void __launch_bounds__(kLevelBlock)
 msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, int per_group, int xcd_map)
 {
@@ -131,76 +131,86 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     const int heavy_blocks = per_group - light_blocks;
     if (vb >= heavy_blocks) {
         const int32_t lb = vb - heavy_blocks;
-        // one thread per (vertex, word): commit for every vertex; the search
-        // of vertices of degree > heavy_deg is left to the heavy waves (except
-        // at level 1, where all are searched here)
-        const int64_t idx = (int64_t)lb * kLevelBlock + threadIdx.x;
-        const int32_t v = (int32_t)(idx >> LW);
-        const int w = (int)(idx & (WORDS - 1));
-        int cols = 0;
-        if (v < a.n) {
-            const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+        // VERTS (vertex, word) items per thread, kLevelBlock apart: the row
+        // pointers, frontier and visited words of all of them are loaded
+        // before any is used, so that each wave keeps several loads in
+        // flight.  Every vertex is committed; the search of vertices of
+        // degree > heavy_deg is left to the heavy waves (except at level 1,
+        // where all are searched here).
+        const int64_t idx0 = (int64_t)lb * kLevelBlock * VERTS + threadIdx.x;
+        const int w = (int)(idx0 & (WORDS - 1));
+        int32_t e0[VERTS], e1[VERTS];
+        uint64_t f[VERTS], vis[VERTS];
+#pragma unroll
+        for (int j = 0; j < VERTS; ++j) {
+            const int32_t v = (int32_t)((idx0 + (int64_t)j * kLevelBlock) >> LW);
+            const bool in = v < a.n;
             const size_t me = gbase + ((size_t)v << LW) + w;
-            // the first batch of neighbour ids is read before the commit, so
-            // that its latency overlaps the commit's loads
-            const bool search = level >= 2 && !commit_only && e1 - e0 <= a.heavy_deg;
-            int32_t u0[kGatherBatch];
+            e0[j] = in ? a.row_ptr[v] : 0;
+            e1[j] = in ? a.row_ptr[v + 1] : 0;
+            f[j] = in ? fr[me] : 0ull;
+            vis[j] = in ? a.visited[me] : 0ull;
+        }
 #pragma unroll
-            for (int i = 0; i < kGatherBatch; ++i) u0[i] = search && e0 + i < e1 ? a.col[e0 + i] : -1;
-            const uint64_t vis = commit_word(a, level, me, c);
-            if (level == 1 || e1 - e0 <= a.heavy_deg) {
-                if (!commit_only) {
-                    const int32_t ls0 = g * 64 * WORDS + 64 * w;
-                    const uint64_t unv = ~vis & word_valid_mask(a.n_slots, ls0);
-                    uint64_t acc = 0;
-                    if (unv) {
-                        if (level == 1) {
-                            const int32_t gs0 = a.slot0 + ls0;
-                            const int32_t gl = min(gs0 + 63, a.slot0 + a.n_slots - 1);
-                            const int32_t lo = a.usrc[gs0], hi = a.usrc[gl];
-                            int32_t lo_e = e0, hi_e = e1;
-                            while (lo_e < hi_e) {
-                                const int32_t mid = (lo_e + hi_e) >> 1;
-                                ++cols;
-                                if (a.col[mid] < lo) lo_e = mid + 1;
-                                else hi_e = mid;
-                            }
-                            for (int32_t e = lo_e; e < e1; ++e) {
-                                const int32_t u = a.col[e];
-                                ++cols;
-                                if (u > hi) break;
-                                const int32_t s = a.slot_of[u];
-                                if (s >= 0) acc |= 1ull << (s - gs0);
-                            }
-                        } else {
-                            for (int32_t e = e0; e < e1; e += kGatherBatch) {
-                                // kGatherBatch independent neighbour loads in flight
-                                int32_t u[kGatherBatch];
+        for (int j = 0; j < VERTS; ++j) {
+            const int32_t v = (int32_t)((idx0 + (int64_t)j * kLevelBlock) >> LW);
+            vis[j] = commit_word(a, level, gbase + ((size_t)v << LW) + w, f[j], vis[j], c);
+        }
 #pragma unroll
-                                for (int i = 0; i < kGatherBatch; ++i)
-                                    u[i] = e == e0 ? u0[i] : (e + i < e1 ? a.col[e + i] : -1);
-                                uint64_t x = 0;
+        for (int j = 0; j < VERTS; ++j) {
+            const int32_t v = (int32_t)((idx0 + (int64_t)j * kLevelBlock) >> LW);
+            const size_t me = gbase + ((size_t)v << LW) + w;
+            int cols = 0;
+            if (v < a.n && !commit_only && (level == 1 || e1[j] - e0[j] <= a.heavy_deg)) {
+                const int32_t ls0 = g * 64 * WORDS + 64 * w;
+                const uint64_t unv = ~vis[j] & word_valid_mask(a.n_slots, ls0);
+                uint64_t acc = 0;
+                if (unv) {
+                    if (level == 1) {
+                        const int32_t gs0 = a.slot0 + ls0;
+                        const int32_t gl = min(gs0 + 63, a.slot0 + a.n_slots - 1);
+                        const int32_t lo = a.usrc[gs0], hi = a.usrc[gl];
+                        int32_t lo_e = e0[j], hi_e = e1[j];
+                        while (lo_e < hi_e) {
+                            const int32_t mid = (lo_e + hi_e) >> 1;
+                            ++cols;
+                            if (a.col[mid] < lo) lo_e = mid + 1;
+                            else hi_e = mid;
+                        }
+                        for (int32_t e = lo_e; e < e1[j]; ++e) {
+                            const int32_t u = a.col[e];
+                            ++cols;
+                            if (u > hi) break;
+                            const int32_t s = a.slot_of[u];
+                            if (s >= 0) acc |= 1ull << (s - gs0);
+                        }
+                    } else {
+                        for (int32_t e = e0[j]; e < e1[j]; e += kGatherBatch) {
+                            // kGatherBatch independent neighbour loads in flight
+                            int32_t u[kGatherBatch];
 #pragma unroll
-                                for (int i = 0; i < kGatherBatch; ++i)
-                                    if (u[i] >= 0) x |= fr[gbase + ((size_t)u[i] << LW) + w];
-                                const int got = min(kGatherBatch, e1 - e);
-                                cols += got;
-                                c.v[kFieldGathers] += got;
-                                acc |= x;
-                                if ((acc & unv) == unv) break;
-                            }
+                            for (int i = 0; i < kGatherBatch; ++i) u[i] = e + i < e1[j] ? a.col[e + i] : -1;
+                            uint64_t x = 0;
+#pragma unroll
+                            for (int i = 0; i < kGatherBatch; ++i)
+                                if (u[i] >= 0) x |= fr[gbase + ((size_t)u[i] << LW) + w];
+                            const int got = min(kGatherBatch, e1[j] - e);
+                            cols += got;
+                            c.v[kFieldGathers] += got;
+                            acc |= x;
+                            if ((acc & unv) == unv) break;
                         }
                     }
-                    const uint64_t nw = acc & unv;
-                    a.front[(level + 1) & 1][me] = nw;
-                    c.v[kFieldNewBits] += __popcll(nw);
                 }
+                const uint64_t nw = acc & unv;
+                a.front[(level + 1) & 1][me] = nw;
+                c.v[kFieldNewBits] += __popcll(nw);
             }
-        }
-        // adjacency entries are shared by the word threads of a vertex: count the longest scan once
+            // adjacency entries are shared by the word threads of a vertex: count the longest scan once
 #pragma unroll
-        for (int o = 1; o < WORDS; o <<= 1) cols = max(cols, __shfl_xor(cols, o, GM_WAVE));
-        if (w == 0) c.v[kFieldCols] += cols;
+            for (int o = 1; o < WORDS; o <<= 1) cols = max(cols, __shfl_xor(cols, o, GM_WAVE));
+            if (w == 0) c.v[kFieldCols] += cols;
+        }
     } else if (level >= 2) {
         // one wave per heavy vertex: lane = (neighbour group, word)
         const int32_t hidx = vb * (kLevelBlock / GM_WAVE) + wid;
@@ -722,20 +732,33 @@ hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int WORDS>
+void launch_level_words(int verts, dim3 grid, hipStream_t s, const MsbfsArgs &a, int level, int co, int light,
+                        int per_group, int xcd)
+{
+    if (verts == 4)
+        hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 4>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
+    else if (verts == 2)
+        hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 2>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
+    else
+        hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 1>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
+}
+
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s)
 {
     const int64_t items = (int64_t)a.n * a.words;
-    const int light = (int)((items + kLevelBlock - 1) / kLevelBlock);
+    const int verts = a.level_verts == 2 || a.level_verts == 4 ? a.level_verts : 1;
+    const int light = (int)((items + (int64_t)kLevelBlock * verts - 1) / ((int64_t)kLevelBlock * verts));
     const int heavy = level >= 2 ? (a.n_heavy + kLevelBlock / GM_WAVE - 1) / (kLevelBlock / GM_WAVE) : 0;
     const int per_group = light + heavy;
     const int xcd = (a.xcd_map && a.groups % 8 == 0) ? 1 : 0;
     dim3 grid((unsigned)((int64_t)per_group * a.groups));
     const int co = commit_only ? 1 : 0;
     switch (a.words) {
-    case 1: hipLaunchKernelGGL(msbfs_level_kernel<1>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
-    case 2: hipLaunchKernelGGL(msbfs_level_kernel<2>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
-    case 4: hipLaunchKernelGGL(msbfs_level_kernel<4>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
-    case 8: hipLaunchKernelGGL(msbfs_level_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd); break;
+    case 1: launch_level_words<1>(verts, grid, s, a, level, co, light, per_group, xcd); break;
+    case 2: launch_level_words<2>(verts, grid, s, a, level, co, light, per_group, xcd); break;
+    case 4: launch_level_words<4>(verts, grid, s, a, level, co, light, per_group, xcd); break;
+    case 8: launch_level_words<8>(verts, grid, s, a, level, co, light, per_group, xcd); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

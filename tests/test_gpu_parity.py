@@ -92,6 +92,21 @@ def test_bitset_width_invariance(gumap, words, monkeypatch):
         _check_build(gumap, g, 10, sources=src, hop_matrix=False)
 
 
+@pytest.mark.parametrize("verts", [1, 2, 4])
+def test_level_items_per_thread_invariance(gumap, verts, monkeypatch):
+    """The per-level BFS gives the oracle's rows whether a thread of its
+    level kernel takes 1, 2 or 4 (vertex, word) items: ragged vertex counts,
+    hub vertices searched by whole waves, every bitset width."""
+    monkeypatch.setenv("GUMAP_FUSED", "0")
+    monkeypatch.setenv("GUMAP_LEVEL_VERTS", str(verts))
+    print("level items per thread %d" % verts, flush=True)
+    for g, words in ((G.ba(4099, 4, 33), 8), (G.ba(2051, 6, 34), 2), (G.rgg(1777, 6, 35), 1), (G.star(1025), 4)):
+        monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+        _check_build(gumap, g, 15, hop_matrix=True)
+        src = G.sample_sources(g.n, 333, 36)
+        _check_build(gumap, g, 7, sources=src, hop_matrix=False)
+
+
 def test_sources_with_repeats_and_order(gumap):
     g = G.sbm(2500, 10, 41)
     src = np.concatenate([G.sample_sources(g.n, 300, 42), [5, 5, 17, 2499, 0, 17]]).astype(np.int32)
