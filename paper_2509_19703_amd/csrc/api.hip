@@ -434,10 +434,10 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             // once each) and the three LDS state words per vertex
             prof_set_bytes(mark, (double)(last_level + 1) * a.groups * (8.0 * n + 4.0 * g->nnz + 24.0 * n));
         } else {
-        e = hipMemsetAsync(a.front[1], 0, 2 * arr * 8, s);  // front[1] and visited
-        if (e == hipSuccess) e = hipMemsetAsync(stats, 0, (size_t)(L_cap + 2) * spl * 8, s);
-        if (e == hipSuccess) e = launch_msbfs_init(a, s);
-        if (e != hipSuccess) return hip_status(e, "bfs init");
+        // Level 1 sets the source bits and stores every visited word, so the
+        // frontier and visited words need no clearing; each bit-plane is
+        // cleared before its first hop and the counters of each batch of
+        // levels with the batch.
 
         // sum over spread slots of one field for (level, group)
         auto level_sum = [&](int lv, int q, int field) {
@@ -484,6 +484,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         int32_t *depth = info + 16;
         while (!done) {
             const int first = L;
+            const int batch = std::min(chunk, L_cap + 1 - first);
+            e = hipMemsetAsync(stats + (size_t)first * spl, 0, (size_t)batch * spl * 8, s);
+            if (e != hipSuccess) return hip_status(e, "level counters");
             for (int c2 = 0; c2 < chunk && L <= L_cap; ++c2, ++L) {
                 const int hop = L - 1;   // committed by this launch
                 if (hop >= 1 && (hop & (hop - 1)) == 0) {
@@ -535,8 +538,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if ((hop & (hop - 1)) == 0) {
                     int b = bit_length(hop) - 1;
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
-                    if (e != hipSuccess) return hip_status(e, "plane clear");
                 }
+                if (e == hipSuccess) e = hipMemsetAsync(stats + (size_t)(L_cap + 1) * spl, 0, spl * 8, s);
+                if (e != hipSuccess) return hip_status(e, "plane clear / level counters");
                 const int mk = prof_begin("msbfs_level", s);
                 e = launch_msbfs_level(a, L_cap + 1, true, s);
                 // commit-only: reads front + visited, writes the committed words

@@ -70,7 +70,6 @@ int msbfs_stat_spread();
 // (forced if > 0, else max(64, 8 * mean degree)); info[1] must be zero.
 hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, int32_t *heavy, int32_t *info,
                              hipStream_t s);
-hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s);
 // Small graphs (words == 1, msbfs_fused_lds_bytes(n) of LDS): every level of
 // each group in one workgroup, replacing init + the per-level launches; the
 // planes must be zero beforehand.  group_out[2g] = last level with new

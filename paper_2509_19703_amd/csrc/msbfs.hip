@@ -55,27 +55,22 @@ __device__ __forceinline__ uint64_t word_valid_mask(int32_t n_slots, int32_t loc
     return (1ull << c) - 1ull;
 }
 
-__global__ void msbfs_init_kernel(MsbfsArgs a)
-{
-    // one thread per slot of the round: set the source's own bit (hop 0)
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n_slots) return;
-    const int W = 64 * a.words;
-    int32_t g = i / W, r = i % W, w = r >> 6, bit = r & 63;
-    int32_t u = a.usrc[a.slot0 + i];
-    size_t idx = ((size_t)g * a.n + u) * a.words + w;
-    atomicOr((unsigned long long *)&a.front[1][idx], 1ull << bit);
-}
-
 struct Counters {
     unsigned long long v[kStatFields];
 };
 
 // Commit of the previous level's frontier word f of (vertex, word) at `me`,
-// whose visited word is vis; returns the new visited word.
+// whose visited word is vis; returns the new visited word.  Level 1 (hop 0)
+// stores visited = f for every word, so visited needs no clearing; the
+// bit-planes are cleared by the host before their first hop.
 __device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, size_t me, uint64_t f, uint64_t vis,
                                                 Counters &c)
 {
+    if (level == 1) {
+        a.visited[me] = f;
+        if (f) c.v[kFieldCommits] += 1;
+        return f;
+    }
     if (f) {
         vis |= f;
         a.visited[me] = vis;
@@ -107,6 +102,8 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
         vb = blockIdx.x % per_group;
     }
     const int l = lane(), wid = threadIdx.x / GM_WAVE;
+    const int heavy_blocks = per_group - light_blocks;
+    const size_t gbase = (size_t)g * a.n * WORDS;
     if (level >= 2) {
         // previous level found nothing for this group: nothing to commit or search
         const unsigned long long x =
@@ -124,11 +121,9 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
         if (got == (unsigned long long)(a.n - 1) * (unsigned long long)in_group) commit_only = 1;
     }
     Counters c{};
-    const size_t gbase = (size_t)g * a.n * WORDS;
     const uint64_t *__restrict__ fr = a.front[level & 1];
     // heavy-vertex waves come first in launch order: the longest rows start
     // early instead of forming the tail of the level
-    const int heavy_blocks = per_group - light_blocks;
     if (vb >= heavy_blocks) {
         const int32_t lb = vb - heavy_blocks;
         // VERTS (vertex, word) items per thread, kLevelBlock apart: the row
@@ -148,13 +143,21 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
             const size_t me = gbase + ((size_t)v << LW) + w;
             e0[j] = in ? a.row_ptr[v] : 0;
             e1[j] = in ? a.row_ptr[v + 1] : 0;
-            f[j] = in ? fr[me] : 0ull;
-            vis[j] = in ? a.visited[me] : 0ull;
+            if (level == 1) {
+                // hop 0: the vertex's own bit if it is a source of this word
+                const int32_t ls = (in ? a.slot_of[v] : -1) - a.slot0;
+                const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
+                f[j] = (in && ls >= 0 && ls < a.n_slots && bit >= 0 && bit < 64) ? 1ull << bit : 0ull;
+                vis[j] = 0ull;
+            } else {
+                f[j] = in ? fr[me] : 0ull;
+                vis[j] = in ? a.visited[me] : 0ull;
+            }
         }
 #pragma unroll
         for (int j = 0; j < VERTS; ++j) {
             const int32_t v = (int32_t)((idx0 + (int64_t)j * kLevelBlock) >> LW);
-            vis[j] = commit_word(a, level, gbase + ((size_t)v << LW) + w, f[j], vis[j], c);
+            if (v < a.n) vis[j] = commit_word(a, level, gbase + ((size_t)v << LW) + w, f[j], vis[j], c);
         }
 #pragma unroll
         for (int j = 0; j < VERTS; ++j) {
@@ -724,13 +727,6 @@ hipError_t launch_hops_words(dim3 grid, int variant, const MsbfsArgs &a, int pla
 }
 
 }  // namespace
-
-hipError_t launch_msbfs_init(const MsbfsArgs &a, hipStream_t s)
-{
-    if (a.n_slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(msbfs_init_kernel, dim3((a.n_slots + 255) / 256), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
 
 template <int WORDS>
 void launch_level_words(int verts, dim3 grid, hipStream_t s, const MsbfsArgs &a, int level, int co, int light,
