@@ -21,6 +21,11 @@ extern "C" {
 
 /* Starts (on != 0) or stops recording.  Recording adds two event records per launch. */
 void gumap_profile_enable(int on);
+/* Restricts recording to the kernels named in `names`, a comma-separated
+ * list of the names gumap_profile_entry reports (say "msbfs_level"); NULL or
+ * "" records every kernel again.  The list is copied.  Launches of other
+ * kernels then get no events, so they run as with recording off. */
+void gumap_profile_only(const char *names);
 /* Drops everything recorded so far. */
 void gumap_profile_reset(void);
 /* Number of distinct kernels recorded. */

@@ -142,6 +142,8 @@ def _load() -> ctypes.CDLL:
         f.restype = ctypes.c_int
     lib.gumap_profile_enable.argtypes = [ctypes.c_int]
     lib.gumap_profile_enable.restype = None
+    lib.gumap_profile_only.argtypes = [ctypes.c_char_p]
+    lib.gumap_profile_only.restype = None
     lib.gumap_profile_reset.argtypes = []
     lib.gumap_profile_reset.restype = None
     lib.gumap_profile_count.argtypes = []
@@ -173,6 +175,13 @@ lib = _load()
 def profile_enable(on: bool = True) -> None:
     """Record HIP-event timings of the library's kernel launches (gumap_profile.h)."""
     lib.gumap_profile_enable(1 if on else 0)
+
+
+def profile_only(names=None) -> None:
+    """Record only the kernels named (a list or comma-separated string; None: all)."""
+    if names is not None and not isinstance(names, str):
+        names = ",".join(names)
+    lib.gumap_profile_only(names.encode() if names else None)
 
 
 def profile_reset() -> None:

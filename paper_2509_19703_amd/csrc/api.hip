@@ -1370,10 +1370,10 @@ int effective_resistance(const gumap_graph *g, int32_t q, uint64_t seed, double 
     while (its < max_iters) {
         const int batch = std::min(8, max_iters - its);
         for (int b = 0; b < batch; ++b) {
-            // per iteration: the Laplacian product (rows and neighbour rows of
-            // q values), two passes of dot products, the updates
-            GM_PROF("cg_iteration", (double)(c.n + 1) * 4.0 + (double)g->nnz * (4.0 + 8.0 * q) +
-                                        (double)c.n * q * 8.0 * 12.0,
+            // per iteration: the Laplacian product (row pointers, adjacency and
+            // each vertex's row of q values once: the neighbour-row gathers
+            // repeat rows already read), two passes of dot products, the updates
+            GM_PROF("cg_iteration", (double)(c.n + 1) * 4.0 + (double)g->nnz * 4.0 + (double)c.n * q * 8.0 * 13.0,
                     launch_cg_iteration(a, q, tol, max_iters, s));
             if (e != hipSuccess) return hip_status(e, "cg iteration");
         }

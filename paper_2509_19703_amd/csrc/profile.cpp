@@ -27,6 +27,7 @@ struct Totals {
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    std::vector<std::string> only;   // names recorded (all when empty)
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
     std::map<std::string, Totals> totals;
@@ -62,6 +63,11 @@ int prof_begin(const char *name, hipStream_t s)
 {
     Profiler &p = prof();
     if (!p.on) return -1;
+    if (!p.only.empty()) {
+        bool listed = false;
+        for (const std::string &o : p.only) listed |= o == name;
+        if (!listed) return -1;
+    }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
@@ -127,6 +133,24 @@ void prof_resolve()
 extern "C" {
 
 void gumap_profile_enable(int on) { gm::prof().on = on != 0; }
+
+void gumap_profile_only(const char *names)
+{
+    gm::Profiler &p = gm::prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.only.clear();
+    if (!names) return;
+    std::string cur;
+    for (const char *c = names;; ++c) {
+        if (*c == ',' || *c == '\0') {
+            if (!cur.empty()) p.only.push_back(cur);
+            cur.clear();
+            if (*c == '\0') break;
+        } else {
+            cur.push_back(*c);
+        }
+    }
+}
 
 void gumap_profile_reset(void)
 {

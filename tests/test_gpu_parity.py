@@ -360,3 +360,30 @@ def test_listed_sources_ranking_large_graph(gumap):
     g = G.ba(140000, 2, 403)
     src = np.concatenate([G.sample_sources(g.n, 60, 404), [7, 7, 139999]]).astype(np.int32)
     _check_build(gumap, g, 9, sources=src, hop_matrix=False)
+
+
+def test_profile_only_records_listed_kernels(gumap):
+    """gumap_profile_only restricts the launch profiler to the named kernels
+    and NULL records all of them again; the rows are unaffected."""
+    import torch
+    g = G.ba(9000, 4, 61)
+    rp, ci = to_dev(g)
+    src = torch.from_numpy(G.sample_sources(g.n, 300, 62)).cuda()
+    oi, oh, _ = O.knn_build(g, 9, sources=G.sample_sources(g.n, 300, 62), hop_matrix=False)
+    try:
+        for only, want in ((["knn_select", "msbfs_level"], {"knn_select", "msbfs_level"}), (None, None)):
+            gumap.profile_reset()
+            gumap.profile_only(only)
+            gumap.profile_enable(True)
+            ids, hops, _ = gumap.knn_build(rp, ci, 9, sources=src, hop_matrix=False, flags=gumap.CSR_SORTED)
+            gumap.profile_enable(False)
+            got = set(gumap.profile_entries())
+            assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+            if want is not None:
+                assert got == want
+            else:
+                assert {"knn_select", "msbfs_level", "msbfs_hops"} <= got
+    finally:
+        gumap.profile_enable(False)
+        gumap.profile_only(None)
+        gumap.profile_reset()
