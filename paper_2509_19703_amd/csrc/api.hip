@@ -398,6 +398,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
         a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
         a.level_verts = (int32_t)env_size("GUMAP_LEVEL_VERTS", 2);
+        // Level 1 as a fill plus a top-down scatter from the sources (about
+        // n_slots * mean degree atomic ORs) on sparse graphs, else by the level
+        // kernel's range scan (n * words items per group); GUMAP_FIRST_LEVEL
+        // = 0 / 1 forces either.
+        const size_t first_env = env_size("GUMAP_FIRST_LEVEL", 2);
+        const bool first_split = first_env == 2 ? (double)g->nnz * 256.0 <= (double)n * (double)n : first_env != 0;
         const size_t arr = arr_per_group * a.groups;
         a.front[0] = state;
         a.front[1] = state + arr;
@@ -451,6 +457,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         // algorithmic bytes of one level launch, from its counters
         auto level_bytes = [&](int lv, bool commit_only) {
             double b = 0.0;
+            if (lv == 1 && first_split) {
+                // fill: slot ids read, visited and next-frontier words stored;
+                // scatter: adjacency of the sources, one 8-byte atomic OR each
+                for (int q = 0; q < a.groups; ++q) b += 4.0 * n + 16.0 * (double)n * words + 20.0 * level_sum(1, q, 2);
+                return b;
+            }
             const int hop = lv - 1;
             const int pc = __builtin_popcount((unsigned)(hop > 0 ? hop : 0));
             for (int q = 0; q < a.groups; ++q) {
@@ -494,8 +506,13 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
                     if (e != hipSuccess) return hip_status(e, "plane clear");
                 }
-                marks[L] = prof_begin("msbfs_level", s);
-                e = launch_msbfs_level(a, L, false, s);
+                if (L == 1 && first_split) {
+                    marks[L] = prof_begin("msbfs_first", s);
+                    e = launch_msbfs_first(a, s);
+                } else {
+                    marks[L] = prof_begin("msbfs_level", s);
+                    e = launch_msbfs_level(a, L, false, s);
+                }
                 prof_end(marks[L], s, 0.0);
                 ran[L] = 1;
                 if (e != hipSuccess) return hip_status(e, "bfs level");

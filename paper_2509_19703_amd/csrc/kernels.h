@@ -78,6 +78,11 @@ size_t msbfs_fused_lds_bytes(int32_t n);
 hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t *group_out, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).
+// Level 1 (commit of the sources, hop-1 frontier) as a fill of visited and
+// the next frontier plus a per-source scatter of the sources' bits to their
+// neighbours; leaves the same state and level-1 new-bit counts as
+// launch_msbfs_level(a, 1, false, s).  The level-1 counters must be zero.
+hipError_t launch_msbfs_first(const MsbfsArgs &a, hipStream_t s);
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s);
 // After levels [first, last) of a round: out[0] = bit_length of the last
 // level that found vertices (the plane count the transpose needs once the

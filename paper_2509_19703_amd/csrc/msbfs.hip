@@ -276,6 +276,56 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     }
 }
 
+// Level 1 in two launches (the default; the level kernel can run it too, by
+// a range scan of every vertex's sorted adjacency).  The fill stores, for
+// every (vertex, word) item, visited = the vertex's own bit if it is a
+// source of that word (hop 0) and clears the item's next-frontier word.
+template <int WORDS>
+__global__ void __launch_bounds__(256) msbfs_first_fill_kernel(MsbfsArgs a)
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const int32_t g = blockIdx.y;
+    const int64_t items = (int64_t)a.n * WORDS;
+    const size_t gbase = (size_t)g * items;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < items;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = (int32_t)(idx >> LW);
+        const int w = (int)(idx & (WORDS - 1));
+        const int32_t ls = a.slot_of[v] - a.slot0;
+        const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
+        a.visited[gbase + idx] = (ls >= 0 && ls < a.n_slots && bit >= 0 && bit < 64) ? 1ull << bit : 0ull;
+        a.front[0][gbase + idx] = 0ull;
+    }
+}
+
+// Then one wave per source ORs the source's bit into the hop-1 frontier word
+// of each of its neighbours (top-down: a source's neighbours are exactly the
+// vertices at hop 1 from it) and counts the bits it newly set.
+template <int WORDS>
+__global__ void __launch_bounds__(256) msbfs_first_scatter_kernel(MsbfsArgs a)
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const int l = lane();
+    const int32_t slot = blockIdx.x * (256 / GM_WAVE) + (int32_t)(threadIdx.x / GM_WAVE);   // local slot
+    if (slot >= a.n_slots) return;
+    const int32_t g = slot / (64 * WORDS), w = (slot % (64 * WORDS)) >> 6;
+    const unsigned long long bit = 1ull << (slot & 63);
+    const int32_t v = a.usrc[a.slot0 + slot];
+    const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+    unsigned long long *fr = (unsigned long long *)a.front[0] + (size_t)g * a.n * WORDS + w;
+    unsigned long long nb = 0;
+    for (int32_t e = e0 + l; e < e1; e += GM_WAVE) {
+        const unsigned long long old = atomicOr(fr + ((size_t)a.col[e] << LW), bit);
+        nb += (old & bit) ? 0ull : 1ull;
+    }
+    nb = wave_sum_u64(nb);
+    if (l == 0) {
+        unsigned long long *st = a.stats + ((size_t)(1 * a.stats_groups + g) * kSpread + (slot & (kSpread - 1))) * kStatFields;
+        if (nb) atomicAdd(st + kFieldNewBits, nb);
+        if (e1 > e0) atomicAdd(st + kFieldCols, (unsigned long long)(e1 - e0));
+    }
+}
+
 // Small graphs: all levels of one group in one workgroup, the frontier and
 // visited words (one 64-source word per vertex) in LDS, the bit-planes in
 // global memory for the hop-row transpose.  Same levels, commits and stop
@@ -738,6 +788,28 @@ void launch_level_words(int verts, dim3 grid, hipStream_t s, const MsbfsArgs &a,
         hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 2>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
     else
         hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 1>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
+}
+
+template <int WORDS>
+void launch_first_words(const MsbfsArgs &a, hipStream_t s)
+{
+    const int64_t items = (int64_t)a.n * WORDS;
+    const unsigned fill_blocks = (unsigned)std::min<int64_t>((items + 255) / 256, 65535);
+    hipLaunchKernelGGL(msbfs_first_fill_kernel<WORDS>, dim3(fill_blocks, (unsigned)a.groups), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(msbfs_first_scatter_kernel<WORDS>, dim3((unsigned)((a.n_slots + 3) / 4)), dim3(256), 0, s, a);
+}
+
+hipError_t launch_msbfs_first(const MsbfsArgs &a, hipStream_t s)
+{
+    if (a.n <= 0 || a.n_slots <= 0) return hipSuccess;
+    switch (a.words) {
+    case 1: launch_first_words<1>(a, s); break;
+    case 2: launch_first_words<2>(a, s); break;
+    case 4: launch_first_words<4>(a, s); break;
+    case 8: launch_first_words<8>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s)

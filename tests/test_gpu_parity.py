@@ -92,14 +92,17 @@ def test_bitset_width_invariance(gumap, words, monkeypatch):
         _check_build(gumap, g, 10, sources=src, hop_matrix=False)
 
 
-@pytest.mark.parametrize("verts", [1, 2, 4])
-def test_level_items_per_thread_invariance(gumap, verts, monkeypatch):
+@pytest.mark.parametrize("verts,first", [(1, "1"), (2, "1"), (4, "1"), (1, "0"), (2, "0")])
+def test_level_items_per_thread_invariance(gumap, verts, first, monkeypatch):
     """The per-level BFS gives the oracle's rows whether a thread of its
-    level kernel takes 1, 2 or 4 (vertex, word) items: ragged vertex counts,
-    hub vertices searched by whole waves, every bitset width."""
+    level kernel takes 1, 2 or 4 (vertex, word) items, and whether level 1
+    runs as a fill plus a scatter from the sources or as a range scan in the
+    level kernel: ragged vertex counts, hub vertices searched by whole waves,
+    every bitset width."""
     monkeypatch.setenv("GUMAP_FUSED", "0")
     monkeypatch.setenv("GUMAP_LEVEL_VERTS", str(verts))
-    print("level items per thread %d" % verts, flush=True)
+    monkeypatch.setenv("GUMAP_FIRST_LEVEL", first)
+    print("level items per thread %d, first level split %s" % (verts, first), flush=True)
     for g, words in ((G.ba(4099, 4, 33), 8), (G.ba(2051, 6, 34), 2), (G.rgg(1777, 6, 35), 1), (G.star(1025), 4)):
         monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
         _check_build(gumap, g, 15, hop_matrix=True)
