@@ -893,11 +893,12 @@ def write_traffic(args):
 
 
 def kernel_source_sha() -> str:
-    """Hash of the sources of the BFS level kernel (the one the stored counter
-    readings are for), so they go stale when that kernel changes."""
+    """Hash of the sources of the BFS level kernel and of the host code that
+    picks its launch configuration (the stored counter readings are for that
+    kernel), so they go stale when either changes."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("msbfs.hip", "kernels.h", "device.h"):
+    for name in ("msbfs.hip", "kernels.h", "device.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_2509_19703_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

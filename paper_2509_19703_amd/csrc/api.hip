@@ -397,7 +397,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.heavy_deg = heavy_deg;
         a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
         a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
-        a.level_verts = (int32_t)env_size("GUMAP_LEVEL_VERTS", 2);
+        a.level_verts = (int32_t)env_size("GUMAP_LEVEL_VERTS", 4);
         // Level 1 as a fill plus a top-down scatter from the sources (about
         // n_slots * mean degree atomic ORs) on sparse graphs, else by the level
         // kernel's range scan (n * words items per group); GUMAP_FIRST_LEVEL

@@ -58,7 +58,7 @@ struct MsbfsArgs {
     int32_t heavy_deg;
     int32_t xcd_map;          // keep each group on one XCD when groups % 8 == 0
     int32_t hops_variant;     // hop-row writer: tiles per step / store kind (tuning)
-    int32_t level_verts;      // (vertex, word) items per thread of the level kernel: 1, 2 or 4
+    int32_t level_verts;      // (vertex, word) items per thread of the level kernel: 1, 2, 4 or 8
     const int32_t *planes_dev; // if not NULL: the transpose reads its plane count here (device)
 };
 // Layout of the level counters: stats[((level * groups + g) * spread + slot) * fields + field]

@@ -34,7 +34,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kLevelBlock = 256;
 constexpr int kFusedBlock = 1024;
 #ifndef GM_GATHER_BATCH
-#define GM_GATHER_BATCH 8
+#define GM_GATHER_BATCH 4
 #endif
 constexpr int kGatherBatch = GM_GATHER_BATCH;   // neighbour loads in flight per thread
 #ifndef GM_HEAVY_BATCH
@@ -782,7 +782,9 @@ template <int WORDS>
 void launch_level_words(int verts, dim3 grid, hipStream_t s, const MsbfsArgs &a, int level, int co, int light,
                         int per_group, int xcd)
 {
-    if (verts == 4)
+    if (verts == 8)
+        hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 8>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
+    else if (verts == 4)
         hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 4>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
     else if (verts == 2)
         hipLaunchKernelGGL((msbfs_level_kernel<WORDS, 2>), grid, dim3(kLevelBlock), 0, s, a, level, co, light, per_group, xcd);
@@ -815,7 +817,7 @@ hipError_t launch_msbfs_first(const MsbfsArgs &a, hipStream_t s)
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s)
 {
     const int64_t items = (int64_t)a.n * a.words;
-    const int verts = a.level_verts == 2 || a.level_verts == 4 ? a.level_verts : 1;
+    const int verts = a.level_verts == 2 || a.level_verts == 4 || a.level_verts == 8 ? a.level_verts : 1;
     const int light = (int)((items + (int64_t)kLevelBlock * verts - 1) / ((int64_t)kLevelBlock * verts));
     const int heavy = level >= 2 ? (a.n_heavy + kLevelBlock / GM_WAVE - 1) / (kLevelBlock / GM_WAVE) : 0;
     const int per_group = light + heavy;

@@ -92,10 +92,10 @@ def test_bitset_width_invariance(gumap, words, monkeypatch):
         _check_build(gumap, g, 10, sources=src, hop_matrix=False)
 
 
-@pytest.mark.parametrize("verts,first", [(1, "1"), (2, "1"), (4, "1"), (1, "0"), (2, "0")])
+@pytest.mark.parametrize("verts,first", [(1, "1"), (2, "1"), (4, "1"), (8, "1"), (1, "0"), (4, "0")])
 def test_level_items_per_thread_invariance(gumap, verts, first, monkeypatch):
     """The per-level BFS gives the oracle's rows whether a thread of its
-    level kernel takes 1, 2 or 4 (vertex, word) items, and whether level 1
+    level kernel takes 1, 2, 4 or 8 (vertex, word) items, and whether level 1
     runs as a fill plus a scatter from the sources or as a range scan in the
     level kernel: ragged vertex counts, hub vertices searched by whole waves,
     every bitset width."""
