@@ -229,7 +229,7 @@ FP64_PEAK_TFLOPS = 78.6
 
 def _roofline(prof, steps, dom):
     d = prof[dom]
-    if dom == "neighborhood":
+    if dom in ("neighborhood", "msbfs_stress"):
         # FP64 distance arithmetic against the vector FP64 peak; the counter
         # holds FP64 operations, not bytes
         achieved = d["alg_bytes"] / (d["total_ms"] / 1e3) / 1e12

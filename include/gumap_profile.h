@@ -6,7 +6,8 @@
  * HIP events recorded on the stream the kernel is launched on, and tagged
  * with the algorithmic bytes that launch moves (the bytes its traversal
  * must read and write, computed from the sizes and from the device-side
- * work counters of the BFS levels).  Timings are resolved when a call
+ * work counters of the BFS levels); for the FP64 kernels "neighborhood"
+ * and "msbfs_stress" the figure is their FP64 operation count instead.  Timings are resolved when a call
  * returns, so they cover exactly the calls made while enabled.  Not thread
  * safe against concurrent library calls from several threads.
  */

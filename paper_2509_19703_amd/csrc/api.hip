@@ -581,8 +581,13 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             sa.xy = (const float2 *)so->xy;
             if ((st = scratch_get(kSlotStressSum, parts * sizeof(double), (void **)&sa.part_sum))) return st;
             if ((st = scratch_get(kSlotStressPairs, parts * sizeof(unsigned int), (void **)&sa.part_pairs))) return st;
-            GM_PROF("msbfs_stress", (double)(planes_used + 1) * (double)arr * 8.0 + 8.0 * (double)n,
-                    launch_msbfs_stress(a, planes_used, sa, s));
+            // profiled by its FP64 work: about 10 operations per reachable pair
+            // (two differences, a sum of squares, the square root, the scaling
+            // by 1/h, 1 - x and the squared term added), set once the pair
+            // counts are read back
+            const int stress_mark = prof_begin("msbfs_stress", s);
+            e = launch_msbfs_stress(a, planes_used, sa, s);
+            prof_end(stress_mark, s, 0.0);
             if (e != hipSuccess) return hip_status(e, "stress");
             std::vector<double> hsum(parts);
             std::vector<unsigned int> hpairs(parts);
@@ -591,6 +596,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 e = hipMemcpyAsync(hpairs.data(), sa.part_pairs, parts * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_status(e, "stress sums");
+            double round_pairs = 0.0;
             for (int32_t ls = 0; ls < a.n_slots; ++ls) {
                 double rs = 0.0;
                 int64_t rp = 0;
@@ -601,7 +607,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 const int64_t m = all_sources ? 1 : h_mult[(size_t)a.slot0 + ls];
                 so->sum += rs * (double)m;
                 so->pairs += rp * m;
+                round_pairs += (double)rp;
             }
+            prof_set_bytes(stress_mark, 10.0 * round_pairs);
             continue;
         }
         const double hop_bytes = (double)(planes_used + 1) * (double)arr * 8.0 + (double)a.n_slots * n;
