@@ -1147,25 +1147,33 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
 {
     hipError_t e = launch_lanczos_start(a, c0, seed, s);
     if (e != hipSuccess) return hip_status(e, "lanczos start");
-    std::vector<double> ha((size_t)jmax + 2), hb((size_t)jmax + 2), ta, tb, zl;
+    // Every ten steps the coefficients so far are copied to one of two pinned
+    // buffers; a block is checked on the host only after the next block's
+    // steps are enqueued, so the GPU keeps working during the check.  Steps
+    // past the converged one only write basis columns and coefficients beyond
+    // it, which the Ritz vector does not read.
+    const size_t per = (size_t)jmax + 2;
+    void *hv = nullptr;
+    int st = host_scratch_get(4 * per * sizeof(double), &hv);
+    if (st) return st;
+    double *hbuf[2][2] = {{(double *)hv, (double *)hv + per}, {(double *)hv + 2 * per, (double *)hv + 3 * per}};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) {
+            if (ev[0]) (void)hipEventDestroy(ev[0]);
+            return hip_status(e, "lanczos events");
+        }
+    std::vector<double> ha(per), hb(per), ta, tb, zl;
     int m = 0, top = 0;
     bool converged = false;
-    for (int j = 1; j <= jmax; ++j) {
-        // the sparse product (CSR, degree scales, the vector gathered), the
-        // local recurrence and one pass over the basis (projections, update)
-        GM_PROF("lanczos_step", (double)nnz * 24.0 + (double)a.n * 120.0 + 2.0 * (double)(c0 + j) * (double)a.n * 8.0,
-                launch_lanczos_step(a, c0, j, s));
-        if (e != hipSuccess) return hip_status(e, "lanczos step");
-        if (j % 10 != 0 && j != jmax) continue;
-        e = hipMemcpyAsync(ha.data(), a.alpha, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hb.data(), a.beta, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_status(e, "lanczos coefficients");
+    // check of the coefficients of steps 1..jc: 1 converged, 0 not, -1 solver failure
+    auto check = [&](int jc, const double *ca, const double *cb) {
+        std::copy(ca, ca + jc + 1, ha.begin());
+        std::copy(cb, cb + jc + 1, hb.begin());
         // the recurrence stops at the first zero beta (the Krylov space is exhausted)
-        m = j;
+        m = jc;
         bool exhausted = false;
-        for (int q = 1; q <= j; ++q)
+        for (int q = 1; q <= jc; ++q)
             if (hb[q] == 0.0) {
                 m = q;
                 exhausted = true;
@@ -1174,16 +1182,46 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
         ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
         tb.assign(hb.begin() + 1, hb.begin() + m);
         zl.assign((size_t)m, 0.0);
-        if (!tridiag_eigen(m, ta.data(), tb.data(), nullptr, zl.data()))
-            return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
+        if (!tridiag_eigen(m, ta.data(), tb.data(), nullptr, zl.data())) return -1;
         top = 0;
         for (int q = 1; q < m; ++q)
             if (ta[q] > ta[top]) top = q;
-        if (exhausted || fabs(hb[m] * zl[top]) <= tol) {
-            converged = true;
-            break;
+        return (exhausted || fabs(hb[m] * zl[top]) <= tol) ? 1 : 0;
+    };
+    int pend_j = 0, pend = 0, cur = 0, r = 0;
+    for (int j = 1; j <= jmax && !converged && r >= 0; ++j) {
+        // the sparse product (CSR, degree scales, the vector gathered), the
+        // local recurrence and one pass over the basis (projections, update)
+        GM_PROF("lanczos_step", (double)nnz * 24.0 + (double)a.n * 120.0 + 2.0 * (double)(c0 + j) * (double)a.n * 8.0,
+                launch_lanczos_step(a, c0, j, s));
+        if (e != hipSuccess) break;
+        if (j % 10 != 0 && j != jmax) continue;
+        e = hipMemcpyAsync(hbuf[cur][0], a.alpha, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hbuf[cur][1], a.beta, (size_t)(j + 1) * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[cur], s);
+        if (e != hipSuccess) break;
+        if (pend_j) {
+            if ((e = hipEventSynchronize(ev[pend])) != hipSuccess) break;
+            r = check(pend_j, hbuf[pend][0], hbuf[pend][1]);
+            converged = r > 0;
+        }
+        pend_j = j;
+        pend = cur;
+        cur ^= 1;
+    }
+    if (e == hipSuccess && !converged && r >= 0 && pend_j) {
+        e = hipEventSynchronize(ev[pend]);
+        if (e == hipSuccess) {
+            r = check(pend_j, hbuf[pend][0], hbuf[pend][1]);
+            converged = r > 0;
         }
     }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // no copy into the pinned buffers outlives this call
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (e != hipSuccess) return hip_status(e, "lanczos step");
+    if (r < 0) return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
     if (!converged)
         return set_error(GUMAP_ERANGE, "the Lanczos iteration did not reach residual %g in %d steps", tol, jmax);
     ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
