@@ -85,13 +85,16 @@ sp_heavy_kernel(int32_t n, const int32_t *__restrict__ rp, int32_t *__restrict__
         if (rp[v + 1] - rp[v] > kSpHeavyRow) heavy[atomicAdd(count, 1)] = v;
 }
 
-// y = A x: blocks [0, heavy_blocks) take one heavy row each (block-wide
-// sum), the others kSpTeam lanes per remaining row.
+// y = A x (minus bprev[0] * xprev when xprev is not NULL: the first term of
+// the three-term recurrence): blocks [0, heavy_blocks) take one heavy row
+// each (block-wide sum), the others kSpTeam lanes per remaining row.
 __global__ void __launch_bounds__(kSpBlock)
 sp_spmv_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                const float *__restrict__ val, const double *__restrict__ sinv, const double *__restrict__ x,
-               double *__restrict__ y, const int32_t *__restrict__ heavy, int heavy_blocks)
+               double *__restrict__ y, const int32_t *__restrict__ heavy, int heavy_blocks,
+               const double *__restrict__ xprev, const double *__restrict__ bprev)
 {
+    const double fprev = xprev ? bprev[0] : 0.0;
     if ((int)blockIdx.x < heavy_blocks) {
         __shared__ double sh[kSpBlock / 64];
         const int32_t v = heavy[blockIdx.x];
@@ -101,7 +104,7 @@ sp_spmv_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restr
             acc += (double)val[e] * (sinv[c] * x[c]);
         }
         const double t = block_sum(acc, sh);
-        if (threadIdx.x == 0) y[v] = sinv[v] * t;
+        if (threadIdx.x == 0) y[v] = xprev ? sinv[v] * t - fprev * xprev[v] : sinv[v] * t;
         return;
     }
     const int32_t v = (int32_t)((((int64_t)blockIdx.x - heavy_blocks) * kSpBlock + threadIdx.x) / kSpTeam);
@@ -116,7 +119,7 @@ sp_spmv_kernel(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restr
             acc += (double)val[e] * (sinv[c] * x[c]);
         }
     for (int o = kSpTeam / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (mine && lane_t == 0) y[v] = sinv[v] * acc;
+    if (mine && lane_t == 0) y[v] = xprev ? sinv[v] * acc - fprev * xprev[v] : sinv[v] * acc;
 }
 
 // part[c * tiles + t] = sum over the rows of tile t of Q[:, c] * w, for
@@ -154,11 +157,25 @@ sp_gemvt_kernel(int32_t n, const double *__restrict__ Q, size_t ld, int ncols, c
     }
 }
 
-// w -= coef[0] * q
+// One-column projection finished and applied: s = the sum of the tiles'
+// partials of column 0 (each block sums them in the same order), h[0] =
+// hacc[0] = s, and w -= s * q.
 __global__ void __launch_bounds__(kSpBlock)
-sp_axpy_kernel(int32_t n, const double *__restrict__ q, const double *__restrict__ coef, double *__restrict__ w)
+sp_axpy_reduce_kernel(int32_t n, const double *__restrict__ q, const double *__restrict__ part, int tiles,
+                      double *__restrict__ h, double *__restrict__ hacc, double *__restrict__ w)
 {
-    const double f = coef[0];
+    __shared__ double sv;
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int t = 0; t < tiles; ++t) acc += part[t];
+        sv = acc;
+        if (blockIdx.x == 0) {
+            h[0] = acc;
+            hacc[0] = acc;
+        }
+    }
+    __syncthreads();
+    const double f = sv;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] -= f * q[i];
 }
 
@@ -227,6 +244,27 @@ __global__ void sp_norm_kernel(const double *__restrict__ part, int tiles, doubl
     for (int t = 0; t < tiles; ++t) s += part[t];
     const double r = sqrt(s);
     out[0] = r > tiny ? r : 0.0;
+}
+
+// The norm and the scaling in one launch: every block sums the tiles'
+// squared partials in the same order, r = sqrt(sum) (zero below `tiny`),
+// block 0 stores it to *out, and q = w / r (zero when r is zero).
+__global__ void __launch_bounds__(kSpBlock)
+sp_norm_scale_kernel(int32_t n, const double *w, const double *__restrict__ part, int tiles, double tiny,
+                     double *__restrict__ out, double *q)   // w may equal q
+{
+    __shared__ double rv;
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int t = 0; t < tiles; ++t) acc += part[t];
+        const double r0 = sqrt(acc);
+        rv = r0 > tiny ? r0 : 0.0;
+        if (blockIdx.x == 0) out[0] = rv;
+    }
+    __syncthreads();
+    const double r = rv;
+    const double f = r > 0.0 ? 1.0 / r : 0.0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) q[i] = w[i] * f;
 }
 
 __global__ void __launch_bounds__(kSpBlock)
@@ -381,27 +419,24 @@ hipError_t launch_lanczos_step(const SpectralArgs &a, int c0, int j, hipStream_t
     const int cj = c0 + j - 1;   // column of Lanczos vector j
     const double *qj = a.Q + (size_t)cj * a.ld;
     const int light_blocks = (int)(((int64_t)a.n * kSpTeam + kSpBlock - 1) / kSpBlock);
+    // the three-term recurrence first: w = A q[j] - beta[j-1] q[j-1] (in the
+    // sparse product), then w -= alpha q[j] with alpha = q[j] . w; what
+    // remains along the basis is rounding error, which one full projection
+    // pass removes
     hipLaunchKernelGGL(sp_spmv_kernel, dim3(a.heavy_rows + light_blocks), dim3(kSpBlock), 0, s, a.n, a.row_ptr, a.col,
-                       a.val, a.sinv, qj, a.w, a.heavy, a.heavy_rows);
-    // the three-term recurrence first: w -= beta[j-1] q[j-1], then w -= alpha q[j]
-    // with alpha = q[j] . w; what remains along the basis is rounding error,
-    // which one full projection pass removes
-    if (j > 1)
-        hipLaunchKernelGGL(sp_axpy_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, qj - a.ld, a.beta + j - 1,
-                           a.w);
+                       a.val, a.sinv, qj, a.w, a.heavy, a.heavy_rows, j > 1 ? qj - a.ld : (const double *)nullptr,
+                       a.beta + j - 1);
     hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, 1), dim3(kSpBlock), 0, s, a.n, qj, a.ld, 1, a.w, a.part, tiles);
-    hipLaunchKernelGGL(sp_reduce_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, 1, a.h, a.hacc, 0, -1,
-                       (double *)nullptr);
-    hipLaunchKernelGGL(sp_axpy_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, qj, a.h, a.w);
+    hipLaunchKernelGGL(sp_axpy_reduce_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, qj, a.part, tiles, a.h,
+                       a.hacc, a.w);
     hipLaunchKernelGGL(sp_gemvt_kernel, dim3(tiles, (cj + 1 + kSpCols - 1) / kSpCols), dim3(kSpBlock), 0, s, a.n, a.Q,
                        a.ld, cj + 1, a.w, a.part, tiles);
     hipLaunchKernelGGL(sp_reduce_full_kernel, dim3(1), dim3(kSpBlock), 0, s, a.part, tiles, cj + 1, a.h, cj,
                        a.alpha + j);
     hipLaunchKernelGGL(sp_gemv_sub_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.Q, a.ld, cj + 1, a.h, a.w);
     hipLaunchKernelGGL(sp_sumsq_kernel, dim3(tiles), dim3(kSpBlock), 0, s, a.n, a.w, a.part);
-    hipLaunchKernelGGL(sp_norm_kernel, dim3(1), dim3(64), 0, s, a.part, tiles, a.tiny, a.beta + j);
-    hipLaunchKernelGGL(sp_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.w, a.beta + j,
-                       a.Q + (size_t)(cj + 1) * a.ld);
+    hipLaunchKernelGGL(sp_norm_scale_kernel, dim3(sp_grid(a.n)), dim3(kSpBlock), 0, s, a.n, a.w, a.part, tiles, a.tiny,
+                       a.beta + j, a.Q + (size_t)(cj + 1) * a.ld);
     return hipGetLastError();
 }
 
