@@ -30,7 +30,7 @@ namespace gm {
 namespace {
 
 constexpr int kSpBlock = 256;
-constexpr int kSpTile = 4096;   // rows per partial sum
+constexpr int kSpTile = 2048;   // rows per partial sum
 
 __device__ __forceinline__ uint64_t sp_splitmix64(uint64_t seed, uint64_t i)
 {
@@ -219,6 +219,7 @@ sp_gemv_sub_kernel(int32_t n, const double *__restrict__ Q, size_t ld, int ncols
 {
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double acc = 0.0;
+#pragma unroll 8
         for (int c = 0; c < ncols; ++c) acc += Q[(size_t)c * ld + i] * h[c];
         w[i] -= acc;
     }
