@@ -11,9 +11,12 @@
 // into `visited` and the bit-planes (the commit is lazy so one launch per
 // level suffices), then finds the level-L bits bottom-up: a vertex ORs the
 // frontier words of its neighbours, stopping as soon as every source that has
-// not reached it yet is covered.  Level 1 needs no frontier read: a vertex
-// scans the part of its sorted adjacency that falls in the id range of each
-// 64-source word and sets the bits of the sources it finds.
+// not reached it yet is covered.  Level 1 needs no frontier read: on sparse
+// graphs a fill stores each vertex's own source bits as visited and a wave
+// per source ORs its bit into its neighbours' frontier words; on dense ones
+// a vertex scans the part of its sorted adjacency that falls in the id range
+// of each 64-source word and sets the bits of the sources it finds.  Either
+// way level 1 stores every visited word, so no state is cleared first.
 // After the last level a transpose kernel turns the vertex-major bit-planes
 // into source-major uint8 hop rows, 64 x 64 bits per wave through shuffle
 // butterflies, and counts how many vertices each source reached at hops
