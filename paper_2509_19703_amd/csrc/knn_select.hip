@@ -236,44 +236,72 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
     __shared__ int32_t list[kSelWaves][kMaxChunks];
     const int wid = threadIdx.x / GM_WAVE, l = lane();
     for (int32_t r = blockIdx.x * kSelWaves + wid; r < rows; r += gridDim.x * kSelWaves) {
-        // sum the per-block partial counts: lane = (chunk phase, level)
-        const int h = l & 15;
-        unsigned int sum = 0;
-        for (int32_t cc = l >> 4; cc < chunks; cc += 4) sum += part[((size_t)r * chunks + cc) * kCountLevels + h];
-        sum += __shfl_xor(sum, 16, GM_WAVE);
-        sum += __shfl_xor(sum, 32, GM_WAVE);
-        if (l < kCountLevels) cnt[wid][l + 1] = sum;
-        wave_sync();
-        // last level h* and the number of its vertices taken (as in select_row)
-        int c = 0, hstar = kCountLevels + 1, need = 0;
-        for (int hh = 1; hh <= kCountLevels; ++hh) {
-            const int ch = (int)cnt[wid][hh];
-            if (c + ch >= k) {
-                hstar = hh;
-                need = k - c;
-                break;
+        // each lane loads the 16 per-level counts of its chunks (l, l + 64,
+        // ...) once, summing them per level; its first chunk's stay in registers
+        unsigned int my[kCountLevels], lsum[kCountLevels];
+#pragma unroll
+        for (int h = 0; h < kCountLevels; ++h) my[h] = lsum[h] = 0;
+        for (int32_t cc = l; cc < chunks; cc += GM_WAVE) {
+            const uint4 *p = (const uint4 *)(part + ((size_t)r * chunks + cc) * kCountLevels);
+#pragma unroll
+            for (int i = 0; i < kCountLevels / 4; ++i) {
+                const uint4 x = p[i];
+                const unsigned int xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    lsum[4 * i + j] += xs[j];
+                    if (cc == l) my[4 * i + j] = xs[j];
+                }
             }
-            c += ch;
+        }
+        // per-level totals, level by level until the k-th vertex is reached:
+        // the last level h* and the number of its vertices taken (cnt[1..h*]
+        // for select_row, which stops at the same level)
+        int c = 0, hstar = kCountLevels + 1, need = 0;
+        bool found = false;
+#pragma unroll
+        for (int hh = 1; hh <= kCountLevels; ++hh) {
+            if (!found) {
+                const int ch = wave_sum((int)lsum[hh - 1]);
+                if (l == 0) cnt[wid][hh] = (unsigned int)ch;
+                if (c + ch >= k) {
+                    hstar = hh;
+                    need = k - c;
+                    found = true;
+                } else {
+                    c += ch;
+                }
+            }
         }
         // chunks holding a vertex with hop < h*, or one of the first `need`
         // vertices at hop h* (eq counts scanned in chunk order), in order
         int nlist = 0, eq_carry = 0;
         for (int32_t c0 = 0; c0 < chunks; c0 += GM_WAVE) {
             const int32_t cc = c0 + l;
-            int lt_c = 0, eq_c = 0;
-            if (cc < chunks) {
-                const uint4 *p = (const uint4 *)(part + ((size_t)r * chunks + cc) * kCountLevels);
+            unsigned int v[kCountLevels];
+            if (c0 == 0) {
 #pragma unroll
-                for (int i = 0; i < kCountLevels / 4; ++i) {
-                    const uint4 x = p[i];
-                    const unsigned int xs[4] = {x.x, x.y, x.z, x.w};
+                for (int h = 0; h < kCountLevels; ++h) v[h] = my[h];
+            } else {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int hh = 4 * i + j + 1;
-                        if (hh < hstar) lt_c += (int)xs[j];
-                        else if (hh == hstar) eq_c = (int)xs[j];
+                for (int h = 0; h < kCountLevels; ++h) v[h] = 0;
+                if (cc < chunks) {
+                    const uint4 *p = (const uint4 *)(part + ((size_t)r * chunks + cc) * kCountLevels);
+#pragma unroll
+                    for (int i = 0; i < kCountLevels / 4; ++i) {
+                        const uint4 x = p[i];
+                        v[4 * i] = x.x;
+                        v[4 * i + 1] = x.y;
+                        v[4 * i + 2] = x.z;
+                        v[4 * i + 3] = x.w;
                     }
                 }
+            }
+            int lt_c = 0, eq_c = 0;
+#pragma unroll
+            for (int h = 0; h < kCountLevels; ++h) {
+                if (h + 1 < hstar) lt_c += (int)v[h];
+                else if (h + 1 == hstar) eq_c = (int)v[h];
             }
             const int incl = wave_incl_scan(eq_c);
             const bool needed = cc < chunks && (lt_c > 0 || (eq_c > 0 && eq_carry + incl - eq_c < need));
