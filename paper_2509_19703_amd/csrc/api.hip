@@ -1163,10 +1163,12 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
             if (ev[0]) (void)hipEventDestroy(ev[0]);
             return hip_status(e, "lanczos events");
         }
-    std::vector<double> ha(per), hb(per), ta, tb, zl;
-    int m = 0, top = 0;
+    std::vector<double> ha(per), hb(per), zv(per);
+    int m = 0;
+    double theta = 0.0;
     bool converged = false;
-    // check of the coefficients of steps 1..jc: 1 converged, 0 not, -1 solver failure
+    // check of the coefficients of steps 1..jc: 1 converged, 0 not, -1 solver
+    // failure; leaves the top Ritz value theta and its coefficients zv[0..m)
     auto check = [&](int jc, const double *ca, const double *cb) {
         std::copy(ca, ca + jc + 1, ha.begin());
         std::copy(cb, cb + jc + 1, hb.begin());
@@ -1179,14 +1181,11 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
                 exhausted = true;
                 break;
             }
-        ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
-        tb.assign(hb.begin() + 1, hb.begin() + m);
-        zl.assign((size_t)m, 0.0);
-        if (!tridiag_eigen(m, ta.data(), tb.data(), nullptr, zl.data())) return -1;
-        top = 0;
-        for (int q = 1; q < m; ++q)
-            if (ta[q] > ta[top]) top = q;
-        return (exhausted || fabs(hb[m] * zl[top]) <= tol) ? 1 : 0;
+        // the largest eigenvalue of the recurrence matrix and its eigenvector
+        // (bisection and inverse iteration, O(m)); its residual in A is
+        // |beta_m| times the eigenvector's last component
+        if (!tridiag_top(m, ha.data() + 1, hb.data() + 1, &theta, zv.data())) return -1;
+        return (exhausted || fabs(hb[m] * zv[m - 1]) <= tol) ? 1 : 0;
     };
     int pend_j = 0, pend = 0, cur = 0, r = 0;
     for (int j = 1; j <= jmax && !converged && r >= 0; ++j) {
@@ -1221,24 +1220,15 @@ int lanczos_run(const SpectralArgs &a, int64_t nnz, int c0, int jmax, double tol
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (e != hipSuccess) return hip_status(e, "lanczos step");
-    if (r < 0) return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
+    if (r < 0) return set_error(GUMAP_EDEVICE, "tridiagonal eigenvector solve failed");
     if (!converged)
         return set_error(GUMAP_ERANGE, "the Lanczos iteration did not reach residual %g in %d steps", tol, jmax);
-    ta.assign(ha.begin() + 1, ha.begin() + 1 + m);
-    tb.assign(hb.begin() + 1, hb.begin() + m);
-    std::vector<double> Z((size_t)m * m);
-    if (!tridiag_eigen(m, ta.data(), tb.data(), Z.data(), nullptr))
-        return set_error(GUMAP_EDEVICE, "tridiagonal eigensolver did not converge");
-    top = 0;
-    for (int q = 1; q < m; ++q)
-        if (ta[q] > ta[top]) top = q;
-    std::vector<double> sv((size_t)m);
-    for (int c = 0; c < m; ++c) sv[c] = Z[(size_t)c * m + top];
-    e = hipMemcpyAsync(svec, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);   // sv lives in this frame
+    // the converged check's eigenvector gives the Ritz vector's coefficients
+    e = hipMemcpyAsync(svec, zv.data(), (size_t)m * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // zv lives in this frame
     if (e == hipSuccess) e = launch_ritz_vector(a, c0, m, svec, k, s);
     if (e != hipSuccess) return hip_status(e, "ritz vector");
-    *lambda = 1.0 - ta[top];
+    *lambda = 1.0 - theta;
     *steps += m;
     return GUMAP_OK;
 }

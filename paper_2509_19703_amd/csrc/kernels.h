@@ -294,8 +294,9 @@ hipError_t launch_ritz_deflate(const SpectralArgs &a, int k, int col, hipStream_
 // The two columns of X normalised, signed and scaled into xy (float, x y
 // per vertex); first: two ints set to INT32_MAX beforehand.
 hipError_t launch_spectral_finish(const SpectralArgs &a, int *first, float *xy, hipStream_t s);
-// Host: eigen-decomposition of a symmetric tridiagonal matrix (see spectral.hip).
-bool tridiag_eigen(int m, double *a, double *b, double *Z, double *zlast);
+// Host: largest eigenvalue of a symmetric tridiagonal matrix (diagonal a[0..m),
+// off-diagonal b[0..m-1)) and its unit eigenvector z[0..m); false on failure.
+bool tridiag_top(int m, const double *a, const double *b, double *theta, double *z);
 
 // ----------------------------------------------- spectral sparsification ---
 struct SparsifyArgs {

@@ -14,12 +14,15 @@
 // column 0 = D^1/2 1 normalised, converges the top eigenpair; the second
 // also deflates that eigenvector (column 1) and converges the next, so that
 // a repeated eigenvalue (a cycle's, a complete graph's) still yields two
-// orthogonal eigenvectors, which one Krylov sequence cannot.  The small tridiagonal matrix
-// of the recurrence is diagonalised on the host by implicit QR steps with
-// Wilkinson shifts.  Partial sums are reduced in a fixed order, so a run is
-// reproducible.
+// orthogonal eigenvectors, which one Krylov sequence cannot.  Only the top
+// eigenpair of the small tridiagonal matrix of the recurrence is needed; the
+// host finds it by bisection on Sturm counts and inverse iteration, in O(m).
+// Partial sums are reduced in a fixed order, so a run is reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
+#include <cmath>
 #include <stdint.h>
 
 #include <vector>
@@ -471,62 +474,100 @@ hipError_t launch_spectral_finish(const SpectralArgs &a, int *first, float *xy, 
 }
 
 // ------------------------------------------------------------ host side --
-// Eigen-decomposition of the symmetric tridiagonal matrix with diagonal
-// a[0..m) and off-diagonal b[0..m-1) (b[i] couples i and i + 1) by implicit
-// QR steps with Wilkinson shifts (Golub and Van Loan, Matrix Computations,
-// the symmetric QR algorithm).  On return a holds the eigenvalues; if Z is
-// not NULL (m x m, row-major, set to the identity here) its columns are the
-// eigenvectors; if zlast is not NULL it receives the last row of that
-// matrix (only that row is updated, O(m) per rotation).
-bool tridiag_eigen(int m, double *a, double *b, double *Z, double *zlast)
+// Largest eigenvalue theta of the symmetric tridiagonal matrix T with
+// diagonal a[0..m) and off-diagonal b[0..m-1), and its unit eigenvector z:
+// theta by bisection on Sturm counts (the number of negative pivots of
+// T - x I counts the eigenvalues below x), z by inverse iteration (three
+// solves of (T - theta I) x = y with partial pivoting).  O(m) work per
+// bisection step and per solve.
+bool tridiag_top(int m, const double *a, const double *b, double *theta, double *z)
 {
-    if (Z)
-        for (int i = 0; i < m; ++i)
-            for (int k = 0; k < m; ++k) Z[(size_t)i * m + k] = i == k ? 1.0 : 0.0;
-    if (zlast)
-        for (int k = 0; k < m; ++k) zlast[k] = k == m - 1 ? 1.0 : 0.0;
+    if (m < 1) return false;
+    if (m == 1) {
+        *theta = a[0];
+        z[0] = 1.0;
+        return true;
+    }
     const double eps = 2.220446049250313e-16;
-    int hi = m - 1, iters = 0;
-    while (hi > 0) {
-        if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
-            b[hi - 1] = 0.0;
-            --hi;
-            iters = 0;
-            continue;
+    double lo = a[0], hi = a[0], bmax2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+        if (i + 1 < m) bmax2 = std::max(bmax2, b[i] * b[i]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * std::max(1.0, bmax2);
+    auto below = [&](double x) {   // eigenvalues < x
+        int cnt = 0;
+        double q = a[0] - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++cnt;
+        for (int i = 1; i < m; ++i) {
+            q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+            if (fabs(q) < pivmin) q = -pivmin;
+            if (q < 0.0) ++cnt;
         }
-        if (++iters > 60) return false;
-        int lo = hi - 1;
-        while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
-        // shift: the eigenvalue of the trailing 2 x 2 block closer to a[hi]
-        const double d = 0.5 * (a[hi - 1] - a[hi]);
-        const double bb = b[hi - 1] * b[hi - 1];
-        const double mu = a[hi] - bb / (d + (d >= 0.0 ? 1.0 : -1.0) * sqrt(d * d + bb));
-        double x = a[lo] - mu, z = b[lo];
-        for (int k = lo; k < hi; ++k) {
-            const double r = hypot(x, z);
-            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
-            if (k > lo) b[k - 1] = r;
-            const double ak = a[k], ak1 = a[k + 1], bk = b[k];
-            a[k] = c * c * ak + 2.0 * c * s * bk + s * s * ak1;
-            a[k + 1] = s * s * ak - 2.0 * c * s * bk + c * c * ak1;
-            b[k] = c * s * (ak1 - ak) + (c * c - s * s) * bk;
-            if (k + 1 < hi) {
-                x = b[k];
-                z = s * b[k + 1];
-                b[k + 1] *= c;
-            }
-            if (Z)
-                for (int i = 0; i < m; ++i) {
-                    const double zk = Z[(size_t)i * m + k], zk1 = Z[(size_t)i * m + k + 1];
-                    Z[(size_t)i * m + k] = c * zk + s * zk1;
-                    Z[(size_t)i * m + k + 1] = -s * zk + c * zk1;
-                }
-            if (zlast) {
-                const double zk = zlast[k], zk1 = zlast[k + 1];
-                zlast[k] = c * zk + s * zk1;
-                zlast[k + 1] = -s * zk + c * zk1;
-            }
+        return cnt;
+    };
+    // below(x) == m exactly when x is above the largest eigenvalue
+    for (int it = 0; it < 256; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi || hi - lo <= 2.0 * eps * std::max(fabs(lo), fabs(hi))) break;
+        if (below(mid) == m) hi = mid;
+        else lo = mid;
+    }
+    const double t = 0.5 * (lo + hi);
+    *theta = t;
+    // LU of T - t I with partial pivoting: d (diagonal), du, du2 (first and
+    // second superdiagonals of U), l (multipliers), sw (row i swapped with i + 1)
+    double anorm = 0.0;
+    for (int i = 0; i < m; ++i) anorm = std::max(anorm, fabs(a[i] - t) + (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0));
+    const double tiny = std::max(eps * anorm, pivmin);
+    std::vector<double> d(m), du(m, 0.0), du2(m, 0.0), l(m, 0.0), y(m);
+    std::vector<char> sw(m, 0);
+    for (int i = 0; i < m; ++i) d[i] = a[i] - t;
+    for (int i = 0; i + 1 < m; ++i) du[i] = b[i];
+    for (int i = 0; i + 1 < m; ++i) {
+        const double sub = b[i];   // row i + 1, column i
+        if (fabs(d[i]) >= fabs(sub)) {
+            if (d[i] == 0.0) d[i] = tiny;
+            const double f = sub / d[i];
+            l[i] = f;
+            d[i + 1] -= f * du[i];
+        } else {
+            // rows i and i + 1 exchanged, then column i eliminated from the new row i + 1
+            const double f = d[i] / sub;
+            const double di1 = d[i + 1], dui = du[i], dui1 = i + 2 < m ? du[i + 1] : 0.0;
+            d[i] = sub;
+            du[i] = di1;
+            du2[i] = dui1;
+            d[i + 1] = dui - f * di1;
+            if (i + 2 < m) du[i + 1] = -f * dui1;
+            l[i] = f;
+            sw[i] = 1;
         }
+    }
+    for (int i = 0; i < m; ++i)
+        if (fabs(d[i]) < tiny) d[i] = d[i] < 0.0 ? -tiny : tiny;
+    // start vector with components of both signs' weights spread over the rows
+    for (int i = 0; i < m; ++i) z[i] = 1.0 + 0.25 * (double)(i % 7);
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int i = 0; i < m; ++i) y[i] = z[i];
+        for (int i = 0; i + 1 < m; ++i) {
+            if (sw[i]) std::swap(y[i], y[i + 1]);
+            y[i + 1] -= l[i] * y[i];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double v = y[i];
+            if (i + 1 < m) v -= du[i] * z[i + 1];
+            if (i + 2 < m) v -= du2[i] * z[i + 2];
+            z[i] = v / d[i];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
+        nrm = sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+        for (int i = 0; i < m; ++i) z[i] /= nrm;
     }
     return true;
 }
