@@ -62,8 +62,8 @@ def main():
         write_traffic(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(one GPU's share of the work is what it runs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
