@@ -78,7 +78,8 @@ typedef struct gumap_graph {
  * removed.  The other calls do this themselves unless GUMAP_CSR_SORTED is
  * set; calling it once lets a caller pass the result with that flag.
  *   out_row_ptr device int32[n + 1]; out_col_idx device int32[g->nnz]
- *   (capacity); *out_nnz (host) receives the kept entry count.
+ *   (capacity); *out_nnz (host) receives the kept entry count.  The
+ *   outputs must not overlap the input arrays.
  * Errors: GUMAP_EINVAL, GUMAP_EGRAPH (with GUMAP_VALIDATE), GUMAP_ENOMEM,
  *         GUMAP_EDEVICE.
  */

@@ -322,10 +322,22 @@ canon_huge_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t 
     }
 }
 
-__global__ void canon_copy_kernel(int32_t n, const int32_t *__restrict__ row_ptr_in,
+// The sorted rows are written to col_out at the input offsets.  When every
+// entry was kept (the scanned total equals nnz) that already is the output;
+// otherwise they are staged to tmp and compacted back into col_out.
+__global__ void canon_stage_kernel(int32_t nnz, const int32_t *__restrict__ row_ptr_out, int32_t n,
+                                   const int32_t *__restrict__ col_out, int32_t *__restrict__ tmp)
+{
+    if (row_ptr_out[n] == nnz) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x)
+        tmp[i] = col_out[i];
+}
+
+__global__ void canon_copy_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr_in,
                                   const int32_t *__restrict__ tmp, const int32_t *__restrict__ row_ptr_out,
                                   int32_t *__restrict__ col_out)
 {
+    if (row_ptr_out[n] == nnz) return;
     const int waves = blockDim.x / GM_WAVE;
     for (int64_t v = (int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE; v < n;
          v += (int64_t)gridDim.x * waves) {
@@ -497,10 +509,11 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
         return hipGetLastError();
     }
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)2, 0);
+    // rows are sorted straight into out_col at the input offsets
     hipLaunchKernelGGL(canon_tiny_kernel, dim3(grid_for((n + 3) / 4, kCanonBlock / GM_WAVE, 32768)),
-                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, tmp, cnt);
+                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, out_col, cnt);
     hipLaunchKernelGGL(canon_rows_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 32768)),
-                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, tmp, cnt, big, counters, huge,
+                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, out_col, cnt, big, counters, huge,
                        counters + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -513,16 +526,18 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
         lds_set = true;
     }
     hipLaunchKernelGGL(canon_big_kernel, dim3(512), dim3(kBigBlock), big_lds, s, row_ptr, col_idx,
-                       tmp, cnt, big, counters);
+                       out_col, cnt, big, counters);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(canon_huge_kernel, dim3(kHugeBlocks), dim3(kBigBlock), 0, s, n, row_ptr,
-                       col_idx, tmp, cnt, huge, counters + 1, bitmaps);
+                       col_idx, out_col, cnt, huge, counters + 1, bitmaps);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_exclusive_scan(cnt, out_row_ptr, n, scan_scratch, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(canon_copy_kernel, dim3(grid_for(n, 4, 32768)), dim3(256), 0, s, n, row_ptr,
+    hipLaunchKernelGGL(canon_stage_kernel, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, nnz, out_row_ptr, n,
+                       out_col, tmp);
+    hipLaunchKernelGGL(canon_copy_kernel, dim3(grid_for(n, 4, 32768)), dim3(256), 0, s, n, nnz, row_ptr,
                        tmp, out_row_ptr, out_col);
     return hipGetLastError();
 }
