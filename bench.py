@@ -305,7 +305,7 @@ def bench_allsource(args):
 
 
 def bench_stress(args):
-    """Aggregated stress (Sec. 5.1) of a seeded random drawing of the BA graph
+    """Aggregated stress (Sec. 4.1.3) of a seeded random drawing of the BA graph
     over all ordered vertex pairs: the all-source BFS from every vertex with
     the stress terms folded into its hop-row pass."""
     import numpy as np
@@ -361,7 +361,7 @@ def bench_stress(args):
 
 
 def bench_neighborhood(args):
-    """Neighbourhood preservation (Sec. 5.1, r = 2) of a seeded random drawing
+    """Neighbourhood preservation (Sec. 4.1.3, r = 2) of a seeded random drawing
     of the BA graph, scored for its 4,096 sampled vertices."""
     import numpy as np
     import torch

@@ -103,7 +103,7 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
                     int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream);
 
 /*
- * Aggregated stress of a drawing (Sec. 5.1 quality metrics): the sum over
+ * Aggregated stress of a drawing (Sec. 4.1.3 quality metrics): the sum over
  * ordered pairs (s, v), s in `sources` (every vertex when sources is NULL;
  * a source listed twice counts twice) and v != s reachable from s, of
  * ((d(s,v) - |X_s - X_v|) / d(s,v))^2, with d the hop distance of the graph
@@ -123,7 +123,7 @@ int gumap_stress(const gumap_graph *g, const float *xy, const int32_t *sources, 
                  double *sum, int64_t *pairs, hipStream_t stream);
 
 /*
- * Neighbourhood preservation of a drawing (Sec. 5.1 quality metrics), per
+ * Neighbourhood preservation of a drawing (Sec. 4.1.3 quality metrics), per
  * vertex: the Jaccard index |N_G & N_D| / |N_G | N_D| of the graph ball
  * N_G(v, r) (vertices u != v within r hops) and N_D(v, r), the |N_G(v, r)|
  * vertices u != v nearest to v in the drawing, ranked by squared Euclidean
@@ -298,7 +298,12 @@ typedef struct {
     int32_t neg;       /* negative samples per edge (>= 0) */
     int32_t t;         /* iterations of the whole run (>= 1) */
     uint64_t seed;     /* seed of the negative samples */
+    int32_t parts;     /* synchronous parts per window (>= 0; 0 = GUMAP_LAYOUT_DEFAULT_PARTS) */
+    int32_t pad;
 } gumap_layout_params;
+
+/* Default number of synchronous parts of a GradSample window. */
+#define GUMAP_LAYOUT_DEFAULT_PARTS 4
 
 /*
  * gumap_grad_sample: iterations [it_begin, it_end) of a t-iteration
@@ -313,19 +318,29 @@ typedef struct {
  *                skipped when v = a; with E = X_a - X_v, e2 = |E|^2:
  *                g = clip(c E, -4, 4), c = 2 gamma beta / ((0.001 + e2)(1 + alpha e2^beta)),
  *                or g = (4, 4) when e2 = 0; X_a += lr h g.
- * All moves of an iteration are computed from the positions at its start
- * and added afterwards (a synchronous window).  Positions are kept in fixed
- * point (round(X * 2^32) in int64) during the call and every move is rounded
- * to that grid, so results do not depend on thread scheduling; xy is read at
- * the start and written at the end.  FP64 arithmetic throughout.  Splitting
- * a run into several calls over consecutive iteration ranges gives the
- * same drawing as one call, up to the rounding of xy to float between calls.
+ * Alg. 5 (Sec. 3.3.2) takes the window's entries one after the other, each
+ * reading the coordinates as moved by the entries before it.  Here the window
+ * is cut into P = min(parts, s) consecutive parts (entries l in
+ * [c s / P, (c + 1) s / P), c = 0..P-1) that are applied one after the
+ * other; within a part the entries are applied at once: each entry starts
+ * from the positions at the start of its part and takes its own steps in
+ * Alg. 5's order on its private copy of its vertices (attraction on a and b,
+ * then each negative sample from the moved X_a, reading the moved X_b when
+ * v = b), and the part's moves are added afterwards.  Where no two entries
+ * of a part share a vertex (negative samples included) this is exactly the
+ * serial order; otherwise it is a synchronous approximation of it, closer
+ * the more parts.  Positions are kept in fixed point (round(X * 2^32) in
+ * int64) during the call and every move is rounded to that grid, so results
+ * do not depend on thread scheduling; xy is read at the start and written at
+ * the end.  FP64 arithmetic throughout.  Splitting a run into several calls
+ * over consecutive iteration ranges gives the same drawing as one call, up
+ * to the rounding of xy to float between calls.
  *   n               vertices;  xy device float[2 n] (in/out): x, y of vertex v
  *                   at xy[2v], xy[2v + 1], each of magnitude below 2^20
  *   m, head, tail, w  the shuffled edge array (gumap_edge_shuffle's output)
  *   p               parameters (host)
  * Errors: GUMAP_EINVAL (NULL pointer, n < 0, m < 0, m >= 2^30, m > 0 with n = 0,
- * window outside [1, m], neg < 0, t < 1, iteration range outside [0, t],
+ * window outside [1, m], neg < 0, t < 1, parts < 0, iteration range outside [0, t],
  * an endpoint outside [0, n), a coordinate out of range), GUMAP_ENOMEM,
  * GUMAP_EDEVICE.
  */

@@ -2,17 +2,22 @@
 
 Plain, slow, obviously correct CPU statement of the BFS kNN construction of
 arXiv 2509.19703 (GUMAP steps C0/C1 of Alg. 1, PartialBFS of Alg. 4 in
-Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1) and of the drawing
-quality metrics of Sec. 5.1 computed on the same BFS, and of the layout step C2
+Sec. 3.3.1, and the UMAP fuzzy membership of Sec. 2.1), of the drawing
+quality metrics of Sec. 4.1.3 computed on the same BFS, of the layout step C2
 that follows (fuzzy union of the kNN weights, edge shuffle and the sliding
-window GradSample of Alg. 5) and its spectral initial drawing (dense
-eigendecomposition, in this module), and the spectral sparsification
-front end (effective resistances by random projection and conjugate
-gradients, the maximum spanning forest and the top edges, in this module).  Only ``tests/``,
-``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
-it.  It shares no code with the GPU library and the GPU library never calls
-it.  The arithmetic lives in ``oracle.c`` (plain C, gcc); this module only
-moves numpy arrays in and out.
+window GradSample of Alg. 5, Sec. 3.3.2), of its spectral initial drawing and
+of the spectral sparsification front end (Sec. 3.2, Alg. 2).  Only
+``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may use it.  It shares no code with the GPU library and the GPU
+library never calls it.
+
+Where the arithmetic lives: ``oracle.c`` (plain C, gcc) holds the BFS, kNN,
+partial BFS, membership, stress, neighbourhood preservation, SplitMix64,
+fuzzy union, edge shuffle and GradSample; this module only moves numpy arrays
+in and out of those.  Three oracles are numpy code in this module:
+``spectral_layout`` (a dense eigendecomposition), ``effective_resistance``
+(random projection with preconditioned conjugate gradients) and
+``sparsify_select`` (maximum spanning forest and the top remaining edges).
 """
 from __future__ import annotations
 
@@ -61,7 +66,9 @@ def _load():
         d = ctypes.c_double
         lib.oracle_grad_sample.argtypes = [i32, i64, vp, vp, vp, vp, d, d, d, d, i64, i32, i32, ctypes.c_uint64,
                                            i32, i32, vp]
-        for f in (lib.oracle_fuzzy_union, lib.oracle_edge_shuffle, lib.oracle_grad_sample):
+        lib.oracle_grad_sample_window.argtypes = lib.oracle_grad_sample.argtypes + [i32]
+        for f in (lib.oracle_fuzzy_union, lib.oracle_edge_shuffle, lib.oracle_grad_sample,
+                  lib.oracle_grad_sample_window):
             f.restype = ctypes.c_int
         for f in (lib.oracle_bfs_dist, lib.oracle_knn_build, lib.oracle_knn_partial, lib.oracle_membership,
                   lib.oracle_stress, lib.oracle_neighborhood):
@@ -149,7 +156,7 @@ def membership(hops: np.ndarray, k: int | None = None, threads: int | None = Non
 
 
 def stress_rows(g, xy: np.ndarray, sources=None, threads: int | None = None):
-    """Per-source stress sums and pair counts (Sec. 5.1 aggregated stress).
+    """Per-source stress sums and pair counts (Sec. 4.1.3 aggregated stress).
 
     ``xy`` is float32 [n, 2].  Returns ``(row_sum float64[rows], row_pairs int64[rows])``."""
     rp, ci = _csr(g)
@@ -172,7 +179,7 @@ def stress(g, xy: np.ndarray, sources=None, threads: int | None = None):
 
 
 def neighborhood_scores(g, xy: np.ndarray, r: int = 2, vertices=None, threads: int | None = None):
-    """Per-vertex neighbourhood preservation (Sec. 5.1) of the listed vertices
+    """Per-vertex neighbourhood preservation (Sec. 4.1.3) of the listed vertices
     (all when None): ``(score float64[rows] (NaN where the graph ball is
     empty), ball int32[rows])``."""
     rp, ci = _csr(g)
@@ -238,13 +245,8 @@ def edge_shuffle(row_ptr: np.ndarray, col: np.ndarray, val: np.ndarray, seed: in
     return head[:m], tail[:m], w[:m]
 
 
-def grad_sample(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, gamma: float = 1.0,
-                alpha0: float = 1.0, window: int, neg: int = 5, t: int, seed: int, it_begin: int = 0,
-                it_end: int | None = None, visits: bool = False):
-    """GradSample (Alg. 5) iterations [it_begin, it_end) of a run of ``t``.
-
-    Returns the new float32[n, 2] drawing (and the per-position visit counts
-    when ``visits``)."""
+def _grad_call(fn, n, head, tail, w, xy, a, b, gamma, alpha0, window, neg, t, seed, it_begin, it_end, visits,
+               *extra):
     head = np.ascontiguousarray(head, dtype=np.int32)
     tail = np.ascontiguousarray(tail, dtype=np.int32)
     w = np.ascontiguousarray(w, dtype=np.float32)
@@ -252,15 +254,39 @@ def grad_sample(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, ga
     m = int(head.shape[0])
     vis = np.zeros(max(m, 1), dtype=np.int32) if visits else None
     it_end = t if it_end is None else it_end
-    st = _load().oracle_grad_sample(int(n), m, _ptr(head), _ptr(tail), _ptr(w), _ptr(out), float(a), float(b),
-                                    float(gamma), float(alpha0), int(window), int(neg), int(t),
-                                    ctypes.c_uint64(seed & (2**64 - 1)), int(it_begin), int(it_end), _ptr(vis))
+    st = fn(int(n), m, _ptr(head), _ptr(tail), _ptr(w), _ptr(out), float(a), float(b), float(gamma), float(alpha0),
+            int(window), int(neg), int(t), ctypes.c_uint64(seed & (2**64 - 1)), int(it_begin), int(it_end),
+            _ptr(vis), *extra)
     if st:
         raise OracleError(st)
     return (out, vis[:m]) if visits else out
 
 
-# ------------------------------------------------------ spectral layout ---
+def grad_sample(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, gamma: float = 1.0,
+                alpha0: float = 1.0, window: int, neg: int = 5, t: int, seed: int, it_begin: int = 0,
+                it_end: int | None = None, visits: bool = False):
+    """GradSample (Alg. 5, Sec. 3.3.2) iterations [it_begin, it_end) of a run
+    of ``t``, entries moved one after the other in the paper's order (FP64
+    coordinates during the call).
+
+    Returns the new float32[n, 2] drawing (and the per-position visit counts
+    when ``visits``)."""
+    return _grad_call(_load().oracle_grad_sample, n, head, tail, w, xy, a, b, gamma, alpha0, window, neg, t, seed,
+                      it_begin, it_end, visits)
+
+
+def grad_sample_window(n: int, head, tail, w, xy: np.ndarray, *, a: float, b: float, gamma: float = 1.0,
+                       alpha0: float = 1.0, window: int, neg: int = 5, t: int, seed: int, it_begin: int = 0,
+                       it_end: int | None = None, visits: bool = False, parts: int = 1):
+    """The same iterations with every window cut into ``parts`` consecutive
+    parts, each applied synchronously in 2^-32 fixed point (each entry from
+    its part's start positions, its own steps in Alg. 5's order): the
+    device's form, used to check the kernels' arithmetic; ``grad_sample`` is
+    the paper's serial order."""
+    return _grad_call(_load().oracle_grad_sample_window, n, head, tail, w, xy, a, b, gamma, alpha0, window, neg, t,
+                      seed, it_begin, it_end, visits, int(parts))
+
+
 def spectral_layout(n: int, row_ptr, col, val, dim: int = 2):
     """Spectral initial drawing (Sec. 3.2: the layout starts from a spectral
     layout, as in UMAP): the eigenvectors of the 2nd .. (dim+1)-th smallest

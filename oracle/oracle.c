@@ -16,15 +16,19 @@
  *   oracle_membership    UMAP fuzzy membership rho, sigma and weights in FP64
  *                        (Sec. 2.1, high-dimensional similarity h_ij)
  *   oracle_stress        aggregated stress of a drawing against hop
- *                        distances (Sec. 5.1, quality metrics)
+ *                        distances (Sec. 4.1.3, quality metrics)
  *   oracle_neighborhood  neighbourhood preservation of a drawing, per vertex
- *                        (Sec. 5.1, quality metrics)
+ *                        (Sec. 4.1.3, quality metrics)
  *   oracle_splitmix64    the SplitMix64 generator (published definition)
  *   oracle_fuzzy_union   symmetric fuzzy union of the kNN membership weights
  *                        (UMAP's graph symmetrisation before step C2)
  *   oracle_edge_shuffle  shuffled edge array E_k (Alg. 5, first step)
- *   oracle_grad_sample   sliding-window gradient iterations of the layout
- *                        (Alg. 5 GradSample, cost C of Sec. 2.1)
+ *   oracle_grad_sample   sliding-window gradient iterations of the layout in
+ *                        the paper's serial order (Alg. 5 GradSample,
+ *                        Sec. 3.3.2; cost C of Sec. 2.1)
+ *   oracle_grad_sample_window  the same iterations with each window applied
+ *                        synchronously in fixed point (the device's form; a
+ *                        check of the kernels' arithmetic, not of the paper)
  *
  * Readings where the paper is silent or garbled (each is listed with its
  * justification in the design notes):
@@ -54,9 +58,9 @@
  *     the metric sums the defined scores;
  *   - layout step: the readings are stated at each function below (fuzzy
  *     union as in UMAP, E_k holding both directions of each edge, windows
- *     of s consecutive positions, synchronous update of a window in fixed
- *     point, UMAP's attractive and negative-sample moves scaled by the edge
- *     weight, learning rate alpha0 (1 - it / t)).
+ *     of s consecutive positions, entries moved one after the other, UMAP's
+ *     attractive and negative-sample moves scaled by the edge weight,
+ *     learning rate alpha0 (1 - it / t)).
  *
  * Threads: rows are independent; `nthreads` worker threads take rows from a
  * shared counter.  This parallelism does not change any result.
@@ -419,7 +423,7 @@ int oracle_membership(int64_t rows, int32_t k, const uint8_t *hops, float *weigh
 }
 
 /* ------------------------------------------------------------------------
- * Aggregated stress (Sec. 5.1): for each listed source s and every vertex
+ * Aggregated stress (Sec. 4.1.3): for each listed source s and every vertex
  * v != s reachable from s, ((d(s,v) - |X_s - X_v|) / d(s,v))^2, with d the
  * BFS hop distance and |.| the Euclidean distance of the drawing (xy holds
  * x, y per vertex as float; the arithmetic is FP64).  Per-source sums and
@@ -469,7 +473,7 @@ int oracle_stress(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, con
 }
 
 /* ------------------------------------------------------------------------
- * Neighbourhood preservation (Sec. 5.1): per vertex v, the Jaccard index of
+ * Neighbourhood preservation (Sec. 4.1.3): per vertex v, the Jaccard index of
  * its graph ball N_G(v, r) (hops 1..r) and the same number of nearest
  * vertices in the drawing, ranked by (squared distance, id).  score[v] is
  * NaN when the ball is empty; ball[v] receives |N_G(v, r)|.
@@ -565,7 +569,7 @@ uint64_t oracle_splitmix64(uint64_t seed, uint64_t i)
 
 /* ------------------------------------------------------------------------
  * Fuzzy union of the directed kNN membership graph (UMAP's symmetrisation,
- * which the paper inherits from its UMAP implementation, Sec. 4.1): with
+ * which the paper inherits from its UMAP implementation, Sec. 4.1.1): with
  * A[i][j] = weight of j in row i (0 when j is not in row i), the symmetric
  * graph has U[i][j] = A[i][j] + A[j][i] - A[i][j] * A[j][i] for every pair
  * where this is positive.  Evaluated in FP64 as (a + b) - a * b without
@@ -670,35 +674,35 @@ int oracle_edge_shuffle(int32_t n, const int32_t *row_ptr, const int32_t *col, c
 }
 
 /* ------------------------------------------------------------------------
- * GradSample (Alg. 5) on a 2-D drawing.  Positions are held in fixed point
- * P = round(X * 2^32) (int64 per coordinate, round half to even), so that
- * the sum of the moves of a window does not depend on their order.
+ * GradSample (Alg. 5, Sec. 3.3.2) on a 2-D drawing, in the paper's serial
+ * order: the entries of a window are taken one after the other, and each
+ * reads the CURRENT coordinates of its vertices (as moved by every earlier
+ * entry) and moves them before the next entry is read.  Coordinates are
+ * plain FP64 for the whole call (read from float, written back as float).
  *
  * s = window (edges per iteration, 1 <= s <= m).  Iteration it in
  * [it_begin, it_end) of a run of t iterations:
  *   lr = alpha0 * (1 - it / t)      (UMAP's linear learning-rate decay)
  *   the window holds the array positions (it * s + l) mod m, l = 0..s-1,
- *   i.e. consecutive windows slide over the shuffled array without gaps;
- *   every move of the window is computed from the positions at the start of
- *   the window and the moves are added afterwards (synchronous window).
- * For the window entry (a, b, h) at position l:
- *   D = X_a - X_b, d2 = Dx*Dx + Dy*Dy, T = d2^beta;
+ *   i.e. consecutive windows slide over the shuffled array without gaps.
+ * For the window entry (a, b, h) at position l, in this order:
  *   attraction (gradient of h * log(1 + alpha_ab * d^(2 beta)), the
  *   attractive part of the cross-entropy C of Sec. 2.1 with
- *   w = 1 / (1 + alpha_ab * d^(2 beta))):
+ *   w = 1 / (1 + alpha_ab * d^(2 beta))), from the current X_a, X_b:
+ *     D = X_a - X_b, d2 = Dx*Dx + Dy*Dy, T = d2^beta,
  *     c = -2 alpha_ab beta T / (d2 (1 + alpha_ab T)) if d2 > 0 else 0,
  *     g = clip(c * D, -4, 4) per coordinate,
  *     X_a += lr * h * g,  X_b -= lr * h * g;
- *   repulsion (negative sampling of UMAP's optimiser, neg samples): the
- *   q-th sample is vertex v = splitmix64(seed, ((it * s + l) * neg + q) + 1)
- *   mod n; v == a is skipped; with E = X_a - X_v, e2 = |E|^2, T = e2^beta:
+ *   then the negative samples of UMAP's optimiser, one after the other: the
+ *   q-th is vertex v = splitmix64(seed, ((it * s + l) * neg + q) + 1) mod n;
+ *   v == a is skipped; from the current X_a and X_v, E = X_a - X_v,
+ *   e2 = |E|^2, T = e2^beta:
  *     c = 2 gamma beta / ((0.001 + e2) (1 + alpha_ab T)),
  *     g = clip(c * E, -4, 4) if e2 > 0, else 4 in each coordinate,
  *     X_a += lr * h * g.
- * Each move lr * h * g is rounded to the fixed-point grid on its own.
- * The FP64 expressions are evaluated in exactly the order written, without
- * fused multiply-add.  visits (optional) counts how often each array
- * position was processed.
+ * The FP64 expressions are evaluated in the order written, without fused
+ * multiply-add.  visits (optional) counts how often each array position was
+ * processed.
  * ---------------------------------------------------------------------- */
 static double clip4(double v)
 {
@@ -712,24 +716,20 @@ int oracle_grad_sample(int32_t n, int64_t m, const int32_t *head, const int32_t 
     if (n < 0 || m < 0 || neg < 0 || t < 1 || it_begin < 0 || it_end > t || it_begin > it_end) return ORACLE_EINVAL;
     if (m == 0 || n == 0 || it_begin == it_end) return ORACLE_OK;
     if (s < 1 || s > m) return ORACLE_EINVAL;
-    const double scale = 4294967296.0, inv = 1.0 / 4294967296.0;
-    int64_t *P = (int64_t *)malloc((size_t)n * 2 * sizeof(int64_t));
-    int64_t *acc = (int64_t *)calloc((size_t)n * 2, sizeof(int64_t));
-    if (!P || !acc) { free(P); free(acc); return ORACLE_ENOMEM; }
-    for (size_t i = 0; i < (size_t)n * 2; ++i) P[i] = llrint((double)xy[i] * scale);
     for (int64_t e = 0; e < m; ++e)
-        if (head[e] < 0 || head[e] >= n || tail[e] < 0 || tail[e] >= n) { free(P); free(acc); return ORACLE_EINVAL; }
+        if (head[e] < 0 || head[e] >= n || tail[e] < 0 || tail[e] >= n) return ORACLE_EINVAL;
+    double *X = (double *)malloc((size_t)n * 2 * sizeof(double));
+    if (!X) return ORACLE_ENOMEM;
+    for (size_t i = 0; i < (size_t)n * 2; ++i) X[i] = (double)xy[i];
     for (int32_t it = it_begin; it < it_end; ++it) {
         const double lr = alpha0 * (1.0 - (double)it / (double)t);
         const int64_t j0 = (int64_t)(((__int128)it * s) % m);
         for (int64_t l = 0; l < s; ++l) {
             const int64_t p = (j0 + l) % m;
             if (visits) ++visits[p];
-            const int32_t a = head[p], b = tail[p];
+            const size_t a = (size_t)head[p], b = (size_t)tail[p];
             const double lh = lr * (double)w[p];
-            const double ax = (double)P[2 * (size_t)a] * inv, ay = (double)P[2 * (size_t)a + 1] * inv;
-            const double bx = (double)P[2 * (size_t)b] * inv, by = (double)P[2 * (size_t)b + 1] * inv;
-            const double dx = ax - bx, dy = ay - by;
+            const double dx = X[2 * a] - X[2 * b], dy = X[2 * a + 1] - X[2 * b + 1];
             const double sx = dx * dx, sy = dy * dy;
             const double d2 = sx + sy;
             if (d2 > 0.0) {
@@ -737,17 +737,17 @@ int oracle_grad_sample(int32_t n, int64_t m, const int32_t *head, const int32_t 
                 const double num = -2.0 * alpha_ab * beta * T;
                 const double den = d2 * (1.0 + alpha_ab * T);
                 const double c = num / den;
-                const int64_t qx = llrint(lh * clip4(c * dx) * scale);
-                const int64_t qy = llrint(lh * clip4(c * dy) * scale);
-                acc[2 * (size_t)a] += qx; acc[2 * (size_t)a + 1] += qy;
-                acc[2 * (size_t)b] -= qx; acc[2 * (size_t)b + 1] -= qy;
+                const double mx = lh * clip4(c * dx), my = lh * clip4(c * dy);
+                X[2 * a] += mx;
+                X[2 * a + 1] += my;
+                X[2 * b] -= mx;
+                X[2 * b + 1] -= my;
             }
             for (int32_t q = 0; q < neg; ++q) {
                 const uint64_t idx = ((uint64_t)it * (uint64_t)s + (uint64_t)l) * (uint64_t)neg + (uint64_t)q;
-                const int32_t v = (int32_t)(oracle_splitmix64(seed, idx + 1) % (uint64_t)n);
+                const size_t v = (size_t)(oracle_splitmix64(seed, idx + 1) % (uint64_t)n);
                 if (v == a) continue;
-                const double vx = (double)P[2 * (size_t)v] * inv, vy = (double)P[2 * (size_t)v + 1] * inv;
-                const double ex = ax - vx, ey = ay - vy;
+                const double ex = X[2 * a] - X[2 * v], ey = X[2 * a + 1] - X[2 * v + 1];
                 const double tx = ex * ex, ty = ey * ey;
                 const double e2 = tx + ty;
                 double gx = 4.0, gy = 4.0;
@@ -759,13 +759,103 @@ int oracle_grad_sample(int32_t n, int64_t m, const int32_t *head, const int32_t 
                     gx = clip4(c * ex);
                     gy = clip4(c * ey);
                 }
-                acc[2 * (size_t)a] += llrint(lh * gx * scale);
-                acc[2 * (size_t)a + 1] += llrint(lh * gy * scale);
+                X[2 * a] += lh * gx;
+                X[2 * a + 1] += lh * gy;
             }
         }
-        for (size_t i = 0; i < (size_t)n * 2; ++i) {
-            P[i] += acc[i];
-            acc[i] = 0;
+    }
+    for (size_t i = 0; i < (size_t)n * 2; ++i) xy[i] = (float)X[i];
+    free(X);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * GradSample with synchronous parts in fixed point: the form the device
+ * runs (many entries of a window at once).  A window is cut into
+ * P = min(parts, s) consecutive parts, entries l in [c s / P, (c + 1) s / P),
+ * applied one after the other.  Every entry of a part starts from the
+ * positions at the start of its part and applies its own steps in Alg. 5's
+ * order to a private copy of its vertices (attraction moves X_a and X_b, then
+ * each negative sample reads the entry's moved X_a, and X_b as moved when the
+ * sample is b); the part's moves are added to the positions after the part.  Positions are held as P = round(X * 2^32) (int64 per coordinate,
+ * round half to even) and every single move is rounded to that grid, so the
+ * sum of a window's moves does not depend on their order.  Schedule, learning
+ * rate, attraction and repulsion are those of oracle_grad_sample; where no
+ * two entries of a part share a vertex (negative samples included) the two
+ * agree up to the grid rounding (at most 2^-33 per move).
+ * ---------------------------------------------------------------------- */
+int oracle_grad_sample_window(int32_t n, int64_t m, const int32_t *head, const int32_t *tail, const float *w,
+                              float *xy, double alpha_ab, double beta, double gamma, double alpha0, int64_t s,
+                              int32_t neg, int32_t t, uint64_t seed, int32_t it_begin, int32_t it_end,
+                              int32_t *visits, int32_t parts)
+{
+    if (n < 0 || m < 0 || neg < 0 || t < 1 || it_begin < 0 || it_end > t || it_begin > it_end || parts < 1)
+        return ORACLE_EINVAL;
+    if (m == 0 || n == 0 || it_begin == it_end) return ORACLE_OK;
+    if (s < 1 || s > m) return ORACLE_EINVAL;
+    const double scale = 4294967296.0, inv = 1.0 / 4294967296.0;
+    for (int64_t e = 0; e < m; ++e)
+        if (head[e] < 0 || head[e] >= n || tail[e] < 0 || tail[e] >= n) return ORACLE_EINVAL;
+    int64_t *P = (int64_t *)malloc((size_t)n * 2 * sizeof(int64_t));
+    int64_t *acc = (int64_t *)calloc((size_t)n * 2, sizeof(int64_t));
+    if (!P || !acc) { free(P); free(acc); return ORACLE_ENOMEM; }
+    for (size_t i = 0; i < (size_t)n * 2; ++i) P[i] = llrint((double)xy[i] * scale);
+    const int64_t np = parts < s ? parts : s;
+    for (int32_t it = it_begin; it < it_end; ++it) {
+        const double lr = alpha0 * (1.0 - (double)it / (double)t);
+        const int64_t j0 = (int64_t)(((__int128)it * s) % m);
+        for (int64_t c = 0; c < np; ++c) {
+          for (int64_t l = s * c / np; l < s * (c + 1) / np; ++l) {
+            const int64_t p = (j0 + l) % m;
+            if (visits) ++visits[p];
+            const size_t a = (size_t)head[p], b = (size_t)tail[p];
+            const double lh = lr * (double)w[p];
+            /* the entry's private copies of its two vertices */
+            int64_t pax = P[2 * a], pay = P[2 * a + 1], pbx = P[2 * b], pby = P[2 * b + 1];
+            const double dx = (double)pax * inv - (double)pbx * inv, dy = (double)pay * inv - (double)pby * inv;
+            const double sx = dx * dx, sy = dy * dy;
+            const double d2 = sx + sy;
+            if (d2 > 0.0) {
+                const double T = pow(d2, beta);
+                const double num = -2.0 * alpha_ab * beta * T;
+                const double den = d2 * (1.0 + alpha_ab * T);
+                const double c = num / den;
+                const int64_t qx = llrint(lh * clip4(c * dx) * scale);
+                const int64_t qy = llrint(lh * clip4(c * dy) * scale);
+                pax += qx; pay += qy;
+                pbx -= qx; pby -= qy;
+            }
+            for (int32_t q = 0; q < neg; ++q) {
+                const uint64_t idx = ((uint64_t)it * (uint64_t)s + (uint64_t)l) * (uint64_t)neg + (uint64_t)q;
+                const size_t v = (size_t)(oracle_splitmix64(seed, idx + 1) % (uint64_t)n);
+                if (v == a) continue;
+                const int64_t pvx = v == b ? pbx : P[2 * v], pvy = v == b ? pby : P[2 * v + 1];
+                const double ex = (double)pax * inv - (double)pvx * inv, ey = (double)pay * inv - (double)pvy * inv;
+                const double tx = ex * ex, ty = ey * ey;
+                const double e2 = tx + ty;
+                double gx = 4.0, gy = 4.0;
+                if (e2 > 0.0) {
+                    const double T = pow(e2, beta);
+                    const double num = 2.0 * gamma * beta;
+                    const double den = (0.001 + e2) * (1.0 + alpha_ab * T);
+                    const double c = num / den;
+                    gx = clip4(c * ex);
+                    gy = clip4(c * ey);
+                }
+                pax += llrint(lh * gx * scale);
+                pay += llrint(lh * gy * scale);
+            }
+            acc[2 * a] += pax - P[2 * a];
+            acc[2 * a + 1] += pay - P[2 * a + 1];
+            if (b != a) {
+                acc[2 * b] += pbx - P[2 * b];
+                acc[2 * b + 1] += pby - P[2 * b + 1];
+            }
+          }
+          for (size_t i = 0; i < (size_t)n * 2; ++i) {
+              P[i] += acc[i];
+              acc[i] = 0;
+          }
         }
     }
     for (size_t i = 0; i < (size_t)n * 2; ++i) xy[i] = (float)((double)P[i] * inv);

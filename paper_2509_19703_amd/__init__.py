@@ -45,7 +45,8 @@ class gumap_batch_tuning(ctypes.Structure):
 class gumap_layout_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha0", ctypes.c_double), ("samp", ctypes.c_double), ("window", ctypes.c_int64),
-                ("neg", ctypes.c_int32), ("t", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("neg", ctypes.c_int32), ("t", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("parts", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class gumap_spectral_params(ctypes.Structure):
@@ -55,6 +56,10 @@ class gumap_spectral_params(ctypes.Structure):
 
 # UMAP's curve parameters for min_dist 0.1 and spread 1 (its default fit of
 # 1 / (1 + a d^(2b)) to the target membership curve of the drawing).
+# Synchronous parts per GradSample window when the parameters leave it 0
+# (GUMAP_LAYOUT_DEFAULT_PARTS of the header).
+LAYOUT_DEFAULT_PARTS = 4
+
 UMAP_A = 1.5769434603113077
 UMAP_B = 0.8950608781227859
 
@@ -398,9 +403,10 @@ def edge_shuffle(row_ptr, col, val, seed: int, stream=None):
 
 
 def layout_params(*, a: float = UMAP_A, b: float = UMAP_B, gamma: float = 1.0, alpha0: float = 1.0,
-                  samp: float = 0.9, window: int = 0, neg: int = 5, t: int = 200, seed: int = 0):
+                  samp: float = 0.9, window: int = 0, neg: int = 5, t: int = 200, seed: int = 0, parts: int = 0):
+    """parts: synchronous parts per window (0 = the library's default)."""
     return gumap_layout_params(float(a), float(b), float(gamma), float(alpha0), float(samp), int(window), int(neg),
-                               int(t), int(seed) & (2**64 - 1))
+                               int(t), int(seed) & (2**64 - 1), int(parts), 0)
 
 
 def gumap_grad_sample(n, xy, m, head, tail, w, params, it_begin, it_end, stream=None) -> int:

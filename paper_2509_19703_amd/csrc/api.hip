@@ -1068,6 +1068,7 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
         return set_error(GUMAP_EINVAL, "iteration range [%d, %d) outside [0, %d]", it_begin, it_end, p->t);
     if (!(p->beta > 0.0) || !(p->alpha > 0.0) || !(p->samp > 0.0 || p->window > 0))
         return set_error(GUMAP_EINVAL, "alpha, beta must be positive; samp or window must be set");
+    if (p->parts < 0) return set_error(GUMAP_EINVAL, "parts < 0");
     if (n == 0 || m == 0 || it_begin == it_end) return GUMAP_OK;
     if (!xy || !head || !tail || !w) return set_error(GUMAP_EINVAL, "NULL array");
     int64_t win = p->window;
@@ -1118,18 +1119,22 @@ int grad_sample(int32_t n, float *xy, int64_t m, const int32_t *head, const int3
     int n_heavy = 0;   // one block per heavy vertex in every window
     if ((st = read_flag((const int *)(inc + rec_bytes + off_bytes + heavy_bytes), &n_heavy, s))) return st;
     g.heavy_blocks = n_heavy;
+    const int64_t parts = std::min<int64_t>(p->parts > 0 ? p->parts : GUMAP_LAYOUT_DEFAULT_PARTS, win);
     int cur = 0;
     for (int32_t it = it_begin; it < it_end; ++it) {
         const double lr = p->alpha0 * (1.0 - (double)it / (double)p->t);
-        // moves: the window's entries (12 B) and the positions of their
-        // endpoints and negative samples, 32 B of moves stored; gather: every
-        // incidence code and offset, the stored moves read back, positions in
-        // and out
-        GM_PROF("grad_window", (double)win * (12.0 + 32.0 + 16.0 * p->neg + 32.0) + (double)m * 2.0 * 4.0 +
-                                   (double)n * (8.0 + 32.0) + (double)win * 32.0,
-                launch_grad_window(g, it, lr, B[cur], B[cur ^ 1], moves, s));
-        if (e != hipSuccess) return hip_status(e, "grad sample");
-        cur ^= 1;
+        for (int64_t c = 0; c < parts; ++c) {
+            const int64_t l0 = win * c / parts, l1 = win * (c + 1) / parts;
+            // moves: the part's entries (12 B) and the positions of their
+            // endpoints and negative samples, 32 B of moves stored; gather:
+            // every incidence code and offset, the stored moves read back,
+            // positions in and out
+            GM_PROF("grad_window", (double)(l1 - l0) * (12.0 + 32.0 + 16.0 * p->neg + 32.0) + (double)m * 2.0 * 4.0 +
+                                       (double)n * (8.0 + 32.0) + (double)(l1 - l0) * 32.0,
+                    launch_grad_window(g, it, l0, l1, lr, B[cur], B[cur ^ 1], moves, s));
+            if (e != hipSuccess) return hip_status(e, "grad sample");
+            cur ^= 1;
+        }
     }
     e = launch_layout_out(n, B[cur], xy, s);
     if (e != hipSuccess) return hip_status(e, "grad sample");

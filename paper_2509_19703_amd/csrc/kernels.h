@@ -251,10 +251,11 @@ hipError_t launch_layout_out(int32_t n, const long long *p, float *xy, hipStream
 size_t incidence_scratch_bytes(int32_t n, int64_t m, size_t *sort_tmp);
 hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, uint32_t *code, int32_t *heavy,
                                    int32_t *n_heavy, hipStream_t s);
-// Iteration `it` at learning rate lr: reads the positions R, writes N;
-// moves: 32 bytes per array position (m entries).
-hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
-                              void *moves, hipStream_t s);
+// Window entries l0 .. l1 - 1 of iteration `it` (one synchronous part of the
+// window) at learning rate lr: reads the positions R, writes N; moves: 32
+// bytes per array position (m entries).
+hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, int64_t l0, int64_t l1, double lr, const long long *R,
+                              long long *N, void *moves, hipStream_t s);
 
 // -------------------------------------------- spectral initial drawing ---
 // Lanczos iteration on A = D^-1/2 W D^-1/2 deflated by D^1/2 1 (FP64).

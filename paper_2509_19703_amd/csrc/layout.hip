@@ -9,8 +9,9 @@
 // SplitMix64 key of their position.  GradSample first sorts the 2m
 // incidences (each array entry at its head and at its tail) by vertex.  A
 // window is then two launches: a thread per window entry computes the
-// entry's moves from the positions at the start of the window and stores
-// them at the entry's array position; a thread per vertex (a wave for a
+// entry's moves from the positions at the start of the window (its own steps
+// in Alg. 5's order: attraction, then the negative samples from the moved
+// head) and stores them at the entry's array position; a thread per vertex (a wave for a
 // vertex with many incidences) adds up the stored moves of its incidences
 // that lie in the window and writes its next position once.  Positions are
 // fixed point (int64, 2^-32 units) and moves are summed as integers, so the
@@ -266,28 +267,31 @@ __device__ __forceinline__ void repel(const LayoutArgs &g, double lh, double ex,
 
 __device__ __forceinline__ double fix_to_f64(long long v) { return (double)v * kFixInv; }
 
-// Phase 1, a thread per window entry (a, b, h) at position p: the head's
-// move (attraction plus negative samples) and the attraction alone, rounded
-// to the fixed-point grid, stored at mv[p] = {head x, head y, att x, att y};
-// the tail receives -att.  The positions of up to kNegBatch negative samples
-// are loaded before any of them is used.
+// Phase 1, a thread per window entry (a, b, h) at position p: the entry's
+// steps in Alg. 5's order on its own copy of its vertices, starting from the
+// positions at the start of the window -- the attraction moves a and b, then
+// each negative sample reads a as moved so far (and b as moved when the
+// sample is b).  Every move is rounded to the fixed-point grid.  Stored at
+// mv[p] = {head x, head y, att x, att y}: the head's total move and the
+// attraction (the tail receives -att).  The positions of up to kNegBatch
+// negative samples are loaded before any of them is used.
 constexpr int kNegBatch = 8;
 
 __global__ void __launch_bounds__(kLayoutBlock)
-grad_moves_kernel(LayoutArgs g, int64_t j0, int32_t it, double lr, const longlong2 *__restrict__ R,
-                  longlong2 *__restrict__ mv)
+grad_moves_kernel(LayoutArgs g, int64_t j0, int64_t l0, int64_t l1, int32_t it, double lr,
+                  const longlong2 *__restrict__ R, longlong2 *__restrict__ mv)
 {
 #pragma clang fp contract(off)
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < g.s; l += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t l = l0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < l1; l += (int64_t)gridDim.x * blockDim.x) {
         int64_t p = j0 + l;
         if (p >= g.m) p -= g.m;
         const int32_t a = g.head[p], b = g.tail[p];
         const double lh = lr * (double)g.w[p];
         const longlong2 ra = R[a], rb = R[b];
-        const double ax = fix_to_f64(ra.x), ay = fix_to_f64(ra.y);
         long long qx, qy;
-        attract(g, lh, ax - fix_to_f64(rb.x), ay - fix_to_f64(rb.y), qx, qy);
+        attract(g, lh, fix_to_f64(ra.x) - fix_to_f64(rb.x), fix_to_f64(ra.y) - fix_to_f64(rb.y), qx, qy);
         long long hx = qx, hy = qy;
+        const longlong2 pb = make_longlong2(rb.x - qx, rb.y - qy);
         const uint64_t base = ((uint64_t)it * (uint64_t)g.s + (uint64_t)l) * (uint64_t)g.neg;
         for (int32_t q0 = 0; q0 < g.neg; q0 += kNegBatch) {
             int32_t vq[kNegBatch];
@@ -297,10 +301,12 @@ grad_moves_kernel(LayoutArgs g, int64_t j0, int32_t it, double lr, const longlon
                 vq[u] = q0 + u < g.neg ? (int32_t)(splitmix64(g.seed, base + (uint64_t)(q0 + u) + 1) % (uint64_t)g.n)
                                        : a;
 #pragma unroll
-            for (int u = 0; u < kNegBatch; ++u) rq[u] = vq[u] != a ? R[vq[u]] : ra;
+            for (int u = 0; u < kNegBatch; ++u) rq[u] = (vq[u] != a && vq[u] != b) ? R[vq[u]] : pb;
 #pragma unroll
             for (int u = 0; u < kNegBatch; ++u)
-                if (vq[u] != a) repel(g, lh, ax - fix_to_f64(rq[u].x), ay - fix_to_f64(rq[u].y), hx, hy);
+                if (vq[u] != a)
+                    repel(g, lh, fix_to_f64(ra.x + hx) - fix_to_f64(rq[u].x), fix_to_f64(ra.y + hy) - fix_to_f64(rq[u].y),
+                          hx, hy);
         }
         mv[2 * p] = make_longlong2(hx, hy);
         mv[2 * p + 1] = make_longlong2(qx, qy);
@@ -311,8 +317,9 @@ grad_moves_kernel(LayoutArgs g, int64_t j0, int32_t it, double lr, const longlon
 // `step`, that lie in the window (kGatherLoads codes in flight per round).
 constexpr int kGatherLoads = 4;
 
-__device__ __forceinline__ void gather_range(const LayoutArgs &g, int64_t j0, const longlong2 *__restrict__ mv,
-                                             int32_t i0, int32_t i1, int32_t step, long long &ax, long long &ay)
+__device__ __forceinline__ void gather_range(const LayoutArgs &g, int64_t j0, int64_t len,
+                                             const longlong2 *__restrict__ mv, int32_t i0, int32_t i1, int32_t step,
+                                             long long &ax, long long &ay)
 {
     for (int32_t i = i0; i < i1; i += kGatherLoads * step) {
         uint32_t c[kGatherLoads];
@@ -324,7 +331,7 @@ __device__ __forceinline__ void gather_range(const LayoutArgs &g, int64_t j0, co
         for (int u = 0; u < kGatherLoads; ++u) {
             int64_t l = (int64_t)(c[u] >> 1) - j0;
             if (l < 0) l += g.m;
-            in[u] = c[u] != 0xFFFFFFFFu && l < g.s;
+            in[u] = c[u] != 0xFFFFFFFFu && l < len;
             t[u] = in[u] ? mv[2 * (int64_t)(c[u] >> 1) + (c[u] & 1)] : make_longlong2(0, 0);
         }
 #pragma unroll
@@ -340,15 +347,16 @@ __device__ __forceinline__ void gather_range(const LayoutArgs &g, int64_t j0, co
     }
 }
 
-// Phase 2: N[v] = R[v] + the moves of v's incidences in the window.  Blocks
+// Phase 2: N[v] = R[v] + the moves of v's incidences at array positions
+// j0 .. j0 + len - 1 (mod m).  Blocks
 // [0, heavy_blocks) take the heavy vertices (more than kLayoutHeavyInc
 // incidences), one block each when heavy_blocks equals their count; the
 // other blocks give kGatherTeam lanes to each remaining vertex.
 constexpr int kGatherTeam = 8;
 
 __global__ void __launch_bounds__(kLayoutBlock)
-grad_gather_kernel(LayoutArgs g, int64_t j0, const longlong2 *__restrict__ mv, const longlong2 *__restrict__ R,
-                   longlong2 *__restrict__ N)
+grad_gather_kernel(LayoutArgs g, int64_t j0, int64_t len, const longlong2 *__restrict__ mv,
+                   const longlong2 *__restrict__ R, longlong2 *__restrict__ N)
 {
     if ((int)blockIdx.x < g.heavy_blocks) {
         __shared__ long long part[2][kLayoutBlock / 64];
@@ -357,7 +365,7 @@ grad_gather_kernel(LayoutArgs g, int64_t j0, const longlong2 *__restrict__ mv, c
         for (int32_t h = blockIdx.x; h < cnt; h += g.heavy_blocks) {
             const int32_t v = g.heavy[h];
             long long ax = 0, ay = 0;
-            gather_range(g, j0, mv, g.off[v] + (int32_t)threadIdx.x, g.off[v + 1], kLayoutBlock, ax, ay);
+            gather_range(g, j0, len, mv, g.off[v] + (int32_t)threadIdx.x, g.off[v + 1], kLayoutBlock, ax, ay);
             for (int o = 32; o > 0; o >>= 1) {
                 ax += __shfl_xor(ax, o);
                 ay += __shfl_xor(ay, o);
@@ -386,7 +394,7 @@ grad_gather_kernel(LayoutArgs g, int64_t j0, const longlong2 *__restrict__ mv, c
     const int32_t b = valid ? g.off[v] : 0, e = valid ? g.off[v + 1] : 0;
     const bool mine = valid && e - b <= kLayoutHeavyInc;
     long long ax = 0, ay = 0;
-    if (mine) gather_range(g, j0, mv, b + t, e, kGatherTeam, ax, ay);
+    if (mine) gather_range(g, j0, len, mv, b + t, e, kGatherTeam, ax, ay);
     for (int o = kGatherTeam / 2; o > 0; o >>= 1) {
         ax += __shfl_xor(ax, o);
         ay += __shfl_xor(ay, o);
@@ -562,19 +570,21 @@ hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, u
     return hipSuccess;
 }
 
-hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, double lr, const long long *R, long long *N,
-                              void *moves, hipStream_t s)
+hipError_t launch_grad_window(const LayoutArgs &g, int32_t it, int64_t l0, int64_t l1, double lr, const long long *R,
+                              long long *N, void *moves, hipStream_t s)
 {
     const int64_t j0 = (int64_t)(((unsigned __int128)(uint64_t)it * (uint64_t)g.s) % (uint64_t)g.m);
     longlong2 *mv = (longlong2 *)moves;
-    hipLaunchKernelGGL(grad_moves_kernel, dim3(grid_for(g.s)), dim3(kLayoutBlock), 0, s, g, j0, it, lr,
+    hipLaunchKernelGGL(grad_moves_kernel, dim3(grid_for(l1 - l0)), dim3(kLayoutBlock), 0, s, g, j0, l0, l1, it, lr,
                        (const longlong2 *)R, mv);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    int64_t jp = j0 + l0;
+    if (jp >= g.m) jp -= g.m;
     const int64_t light_threads = (int64_t)g.n * kGatherTeam;
     const int blocks = g.heavy_blocks + (int)((light_threads + kLayoutBlock - 1) / kLayoutBlock);
-    hipLaunchKernelGGL(grad_gather_kernel, dim3(blocks), dim3(kLayoutBlock), 0, s, g, j0, (const longlong2 *)mv,
-                       (const longlong2 *)R, (longlong2 *)N);
+    hipLaunchKernelGGL(grad_gather_kernel, dim3(blocks), dim3(kLayoutBlock), 0, s, g, jp, l1 - l0,
+                       (const longlong2 *)mv, (const longlong2 *)R, (longlong2 *)N);
     return hipGetLastError();
 }
 

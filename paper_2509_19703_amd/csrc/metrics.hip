@@ -1,4 +1,4 @@
-// Neighbourhood preservation of a drawing (Sec. 5.1 quality metrics).
+// Neighbourhood preservation of a drawing (Sec. 4.1.3 quality metrics).
 //
 // One workgroup per listed vertex v:
 //   1. the graph ball N_G(v, r), r in {1, 2}: an n-bit set in LDS, marked by

@@ -569,7 +569,7 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
 // segments (8 * TILES threads per row), instead of 16 bytes into 64
 // different rows per store.  Needs rows aligned to 8 * TILES bytes.
 // With STRESS the staged bytes are not stored: each row's stress terms
-// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 5.1) are summed in
+// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 4.1.3) are summed in
 // FP64 instead, one partial sum and pair count per (slot, block).
 constexpr int kStressIts = 8;   // rows per thread in the store / stress phase of the staged transpose
 
@@ -702,7 +702,7 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
 // segments (8 * TILES threads per row), instead of 16 bytes into 64
 // different rows per store.  Needs rows aligned to 8 * TILES bytes.
 // With STRESS the staged bytes are not stored: each row's stress terms
-// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 5.1) are summed in
+// ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 4.1.3) are summed in
 // FP64 instead, one partial sum and pair count per (slot, block).
 template <int WORDS, int TILES, bool STRESS>
 __global__ void __launch_bounds__(WORDS * GM_WAVE)

@@ -28,7 +28,8 @@ def test_struct_layouts_match_header(gumap):
     assert ctypes.sizeof(gumap.gumap_graph) == 32
     assert ctypes.sizeof(gumap.gumap_batch) == 64
     assert ctypes.sizeof(gumap.gumap_batch_tuning) == 24
-    assert ctypes.sizeof(gumap.gumap_layout_params) == 64
+    assert ctypes.sizeof(gumap.gumap_layout_params) == 72
+    assert gumap.gumap_layout_params.parts.offset == 64
     assert ctypes.sizeof(gumap.gumap_spectral_params) == 24
 
 

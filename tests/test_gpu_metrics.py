@@ -1,4 +1,4 @@
-"""GPU parity of the drawing quality metrics (Sec. 5.1) against the oracle.
+"""GPU parity of the drawing quality metrics (Sec. 4.1.3) against the oracle.
 
 Stress is an FP64 sum of many terms whose order differs between the GPU
 (per-block partial sums) and the oracle (per-row loops): the sums agree to

@@ -1,10 +1,15 @@
-"""Pins of the oracle's layout step (C2 of Sec. 2.1, GradSample of Alg. 5).
+"""Pins of the oracle's layout step (C2 of Sec. 2.1, GradSample of Alg. 5 in
+Sec. 3.3.2).
 
 Each check compares the oracle with something other than itself: the
 generator's published reference outputs, the fuzzy union written as a
 probability (1 - (1 - a)(1 - b)) on dense matrices, finite differences of
-the UMAP cross-entropy terms, the closed-form window schedule, and the
-independence of a synchronous window from the order of its edges.
+the UMAP cross-entropy terms, the closed-form window schedule, windows worked
+by hand in which the serial order of Alg. 5 changes the result, the serial
+window as a composition of one-entry windows, and, for the synchronous
+fixed-point form the device runs, the independence of a window from the
+order of its edges and its agreement with the serial order when no two
+entries share a vertex.
 """
 import os
 
@@ -144,33 +149,126 @@ def test_attraction_is_the_cross_entropy_gradient(xa, xb):
     assert np.allclose(db, lr * h * g, rtol=2e-4, atol=2e-8)
 
 
+def _seed_drawing(n, neg, want, start=1):
+    """The first seed whose neg draws splitmix64(seed, q + 1) mod n equal want."""
+    for seed in range(start, start + 100000):
+        if [O.splitmix64(seed, q + 1) % n for q in range(neg)] == list(want):
+            return seed
+    raise AssertionError("no seed")
+
+
 def test_repulsion_is_the_cross_entropy_gradient():
-    """Negative samples that hit b push a along -grad_a of gamma * (-log(1 - w))
-    (up to UMAP's 0.001 regulariser of d^2); samples hitting a are skipped."""
-    h, lr, gamma, neg, seed = 0.6, 0.01, 1.3, 40, 77
+    """A negative sample that hits b pushes a along -grad_a of
+    gamma * (-log(1 - w)) (up to UMAP's 0.001 regulariser of d^2), taken at
+    a's position after the entry's attraction; a sample hitting a is skipped."""
+    h, lr, gamma = 0.6, 0.1, 1.3
     xa, xb = (0.5, 1.0), (2.5, 3.0)
     head, tail, w, xy = _two(xa, xb, h)
-    kw = dict(a=A_UMAP, b=B_UMAP, gamma=gamma, alpha0=lr, window=1, t=1, seed=seed)
-    base = O.grad_sample(2, head, tail, w, xy, neg=0, **kw)
-    out = O.grad_sample(2, head, tail, w, xy, neg=neg, **kw)
-    hits = sum(O.splitmix64(seed, q + 1) % 2 == 1 for q in range(neg))
-    assert 0 < hits < neg
-    g = _num_grad(_rep_cost, np.array(xy[0], float), np.array(xy[1], float))
+    kw = dict(a=A_UMAP, b=B_UMAP, gamma=gamma, alpha0=lr, window=1, t=1)
+    seed = _seed_drawing(2, 1, [1])
+    base = O.grad_sample(2, head, tail, w, xy, neg=0, seed=seed, **kw)
+    out = O.grad_sample(2, head, tail, w, xy, neg=1, seed=seed, **kw)
+    g = _num_grad(_rep_cost, np.array(base[0], float), np.array(base[1], float))
     rep = out[0].astype(float) - base[0]
-    assert np.allclose(rep, -lr * h * gamma * hits * g, rtol=3e-4)
+    assert np.allclose(rep, -lr * h * gamma * g, rtol=3e-4)
     assert np.array_equal(out[1], base[1])
+    skip = _seed_drawing(2, 2, [0, 1])
+    assert np.array_equal(O.grad_sample(2, head, tail, w, xy, neg=2, seed=skip, **kw), out)
 
 
 def test_repulsion_clip_and_coincident_points():
-    h, lr, neg, seed = 1.0, 0.5, 16, 5
-    hits = sum(O.splitmix64(seed, q + 1) % 2 == 1 for q in range(neg))
+    h, lr = 1.0, 0.01
+    seed = _seed_drawing(2, 1, [1])
     head, tail, w, xy = _two((0.25, 0.5), (0.25, 0.5), h)      # coincident: +4 per coordinate
-    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=neg, t=1, seed=seed)
-    assert np.allclose(out[0] - xy[0], lr * h * 4.0 * hits, rtol=1e-6)
+    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=1, t=1, seed=seed)
+    assert np.allclose(out[0].astype(float) - xy[0], lr * h * 4.0, rtol=1e-6)
     head, tail, w, xy = _two((0.26, 0.5), (0.25, 0.49), h)     # close: clipped at 4
-    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=neg, t=1, seed=seed)
+    out = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=1, t=1, seed=seed)
     base = O.grad_sample(2, head, tail, w, xy, a=A_UMAP, b=B_UMAP, alpha0=lr, window=1, neg=0, t=1, seed=seed)
-    assert np.allclose(out[0].astype(float) - base[0], lr * h * 4.0 * hits, rtol=1e-5)
+    assert np.allclose(out[0].astype(float) - base[0], lr * h * 4.0, rtol=1e-5)
+
+
+def _golden_cases():
+    cases, cur = [], None
+    for line in open(os.path.join(GOLDEN, "gradsample_hand_3v.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        key, *rest = line.split()
+        if key == "case":
+            cur = {"name": rest[0]}
+        elif key == "params":
+            cur["params"] = {k: float(v) for k, v in (r.split("=") for r in rest)}
+        elif key == "end":
+            cases.append(cur)
+        else:
+            cur[key] = [float(x) for x in rest]
+    return cases
+
+
+@pytest.mark.parametrize("case", _golden_cases(), ids=lambda c: c["name"])
+def test_grad_sample_hand_worked_windows(case):
+    """Windows worked by hand: the serial order (each entry reads the moved
+    coordinates) and the synchronous form differ on a chain of entries, and
+    a negative sample reads its head after the entry's attraction."""
+    p = case["params"]
+    n = int(p["n"])
+    e = np.array(case["edges"]).reshape(-1, 3)
+    head, tail, w = e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2].astype(np.float32)
+    xy = np.array(case["xy"], np.float32).reshape(n, 2)
+    if "drawn" in p:
+        assert O.splitmix64(int(p["seed"]), 1) % n == int(p["drawn"])
+    kw = dict(a=p["a"], b=p["b"], gamma=p["gamma"], alpha0=p["alpha0"], window=int(p["window"]),
+              neg=int(p["neg"]), t=int(p["t"]), seed=int(p["seed"]))
+    ser = O.grad_sample(n, head, tail, w, xy, **kw)
+    win = O.grad_sample_window(n, head, tail, w, xy, **kw)
+    exp_s = np.array(case["serial"], np.float64).reshape(n, 2)
+    exp_w = np.array(case["window"], np.float64).reshape(n, 2)
+    assert np.allclose(ser, exp_s, rtol=2e-7, atol=1e-7), ser
+    assert np.allclose(win, exp_w, rtol=2e-7, atol=1e-7), win
+
+
+def test_serial_window_is_a_composition_of_single_entries():
+    """A window of s entries (no negative samples) equals s one-entry windows
+    applied in the same order at the same rate, and depends on the order."""
+    g = G.grid_2d(5, 6)
+    rng = np.random.default_rng(12)
+    head = np.repeat(np.arange(g.n), np.diff(g.row_ptr)).astype(np.int32)
+    tail = g.col_idx.astype(np.int32)
+    w = rng.uniform(0.2, 1.0, len(tail)).astype(np.float32)
+    xy = rng.uniform(-3, 3, (g.n, 2)).astype(np.float32)
+    m = len(tail)
+    kw = dict(a=A_UMAP, b=B_UMAP, alpha0=0.3, neg=0, t=1, seed=1)
+    whole = O.grad_sample(g.n, head, tail, w, xy, window=m, **kw)
+    step = xy.copy()
+    for e in range(m):
+        step = O.grad_sample(g.n, head[e:e + 1], tail[e:e + 1], w[e:e + 1], step, window=1, **kw)
+    # one-entry calls round the drawing to float after every entry
+    assert np.allclose(whole, step, rtol=0, atol=5e-6)
+    p = rng.permutation(m)
+    other = O.grad_sample(g.n, head[p], tail[p], w[p], xy, window=m, **kw)
+    assert np.abs(other.astype(float) - whole).max() > 1e-3
+
+
+def test_window_form_equals_serial_on_disjoint_entries():
+    """When no two entries of a window share a vertex (negative samples
+    included), the synchronous fixed-point form and the serial order agree up
+    to the 2^-33 rounding of each move."""
+    n, pairs, neg, seed = 4000, 40, 5, 4242
+    drawn = {O.splitmix64(seed, l * neg + q + 1) % n for l in range(pairs) for q in range(neg)}
+    free = np.array(sorted(set(range(n)) - drawn))
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(free)
+    head, tail = perm[:pairs].astype(np.int32), perm[pairs:2 * pairs].astype(np.int32)
+    w = rng.uniform(0.3, 1.0, pairs).astype(np.float32)
+    xy = rng.uniform(-10, 10, (n, 2)).astype(np.float32)
+    kw = dict(a=A_UMAP, b=B_UMAP, alpha0=1.0, window=pairs, neg=neg, t=3, seed=seed, it_begin=0, it_end=1)
+    ser = O.grad_sample(n, head, tail, w, xy, **kw).astype(np.float64)
+    win = O.grad_sample_window(n, head, tail, w, xy, **kw).astype(np.float64)
+    # grid rounding: the start position and each of at most neg + 1 moves
+    # by 2^-33, then both sides round to float once
+    ulp = np.spacing(np.abs(ser).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(ser - win) <= ulp + (neg + 2) * 2.0**-33)
+    assert np.mean(ser == win) > 0.98
 
 
 @pytest.mark.parametrize("m,s,t", [(37, 5, 20), (10, 10, 3), (11, 1, 25), (64, 63, 7)])
@@ -199,9 +297,9 @@ def test_learning_rate_decays_linearly():
 
 
 def test_synchronous_window_ignores_edge_order():
-    """One window over all edges (s = m, no negatives): permuting the edge
-    array leaves the result bit-identical, and each window equals the sum of
-    the single-edge moves."""
+    """The device's synchronous form: one window over all edges (s = m, no
+    negatives): permuting the edge array leaves the result bit-identical, and
+    each window equals the sum of the single-edge moves."""
     g = G.grid_2d(6, 7)
     rng = np.random.default_rng(2)
     head = np.repeat(np.arange(g.n), np.diff(g.row_ptr)).astype(np.int32)
@@ -210,14 +308,14 @@ def test_synchronous_window_ignores_edge_order():
     xy = rng.uniform(-3, 3, (g.n, 2)).astype(np.float32)
     m = len(tail)
     kw = dict(a=A_UMAP, b=B_UMAP, alpha0=0.3, window=m, neg=0, t=4, seed=1)
-    r1 = O.grad_sample(g.n, head, tail, w, xy, **kw)
+    r1 = O.grad_sample_window(g.n, head, tail, w, xy, **kw)
     p = rng.permutation(m)
-    r2 = O.grad_sample(g.n, head[p], tail[p], w[p], xy, **kw)
+    r2 = O.grad_sample_window(g.n, head[p], tail[p], w[p], xy, **kw)
     assert np.array_equal(r1, r2)
-    one = O.grad_sample(g.n, head, tail, w, xy, **dict(kw, t=1))
+    one = O.grad_sample_window(g.n, head, tail, w, xy, **dict(kw, t=1))
     acc = np.zeros((g.n, 2))
     for e in range(m):
-        single = O.grad_sample(g.n, head[e:e + 1], tail[e:e + 1], w[e:e + 1], xy, **dict(kw, window=1, t=1))
+        single = O.grad_sample_window(g.n, head[e:e + 1], tail[e:e + 1], w[e:e + 1], xy, **dict(kw, window=1, t=1))
         acc += single.astype(float) - xy
     assert np.allclose(one.astype(float) - xy, acc, atol=1e-6)
 
@@ -255,3 +353,24 @@ def test_grad_sample_argument_errors():
         O.grad_sample(2, head, np.array([2], np.int32), w, xy, a=1, b=1, window=1, t=1, seed=0)
     out = O.grad_sample(2, head, tail, w, xy, a=1, b=1, window=1, t=3, seed=0, it_begin=2, it_end=2)
     assert np.array_equal(out, xy)
+
+
+def test_window_form_with_one_entry_per_part_is_serial():
+    """With as many parts as entries, every part is one entry and the
+    synchronous form takes the entries one after the other: it then follows
+    the serial order up to the 2^-32 grid (on a grid graph, where the
+    entries of a window share vertices everywhere)."""
+    g = G.grid_2d(7, 6)
+    rng = np.random.default_rng(21)
+    head = np.repeat(np.arange(g.n), np.diff(g.row_ptr)).astype(np.int32)
+    tail = g.col_idx.astype(np.int32)
+    w = rng.uniform(0.2, 1.0, len(tail)).astype(np.float32)
+    xy = rng.uniform(-3, 3, (g.n, 2)).astype(np.float32)
+    m = len(tail)
+    s = m - 7
+    kw = dict(a=A_UMAP, b=B_UMAP, alpha0=0.5, window=s, neg=4, t=5, seed=31, it_begin=2, it_end=4)
+    ser = O.grad_sample(g.n, head, tail, w, xy, **kw)
+    one = O.grad_sample_window(g.n, head, tail, w, xy, parts=s, **kw)
+    whole = O.grad_sample_window(g.n, head, tail, w, xy, parts=1, **kw)
+    assert np.abs(one.astype(float) - ser).max() < 1e-5
+    assert np.abs(whole.astype(float) - ser).max() > 1e-2

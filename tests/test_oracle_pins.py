@@ -426,7 +426,7 @@ def test_hand_worked_example():
             assert np.allclose(w[0], gv["k%d_weights" % k], rtol=1e-6, atol=0)
 
 
-# ----------------------------------------------------- stress (Sec. 5.1) --
+# ----------------------------------------------------- stress (Sec. 4.1.3) --
 
 def _line_layout(n, scale=1.0):
     return np.stack([scale * np.arange(n), np.zeros(n)], 1).astype(np.float32)
@@ -507,7 +507,7 @@ def test_stress_brute_force_tiny_graphs():
         assert pairs == cnt and s == pytest.approx(tot, rel=1e-12, abs=1e-12)
 
 
-# ---------------------------------------- neighbourhood preservation (Sec. 5.1) --
+# ---------------------------------------- neighbourhood preservation (Sec. 4.1.3) --
 
 def test_neighborhood_line_and_lattice_drawings_score_one():
     """A path on a line and a grid at its lattice points keep every graph ball
