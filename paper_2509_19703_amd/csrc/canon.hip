@@ -518,12 +518,16 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t big_lds = (kBigRow + 32) * sizeof(int32_t);
-    static bool lds_set = false;
-    if (!lds_set) {
+    // the LDS limit is an attribute of the kernel on each device
+    static bool lds_set[64] = {};
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64 || !lds_set[dev]) {
         e = hipFuncSetAttribute((const void *)canon_big_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)big_lds);
         if (e != hipSuccess) return e;
-        lds_set = true;
+        if (dev >= 0 && dev < 64) lds_set[dev] = true;
     }
     hipLaunchKernelGGL(canon_big_kernel, dim3(512), dim3(kBigBlock), big_lds, s, row_ptr, col_idx,
                        out_col, cnt, big, counters);
