@@ -54,7 +54,8 @@ extern "C" {
 #define GUMAP_ERANGE (-3)    /* hop_matrix requested and a finite hop exceeds 254 */
 #define GUMAP_ENOMEM (-4)    /* device or host allocation failed */
 #define GUMAP_EDEVICE (-5)   /* HIP runtime error */
-#define GUMAP_E2BIG (-6)     /* served job larger than the server's memory budget */
+#define GUMAP_E2BIG (-6)     /* served job larger than the server's memory budget, or input too large
+                                for gumap_knn_partial_noalloc's fixed scratch */
 #define GUMAP_ENOTFOUND (-7) /* unknown or released ticket */
 
 /* Graph flags. */
@@ -153,6 +154,33 @@ int gumap_neighborhood(const gumap_graph *g, const float *xy, int32_t r, const i
  */
 int gumap_knn_partial(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
                       hipStream_t stream);
+
+/*
+ * gumap_knn_partial_noalloc: gumap_knn_partial for callers that cannot
+ * allocate device or host memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and kernels as gumap_knn_partial; it calls no hipMalloc, hipFree or other
+ * allocating routine.  The canonical CSR and the canonicalisation's work
+ * arrays live in one fixed device array of GUMAP_NOALLOC_SCRATCH_BYTES that
+ * each device the library runs on holds until the process ends; its address
+ * on a device is looked up on the first call there.
+ * Differences from gumap_knn_partial:
+ *   - GUMAP_VALIDATE is rejected (GUMAP_EINVAL): validation reads its result
+ *     back through pinned host memory that the library allocates;
+ *   - without GUMAP_CSR_SORTED the graph must fit the fixed scratch:
+ *     256-byte-rounded 4 (n + 1) + 4 nnz bytes for the canonical CSR plus the
+ *     canonicalisation's work arrays (about 12 n + 4 nnz bytes more); a larger
+ *     one returns GUMAP_E2BIG (with GUMAP_CSR_SORTED no scratch is used and
+ *     any size is accepted);
+ *   - every call on a device shares that device's array, so calls that
+ *     overlap on one device (from several processes' streams, or a captured
+ *     graph replayed while a call runs) race; calls from threads of one
+ *     process are serialised like every other call.
+ * Errors: GUMAP_EINVAL, GUMAP_E2BIG, GUMAP_EDEVICE.
+ */
+#define GUMAP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int gumap_knn_partial_noalloc(const gumap_graph *g, int32_t k, int32_t *nbr_ids, uint8_t *nbr_hops,
+                              hipStream_t stream);
 
 /*
  * UMAP fuzzy membership of kNN rows (Sec. 2.1): per row with K valid

@@ -142,7 +142,8 @@ def _load() -> ctypes.CDLL:
     lib.gumap_batch_plan_destroy.restype = None
     lib.gumap_batch_plan_tuning.argtypes = [vp, ctypes.POINTER(gumap_batch_tuning)]
     lib.gumap_batch_plan_tuning.restype = ctypes.c_int
-    for f in (lib.gumap_knn_build, lib.gumap_knn_partial, lib.gumap_membership,
+    lib.gumap_knn_partial_noalloc.argtypes = [G, i32, vp, vp, vp]
+    for f in (lib.gumap_knn_build, lib.gumap_knn_partial, lib.gumap_membership, lib.gumap_knn_partial_noalloc,
               lib.gumap_knn_partial_batch, lib.gumap_batch_plan_create, lib.gumap_batch_plan_launch):
         f.restype = ctypes.c_int
     lib.gumap_profile_enable.argtypes = [ctypes.c_int]
@@ -258,6 +259,11 @@ def gumap_knn_partial(graph: gumap_graph, k: int, nbr_ids, nbr_hops, stream=None
                                         _stream(stream)))
 
 
+def gumap_knn_partial_noalloc(graph: gumap_graph, k: int, nbr_ids, nbr_hops, stream=None) -> int:
+    return _check(lib.gumap_knn_partial_noalloc(ctypes.byref(graph), k, _ptr(nbr_ids), _ptr(nbr_hops),
+                                                _stream(stream)))
+
+
 def gumap_membership(rows: int, k: int, nbr_hops, weights, rho=None, sigma=None, stream=None) -> int:
     return _check(lib.gumap_membership(rows, k, _ptr(nbr_hops), _ptr(weights), _ptr(rho), _ptr(sigma),
                                        _stream(stream)))
@@ -267,6 +273,11 @@ def gumap_knn_partial_batch(batch: gumap_batch, k: int, nbr_ids, nbr_hops, weigh
                             sigma=None, stream=None) -> int:
     return _check(lib.gumap_knn_partial_batch(ctypes.byref(batch), k, _ptr(nbr_ids), _ptr(nbr_hops),
                                               _ptr(weights), _ptr(rho), _ptr(sigma), _stream(stream)))
+
+
+# Bytes of gumap_knn_partial_noalloc's fixed device scratch
+# (GUMAP_NOALLOC_SCRATCH_BYTES of the header).
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 # ------------------------------------------------------ allocating helpers ---
