@@ -33,6 +33,16 @@ size_t exclusive_scan_scratch_bytes(int64_t len);
 hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t len, void *scratch,
                                  hipStream_t s);
 
+// Stable LSD radix sort of (key, value) pairs by key bits [begin_bit,
+// end_bit), 8 bits per pass, count < 2^31 (hipErrorInvalidValue otherwise).
+// The passes alternate between (keys, vals) and (keys_alt, vals_alt); the
+// result is in the _alt pair when *in_alt is set on return.  scratch:
+// radix_sort_scratch_bytes(count).
+size_t radix_sort_scratch_bytes(int64_t count);
+template <typename K>
+hipError_t radix_sort_pairs(K *keys, K *keys_alt, uint32_t *vals, uint32_t *vals_alt, int64_t count, int begin_bit,
+                            int end_bit, void *scratch, hipStream_t s, bool *in_alt);
+
 // ------------------------------------------------------ all-source BFS ---
 // Multi-source bit-parallel BFS over groups of W = 64 * words sources.
 // Layout of every state array: [group][vertex][word] of uint64.

@@ -3,10 +3,10 @@
 // graph symmetric, the keyed shuffle of its edge array E_k and the
 // sliding-window gradient iterations.
 //
-// Union and shuffle are sorts: every directed kNN cell emits at most two
-// (row, col) keys with their union weight, one radix sort orders them and a
-// segment pass writes the CSR; the shuffle sorts the entries by a
-// SplitMix64 key of their position.  GradSample first sorts the 2m
+// Union and shuffle are sorts (the stable radix sort of radix_sort.hip):
+// every directed kNN cell emits at most two (row, col) keys with their union
+// weight, one radix sort orders them and a segment pass writes the CSR; the
+// shuffle sorts the entries by a SplitMix64 key of their position.  GradSample first sorts the 2m
 // incidences (each array entry at its head and at its tail) by vertex.  A
 // window is then two launches: a thread per window entry computes the
 // entry's moves from the positions at the start of the window (its own steps
@@ -19,7 +19,6 @@
 // (device-wide 64-bit atomics on one address serialise, and a high-degree
 // vertex receives thousands of moves per window).
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 #include <stdint.h>
 
@@ -428,12 +427,7 @@ int union_key_bits(int32_t rows)
 size_t union_scratch_bytes(int32_t rows, int32_t k, size_t *sort_tmp)
 {
     const int64_t total = 2 * (int64_t)rows * k;
-    size_t tmp = 0;
-    hipcub::DoubleBuffer<uint64_t> kb(nullptr, nullptr);
-    hipcub::DoubleBuffer<float> vb(nullptr, nullptr);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)total, 0, union_key_bits(rows),
-                                             (hipStream_t)0);
-    tmp = (tmp + 255) & ~(size_t)255;
+    size_t tmp = (radix_sort_scratch_bytes(total) + 255) & ~(size_t)255;
     *sort_tmp = tmp;
     const size_t t = (size_t)(total > 0 ? total : 1);
     return tmp + 2 * t * sizeof(uint64_t) + 2 * t * sizeof(float) + 1024;
@@ -456,22 +450,17 @@ hipError_t launch_fuzzy_union(int32_t rows, int32_t k, const int32_t *ids, const
                        v0, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
-    hipcub::DoubleBuffer<float> vb(v0, v1);
-    e = hipcub::DeviceRadixSort::SortPairs(p, tmp, kb, vb, (int)total, 0, union_key_bits(rows), s);
+    bool alt = false;
+    e = radix_sort_pairs<uint64_t>(k0, k1, (uint32_t *)v0, (uint32_t *)v1, total, 0, union_key_bits(rows), p, s, &alt);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(union_rows_kernel, dim3(grid_for(total)), dim3(kLayoutBlock), 0, s, rows, total,
-                       (const uint64_t *)kb.Current(), (const float *)vb.Current(), row_ptr, col, val, cap, nnz);
+                       (const uint64_t *)(alt ? k1 : k0), (const float *)(alt ? v1 : v0), row_ptr, col, val, cap, nnz);
     return hipGetLastError();
 }
 
 size_t shuffle_scratch_bytes(int64_t m, size_t *sort_tmp)
 {
-    size_t tmp = 0;
-    hipcub::DoubleBuffer<uint64_t> kb(nullptr, nullptr);
-    hipcub::DoubleBuffer<int32_t> vb(nullptr, nullptr);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)m, 0, 64, (hipStream_t)0);
-    tmp = (tmp + 255) & ~(size_t)255;
+    size_t tmp = (radix_sort_scratch_bytes(m) + 255) & ~(size_t)255;
     *sort_tmp = tmp;
     const size_t t = (size_t)(m > 0 ? m : 1);
     return tmp + 2 * t * sizeof(uint64_t) + 2 * t * sizeof(int32_t) + 1024;
@@ -491,12 +480,11 @@ hipError_t launch_edge_shuffle(int32_t n, int64_t m, const int32_t *row_ptr, con
     hipLaunchKernelGGL(shuffle_keys_kernel, dim3(grid_for(m)), dim3(kLayoutBlock), 0, s, m, seed, k0, o0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipcub::DoubleBuffer<uint64_t> kb(k0, k1);
-    hipcub::DoubleBuffer<int32_t> ob(o0, o1);
-    e = hipcub::DeviceRadixSort::SortPairs(p, tmp, kb, ob, (int)m, 0, 64, s);
+    bool alt = false;
+    e = radix_sort_pairs<uint64_t>(k0, k1, (uint32_t *)o0, (uint32_t *)o1, m, 0, 64, p, s, &alt);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(shuffle_gather_kernel, dim3(grid_for(m)), dim3(kLayoutBlock), 0, s, n, m, row_ptr, col, val,
-                       (const int32_t *)ob.Current(), head, tail, w);
+                       (const int32_t *)(alt ? o1 : o0), head, tail, w);
     return hipGetLastError();
 }
 
@@ -520,13 +508,8 @@ hipError_t launch_layout_out(int32_t n, const long long *p, float *xy, hipStream
 
 size_t incidence_scratch_bytes(int32_t n, int64_t m, size_t *sort_tmp)
 {
-    size_t tmp = 0;
-    hipcub::DoubleBuffer<uint32_t> kb(nullptr, nullptr);
-    hipcub::DoubleBuffer<uint32_t> vb(nullptr, nullptr);
-    int bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)n) ++bits;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)(2 * m), 0, bits, (hipStream_t)0);
-    tmp = (tmp + 255) & ~(size_t)255;
+    (void)n;
+    size_t tmp = (radix_sort_scratch_bytes(2 * m) + 255) & ~(size_t)255;
     *sort_tmp = tmp;
     const size_t t = (size_t)(2 * m);
     return tmp + 3 * t * sizeof(uint32_t) + 1024;
@@ -546,16 +529,15 @@ hipError_t launch_layout_incidence(LayoutArgs &g, void *scratch, int32_t *off, u
     if (e != hipSuccess) return e;
     int bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) < (int64_t)g.n) ++bits;
-    hipcub::DoubleBuffer<uint32_t> kb(k0, k1);
-    hipcub::DoubleBuffer<uint32_t> cb(c0, code);   // the sorted codes may end in either buffer
-    e = hipcub::DeviceRadixSort::SortPairs(p, tmp, kb, cb, (int)total, 0, bits, s);
+    bool alt = false;   // the sorted codes may end in either buffer
+    e = radix_sort_pairs<uint32_t>(k0, k1, c0, code, total, 0, bits, p, s, &alt);
     if (e != hipSuccess) return e;
-    if (cb.Current() != code) {
-        e = hipMemcpyAsync(code, cb.Current(), (size_t)total * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (!alt) {
+        e = hipMemcpyAsync(code, c0, (size_t)total * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(incidence_rows_kernel, dim3(grid_for(total)), dim3(kLayoutBlock), 0, s, g.n, total,
-                       (const uint32_t *)kb.Current(), off);
+                       (const uint32_t *)(alt ? k1 : k0), off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = hipMemsetAsync(n_heavy, 0, sizeof(int32_t), s);
     if (e != hipSuccess) return e;

@@ -20,7 +20,6 @@
 // labels compressed, until no component gains an edge.  The remaining
 // edges are ranked by a stable radix sort on the resistance bits.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 #include <stdint.h>
 
@@ -573,11 +572,7 @@ hipError_t launch_forest_round(const SparsifyArgs &a, const double *R, int *adde
 
 size_t rank_scratch_bytes(int64_t m, size_t *sort_tmp)
 {
-    size_t tmp = 0;
-    hipcub::DoubleBuffer<unsigned long long> kb(nullptr, nullptr);
-    hipcub::DoubleBuffer<int32_t> vb(nullptr, nullptr);
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)m, 0, 64, (hipStream_t)0);
-    tmp = (tmp + 255) & ~(size_t)255;
+    size_t tmp = (radix_sort_scratch_bytes(m) + 255) & ~(size_t)255;
     *sort_tmp = tmp;
     const size_t t = (size_t)(m > 0 ? m : 1);
     return tmp + 2 * t * sizeof(unsigned long long) + 4 * t * sizeof(int32_t) + exclusive_scan_scratch_bytes(m) + 4096;
@@ -596,17 +591,16 @@ hipError_t launch_take_top(const SparsifyArgs &a, const double *R, int64_t need,
     hipLaunchKernelGGL(ss_rank_keys_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, R, k0, o0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipcub::DoubleBuffer<unsigned long long> kb(k0, k1);
-    hipcub::DoubleBuffer<int32_t> ob(o0, o1);
-    e = hipcub::DeviceRadixSort::SortPairs(p, tmp, kb, ob, (int)a.m, 0, 64, s);   // stable: ties keep index order
+    bool alt = false;   // stable: ties keep index order
+    e = radix_sort_pairs<unsigned long long>(k0, k1, (uint32_t *)o0, (uint32_t *)o1, a.m, 0, 64, p, s, &alt);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ss_rest_flags_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m,
-                       (const int32_t *)ob.Current(), a.keep, flags);
+    const int32_t *order = alt ? o1 : o0;
+    hipLaunchKernelGGL(ss_rest_flags_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, order, a.keep, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = launch_exclusive_scan(flags, pos, a.m, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ss_take_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, (const int32_t *)ob.Current(),
-                       flags, pos, need, a.keep);
+    hipLaunchKernelGGL(ss_take_kernel, dim3(ss_grid(a.m)), dim3(kSsBlock), 0, s, a.m, order, flags, pos, need,
+                       a.keep);
     return hipGetLastError();
 }
 
