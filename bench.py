@@ -1,8 +1,8 @@
 """Benchmark of the BFS-kNN hot path on one MI355X.
 
-One step = the whole hot path over the Barabasi-Albert workload (n = 100,000,
-4 edges per new vertex, m = 399,990; seeded synthetic input standing in for
-the paper's scale-free graphs):
+The headline step is the whole hot path over the Barabasi-Albert workload
+(n = 100,000, 4 edges per new vertex, m = 399,990; seeded synthetic input
+standing in for the paper's scale-free graphs):
   1. CSR ingest: canonicalise the input CSR (its rows arrive unsorted);
   2. all-source BFS hop distances from 4,096 seeded sample sources, written as
      a uint8 hop matrix (409.6 MB), and the (hop, id) kNN of those rows, k = 15;
@@ -11,7 +11,15 @@ the paper's scale-free graphs):
 value = Graph500-convention GTEPS of the step: 4,096 sources x m undirected
 edges (the graph is connected) divided by the whole step's time.
 
-Prints one JSON line.  --gpus > 1 is refused (one-GPU build).
+The default run (--workload all) adds the rest of the metric under
+"workloads": the 32 x 32 grid and the dense Erdos-Renyi graph (GTEPS of the
+all-source path), the batch of 2,048 uneven graphs (graphs/s batched against
+the plain per-graph loop) and the served stream of 4,096 distinct jobs (p50 /
+p99 latency and graphs/s against the plain loop), each with its parity check,
+roofline and CPU-oracle baseline.
+
+Prints one JSON line (progress goes to stderr).  --gpus > 1 is refused
+(one-GPU build).
 """
 from __future__ import annotations
 
@@ -31,12 +39,12 @@ METRIC = "GTEPS + kNN graphs/sec vs plain; p50/p99 served latency, bit-exact"
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--workload", default="ba100k", choices=["ba100k", "grid", "er", "batch", "serve", "stress", "neighborhood",
-                                                             "layout", "sparsify"])
+    p.add_argument("--workload", default="all", choices=["all", "ba100k", "grid", "er", "batch", "serve", "stress",
+                                                          "neighborhood", "layout", "sparsify"])
     p.add_argument("--layout-iters", type=int, default=200)
     p.add_argument("--batch-graphs", type=int, default=2048)
-    p.add_argument("--serve-jobs", type=int, default=1024)
-    p.add_argument("--serve-pool", type=int, default=64)
+    p.add_argument("--serve-jobs", type=int, default=4096)
+    p.add_argument("--serve-warmup", type=int, default=256)
     p.add_argument("--serve-budget-gb", type=float, default=64.0)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
@@ -44,7 +52,8 @@ def parse():
     p.add_argument("--sources", type=int, default=4096)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-parity", action="store_true")
-    p.add_argument("--cpu-sample-sources", type=int, default=1024)
+    p.add_argument("--cpu-one-thread-fraction", type=int, default=8,
+                   help="the one-thread oracle time is measured on 1/N of each workload and scaled")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     p.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -65,18 +74,14 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(one GPU's share of the work is what it runs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-
-    import graphgen as G
-    import paper_2509_19703_amd as gm
-
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload in ("grid", "er"):
-        return bench_allsource(args)
+    if args.calibrate_copy:
+        return calibrate_copy()
+    single = {"batch": run_batch, "serve": run_serve, "grid": lambda a: run_allsource(a, "grid"),
+              "er": lambda a: run_allsource(a, "er"), "ba100k": run_ba}
+    if args.workload in single:
+        out = single[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "stress":
         return bench_stress(args)
     if args.workload == "neighborhood":
@@ -85,19 +90,92 @@ def main():
         return bench_layout(args)
     if args.workload == "sparsify":
         return bench_sparsify(args)
+    # all: the headline BA step, then the other workloads of the metric
+    t_all = time.perf_counter()
+    _progress("ba100k")
+    out = run_ba(args)
+    subs = {}
+    for name, fn in (("grid32", lambda: run_allsource(args, "grid")), ("er16k", lambda: run_allsource(args, "er")),
+                     ("batch2048", lambda: run_batch(args)), ("stream%d" % args.serve_jobs, lambda: run_serve(args))):
+        _progress(name)
+        subs[name] = _sub(fn())
+    out["workloads"] = subs
+    b = subs["batch2048"]
+    v = subs["stream%d" % args.serve_jobs]
+    out["knn_graphs_per_s_batched"] = b["value"]
+    out["knn_graphs_per_s_plain_loop"] = b["graphs_per_s_plain_loop"]
+    out["batched_vs_plain"] = b["speedup_vs_plain"]
+    out["served_graphs_per_s"] = v["value"]
+    out["served_saturation_graphs_per_s"] = v["saturation_graphs_per_s"]
+    out["served_vs_plain"] = v["speedup_vs_plain"]
+    out["served_p50_ms"] = v["p50_ms"]
+    out["served_p99_ms"] = v["p99_ms"]
+    out["parity_all_workloads"] = bool(out.get("parity_sampled_bit_exact", True) and all(
+        w.get("parity_sampled_bit_exact", True) for w in subs.values()))
+    out["bench_wall_s"] = time.perf_counter() - t_all
+    print(json.dumps(out), flush=True)
 
-    if args.calibrate_copy:
-        n_bytes = 1 << 30
-        a = torch.empty(n_bytes // 4, dtype=torch.int32, device="cuda")
-        b_ = torch.empty_like(a)
-        a.fill_(1)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            b_.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n_bytes,
-                          "bytes_written_per_copy": n_bytes, "copies": 3}), flush=True)
-        return
+
+def _progress(name):
+    print("bench: %s" % name, file=sys.stderr, flush=True)
+
+
+def _sub(d):
+    """A workload's record inside the headline line (the top-level keys that
+    only describe the line itself are dropped)."""
+    return {key: val for key, val in d.items() if key not in ("metric", "n_gpus", "higher_is_better", "scaling",
+                                                              "vs_baseline", "data")}
+
+
+def calibrate_copy():
+    """A plain 1 GiB device copy, the reference for the HBM byte counters."""
+    import torch
+    n_bytes = 1 << 30
+    a = torch.empty(n_bytes // 4, dtype=torch.int32, device="cuda")
+    b_ = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b_.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n_bytes,
+                      "bytes_written_per_copy": n_bytes, "copies": 3}), flush=True)
+
+
+def cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def cpu_block(work, unit, t_all, threads, t_one, sample):
+    """cpu_baseline record: `work` units of the workload took t_all seconds on
+    `threads` threads and t_one (estimated) on one thread."""
+    return {"value": work / t_all, "unit": unit, "cores": threads, "kind": "oracle", "sample": sample,
+            "seconds_all_cores": t_all, "value_one_thread": work / t_one, "seconds_one_thread": t_one,
+            "cpu_model": cpu_model()}
+
+
+def run_ba(args):
+    """The headline step on the BA graph (canonicalise, all-source BFS from
+    4,096 sources with the hop matrix and kNN, partial BFS from every vertex,
+    membership)."""
+    import numpy as np
+    import torch
+
+    import graphgen as G
+    import paper_2509_19703_amd as gm
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -174,7 +252,7 @@ def main():
                      "alg_bytes_per_launch": d["alg_bytes"] / d["launches"]},
         "kernels_ms_per_step": {kname: v["total_ms"] / args.steps for kname, v in prof.items()},
         "ms_per_step_without_events": dt_plain * 1e3,
-        "knn_graphs_per_s": 1.0 / dt,
+        "steps_per_s": 1.0 / dt,
     }
     if not args.no_parity:
         import oracle as O
@@ -189,8 +267,8 @@ def main():
             and np.array_equal(p_hops[torch.from_numpy(vs).to(dev)].cpu().numpy(), ph)
         out["parity_sampled_bit_exact"] = bool(ok)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, src, k, m, args.cpu_sample_sources)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline_ba(g, src, k, m, args.cpu_one_thread_fraction)
+    return out
 
 
 def _profiled(gm, fn, steps):
@@ -246,16 +324,17 @@ def _roofline(prof, steps, dom):
         {kname: v["total_ms"] / steps for kname, v in prof.items()}
 
 
-def bench_allsource(args):
+def run_allsource(args, which):
     """Plain GUMAP C0 + C1 on one graph: all-source BFS with the uint8 hop
-    matrix, (hop, id) kNN and membership (32x32 grid or dense ER)."""
+    matrix, (hop, id) kNN and membership (the 32 x 32 grid, or the dense ER
+    graph the paper flags as costly)."""
     import numpy as np
     import torch
 
     import graphgen as G
     import paper_2509_19703_amd as gm
     k = args.k
-    g = G.config_grid() if args.workload == "grid" else G.config_er()
+    g = G.config_grid() if which == "grid" else G.config_er()
     n, m = g.n, g.m
     rp = torch.from_numpy(g.row_ptr).cuda()
     ci = torch.from_numpy(g.col_idx).cuda()
@@ -280,28 +359,50 @@ def bench_allsource(args):
     out = {"metric": METRIC, "value": n * m / dt / 1e9, "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": "%s: all-source BFS with uint8 hop matrix, (hop,id) kNN k=%d, FP32 membership"
-                                  % (g.name or args.workload, k), "n": n, "m": m, "k": k},
+           "config": {"workload": "%s: all-source BFS from all %d vertices with uint8 hop matrix, (hop,id) kNN "
+                                  "k=%d, FP32 membership" % (g.name or which, n, k), "n": n, "m": m, "k": k},
            "roofline": roof, "kernels_ms_per_step": kms}
     if not args.no_parity:
         import oracle as O
-        pick = np.arange(0, n, max(1, n // 64))
-        oi, oh, ohm = O.knn_build(g, k, sources=pick, hop_matrix=True)
-        pt = torch.from_numpy(pick).cuda()
-        out["parity_sampled_bit_exact"] = bool(np.array_equal(ids[pt].cpu().numpy(), oi)
-                                               and np.array_equal(hops[pt].cpu().numpy(), oh)
-                                               and np.array_equal(hm[pt].cpu().numpy(), ohm))
+        if which == "grid":
+            oi, oh, ohm = O.knn_build(g, k, hop_matrix=True)
+            ok = (np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
+                  and np.array_equal(hm.cpu().numpy(), ohm))
+            out["parity_sample"] = "every row against the oracle (ids, hops, hop matrix)"
+        else:
+            pick = np.arange(0, n, max(1, n // 64))
+            oi, oh, ohm = O.knn_build(g, k, sources=pick, hop_matrix=True)
+            pt = torch.from_numpy(pick).cuda()
+            ok = (np.array_equal(ids[pt].cpu().numpy(), oi) and np.array_equal(hops[pt].cpu().numpy(), oh)
+                  and np.array_equal(hm[pt].cpu().numpy(), ohm))
+            # every row against the diameter-2 closed form: 0 on the diagonal,
+            # 1 for an edge, 2 otherwise (the oracle's BFS certifies diameter 2
+            # on the sampled rows)
+            exp = torch.full((n, n), 2, dtype=torch.uint8, device="cuda")
+            rows = torch.repeat_interleave(torch.arange(n, device="cuda"), rp[1:] - rp[:-1])
+            exp[rows, ci.long()] = 1
+            exp.fill_diagonal_(0)
+            ok = ok and bool(torch.equal(exp, hm)) and int(ohm.max()) <= 2
+            del exp
+            out["parity_sample"] = ("%d rows against the oracle; every row against the closed form (1 if adjacent, "
+                                    "else 2)" % len(pick))
+        out["parity_sampled_bit_exact"] = bool(ok)
     if not args.no_cpu_baseline:
         import oracle as O
         threads = O.default_threads()
-        sub = np.arange(0, n, max(1, n // (n if n <= 2048 else 256)))
-        t0 = time.perf_counter()
-        _, oh, _ = O.knn_build(g, k, sources=sub, hop_matrix=True, threads=threads)
-        t_b = (time.perf_counter() - t0) * n / len(sub)
-        t = t_b
-        out["cpu_baseline"] = {"value": n * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-                               "sample": "oracle all-source BFS + kNN from %d of %d sources, scaled" % (len(sub), n)}
-    print(json.dumps(out), flush=True)
+        if which == "grid":
+            t_all = _timed(lambda: O.knn_build(g, k, hop_matrix=True, threads=threads))
+            t_one = _timed(lambda: O.knn_build(g, k, hop_matrix=True, threads=1))
+            sample = "oracle: all %d sources on all %d host threads, and on one thread" % (n, threads)
+        else:
+            sub = np.arange(0, n, 16, dtype=np.int32)
+            one = np.arange(0, n, 256, dtype=np.int32)
+            t_all = _timed(lambda: O.knn_build(g, k, sources=sub, hop_matrix=True, threads=threads)) * n / len(sub)
+            t_one = _timed(lambda: O.knn_build(g, k, sources=one, hop_matrix=True, threads=1)) * n / len(one)
+            sample = ("oracle: %d of the %d sources on all %d host threads, %d on one thread, each scaled to all "
+                      "sources" % (len(sub), n, threads, len(one)))
+        out["cpu_baseline"] = cpu_block(n * m / 1e9, "GTEPS", t_all, threads, t_one, sample)
+    return out
 
 
 def bench_stress(args):
@@ -522,17 +623,20 @@ def bench_layout(args):
             chk = xy0_d.clone()
             p = gm.layout_params(t=t, neg=5, samp=0.9, seed=seed_neg)
             gm.gumap_grad_sample(n, chk, mm, head, tail, ew, p, 0, few, stream)
+            wxy = O.grad_sample_window(n, eh, et, ew_, xy0, a=gm.UMAP_A, b=gm.UMAP_B, window=s_win, neg=5, t=t,
+                                       seed=seed_neg, it_begin=0, it_end=few, parts=gm.LAYOUT_DEFAULT_PARTS)
             out["parity_sampled_bit_exact"] = bool(
                 len(ocol) == mm and np.array_equal(head[:mm].cpu().numpy(), eh)
-                and np.array_equal(tail[:mm].cpu().numpy(), et) and np.array_equal(chk.cpu().numpy(), oxy))
+                and np.array_equal(tail[:mm].cpu().numpy(), et) and np.array_equal(chk.cpu().numpy(), wxy))
             out["parity_sample"] = ("union + shuffled E_k, and the drawing after the first %d iterations from a "
-                                    "seeded uniform drawing" % few)
+                                    "seeded uniform drawing against the oracle of the device's synchronous "
+                                    "parts (the serial order of Alg. 5 is checked by the tests)" % few)
         if not args.no_cpu_baseline:
             est = t_prep + t * t_win
             out["cpu_baseline"] = {"value": samples / est, "unit": "edge samples/s", "cores": threads,
                                    "kind": "oracle",
                                    "sample": "oracle kNN/membership/union/shuffle in full (%d threads) and %d of %d "
-                                             "GradSample iterations (one thread), scaled; the spectral drawing is "
+                                             "GradSample iterations in the serial order (one thread), scaled; the spectral drawing is "
                                              "left out (the oracle's dense eigendecomposition does not scale to "
                                              "n = 100,000); run estimate %.1f s" % (threads, few, t, est)}
     print(json.dumps(out), flush=True)
@@ -623,7 +727,7 @@ def bench_sparsify(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args):
+def run_batch(args):
     """Many uneven graphs: partial BFS kNN + membership for every vertex of
     every graph, as one persistent launch (captured plan) against the plain
     per-graph loop (two synchronous calls per graph)."""
@@ -714,38 +818,47 @@ def bench_batch(args):
            "host_generation_s": t_gen}
     if not args.no_parity:
         import oracle as O
-        ok = True
-        for i in range(0, ng, max(1, ng // 24)):
+        ok = same_plain and same_plan
+        wmax = 0.0
+        for i in range(0, ng, max(1, ng // 32)):
             oi, oh = O.knn_partial(graphs[i], k)
+            ow, orho, _ = O.membership(oh, k)
             r0, r1 = int(voff[i]), int(voff[i + 1])
-            ok = ok and np.array_equal(ref[0][r0:r1], oi) and np.array_equal(ref[1][r0:r1], oh)
-        out["parity_sampled_bit_exact"] = bool(ok)
+            ok = ok and np.array_equal(ref[0][r0:r1], oi) and np.array_equal(ref[1][r0:r1], oh) \
+                and np.array_equal(ref[3][r0:r1], orho)
+            err = np.abs(ref[2][r0:r1].astype(np.float64) - ow) - (1e-5 * np.abs(ow) + 2.0**-126)
+            wmax = max(wmax, float(err.max()) if err.size else 0.0)
+        out["parity_sampled_bit_exact"] = bool(ok and wmax <= 0.0)
+        out["parity_sample"] = ("ids, hops and rho bit-exact, weights within 1e-5 relative, on every row of %d of "
+                                "the %d graphs; the batched call and the plan replay equal to the plain loop on "
+                                "every row" % (len(range(0, ng, max(1, ng // 32))), ng))
     if not args.no_cpu_baseline:
         import oracle as O
         threads = O.default_threads()
-        pick = list(range(0, ng, 8))
-        t0 = time.perf_counter()
-        for i in pick:
-            _, oh = O.knn_partial(graphs[i], k, threads=threads)
-            O.membership(oh, k, threads=threads)
-        t = (time.perf_counter() - t0) * ng / len(pick)
-        out["cpu_baseline"] = {"value": ng / t, "unit": "graphs/s", "cores": threads, "kind": "oracle",
-                               "sample": "oracle partial BFS + membership on %d of the %d graphs, scaled"
-                                         % (len(pick), ng)}
-    print(json.dumps(out), flush=True)
+        frac = args.cpu_one_thread_fraction
+
+        def run(sel, th):
+            for i in sel:
+                _, oh = O.knn_partial(graphs[i], k, threads=th)
+                O.membership(oh, k, threads=th)
+
+        t_all = _timed(lambda: run(range(ng), threads))
+        one = range(0, ng, frac)
+        scale = sum(g.nnz + g.n for g in graphs) / max(1, sum(graphs[i].nnz + graphs[i].n for i in one))
+        t_one = _timed(lambda: run(one, 1)) * scale
+        out["cpu_baseline"] = cpu_block(ng, "graphs/s", t_all, threads, t_one,
+                                        "oracle partial BFS + membership: all %d graphs on all %d host threads; every "
+                                        "%dth graph on one thread, scaled by vertices + entries (x%.1f)"
+                                        % (ng, threads, frac, scale))
+    return out
 
 
-def _gen_job_graph(job):
-    import graphgen as G
-    g = G.stream_job_graph(job)
-    return g.n, g.row_ptr, g.col_idx
-
-
-def bench_serve(args):
+def run_serve(args):
     """Served request stream: jobs (graph + k) arrive by a Poisson process at
-    0.8 x the measured saturation rate; latency submit -> done per job."""
-    import multiprocessing as mp
+    0.8 x the measured saturation rate; latency submit -> done per job.  Every
+    job is a distinct graph of the stream's generator mix."""
     import threading
+    from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
     import torch
@@ -753,21 +866,22 @@ def bench_serve(args):
     import graphgen as G
     import paper_2509_19703_amd as gm
     jobs = G.config_stream_jobs(args.serve_jobs)
-    pool_n = min(args.serve_pool, len(jobs))
+    nj = len(jobs)
+    warm = min(args.serve_warmup, nj // 2)
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        graphs = pool.map(_gen_job_graph, jobs[:pool_n])
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:   # the generators run in C, off the GIL
+        graphs = list(ex.map(G.stream_job_graph, jobs))
     t_gen = time.perf_counter() - t0
-    gk = [(graphs[i % pool_n], jobs[i]["k"]) for i in range(len(jobs))]
+    ks = [j["k"] for j in jobs]
     budget = int(args.serve_budget_gb * (1 << 30))
-    warm = max(1, len(jobs) // 8)
     server = gm.Server(budget)
-    # warm-up burst (first launches load code objects), then saturation:
-    # everything submitted at once; rate from the server's own clock
-    for t in [server.submit(rp, ci, k) for (n, rp, ci), k in gk[:warm]]:
+    # warm-up burst (first launches load code objects), then a saturation
+    # burst of distinct jobs submitted at once; rate from the server's clock
+    for t in [server.submit(graphs[i].row_ptr, graphs[i].col_idx, ks[i]) for i in range(warm)]:
         server.wait(t, copy_results=False)
         server.release(t)
-    tk = [server.submit(rp, ci, k) for (n, rp, ci), k in gk[warm:warm * 3]]
+    sat_jobs = list(range(warm, min(nj, warm + 1024)))
+    tk = [server.submit(graphs[i].row_ptr, graphs[i].col_idx, ks[i]) for i in sat_jobs]
     t_first = t_last = None
     for t in tk:
         r = server.wait(t, copy_results=False)
@@ -776,84 +890,120 @@ def bench_serve(args):
         t_last = r["t_done_ns"] if t_last is None else max(t_last, r["t_done_ns"])
     sat_rate = len(tk) / ((t_last - t_first) / 1e9)
     rate = 0.8 * sat_rate
-    # Poisson arrivals at `rate`
-    gaps = -np.log1p(-G.uniform(G.BASE_SEED + 200, len(jobs))) / rate
+    # Poisson arrivals at `rate` over the whole stream (its first `warm` jobs
+    # are left out of the statistics)
+    gaps = -np.log1p(-G.uniform(G.BASE_SEED + 200, nj)) / rate
     arrivals = np.cumsum(gaps)
-    tickets = [None] * len(jobs)
+    tickets = [None] * nj
+    check = set(np.linspace(warm, nj - 1, 8).astype(int).tolist()) if not args.no_parity else set()
 
     def submitter():
         start = time.perf_counter()
-        for i, ((n, rp, ci), k) in enumerate(gk):
+        for i in range(nj):
             delay = arrivals[i] - (time.perf_counter() - start)
             if delay > 0:
                 time.sleep(delay)
-            tickets[i] = server.submit(rp, ci, k)
+            tickets[i] = server.submit(graphs[i].row_ptr, graphs[i].col_idx, ks[i])
 
     th = threading.Thread(target=submitter)
     t_start = time.perf_counter()
     th.start()
     lat = []
-    first_done = last_done = None
-    for i in range(len(jobs)):
+    first_sub = last_done = None
+    kept = {}
+    for i in range(nj):
         while tickets[i] is None:
             time.sleep(0.0002)
-        r = server.wait(tickets[i], copy_results=(i == 3 and not args.no_parity))
+        r = server.wait(tickets[i], copy_results=(i in check))
         if r["status"] != gm.OK:
             raise RuntimeError("job %d failed: %d" % (i, r["status"]))
         if i >= warm:
             lat.append((r["t_done_ns"] - r["t_submit_ns"]) / 1e6)
-            first_done = r["t_submit_ns"] if first_done is None else first_done
-            last_done = r["t_done_ns"]
-        if i == 3 and not args.no_parity:
-            keep = r
+            first_sub = r["t_submit_ns"] if first_sub is None else min(first_sub, r["t_submit_ns"])
+            last_done = r["t_done_ns"] if last_done is None else max(last_done, r["t_done_ns"])
+        if i in check:
+            kept[i] = r
         server.release(tickets[i])
     th.join()
     t_total = time.perf_counter() - t_start
     stats = server.stats()
+    server.close()
     lat = np.array(lat)
-    measured = len(jobs) - warm
-    out = {"metric": METRIC, "value": measured / ((last_done - first_done) / 1e9), "unit": "graphs/s",
-           "n_gpus": 1, "steps": len(jobs), "warmup": warm, "ms_per_step": float(np.mean(lat)),
+    measured = nj - warm
+    out = {"metric": METRIC, "value": measured / ((last_done - first_sub) / 1e9), "unit": "graphs/s",
+           "n_gpus": 1, "steps": nj, "warmup": warm, "ms_per_step": float(np.mean(lat)),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8+f64",
            "data": "synthetic",
-           "config": {"workload": "stream: %d jobs (first %d warm-up), Poisson arrivals at 0.8x saturation "
-                                  "(%.1f jobs/s), graphs BA/RGG/SBM n log-uniform [1e3, 2e5], degree U[4, 64], "
-                                  "k in {10, 15, 30}; %d distinct graphs reused round-robin; budget %.0f GB"
-                                  % (len(jobs), warm, rate, pool_n, args.serve_budget_gb),
-                      "jobs": len(jobs), "rate_jobs_per_s": rate, "budget_bytes": budget},
+           "config": {"workload": "stream: %d distinct jobs (first %d left out of the statistics), Poisson arrivals "
+                                  "at 0.8x saturation (%.1f jobs/s), graphs BA/RGG/SBM n log-uniform [1e3, 2e5], "
+                                  "degree U[4, 64], k in {10, 15, 30}; partial BFS kNN + FP32 membership per job; "
+                                  "budget %.0f GB" % (nj, warm, rate, args.serve_budget_gb),
+                      "jobs": nj, "rate_jobs_per_s": rate, "budget_bytes": budget,
+                      "vertices": int(sum(g.n for g in graphs)), "nnz": int(sum(g.nnz for g in graphs))},
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-           "saturation_graphs_per_s": sat_rate, "iterations": stats["iterations"],
-           "peak_resident_bytes": stats["peak_resident_bytes"], "wall_s": t_total, "host_generation_s": t_gen}
+           "saturation_graphs_per_s": sat_rate, "saturation_jobs": len(sat_jobs), "iterations": stats["iterations"],
+           "peak_resident_bytes": stats["peak_resident_bytes"], "wall_s": t_total, "host_generation_s": t_gen,
+           "roofline": None,
+           "roofline_note": "bound by host-device transfers (each job's CSR in, its rows out), not by a kernel"}
     # plain loop on the same GPU: copy in, two synchronous calls, copy out, per job
-    plain = gk[:min(64, len(gk))]
+    plain = list(range(warm, min(nj, warm + 256)))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for (n, rp, ci), k in plain:
-        drp = torch.from_numpy(rp).cuda()
-        dci = torch.from_numpy(ci).cuda()
-        i_, h_ = gm.knn_partial(drp, dci, k, flags=gm.CSR_SORTED)
+    for i in plain:
+        drp = torch.from_numpy(graphs[i].row_ptr).cuda()
+        dci = torch.from_numpy(graphs[i].col_idx).cuda()
+        i_, h_ = gm.knn_partial(drp, dci, ks[i], flags=gm.CSR_SORTED)
         w_, r_, s_ = gm.membership(h_)
         i_.cpu(), h_.cpu(), w_.cpu(), r_.cpu(), s_.cpu()
     t_plain = (time.perf_counter() - t0) / len(plain)
     # the same plain calls with the graphs already resident and the results
     # left on the device: what the per-graph launches cost without transfers
-    resident = [(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), k) for (n, rp, ci), k in plain]
+    resident = [(torch.from_numpy(graphs[i].row_ptr).cuda(), torch.from_numpy(graphs[i].col_idx).cuda(), ks[i])
+                for i in plain]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for drp, dci, k in resident:
         i_, h_ = gm.knn_partial(drp, dci, k, flags=gm.CSR_SORTED)
         gm.membership(h_)
     torch.cuda.synchronize()
+    del resident
     out["graphs_per_s_plain_loop_resident"] = len(plain) / (time.perf_counter() - t0)
     out["graphs_per_s_plain_loop"] = 1.0 / t_plain
     out["speedup_vs_plain"] = out["saturation_graphs_per_s"] * t_plain
+    out["speedup_vs_plain_at_rate"] = out["value"] * t_plain
     if not args.no_parity:
         import oracle as O
-        (n, rp, ci), k = gk[3]
-        g = G.CSR(n, rp, ci)
-        oi, oh = O.knn_partial(g, k)
-        out["parity_sampled_bit_exact"] = bool(np.array_equal(keep["ids"], oi) and np.array_equal(keep["hops"], oh))
-    server.close()
-    print(json.dumps(out), flush=True)
+        ok = True
+        for i, r in kept.items():
+            oi, oh = O.knn_partial(graphs[i], ks[i])
+            ow, orho, _ = O.membership(oh, ks[i])
+            ok = ok and np.array_equal(r["ids"], oi) and np.array_equal(r["hops"], oh) \
+                and np.array_equal(r["rho"], orho) \
+                and bool(np.all(np.abs(r["weights"].astype(np.float64) - ow) <= 1e-5 * np.abs(ow) + 2.0**-126))
+        out["parity_sampled_bit_exact"] = bool(ok)
+        out["parity_sample"] = ("%d jobs spread over the stream, every row: ids, hops, rho bit-exact, weights "
+                                "within 1e-5 relative" % len(kept))
+    if not args.no_cpu_baseline:
+        import oracle as O
+        threads = O.default_threads()
+        frac = args.cpu_one_thread_fraction
+        sel = list(range(warm, min(nj, warm + 64)))
+
+        def run(sel_, th):
+            for i in sel_:
+                _, oh = O.knn_partial(graphs[i], ks[i], threads=th)
+                O.membership(oh, ks[i], threads=th)
+
+        t_all = _timed(lambda: run(sel, threads))
+        one = sel[::frac]
+        scale = sum(graphs[i].nnz + graphs[i].n for i in sel) / max(1, sum(graphs[i].nnz + graphs[i].n for i in one))
+        t_one = _timed(lambda: run(one, 1)) * scale
+        out["cpu_baseline"] = cpu_block(len(sel), "graphs/s", t_all, threads, t_one,
+                                        "oracle partial BFS + membership: %d jobs of the stream on all %d host "
+                                        "threads; %d of them on one thread, scaled by vertices + entries (x%.1f)"
+                                        % (len(sel), threads, len(one), scale))
+    del graphs
+    return out
 
 
 def _counter_avg_kib(run_dir: str, kernel_substr: str):
@@ -904,29 +1054,27 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(g, src, k, m, sample_sources):
-    """The oracle (as it stands) on a bounded sample of the same step, scaled
-    to the whole step: all-source BFS + kNN from `sample_sources` of the
-    sampled sources (time x len(src)/sample), partial BFS + membership on all
-    rows."""
+def cpu_baseline_ba(g, src, k, m, frac):
+    """The oracle (as it stands) on the whole headline step with all host
+    cores (all-source BFS with the hop matrix and kNN from the 4,096 sources,
+    partial BFS and membership on all rows), and on one thread over 1/frac of
+    the sources and rows, scaled."""
+    import numpy as np
     import oracle as O
     threads = O.default_threads()
-    sub = src[:sample_sources]
-    t0 = time.perf_counter()
-    O.knn_build(g, k, sources=sub, hop_matrix=True, threads=threads)
-    t_build = (time.perf_counter() - t0) * len(src) / len(sub)
-    t0 = time.perf_counter()
-    _, ph = O.knn_partial(g, k, threads=threads)
-    t_partial = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    O.membership(ph, k, threads=threads)
-    t_memb = time.perf_counter() - t0
-    t = t_build + t_partial + t_memb
-    return {"value": len(src) * m / t / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-            "sample": "oracle all-source BFS + kNN from %d of the %d sources (scaled x%.0f), partial BFS "
-                      "+ membership on all %d rows; step estimate %.2f s" % (
-                          len(sub), len(src), len(src) / len(sub), g.n, t),
-            "seconds_per_step_est": t}
+
+    def step(sources, rows, th):
+        O.knn_build(g, k, sources=sources, hop_matrix=True, threads=th)
+        _, ph = O.knn_partial(g, k, sources=rows, threads=th)
+        O.membership(ph, k, threads=th)
+
+    t_all = _timed(lambda: step(src, None, threads))
+    sub = src[:max(1, len(src) // frac)]
+    rows = np.arange(0, g.n, frac, dtype=np.int32)
+    t_one = _timed(lambda: step(sub, rows, 1)) * frac
+    return cpu_block(len(src) * m / 1e9, "GTEPS", t_all, threads, t_one,
+                     "oracle: the whole step on all %d host threads; one thread on %d of the %d sources and every "
+                     "%dth row, scaled x%d" % (threads, len(sub), len(src), frac, frac))
 
 
 if __name__ == "__main__":

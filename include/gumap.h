@@ -481,8 +481,12 @@ typedef struct gumap_server_stats {
 
 /* hbm_budget_bytes: device bytes the resident jobs may hold together;
  * max_slots: jobs admitted at once (0 = no limit).  Job inputs and results
- * are staged in a pinned host pool (GUMAP_SERVE_HOST_POOL_MB, default 4096);
- * when it is full, pageable host memory is used instead. */
+ * are staged in a pinned host pool (GUMAP_SERVE_HOST_POOL_MB, default 16384,
+ * touched once at creation).  A submission that finds the pool full waits up
+ * to 200 ms while inputs of earlier jobs are still in it (each leaves once
+ * uploaded), then uses pageable host memory; results that find it full use
+ * pageable memory.  t_submit_ns is taken when gumap_submit is entered, so
+ * latencies include the copy of the CSR. */
 gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, uint32_t flags,
                                   int *status);
 /* Copies the job and returns a ticket.  GUMAP_E2BIG if it can never fit. */

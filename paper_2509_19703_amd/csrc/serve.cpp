@@ -2,7 +2,10 @@
 // (partial-BFS kNN + membership of one graph per job) on one device.
 //
 // gumap_submit copies a job's host CSR into pinned host memory (a pool
-// reserved at creation; pageable memory if the pool is full) and queues it.
+// reserved at creation) and queues it.  When the pool is full it waits, for a
+// bounded time, while inputs of earlier jobs are still held there (each is
+// returned as soon as it is uploaded); only then does it fall back to
+// pageable memory, whose uploads are several times slower.
 // A scheduler thread runs a pipeline on three streams:
 //   admission   queued jobs are admitted first-come-first-served while their
 //               device bytes fit the budget, a slot is free and their result
@@ -188,6 +191,7 @@ size_t job_input_bytes(int32_t n, int32_t nnz)
 }
 
 constexpr int kInFlight = 2;
+constexpr int kPoolWaitMs = 200;   // longest wait of a submission for pinned pool space
 
 // Host copies of submitted CSRs, split into 1 MiB parts over a few
 // persistent threads plus the caller: one thread reaches only a fraction of
@@ -329,6 +333,8 @@ struct gumap_server {
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_space;  // pinned pool space returned
+    size_t pinned_inputs = 0;          // pool bytes held by inputs not yet uploaded
     std::deque<std::shared_ptr<Job>> queue;               // waiting for admission
     std::vector<std::shared_ptr<Job>> admitted;           // resident, rows left or in flight
     std::vector<std::shared_ptr<Job>> downloading;
@@ -361,7 +367,11 @@ struct gumap_server {
 void gumap_server::free_input_locked(Job &j)
 {
     if (j.input_freed) return;
-    if (j.in_pinned) host_alloc.release(j.in_off, j.in_bytes);
+    if (j.in_pinned) {
+        host_alloc.release(j.in_off, j.in_bytes);
+        pinned_inputs -= j.in_bytes;
+        cv_space.notify_all();
+    }
     j.pg_rp.clear();
     j.pg_rp.shrink_to_fit();
     j.pg_col.clear();
@@ -745,7 +755,7 @@ gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
     s->iter_rows = (int64_t)gm::env_size("GUMAP_SERVE_ITER_ROWS", 1 << 20);
     s->table_cap = 4096;
     s->chunk_cap = (int32_t)std::min<int64_t>(1 << 22, s->iter_rows + s->table_cap);
-    s->host_pool_bytes = gm::env_size("GUMAP_SERVE_HOST_POOL_MB", s->no_device ? 256 : 4096) << 20;
+    s->host_pool_bytes = gm::env_size("GUMAP_SERVE_HOST_POOL_MB", s->no_device ? 256 : 16384) << 20;
     s->host_alloc.reset(s->host_pool_bytes);
     hipError_t e = hipSuccess;
     if (s->no_device) {
@@ -802,6 +812,7 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
         return gm::set_error(GUMAP_EINVAL, "NULL CSR array");
     if (job->flags & ~(GUMAP_CSR_SORTED | GUMAP_VALIDATE)) return gm::set_error(GUMAP_EINVAL, "unknown flags");
     auto j = std::make_shared<Job>();
+    j->t_submit = now_ns();   // latency counts the copy into the pool
     j->n = job->n;
     j->nnz = job->nnz;
     j->k = job->k;
@@ -812,11 +823,20 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
     j->out_bytes = job_result_bytes(j->n, j->k, j->weights);
     if (j->bytes > s->budget)
         return gm::set_error(GUMAP_E2BIG, "job needs %zu device bytes, budget is %zu", j->bytes, s->budget);
-    // copy the CSR now: into the pinned pool when it has room, else pageable memory
+    // copy the CSR now: into the pinned pool when it has room (waiting up to
+    // kPoolWaitMs while earlier inputs still held there are being uploaded),
+    // else into pageable memory
     j->in_bytes = job_input_bytes(j->n, j->nnz);
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::unique_lock<std::mutex> lk(s->mu);
         j->in_pinned = s->host_alloc.alloc(j->in_bytes, &j->in_off);
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(kPoolWaitMs);
+        while (!j->in_pinned && s->pinned_inputs > 0 && j->in_bytes <= s->host_pool_bytes && !s->stop) {
+            const bool timed_out = s->cv_space.wait_until(lk, deadline) == std::cv_status::timeout;
+            j->in_pinned = s->host_alloc.alloc(j->in_bytes, &j->in_off);
+            if (timed_out) break;
+        }
+        if (j->in_pinned) s->pinned_inputs += j->in_bytes;
     }
     if (j->in_pinned) {
         j->in_rp = (int32_t *)(s->host_pool + j->in_off);
@@ -830,7 +850,6 @@ int gumap_submit(gumap_server *s, const gumap_job *job, uint64_t *ticket)
     if (j->n > 0) s->copier->copy(j->in_rp, job->row_ptr, (size_t)(j->n + 1) * 4);
     else j->in_rp[0] = 0;
     if (j->nnz > 0) s->copier->copy(j->in_col, job->col_idx, (size_t)j->nnz * 4);
-    j->t_submit = now_ns();
     std::lock_guard<std::mutex> lk(s->mu);
     j->ticket = s->next_ticket++;
     s->jobs[j->ticket] = j;
@@ -892,7 +911,10 @@ int gumap_release(gumap_server *s, uint64_t ticket)
     if (it == s->jobs.end()) return gm::set_error(GUMAP_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     if (it->second->state != kDone) return GUMAP_PENDING;
     Job &j = *it->second;
-    if (j.out_pinned) s->host_alloc.release(j.out_off, j.out_bytes);
+    if (j.out_pinned) {
+        s->host_alloc.release(j.out_off, j.out_bytes);
+        s->cv_space.notify_all();
+    }
     j.out_pinned = false;
     s->jobs.erase(it);
     s->kick = true;
@@ -919,6 +941,7 @@ void gumap_server_destroy(gumap_server *s)
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_space.notify_all();
     if (s->worker.joinable()) s->worker.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);

@@ -182,3 +182,93 @@ def test_server_unsorted_jobs(gumap):
         r = s.wait(t, 60000)
     oi, oh = O.knn_partial(g, 15)
     assert r["status"] == gumap.OK and np.array_equal(r["ids"], oi) and np.array_equal(r["hops"], oh)
+
+
+def _sampled_rows(g, per_graph, seed):
+    """First, last and seeded rows of a graph (sorted, unique)."""
+    if g.n == 0:
+        return np.zeros(0, np.int32)
+    rng = np.random.default_rng(seed)
+    pick = np.concatenate([[0, g.n - 1], rng.integers(0, g.n, per_graph)])
+    return np.unique(pick).astype(np.int32)
+
+
+def test_batch2048_full_size_sampled(gumap):
+    """The batch workload at its full size (2,048 graphs, n log-uniform in
+    [256, 16,384], mean degree U[4, 32], BA / RGG / SBM; 7.9 M rows, int64
+    offsets): the batched call and the captured plan against the oracle on
+    sampled rows of EVERY graph (ids, hops, rho bit-exact; weights to 1e-5)
+    and against each other on every row."""
+    k = 15
+    graphs = G.config_batch_graphs(2048)
+    pb = gumap.PackedBatch(graphs)
+    print("batch2048 rows=%d nnz=%d" % (pb.total_vertices, pb.total_nnz), flush=True)
+    got = [t.cpu().numpy() for t in gumap.knn_partial_batch(pb, k)]
+    plan = gumap.BatchPlan(pb, k)
+    rep = [t.cpu().numpy() for t in plan.launch()]
+    plan.close()
+    for a, b in zip(got, rep):
+        assert np.array_equal(a, b)
+    voff = pb.vtx_offset_host
+    for i, g in enumerate(graphs):
+        rows = _sampled_rows(g, 3, i)
+        oi, oh = O.knn_partial(g, k, sources=rows)
+        ow, orho, osig = O.membership(oh, k)
+        r = int(voff[i]) + rows
+        assert np.array_equal(got[0][r], oi) and np.array_equal(got[1][r], oh), "graph %d" % i
+        assert_weights_close(got[2][r], ow, got[3][r], orho, got[4][r], osig)
+
+
+def _stream_pick():
+    """Jobs of the served stream's own generator: for each k in {10, 15, 30}
+    the two largest graphs of its first 4,096 jobs, plus 18 seeded others."""
+    jobs = G.config_stream_jobs(4096)
+    pick = []
+    for k in (10, 15, 30):
+        with_k = sorted((j for j in jobs if j["k"] == k), key=lambda j: -j["n"])
+        pick += with_k[:2]
+    rng = np.random.default_rng(G.BASE_SEED + 205)
+    for i in rng.choice(len(jobs), 18, replace=False):
+        if jobs[i] not in pick:
+            pick.append(jobs[i])
+    return pick
+
+
+def test_served_stream_full_size_mix_and_alone(gumap):
+    """Jobs of the served workload at full size (n up to 2e5, degree up to
+    64, k in {10, 15, 30}) submitted in waves while earlier ones run: every
+    job equals the oracle (ids, hops, rho bit-exact, weights to 1e-5) and,
+    for the largest of each k, the same job run alone on a fresh server."""
+    jobs = _stream_pick()
+    graphs = [G.stream_job_graph(j) for j in jobs]
+    print("stream jobs: n max %d, total nnz %d" % (max(g.n for g in graphs), sum(g.nnz for g in graphs)),
+          flush=True)
+    assert max(g.n for g in graphs) > 150000
+    results = {}
+    with gumap.Server(64 << 30) as s:
+        pending = []
+        for w0 in range(0, len(jobs), 5):
+            for i in range(w0, min(len(jobs), w0 + 5)):
+                pending.append((i, s.submit(graphs[i].row_ptr, graphs[i].col_idx, jobs[i]["k"])))
+            # collect the oldest half while the newer ones run
+            while len(pending) > 4:
+                i, t = pending.pop(0)
+                results[i] = s.wait(t, 120000)
+                s.release(t)
+        for i, t in pending:
+            results[i] = s.wait(t, 120000)
+            s.release(t)
+    for i, (g, j) in enumerate(zip(graphs, jobs)):
+        r = results[i]
+        assert r["status"] == gumap.OK
+        oi, oh = O.knn_partial(g, j["k"])
+        ow, orho, osig = O.membership(oh, j["k"])
+        assert np.array_equal(r["ids"], oi) and np.array_equal(r["hops"], oh), "job %d" % i
+        assert_weights_close(r["weights"], ow, r["rho"], orho, r["sigma"], osig)
+    with gumap.Server(64 << 30) as s:
+        for i in range(6):
+            t = s.submit(graphs[i].row_ptr, graphs[i].col_idx, jobs[i]["k"])
+            a = s.wait(t, 120000)
+            for key in ("ids", "hops", "weights", "rho", "sigma"):
+                assert np.array_equal(a[key], results[i][key]), (i, key)
+            s.release(t)
