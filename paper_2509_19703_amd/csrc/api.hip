@@ -739,6 +739,7 @@ int csr_canonicalize(const gumap_graph *g, int32_t *out_rp, int32_t *out_col, in
     if (e != hipSuccess) return hip_status(e, "canonicalize");
     if ((st = finish(s, "gumap_csr_canonicalize"))) return st;
     *out_nnz = *(int32_t *)h;
+    if (*out_nnz < 0) return set_error(GUMAP_EDEVICE, "canonicalisation scan did not complete");
     return GUMAP_OK;
 }
 

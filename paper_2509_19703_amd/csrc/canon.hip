@@ -1,8 +1,17 @@
 // CSR ingest: structural validation, symmetry check, canonicalisation
 // (rows sorted ascending, repeats and self-loops removed) and the exclusive
-// scan used to rebuild row pointers.  The kNN results depend only on the
+// scan used elsewhere to rebuild offsets.  The kNN results depend only on the
 // undirected edge set; a canonical adjacency is what lets the partial BFS
 // merge sorted neighbour lists and stop early.
+//
+// Canonicalisation is five launches: rows of at most 32 entries are sorted
+// by one thread each (registers) and longer rows listed; rows of up to 1,024
+// entries are sorted by one wave each and longer ones by a 1,024-thread
+// workgroup (LDS, or an n-bit bitmap past 32,768 entries), both reading the
+// lists through a slot permutation that spreads the high-degree rows; a
+// single-pass scan with decoupled look-back writes the row pointers; a
+// fix-up moves rows only when a repeat or self-loop was dropped (rows are
+// sorted in place at their input offsets, with a staged copy for that case).
 #include "device.h"
 #include "kernels.h"
 
@@ -15,7 +24,6 @@ constexpr int kMidRow = 1024;      // one wave, registers
 constexpr int kBigRow = 32768;     // one workgroup, LDS
 constexpr int kCanonBlock = 256;   // 4 waves
 constexpr int kBigBlock = 1024;
-constexpr int kHugeBlocks = 32;
 
 __global__ void validate_structure_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col, int *err)
@@ -60,16 +68,16 @@ __global__ void check_symmetric_kernel(int32_t n, const int32_t *__restrict__ ro
     }
 }
 
-constexpr int kTinyRow = 16;       // four rows per wave, 16 lanes each
 
 // Bitonic sort of one row of 64 * R entries (padding GM_INF_ID) held in
 // registers: element i = lane + 64 * r sits in register r of lane i % 64.
 // Compare-exchange distances below 64 cross lanes (shuffles), larger ones
-// stay within a lane.  Unique entries other than v go to tmp[a, ...) in
-// order and their count to cnt[v].
+// stay within a lane.  Unique entries other than v go to out[a, ...) and
+// stg[a, ...) in order and their count to cnt[v].
 template <int R>
 __device__ __forceinline__ void wave_sort_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
-                                              int32_t *__restrict__ tmp, int32_t *__restrict__ cnt)
+                                              int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                                              int32_t *__restrict__ cnt)
 {
     constexpr int P = GM_WAVE * R;
     const int l = lane();
@@ -114,28 +122,23 @@ __device__ __forceinline__ void wave_sort_row(int64_t v, int32_t a, int32_t d, c
         if (l == 0) prev = carry;
         const bool keep = x[r] != GM_INF_ID && x[r] != (int)v && (r + l == 0 || x[r] != prev);
         const unsigned long long m = __ballot(keep);
-        if (keep) tmp[a + base + lanes_below(m)] = x[r];
+        if (keep) {
+            out[a + base + lanes_below(m)] = x[r];
+            stg[a + base + lanes_below(m)] = x[r];
+        }
         base += __popcll(m);
         carry = __shfl(x[r], GM_WAVE - 1, GM_WAVE);
     }
     if (l == 0) cnt[v] = base;
 }
 
-// Sorts row v (a = its first entry, d its length, kTinyRow < d) into
-// tmp[a, a + unique) and records the count; rows longer than kMidRow are
-// queued for the workgroup kernels.
+// Sorts row v (a = its first entry, kThreadRow < d <= kMidRow) with one wave
+// into out and stg at [a, a + unique) and records the count.
 __device__ __forceinline__ void canon_one_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
-                              int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, int32_t *big_list,
-                              int32_t *big_count, int32_t *huge_list, int32_t *huge_count)
+                                             int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                                             int32_t *__restrict__ cnt)
 {
     const int l = lane();
-    if (d > kMidRow) {
-        if (l == 0) {
-            if (d > kBigRow) huge_list[atomicAdd(huge_count, 1)] = (int32_t)v;
-            else big_list[atomicAdd(big_count, 1)] = (int32_t)v;
-        }
-        return;
-    }
     if (d <= kSmallRow) {
         int x = l < d ? col[a + l] : GM_INF_ID;
         // bitonic sort across the 64 lanes, ascending
@@ -152,197 +155,380 @@ __device__ __forceinline__ void canon_one_row(int64_t v, int32_t a, int32_t d, c
         int prev = __shfl_up(x, 1, GM_WAVE);
         bool keep = x != GM_INF_ID && x != (int)v && (l == 0 || x != prev);
         unsigned long long m = __ballot(keep);
-        if (keep) tmp[a + lanes_below(m)] = x;
+        if (keep) {
+            out[a + lanes_below(m)] = x;
+            stg[a + lanes_below(m)] = x;
+        }
         if (l == 0) cnt[v] = __popcll(m);
         return;
     }
     // 64 < d <= 1024: bitonic sort in registers, R = 2..16 per lane
-    if (d <= 128) wave_sort_row<2>(v, a, d, col, tmp, cnt);
-    else if (d <= 256) wave_sort_row<4>(v, a, d, col, tmp, cnt);
-    else if (d <= 512) wave_sort_row<8>(v, a, d, col, tmp, cnt);
-    else wave_sort_row<16>(v, a, d, col, tmp, cnt);
+    if (d <= 128) wave_sort_row<2>(v, a, d, col, out, stg, cnt);
+    else if (d <= 256) wave_sort_row<4>(v, a, d, col, out, stg, cnt);
+    else if (d <= 512) wave_sort_row<8>(v, a, d, col, out, stg, cnt);
+    else wave_sort_row<16>(v, a, d, col, out, stg, cnt);
 }
 
-// Rows of length <= 16, four per wave: one 16-lane segment each, bitonic
-// sort within the segment.  Longer rows are left to canon_rows_kernel.
-__global__ void __launch_bounds__(kCanonBlock)
-canon_tiny_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt)
+// Short rows (at most kThreadRow entries) are sorted by one thread each,
+// with a bitonic network over N registers (compile-time indices, so the row
+// stays in registers); repeats and the row's own vertex are dropped as the
+// row is written.
+constexpr int kThreadRow = 32;
+constexpr int kListRows = 256;   // rows per block of canon_sort_kernel
+
+template <int N>
+__device__ __forceinline__ void thread_sort_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
+                                                int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                                                int32_t *__restrict__ cnt)
 {
-    const int l = lane();
-    const int seg = l >> 4, sl = l & (kTinyRow - 1);
-    const int64_t waves = blockDim.x / GM_WAVE;
-    for (int64_t v0 = ((int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE) * 4; v0 < n;
-         v0 += (int64_t)gridDim.x * waves * 4) {
-        const int64_t v = v0 + seg;
-        int32_t a = 0, d = 0;
-        if (v < n) {
-            a = row_ptr[v];
-            d = row_ptr[v + 1] - a;
-        }
-        const bool tiny = v < n && d <= kTinyRow;
-        int x = (tiny && sl < d) ? col[a + sl] : GM_INF_ID;
+    int x[N];
 #pragma unroll
-        for (int kk = 2; kk <= kTinyRow; kk <<= 1) {
+    for (int i = 0; i < N; ++i) x[i] = i < d ? col[a + i] : GM_INF_ID;
 #pragma unroll
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                int p = __shfl_xor(x, j, GM_WAVE);
-                bool up = (sl & kk) == 0;
-                bool low = (sl & j) == 0;
-                x = (low == up) ? min(x, p) : max(x, p);
+    for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int o = i ^ j;
+                if (o > i) {
+                    const int lo = min(x[i], x[o]), hi = max(x[i], x[o]);
+                    const bool up = (i & kk) == 0;
+                    x[i] = up ? lo : hi;
+                    x[o] = up ? hi : lo;
+                }
             }
         }
-        const int prev = __shfl_up(x, 1, GM_WAVE);
-        const bool keep = tiny && x != GM_INF_ID && x != (int)v && (sl == 0 || x != prev);
-        const unsigned long long m = __ballot(keep);
-        const unsigned long long segm = 0xFFFFull << (16 * seg);
-        if (keep) tmp[a + __popcll(m & segm & ((1ull << l) - 1ull))] = x;
-        if (tiny && sl == 0) cnt[v] = __popcll(m & segm);
     }
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const bool keep = x[i] != GM_INF_ID && x[i] != (int)v && (i == 0 || x[i] != x[i > 0 ? i - 1 : 0]);
+        if (keep) {
+            out[a + c] = x[i];
+            stg[a + c] = x[i];
+        }
+        c += keep;
+    }
+    cnt[v] = c;
 }
 
-// Rows longer than 16, one wave each (see canon_one_row); rows longer than
-// kMidRow are queued for the workgroup kernels.
+// A thread per row: rows of at most kThreadRow entries are sorted here into
+// out and stg at the row's input offset, with their kept count in cnt;
+// longer rows are listed per block (kListRows slots per block and list):
+// up to kMidRow entries in list_mid, longer ones in list_big, with the
+// counts in n_mid / n_big.  Block 0 also clears
+// the look-back flags of canon_scan_kernel (launched after the sorts).
+__global__ void __launch_bounds__(kListRows)
+canon_sort_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                  int32_t *__restrict__ out, int32_t *__restrict__ stg, int32_t *__restrict__ cnt,
+                  int32_t *__restrict__ lists, int32_t *__restrict__ counts, int64_t list_stride,
+                  unsigned long long *__restrict__ flags, int32_t n_flags)
+{
+    __shared__ int32_t s_n[2];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0)
+        for (int32_t i = t; i < n_flags; i += blockDim.x) flags[i] = 0ull;
+    if (t < 2) s_n[t] = 0;
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * kListRows + t;
+    const int64_t base = (int64_t)blockIdx.x * kListRows;
+    if (v < n) {
+        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
+        if (d <= 16) {
+            thread_sort_row<16>(v, a, d, col, out, stg, cnt);
+        } else if (d <= kThreadRow) {
+            thread_sort_row<kThreadRow>(v, a, d, col, out, stg, cnt);
+        } else {
+            const int which = d <= kMidRow ? 0 : 1;
+            lists[which * list_stride + base + atomicAdd(&s_n[which], 1)] = (int32_t)v;
+        }
+    }
+    __syncthreads();
+    if (t < 2) counts[(int64_t)t * (list_stride / kListRows) + blockIdx.x] = s_n[t];
+}
+
+// The listed rows are addressed by slots s in [0, S), S the power of two at
+// or above blocks * kListRows: slot s stands for entry f % kListRows of
+// block f / kListRows's list, f = s * kSlotMul mod S (kSlotMul odd, so this
+// is a permutation), when f is inside the lists.  Long rows cluster in a few
+// blocks (the low ids of a preferential-attachment graph); scattering the
+// slots spreads them over many waves instead of leaving a block's list to
+// one.
+constexpr uint64_t kSlotMul = 2654435761ull;
+constexpr int kMidSlots = 16;   // slots per wave (mid rows) and per workgroup (block rows)
+
+__device__ __forceinline__ bool list_slot(int64_t s, int64_t slots_pow2, int64_t slots,
+                                          const int32_t *__restrict__ counts, int64_t &entry)
+{
+    if (s >= slots_pow2) return false;
+    const int64_t f = (int64_t)(((uint64_t)s * kSlotMul) & (uint64_t)(slots_pow2 - 1));
+    if (f >= slots) return false;
+    entry = f;
+    return (f % kListRows) < counts[f / kListRows];
+}
+
+// Rows of kThreadRow + 1 .. kMidRow entries: wave w of the launch looks at
+// mid-list slots [kMidSlots w, kMidSlots (w + 1)) and sorts each row found
+// there with the whole wave (registers).
 __global__ void __launch_bounds__(kCanonBlock)
-canon_rows_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, int32_t *big_list,
-                  int32_t *big_count, int32_t *huge_list, int32_t *huge_count)
+canon_mid_kernel(int32_t blocks, int64_t slots_pow2, const int32_t *__restrict__ row_ptr,
+                 const int32_t *__restrict__ col, int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                 int32_t *__restrict__ cnt, const int32_t *__restrict__ list_mid, const int32_t *__restrict__ n_mid)
 {
-    const int wid = threadIdx.x / GM_WAVE;
-    const int waves = blockDim.x / GM_WAVE;
-    for (int64_t v = (int64_t)blockIdx.x * waves + wid; v < n; v += (int64_t)gridDim.x * waves) {
+    const int64_t slots = (int64_t)blocks * kListRows;
+    const int l = lane();
+    const int64_t w = (int64_t)blockIdx.x * (kCanonBlock / GM_WAVE) + threadIdx.x / GM_WAVE;
+    int64_t entry = 0;
+    const bool ok = l < kMidSlots && list_slot(w * kMidSlots + l, slots_pow2, slots, n_mid, entry);
+    unsigned long long fm = __ballot(ok);
+    while (fm) {
+        const int src = __ffsll((long long)fm) - 1;
+        fm &= fm - 1;
+        const int32_t v = list_mid[__shfl(entry, src, GM_WAVE)];
         const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
-        if (d <= kTinyRow) continue;
-        canon_one_row(v, a, d, col, tmp, cnt, big_list, big_count, huge_list, huge_count);
+        canon_one_row(v, a, d, col, out, stg, cnt);
     }
 }
 
-// One workgroup per queued row of length (kMidRow, kBigRow].
+// Rows longer than kMidRow, each sorted by a whole 1,024-thread workgroup:
+// up to kBigRow entries by a bitonic sort in LDS, longer ones by marking the
+// neighbours in an n-bit bitmap (this workgroup's own, in scratch) and
+// emitting the set bits in order.  Workgroup c looks at big-list slots
+// [1024 c', 1024 c' + 1024) for c' = c, c + gridDim.x, ...
 __global__ void __launch_bounds__(kBigBlock)
-canon_big_kernel(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                 int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, const int32_t *big_list,
-                 const int32_t *big_count)
+canon_big_kernel(int32_t n, int32_t blocks, int64_t slots_pow2, const int32_t *__restrict__ row_ptr,
+                 const int32_t *__restrict__ col, int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                 int32_t *__restrict__ cnt, const int32_t *__restrict__ list_big, const int32_t *__restrict__ n_big,
+                 uint32_t *__restrict__ bitmaps)
 {
-    extern __shared__ int32_t sbuf[];  // kBigRow ints + 32 ints of wave counts
-    int32_t *wcnt = sbuf + kBigRow;
-    const int nbig = *big_count;
-    const int t = threadIdx.x, l = lane(), wid = t / GM_WAVE;
-    for (int r = blockIdx.x; r < nbig; r += gridDim.x) {
-        const int32_t v = big_list[r];
-        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
-        int P = 2048;
-        while (P < d) P <<= 1;
-        for (int i = t; i < P; i += blockDim.x) sbuf[i] = i < d ? col[a + i] : GM_INF_ID;
+    extern __shared__ int32_t sbuf[];  // kBigRow ints, then kBigBlock ints of per-thread counts
+    int32_t *part = sbuf + kBigRow;
+    __shared__ int32_t found[kBigBlock];
+    __shared__ int32_t n_found;
+    const int t = threadIdx.x;
+    const int64_t words = ((int64_t)n + 31) / 32;
+    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    const int64_t slots = (int64_t)blocks * kListRows;
+    for (int64_t c0 = (int64_t)blockIdx.x * kBigBlock; c0 < slots_pow2; c0 += (int64_t)gridDim.x * kBigBlock) {
+        if (t == 0) n_found = 0;
         __syncthreads();
-        for (int kk = 2; kk <= P; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int i = t; i < P; i += blockDim.x) {
-                    int q = i ^ j;
-                    if (q > i) {
-                        int x = sbuf[i], y = sbuf[q];
-                        bool up = (i & kk) == 0;
-                        if ((x > y) == up) { sbuf[i] = y; sbuf[q] = x; }
+        {
+            int64_t entry = 0;
+            if (list_slot(c0 + t, slots_pow2, slots, n_big, entry)) found[atomicAdd(&n_found, 1)] = list_big[entry];
+        }
+        __syncthreads();
+        const int nf = n_found;
+        for (int q = 0; q < nf; ++q) {
+            const int32_t rv = found[q];
+            const int32_t a = row_ptr[rv], d = row_ptr[rv + 1] - a;
+            if (d <= kBigRow) {
+                int P = kBigBlock;
+                while (P < d) P <<= 1;
+                for (int i = t; i < P; i += blockDim.x) sbuf[i] = i < d ? col[a + i] : GM_INF_ID;
+                __syncthreads();
+                for (int kk = 2; kk <= P; kk <<= 1) {
+                    for (int j = kk >> 1; j > 0; j >>= 1) {
+                        for (int i = t; i < P; i += blockDim.x) {
+                            const int o = i ^ j;
+                            if (o > i) {
+                                const int x = sbuf[i], y = sbuf[o];
+                                const bool up = (i & kk) == 0;
+                                if ((x > y) == up) {
+                                    sbuf[i] = y;
+                                    sbuf[o] = x;
+                                }
+                            }
+                        }
+                        __syncthreads();
                     }
                 }
+                // unique entries other than rv, in order: per-thread counts of
+                // a contiguous range, a block scan, then the writes
+                const int chunk = P / (int)blockDim.x;
+                const int i0 = t * chunk;
+                int mine = 0;
+                for (int i = i0; i < i0 + chunk; ++i) {
+                    const int x = sbuf[i];
+                    mine += x != GM_INF_ID && x != rv && (i == 0 || x != sbuf[i - 1]);
+                }
+                part[t] = mine;
+                __syncthreads();
+                for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+                    const int y = t >= o ? part[t - o] : 0;
+                    __syncthreads();
+                    part[t] += y;
+                    __syncthreads();
+                }
+                int pos = part[t] - mine;
+                for (int i = i0; i < i0 + chunk; ++i) {
+                    const int x = sbuf[i];
+                    if (x != GM_INF_ID && x != rv && (i == 0 || x != sbuf[i - 1])) {
+                        out[a + pos] = x;
+                        stg[a + pos] = x;
+                        ++pos;
+                    }
+                }
+                if (t == (int)blockDim.x - 1) cnt[rv] = part[t];
+                __syncthreads();
+            } else {
+                for (int64_t i = t; i < words; i += blockDim.x) bm[i] = 0u;
+                __threadfence_block();
+                __syncthreads();
+                for (int32_t e = a + t; e < a + d; e += blockDim.x) {
+                    const int32_t w = col[e];
+                    if (w != rv) atomicOr(&bm[w >> 5], 1u << (w & 31));
+                }
+                __threadfence_block();
+                __syncthreads();
+                const int64_t wper = (words + blockDim.x - 1) / blockDim.x;
+                const int64_t w0 = min(words, (int64_t)t * wper), w1 = min(words, w0 + wper);
+                int mine = 0;
+                for (int64_t i = w0; i < w1; ++i)
+                    mine += __popc(__hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                part[t] = mine;
+                __syncthreads();
+                for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+                    const int y = t >= o ? part[t - o] : 0;
+                    __syncthreads();
+                    part[t] += y;
+                    __syncthreads();
+                }
+                int pos = part[t] - mine;
+                for (int64_t i = w0; i < w1; ++i) {
+                    uint32_t bits = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    while (bits) {
+                        const int bit = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        out[a + pos] = (int32_t)(i * 32 + bit);
+                        stg[a + pos] = (int32_t)(i * 32 + bit);
+                        ++pos;
+                    }
+                }
+                if (t == (int)blockDim.x - 1) cnt[rv] = part[t];
                 __syncthreads();
             }
         }
-        int base = 0;
-        for (int c = 0; c < P; c += blockDim.x) {
-            int i = c + t;
-            int x = sbuf[i];
-            bool keep = x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1]);
-            unsigned long long m = __ballot(keep);
-            if (l == 0) wcnt[wid] = __popcll(m);
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int w = 0; w < (int)(blockDim.x / GM_WAVE); ++w) {
-                int cw = wcnt[w];
-                if (w < wid) before += cw;
-                total += cw;
-            }
-            if (keep) tmp[a + base + before + lanes_below(m)] = x;
-            base += total;
-            __syncthreads();
-        }
-        if (t == 0) cnt[v] = base;
-        __syncthreads();
     }
 }
 
-// Rows longer than kBigRow: mark neighbours in a bitmap of n bits (one bitmap
-// per workgroup, in scratch), then emit the set bits in order.
-__global__ void __launch_bounds__(kBigBlock)
-canon_huge_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                  int32_t *__restrict__ tmp, int32_t *__restrict__ cnt, const int32_t *huge_list,
-                  const int32_t *huge_count, uint32_t *bitmaps)
+// Single-pass scan of the row counts with decoupled look-back.  Tile b =
+// rows [b * kScanRows, ...): its count total is published as an aggregate,
+// the exclusive prefix is found by walking back over earlier tiles' flags
+// (a published inclusive prefix ends the walk), and the tile's inclusive
+// prefix is published; then it writes its output row pointers.  A flag is 0
+// (not ready), or (status << 62 | value) with status 1 = aggregate, 2 =
+// inclusive prefix; canon_sort_kernel cleared them for this call.  A wait on
+// a flag is bounded: past kSpinLimit polls the tile writes
+// out_row_ptr[n] = -1 and stops (the host reports it).
+constexpr int kScanRows = 1024;
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = kScanRows / kScanThreads;
+constexpr unsigned long long kFlagAgg = 1ull << 62, kFlagPrefix = 2ull << 62;
+constexpr unsigned long long kFlagValue = (1ull << 62) - 1ull;
+constexpr int kSpinLimit = 1 << 22;
+
+__global__ void __launch_bounds__(kScanThreads)
+canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restrict__ out_row_ptr,
+                  unsigned long long *flags)
 {
-    __shared__ int32_t part[kBigBlock];
-    const int nhuge = *huge_count;
-    const int64_t words = ((int64_t)n + 31) / 32;
-    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
-    const int t = threadIdx.x;
-    for (int r = blockIdx.x; r < nhuge; r += gridDim.x) {
-        const int32_t v = huge_list[r];
-        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
-        for (int64_t i = t; i < words; i += blockDim.x) bm[i] = 0u;
-        __threadfence();
-        __syncthreads();
-        for (int32_t e = a + t; e < b; e += blockDim.x) {
-            int32_t w = col[e];
-            if (w != v) atomicOr(&bm[w >> 5], 1u << (w & 31));
-        }
-        __threadfence();
-        __syncthreads();
-        // contiguous word range per thread
-        const int64_t per = (words + blockDim.x - 1) / blockDim.x;
-        const int64_t w0 = min(words, (int64_t)t * per), w1 = min(words, w0 + per);
-        int mine = 0;
-        for (int64_t i = w0; i < w1; ++i)
-            mine += __popc(__hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        part[t] = mine;
-        __syncthreads();
-        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-            int x = t >= o ? part[t - o] : 0;
-            __syncthreads();
-            part[t] += x;
-            __syncthreads();
-        }
-        int pos = part[t] - mine;
-        for (int64_t i = w0; i < w1; ++i) {
-            uint32_t bits = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (bits) {
-                int bit = __ffs(bits) - 1;
-                bits &= bits - 1;
-                tmp[a + pos++] = (int32_t)(i * 32 + bit);
-            }
-        }
-        if (t == blockDim.x - 1) cnt[v] = part[t];
-        __syncthreads();
+    __shared__ int32_t s_wave[kScanThreads / GM_WAVE];
+    __shared__ int64_t s_excl;
+    __shared__ int s_fail;
+    const int t = threadIdx.x, l = lane(), wid = t / GM_WAVE;
+    const int64_t v0 = (int64_t)blockIdx.x * kScanRows;
+    const int rows = (int)min((int64_t)kScanRows, (int64_t)n - v0);
+    int c[kScanPer];
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        const int r = t * kScanPer + q;
+        c[q] = r < rows ? cnt[v0 + r] : 0;
+        mine += c[q];
     }
+    const int inc = wave_incl_scan(mine);
+    if (l == GM_WAVE - 1) s_wave[wid] = inc;
+    if (t == 0) s_fail = 0;
+    __syncthreads();
+    int before = 0, agg = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / GM_WAVE; ++w) {
+        if (w < wid) before += s_wave[w];
+        agg += s_wave[w];
+    }
+    if (wid == 0) {
+        // look-back by the first wave, 64 earlier tiles per window: lane q
+        // reads tile j - q; the window is summed up to the nearest published
+        // inclusive prefix once every flag before it is ready
+        int64_t excl = 0;
+        if (blockIdx.x == 0) {
+            if (l == 0)
+                __hip_atomic_store(&flags[0], kFlagPrefix | (unsigned long long)agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (l == 0)
+                __hip_atomic_store(&flags[blockIdx.x], kFlagAgg | (unsigned long long)agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = (int64_t)blockIdx.x - 1;
+            int spins = 0;
+            bool fail = false;
+            while (j >= 0) {
+                const int64_t tile = j - l;
+                const unsigned long long f = tile >= 0
+                    ? __hip_atomic_load(&flags[tile], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : kFlagPrefix;   // before tile 0: an empty prefix
+                const unsigned long long pre = __ballot((f & ~kFlagValue) == kFlagPrefix);
+                const int stop = pre ? __ffsll((long long)pre) - 1 : GM_WAVE - 1;   // nearest prefix lane
+                const unsigned long long need = stop == GM_WAVE - 1 ? ~0ull : ((2ull << stop) - 1ull);
+                if ((__ballot(f != 0ull) & need) != need) {
+                    if (++spins > kSpinLimit) {
+                        fail = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                const unsigned long long mine_v = (l <= stop && tile >= 0) ? (f & kFlagValue) : 0ull;
+                excl += (int64_t)wave_sum_u64(mine_v);
+                if (pre) break;
+                j -= GM_WAVE;
+            }
+            if (l == 0)
+                __hip_atomic_store(&flags[blockIdx.x], kFlagPrefix | (unsigned long long)(excl + agg),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (l == 0 && fail) s_fail = 1;
+        }
+        if (l == 0) s_excl = excl;
+    }
+    __syncthreads();
+    if (s_fail) {
+        if (t == 0) out_row_ptr[n] = -1;
+        return;
+    }
+    int off = (int)s_excl + before + inc - mine;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        const int r = t * kScanPer + q;
+        if (r < rows) out_row_ptr[v0 + r] = off;
+        off += c[q];
+    }
+    if (v0 + rows == n && t == kScanThreads - 1) out_row_ptr[n] = off;
 }
 
-// The sorted rows are written to col_out at the input offsets.  When every
-// entry was kept (the scanned total equals nnz) that already is the output;
-// otherwise they are staged to tmp and compacted back into col_out.
-__global__ void canon_stage_kernel(int32_t nnz, const int32_t *__restrict__ row_ptr_out, int32_t n,
-                                   const int32_t *__restrict__ col_out, int32_t *__restrict__ tmp)
+// The sorted rows already sit in out_col at the input offsets; when every
+// entry was kept (out_row_ptr[n] == nnz) that is the output.  Otherwise each
+// row's kept entries move from the staged copy to the output offsets (a wave
+// per row).
+__global__ void __launch_bounds__(kCanonBlock)
+canon_fixup_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ stg,
+                   const int32_t *__restrict__ out_row_ptr, int32_t *__restrict__ out_col)
 {
-    if (row_ptr_out[n] == nnz) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x)
-        tmp[i] = col_out[i];
-}
-
-__global__ void canon_copy_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr_in,
-                                  const int32_t *__restrict__ tmp, const int32_t *__restrict__ row_ptr_out,
-                                  int32_t *__restrict__ col_out)
-{
-    if (row_ptr_out[n] == nnz) return;
+    if (out_row_ptr[n] == nnz) return;
     const int waves = blockDim.x / GM_WAVE;
     for (int64_t v = (int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE; v < n;
          v += (int64_t)gridDim.x * waves) {
-        const int32_t a = row_ptr_in[v], o = row_ptr_out[v], c = row_ptr_out[v + 1] - o;
-        for (int32_t i = lane(); i < c; i += GM_WAVE) col_out[o + i] = tmp[a + i];
+        const int32_t a = row_ptr[v], o = out_row_ptr[v], c = out_row_ptr[v + 1] - o;
+        for (int32_t i = lane(); i < c; i += GM_WAVE) out_col[o + i] = stg[a + i];
     }
 }
 
@@ -479,16 +665,25 @@ hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t len, v
     return hipGetLastError();
 }
 
+constexpr int kLongBlocks = 64;
+
+int64_t pow2_at_least(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
 size_t canon_scratch_bytes(int32_t n, int32_t nnz)
 {
+    const size_t blocks = ((size_t)n + kListRows - 1) / kListRows;
     size_t b = 0;
-    b += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));  // tmp
-    b += align256((size_t)(n + 1) * sizeof(int32_t));              // cnt
-    b += align256((size_t)(n + 1) * sizeof(int32_t));              // big list
-    b += align256((size_t)(n + 1) * sizeof(int32_t));              // huge list
-    b += align256(2 * sizeof(int32_t));                            // counters
-    b += align256((size_t)kHugeBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));
-    b += exclusive_scan_scratch_bytes(n);
+    b += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));                               // staged rows
+    b += align256((size_t)(n + 1) * sizeof(int32_t));                                           // cnt
+    b += align256(2 * (blocks + 1) * kListRows * sizeof(int32_t));                              // row lists
+    b += align256(2 * (blocks + 1) * sizeof(int32_t));                                          // list counts
+    b += align256((size_t)((n + kScanRows - 1) / kScanRows + 1) * sizeof(unsigned long long));   // flags
+    b += align256((size_t)kLongBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));             // bitmaps
     return b;
 }
 
@@ -496,30 +691,36 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                                const int32_t *col_idx, int32_t *out_row_ptr, int32_t *out_col,
                                void *scratch, hipStream_t s)
 {
-    char *p = (char *)scratch;
-    int32_t *tmp = (int32_t *)p;      p += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
-    int32_t *cnt = (int32_t *)p;      p += align256((size_t)(n + 1) * sizeof(int32_t));
-    int32_t *big = (int32_t *)p;      p += align256((size_t)(n + 1) * sizeof(int32_t));
-    int32_t *huge = (int32_t *)p;     p += align256((size_t)(n + 1) * sizeof(int32_t));
-    int32_t *counters = (int32_t *)p; p += align256(2 * sizeof(int32_t));
-    uint32_t *bitmaps = (uint32_t *)p; p += align256((size_t)kHugeBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));
-    void *scan_scratch = p;
     if (n <= 0) {
         hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, out_row_ptr, (int64_t)1, 0);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, counters, (int64_t)2, 0);
-    // rows are sorted straight into out_col at the input offsets
-    hipLaunchKernelGGL(canon_tiny_kernel, dim3(grid_for((n + 3) / 4, kCanonBlock / GM_WAVE, 32768)),
-                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, out_col, cnt);
-    hipLaunchKernelGGL(canon_rows_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 32768)),
-                       dim3(kCanonBlock), 0, s, n, row_ptr, col_idx, out_col, cnt, big, counters, huge,
-                       counters + 1);
+    const int32_t blocks = (int32_t)(((int64_t)n + kListRows - 1) / kListRows);
+    const int32_t tiles = (int32_t)(((int64_t)n + kScanRows - 1) / kScanRows);
+    const int64_t slots_pow2 = pow2_at_least((int64_t)blocks * kListRows);
+    char *p = (char *)scratch;
+    int32_t *stg = (int32_t *)p;       p += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    int32_t *cnt = (int32_t *)p;       p += align256((size_t)(n + 1) * sizeof(int32_t));
+    // two lists of (blocks + 1) * kListRows entries and two count arrays of
+    // blocks + 1 (mid and big rows)
+    const int64_t list_stride = (int64_t)(blocks + 1) * kListRows;
+    int32_t *lists = (int32_t *)p;     p += align256(2 * (size_t)list_stride * sizeof(int32_t));
+    int32_t *counts = (int32_t *)p;    p += align256(2 * ((size_t)blocks + 1) * sizeof(int32_t));
+    unsigned long long *flags = (unsigned long long *)p;
+    p += align256((size_t)(tiles + 1) * sizeof(unsigned long long));
+    uint32_t *bitmaps = (uint32_t *)p;
+    hipLaunchKernelGGL(canon_sort_kernel, dim3((unsigned)blocks), dim3(kListRows), 0, s, n, row_ptr, col_idx, out_col,
+                       stg, cnt, lists, counts, list_stride, flags, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t big_lds = (kBigRow + 32) * sizeof(int32_t);
-    // the LDS limit is an attribute of the kernel on each device
-    static bool lds_set[64] = {};
+    const int32_t *list_mid = lists, *list_big = lists + list_stride;
+    const int32_t *n_mid = counts, *n_big = counts + (blocks + 1);
+    const int64_t mid_blocks = (slots_pow2 / kMidSlots + kCanonBlock / GM_WAVE - 1) / (kCanonBlock / GM_WAVE);
+    hipLaunchKernelGGL(canon_mid_kernel, dim3((unsigned)mid_blocks), dim3(kCanonBlock), 0, s, blocks, slots_pow2,
+                       row_ptr, col_idx, out_col, stg, cnt, list_mid, n_mid);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t big_lds = (kBigRow + kBigBlock) * sizeof(int32_t);
+    static bool lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
     int dev = 0;
     e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -529,20 +730,14 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
         if (e != hipSuccess) return e;
         if (dev >= 0 && dev < 64) lds_set[dev] = true;
     }
-    hipLaunchKernelGGL(canon_big_kernel, dim3(512), dim3(kBigBlock), big_lds, s, row_ptr, col_idx,
-                       out_col, cnt, big, counters);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(canon_huge_kernel, dim3(kHugeBlocks), dim3(kBigBlock), 0, s, n, row_ptr,
-                       col_idx, out_col, cnt, huge, counters + 1, bitmaps);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = launch_exclusive_scan(cnt, out_row_ptr, n, scan_scratch, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(canon_stage_kernel, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, nnz, out_row_ptr, n,
-                       out_col, tmp);
-    hipLaunchKernelGGL(canon_copy_kernel, dim3(grid_for(n, 4, 32768)), dim3(256), 0, s, n, nnz, row_ptr,
-                       tmp, out_row_ptr, out_col);
+    hipLaunchKernelGGL(canon_big_kernel, dim3(kLongBlocks), dim3(kBigBlock), big_lds, s, n, blocks, slots_pow2, row_ptr,
+                       col_idx, out_col, stg, cnt, list_big, n_big, bitmaps);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(canon_scan_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, (const int32_t *)cnt,
+                       out_row_ptr, flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(canon_fixup_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 256)), dim3(kCanonBlock), 0, s, n,
+                       nnz, row_ptr, (const int32_t *)stg, (const int32_t *)out_row_ptr, out_col);
     return hipGetLastError();
 }
 
