@@ -476,7 +476,10 @@ typedef struct gumap_server_stats {
 } gumap_server_stats;
 
 /* Server flag: run the scheduler without a device (results are zeros); for
- * testing admission and ordering logic on machines without a GPU. */
+ * testing admission and ordering logic on machines without a GPU.  In this
+ * mode the environment variable GUMAP_SERVE_NODEV_FAIL_ITER=N makes the
+ * executor report iteration N as failed, as a device error would: every job
+ * with rows in it ends with GUMAP_EDEVICE and the others are unaffected. */
 #define GUMAP_SERVER_NO_DEVICE 1u
 
 /* hbm_budget_bytes: device bytes the resident jobs may hold together;

@@ -29,6 +29,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -350,8 +351,12 @@ struct gumap_server {
     struct Flight {
         int64_t iter;
         int slot;
+        std::vector<std::shared_ptr<Job>> jobs;        // jobs with rows in it
         std::vector<std::shared_ptr<Job>> finishing;   // jobs whose last rows are in it
     };
+    // Device-free scheduler only: the executor reports this iteration as
+    // failed, as a device error would (test hook, GUMAP_SERVE_NODEV_FAIL_ITER).
+    int64_t fail_iter = -1;
     std::deque<Flight> flights;
     int64_t iter_count = 0;
 
@@ -507,6 +512,7 @@ bool gumap_server::launch_iteration()
             j->next_row = r;
             j->last_iter = iter_count;
             if (r >= j->n) fl.finishing.push_back(j);
+            fl.jobs.push_back(j);
         }
         if (table.empty()) return false;
         stats.iterations++;
@@ -562,13 +568,30 @@ bool gumap_server::retire_iterations()
     bool popped = false;
     while (!flights.empty()) {
         Flight &fl = flights.front();
+        bool iter_failed = false;
         if (!no_device) {
             hipError_t q = hipEventQuery(iter_done[fl.slot]);
             if (q == hipErrorNotReady) break;
-            if (q != hipSuccess) (void)hipGetLastError();
+            if (q != hipSuccess) {
+                (void)hipGetLastError();
+                iter_failed = true;
+            }
+        } else {
+            iter_failed = fl.iter == fail_iter;
+        }
+        if (iter_failed) {
+            // the executor reported an error: every job with rows in the
+            // iteration ends with GUMAP_EDEVICE, the others go on
+            for (auto &j : fl.jobs)
+                if (j->state == kAdmitted && std::find(failed.begin(), failed.end(), j) == failed.end())
+                    failed.push_back(j);
+            flights.pop_front();
+            popped = true;
+            continue;
         }
         for (auto &j : fl.finishing) {
             if (j->last_iter != fl.iter || j->state != kAdmitted) continue;
+            if (std::find(failed.begin(), failed.end(), j) != failed.end()) continue;
             const size_t nk = (size_t)j->n * j->k;
             hipError_t e = hipSuccess;
             if (!no_device && j->n > 0) {
@@ -603,6 +626,7 @@ bool gumap_server::retire_iterations()
     }
     std::lock_guard<std::mutex> lk(mu);
     for (auto &j : failed) {
+        if (j->state != kAdmitted) continue;
         admitted.erase(std::remove(admitted.begin(), admitted.end(), j), admitted.end());
         finish_locked(j, GUMAP_EDEVICE);
     }
@@ -750,6 +774,10 @@ gumap_server *gumap_server_create(size_t hbm_budget_bytes, int32_t max_slots, ui
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->no_device = (flags & GUMAP_SERVER_NO_DEVICE) != 0;
+    if (s->no_device) {
+        const char *fi = getenv("GUMAP_SERVE_NODEV_FAIL_ITER");
+        if (fi && *fi) s->fail_iter = strtoll(fi, nullptr, 10);
+    }
     s->alloc.reset(hbm_budget_bytes);
     s->stats.budget_bytes = hbm_budget_bytes;
     s->iter_rows = (int64_t)gm::env_size("GUMAP_SERVE_ITER_ROWS", 1 << 20);

@@ -2,7 +2,7 @@
 
 Every check here is independent of the oracle's own code path: Floyd-Warshall
 and networkx for hop distances, closed forms for structured graphs, the BFS
-certificate, a separate statement of Alg. 4 for the truncated search, the
+certificate, the k nearest hops from networkx distances for the truncated search, the
 companion-matrix roots of the membership polynomial, closed-form bandwidths,
 and a hand-worked example under tests/golden/.
 """
@@ -246,30 +246,25 @@ def test_knn_invariants_against_networkx():
                 assert not others or min(others) > max(chosen_last)
 
 
-# ------------------------------------------------- P-eq and P-alg4 pins
+# ------------------------------------------ P-eq and the k-nearest definition
 
-def partial_bfs_alg4(g, k, v):
-    """Alg. 4 (Sec. 3.3.1) restated with the readings: source at distance 0,
-    a level is a set, stop when the frontier empties.  Tie order is whatever
-    adjacency order gives; only the hop multiset is compared."""
-    visited, tovisit, dist, S = [], [v], 0, {}
-    while len(visited) <= k and tovisit:
-        newvisit = []
-        for u in tovisit:
-            visited.append(u)
-            S[u] = dist
-            if len(visited) > k:
-                break
-            for w in g.neighbors(u):
-                w = int(w)
-                if w not in visited and w not in tovisit and w not in newvisit:
-                    newvisit.append(w)
-        tovisit = newvisit
-        dist += 1
-    return sorted(d for u, d in S.items() if u != v)
+def k_nearest_hops(g, k, v):
+    """The hops of the k nearest other vertices of v (Sec. 3.3.1: the search
+    stops once k other vertices are reached), from the definition: the k
+    smallest shortest-path distances from v to the other vertices it reaches,
+    whatever the tie order.  Distances come from networkx, not from the
+    oracle's BFS."""
+    nxg = nx.Graph()
+    nxg.add_nodes_from(range(g.n))
+    for u in range(g.n):
+        for w in g.col_idx[g.row_ptr[u]:g.row_ptr[u + 1]]:
+            if int(w) != u:
+                nxg.add_edge(u, int(w))
+    dist = nx.single_source_shortest_path_length(nxg, v)
+    return sorted(d for u, d in dist.items() if u != v)[:k]
 
 
-def test_partial_equals_build_and_alg4_multisets():
+def test_partial_equals_build_and_definition_multisets():
     gs = [G.ba(800, 3, 21), G.rgg(800, 6, 22), G.sbm(800, 6, 23), G.grid_2d(15, 20),
           G.star(25), G.disjoint_union([G.path(4), G.cycle(7), G.complete(3), G.empty(2)])]
     for g in gs:
@@ -278,7 +273,7 @@ def test_partial_equals_build_and_alg4_multisets():
             pids, phops = O.knn_partial(g, k)
             assert np.array_equal(ids, pids) and np.array_equal(hops, phops)
             for v in range(0, g.n, max(1, g.n // 60)):
-                ms = partial_bfs_alg4(g, k, v)
+                ms = k_nearest_hops(g, k, v)
                 got = sorted(int(h) for h in phops[v] if h != 255)
                 assert got == ms, (g.name, k, v)
 

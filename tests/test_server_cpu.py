@@ -88,3 +88,23 @@ def test_destroy_with_jobs_in_flight(gumap):
         s.submit(g.row_ptr, g.col_idx, 15)
     s.close()   # must return without waiting for a device
     s.close()
+
+
+def test_executor_device_error_fails_only_its_jobs(gumap, monkeypatch):
+    """The executor reports an iteration as failed (as a device error would):
+    the jobs with rows in it end with EDEVICE, jobs of other iterations
+    finish normally, and the server keeps serving."""
+    monkeypatch.setenv("GUMAP_SERVE_NODEV_FAIL_ITER", "0")
+    first = G.ba(2000, 4, 31)
+    with _server(gumap, 1 << 30) as s:
+        t0 = s.submit(first.row_ptr, first.col_idx, 15)
+        r0 = s.wait(t0, 10000)
+        assert r0["status"] == gumap.EDEVICE
+        later = [G.ba(1500 + 10 * i, 4, 40 + i) for i in range(4)]
+        ts = [s.submit(g.row_ptr, g.col_idx, 15) for g in later]
+        rs = [s.wait(t, 10000) for t in ts]
+        assert all(r["status"] == gumap.OK for r in rs)
+        st = s.stats()
+        assert st["failed"] == 1 and st["completed"] == 4
+        for t in [t0] + ts:
+            s.release(t)
