@@ -36,6 +36,12 @@ int gumap_profile_count(void);
  * Returns 0, or -1 if i is out of range. */
 int gumap_profile_entry(int i, const char **name, int64_t *launches, double *total_ms,
                         double *alg_bytes);
+/* Entry i's total bytes moved beyond its algorithmic bytes: for "msbfs_level"
+ * the lazy commit of the previous level (the visited word written back and
+ * the bit-plane read-modify-writes of each committed word), which the
+ * per-level byte count of the all-source BFS does not include; 0 for other
+ * kernels.  Returns 0, or -1 if i is out of range. */
+int gumap_profile_extra(int i, double *extra_bytes);
 
 #ifdef __cplusplus
 }

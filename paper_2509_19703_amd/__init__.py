@@ -157,6 +157,8 @@ def _load() -> ctypes.CDLL:
     lib.gumap_profile_entry.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.gumap_profile_entry.restype = ctypes.c_int
+    lib.gumap_profile_extra.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.gumap_profile_extra.restype = ctypes.c_int
     lib.gumap_last_error.argtypes = []
     lib.gumap_last_error.restype = ctypes.c_char_p
     if hasattr(lib, "gumap_server_create"):
@@ -195,16 +197,20 @@ def profile_reset() -> None:
 
 
 def profile_entries() -> dict:
-    """{kernel: {"launches", "total_ms", "alg_bytes"}} recorded so far."""
+    """{kernel: {"launches", "total_ms", "alg_bytes", "extra_bytes"}} recorded
+    so far (extra_bytes: bytes moved beyond the algorithmic bytes, see
+    gumap_profile_extra)."""
     out = {}
     for i in range(lib.gumap_profile_count()):
         name = ctypes.c_char_p()
         launches = ctypes.c_int64()
         ms = ctypes.c_double()
         b = ctypes.c_double()
+        x = ctypes.c_double()
         if lib.gumap_profile_entry(i, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms),
-                                   ctypes.byref(b)) == 0:
-            out[name.value.decode()] = {"launches": launches.value, "total_ms": ms.value, "alg_bytes": b.value}
+                                   ctypes.byref(b)) == 0 and lib.gumap_profile_extra(i, ctypes.byref(x)) == 0:
+            out[name.value.decode()] = {"launches": launches.value, "total_ms": ms.value, "alg_bytes": b.value,
+                                        "extra_bytes": x.value}
     return out
 
 

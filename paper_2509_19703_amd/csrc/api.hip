@@ -348,8 +348,13 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const bool full_hops = hop_matrix != nullptr || so != nullptr;   // every finite hop <= 254 is needed
     const int L_cap = full_hops ? 255 : k;
     const int planes_alloc = full_hops ? 8 : bit_length(k);
+    // history mode (not for the fused small-graph kernel): the frontiers of
+    // hops 1..H are kept, so those hops need no bit-plane commits
+    const int hist_levels = fused ? 0 : (int)std::min<size_t>(env_size("GUMAP_HIST_LEVELS", 15), 64);
+    const size_t state_arrays = hist_levels > 0 ? 1 + (size_t)(hist_levels + 3) + (size_t)planes_alloc
+                                                : 3 + (size_t)planes_alloc;
     const size_t arr_per_group = (size_t)n * words;  // uint64 per array per group
-    const size_t bytes_per_group = (3 + (size_t)planes_alloc) * arr_per_group * 8 +
+    const size_t bytes_per_group = state_arrays * arr_per_group * 8 +
                                    (full_hops ? 0 : (size_t)W * n) + (size_t)W * msbfs_hop_chunks(n, 1) * 16 * 4 +
                                    (size_t)(L_cap + 2) * msbfs_stat_spread() * msbfs_stat_fields() * 8;
     const size_t budget = env_size("GUMAP_BFS_BUDGET_MB", 8192) << 20;
@@ -363,7 +368,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const int SF = msbfs_stat_fields(), SP = msbfs_stat_spread();
     const size_t stats_per_level = (size_t)groups_round * SP * SF;   // u64 per level
     const size_t arr_round = arr_per_group * groups_round;
-    if ((st = scratch_get(kSlotBfsState, (3 + (size_t)planes_alloc) * arr_round * 8, (void **)&state))) return st;
+    if ((st = scratch_get(kSlotBfsState, state_arrays * arr_round * 8, (void **)&state))) return st;
     if ((st = scratch_get(kSlotStats, (size_t)(L_cap + 2) * stats_per_level * 8, (void **)&stats))) return st;
     // hop counts per (slot, transpose block); rounds with fewer groups use more blocks per group
     const size_t lvl_cnt_bytes = std::max((size_t)groups_round * msbfs_hop_chunks(n, groups_round),
@@ -405,11 +410,22 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         const size_t first_env = env_size("GUMAP_FIRST_LEVEL", 2);
         const bool first_split = first_env == 2 ? (double)g->nnz * 256.0 <= (double)n * (double)n : first_env != 0;
         const size_t arr = arr_per_group * a.groups;
-        a.front[0] = state;
-        a.front[1] = state + arr;
-        a.visited = state + 2 * arr;
-        a.planes = state + 3 * arr;
+        a.hist_levels = hist_levels;
+        a.levels_run = 0;
+        if (hist_levels > 0) {
+            a.front[0] = a.front[1] = nullptr;
+            a.visited = state;
+            a.hist = state + arr;
+            a.planes = state + (size_t)(1 + hist_levels + 3) * arr;
+        } else {
+            a.hist = nullptr;
+            a.front[0] = state;
+            a.front[1] = state + arr;
+            a.visited = state + 2 * arr;
+            a.planes = state + 3 * arr;
+        }
         a.plane_stride = arr;
+        bool planes_cleared = false;   // history mode: planes cleared before the first hop above H
         a.stats = stats;
         a.stats_groups = a.groups;
         const size_t spl = (size_t)a.groups * SP * SF;   // u64 per level this round
@@ -419,6 +435,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         const int64_t *hop_rows_of = hop_matrix ? slot_row + a.slot0 : local_rows;
         bool spec_valid = false;    // hop rows and selection already launched for the complete BFS
         int spec_hops_mark = -1;
+        std::vector<int> depth_of(a.groups, 0);   // per group: last hop with vertices (per-level path)
         if (fused) {
             int32_t *gout = nullptr;
             void *hg = nullptr;
@@ -454,7 +471,27 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         };
         std::vector<int> marks(L_cap + 3, -1);
         std::vector<char> ran(L_cap + 3, 0);
-        // algorithmic bytes of one level launch, from its counters
+        // algorithmic bytes of one level launch, from its counters: per
+        // group the row pointers (8 per vertex scanned), the frontier,
+        // visited and next-frontier rows (3 W/8 per vertex), the neighbour
+        // frontier words gathered (W/8 per adjacency entry checked) and the
+        // adjacency entries read (4 each).  The lazy commit of the previous
+        // level (visited word written back, bit-plane read-modify-writes)
+        // is counted apart, in commit_bytes.
+        auto commit_bytes = [&](int lv) {
+            double b = 0.0;
+            if (lv == 1 && first_split) return b;
+            const int hop = lv - 1;
+            // history mode keeps hops 1..H as frontiers: no plane writes for them
+            const bool to_planes = hist_levels <= 0 || hop > hist_levels;
+            const int pc = to_planes ? __builtin_popcount((unsigned)(hop > 0 ? hop : 0)) : 0;
+            for (int q = 0; q < a.groups; ++q) {
+                if (!(lv == 1 || level_sum(lv - 1, q, 0) != 0)) continue;
+                const double commits = (double)level_sum(lv, q, 3);
+                b += 8.0 * commits + 16.0 * commits * pc;
+            }
+            return b;
+        };
         auto level_bytes = [&](int lv, bool commit_only) {
             double b = 0.0;
             if (lv == 1 && first_split) {
@@ -463,8 +500,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 for (int q = 0; q < a.groups; ++q) b += 4.0 * n + 16.0 * (double)n * words + 20.0 * level_sum(1, q, 2);
                 return b;
             }
-            const int hop = lv - 1;
-            const int pc = __builtin_popcount((unsigned)(hop > 0 ? hop : 0));
             for (int q = 0; q < a.groups; ++q) {
                 const bool active = lv == 1 || level_sum(lv - 1, q, 0) != 0;
                 if (!active) continue;
@@ -472,9 +507,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 // the launch only committed: no search and nothing found)
                 const bool searched = !commit_only && (level_sum(lv, q, 0) != 0 || level_sum(lv, q, 1) != 0);
                 b += 8.0 * n + (searched ? 24.0 : 16.0) * (double)n * words;
-                // committed words: visited write + plane read-modify-write per set hop bit
-                const double commits = (double)level_sum(lv, q, 3);
-                b += 8.0 * commits + 16.0 * commits * pc;
                 // neighbour frontier words gathered and adjacency entries read
                 b += 8.0 * (double)level_sum(lv, q, 1) + 4.0 * (double)level_sum(lv, q, 2);
             }
@@ -501,7 +533,13 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if (e != hipSuccess) return hip_status(e, "level counters");
             for (int c2 = 0; c2 < chunk && L <= L_cap; ++c2, ++L) {
                 const int hop = L - 1;   // committed by this launch
-                if (hop >= 1 && (hop & (hop - 1)) == 0) {
+                if (hist_levels > 0) {
+                    if (hop > hist_levels && !planes_cleared) {
+                        e = hipMemsetAsync(a.planes, 0, (size_t)planes_alloc * arr * 8, s);
+                        if (e != hipSuccess) return hip_status(e, "plane clear");
+                        planes_cleared = true;
+                    }
+                } else if (hop >= 1 && (hop & (hop - 1)) == 0) {
                     int b = bit_length(hop) - 1;
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
                     if (e != hipSuccess) return hip_status(e, "plane clear");
@@ -520,11 +558,14 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             e = hipMemcpyAsync(hstats + (size_t)first * spl, stats + (size_t)first * spl,
                                (size_t)(L - first) * spl * 8, hipMemcpyDeviceToHost, s);
             bool spec = false;
+            a.levels_run = L - 1;
             if (e == hipSuccess && !so) {
                 e = launch_msbfs_depth(a, first, L, depth, s);
                 a.planes_dev = depth;
                 spec_hops_mark = prof_begin("msbfs_hops", s);
-                if (e == hipSuccess) e = launch_msbfs_hops_counted(a, 8, hop_out, hop_rows_of, n, lvl_cnt, s);
+                // if this batch completed the search, no hop exceeds L - 1
+                if (e == hipSuccess)
+                    e = launch_msbfs_hops_counted(a, std::min(8, bit_length(L - 1)), hop_out, hop_rows_of, n, lvl_cnt, s);
                 prof_end(spec_hops_mark, s, 0.0);
                 a.planes_dev = nullptr;
                 if (e == hipSuccess)
@@ -536,7 +577,10 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_status(e, "bfs stats");
-            for (int lv = first; lv < L; ++lv) prof_set_bytes(marks[lv], level_bytes(lv, false));
+            for (int lv = first; lv < L; ++lv) {
+                prof_set_bytes(marks[lv], level_bytes(lv, false));
+                prof_set_extra(marks[lv], commit_bytes(lv));
+            }
             for (int lv = first; lv < L && !done; ++lv) {
                 bool any = false;
                 for (int q = 0; q < a.groups; ++q) any |= level_sum(lv, q, 0) != 0;
@@ -552,7 +596,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if (!done && L > L_cap) {
                 // level L_cap found vertices; commit them without searching further
                 const int hop = L_cap;
-                if ((hop & (hop - 1)) == 0) {
+                if (hist_levels > 0) {
+                    if (hop > hist_levels && !planes_cleared) {
+                        e = hipMemsetAsync(a.planes, 0, (size_t)planes_alloc * arr * 8, s);
+                        planes_cleared = true;
+                    }
+                } else if ((hop & (hop - 1)) == 0) {
                     int b = bit_length(hop) - 1;
                     if (b < planes_alloc) e = hipMemsetAsync(a.planes + (size_t)b * arr, 0, arr * 8, s);
                 }
@@ -560,6 +609,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if (e != hipSuccess) return hip_status(e, "plane clear / level counters");
                 const int mk = prof_begin("msbfs_level", s);
                 e = launch_msbfs_level(a, L_cap + 1, true, s);
+                a.levels_run = L_cap + 1;
                 // commit-only: reads front + visited, writes the committed words
                 prof_end(mk, s, (double)a.groups * (8.0 * n + 16.0 * (double)n * words));
                 if (e != hipSuccess) return hip_status(e, "bfs commit");
@@ -569,6 +619,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             chunk = std::max(8, L / 2);
         }
+        for (int q = 0; q < a.groups; ++q)
+            for (int lv = 1; lv <= last_level; ++lv)
+                if (level_sum(lv, q, 0) != 0) depth_of[q] = lv;
         }   // per-level launches
         if (range_error)
             return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
@@ -612,7 +665,20 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             prof_set_bytes(stress_mark, 10.0 * round_pairs);
             continue;
         }
-        const double hop_bytes = (double)(planes_used + 1) * (double)arr * 8.0 + (double)a.n_slots * n;
+        // bytes of the transpose: the state words it reads per group (visited
+        // and the planes in use; in history mode the source slots and the
+        // frontiers up to the group's depth, plus the planes of hops above H)
+        // and the hop rows it writes
+        double hop_bytes = (double)a.n_slots * n;
+        for (int q = 0; q < a.groups; ++q) {
+            if (hist_levels <= 0) {
+                hop_bytes += (double)(planes_used + 1) * (double)arr_per_group * 8.0;
+                continue;
+            }
+            const int dq = depth_of[q];
+            const int read = std::min(dq, hist_levels) + (dq > hist_levels ? planes_used : 0);
+            hop_bytes += 4.0 * n + (double)read * (double)arr_per_group * 8.0;
+        }
         if (spec_valid) {
             prof_set_bytes(spec_hops_mark, hop_bytes);
             continue;

@@ -57,10 +57,19 @@ struct MsbfsArgs {
     const int32_t *usrc;      // sorted unique sources, indexed by global slot
     int32_t n_usrc;           // total slots
     const int32_t *slot_of;   // vertex -> global slot or -1
-    uint64_t *front[2];       // rotating frontier / next arrays
+    uint64_t *front[2];       // plane mode: rotating frontier / next arrays
     uint64_t *visited;
     uint64_t *planes;         // 8 bit-planes of the discovery level, plane-major
     size_t plane_stride;      // uint64 elements per plane (= groups * n * words)
+    // History mode (hist_levels = H > 0): the frontier found at hop h is kept
+    // in hist slot h - 1 for h <= H + 1 (two rotating slots H + 1, H + 2
+    // beyond), so hops 1..H need no bit-plane commits: the transposes read
+    // them from the history (up to each group's depth, found from the level
+    // counters of the levels_run levels launched so far); only hops above H
+    // go to the planes.  hist_levels = 0: plane mode (front[2] rotate).
+    uint64_t *hist;
+    int32_t hist_levels;
+    int32_t levels_run;
     unsigned long long *stats; // [level][group][spread][field] counters of each level
     int32_t stats_groups;     // groups per stats level
     const int32_t *heavy;     // vertices of degree above heavy_deg

@@ -62,10 +62,114 @@ struct Counters {
     unsigned long long v[kStatFields];
 };
 
+// The array holding the frontier found at hop h (h >= 1).
+__device__ __forceinline__ uint64_t *front_of(const MsbfsArgs &a, int h)
+{
+    if (a.hist_levels > 0) {
+        const int slot = h <= a.hist_levels + 1 ? h - 1 : a.hist_levels + 1 + (h & 1);
+        return a.hist + (size_t)slot * a.plane_stride;
+    }
+    return a.front[(h + 1) & 1];
+}
+
+// Depth of group g (the last hop at which it found vertices) among the
+// levels launched so far, capped at hist_levels + 1: whole-block call.
+__device__ __forceinline__ int group_depth(const MsbfsArgs &a, int32_t g, int *s_depth)
+{
+    if (a.hist_levels <= 0) return 0;
+    if (threadIdx.x == 0) *s_depth = 0;
+    __syncthreads();
+    const int levels = min(a.levels_run, a.hist_levels + 1);
+    for (int i = threadIdx.x; i < levels * kSpread; i += blockDim.x) {
+        const int h = 1 + i / kSpread, sl = i % kSpread;
+        if (a.stats[(((size_t)h * a.stats_groups + g) * kSpread + sl) * kStatFields + kFieldNewBits]) atomicMax(s_depth, h);
+    }
+    __syncthreads();
+    return *s_depth;
+}
+
+// Visited and first PL bit-plane words of lane l's vertex in each of TILES
+// consecutive 64-vertex tiles from `tile` (word w of group g; items past the
+// graph or past t_end read as 0).  Plane mode reads the stored arrays.  In
+// history mode the visited word is the vertex's own source bit (hop 0) ORed
+// with the frontiers of hops 1..min(depth, H) and the stored planes of the
+// hops above H, and plane bit b is the OR of the frontiers of the hops with
+// bit b set: the frontier loads go out four hops at a time for all tiles
+// before any is used, so that they overlap.
+constexpr int kHistBatch = 2;   // frontier hops loaded together per tile
+
+template <int WORDS, int PL, int TILES>
+__device__ __forceinline__ void load_tile_state(const MsbfsArgs &a, int32_t g, int w, int32_t tile, int32_t t_end,
+                                                int planes_used, int depth, uint64_t (&wv)[TILES],
+                                                uint64_t (&wp)[TILES][PL])
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    const size_t gbase = (size_t)g * a.n * WORDS + w;
+    size_t me[TILES];
+    bool in[TILES];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int32_t v = (tile + t) * 64 + lane();
+        in[t] = v < a.n && tile + t < t_end;
+        me[t] = gbase + ((size_t)(in[t] ? v : 0) << LW);
+#pragma unroll
+        for (int b = 0; b < PL; ++b) wp[t][b] = 0ull;
+    }
+    if (a.hist_levels <= 0) {
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) {
+            wv[t] = in[t] ? a.visited[me[t]] : 0ull;
+#pragma unroll
+            for (int b = 0; b < PL; ++b)
+                if (b < planes_used && in[t]) wp[t][b] = a.planes[(size_t)b * a.plane_stride + me[t]];
+        }
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+        const int32_t v = (tile + t) * 64 + lane();
+        const int32_t ls = (in[t] ? a.slot_of[v] : -1) - a.slot0;
+        const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
+        wv[t] = (in[t] && ls >= 0 && ls < a.n_slots && bit >= 0 && bit < 64) ? 1ull << bit : 0ull;
+    }
+    const int hmax = min(depth, a.hist_levels);
+    for (int h0 = 1; h0 <= hmax; h0 += kHistBatch) {
+        uint64_t f[TILES][kHistBatch];
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u)
+#pragma unroll
+            for (int t = 0; t < TILES; ++t)
+                f[t][u] = (in[t] && h0 + u <= hmax) ? a.hist[(size_t)(h0 + u - 1) * a.plane_stride + me[t]] : 0ull;
+#pragma unroll
+        for (int u = 0; u < kHistBatch; ++u) {
+            const int h = h0 + u;
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) {
+                wv[t] |= f[t][u];
+#pragma unroll
+                for (int b = 0; b < PL; ++b)
+                    if ((h >> b) & 1) wp[t][b] |= f[t][u];
+            }
+        }
+    }
+    if (depth > a.hist_levels) {
+#pragma unroll
+        for (int t = 0; t < TILES; ++t)
+#pragma unroll
+            for (int b = 0; b < PL; ++b)
+                if (b < planes_used && in[t]) {
+                    const uint64_t x = a.planes[(size_t)b * a.plane_stride + me[t]];
+                    wp[t][b] |= x;
+                    wv[t] |= x;
+                }
+    }
+}
+
 // Commit of the previous level's frontier word f of (vertex, word) at `me`,
 // whose visited word is vis; returns the new visited word.  Level 1 (hop 0)
 // stores visited = f for every word, so visited needs no clearing; the
-// bit-planes are cleared by the host before their first hop.
+// bit-planes (every hop in plane mode, hops above H in history mode) are
+// cleared by the host before their first use.
 __device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, size_t me, uint64_t f, uint64_t vis,
                                                 Counters &c)
 {
@@ -78,8 +182,9 @@ __device__ __forceinline__ uint64_t commit_word(const MsbfsArgs &a, int level, s
         vis |= f;
         a.visited[me] = vis;
         const int hop = level - 1;
-        for (int b = 0; b < 8; ++b)
-            if ((hop >> b) & 1) a.planes[(size_t)b * a.plane_stride + me] |= f;
+        if (a.hist_levels <= 0 || hop > a.hist_levels)
+            for (int b = 0; b < 8; ++b)
+                if ((hop >> b) & 1) a.planes[(size_t)b * a.plane_stride + me] |= f;
         c.v[kFieldCommits] += 1;
     }
     return vis;
@@ -124,7 +229,8 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
         if (got == (unsigned long long)(a.n - 1) * (unsigned long long)in_group) commit_only = 1;
     }
     Counters c{};
-    const uint64_t *__restrict__ fr = a.front[level & 1];
+    const uint64_t *__restrict__ fr = level >= 2 ? front_of(a, level - 1) : nullptr;
+    uint64_t *__restrict__ nx = front_of(a, level);
     // heavy-vertex waves come first in launch order: the longest rows start
     // early instead of forming the tail of the level
     if (vb >= heavy_blocks) {
@@ -209,7 +315,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                     }
                 }
                 const uint64_t nw = acc & unv;
-                a.front[(level + 1) & 1][me] = nw;
+                nx[me] = nw;
                 c.v[kFieldNewBits] += __popcll(nw);
             }
             // adjacency entries are shared by the word threads of a vertex: count the longest scan once
@@ -256,7 +362,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                 }
                 const uint64_t nw = redv & unv;
                 if (grp == 0) {
-                    a.front[(level + 1) & 1][me] = nw;
+                    nx[me] = nw;
                     c.v[kFieldNewBits] += __popcll(nw);
                 }
             }
@@ -297,7 +403,7 @@ __global__ void __launch_bounds__(256) msbfs_first_fill_kernel(MsbfsArgs a)
         const int32_t ls = a.slot_of[v] - a.slot0;
         const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
         a.visited[gbase + idx] = (ls >= 0 && ls < a.n_slots && bit >= 0 && bit < 64) ? 1ull << bit : 0ull;
-        a.front[0][gbase + idx] = 0ull;
+        front_of(a, 1)[gbase + idx] = 0ull;
     }
 }
 
@@ -315,7 +421,7 @@ __global__ void __launch_bounds__(256) msbfs_first_scatter_kernel(MsbfsArgs a)
     const unsigned long long bit = 1ull << (slot & 63);
     const int32_t v = a.usrc[a.slot0 + slot];
     const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
-    unsigned long long *fr = (unsigned long long *)a.front[0] + (size_t)g * a.n * WORDS + w;
+    unsigned long long *fr = (unsigned long long *)front_of(a, 1) + (size_t)g * a.n * WORDS + w;
     unsigned long long nb = 0;
     for (int32_t e = e0 + l; e < e1; e += GM_WAVE) {
         const unsigned long long old = atomicOr(fr + ((size_t)a.col[e] << LW), bit);
@@ -485,15 +591,15 @@ __global__ void __launch_bounds__(WORDS * GM_WAVE)
 msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
                   const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part)
 {
-    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
     const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
     const int w = threadIdx.x / GM_WAVE, l = lane();
     const int32_t g = blockIdx.y;
+    __shared__ int s_depth;
+    const int depth = group_depth(a, g, &s_depth);
     const int32_t local_slot = g * 64 * WORDS + 64 * w + l;
     const bool slot_ok = local_slot < a.n_slots;
     const int64_t row = slot_ok ? slot_row[local_slot] : 0;
     const int32_t ntiles = (a.n + 63) / 64;
-    const size_t gbase = (size_t)g * a.n * WORDS + w;
     unsigned int cnt[kCountLevels];
 #pragma unroll
     for (int h = 0; h < kCountLevels; ++h) cnt[h] = 0;
@@ -504,16 +610,14 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
     const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     for (int32_t tile = t_begin; tile < t_end; tile += STEP) {
         uint64_t outw[STEP][8];
+        uint64_t sv[STEP], sp[STEP][8];
+        load_tile_state<WORDS, 8, STEP>(a, g, w, tile, t_end, planes_used, depth, sv, sp);
 #pragma unroll
         for (int half = 0; half < STEP; ++half) {
-            const int32_t v = (tile + half) * 64 + l;
-            const bool in = v < a.n && tile + half < t_end;
-            const size_t me = gbase + ((size_t)v << LW);
-            uint64_t vis = in ? a.visited[me] : 0ull;
+            uint64_t vis = transpose64(sv[half]);
             uint64_t pl[8];
 #pragma unroll
-            for (int b = 0; b < 8; ++b) pl[b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
-            vis = transpose64(vis);
+            for (int b = 0; b < 8; ++b) pl[b] = sp[half][b];
 #pragma unroll
             for (int b = 0; b < 8; ++b)
                 if (b < planes_used) pl[b] = transpose64(pl[b]);
@@ -578,12 +682,12 @@ constexpr int kStressIts = 8;   // rows per thread in the store / stress phase o
 // are loaded before the current tiles' rows are stored, so that the loads
 // overlap the stores; the 8-plane form would need too many registers for that.
 template <int WORDS, int TILES, bool STRESS, int PL>
-__device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_used, uint8_t *__restrict__ hop_out,
-                                                 unsigned int *__restrict__ part, const StressArgs &sa,
-                                                 uint8_t *stage, const int64_t *row_base, const double *rinv,
-                                                 double *st_sum, unsigned int *st_cnt, const float2 *st_xy)
+__device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_used, int depth,
+                                                 uint8_t *__restrict__ hop_out, unsigned int *__restrict__ part,
+                                                 const StressArgs &sa, uint8_t *stage, const int64_t *row_base,
+                                                 const double *rinv, double *st_sum, unsigned int *st_cnt,
+                                                 const float2 *st_xy)
 {
-    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
     constexpr int ROWS = WORDS * GM_WAVE;        // sources of the group = rows staged
     constexpr int SEG = 64 * TILES;              // bytes per row per step
     constexpr int UNIT = 8 * TILES;              // bytes per store: 8 or 16
@@ -595,7 +699,6 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
     const int32_t local_slot = g * ROWS + 64 * w + l;
     const bool slot_ok = local_slot < a.n_slots;
     const int32_t ntiles = (a.n + 63) / 64;
-    const size_t gbase = (size_t)g * a.n * WORDS + w;
     unsigned int cnt[kCountLevels];
 #pragma unroll
     for (int h = 0; h < kCountLevels; ++h) cnt[h] = 0;
@@ -604,16 +707,7 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
     const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     uint64_t wv[TILES], wp[TILES][PL];   // visited and plane words of the tiles being (or next to be) transposed
     auto load_tiles = [&](int32_t tile) {
-#pragma unroll
-        for (int half = 0; half < TILES; ++half) {
-            const int32_t v = (tile + half) * 64 + l;
-            const bool in = v < a.n && tile + half < t_end;
-            const size_t me = gbase + ((size_t)v << LW);
-            wv[half] = in ? a.visited[me] : 0ull;
-#pragma unroll
-            for (int b = 0; b < PL; ++b)
-                wp[half][b] = (b < planes_used && in) ? a.planes[(size_t)b * a.plane_stride + me] : 0ull;
-        }
+        load_tile_state<WORDS, PL, TILES>(a, g, w, tile, t_end, planes_used, depth, wv, wp);
     };
     if (PREFETCH && t_begin < t_end) load_tiles(t_begin);
     for (int32_t tile = t_begin; tile < t_end; tile += TILES) {
@@ -704,17 +798,21 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
 // With STRESS the staged bytes are not stored: each row's stress terms
 // ((h - |X_s - X_v|) / h)^2 over reachable v != s (Sec. 4.1.3) are summed in
 // FP64 instead, one partial sum and pair count per (slot, block).
-template <int WORDS, int TILES, bool STRESS>
-__global__ void __launch_bounds__(WORDS * GM_WAVE)
+// PL (4 or 8) bounds the planes in use; the launcher picks it from
+// planes_arg, an upper bound of the count read from planes_dev when that is
+// set, so that each form gets its own register budget.
+template <int WORDS, int TILES, bool STRESS, int PL>
+__global__ void __launch_bounds__(WORDS * GM_WAVE) __attribute__((amdgpu_waves_per_eu(STRESS || PL > 4 ? 1 : 4)))
 msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
                          const int64_t *__restrict__ slot_row, int64_t row_stride, unsigned int *__restrict__ part,
                          StressArgs sa)
 {
-    const int planes_used = a.planes_dev ? *a.planes_dev : planes_arg;
+    const int planes_used = min(a.planes_dev ? *a.planes_dev : planes_arg, PL);
     constexpr int ROWS = WORDS * GM_WAVE;
     constexpr int PITCH = 64 * TILES + 8 * TILES;
     __shared__ __align__(16) uint8_t stage[ROWS * PITCH];
     __shared__ int64_t row_base[ROWS];
+    __shared__ int s_depth;
     __shared__ double rinv[STRESS ? 256 : 1];   // 1 / h for the stress terms
     const int32_t g = blockIdx.y;
     const int32_t local_slot = g * ROWS + threadIdx.x;
@@ -734,12 +832,9 @@ msbfs_hops_staged_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_
     } else {
         row_base[threadIdx.x] = local_slot < a.n_slots ? slot_row[local_slot] * row_stride : -1;
     }
-    if (planes_used <= 4)
-        hops_staged_body<WORDS, TILES, STRESS, 4>(a, planes_used, hop_out, part, sa, stage, row_base, rinv, st_sum,
-                                                  st_cnt, st_xy);
-    else
-        hops_staged_body<WORDS, TILES, STRESS, 8>(a, planes_used, hop_out, part, sa, stage, row_base, rinv, st_sum,
-                                                  st_cnt, st_xy);
+    const int depth = group_depth(a, g, &s_depth);
+    hops_staged_body<WORDS, TILES, STRESS, PL>(a, planes_used, depth, hop_out, part, sa, stage, row_base, rinv, st_sum,
+                                               st_cnt, st_xy);
     if (STRESS) {
         // the 8 threads of a row are adjacent lanes: reduce, then one writes
 #pragma unroll
@@ -768,15 +863,32 @@ hipError_t launch_hops_words(dim3 grid, int variant, const MsbfsArgs &a, int pla
     const bool a16 = (row_stride % 16) == 0 && (((uintptr_t)hop_out) & 15) == 0;
     const bool a8 = (row_stride % 8) == 0 && (((uintptr_t)hop_out) & 7) == 0;
     const StressArgs none{};
-    if (variant == 0 && a16)
-        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
-    else if ((variant == 0 || variant == 3) && a8)
-        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 1, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+    const bool pl4 = planes_used <= 4;
+    if (variant == 0 && a16) {
+        if (pl4)
+            hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, false, 4>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+        else
+            hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, false, 8>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+    } else if ((variant == 0 || variant == 3) && a8) {
+        if (pl4)
+            hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 1, false, 4>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+        else
+            hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 1, false, 8>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part, none);
+    }
     else if (variant == 2)
         hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 2, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
     else
         hipLaunchKernelGGL((msbfs_hops_kernel<WORDS, 1, false>), grid, block, 0, s, a, planes_used, hop_out, slot_row, row_stride, part);
     return hipGetLastError();
+}
+
+template <int WORDS>
+void launch_stress_words(dim3 grid, const MsbfsArgs &a, int planes_used, const StressArgs &sa, hipStream_t s)
+{
+    if (planes_used <= 4)
+        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, true, 4>), grid, dim3(WORDS * GM_WAVE), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa);
+    else
+        hipLaunchKernelGGL((msbfs_hops_staged_kernel<WORDS, 2, true, 8>), grid, dim3(WORDS * GM_WAVE), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa);
 }
 
 }  // namespace
@@ -912,10 +1024,10 @@ hipError_t launch_msbfs_stress(const MsbfsArgs &a, int planes_used, const Stress
 {
     dim3 grid((unsigned)msbfs_hop_chunks(a.n, a.groups), (unsigned)a.groups);
     switch (a.words) {
-    case 1: hipLaunchKernelGGL((msbfs_hops_staged_kernel<1, 2, true>), grid, dim3(64), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
-    case 2: hipLaunchKernelGGL((msbfs_hops_staged_kernel<2, 2, true>), grid, dim3(128), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
-    case 4: hipLaunchKernelGGL((msbfs_hops_staged_kernel<4, 2, true>), grid, dim3(256), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
-    case 8: hipLaunchKernelGGL((msbfs_hops_staged_kernel<8, 2, true>), grid, dim3(512), 0, s, a, planes_used, nullptr, nullptr, 0, nullptr, sa); break;
+    case 1: launch_stress_words<1>(grid, a, planes_used, sa, s); break;
+    case 2: launch_stress_words<2>(grid, a, planes_used, sa, s); break;
+    case 4: launch_stress_words<4>(grid, a, planes_used, sa, s); break;
+    case 8: launch_stress_words<8>(grid, a, planes_used, sa, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

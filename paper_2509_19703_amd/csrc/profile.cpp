@@ -16,12 +16,12 @@ namespace {
 struct Pending {
     std::string name;
     hipEvent_t start = nullptr, stop = nullptr;
-    double bytes = 0.0;
+    double bytes = 0.0, extra = 0.0;
 };
 
 struct Totals {
     int64_t launches = 0;
-    double ms = 0.0, bytes = 0.0;
+    double ms = 0.0, bytes = 0.0, extra = 0.0;
 };
 
 struct Profiler {
@@ -106,6 +106,14 @@ void prof_set_bytes(int mark, double bytes)
     if (mark < (int)p.pending.size()) p.pending[mark].bytes = bytes;
 }
 
+void prof_set_extra(int mark, double bytes)
+{
+    if (mark < 0) return;
+    Profiler &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (mark < (int)p.pending.size()) p.pending[mark].extra = bytes;
+}
+
 void prof_resolve()
 {
     Profiler &p = prof();
@@ -121,6 +129,7 @@ void prof_resolve()
             it->second.launches += 1;
             it->second.ms += ms;
             it->second.bytes += x.bytes;
+            it->second.extra += x.extra;
         } else {
             (void)hipGetLastError();
         }
@@ -180,6 +189,15 @@ int gumap_profile_entry(int i, const char **name, int64_t *launches, double *tot
     if (launches) *launches = t.launches;
     if (total_ms) *total_ms = t.ms;
     if (alg_bytes) *alg_bytes = t.bytes;
+    return 0;
+}
+
+int gumap_profile_extra(int i, double *extra_bytes)
+{
+    gm::Profiler &p = gm::prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (i < 0 || i >= (int)p.order.size()) return -1;
+    if (extra_bytes) *extra_bytes = p.totals[p.order[i]].extra;
     return 0;
 }
 

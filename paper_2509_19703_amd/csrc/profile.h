@@ -12,6 +12,8 @@ bool prof_on();
 int prof_begin(const char *name, hipStream_t s);
 void prof_end(int mark, hipStream_t s, double bytes);
 void prof_set_bytes(int mark, double bytes);
+// Bytes a launch moves beyond its algorithmic bytes (reported separately).
+void prof_set_extra(int mark, double bytes);
 void prof_resolve();
 
 }  // namespace gm

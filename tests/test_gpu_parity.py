@@ -110,6 +110,32 @@ def test_level_items_per_thread_invariance(gumap, verts, first, monkeypatch):
         _check_build(gumap, g, 7, sources=src, hop_matrix=False)
 
 
+@pytest.mark.parametrize("hist", ["0", "1", "3", "15"])
+def test_frontier_history_depth_invariance(gumap, hist, monkeypatch):
+    """The hop rows are the oracle's whether hops 1..H are rebuilt from the
+    kept frontiers (H = 1, 3, 15) or every hop goes to the bit-planes
+    (H = 0): graphs whose depth is below, at and far above H (a path of
+    depth 249, a grid of depth 55), truncated searches that end at k, and
+    the stress terms that read the same hop rows."""
+    import torch
+    monkeypatch.setenv("GUMAP_FUSED", "0")
+    monkeypatch.setenv("GUMAP_HIST_LEVELS", hist)
+    print("frontier history levels %s" % hist, flush=True)
+    for g, words in ((G.path(250), 1), (G.grid_2d(20, 37), 2), (G.ba(3001, 3, 61), 8), (G.star(700), 4)):
+        monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+        _check_build(gumap, g, 15, hop_matrix=True)
+        src = G.sample_sources(g.n, 257, 62)
+        _check_build(gumap, g, 3, sources=src, hop_matrix=False)
+        _check_build(gumap, g, 17, sources=src, hop_matrix=True)
+    g = G.grid_2d(24, 29)
+    xy = np.random.default_rng(63).standard_normal((g.n, 2)).astype(np.float32)
+    rp, ci = to_dev(g)
+    gs, gp = gumap.stress(rp, ci, torch.from_numpy(xy).cuda(), flags=gumap.CSR_SORTED)
+    os_, op = O.stress(g, xy)
+    assert gp == op
+    assert abs(gs - os_) <= 1e-9 * max(1.0, abs(os_))
+
+
 def test_sources_with_repeats_and_order(gumap):
     g = G.sbm(2500, 10, 41)
     src = np.concatenate([G.sample_sources(g.n, 300, 42), [5, 5, 17, 2499, 0, 17]]).astype(np.int32)
