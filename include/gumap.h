@@ -104,6 +104,57 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
                     int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream);
 
 /*
+ * Autotuning of gumap_knn_build (the same outputs; only the speed of the
+ * search depends on these settings).  gumap_knn_build_tune runs the call
+ * on the caller's graph, sources and outputs once per candidate setting --
+ * one warm-up, then the fastest of three timed calls -- by a coordinate
+ * descent from the defaults over: the one-workgroup-per-group form for
+ * small graphs; the source-bitset width (64 x {1, 2, 4, 8} sources per
+ * group); (vertex, word) items per thread of the level kernel {1, 2, 4, 8};
+ * level 1 as a top-down scatter from the sources or a range scan; the
+ * degree above which a vertex is searched by a whole wave {default rule,
+ * 32, 128, 512}; hops kept as frontiers {0, 15}; levels 2.. that may run
+ * top-down {0, 2}.  The pick is written to *out and recorded for the shape
+ * of the call (floor(log2) of n, of the mean degree nnz / n, of the number
+ * of sources and of k, and whether hop_matrix is given); later
+ * gumap_knn_build calls of that shape (and gumap_stress calls, k = 1 with
+ * hop rows) use it.  A setting given in the environment (GUMAP_FUSED,
+ * GUMAP_FORCE_WORDS, GUMAP_LEVEL_VERTS, GUMAP_FIRST_LEVEL,
+ * GUMAP_HEAVY_DEGREE, GUMAP_HIST_LEVELS, GUMAP_PUSH_LEVELS) overrides the
+ * recorded one.  If GUMAP_AUTOTUNE_CACHE names a file, the recorded picks
+ * are read from it on first use and the file is rewritten (JSON) after each
+ * tuning.  Arguments and errors as gumap_knn_build; GUMAP_EINVAL also for
+ * out == NULL or an unwritable cache file.
+ */
+typedef struct gumap_build_tuning {
+    int32_t fused;        /* 1: every level of a group in one workgroup (words = 1) */
+    int32_t words;        /* 64-bit source words per vertex per group */
+    int32_t level_verts;  /* (vertex, word) items per thread of the level kernel */
+    int32_t first_level;  /* 1: fill + top-down scatter from the sources; 0: range scan */
+    int32_t heavy_degree; /* whole-wave search above this degree; 0: max(64, 8 x mean degree) */
+    int32_t hist_levels;  /* hops kept as frontiers instead of bit-plane updates */
+    int32_t push_levels;  /* levels after the sources that may run top-down */
+    int32_t candidates;   /* settings timed */
+    float best_ms;        /* one call with the pick */
+    float default_ms;     /* one call with the defaults */
+} gumap_build_tuning;
+int gumap_knn_build_tune(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
+                         int32_t *nbr_ids, uint8_t *nbr_hops, uint8_t *hop_matrix, hipStream_t stream,
+                         gumap_build_tuning *out);
+/* The recorded pick for calls of this shape (hop_matrix != 0: hop rows
+ * wanted); host only.  Returns 1 and fills *out if there is one, 0 if not,
+ * GUMAP_EINVAL for out == NULL, a negative size or k < 1. */
+int gumap_build_tuning_lookup(int32_t n, int64_t nnz, int64_t n_sources, int32_t k, int hop_matrix,
+                              gumap_build_tuning *out);
+/* Replace the recorded picks by those of a cache file / write them to one;
+ * host only.  GUMAP_EINVAL if the file cannot be read or written or is not a
+ * cache written by this library (the picks are then unchanged). */
+int gumap_autotune_cache_load(const char *path);
+int gumap_autotune_cache_save(const char *path);
+/* Forget every recorded pick (and do not read GUMAP_AUTOTUNE_CACHE again). */
+void gumap_autotune_clear(void);
+
+/*
  * Aggregated stress of a drawing (Sec. 4.1.3 quality metrics): the sum over
  * ordered pairs (s, v), s in `sources` (every vertex when sources is NULL;
  * a source listed twice counts twice) and v != s reachable from s, of

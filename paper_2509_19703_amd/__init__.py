@@ -42,6 +42,16 @@ class gumap_batch_tuning(ctypes.Structure):
                 ("candidates", ctypes.c_int32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float)]
 
 
+class gumap_build_tuning(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_int32), ("words", ctypes.c_int32), ("level_verts", ctypes.c_int32),
+                ("first_level", ctypes.c_int32), ("heavy_degree", ctypes.c_int32), ("hist_levels", ctypes.c_int32),
+                ("push_levels", ctypes.c_int32), ("candidates", ctypes.c_int32), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class gumap_layout_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha0", ctypes.c_double), ("samp", ctypes.c_double), ("window", ctypes.c_int64),
@@ -118,6 +128,16 @@ def _load() -> ctypes.CDLL:
     lib.gumap_csr_canonicalize.restype = ctypes.c_int
     lib.gumap_knn_build.argtypes = [G, i32, vp, i32, vp, vp, vp, vp]
     lib.gumap_knn_partial.argtypes = [G, i32, vp, vp, vp]
+    lib.gumap_knn_build_tune.argtypes = [G, i32, vp, i32, vp, vp, vp, vp, ctypes.POINTER(gumap_build_tuning)]
+    lib.gumap_knn_build_tune.restype = ctypes.c_int
+    lib.gumap_build_tuning_lookup.argtypes = [i32, i64, i64, i32, ctypes.c_int, ctypes.POINTER(gumap_build_tuning)]
+    lib.gumap_build_tuning_lookup.restype = ctypes.c_int
+    lib.gumap_autotune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.gumap_autotune_cache_load.restype = ctypes.c_int
+    lib.gumap_autotune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.gumap_autotune_cache_save.restype = ctypes.c_int
+    lib.gumap_autotune_clear.argtypes = []
+    lib.gumap_autotune_clear.restype = None
     lib.gumap_stress.argtypes = [G, vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp]
     lib.gumap_stress.restype = ctypes.c_int
     lib.gumap_neighborhood.argtypes = [G, vp, i32, vp, i32, vp, vp, vp]
@@ -260,6 +280,34 @@ def gumap_knn_build(graph: gumap_graph, k: int, sources, n_sources: int, nbr_ids
                                       _ptr(nbr_hops), _ptr(hop_matrix), _stream(stream)))
 
 
+def gumap_knn_build_tune(graph: gumap_graph, k: int, sources, n_sources: int, nbr_ids, nbr_hops,
+                         hop_matrix=None, stream=None) -> dict:
+    """Autotune gumap_knn_build on this call (it writes the outputs); returns the pick."""
+    out = gumap_build_tuning()
+    _check(lib.gumap_knn_build_tune(ctypes.byref(graph), k, _ptr(sources), n_sources, _ptr(nbr_ids),
+                                    _ptr(nbr_hops), _ptr(hop_matrix), _stream(stream), ctypes.byref(out)))
+    return out.as_dict()
+
+
+def gumap_build_tuning_lookup(n: int, nnz: int, n_sources: int, k: int, hop_matrix: bool):
+    """The recorded autotuner pick for calls of this shape, or None."""
+    out = gumap_build_tuning()
+    found = _check(lib.gumap_build_tuning_lookup(n, nnz, n_sources, k, 1 if hop_matrix else 0, ctypes.byref(out)))
+    return out.as_dict() if found == 1 else None
+
+
+def gumap_autotune_cache_load(path: str) -> int:
+    return _check(lib.gumap_autotune_cache_load(path.encode()))
+
+
+def gumap_autotune_cache_save(path: str) -> int:
+    return _check(lib.gumap_autotune_cache_save(path.encode()))
+
+
+def gumap_autotune_clear() -> None:
+    lib.gumap_autotune_clear()
+
+
 def gumap_knn_partial(graph: gumap_graph, k: int, nbr_ids, nbr_hops, stream=None) -> int:
     return _check(lib.gumap_knn_partial(ctypes.byref(graph), k, _ptr(nbr_ids), _ptr(nbr_hops),
                                         _stream(stream)))
@@ -315,6 +363,20 @@ def knn_build(row_ptr, col_idx, k: int, sources=None, hop_matrix: bool = False, 
     hm = torch.empty((rows, g.n), dtype=torch.uint8, device=dev) if hop_matrix else None
     gumap_knn_build(g, k, sources, rows if sources is not None else 0, ids, hops, hm, stream)
     return ids, hops, hm
+
+
+def knn_build_tune(row_ptr, col_idx, k: int, sources=None, hop_matrix: bool = False, flags: int = 0,
+                   stream=None):
+    """knn_build through the autotuner.  Returns (ids, hops, hop_matrix or None, pick)."""
+    torch = _torch()
+    dev = row_ptr.device
+    g = make_graph(row_ptr, col_idx, flags=flags)
+    rows = g.n if sources is None else int(sources.shape[0])
+    ids = torch.empty((rows, k), dtype=torch.int32, device=dev)
+    hops = torch.empty((rows, k), dtype=torch.uint8, device=dev)
+    hm = torch.empty((rows, g.n), dtype=torch.uint8, device=dev) if hop_matrix else None
+    pick = gumap_knn_build_tune(g, k, sources, rows if sources is not None else 0, ids, hops, hm, stream)
+    return ids, hops, hm, pick
 
 
 def knn_partial(row_ptr, col_idx, k: int, flags: int = 0, stream=None):

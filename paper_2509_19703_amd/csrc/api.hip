@@ -132,6 +132,13 @@ size_t env_size(const char *name, size_t dflt)
     return end && end != v ? (size_t)x : dflt;
 }
 
+size_t knob(const char *name, int kb_value, size_t dflt)
+{
+    const char *v = getenv(name);
+    if (v && *v) return env_size(name, dflt);
+    return kb_value >= 0 ? (size_t)kb_value : dflt;
+}
+
 // Reads a device int flag (after the stream drains).
 int read_flag(const int *dflag, int *out, hipStream_t s)
 {
@@ -241,9 +248,9 @@ int bit_length(int x)
     return b;
 }
 
-int choose_words(int32_t n_uniq)
+int choose_words(int32_t n_uniq, const BuildKnobs *kb)
 {
-    size_t forced = env_size("GUMAP_FORCE_WORDS", 0);
+    size_t forced = knob("GUMAP_FORCE_WORDS", kb ? kb->words : -1, 0);
     if (forced == 1 || forced == 2 || forced == 4 || forced == 8) return (int)forced;
     int need = (n_uniq + 63) / 64;
     int w = 1;
@@ -263,8 +270,12 @@ struct StressOut {
 };
 
 int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources,
-              int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s, StressOut *so = nullptr)
+              int32_t *ids, uint8_t *hops, uint8_t *hop_matrix, hipStream_t s, StressOut *so = nullptr,
+              const BuildKnobs *kb = nullptr)
 {
+    const BuildKnobs none;
+    if (!kb) kb = &none;
+    const int32_t heavy_forced = (int32_t)knob("GUMAP_HEAVY_DEGREE", kb->heavy, 0);
     int st;
     if ((st = check_graph_args(g))) return st;
     if ((st = check_k(k))) return st;
@@ -308,7 +319,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if ((st = scratch_get(kSlotMult, (size_t)n * sizeof(int32_t), (void **)&mult))) return st;
         }
         if (sources_ranked_small(rows, n))
-            e = prepare_sources_small(sources, rows, n, c.row_ptr, (int32_t)env_size("GUMAP_HEAVY_DEGREE", 0), heavy,
+            e = prepare_sources_small(sources, rows, n, c.row_ptr, heavy_forced, heavy,
                                       first_row, count, usrc, slot_row, slot_of, mult, info, s);
         else
             e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of,
@@ -316,7 +327,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     }
     // vertices of high degree get a whole wave per level
     if (e == hipSuccess && (all_sources || !sources_ranked_small(rows, n)))
-        e = launch_heavy_list(n, c.row_ptr, (int32_t)env_size("GUMAP_HEAVY_DEGREE", 0), heavy, info, s);
+        e = launch_heavy_list(n, c.row_ptr, heavy_forced, heavy, info, s);
     if (e != hipSuccess) return hip_status(e, "source setup");
     int32_t hinfo[8];
     {
@@ -340,9 +351,9 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
 
     // small graphs: every level of a group in one workgroup with its state in
     // LDS (one 64-source word per vertex), instead of one launch per level
-    const bool fused = env_size("GUMAP_FUSED", 1) != 0 && env_size("GUMAP_FORCE_WORDS", 0) == 0 &&
+    const bool fused = knob("GUMAP_FUSED", kb->fused, 1) != 0 && env_size("GUMAP_FORCE_WORDS", 0) == 0 &&
                        msbfs_fused_lds_bytes(n) <= 144 * 1024;
-    const int words = fused ? 1 : choose_words(n_uniq);
+    const int words = fused ? 1 : choose_words(n_uniq, kb);
     const int W = 64 * words;
     const int32_t groups_total = (n_uniq + W - 1) / W;
     const bool full_hops = hop_matrix != nullptr || so != nullptr;   // every finite hop <= 254 is needed
@@ -350,7 +361,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     const int planes_alloc = full_hops ? 8 : bit_length(k);
     // history mode (not for the fused small-graph kernel): the frontiers of
     // hops 1..H are kept, so those hops need no bit-plane commits
-    const int hist_levels = fused ? 0 : (int)std::min<size_t>(env_size("GUMAP_HIST_LEVELS", 15), 64);
+    const int hist_levels = fused ? 0 : (int)std::min<size_t>(knob("GUMAP_HIST_LEVELS", kb->hist, 15), 64);
     const size_t state_arrays = hist_levels > 0 ? 1 + (size_t)(hist_levels + 3) + (size_t)planes_alloc
                                                 : 3 + (size_t)planes_alloc;
     const size_t arr_per_group = (size_t)n * words;  // uint64 per array per group
@@ -400,15 +411,24 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         a.heavy = heavy;
         a.n_heavy = n_heavy;
         a.heavy_deg = heavy_deg;
+        a.heavy_maxdeg = hinfo[4];
         a.xcd_map = (int32_t)env_size("GUMAP_XCD_MAP", 1);
         a.hops_variant = (int32_t)env_size("GUMAP_HOPS_VARIANT", 0);
-        a.level_verts = (int32_t)env_size("GUMAP_LEVEL_VERTS", 4);
+        a.level_verts = (int32_t)knob("GUMAP_LEVEL_VERTS", kb->verts, 4);
         // Level 1 as a fill plus a top-down scatter from the sources (about
         // n_slots * mean degree atomic ORs) on sparse graphs, else by the level
         // kernel's range scan (n * words items per group); GUMAP_FIRST_LEVEL
         // = 0 / 1 forces either.
-        const size_t first_env = env_size("GUMAP_FIRST_LEVEL", 2);
+        const size_t first_env = knob("GUMAP_FIRST_LEVEL", kb->first, 2);
         const bool first_split = first_env == 2 ? (double)g->nnz * 256.0 <= (double)n * (double)n : first_env != 0;
+        // Levels 2..push_levels may run top-down per group (see level_pushes):
+        // needs the first fill, which clears their next-frontier arrays, and
+        // in plane mode only level 2 has an array of its own to clear.
+        a.nnz = g->nnz;
+        a.push_ratio = (int32_t)std::min<size_t>(env_size("GUMAP_PUSH_RATIO", 4), 1 << 20);
+        a.push_levels = first_split ? (int32_t)std::min<size_t>(knob("GUMAP_PUSH_LEVELS", kb->push, 0), hist_levels > 0 ? 3 : 2)
+                                    : 0;
+        a.push_levels = std::min(a.push_levels, L_cap);
         const size_t arr = arr_per_group * a.groups;
         a.hist_levels = hist_levels;
         a.levels_run = 0;
@@ -478,6 +498,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         // adjacency entries read (4 each).  The lazy commit of the previous
         // level (visited word written back, bit-plane read-modify-writes)
         // is counted apart, in commit_bytes.
+        // whether group q ran level lv top-down (the kernels' own test)
+        auto pushes = [&](int lv, int q) {
+            return lv >= 2 && lv <= a.push_levels &&
+                   level_sum(lv - 1, q, 4) * (unsigned long long)a.push_ratio < (unsigned long long)g->nnz * words;
+        };
         auto commit_bytes = [&](int lv) {
             double b = 0.0;
             if (lv == 1 && first_split) return b;
@@ -486,7 +511,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             const bool to_planes = hist_levels <= 0 || hop > hist_levels;
             const int pc = to_planes ? __builtin_popcount((unsigned)(hop > 0 ? hop : 0)) : 0;
             for (int q = 0; q < a.groups; ++q) {
-                if (!(lv == 1 || level_sum(lv - 1, q, 0) != 0)) continue;
+                if (!(lv == 1 || level_sum(lv - 1, q, 0) != 0) || pushes(lv, q)) continue;
                 const double commits = (double)level_sum(lv, q, 3);
                 b += 8.0 * commits + 16.0 * commits * pc;
             }
@@ -502,7 +527,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             for (int q = 0; q < a.groups; ++q) {
                 const bool active = lv == 1 || level_sum(lv - 1, q, 0) != 0;
-                if (!active) continue;
+                if (!active || pushes(lv, q)) continue;
                 // row pointers, frontier + visited reads, next-frontier writes (none when
                 // the launch only committed: no search and nothing found)
                 const bool searched = !commit_only && (level_sum(lv, q, 0) != 0 || level_sum(lv, q, 1) != 0);
@@ -512,6 +537,24 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             }
             return b;
         };
+        // a top-down level: the frontier words scanned, each frontier item's
+        // visited word read and written back (with its plane updates), the
+        // adjacency entries read, and per push the neighbour's visited and
+        // frontier words read and its next-frontier word ORed
+        auto push_bytes = [&](int lv) {
+            double b = 0.0;
+            const int hop = lv - 1;
+            const bool to_planes = hist_levels <= 0 || hop > hist_levels;
+            const int pc = to_planes ? __builtin_popcount((unsigned)hop) : 0;
+            for (int q = 0; q < a.groups; ++q) {
+                if (!pushes(lv, q) || level_sum(lv - 1, q, 0) == 0) continue;
+                const double commits = (double)level_sum(lv, q, 3);
+                b += 8.0 * (double)n * words + (16.0 + 16.0 * pc) * commits + 4.0 * (double)level_sum(lv, q, 2) +
+                     24.0 * (double)level_sum(lv, q, 1);
+            }
+            return b;
+        };
+        std::vector<int> push_marks(L_cap + 3, -1);
 
         // levels launched between reads of the counters: the first batch covers
         // about 1.5x the depth a graph of this mean degree reaches (a level
@@ -548,6 +591,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                     marks[L] = prof_begin("msbfs_first", s);
                     e = launch_msbfs_first(a, s);
                 } else {
+                    if (L <= a.push_levels) {
+                        push_marks[L] = prof_begin("msbfs_push", s);
+                        e = launch_msbfs_push(a, L, s);
+                        prof_end(push_marks[L], s, 0.0);
+                        if (e != hipSuccess) return hip_status(e, "bfs level (top-down)");
+                    }
                     marks[L] = prof_begin("msbfs_level", s);
                     e = launch_msbfs_level(a, L, false, s);
                 }
@@ -580,6 +629,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             for (int lv = first; lv < L; ++lv) {
                 prof_set_bytes(marks[lv], level_bytes(lv, false));
                 prof_set_extra(marks[lv], commit_bytes(lv));
+                if (push_marks[lv] >= 0) prof_set_bytes(push_marks[lv], push_bytes(lv));
             }
             for (int lv = first; lv < L && !done; ++lv) {
                 bool any = false;
@@ -699,13 +749,21 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     return finish(s, "gumap_knn_build");
 }
 
+int knn_build_tuned(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources, int32_t *ids,
+                    uint8_t *hops, uint8_t *hop_matrix, hipStream_t s, const BuildKnobs *kb)
+{
+    return knn_build(g, k, sources, n_sources, ids, hops, hop_matrix, s, nullptr, kb);
+}
+
 int stress(const gumap_graph *g, const float *xy, const int32_t *sources, int32_t n_sources, double *sum,
            int64_t *pairs, hipStream_t s)
 {
     if (!sum || !pairs) return set_error(GUMAP_EINVAL, "output pointer is NULL");
     StressOut so;
     so.xy = xy;
-    int st = knn_build(g, 1, sources, n_sources, nullptr, nullptr, nullptr, s, &so);
+    BuildKnobs kb;
+    const bool tuned = tuned_knobs(g->n, g->nnz, sources ? n_sources : g->n, 1, true, &kb);
+    int st = knn_build(g, 1, sources, n_sources, nullptr, nullptr, nullptr, s, &so, tuned ? &kb : nullptr);
     if (st) return st;
     *sum = so.sum;
     *pairs = so.pairs;
@@ -1599,7 +1657,11 @@ int gumap_knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int
 {
     std::lock_guard<std::mutex> lock(gm::api_mutex());
     gm::clear_error();
-    return gm::settle(gm::knn_build(g, k, sources, n_sources, nbr_ids, nbr_hops, hop_matrix, stream), stream);
+    gm::BuildKnobs kb;
+    const bool tuned = g && gm::tuned_knobs(g->n, g->nnz, sources ? n_sources : g->n, k, hop_matrix != nullptr, &kb);
+    return gm::settle(gm::knn_build(g, k, sources, n_sources, nbr_ids, nbr_hops, hop_matrix, stream, nullptr,
+                                    tuned ? &kb : nullptr),
+                      stream);
 }
 
 int gumap_neighborhood(const gumap_graph *g, const float *xy, int32_t r, const int32_t *vertices,

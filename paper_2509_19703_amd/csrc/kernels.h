@@ -75,18 +75,27 @@ struct MsbfsArgs {
     const int32_t *heavy;     // vertices of degree above heavy_deg
     int32_t n_heavy;
     int32_t heavy_deg;
+    int32_t heavy_maxdeg;     // largest degree among them
     int32_t xcd_map;          // keep each group on one XCD when groups % 8 == 0
     int32_t hops_variant;     // hop-row writer: tiles per step / store kind (tuning)
     int32_t level_verts;      // (vertex, word) items per thread of the level kernel: 1, 2, 4 or 8
     const int32_t *planes_dev; // if not NULL: the transpose reads its plane count here (device)
+    // Direction: levels 2..push_levels may run top-down (msbfs_push_kernel),
+    // per group, when the frontier's edge-words * push_ratio < nnz * words;
+    // the first fill then clears their next-frontier arrays.  0: bottom-up only.
+    int32_t push_levels;
+    int32_t push_ratio;
+    int32_t nnz;
 };
 // Layout of the level counters: stats[((level * groups + g) * spread + slot) * fields + field]
-// with fields {new bits, frontier words gathered, adjacency entries read,
-// frontier words committed}; a level's value is the sum over the spread slots.
+// with fields {new bits, frontier words gathered (pull) or pushed (push),
+// adjacency entries read, frontier words committed, edge-words of the items
+// found}; a level's value is the sum over the spread slots.
 int msbfs_stat_fields();
 int msbfs_stat_spread();
 // heavy[0 .. info[1]) = vertices of degree above the threshold info[2]
-// (forced if > 0, else max(64, 8 * mean degree)); info[1] must be zero.
+// (forced if > 0, else max(64, 8 * mean degree)), info[4] = the largest of
+// their degrees; info[1] and info[4] must be zero.
 hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, int32_t *heavy, int32_t *info,
                              hipStream_t s);
 // Small graphs (words == 1, msbfs_fused_lds_bytes(n) of LDS): every level of
@@ -103,6 +112,10 @@ hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int
 // launch_msbfs_level(a, 1, false, s).  The level-1 counters must be zero.
 hipError_t launch_msbfs_first(const MsbfsArgs &a, hipStream_t s);
 hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, hipStream_t s);
+// The top-down form of level `level` (2 <= level <= a.push_levels) for the
+// groups that pick it; launched beside launch_msbfs_level, whose blocks of
+// those groups return at once (and the other way round).
+hipError_t launch_msbfs_push(const MsbfsArgs &a, int level, hipStream_t s);
 // After levels [first, last) of a round: out[0] = bit_length of the last
 // level that found vertices (the plane count the transpose needs once the
 // BFS is complete), out[1] = 1 if level last - 1 still found vertices.

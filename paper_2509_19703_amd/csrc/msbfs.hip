@@ -47,8 +47,12 @@ constexpr int kHeavyBatch = GM_HEAVY_BATCH;     // neighbour loads in flight per
 constexpr int kFullCheckLevels = 32;  // levels up to which a finished group is detected
 constexpr int kCountLevels = 16;
 constexpr int kSpread = 64;        // level counters are spread over 64 slots per group
-constexpr int kStatFields = 4;
-enum { kFieldNewBits = 0, kFieldGathers = 1, kFieldCols = 2, kFieldCommits = 3 };
+constexpr int kStatFields = 5;
+// per level: bits found, neighbour words read (pull) or pushed (push),
+// adjacency entries read, frontier words committed, and the frontier's
+// edge-words (sum over (vertex, word) items found of the vertex degree,
+// which prices a top-down next level)
+enum { kFieldNewBits = 0, kFieldGathers = 1, kFieldCols = 2, kFieldCommits = 3, kFieldFrontEdges = 4 };
 
 __device__ __forceinline__ uint64_t word_valid_mask(int32_t n_slots, int32_t local_slot0)
 {
@@ -70,6 +74,26 @@ __device__ __forceinline__ uint64_t *front_of(const MsbfsArgs &a, int h)
         return a.hist + (size_t)slot * a.plane_stride;
     }
     return a.front[(h + 1) & 1];
+}
+
+// Whether level `level` of group g runs top-down (msbfs_push_kernel) instead
+// of bottom-up: only levels 2..push_levels, whose next-frontier arrays the
+// first fill clears, and only when the edge-words of the group's frontier
+// (the pushes a top-down level makes), weighted by push_ratio, stay below
+// nnz * WORDS (what a bottom-up level scans while few vertices are reached).
+// Whole-wave call; every block of the group gets the same answer.
+template <int WORDS>
+__device__ __forceinline__ unsigned long long front_edges(const MsbfsArgs &a, int level, int32_t g)
+{
+    return wave_sum_u64(
+        a.stats[(((size_t)(level - 1) * a.stats_groups + g) * kSpread + lane()) * kStatFields + kFieldFrontEdges]);
+}
+
+template <int WORDS>
+__device__ __forceinline__ bool level_pushes(const MsbfsArgs &a, int level, int32_t g)
+{
+    if (level < 2 || level > a.push_levels) return false;
+    return front_edges<WORDS>(a, level, g) * (unsigned long long)a.push_ratio < (unsigned long long)a.nnz * WORDS;
 }
 
 // Depth of group g (the last hop at which it found vertices) among the
@@ -212,6 +236,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
     const int l = lane(), wid = threadIdx.x / GM_WAVE;
     const int heavy_blocks = per_group - light_blocks;
     const size_t gbase = (size_t)g * a.n * WORDS;
+    if (!commit_only && level_pushes<WORDS>(a, level, g)) return;   // run top-down by msbfs_push_kernel
     if (level >= 2) {
         // previous level found nothing for this group: nothing to commit or search
         const unsigned long long x =
@@ -317,6 +342,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                 const uint64_t nw = acc & unv;
                 nx[me] = nw;
                 c.v[kFieldNewBits] += __popcll(nw);
+                if (nw) c.v[kFieldFrontEdges] += (unsigned long long)(e1[j] - e0[j]);
             }
             // adjacency entries are shared by the word threads of a vertex: count the longest scan once
 #pragma unroll
@@ -364,6 +390,7 @@ msbfs_level_kernel(MsbfsArgs a, int level, int commit_only, int light_blocks, in
                 if (grp == 0) {
                     nx[me] = nw;
                     c.v[kFieldNewBits] += __popcll(nw);
+                    if (nw) c.v[kFieldFrontEdges] += (unsigned long long)(a.row_ptr[v + 1] - a.row_ptr[v]);
                 }
             }
         }
@@ -404,6 +431,7 @@ __global__ void __launch_bounds__(256) msbfs_first_fill_kernel(MsbfsArgs a)
         const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
         a.visited[gbase + idx] = (ls >= 0 && ls < a.n_slots && bit >= 0 && bit < 64) ? 1ull << bit : 0ull;
         front_of(a, 1)[gbase + idx] = 0ull;
+        for (int h = 2; h <= a.push_levels; ++h) front_of(a, h)[gbase + idx] = 0ull;
     }
 }
 
@@ -422,16 +450,124 @@ __global__ void __launch_bounds__(256) msbfs_first_scatter_kernel(MsbfsArgs a)
     const int32_t v = a.usrc[a.slot0 + slot];
     const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
     unsigned long long *fr = (unsigned long long *)front_of(a, 1) + (size_t)g * a.n * WORDS + w;
-    unsigned long long nb = 0;
+    unsigned long long nb = 0, fe = 0;
     for (int32_t e = e0 + l; e < e1; e += GM_WAVE) {
-        const unsigned long long old = atomicOr(fr + ((size_t)a.col[e] << LW), bit);
+        const int32_t u = a.col[e];
+        const unsigned long long old = atomicOr(fr + ((size_t)u << LW), bit);
         nb += (old & bit) ? 0ull : 1ull;
+        if (old == 0ull) fe += (unsigned long long)(a.row_ptr[u + 1] - a.row_ptr[u]);   // item newly in the frontier
     }
     nb = wave_sum_u64(nb);
+    fe = wave_sum_u64(fe);
     if (l == 0) {
         unsigned long long *st = a.stats + ((size_t)(1 * a.stats_groups + g) * kSpread + (slot & (kSpread - 1))) * kStatFields;
         if (nb) atomicAdd(st + kFieldNewBits, nb);
         if (e1 > e0) atomicAdd(st + kFieldCols, (unsigned long long)(e1 - e0));
+        if (fe) atomicAdd(st + kFieldFrontEdges, fe);
+    }
+}
+
+// A level run top-down, for the groups level_pushes picks (small frontiers,
+// the levels right after the sources): every frontier item (u, w), f = its
+// word of hop level - 1, is committed, and f less what each neighbour v has
+// reached by hop level - 1 (v's visited word ORed with its frontier word,
+// the same whether or not v's own commit has landed) and not yet in v's
+// next-frontier word (cleared by the first fill) is ORed into it.  A bit that several
+// frontier vertices reach is counted once, by the OR that set it.  One
+// thread per item for vertices of degree <= heavy_deg; a heavy vertex's
+// adjacency is cut into chunks of (64 / WORDS) * kHeavyBatch entries, one
+// wave per chunk (lane = entry, word; all its loads in flight at once),
+// heavy waves first.
+template <int WORDS>
+__global__ void __launch_bounds__(kLevelBlock)
+msbfs_push_kernel(MsbfsArgs a, int level, int light_blocks, int per_group, int chunks)
+{
+    constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
+    constexpr int G = GM_WAVE / WORDS;
+    __shared__ unsigned long long red[kLevelBlock / GM_WAVE][kStatFields];
+    const int32_t g = blockIdx.x / per_group, vb = blockIdx.x % per_group;
+    if (!level_pushes<WORDS>(a, level, g)) return;
+    const int l = lane(), wid = threadIdx.x / GM_WAVE;
+    const int heavy_blocks = per_group - light_blocks;
+    const size_t gbase = (size_t)g * a.n * WORDS;
+    const uint64_t *__restrict__ fr = front_of(a, level - 1);
+    unsigned long long *nx = (unsigned long long *)front_of(a, level);
+    Counters c{};
+    auto push = [&](int32_t u, int w, uint64_t f) {
+        const size_t mu = gbase + ((size_t)u << LW) + w;
+        // bits already in the next-frontier word need no atomic: a hub that
+        // many frontier vertices reach then takes a few ORs, not one each (a
+        // stale read only costs an OR; bits are never cleared)
+        const uint64_t x = f & ~(a.visited[mu] | fr[mu] | nx[mu]);
+        if (x) {
+            const uint64_t old = atomicOr(nx + mu, (unsigned long long)x);
+            c.v[kFieldNewBits] += __popcll(x & ~old);
+            if (old == 0ull) c.v[kFieldFrontEdges] += (unsigned long long)(a.row_ptr[u + 1] - a.row_ptr[u]);
+        }
+    };
+    if (vb >= heavy_blocks) {
+        const int64_t idx = (int64_t)(vb - heavy_blocks) * kLevelBlock + threadIdx.x;
+        const int32_t v = (int32_t)(idx >> LW);
+        const int w = (int)(idx & (WORDS - 1));
+        if (v < a.n) {
+            const size_t me = gbase + (size_t)idx;
+            const uint64_t f = fr[me];
+            if (f) {
+                commit_word(a, level, me, f, a.visited[me], c);
+                const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
+                if (e1 - e0 <= a.heavy_deg) {
+                    for (int32_t e = e0; e < e1; e += kGatherBatch) {
+                        int32_t u[kGatherBatch];
+#pragma unroll
+                        for (int i = 0; i < kGatherBatch; ++i) u[i] = e + i < e1 ? a.col[e + i] : -1;
+#pragma unroll
+                        for (int i = 0; i < kGatherBatch; ++i)
+                            if (u[i] >= 0) push(u[i], w, f);
+                    }
+                    c.v[kFieldGathers] += (unsigned long long)(e1 - e0);
+                    if (w == 0) c.v[kFieldCols] += (unsigned long long)(e1 - e0);
+                }
+            }
+        }
+    } else {
+        const int64_t hw = (int64_t)vb * (kLevelBlock / GM_WAVE) + wid;
+        const int32_t hidx = (int32_t)(hw / chunks), ch = (int32_t)(hw % chunks);
+        if (hidx < a.n_heavy) {
+            const int32_t v = a.heavy[hidx];
+            const int w = l & (WORDS - 1), grp = l >> LW;
+            const uint64_t f = fr[gbase + ((size_t)v << LW) + w];
+            const int32_t e1 = a.row_ptr[v + 1];
+            const int32_t cb = a.row_ptr[v] + ch * (G * kHeavyBatch);
+            if (__ballot(f != 0ull) && cb < e1) {
+                int32_t u[kHeavyBatch];
+#pragma unroll
+                for (int i = 0; i < kHeavyBatch; ++i) {
+                    const int32_t e = cb + grp + G * i;
+                    u[i] = f && e < e1 ? a.col[e] : -1;
+                }
+#pragma unroll
+                for (int i = 0; i < kHeavyBatch; ++i)
+                    if (u[i] >= 0) {
+                        push(u[i], w, f);
+                        c.v[kFieldGathers] += 1;
+                    }
+                if (l == 0) c.v[kFieldCols] += (unsigned long long)min(G * kHeavyBatch, e1 - cb);
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < kStatFields; ++f) {
+        const unsigned long long t = wave_sum_u64(c.v[f]);
+        if (l == 0) red[wid][f] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kStatFields) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kLevelBlock / GM_WAVE; ++q) t += red[q][threadIdx.x];
+        if (t)
+            atomicAdd(&a.stats[(((size_t)level * a.stats_groups + g) * kSpread + (vb & (kSpread - 1))) *
+                                   kStatFields + threadIdx.x],
+                      t);
     }
 }
 
@@ -551,7 +687,10 @@ __global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int
     const int32_t thr = heavy_threshold(n, rp, forced);
     if (blockIdx.x == 0 && threadIdx.x == 0) info[2] = thr;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        if (rp[v + 1] - rp[v] > thr) heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
+        if (rp[v + 1] - rp[v] > thr) {
+            heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
+            atomicMax(&info[4], rp[v + 1] - rp[v]);
+        }
 }
 
 // Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
@@ -944,6 +1083,26 @@ hipError_t launch_msbfs_level(const MsbfsArgs &a, int level, bool commit_only, h
     case 2: launch_level_words<2>(verts, grid, s, a, level, co, light, per_group, xcd); break;
     case 4: launch_level_words<4>(verts, grid, s, a, level, co, light, per_group, xcd); break;
     case 8: launch_level_words<8>(verts, grid, s, a, level, co, light, per_group, xcd); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_msbfs_push(const MsbfsArgs &a, int level, hipStream_t s)
+{
+    const int64_t items = (int64_t)a.n * a.words;
+    const int light = (int)((items + kLevelBlock - 1) / kLevelBlock);
+    const int chunk = (GM_WAVE / std::max(1, a.words)) * kHeavyBatch;   // adjacency entries per heavy wave
+    const int chunks = std::max(1, (a.heavy_maxdeg + chunk - 1) / chunk);
+    const int64_t heavy_waves = (int64_t)a.n_heavy * chunks;
+    const int heavy = (int)((heavy_waves + kLevelBlock / GM_WAVE - 1) / (kLevelBlock / GM_WAVE));
+    const int per_group = light + heavy;
+    dim3 grid((unsigned)((int64_t)per_group * a.groups));
+    switch (a.words) {
+    case 1: hipLaunchKernelGGL(msbfs_push_kernel<1>, grid, dim3(kLevelBlock), 0, s, a, level, light, per_group, chunks); break;
+    case 2: hipLaunchKernelGGL(msbfs_push_kernel<2>, grid, dim3(kLevelBlock), 0, s, a, level, light, per_group, chunks); break;
+    case 4: hipLaunchKernelGGL(msbfs_push_kernel<4>, grid, dim3(kLevelBlock), 0, s, a, level, light, per_group, chunks); break;
+    case 8: hipLaunchKernelGGL(msbfs_push_kernel<8>, grid, dim3(kLevelBlock), 0, s, a, level, light, per_group, chunks); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -71,6 +71,27 @@ int hip_status(hipError_t e, const char *what);
 std::mutex &api_mutex();
 size_t env_size(const char *name, size_t dflt);
 
+// Launch settings of the all-source BFS (gumap_knn_build, gumap_stress) that
+// change only its speed; -1 leaves a setting to its default.  A setting
+// given in the environment (GUMAP_FUSED, GUMAP_FORCE_WORDS,
+// GUMAP_LEVEL_VERTS, GUMAP_FIRST_LEVEL, GUMAP_HEAVY_DEGREE,
+// GUMAP_HIST_LEVELS, GUMAP_PUSH_LEVELS) takes precedence.
+struct BuildKnobs {
+    int fused = -1;    // 1: one workgroup per group runs every level (small graphs); 0: per-level launches
+    int words = -1;    // 64-bit source words per vertex per group: 1, 2, 4, 8
+    int verts = -1;    // (vertex, word) items per thread of the level kernel: 1, 2, 4, 8
+    int first = -1;    // level 1: 1 fill + top-down scatter, 0 range scan in the level kernel
+    int heavy = -1;    // degree above which a vertex is searched by a whole wave; 0: the default rule
+    int hist = -1;     // hops kept as frontiers instead of bit-planes (0: planes only)
+    int push = -1;     // levels that may run top-down (0: bottom-up only)
+};
+// The value of knob `name`: the environment's if set, else kb_value if >= 0, else dflt.
+size_t knob(const char *name, int kb_value, size_t dflt);
+int knn_build_tuned(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n_sources, int32_t *ids,
+                    uint8_t *hops, uint8_t *hop_matrix, hipStream_t s, const BuildKnobs *kb);
+// The settings the autotuner recorded for calls of this shape, if any.
+bool tuned_knobs(int32_t n, int64_t nnz, int64_t rows, int32_t k, bool hop_matrix, BuildKnobs *out);
+
 int scratch_get(int slot, size_t bytes, void **out);
 int host_scratch_get(size_t bytes, void **out);
 

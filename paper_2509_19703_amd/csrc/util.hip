@@ -75,7 +75,8 @@ __global__ void source_slots_k(int32_t n, const int32_t *first, const int32_t *p
 
 // Few listed sources on a small graph (at most kRankMax rows, kRankMaxN vertices).  First a pass over the
 // vertices: not a source yet (first = INT32_MAX, slot -1, count 0), and the
-// heavy-vertex list of the level kernel (info[1] entries, threshold info[2]).
+// heavy-vertex list of the level kernel (info[1] entries, threshold info[2],
+// largest degree among them info[4]).
 constexpr int kRankThreads = 1024;
 constexpr int kRankMax = 4096;
 
@@ -89,7 +90,10 @@ __global__ void source_vertex_prep_k(int32_t n, const int32_t *__restrict__ rp, 
         first[v] = INT32_MAX;
         slot_of[v] = -1;
         if (count) count[v] = 0;
-        if (rp[v + 1] - rp[v] > thr) heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
+        if (rp[v + 1] - rp[v] > thr) {
+            heavy[atomicAdd(&info[1], 1)] = (int32_t)v;
+            atomicMax(&info[4], rp[v + 1] - rp[v]);
+        }
     }
 }
 

@@ -31,6 +31,8 @@ def test_struct_layouts_match_header(gumap):
     assert ctypes.sizeof(gumap.gumap_layout_params) == 72
     assert gumap.gumap_layout_params.parts.offset == 64
     assert ctypes.sizeof(gumap.gumap_spectral_params) == 24
+    assert ctypes.sizeof(gumap.gumap_build_tuning) == 40
+    assert gumap.gumap_build_tuning.best_ms.offset == 32
 
 
 def test_host_side_argument_errors(gumap):
@@ -128,3 +130,50 @@ def test_python_names_mirror_c_entry_points(gumap):
                  "gumap_fuzzy_union", "gumap_edge_shuffle", "gumap_grad_sample", "gumap_spectral_layout",
                  "gumap_effective_resistance", "gumap_sparsify_select"):
         assert callable(getattr(gumap, name))
+
+
+def test_autotune_cache_round_trip_and_buckets(gumap, tmp_path):
+    """The tuning cache is JSON that the library reads back; picks are found
+    by the shape bucket of a call (floor(log2) of n, mean degree, sources
+    and k, hop rows or not), and a malformed or foreign file is refused
+    without touching the recorded picks.  Host only."""
+    import json
+    gumap.gumap_autotune_clear()
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 15, True) is None
+    entry = {"n_log2": 16, "deg_log2": 3, "rows_log2": 12, "k_log2": 3, "hop_matrix": 1, "fused": 0, "words": 4,
+             "level_verts": 2, "first_level": 1, "heavy_degree": 128, "hist_levels": 15, "push_levels": 0,
+             "candidates": 14, "best_ms": 0.9, "default_ms": 1.0}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "gumap-build-tuning", "version": 1, "entries": [entry]}))
+    assert gumap.gumap_autotune_cache_load(str(path)) == gumap.OK
+    # n in [2^16, 2^17), nnz / n in [8, 16), sources in [2^12, 2^13), k in [8, 16), hop rows
+    got = gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 15, True)
+    assert got is not None and got["words"] == 4 and got["level_verts"] == 2 and got["heavy_degree"] == 128
+    assert gumap.gumap_build_tuning_lookup(131071, 131071 * 15, 8191, 8, True)["words"] == 4
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 15, False) is None
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 8192, 15, True) is None
+    assert gumap.gumap_build_tuning_lookup(100000, 1600000, 4096, 15, True) is None
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 16, True) is None
+    # written back by the library, read again: the same entry
+    out = tmp_path / "again.json"
+    assert gumap.gumap_autotune_cache_save(str(out)) == gumap.OK
+    back = json.loads(out.read_text())
+    assert back["format"] == "gumap-build-tuning" and len(back["entries"]) == 1
+    assert {k2: back["entries"][0][k2] for k2 in entry if k2 not in ("best_ms", "default_ms")} == \
+        {k2: v for k2, v in entry.items() if k2 not in ("best_ms", "default_ms")}
+    # refused: not a cache, a setting out of range, a missing field, a missing file
+    bad = tmp_path / "bad.json"
+    for text in ('{"entries": []}',
+                 json.dumps({"format": "gumap-build-tuning", "entries": [dict(entry, words=3)]}),
+                 json.dumps({"format": "gumap-build-tuning", "entries": [{k2: v for k2, v in entry.items()
+                                                                           if k2 != "push_levels"}]})):
+        bad.write_text(text)
+        with pytest.raises(gumap.GumapError):
+            gumap.gumap_autotune_cache_load(str(bad))
+    with pytest.raises(gumap.GumapError):
+        gumap.gumap_autotune_cache_load(str(tmp_path / "missing.json"))
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 15, True)["words"] == 4
+    with pytest.raises(gumap.GumapError):
+        gumap.gumap_build_tuning_lookup(-1, 0, 0, 15, True)
+    gumap.gumap_autotune_clear()
+    assert gumap.gumap_build_tuning_lookup(100000, 800000, 4096, 15, True) is None

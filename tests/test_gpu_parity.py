@@ -136,6 +136,32 @@ def test_frontier_history_depth_invariance(gumap, hist, monkeypatch):
     assert abs(gs - os_) <= 1e-9 * max(1.0, abs(os_))
 
 
+@pytest.mark.parametrize("push_levels,ratio,hist,first", [
+    ("0", "4", "15", "1"), ("0", "4", "0", "0"), ("2", "4", "15", "0"),
+    ("2", "0", "15", "1"), ("3", "0", "15", "1"), ("2", "0", "0", "1"),
+    ("3", "4", "15", "1"), ("2", "4", "0", "1")])
+def test_direction_invariance(gumap, push_levels, ratio, hist, first, monkeypatch):
+    """The hop rows are the oracle's whether levels 2..3 run top-down (every
+    group forced with ratio 0, or picked by the frontier edge count) or
+    bottom-up, in history and plane mode, with level 1 as a scatter or a
+    range scan (which turns the top-down levels off): hub vertices pushed
+    in chunks and gathered by whole waves (star, BA), deep graphs, repeated
+    sources, truncated searches and every bitset width."""
+    monkeypatch.setenv("GUMAP_FUSED", "0")
+    monkeypatch.setenv("GUMAP_FIRST_LEVEL", first)
+    monkeypatch.setenv("GUMAP_PUSH_LEVELS", push_levels)
+    monkeypatch.setenv("GUMAP_PUSH_RATIO", ratio)
+    monkeypatch.setenv("GUMAP_HIST_LEVELS", hist)
+    print("push levels %s ratio %s history %s first %s" % (push_levels, ratio, hist, first), flush=True)
+    for g, words in ((G.ba(3001, 3, 71), 8), (G.star(1500), 4), (G.grid_2d(23, 31), 2), (G.rgg(2500, 7, 72), 1),
+                     (G.sbm(2000, 10, 73), 8)):
+        monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+        _check_build(gumap, g, 15, hop_matrix=True)
+        src = np.concatenate([G.sample_sources(g.n, 300, 74), [0, 0, 7]]).astype(np.int32)
+        _check_build(gumap, g, 2, sources=src, hop_matrix=False)
+        _check_build(gumap, g, 9, sources=src, hop_matrix=True)
+
+
 def test_sources_with_repeats_and_order(gumap):
     g = G.sbm(2500, 10, 41)
     src = np.concatenate([G.sample_sources(g.n, 300, 42), [5, 5, 17, 2499, 0, 17]]).astype(np.int32)
