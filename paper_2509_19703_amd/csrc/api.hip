@@ -301,13 +301,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     if ((st = scratch_get(kSlotSlotRow, (size_t)n * sizeof(int64_t), (void **)&slot_row))) return st;
     if ((st = scratch_get(kSlotInfo, 256, (void **)&info))) return st;
     if ((st = scratch_get(kSlotHeavy, (size_t)(n + 1) * sizeof(int32_t), (void **)&heavy))) return st;
-    hipError_t e = hipMemsetAsync(info, 0, 8 * sizeof(int32_t), s);
-    if (e != hipSuccess) return hip_status(e, "source setup");
+    hipError_t e = hipSuccess;
     if (all_sources) {
-        e = iota_i32(usrc, n, s);
-        if (e == hipSuccess) e = iota_i32(slot_of, n, s);
-        if (e == hipSuccess) e = iota_i64(slot_row, n, 0, s);
+        e = all_sources_setup(n, usrc, slot_of, slot_row, info, s);
     } else {
+        e = hipMemsetAsync(info, 0, 8 * sizeof(int32_t), s);
+        if (e != hipSuccess) return hip_status(e, "source setup");
         int32_t *count = nullptr, *marks = nullptr, *pos = nullptr;
         void *scan_tmp = nullptr;
         if ((st = scratch_get(kSlotFirst, (size_t)n * sizeof(int32_t), (void **)&first_row))) return st;
@@ -325,12 +324,19 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of,
                                 mult, info, s);
     }
+    // small graphs: every level of a group in one workgroup with its state in
+    // LDS (one 64-source word per vertex), instead of one launch per level
+    const bool fused = knob("GUMAP_FUSED", kb->fused, 1) != 0 && env_size("GUMAP_FORCE_WORDS", 0) == 0 &&
+                       msbfs_fused_lds_bytes(n) <= 144 * 1024;
+    // with every vertex a source the one-workgroup form needs neither the
+    // heavy-vertex list nor the source count: no read-back before the search
+    const bool setup_known = all_sources && fused;
     // vertices of high degree get a whole wave per level
-    if (e == hipSuccess && (all_sources || !sources_ranked_small(rows, n)))
+    if (e == hipSuccess && !setup_known && (all_sources || !sources_ranked_small(rows, n)))
         e = launch_heavy_list(n, c.row_ptr, heavy_forced, heavy, info, s);
     if (e != hipSuccess) return hip_status(e, "source setup");
-    int32_t hinfo[8];
-    {
+    int32_t hinfo[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (!setup_known) {
         void *hv = nullptr;
         if ((st = host_scratch_get(256, &hv))) return st;
         e = hipMemcpyAsync(hv, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -349,10 +355,6 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e != hipSuccess) return hip_status(e, "source multiplicities");
     }
 
-    // small graphs: every level of a group in one workgroup with its state in
-    // LDS (one 64-source word per vertex), instead of one launch per level
-    const bool fused = knob("GUMAP_FUSED", kb->fused, 1) != 0 && env_size("GUMAP_FORCE_WORDS", 0) == 0 &&
-                       msbfs_fused_lds_bytes(n) <= 144 * 1024;
     const int words = fused ? 1 : choose_words(n_uniq, kb);
     const int W = 64 * words;
     const int32_t groups_total = (n_uniq + W - 1) / W;
@@ -456,14 +458,41 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         bool spec_valid = false;    // hop rows and selection already launched for the complete BFS
         int spec_hops_mark = -1;
         std::vector<int> depth_of(a.groups, 0);   // per group: last hop with vertices (per-level path)
+        bool rows_done = false;   // hop rows and their counts written by the search itself
         if (fused) {
             int32_t *gout = nullptr;
             void *hg = nullptr;
             if ((st = scratch_get(kSlotGroupOut, (size_t)a.groups * 2 * sizeof(int32_t), (void **)&gout))) return st;
             if ((st = host_scratch_get((size_t)a.groups * 2 * sizeof(int32_t) + 256, &hg))) return st;
-            e = hipMemsetAsync(a.planes, 0, (size_t)planes_alloc * arr * 8, s);
+            // with hop rows wanted and the CSR small enough, the search keeps
+            // everything in LDS and writes the rows itself
+            rows_done = !so && n <= 2048 && msbfs_fused_rows_lds_bytes(n, g->nnz) <= 150 * 1024;
             const int mark = prof_begin("msbfs_level", s);
-            if (e == hipSuccess) e = launch_msbfs_fused(a, L_cap, full_hops, gout, s);
+            if (rows_done) {
+                // the selection follows at once: the levels found are read
+                // back afterwards, only for the hop-range check
+                e = launch_msbfs_fused_rows(a, L_cap, full_hops, g->nnz, hop_out,
+                                            hop_rows_of, n, lvl_cnt, gout, s);
+                prof_end(mark, s, 0.0);
+                if (e == hipSuccess)
+                    GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
+                            launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
+                                                      slot_row + a.slot0, lvl_cnt, 1, ids, hops, s));
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(hg, gout, (size_t)a.groups * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_status(e, "bfs (fused) / selection");
+                const int32_t *hgo = (const int32_t *)hg;
+                for (int32_t q = 0; q < a.groups; ++q) range_error |= hgo[2 * q + 1] != 0;
+                if (range_error)
+                    return set_error(GUMAP_ERANGE, "a finite hop exceeds 254; it does not fit the uint8 hop matrix");
+                // the CSR read once per group and the hop rows written
+                prof_set_bytes(mark, (double)a.groups * (4.0 * (n + 1) + 4.0 * g->nnz) + (double)a.n_slots * n);
+                continue;
+            } else {
+                e = hipMemsetAsync(a.planes, 0, (size_t)planes_alloc * arr * 8, s);
+                if (e == hipSuccess) e = launch_msbfs_fused(a, L_cap, full_hops, gout, s);
+            }
             prof_end(mark, s, 0.0);
             if (e == hipSuccess) e = hipMemcpyAsync(hg, gout, (size_t)a.groups * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -104,6 +104,15 @@ hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, 
 // vertices, group_out[2g + 1] = hop-range flag.
 size_t msbfs_fused_lds_bytes(int32_t n);
 hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t *group_out, hipStream_t s);
+// The same search with the CSR and a 64-source hop tile in LDS
+// (msbfs_fused_rows_lds_bytes(n, nnz) bytes): writes each group's hop rows
+// to hop_out + hop_row[slot] * row_stride and the per-slot counts of hops
+// 1..16 to part[slot * 16 + h - 1] (the layout launch_knn_select_counted
+// reads with chunks = 1) instead of bit-planes; group_out as above.
+size_t msbfs_fused_rows_lds_bytes(int32_t n, int32_t nnz);
+hipError_t launch_msbfs_fused_rows(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t nnz, uint8_t *hop_out,
+                                   const int64_t *hop_row, int64_t row_stride, unsigned int *part,
+                                   int32_t *group_out, hipStream_t s);
 // One BFS level: commit the previous level's frontier, then find level `level`.
 // commit_only: only commit (used after the last level the caller wants).
 // Level 1 (commit of the sources, hop-1 frontier) as a fill of visited and

@@ -643,6 +643,131 @@ msbfs_fused_kernel(MsbfsArgs a, int L_cap, int full_hops, int32_t *group_out)
     }
 }
 
+// Small graphs, hop rows wanted (no stress): as msbfs_fused_kernel, with
+// the whole search in LDS -- the CSR, the frontier and visited words, and a
+// 64 x n tile of hop bytes in which each commit records, for every source
+// bit of the committed word, the hop at which that source reached the
+// vertex (255 stays for unreached) and counts hops 1..16 per source.  The
+// block then writes its 64 hop rows (to row hop_row[slot] of hop_out, n
+// bytes each) and the counts (part[slot * 16 + h - 1]) itself, so no
+// bit-planes, transpose or plane clears are needed.  One barrier per level.
+constexpr int kRowsVerts = 2;   // vertices per thread of msbfs_fused_rows_kernel (n <= 2 * kFusedBlock)
+constexpr int kRowsNbrs = 8;    // neighbour ids of a vertex held in registers
+
+__global__ void __launch_bounds__(kFusedBlock)
+msbfs_fused_rows_kernel(MsbfsArgs a, int L_cap, int full_hops, int32_t nnz, uint8_t *__restrict__ hop_out,
+                        const int64_t *__restrict__ hop_row, int64_t row_stride, unsigned int *__restrict__ part,
+                        int32_t *group_out)
+{
+    extern __shared__ uint64_t fsm[];
+    const int32_t n = a.n, g = blockIdx.x;
+    uint64_t *front0 = fsm, *front1 = fsm + n;
+    unsigned int *cnt = (unsigned int *)(fsm + 3 * (size_t)n);            // [64][16]
+    int32_t *rp = (int32_t *)(cnt + 64 * kCountLevels);                   // [n + 1]
+    int32_t *col = rp + (n + 1);                                          // [nnz]
+    const size_t tile_off = ((3 * (size_t)n * 8 + 64 * kCountLevels * 4 + ((size_t)n + 1 + nnz) * 4) + 15) & ~(size_t)15;
+    uint8_t *tile = (uint8_t *)fsm + tile_off;                            // [64][n], 16-byte aligned
+    __shared__ int found[3];
+    const uint64_t valid = word_valid_mask(a.n_slots, g * 64);
+    for (int32_t i = threadIdx.x; i <= n; i += kFusedBlock) rp[i] = a.row_ptr[i];
+    for (int32_t i = threadIdx.x; i < nnz; i += kFusedBlock) col[i] = a.col[i];
+    for (int32_t i = threadIdx.x; i < 64 * kCountLevels; i += kFusedBlock) cnt[i] = 0u;
+    {
+        uint32_t *t4 = (uint32_t *)tile;
+        const int32_t words = 16 * n;   // 64 * n bytes
+        for (int32_t i = threadIdx.x; i < words; i += kFusedBlock) t4[i] = 0xFFFFFFFFu;
+    }
+    if (threadIdx.x < 3) found[threadIdx.x] = 0;
+    __syncthreads();
+    // a thread's own vertices: their frontier and visited words (only this
+    // thread writes them) and their first kRowsNbrs neighbours in registers
+    uint64_t fw[kRowsVerts], vw[kRowsVerts];
+    int32_t e0[kRowsVerts], e1[kRowsVerts], nb[kRowsVerts][kRowsNbrs];
+#pragma unroll
+    for (int j = 0; j < kRowsVerts; ++j) {
+        const int32_t v = threadIdx.x + j * kFusedBlock;
+        const bool in = v < n;
+        const int32_t sl = in ? a.slot_of[v] : -1;
+        fw[j] = (in && sl >= a.slot0 + g * 64 && sl < a.slot0 + g * 64 + 64) ? 1ull << (sl - a.slot0 - g * 64) : 0ull;
+        vw[j] = 0ull;
+        e0[j] = in ? rp[v] : 0;
+        e1[j] = in ? rp[v + 1] : 0;
+#pragma unroll
+        for (int i = 0; i < kRowsNbrs; ++i) nb[j][i] = e0[j] + i < e1[j] ? col[e0[j] + i] : -1;
+        if (in) front1[v] = fw[j];
+    }
+    __syncthreads();
+    int last = 0, range = 0;
+    for (int L = 1;; ++L) {
+        const uint64_t *cur = (L & 1) ? front1 : front0;
+        uint64_t *nxt = (L & 1) ? front0 : front1;
+        const bool search = L <= L_cap;
+        const int hop = L - 1;
+        // found[L % 3] is written in this level; found[(L + 1) % 3] was last
+        // read two levels ago (before the previous barrier): clear it for the next
+        if (threadIdx.x == 0) found[(L + 1) % 3] = 0;
+#pragma unroll
+        for (int j = 0; j < kRowsVerts; ++j) {
+            const int32_t v = threadIdx.x + j * kFusedBlock;
+            const uint64_t f = fw[j];
+            if (f) {
+                vw[j] |= f;
+                const uint8_t hb = (uint8_t)min(hop, 255);
+                for (uint64_t m = f; m; m &= m - 1) {
+                    const int sbit = __ffsll((unsigned long long)m) - 1;
+                    tile[(size_t)sbit * n + v] = hb;
+                    if (hop >= 1 && hop <= kCountLevels) atomicAdd(&cnt[sbit * kCountLevels + hop - 1], 1u);
+                }
+            }
+            if (!search || v >= n) continue;
+            const uint64_t unv = ~vw[j] & valid;
+            uint64_t acc = 0;
+            if (unv) {
+#pragma unroll
+                for (int i = 0; i < kRowsNbrs; ++i)
+                    if (nb[j][i] >= 0) acc |= cur[nb[j][i]];
+                for (int32_t e = e0[j] + kRowsNbrs; e < e1[j] && (acc & unv) != unv; ++e) acc |= cur[col[e]];
+            }
+            const uint64_t nw = acc & unv;
+            nxt[v] = nw;
+            fw[j] = nw;
+            if (nw) found[L % 3] = 1;
+        }
+        __syncthreads();
+        const bool any = found[L % 3] != 0;
+        if (!search) break;                  // the commit-only step after the hop cap
+        if (!any) break;                     // level L found nothing: hop L-1 was the last
+        last = L;
+        if (full_hops && L == 255) {
+            range = 1;
+            break;
+        }
+    }
+    __syncthreads();
+    // the group's rows: 16-byte pieces when rows are 16-byte aligned
+    const int32_t in_group = min(64, a.n_slots - g * 64);
+    const bool a16 = (n & 15) == 0 && (row_stride & 15) == 0 && (((uintptr_t)hop_out) & 15) == 0;
+    if (a16) {
+        const int32_t per_row = n / 16;
+        for (int32_t i = threadIdx.x; i < in_group * per_row; i += kFusedBlock) {
+            const int32_t sb = i / per_row, c = i % per_row;
+            const uint4 q = *(const uint4 *)(tile + (size_t)sb * n + 16 * c);
+            *(uint4 *)(hop_out + hop_row[g * 64 + sb] * row_stride + 16 * c) = q;
+        }
+    } else {
+        for (int32_t i = threadIdx.x; i < in_group * n; i += kFusedBlock) {
+            const int32_t sb = i / n, v = i % n;
+            hop_out[hop_row[g * 64 + sb] * row_stride + v] = tile[(size_t)sb * n + v];
+        }
+    }
+    for (int32_t i = threadIdx.x; i < in_group * kCountLevels; i += kFusedBlock)
+        part[(size_t)(g * 64) * kCountLevels + i] = cnt[i];
+    if (threadIdx.x == 0) {
+        group_out[2 * g] = last;
+        group_out[2 * g + 1] = range;
+    }
+}
+
 // Degree above which a vertex is searched by a whole wave: hubs well above
 // the mean degree (a lone thread would walk their rows serially while the
 // rest of its wave waits); dense graphs with an even degree keep one thread
@@ -1123,6 +1248,34 @@ hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int
     }
     hipLaunchKernelGGL(msbfs_fused_kernel, dim3(a.groups), dim3(kFusedBlock), lds, s, a, L_cap, full_hops ? 1 : 0,
                        group_out);
+    return hipGetLastError();
+}
+
+size_t msbfs_fused_rows_lds_bytes(int32_t n, int32_t nnz)
+{
+    return 3 * (size_t)n * sizeof(uint64_t) + 64 * kCountLevels * sizeof(unsigned int) +
+           ((size_t)n + 1 + (size_t)nnz) * sizeof(int32_t) + 64 * (size_t)n + 16;
+}
+
+hipError_t launch_msbfs_fused_rows(const MsbfsArgs &a, int L_cap, bool full_hops, int32_t nnz, uint8_t *hop_out,
+                                   const int64_t *hop_row, int64_t row_stride, unsigned int *part,
+                                   int32_t *group_out, hipStream_t s)
+{
+    if (a.words != 1 || a.groups <= 0 || a.n > kRowsVerts * kFusedBlock) return hipErrorInvalidValue;
+    const size_t lds = msbfs_fused_rows_lds_bytes(a.n, nnz);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static size_t lds_set[64] = {};
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (lds > 48 * 1024 && lds > lds_set[dev]) {
+        e = hipFuncSetAttribute((const void *)msbfs_fused_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set[dev] = lds;
+    }
+    hipLaunchKernelGGL(msbfs_fused_rows_kernel, dim3(a.groups), dim3(kFusedBlock), lds, s, a, L_cap,
+                       full_hops ? 1 : 0, nnz, hop_out, hop_row, row_stride, part, group_out);
     return hipGetLastError();
 }
 

@@ -9,6 +9,10 @@ namespace gm {
 hipError_t fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 hipError_t iota_i32(int32_t *p, int64_t count, hipStream_t s);
 hipError_t iota_i64(int64_t *p, int64_t count, int64_t start, hipStream_t s);
+// Every vertex a source: usrc, slot_of and slot_row the identity on [0, n),
+// info[0..8) cleared, in one launch.
+hipError_t all_sources_setup(int32_t n, int32_t *usrc, int32_t *slot_of, int64_t *slot_row, int32_t *info,
+                             hipStream_t s);
 // slot_of[usrc[i]] = i
 hipError_t scatter_slots(const int32_t *usrc, int32_t count, int32_t *slot_of, hipStream_t s);
 // Listed sources src[rows] -> sorted unique sources on the device:

@@ -27,6 +27,17 @@ int blocks_for(int64_t items, int threads = 256, int cap = 65536)
 __global__ void fill_i32_k(int32_t *p, int64_t count, int32_t v) { GRID_STRIDE(i, count) p[i] = v; }
 __global__ void iota_i32_k(int32_t *p, int64_t count) { GRID_STRIDE(i, count) p[i] = (int32_t)i; }
 __global__ void iota_i64_k(int64_t *p, int64_t count, int64_t start) { GRID_STRIDE(i, count) p[i] = start + i; }
+// Every vertex a source: slot = vertex = row, and the eight info words cleared.
+__global__ void all_sources_setup_k(int32_t n, int32_t *usrc, int32_t *slot_of, int64_t *slot_row, int32_t *info)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 8) info[threadIdx.x] = 0;
+    GRID_STRIDE(i, (int64_t)n)
+    {
+        usrc[i] = (int32_t)i;
+        slot_of[i] = (int32_t)i;
+        slot_row[i] = i;
+    }
+}
 __global__ void scatter_slots_k(const int32_t *usrc, int32_t count, int32_t *slot_of)
 {
     GRID_STRIDE(i, count) slot_of[usrc[i]] = (int32_t)i;
@@ -329,6 +340,14 @@ hipError_t iota_i32(int32_t *p, int64_t count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(iota_i32_k, dim3(blocks_for(count)), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t all_sources_setup(int32_t n, int32_t *usrc, int32_t *slot_of, int64_t *slot_row, int32_t *info,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(all_sources_setup_k, dim3(blocks_for(n > 0 ? n : 1)), dim3(256), 0, s, n, usrc, slot_of,
+                       slot_row, info);
     return hipGetLastError();
 }
 
