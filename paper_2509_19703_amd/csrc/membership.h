@@ -12,7 +12,8 @@
 // levels keep the counts implicit and bisect in x instead.  Then
 // sigma = -1/ln x and w_j = x^(h_j - rho).  Rows without a root take the
 // limits: K = 0 -> all zero; c_0 >= log2 k -> sigma = 0, weights 1 at rho
-// and 0 beyond; K <= log2 k -> sigma = +inf, weights 1.
+// and 0 beyond; K <= log2 k -> sigma = +inf, weights 1.  The weights are
+// x^(h_j - rho) by repeated products in double, no exponentials.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,16 +75,17 @@ __device__ __forceinline__ void membership_row(HopAt hop_at, int k, float *w, fl
     } else {
         double x = 1.0;
         if (!wide) {
-            double cnt[kMembLevels];
-#pragma unroll
-            for (int d = 0; d < kMembLevels; ++d)
-                cnt[d] = (double)(((d < 8 ? lo8 : hi8) >> (8 * (d & 7))) & 0xFF);
+            // P and P' over the levels the row has (d <= dmax, often 2 or 3),
+            // the counts read from their 8-bit fields
+            const int dmax = hop_at(K - 1) - rho;
             for (int it = 0; it < 1000; ++it) {
-                double p = cnt[kMembLevels - 1], dp = 0.0;
-#pragma unroll
-                for (int d = kMembLevels - 2; d >= 0; --d) {
-                    dp = fma(dp, x, p);
-                    p = fma(p, x, cnt[d]);
+                double p = 0.0, dp = 0.0, pw = 1.0, pwm1 = 0.0;   // x^d, x^(d - 1)
+                for (int d = 0; d <= dmax; ++d) {
+                    const double c = (double)(((d < 8 ? lo8 : hi8) >> (8 * (d & 7))) & 0xFF);
+                    p = fma(c, pw, p);
+                    dp = fma(c * (double)d, pwm1, dp);
+                    pwm1 = pw;
+                    pw *= x;
                 }
                 const double xn = x - (p - T) / dp;
                 if (!(xn < x)) break;
@@ -99,9 +101,19 @@ __device__ __forceinline__ void membership_row(HopAt hop_at, int k, float *w, fl
             }
             x = hi;
         }
-        const double lx = log(x);
-        sigma = (float)(-1.0 / lx);
-        for (int j = 0; j < K; ++j) w[j] = (float)exp((double)(hop_at(j) - rho) * lx);
+        sigma = (float)(-1.0 / log(x));
+        // w_j = x^(h_j - rho); the hops are sorted, so one running power
+        // serves the row (at most 254 products, relative error below 1e-13)
+        double pw = 1.0;
+        int cur = 0;
+        for (int j = 0; j < K; ++j) {
+            const int d = hop_at(j) - rho;
+            while (cur < d) {
+                pw *= x;
+                ++cur;
+            }
+            w[j] = (float)pw;
+        }
     }
     for (int j = K; j < k; ++j) w[j] = 0.0f;
     if (rho_out) *rho_out = (float)rho;

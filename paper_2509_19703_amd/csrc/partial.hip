@@ -378,6 +378,34 @@ partial_jobs_kernel(const DevJob *__restrict__ jobs, const JobChunk *__restrict_
 
 __global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
 
+// Rows of k <= kMembStageK: a block of kMembRows threads, one row each,
+// with its rows' hop bytes and weights staged in LDS so that the global
+// reads and writes are contiguous runs instead of k-strided ones.
+constexpr int kMembRows = 256;
+constexpr int kMembStageK = 32;
+
+__global__ void __launch_bounds__(kMembRows)
+membership_staged_kernel(int32_t rows, int32_t k, const uint8_t *__restrict__ hops, float *__restrict__ weights,
+                         float *__restrict__ rho, float *__restrict__ sigma)
+{
+    __shared__ uint8_t hs[kMembRows * kMembStageK];
+    __shared__ float ws[kMembRows * kMembStageK];
+    const int64_t r0 = (int64_t)blockIdx.x * kMembRows;
+    const int nr = (int)min((int64_t)kMembRows, (int64_t)rows - r0);
+    const int cells = nr * k;
+    const uint8_t *src = hops + r0 * k;
+    for (int i = threadIdx.x; i < cells; i += kMembRows) hs[i] = src[i];
+    __syncthreads();
+    if ((int)threadIdx.x < nr) {
+        const uint8_t *h = hs + threadIdx.x * k;
+        membership_row([&](int j) { return (int)h[j]; }, k, ws + threadIdx.x * k,
+                       rho ? rho + r0 + threadIdx.x : nullptr, sigma ? sigma + r0 + threadIdx.x : nullptr);
+    }
+    __syncthreads();
+    float *dst = weights + r0 * k;
+    for (int i = threadIdx.x; i < cells; i += kMembRows) dst[i] = ws[i];
+}
+
 __global__ void membership_kernel(int32_t rows, int32_t k, const uint8_t *__restrict__ hops,
                                   float *__restrict__ weights, float *__restrict__ rho,
                                   float *__restrict__ sigma)
@@ -508,6 +536,12 @@ hipError_t launch_membership(int32_t rows, int32_t k, const uint8_t *hops, float
                              float *rho, float *sigma, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
+    if (k <= kMembStageK) {
+        const int64_t blocks = ((int64_t)rows + kMembRows - 1) / kMembRows;
+        hipLaunchKernelGGL(membership_staged_kernel, dim3((unsigned)blocks), dim3(kMembRows), 0, s, rows, k, hops,
+                           weights, rho, sigma);
+        return hipGetLastError();
+    }
     int blocks = (rows + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(membership_kernel, dim3(blocks), dim3(256), 0, s, rows, k, hops, weights, rho, sigma);
