@@ -1035,11 +1035,22 @@ def run_serve(args):
 
 def _counter_avg_kib(run_dir: str, kernel_substr: str):
     """Average counter value (KiB) per dispatch of the kernels whose name contains kernel_substr."""
+    import csv
     import glob
     import sqlite3
+    csvs = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if csvs:
+        # one or more rows per dispatch: summed per dispatch, averaged over dispatches
+        per = {}
+        with open(csvs[0]) as f:
+            for r in csv.DictReader(f):
+                if kernel_substr in r["Kernel_Name"]:
+                    per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        vals = list(per.values())
+        return (sum(vals) / len(vals) if vals else None), len(vals)
     dbs = glob.glob(os.path.join(run_dir, "**", "*.db"), recursive=True)
     if not dbs:
-        raise FileNotFoundError("no rocprofv3 database under %s" % run_dir)
+        raise FileNotFoundError("no rocprofv3 output under %s" % run_dir)
     con = sqlite3.connect(dbs[0])
     rows = con.execute("select kernel_name, value from counters_collection").fetchall()
     vals = [v for name, v in rows if kernel_substr in name]
