@@ -329,7 +329,8 @@ def _hbm_roofline(d, dom, traffic, breakdown=None):
         out.update({"extra_bytes_per_launch": extra, "achieved_with_extra": with_extra,
                     "frac_with_extra": with_extra / HBM_PEAK_GBS,
                     "extra_note": "bytes beyond the per-level count: the lazy commit of the previous level "
-                                  "(visited write-back and bit-plane read-modify-writes)"})
+                                  "(the visited word written back, plus bit-plane read-modify-writes for hops "
+                                  "above the frontier history)"})
     return out
 
 
