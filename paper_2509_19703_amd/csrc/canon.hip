@@ -4,14 +4,17 @@
 // undirected edge set; a canonical adjacency is what lets the partial BFS
 // merge sorted neighbour lists and stop early.
 //
-// Canonicalisation is five launches: rows of at most 32 entries are sorted
-// by one thread each (registers) and longer rows listed; rows of up to 1,024
-// entries are sorted by one wave each and longer ones by a 1,024-thread
-// workgroup (LDS, or an n-bit bitmap past 32,768 entries), both reading the
-// lists through a slot permutation that spreads the high-degree rows; a
-// single-pass scan with decoupled look-back writes the row pointers; a
-// fix-up moves rows only when a repeat or self-loop was dropped (rows are
-// sorted in place at their input offsets, with a staged copy for that case).
+// Canonicalisation is three launches: every row of at most 4,096 entries is
+// sorted by the workgroup that owns it (rows assigned with a stride so that
+// the long rows, which a preferential-attachment graph puts at its lowest
+// ids, land in different workgroups): a thread per row of at most 32 entries
+// (registers), a wave per row of at most 256, the whole workgroup in LDS
+// above that; longer rows are listed and sorted by a 1,024-thread workgroup
+// each (LDS, or an n-bit bitmap past 32,768 entries), reached through a slot
+// permutation that spreads them; then a single-pass scan with decoupled
+// look-back writes the row pointers and moves the rows that an earlier
+// dropped repeat or self-loop shifted (rows are sorted in place at their
+// input offsets, with a staged copy for that case).
 #include "device.h"
 #include "kernels.h"
 
@@ -20,7 +23,7 @@ namespace gm {
 namespace {
 
 constexpr int kSmallRow = 64;      // one wave, registers
-constexpr int kMidRow = 1024;      // one wave, registers
+constexpr int kMidRow = 256;       // one wave, registers (longer: the workgroup, LDS)
 constexpr int kBigRow = 32768;     // one workgroup, LDS
 constexpr int kCanonBlock = 256;   // 4 waves
 constexpr int kBigBlock = 1024;
@@ -213,39 +216,168 @@ __device__ __forceinline__ void thread_sort_row(int64_t v, int32_t a, int32_t d,
     cnt[v] = c;
 }
 
-// A thread per row: rows of at most kThreadRow entries are sorted here into
-// out and stg at the row's input offset, with their kept count in cnt;
-// longer rows are listed per block (kListRows slots per block and list):
-// up to kMidRow entries in list_mid, longer ones in list_big, with the
-// counts in n_mid / n_big.  Block 0 also clears
-// the look-back flags of canon_scan_kernel (launched after the sorts).
+// Rows of kMidRow + 1 .. kBlockSortMax entries are sorted by the whole
+// workgroup of canon_rows_kernel in LDS (bitonic over the next power of two
+// >= max(d, 256) entries), then written without repeats and without v.
+constexpr int kBlockSortMax = 4096;
+
+__device__ void block_sort_row(int32_t v, int32_t a, int32_t d, const int32_t *__restrict__ col, int32_t *sbuf,
+                               int32_t *part, int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                               int32_t *__restrict__ cnt)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    int P = nt;
+    while (P < d) P <<= 1;
+    for (int i = t; i < P; i += nt) sbuf[i] = i < d ? col[a + i] : GM_INF_ID;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < P; i += nt) {
+                const int o = i ^ j;
+                if (o > i) {
+                    const int x = sbuf[i], y = sbuf[o];
+                    const bool up = (i & kk) == 0;
+                    if ((x > y) == up) {
+                        sbuf[i] = y;
+                        sbuf[o] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // kept entries: per-thread counts of a contiguous range, a block scan, the writes
+    const int chunk = P / nt;
+    const int i0 = t * chunk;
+    int mine = 0;
+    for (int i = i0; i < i0 + chunk; ++i) {
+        const int x = sbuf[i];
+        mine += x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1]);
+    }
+    part[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const int y = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    int pos = part[t] - mine;
+    for (int i = i0; i < i0 + chunk; ++i) {
+        const int x = sbuf[i];
+        if (x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1])) {
+            out[a + pos] = x;
+            stg[a + pos] = x;
+            ++pos;
+        }
+    }
+    if (t == nt - 1) cnt[v] = part[t];
+    __syncthreads();
+}
+
+// The same row through an n-bit set in LDS when n <= 32 * kRowBitmapWords:
+// the entries other than v set their bits (repeats collapse), then each
+// thread counts the set bits of a contiguous range of words, a block scan
+// gives its first output position, and it writes its bits' ids in order.
+// The cost depends on n, not on d.
+constexpr int kRowBitmapWords = 8192;   // 32 KB: graphs of up to 262,144 vertices
+
+__device__ void block_bitmap_row(int32_t v, int32_t a, int32_t d, int32_t n, const int32_t *__restrict__ col,
+                                 uint32_t *bm, int32_t *part, int32_t *__restrict__ out, int32_t *__restrict__ stg,
+                                 int32_t *__restrict__ cnt)
+{
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int32_t words = (n + 31) / 32;
+    for (int32_t i = t; i < words; i += nt) bm[i] = 0u;
+    __syncthreads();
+    for (int32_t e = t; e < d; e += nt) {
+        const int32_t u = col[a + e];
+        if (u != v) atomicOr(&bm[u >> 5], 1u << (u & 31));
+    }
+    __syncthreads();
+    const int32_t wper = (words + nt - 1) / nt;
+    const int32_t w0 = min(words, t * wper), w1 = min(words, w0 + wper);
+    int mine = 0;
+    for (int32_t i = w0; i < w1; ++i) mine += __popc(bm[i]);
+    part[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const int y = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    int pos = part[t] - mine;
+    for (int32_t i = w0; i < w1; ++i) {
+        uint32_t bits = bm[i];
+        while (bits) {
+            const int32_t u = i * 32 + __ffs(bits) - 1;
+            bits &= bits - 1;
+            out[a + pos] = u;
+            stg[a + pos] = u;
+            ++pos;
+        }
+    }
+    if (t == nt - 1) cnt[v] = part[t];
+    __syncthreads();
+}
+
+// Every row of at most kBlockSortMax entries, in one launch.  Workgroup b
+// takes rows b, b + blocks, b + 2 blocks, ... (the long rows of a
+// preferential-attachment graph sit at the lowest ids; striding puts them in
+// different workgroups): a thread sorts each row of at most kThreadRow
+// entries in registers; rows up to kMidRow are sorted by a wave each and the
+// longer ones by the whole workgroup in LDS, once its short rows are done.
+// Rows past kBlockSortMax are listed (kListRows slots per workgroup, count
+// in counts[blocks + 1 + b]) for canon_big_kernel.  Workgroup 0 also clears
+// the look-back flags of canon_scan_kernel.
 __global__ void __launch_bounds__(kListRows)
-canon_sort_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+canon_rows_kernel(int32_t n, int32_t blocks, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                   int32_t *__restrict__ out, int32_t *__restrict__ stg, int32_t *__restrict__ cnt,
                   int32_t *__restrict__ lists, int32_t *__restrict__ counts, int64_t list_stride,
                   unsigned long long *__restrict__ flags, int32_t n_flags)
 {
-    __shared__ int32_t s_n[2];
-    const int t = threadIdx.x;
+    __shared__ int32_t s_n[2];                 // rows kept for this workgroup, rows listed for canon_big_kernel
+    __shared__ int32_t s_rows[kListRows];
+    __shared__ int32_t sbuf[kBlockSortMax];
+    __shared__ uint32_t bm[kRowBitmapWords];
+    __shared__ int32_t part[kListRows];
+    const int t = threadIdx.x, wid = t / GM_WAVE;
     if (blockIdx.x == 0)
         for (int32_t i = t; i < n_flags; i += blockDim.x) flags[i] = 0ull;
     if (t < 2) s_n[t] = 0;
     __syncthreads();
-    const int64_t v = (int64_t)blockIdx.x * kListRows + t;
-    const int64_t base = (int64_t)blockIdx.x * kListRows;
+    const int64_t v = (int64_t)blockIdx.x + (int64_t)t * blocks;
     if (v < n) {
         const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
         if (d <= 16) {
             thread_sort_row<16>(v, a, d, col, out, stg, cnt);
         } else if (d <= kThreadRow) {
             thread_sort_row<kThreadRow>(v, a, d, col, out, stg, cnt);
+        } else if (d <= kBlockSortMax) {
+            s_rows[atomicAdd(&s_n[0], 1)] = (int32_t)v;
         } else {
-            const int which = d <= kMidRow ? 0 : 1;
-            lists[which * list_stride + base + atomicAdd(&s_n[which], 1)] = (int32_t)v;
+            lists[list_stride + (int64_t)blockIdx.x * kListRows + atomicAdd(&s_n[1], 1)] = (int32_t)v;
         }
     }
     __syncthreads();
-    if (t < 2) counts[(int64_t)t * (list_stride / kListRows) + blockIdx.x] = s_n[t];
+    const int nr = s_n[0];
+    for (int i = wid; i < nr; i += kListRows / GM_WAVE) {
+        const int32_t rv = s_rows[i];
+        const int32_t a = row_ptr[rv], d = row_ptr[rv + 1] - a;
+        if (d <= kMidRow) canon_one_row(rv, a, d, col, out, stg, cnt);
+    }
+    for (int i = 0; i < nr; ++i) {
+        const int32_t rv = s_rows[i];
+        const int32_t a = row_ptr[rv], d = row_ptr[rv + 1] - a;
+        if (d <= kMidRow) continue;
+        if (n <= 32 * kRowBitmapWords) block_bitmap_row(rv, a, d, n, col, bm, part, out, stg, cnt);
+        else block_sort_row(rv, a, d, col, sbuf, part, out, stg, cnt);
+    }
+    if (t == 0) {
+        counts[blockIdx.x] = 0;
+        counts[(list_stride / kListRows) + blockIdx.x] = s_n[1];
+    }
 }
 
 // The listed rows are addressed by slots s in [0, S), S the power of two at
@@ -256,7 +388,6 @@ canon_sort_kernel(int32_t n, const int32_t *__restrict__ row_ptr, const int32_t 
 // slots spreads them over many waves instead of leaving a block's list to
 // one.
 constexpr uint64_t kSlotMul = 2654435761ull;
-constexpr int kMidSlots = 16;   // slots per wave (mid rows) and per workgroup (block rows)
 
 __device__ __forceinline__ bool list_slot(int64_t s, int64_t slots_pow2, int64_t slots,
                                           const int32_t *__restrict__ counts, int64_t &entry)
@@ -268,30 +399,7 @@ __device__ __forceinline__ bool list_slot(int64_t s, int64_t slots_pow2, int64_t
     return (f % kListRows) < counts[f / kListRows];
 }
 
-// Rows of kThreadRow + 1 .. kMidRow entries: wave w of the launch looks at
-// mid-list slots [kMidSlots w, kMidSlots (w + 1)) and sorts each row found
-// there with the whole wave (registers).
-__global__ void __launch_bounds__(kCanonBlock)
-canon_mid_kernel(int32_t blocks, int64_t slots_pow2, const int32_t *__restrict__ row_ptr,
-                 const int32_t *__restrict__ col, int32_t *__restrict__ out, int32_t *__restrict__ stg,
-                 int32_t *__restrict__ cnt, const int32_t *__restrict__ list_mid, const int32_t *__restrict__ n_mid)
-{
-    const int64_t slots = (int64_t)blocks * kListRows;
-    const int l = lane();
-    const int64_t w = (int64_t)blockIdx.x * (kCanonBlock / GM_WAVE) + threadIdx.x / GM_WAVE;
-    int64_t entry = 0;
-    const bool ok = l < kMidSlots && list_slot(w * kMidSlots + l, slots_pow2, slots, n_mid, entry);
-    unsigned long long fm = __ballot(ok);
-    while (fm) {
-        const int src = __ffsll((long long)fm) - 1;
-        fm &= fm - 1;
-        const int32_t v = list_mid[__shfl(entry, src, GM_WAVE)];
-        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
-        canon_one_row(v, a, d, col, out, stg, cnt);
-    }
-}
-
-// Rows longer than kMidRow, each sorted by a whole 1,024-thread workgroup:
+// Rows longer than kBlockSortMax, each sorted by a whole 1,024-thread workgroup:
 // up to kBigRow entries by a bitonic sort in LDS, longer ones by marking the
 // neighbours in an n-bit bitmap (this workgroup's own, in scratch) and
 // emitting the set bits in order.  Workgroup c looks at big-list slots
@@ -418,7 +526,7 @@ canon_big_kernel(int32_t n, int32_t blocks, int64_t slots_pow2, const int32_t *_
 // (a published inclusive prefix ends the walk), and the tile's inclusive
 // prefix is published; then it writes its output row pointers.  A flag is 0
 // (not ready), or (status << 62 | value) with status 1 = aggregate, 2 =
-// inclusive prefix; canon_sort_kernel cleared them for this call.  A wait on
+// inclusive prefix; canon_rows_kernel cleared them for this call.  A wait on
 // a flag is bounded: past kSpinLimit polls the tile writes
 // out_row_ptr[n] = -1 and stops (the host reports it).
 constexpr int kScanRows = 1024;
@@ -430,11 +538,14 @@ constexpr int kSpinLimit = 1 << 22;
 
 __global__ void __launch_bounds__(kScanThreads)
 canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restrict__ out_row_ptr,
-                  unsigned long long *flags)
+                  unsigned long long *flags, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ stg,
+                  int32_t *__restrict__ out_col)
 {
     __shared__ int32_t s_wave[kScanThreads / GM_WAVE];
     __shared__ int64_t s_excl;
     __shared__ int s_fail;
+    __shared__ int32_t s_long[kScanRows];   // rows of more than 64 kept entries to move
+    __shared__ int s_nlong;
     const int t = threadIdx.x, l = lane(), wid = t / GM_WAVE;
     const int64_t v0 = (int64_t)blockIdx.x * kScanRows;
     const int rows = (int)min((int64_t)kScanRows, (int64_t)n - v0);
@@ -505,7 +616,8 @@ canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restric
         if (t == 0) out_row_ptr[n] = -1;
         return;
     }
-    int off = (int)s_excl + before + inc - mine;
+    const int off0 = (int)s_excl + before + inc - mine;
+    int off = off0;
 #pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
         const int r = t * kScanPer + q;
@@ -513,22 +625,36 @@ canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restric
         off += c[q];
     }
     if (v0 + rows == n && t == kScanThreads - 1) out_row_ptr[n] = off;
-}
-
-// The sorted rows already sit in out_col at the input offsets; when every
-// entry was kept (out_row_ptr[n] == nnz) that is the output.  Otherwise each
-// row's kept entries move from the staged copy to the output offsets (a wave
-// per row).
-__global__ void __launch_bounds__(kCanonBlock)
-canon_fixup_kernel(int32_t n, int32_t nnz, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ stg,
-                   const int32_t *__restrict__ out_row_ptr, int32_t *__restrict__ out_col)
-{
-    if (out_row_ptr[n] == nnz) return;
-    const int waves = blockDim.x / GM_WAVE;
-    for (int64_t v = (int64_t)blockIdx.x * waves + threadIdx.x / GM_WAVE; v < n;
-         v += (int64_t)gridDim.x * waves) {
-        const int32_t a = row_ptr[v], o = out_row_ptr[v], c = out_row_ptr[v + 1] - o;
-        for (int32_t i = lane(); i < c; i += GM_WAVE) out_col[o + i] = stg[a + i];
+    // The sorted rows sit at their input offsets (kept entries first, also
+    // in the staged copy).  A row moves to its output offset when an entry
+    // was dropped before it: nothing moves in a tile that starts where its
+    // input starts and keeps every entry.
+    const int32_t in0 = row_ptr[v0], in1 = row_ptr[v0 + rows];
+    if ((int64_t)s_excl == (int64_t)in0 && (int64_t)agg == (int64_t)in1 - in0) return;
+    if (t == 0) s_nlong = 0;
+    __syncthreads();
+    off = off0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        const int r = t * kScanPer + q;
+        if (r < rows) {
+            const int32_t a = row_ptr[v0 + r];
+            if (off != a) {
+                if (c[q] <= GM_WAVE) {
+                    for (int i = 0; i < c[q]; ++i) out_col[off + i] = stg[a + i];
+                } else {
+                    s_long[atomicAdd(&s_nlong, 1)] = r;
+                }
+            }
+        }
+        off += c[q];
+    }
+    __syncthreads();
+    const int nl = s_nlong;
+    for (int i = wid; i < nl; i += kScanThreads / GM_WAVE) {
+        const int64_t v = v0 + s_long[i];
+        const int32_t a = row_ptr[v], o = out_row_ptr[v], cv = cnt[v];
+        for (int32_t e = l; e < cv; e += GM_WAVE) out_col[o + e] = stg[a + e];
     }
 }
 
@@ -709,16 +835,12 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
     unsigned long long *flags = (unsigned long long *)p;
     p += align256((size_t)(tiles + 1) * sizeof(unsigned long long));
     uint32_t *bitmaps = (uint32_t *)p;
-    hipLaunchKernelGGL(canon_sort_kernel, dim3((unsigned)blocks), dim3(kListRows), 0, s, n, row_ptr, col_idx, out_col,
-                       stg, cnt, lists, counts, list_stride, flags, tiles);
+    hipLaunchKernelGGL(canon_rows_kernel, dim3((unsigned)blocks), dim3(kListRows), 0, s, n, blocks, row_ptr, col_idx,
+                       out_col, stg, cnt, lists, counts, list_stride, flags, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int32_t *list_mid = lists, *list_big = lists + list_stride;
-    const int32_t *n_mid = counts, *n_big = counts + (blocks + 1);
-    const int64_t mid_blocks = (slots_pow2 / kMidSlots + kCanonBlock / GM_WAVE - 1) / (kCanonBlock / GM_WAVE);
-    hipLaunchKernelGGL(canon_mid_kernel, dim3((unsigned)mid_blocks), dim3(kCanonBlock), 0, s, blocks, slots_pow2,
-                       row_ptr, col_idx, out_col, stg, cnt, list_mid, n_mid);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int32_t *list_big = lists + list_stride;
+    const int32_t *n_big = counts + (blocks + 1);
     const size_t big_lds = (kBigRow + kBigBlock) * sizeof(int32_t);
     static bool lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
     int dev = 0;
@@ -734,10 +856,7 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                        col_idx, out_col, stg, cnt, list_big, n_big, bitmaps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(canon_scan_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, (const int32_t *)cnt,
-                       out_row_ptr, flags);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(canon_fixup_kernel, dim3(grid_for(n, kCanonBlock / GM_WAVE, 256)), dim3(kCanonBlock), 0, s, n,
-                       nnz, row_ptr, (const int32_t *)stg, (const int32_t *)out_row_ptr, out_col);
+                       out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col);
     return hipGetLastError();
 }
 
