@@ -4,14 +4,18 @@
 // undirected edge set; a canonical adjacency is what lets the partial BFS
 // merge sorted neighbour lists and stop early.
 //
-// Canonicalisation is three launches: every row of at most 4,096 entries is
-// sorted by the workgroup that owns it (rows assigned with a stride so that
-// the long rows, which a preferential-attachment graph puts at its lowest
-// ids, land in different workgroups): a thread per row of at most 32 entries
-// (registers), a wave per row of at most 256, the whole workgroup in LDS
-// above that; longer rows are listed and sorted by a 1,024-thread workgroup
-// each (LDS, or an n-bit bitmap past 32,768 entries), reached through a slot
-// permutation that spreads them; then a single-pass scan with decoupled
+// Canonicalisation is two launches, three on graphs of more than 262,144
+// vertices.  The row kernel sorts a thread per row of at most 32 entries,
+// workgroup b taking rows [256 b, 256 b + 256) (neighbouring threads read
+// neighbouring rows); longer rows are dealt with a stride (rows b,
+// b + blocks, ...), so that the long rows, which a preferential-attachment
+// graph puts at its lowest ids, land in different workgroups: a wave per row
+// of at most 256 entries (registers), the whole workgroup above that (an
+// n-bit set in LDS, whatever the row's length, when n <= 262,144; else a
+// bitonic sort in LDS up to 4,096 entries).  On larger graphs the rows past
+// 4,096 entries are listed and sorted by a 1,024-thread workgroup each (LDS,
+// or an n-bit bitmap past 32,768 entries), reached through a slot
+// permutation that spreads them.  Then a single-pass scan with decoupled
 // look-back writes the row pointers and moves the rows that an earlier
 // dropped repeat or self-loop shifted (rows are sorted in place at their
 // input offsets, with a staged copy for that case).
@@ -180,13 +184,13 @@ constexpr int kThreadRow = 32;
 constexpr int kListRows = 256;   // rows per block of canon_sort_kernel
 
 template <int N>
-__device__ __forceinline__ void thread_sort_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ col,
+__device__ __forceinline__ void thread_sort_row(int64_t v, int32_t a, int32_t d, const int32_t *__restrict__ src,
                                                 int32_t *__restrict__ out, int32_t *__restrict__ stg,
                                                 int32_t *__restrict__ cnt)
 {
-    int x[N];
+    int x[N];   // src: the row's first entry (in global memory or in LDS)
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = i < d ? col[a + i] : GM_INF_ID;
+    for (int i = 0; i < N; ++i) x[i] = i < d ? src[i] : GM_INF_ID;
 #pragma unroll
     for (int kk = 2; kk <= N; kk <<= 1) {
 #pragma unroll
@@ -214,6 +218,26 @@ __device__ __forceinline__ void thread_sort_row(int64_t v, int32_t a, int32_t d,
         c += keep;
     }
     cnt[v] = c;
+}
+
+// Exclusive prefix of `mine` over a workgroup of kListRows threads, and the
+// total, through per-wave sums in wsum[kListRows / 64].  The caller passes a
+// barrier before wsum is written again.
+__device__ __forceinline__ int row_block_scan(int mine, int32_t *wsum, int *total)
+{
+    const int l = lane(), wid = threadIdx.x / GM_WAVE;
+    const int inc = wave_incl_scan(mine);
+    if (l == GM_WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kListRows / GM_WAVE; ++w) {
+        const int x = wsum[w];
+        if (w < wid) before += x;
+        tot += x;
+    }
+    *total = tot;
+    return before + inc - mine;
 }
 
 // Rows of kMidRow + 1 .. kBlockSortMax entries are sorted by the whole
@@ -254,15 +278,8 @@ __device__ void block_sort_row(int32_t v, int32_t a, int32_t d, const int32_t *_
         const int x = sbuf[i];
         mine += x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1]);
     }
-    part[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < nt; o <<= 1) {
-        const int y = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += y;
-        __syncthreads();
-    }
-    int pos = part[t] - mine;
+    int total = 0;
+    int pos = row_block_scan(mine, part, &total);
     for (int i = i0; i < i0 + chunk; ++i) {
         const int x = sbuf[i];
         if (x != GM_INF_ID && x != v && (i == 0 || x != sbuf[i - 1])) {
@@ -271,15 +288,16 @@ __device__ void block_sort_row(int32_t v, int32_t a, int32_t d, const int32_t *_
             ++pos;
         }
     }
-    if (t == nt - 1) cnt[v] = part[t];
+    if (t == 0) cnt[v] = total;
     __syncthreads();
 }
 
-// The same row through an n-bit set in LDS when n <= 32 * kRowBitmapWords:
-// the entries other than v set their bits (repeats collapse), then each
-// thread counts the set bits of a contiguous range of words, a block scan
-// gives its first output position, and it writes its bits' ids in order.
-// The cost depends on n, not on d.
+// A row of any length above kMidRow through an n-bit set in LDS when
+// n <= 32 * kRowBitmapWords: the entries other than v set their bits
+// (repeats collapse), then each thread counts the set bits of a contiguous
+// range of words, a block scan gives its first output position, and it
+// writes its bits' ids in order.  The cost is n / 32 words plus d / 256
+// entries per thread.
 constexpr int kRowBitmapWords = 8192;   // 32 KB: graphs of up to 262,144 vertices
 
 __device__ void block_bitmap_row(int32_t v, int32_t a, int32_t d, int32_t n, const int32_t *__restrict__ col,
@@ -299,15 +317,8 @@ __device__ void block_bitmap_row(int32_t v, int32_t a, int32_t d, int32_t n, con
     const int32_t w0 = min(words, t * wper), w1 = min(words, w0 + wper);
     int mine = 0;
     for (int32_t i = w0; i < w1; ++i) mine += __popc(bm[i]);
-    part[t] = mine;
-    __syncthreads();
-    for (int o = 1; o < nt; o <<= 1) {
-        const int y = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += y;
-        __syncthreads();
-    }
-    int pos = part[t] - mine;
+    int total = 0;
+    int pos = row_block_scan(mine, part, &total);
     for (int32_t i = w0; i < w1; ++i) {
         uint32_t bits = bm[i];
         while (bits) {
@@ -318,65 +329,103 @@ __device__ void block_bitmap_row(int32_t v, int32_t a, int32_t d, int32_t n, con
             ++pos;
         }
     }
-    if (t == nt - 1) cnt[v] = part[t];
+    if (t == 0) cnt[v] = total;
     __syncthreads();
 }
 
-// Every row of at most kBlockSortMax entries, in one launch.  Workgroup b
-// takes rows b, b + blocks, b + 2 blocks, ... (the long rows of a
-// preferential-attachment graph sit at the lowest ids; striding puts them in
-// different workgroups): a thread sorts each row of at most kThreadRow
-// entries in registers; rows up to kMidRow are sorted by a wave each and the
-// longer ones by the whole workgroup in LDS, once its short rows are done.
-// Rows past kBlockSortMax are listed (kListRows slots per workgroup, count
-// in counts[blocks + 1 + b]) for canon_big_kernel.  Workgroup 0 also clears
-// the look-back flags of canon_scan_kernel.
+// The row kernel, 2 * blocks workgroups of kListRows threads.
+//   b < blocks (launched first) takes share b, the rows b, b + blocks,
+//     b + 2 blocks, ... (the long rows of a preferential-attachment graph sit
+//     at the lowest ids; striding puts them in different workgroups), and
+//     sorts those of more than kThreadRow entries: up to kMidRow a wave each
+//     in registers, longer ones the whole workgroup, through the n-bit set
+//     when n <= 32 * kRowBitmapWords (any length), else by the LDS bitonic
+//     sort up to kBlockSortMax; rows left over (n above that bound and more
+//     than kBlockSortMax entries) are listed (kListRows slots per workgroup,
+//     count in counts[blocks + 1 + b]) for canon_big_kernel.  Workgroup 0
+//     also clears the look-back flags of canon_scan_kernel.
+//   b >= blocks, c = b - blocks, sorts the rows of at most kThreadRow entries
+//     among [c * kListRows, (c + 1) * kListRows), a thread each in registers;
+//     when the range's entries fit in LDS they are first loaded there with
+//     contiguous reads.
+// The long rows thus run beside the short ones instead of after them.
+static_assert(kRowBitmapWords >= kBlockSortMax, "the LDS row buffer serves both workgroup sorts");
+
 __global__ void __launch_bounds__(kListRows)
 canon_rows_kernel(int32_t n, int32_t blocks, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                   int32_t *__restrict__ out, int32_t *__restrict__ stg, int32_t *__restrict__ cnt,
                   int32_t *__restrict__ lists, int32_t *__restrict__ counts, int64_t list_stride,
                   unsigned long long *__restrict__ flags, int32_t n_flags)
 {
-    __shared__ int32_t s_n[2];                 // rows kept for this workgroup, rows listed for canon_big_kernel
-    __shared__ int32_t s_rows[kListRows];
-    __shared__ int32_t sbuf[kBlockSortMax];
-    __shared__ uint32_t bm[kRowBitmapWords];
-    __shared__ int32_t part[kListRows];
+    // s_n: wave rows kept (listed from the front of s_rows), workgroup rows
+    // kept (from the back), rows listed for canon_big_kernel; in a short-row
+    // workgroup, its range's first entry and end
+    __shared__ int32_t s_n[3];
+    __shared__ int32_t s_rows[kListRows], s_a[kListRows], s_d[kListRows];   // row, first entry, length
+    __shared__ int32_t lbuf[kRowBitmapWords];  // the n-bit set, the bitonic sort's entries, or staged short rows
+    __shared__ int32_t part[kListRows / GM_WAVE];
     const int t = threadIdx.x, wid = t / GM_WAVE;
-    if (blockIdx.x == 0)
-        for (int32_t i = t; i < n_flags; i += blockDim.x) flags[i] = 0ull;
-    if (t < 2) s_n[t] = 0;
-    __syncthreads();
-    const int64_t v = (int64_t)blockIdx.x + (int64_t)t * blocks;
-    if (v < n) {
-        const int32_t a = row_ptr[v], d = row_ptr[v + 1] - a;
-        if (d <= 16) {
-            thread_sort_row<16>(v, a, d, col, out, stg, cnt);
-        } else if (d <= kThreadRow) {
-            thread_sort_row<kThreadRow>(v, a, d, col, out, stg, cnt);
-        } else if (d <= kBlockSortMax) {
-            s_rows[atomicAdd(&s_n[0], 1)] = (int32_t)v;
-        } else {
-            lists[list_stride + (int64_t)blockIdx.x * kListRows + atomicAdd(&s_n[1], 1)] = (int32_t)v;
+    if ((int32_t)blockIdx.x < blocks) {
+        const int32_t share = (int32_t)blockIdx.x;
+        if (share == 0)
+            for (int32_t i = t; i < n_flags; i += blockDim.x) flags[i] = 0ull;
+        if (t < 3) s_n[t] = 0;
+        __syncthreads();
+        const bool bitmap_rows = n <= 32 * kRowBitmapWords;
+        const int64_t vs = (int64_t)share + (int64_t)t * blocks;
+        if (vs < n) {
+            const int32_t a = row_ptr[vs], d = row_ptr[vs + 1] - a;
+            int slot = -1;
+            if (d > kMidRow) {
+                if (bitmap_rows || d <= kBlockSortMax) slot = kListRows - 1 - atomicAdd(&s_n[1], 1);
+                else lists[list_stride + (int64_t)share * kListRows + atomicAdd(&s_n[2], 1)] = (int32_t)vs;
+            } else if (d > kThreadRow) {
+                slot = atomicAdd(&s_n[0], 1);
+            }
+            if (slot >= 0) {
+                s_rows[slot] = (int32_t)vs;
+                s_a[slot] = a;
+                s_d[slot] = d;
+            }
         }
+        __syncthreads();
+        const int nm = s_n[0], nb = s_n[1];
+        for (int i = wid; i < nm; i += kListRows / GM_WAVE)
+            canon_one_row(s_rows[i], s_a[i], s_d[i], col, out, stg, cnt);
+        for (int i = 0; i < nb; ++i) {
+            const int32_t rv = s_rows[kListRows - 1 - i];
+            const int32_t a = s_a[kListRows - 1 - i], d = s_d[kListRows - 1 - i];
+            if (bitmap_rows) block_bitmap_row(rv, a, d, n, col, (uint32_t *)lbuf, part, out, stg, cnt);
+            else block_sort_row(rv, a, d, col, lbuf, part, out, stg, cnt);
+        }
+        if (t == 0) counts[(list_stride / kListRows) + share] = s_n[2];
+        return;
+    }
+    const int64_t v0 = ((int64_t)blockIdx.x - blocks) * kListRows;
+    const int32_t rows_here = (int32_t)min((int64_t)kListRows, (int64_t)n - v0);
+    int32_t a = 0, d = 0;
+    if (t < rows_here) {
+        a = row_ptr[v0 + t];
+        d = row_ptr[v0 + t + 1] - a;
+        if (t == 0) s_n[0] = a;                       // the range's first entry
+        if (t == rows_here - 1) s_n[1] = a + d;       // and its end
     }
     __syncthreads();
-    const int nr = s_n[0];
-    for (int i = wid; i < nr; i += kListRows / GM_WAVE) {
-        const int32_t rv = s_rows[i];
-        const int32_t a = row_ptr[rv], d = row_ptr[rv + 1] - a;
-        if (d <= kMidRow) canon_one_row(rv, a, d, col, out, stg, cnt);
+    const int32_t base = s_n[0], span = s_n[1] - base;
+    const bool staged = span <= kRowBitmapWords;   // the same for the whole workgroup
+    if (staged) {
+        for (int32_t j = t; j < span; j += kListRows) lbuf[j] = col[base + j];
+        __syncthreads();
     }
-    for (int i = 0; i < nr; ++i) {
-        const int32_t rv = s_rows[i];
-        const int32_t a = row_ptr[rv], d = row_ptr[rv + 1] - a;
-        if (d <= kMidRow) continue;
-        if (n <= 32 * kRowBitmapWords) block_bitmap_row(rv, a, d, n, col, bm, part, out, stg, cnt);
-        else block_sort_row(rv, a, d, col, sbuf, part, out, stg, cnt);
-    }
-    if (t == 0) {
-        counts[blockIdx.x] = 0;
-        counts[(list_stride / kListRows) + blockIdx.x] = s_n[1];
+    if (t < rows_here) {
+        const int64_t v = v0 + t;
+        if (staged) {
+            if (d <= 16) thread_sort_row<16>(v, a, d, lbuf + (a - base), out, stg, cnt);
+            else if (d <= kThreadRow) thread_sort_row<kThreadRow>(v, a, d, lbuf + (a - base), out, stg, cnt);
+        } else {
+            if (d <= 16) thread_sort_row<16>(v, a, d, col + a, out, stg, cnt);
+            else if (d <= kThreadRow) thread_sort_row<kThreadRow>(v, a, d, col + a, out, stg, cnt);
+        }
     }
 }
 
@@ -835,10 +884,15 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
     unsigned long long *flags = (unsigned long long *)p;
     p += align256((size_t)(tiles + 1) * sizeof(unsigned long long));
     uint32_t *bitmaps = (uint32_t *)p;
-    hipLaunchKernelGGL(canon_rows_kernel, dim3((unsigned)blocks), dim3(kListRows), 0, s, n, blocks, row_ptr, col_idx,
+    hipLaunchKernelGGL(canon_rows_kernel, dim3(2 * (unsigned)blocks), dim3(kListRows), 0, s, n, blocks, row_ptr, col_idx,
                        out_col, stg, cnt, lists, counts, list_stride, flags, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (n <= 32 * kRowBitmapWords) {   // the row kernel sorted every row
+        hipLaunchKernelGGL(canon_scan_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, (const int32_t *)cnt,
+                           out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col);
+        return hipGetLastError();
+    }
     const int32_t *list_big = lists + list_stride;
     const int32_t *n_big = counts + (blocks + 1);
     const size_t big_lds = (kBigRow + kBigBlock) * sizeof(int32_t);

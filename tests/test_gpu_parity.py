@@ -189,6 +189,73 @@ def test_long_rows_canonicalised(gumap):
     assert np.array_equal(ids.cpu().numpy(), oi) and np.array_equal(hops.cpu().numpy(), oh)
 
 
+def _rows_of_lengths(n, special, seed):
+    """CSR input with row v of length special[v] where given (else 0..12),
+    entries drawn uniformly from [0, n) with repeats and about one in ten
+    replaced by the row's own id (a self-loop).  Symmetry is not needed to
+    canonicalise."""
+    rng = np.random.default_rng(seed)
+    lengths = rng.integers(0, 13, n).astype(np.int64)
+    for v, d in special.items():
+        lengths[v] = d
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lengths, out=rp[1:])
+    src = np.repeat(np.arange(n, dtype=np.int64), lengths)
+    col = rng.integers(0, n, int(rp[-1]))
+    loop = rng.random(len(col)) < 0.1
+    col[loop] = src[loop]
+    return rp.astype(np.int32), col.astype(np.int32)
+
+
+def _canonical_by_definition(n, rp, col):
+    """Rows sorted ascending, repeats and the row's own vertex removed."""
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    dst = col.astype(np.int64)
+    key = np.unique(src[src != dst] * n + dst[src != dst])
+    out_rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(key // n, minlength=n), out=out_rp[1:])
+    return out_rp.astype(np.int32), (key % n).astype(np.int32)
+
+
+@pytest.mark.parametrize("n", [5000, 300000])
+def test_canonicalize_row_lengths(gumap, n):
+    """gumap_csr_canonicalize against the definition, with input rows on
+    each side of every bound between sorting paths (thread 16/32, wave
+    64/256, workgroup 4,096, big-row LDS 32,768), at the lowest ids (where a
+    preferential-attachment graph puts its hubs), among them, and at the
+    last ids; n = 5,000 sorts every long row through the n-bit set of the
+    row kernel, n = 300,000 through the LDS bitonic sort and the big-row
+    kernel.  The last tile of rows is ragged in both."""
+    import torch
+    lengths = (0, 1, 15, 16, 17, 31, 32, 33, 63, 64, 65, 255, 256, 257, 4095, 4096, 4097, 32768, 32769, 50000)
+    special = {}
+    for i, d in enumerate(lengths):
+        special[i] = d                    # lowest ids
+        special[n // 2 + 37 * i] = d      # spread
+        special[n - 1 - i] = d            # last ids
+    rp, col = _rows_of_lengths(n, special, 71 + n)
+    print("canonicalize n=%d nnz=%d" % (n, len(col)), flush=True)
+    out_rp, out_col = gumap.csr_canonicalize(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda())
+    want_rp, want_col = _canonical_by_definition(n, rp, col)
+    assert np.array_equal(out_rp.cpu().numpy(), want_rp), first_mismatch(out_rp.cpu().numpy(), want_rp)
+    assert np.array_equal(out_col.cpu().numpy(), want_col), first_mismatch(out_col.cpu().numpy(), want_col)
+
+
+def test_canonicalize_degenerate(gumap):
+    """Edgeless rows, a graph of self-loops only, and an already canonical
+    graph (nothing moves) against the definition."""
+    import torch
+    cases = [(7, np.zeros(8, np.int32), np.zeros(0, np.int32)),
+             (5, np.arange(6, dtype=np.int32), np.arange(5, dtype=np.int32)),
+             (G.ba(3000, 4, 72).n, G.ba(3000, 4, 72).row_ptr, G.ba(3000, 4, 72).col_idx)]
+    for n, rp, col in cases:
+        out_rp, out_col = gumap.csr_canonicalize(torch.from_numpy(np.ascontiguousarray(rp)).cuda(),
+                                                 torch.from_numpy(np.ascontiguousarray(col)).cuda())
+        want_rp, want_col = _canonical_by_definition(n, rp, col)
+        assert np.array_equal(out_rp.cpu().numpy(), want_rp)
+        assert np.array_equal(out_col.cpu().numpy(), want_col)
+
+
 def test_hop_range_error(gumap):
     import torch
     g = G.path(300)
