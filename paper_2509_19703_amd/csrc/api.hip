@@ -477,7 +477,7 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if (e == hipSuccess)
                     GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
                             launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                                      slot_row + a.slot0, lvl_cnt, 1, ids, hops, s));
+                                                      slot_row + a.slot0, lvl_cnt, 1, c.row_ptr, c.col, ids, hops, s));
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(hg, gout, (size_t)a.groups * 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -649,8 +649,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 if (e == hipSuccess)
                     GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
                             launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                                      slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups), ids,
-                                                      hops, s));
+                                                      slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups),
+                                                      c.row_ptr, c.col, ids, hops, s));
                 spec = true;
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -767,8 +767,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
         if (e == hipSuccess)
             GM_PROF("knn_select", (double)a.n_slots * n + (double)a.n_slots * k * 5.0,
                     launch_knn_select_counted(n, k, a.n_slots, hop_out, hop_rows_of, n, usrc + a.slot0,
-                                              slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups), ids,
-                                              hops, s));
+                                              slot_row + a.slot0, lvl_cnt, msbfs_hop_chunks(n, a.groups),
+                                              c.row_ptr, c.col, ids, hops, s));
         if (e != hipSuccess) return hip_status(e, "hop rows / selection");
     }
     if (!so && !all_sources && n_uniq < rows) {

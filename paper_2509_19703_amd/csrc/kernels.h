@@ -170,9 +170,13 @@ hipError_t launch_knn_select(int32_t n, int32_t k, int32_t rows, const uint8_t *
                              const int64_t *out_row, int32_t *ids, uint8_t *hops, hipStream_t s);
 // Same, with the per-block counts of vertices at hops 1..16 written by
 // launch_msbfs_hops_counted (part, `chunks` blocks per row); used when k <= 16.
+// With the canonical CSR (csr_row_ptr, csr_col; may be null) and src_of[r] the
+// source vertex of row r, the entries at hop 1 are copied from the source's
+// adjacency row instead of found in the hop row.
 hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
                                      const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
                                      const int64_t *out_row, const unsigned int *part, int32_t chunks,
+                                     const int32_t *csr_row_ptr, const int32_t *csr_col,
                                      int32_t *ids, uint8_t *hops, hipStream_t s);
 
 // Copy output rows src_row -> dst_row for repeated sources (pairs on device).

@@ -11,7 +11,12 @@
 // and stops as soon as all of them are found.  With per-chunk counts the pass
 // visits only the chunks that hold a vertex with hop < h* or one of the
 // needed vertices at hop h*.  Bytes are classified four at a time with SWAR
-// compares; only lanes holding a taken entry walk their bytes.
+// compares; only lanes holding a taken entry walk their bytes.  On the
+// canonical CSR the vertices at hop 1 are exactly the source's adjacency row,
+// already in id order: the counted kernel copies them from there (all of
+// them, or the first k when hop 1 alone reaches k) and scans the hop row
+// only for hops 2..h*, unless the row's length disagrees with the count of
+// hop 1 (then it scans for every hop).
 #include "device.h"
 #include "kernels.h"
 
@@ -74,7 +79,8 @@ struct Classes {
     uint32_t lt[4], eq[4];   // high-bit masks: 1 <= b < h*, b == h*
 };
 
-__device__ __forceinline__ Classes classify(uint4 q, int hstar, bool swar)
+// lt: lo <= b < h* (lo = 1, or 2 when hop 1 is taken from the CSR row).
+__device__ __forceinline__ Classes classify(uint4 q, int hstar, int lo, bool swar)
 {
     Classes c;
     const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
@@ -83,13 +89,13 @@ __device__ __forceinline__ Classes classify(uint4 q, int hstar, bool swar)
         const uint32_t x = qq[i];
         if (swar) {
             c.eq[i] = zero_hi(x ^ ((uint32_t)hstar * 0x01010101u));
-            c.lt[i] = ~ge_hi(x, (uint32_t)hstar) & ~zero_hi(x) & 0x80808080u;
+            c.lt[i] = ~ge_hi(x, (uint32_t)hstar) & ge_hi(x, (uint32_t)lo);
         } else {
             uint32_t lt = 0, eq = 0;
 #pragma unroll 1
             for (int j = 0; j < 4; ++j) {
                 const int b = (x >> (8 * j)) & 0xFF;
-                if (b >= 1 && b < hstar && b <= 254) lt |= 0x80u << (8 * j);
+                if (b >= lo && b < hstar && b <= 254) lt |= 0x80u << (8 * j);
                 if (b == hstar) eq |= 0x80u << (8 * j);
             }
             c.lt[i] = lt;
@@ -111,9 +117,11 @@ __device__ __forceinline__ void chunk_range(int32_t c, int32_t chunks, int32_t n
 // Selection pass.  cnt[h] (h = 1..hmax) holds the per-hop counts; got/base
 // are per-wave LDS scratch of 256 ints each.  The pass scans the chunks
 // list[0..nlist) in that (ascending) order, or the whole row if list is null.
+// With lo = 2 the entries at hop 1 (positions 0 .. cnt[1] - 1, h* > 1) are
+// written by the caller and the pass takes hops 2 and up.
 __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsigned int *cnt, int hmax,
                            const int32_t *list, int nlist, int32_t chunks, int *got, int *base,
-                           int32_t *ids_out, uint8_t *hops_out)
+                           int32_t *ids_out, uint8_t *hops_out, int lo)
 {
     const int l = lane();
     int c = 0, hstar = hmax + 1, need = 0;
@@ -127,6 +135,7 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
         c += ch;
     }
     const int c_less = c;
+    const int c_scan = lo == 2 ? c_less - (int)cnt[1] : c_less;   // hop < h* entries the pass writes
     if (l == 0) {
         int acc = 0;
         for (int h = 1; h < hstar && h <= hmax; ++h) {
@@ -140,7 +149,7 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
     const bool swar = hstar <= 128;
     if (!list) nlist = 1;
     int found_lt = 0, found_eq = 0;
-    if ((c_less > 0 || need > 0) && nlist > 0) {
+    if ((c_scan > 0 || need > 0) && nlist > 0) {
         // lanes at or past the end of the current chunk read all-255 bytes
         auto load = [&](int32_t v, int32_t e) {
             return v < e ? load16(row, n, v, aligned) : make_uint4(~0u, ~0u, ~0u, ~0u);
@@ -160,7 +169,7 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
             const bool more = nli < nlist;
             const uint4 qn = more ? load(nvb + 16 * l, nce) : make_uint4(~0u, ~0u, ~0u, ~0u);   // in flight
             const int32_t v = vb + 16 * l;
-            const Classes cl = classify(q, hstar, swar);
+            const Classes cl = classify(q, hstar, lo, swar);
             const int n_lt = __popc(cl.lt[0]) + __popc(cl.lt[1]) + __popc(cl.lt[2]) + __popc(cl.lt[3]);
             const int n_eq = __popc(cl.eq[0]) + __popc(cl.eq[1]) + __popc(cl.eq[2]) + __popc(cl.eq[3]);
             const uint32_t qq[4] = {q.x, q.y, q.z, q.w};
@@ -209,7 +218,7 @@ __device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsig
                 }
                 found_eq += __shfl(incl, GM_WAVE - 1, GM_WAVE);
             }
-            if ((found_lt >= c_less && found_eq >= need) || !more) break;
+            if ((found_lt >= c_scan && found_eq >= need) || !more) break;
             li = nli;
             vb = nvb;
             ce = nce;
@@ -228,7 +237,9 @@ __global__ void __launch_bounds__(kSelWaves * GM_WAVE)
 knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__restrict__ hop_rows,
                           const int64_t *__restrict__ row_of, int64_t row_stride,
                           const int64_t *__restrict__ out_row, const unsigned int *__restrict__ part,
-                          int32_t chunks, int32_t *__restrict__ ids, uint8_t *__restrict__ hops)
+                          int32_t chunks, const int32_t *__restrict__ csr_row_ptr,
+                          const int32_t *__restrict__ csr_col, const int32_t *__restrict__ src_of,
+                          int32_t *__restrict__ ids, uint8_t *__restrict__ hops)
 {
     __shared__ unsigned int cnt[kSelWaves][kCountLevels + 2];
     __shared__ int got[kSelWaves][kCountLevels + 2];
@@ -257,12 +268,13 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
         // per-level totals, level by level until the k-th vertex is reached:
         // the last level h* and the number of its vertices taken (cnt[1..h*]
         // for select_row, which stops at the same level)
-        int c = 0, hstar = kCountLevels + 1, need = 0;
+        int c = 0, hstar = kCountLevels + 1, need = 0, c1 = 0;
         bool found = false;
 #pragma unroll
         for (int hh = 1; hh <= kCountLevels; ++hh) {
             if (!found) {
                 const int ch = wave_sum((int)lsum[hh - 1]);
+                if (hh == 1) c1 = ch;
                 if (l == 0) cnt[wid][hh] = (unsigned int)ch;
                 if (c + ch >= k) {
                     hstar = hh;
@@ -273,8 +285,25 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
                 }
             }
         }
-        // chunks holding a vertex with hop < h*, or one of the first `need`
-        // vertices at hop h* (eq counts scanned in chunk order), in order
+        // hop 1 from the source's canonical adjacency row when its length
+        // matches the count: the first `need` entries when h* = 1, else all
+        const int64_t o = out_row[r] * (int64_t)k;
+        int lo = 1;
+        if (csr_row_ptr) {
+            const int32_t sv = src_of[r];
+            const int32_t ca = csr_row_ptr[sv], cdeg = csr_row_ptr[sv + 1] - ca;
+            if (cdeg == c1) {
+                lo = 2;
+                const int take = hstar == 1 ? need : c1;
+                for (int i = l; i < take; i += GM_WAVE) {
+                    ids[o + i] = csr_col[ca + i];
+                    hops[o + i] = 1;
+                }
+            }
+        }
+        if (lo == 2 && hstar == 1) continue;   // row complete: k entries at hop 1
+        // chunks holding a vertex with lo <= hop < h*, or one of the first
+        // `need` vertices at hop h* (eq counts scanned in chunk order), in order
         int nlist = 0, eq_carry = 0;
         for (int32_t c0 = 0; c0 < chunks; c0 += GM_WAVE) {
             const int32_t cc = c0 + l;
@@ -300,7 +329,7 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
             int lt_c = 0, eq_c = 0;
 #pragma unroll
             for (int h = 0; h < kCountLevels; ++h) {
-                if (h + 1 < hstar) lt_c += (int)v[h];
+                if (h + 1 >= lo && h + 1 < hstar) lt_c += (int)v[h];
                 else if (h + 1 == hstar) eq_c = (int)v[h];
             }
             const int incl = wave_incl_scan(eq_c);
@@ -312,9 +341,8 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
         }
         wave_sync();
         const uint8_t *row = hop_rows + row_of[r] * row_stride;
-        const int64_t o = out_row[r] * (int64_t)k;
         select_row(row, n, k, cnt[wid], kCountLevels, list[wid], nlist, chunks, got[wid], base[wid], ids + o,
-                   hops + o);
+                   hops + o, lo);
         wave_sync();
     }
 }
@@ -353,7 +381,7 @@ knn_select_hist_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__rest
         }
         wave_sync();
         const int64_t o = out_row[r] * (int64_t)k;
-        select_row(row, n, k, cnt, k, nullptr, 0, 1, got, base, ids + o, hops + o);
+        select_row(row, n, k, cnt, k, nullptr, 0, 1, got, base, ids + o, hops + o, 1);
         wave_sync();
     }
 }
@@ -378,15 +406,17 @@ __global__ void copy_rows_kernel(int32_t pairs, const int64_t *__restrict__ dst_
 hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const uint8_t *hop_rows,
                                      const int64_t *row_of, int64_t row_stride, const int32_t *src_of,
                                      const int64_t *out_row, const unsigned int *part, int32_t chunks,
+                                     const int32_t *csr_row_ptr, const int32_t *csr_col,
                                      int32_t *ids, uint8_t *hops, hipStream_t s)
 {
-    (void)src_of;
     if (rows <= 0) return hipSuccess;
+    if (!src_of) csr_row_ptr = nullptr;
     if (part && k <= kCountLevels && chunks >= 1 && chunks <= kMaxChunks) {
         int blocks = (rows + kSelWaves - 1) / kSelWaves;
         if (blocks > 65536) blocks = 65536;
         hipLaunchKernelGGL(knn_select_counted_kernel, dim3(blocks), dim3(kSelWaves * GM_WAVE), 0, s, n, k,
-                           rows, hop_rows, row_of, row_stride, out_row, part, chunks, ids, hops);
+                           rows, hop_rows, row_of, row_stride, out_row, part, chunks, csr_row_ptr, csr_col,
+                           src_of, ids, hops);
     } else {
         const size_t lds = ((size_t)(k + 1) * GM_WAVE + 256) * sizeof(unsigned int);
         static bool lds_set = false;
@@ -409,7 +439,7 @@ hipError_t launch_knn_select(int32_t n, int32_t k, int32_t rows, const uint8_t *
                              const int64_t *out_row, int32_t *ids, uint8_t *hops, hipStream_t s)
 {
     return launch_knn_select_counted(n, k, rows, hop_rows, row_of, row_stride, src_of, out_row, nullptr, 0,
-                                     ids, hops, s);
+                                     nullptr, nullptr, ids, hops, s);
 }
 
 hipError_t launch_copy_rows(int32_t pairs, const int64_t *dst_src, int32_t k, int32_t n,
