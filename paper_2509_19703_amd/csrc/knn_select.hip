@@ -247,6 +247,16 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
     __shared__ int32_t list[kSelWaves][kMaxChunks];
     const int wid = threadIdx.x / GM_WAVE, l = lane();
     for (int32_t r = blockIdx.x * kSelWaves + wid; r < rows; r += gridDim.x * kSelWaves) {
+        // the source's adjacency row and its first k entries (the candidates
+        // at hop 1) are loaded first, beside the counts; they are stored once
+        // the row's other entries are placed
+        int32_t ca = 0, cdeg = -1, h1 = 0;
+        if (csr_row_ptr) {
+            const int32_t sv = src_of[r];
+            ca = csr_row_ptr[sv];
+            cdeg = csr_row_ptr[sv + 1] - ca;
+            if (l < min(cdeg, k)) h1 = csr_col[ca + l];
+        }
         // each lane loads the 16 per-level counts of its chunks (l, l + 64,
         // ...) once, summing them per level; its first chunk's stay in registers
         unsigned int my[kCountLevels], lsum[kCountLevels];
@@ -288,20 +298,15 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
         // hop 1 from the source's canonical adjacency row when its length
         // matches the count: the first `need` entries when h* = 1, else all
         const int64_t o = out_row[r] * (int64_t)k;
-        int lo = 1;
-        if (csr_row_ptr) {
-            const int32_t sv = src_of[r];
-            const int32_t ca = csr_row_ptr[sv], cdeg = csr_row_ptr[sv + 1] - ca;
-            if (cdeg == c1) {
-                lo = 2;
-                const int take = hstar == 1 ? need : c1;
-                for (int i = l; i < take; i += GM_WAVE) {
-                    ids[o + i] = csr_col[ca + i];
-                    hops[o + i] = 1;
-                }
+        const int lo = cdeg == c1 ? 2 : 1;
+        const int take1 = lo == 2 ? (hstar == 1 ? need : c1) : 0;   // at most k - 1 <= 63, or need = k <= 16
+        if (lo == 2 && hstar == 1) {   // row complete: k entries at hop 1
+            if (l < take1) {
+                ids[o + l] = h1;
+                hops[o + l] = 1;
             }
+            continue;
         }
-        if (lo == 2 && hstar == 1) continue;   // row complete: k entries at hop 1
         // chunks holding a vertex with lo <= hop < h*, or one of the first
         // `need` vertices at hop h* (eq counts scanned in chunk order), in order
         int nlist = 0, eq_carry = 0;
@@ -343,6 +348,10 @@ knn_select_counted_kernel(int32_t n, int32_t k, int32_t rows, const uint8_t *__r
         const uint8_t *row = hop_rows + row_of[r] * row_stride;
         select_row(row, n, k, cnt[wid], kCountLevels, list[wid], nlist, chunks, got[wid], base[wid], ids + o,
                    hops + o, lo);
+        if (l < take1) {
+            ids[o + l] = h1;
+            hops[o + l] = 1;
+        }
         wave_sync();
     }
 }
