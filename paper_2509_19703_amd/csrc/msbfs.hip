@@ -772,21 +772,35 @@ msbfs_fused_rows_kernel(MsbfsArgs a, int L_cap, int full_hops, int32_t nnz, uint
 // the mean degree (a lone thread would walk their rows serially while the
 // rest of its wave waits); dense graphs with an even degree keep one thread
 // per vertex word, which stops early.  info[1] = count, info[2] = threshold.
-// Plane count of the levels run so far: one block sums the new-vertex field
-// of every (level, group, spread slot) counter of levels [first, last).
-__global__ void __launch_bounds__(256)
+// Plane count of the levels run so far: one block looks at the new-vertex
+// field of every (level, group, spread slot) counter of levels [first, last),
+// each thread kDepthLoads counters of the flat (level, slot) range at a time
+// with all of its loads in flight (the levels are independent).
+constexpr int kDepthThreads = 1024;
+constexpr int kDepthLoads = 4;
+
+__global__ void __launch_bounds__(kDepthThreads)
 msbfs_depth_kernel(const unsigned long long *__restrict__ stats, int32_t groups, int first, int last,
                    int32_t *__restrict__ out)
 {
     __shared__ int found[256];
     const int per_level = groups * kSpread;
-    for (int lv = first + (int)threadIdx.x; lv < last && lv < first + 256; lv += blockDim.x) found[lv - first] = 0;
+    const int nlev = min(last, first + 256) - first;
+    for (int i = threadIdx.x; i < nlev; i += blockDim.x) found[i] = 0;
     __syncthreads();
-    for (int lv = first; lv < last && lv < first + 256; ++lv) {
-        unsigned long long t = 0;
-        for (int i = threadIdx.x; i < per_level; i += blockDim.x)
-            t |= stats[((size_t)lv * per_level + i) * kStatFields + 0];
-        if (t) found[lv - first] = 1;
+    const int64_t total = (int64_t)max(nlev, 0) * per_level;
+    for (int64_t b = 0; b < total; b += (int64_t)kDepthThreads * kDepthLoads) {
+        unsigned long long x[kDepthLoads];
+#pragma unroll
+        for (int j = 0; j < kDepthLoads; ++j) {
+            const int64_t idx = b + threadIdx.x + (int64_t)j * kDepthThreads;
+            x[j] = idx < total ? stats[((size_t)first * per_level + idx) * kStatFields + 0] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kDepthLoads; ++j) {
+            const int64_t idx = b + threadIdx.x + (int64_t)j * kDepthThreads;
+            if (x[j]) found[idx / per_level] = 1;   // every writer stores 1
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1290,7 +1304,7 @@ hipError_t launch_heavy_list(int32_t n, const int32_t *row_ptr, int32_t forced, 
 
 hipError_t launch_msbfs_depth(const MsbfsArgs &a, int first, int last, int32_t *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(msbfs_depth_kernel, dim3(1), dim3(256), 0, s, (const unsigned long long *)a.stats,
+    hipLaunchKernelGGL(msbfs_depth_kernel, dim3(1), dim3(kDepthThreads), 0, s, (const unsigned long long *)a.stats,
                        a.stats_groups, first, last, out);
     return hipGetLastError();
 }
