@@ -90,6 +90,7 @@ __global__ void source_slots_k(int32_t n, const int32_t *first, const int32_t *p
 // largest degree among them info[4]).
 constexpr int kRankThreads = 1024;
 constexpr int kRankMax = 4096;
+static_assert(kRankMax % kRankThreads == 0, "rows are read kRankMax / kRankThreads per thread");
 
 __global__ void source_vertex_prep_k(int32_t n, const int32_t *__restrict__ rp, int32_t forced, int32_t *first,
                                      int32_t *count, int32_t *slot_of, int32_t *heavy, int32_t *info)
@@ -133,10 +134,21 @@ source_rank_small_k(const int32_t *__restrict__ src, int32_t rows, int32_t n, in
     __shared__ int32_t wsum[kRankThreads / GM_WAVE];
     const int t = threadIdx.x;
     const int W = (n + 63) / 64;
+    // this thread's rows t, t + kRankThreads, ... (rows <= kRankMax), read once
+    constexpr int kPer = kRankMax / kRankThreads;
+    int32_t sv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int r = t + j * kRankThreads;
+        sv[j] = r < rows ? src[r] : 0;
+    }
     for (int w = t; w < W; w += kRankThreads) bits[w] = 0;
     __syncthreads();
-    for (int r = t; r < rows; r += kRankThreads) {
-        const int32_t v = src[r];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int r = t + j * kRankThreads;
+        if (r >= rows) continue;
+        const int32_t v = sv[j];
         if (v < 0 || v >= n) atomicOr(&info[0], 1);
         else atomicOr(&bits[v >> 6], 1ull << (v & 63));
     }
@@ -166,9 +178,11 @@ source_rank_small_k(const int32_t *__restrict__ src, int32_t rows, int32_t n, in
         times[q] = 0;
     }
     __syncthreads();
-    for (int r = t; r < rows; r += kRankThreads) {
-        const int32_t v = src[r];
-        if (v < 0 || v >= n) continue;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int r = t + j * kRankThreads;
+        const int32_t v = sv[j];
+        if (r >= rows || v < 0 || v >= n) continue;
         const int32_t q = rank_of(bits, prefix, v);
         atomicMin(&first_row[q], r);
         atomicAdd(&times[q], 1);
