@@ -342,7 +342,7 @@ __device__ void block_bitmap_row(int32_t v, int32_t a, int32_t d, int32_t n, con
 //     when n <= 32 * kRowBitmapWords (any length), else by the LDS bitonic
 //     sort up to kBlockSortMax; rows left over (n above that bound and more
 //     than kBlockSortMax entries) are listed (kListRows slots per workgroup,
-//     count in counts[blocks + 1 + b]) for canon_big_kernel.  Workgroup 0
+//     list_big[b * kListRows ...], count in n_big[b]) for canon_big_kernel.  Workgroup 0
 //     also clears the look-back flags of canon_scan_kernel.
 //   b >= blocks, c = b - blocks, sorts the rows of at most kThreadRow entries
 //     among [c * kListRows, (c + 1) * kListRows), a thread each in registers;
@@ -354,7 +354,7 @@ static_assert(kRowBitmapWords >= kBlockSortMax, "the LDS row buffer serves both 
 __global__ void __launch_bounds__(kListRows)
 canon_rows_kernel(int32_t n, int32_t blocks, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                   int32_t *__restrict__ out, int32_t *__restrict__ stg, int32_t *__restrict__ cnt,
-                  int32_t *__restrict__ lists, int32_t *__restrict__ counts, int64_t list_stride,
+                  int32_t *__restrict__ list_big, int32_t *__restrict__ n_big,
                   unsigned long long *__restrict__ flags, int32_t n_flags)
 {
     // s_n: wave rows kept (listed from the front of s_rows), workgroup rows
@@ -378,7 +378,7 @@ canon_rows_kernel(int32_t n, int32_t blocks, const int32_t *__restrict__ row_ptr
             int slot = -1;
             if (d > kMidRow) {
                 if (bitmap_rows || d <= kBlockSortMax) slot = kListRows - 1 - atomicAdd(&s_n[1], 1);
-                else lists[list_stride + (int64_t)share * kListRows + atomicAdd(&s_n[2], 1)] = (int32_t)vs;
+                else list_big[(int64_t)share * kListRows + atomicAdd(&s_n[2], 1)] = (int32_t)vs;
             } else if (d > kThreadRow) {
                 slot = atomicAdd(&s_n[0], 1);
             }
@@ -398,7 +398,7 @@ canon_rows_kernel(int32_t n, int32_t blocks, const int32_t *__restrict__ row_ptr
             if (bitmap_rows) block_bitmap_row(rv, a, d, n, col, (uint32_t *)lbuf, part, out, stg, cnt);
             else block_sort_row(rv, a, d, col, lbuf, part, out, stg, cnt);
         }
-        if (t == 0) counts[(list_stride / kListRows) + share] = s_n[2];
+        if (t == 0) n_big[share] = s_n[2];
         return;
     }
     const int64_t v0 = ((int64_t)blockIdx.x - blocks) * kListRows;
@@ -855,8 +855,8 @@ size_t canon_scratch_bytes(int32_t n, int32_t nnz)
     size_t b = 0;
     b += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));                               // staged rows
     b += align256((size_t)(n + 1) * sizeof(int32_t));                                           // cnt
-    b += align256(2 * (blocks + 1) * kListRows * sizeof(int32_t));                              // row lists
-    b += align256(2 * (blocks + 1) * sizeof(int32_t));                                          // list counts
+    b += align256(blocks * kListRows * sizeof(int32_t));                                        // long-row lists
+    b += align256((blocks + 1) * sizeof(int32_t));                                              // list counts
     b += align256((size_t)((n + kScanRows - 1) / kScanRows + 1) * sizeof(unsigned long long));   // flags
     b += align256((size_t)kLongBlocks * (((size_t)n + 31) / 32) * sizeof(uint32_t));             // bitmaps
     return b;
@@ -876,16 +876,15 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
     char *p = (char *)scratch;
     int32_t *stg = (int32_t *)p;       p += align256((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
     int32_t *cnt = (int32_t *)p;       p += align256((size_t)(n + 1) * sizeof(int32_t));
-    // two lists of (blocks + 1) * kListRows entries and two count arrays of
-    // blocks + 1 (mid and big rows)
-    const int64_t list_stride = (int64_t)(blocks + 1) * kListRows;
-    int32_t *lists = (int32_t *)p;     p += align256(2 * (size_t)list_stride * sizeof(int32_t));
-    int32_t *counts = (int32_t *)p;    p += align256(2 * ((size_t)blocks + 1) * sizeof(int32_t));
+    // rows past kBlockSortMax on graphs above the n-bit set's bound: kListRows
+    // slots per workgroup and a count per workgroup
+    int32_t *list_big = (int32_t *)p;  p += align256((size_t)blocks * kListRows * sizeof(int32_t));
+    int32_t *n_big = (int32_t *)p;     p += align256(((size_t)blocks + 1) * sizeof(int32_t));
     unsigned long long *flags = (unsigned long long *)p;
     p += align256((size_t)(tiles + 1) * sizeof(unsigned long long));
     uint32_t *bitmaps = (uint32_t *)p;
     hipLaunchKernelGGL(canon_rows_kernel, dim3(2 * (unsigned)blocks), dim3(kListRows), 0, s, n, blocks, row_ptr, col_idx,
-                       out_col, stg, cnt, lists, counts, list_stride, flags, tiles);
+                       out_col, stg, cnt, list_big, n_big, flags, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n <= 32 * kRowBitmapWords) {   // the row kernel sorted every row
@@ -893,8 +892,6 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                            out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col);
         return hipGetLastError();
     }
-    const int32_t *list_big = lists + list_stride;
-    const int32_t *n_big = counts + (blocks + 1);
     const size_t big_lds = (kBigRow + kBigBlock) * sizeof(int32_t);
     static bool lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
     int dev = 0;
