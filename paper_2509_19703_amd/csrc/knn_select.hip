@@ -119,9 +119,9 @@ __device__ __forceinline__ void chunk_range(int32_t c, int32_t chunks, int32_t n
 // list[0..nlist) in that (ascending) order, or the whole row if list is null.
 // With lo = 2 the entries at hop 1 (positions 0 .. cnt[1] - 1, h* > 1) are
 // written by the caller and the pass takes hops 2 and up.
-__device__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsigned int *cnt, int hmax,
-                           const int32_t *list, int nlist, int32_t chunks, int *got, int *base,
-                           int32_t *ids_out, uint8_t *hops_out, int lo)
+__device__ __forceinline__ void select_row(const uint8_t *row, int32_t n, int32_t k, const unsigned int *cnt,
+                                           int hmax, const int32_t *list, int nlist, int32_t chunks, int *got,
+                                           int *base, int32_t *ids_out, uint8_t *hops_out, int lo)
 {
     const int l = lane();
     int c = 0, hstar = hmax + 1, need = 0;
