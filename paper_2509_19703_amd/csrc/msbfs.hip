@@ -849,14 +849,32 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x)
     return x;
 }
 
-// 8 bits -> 8 bytes holding 0 or 1, bit i in byte i.
-__device__ __forceinline__ uint64_t spread8(uint64_t bits8)
+// 4 bits -> 4 bytes holding 0 or 1, bit i in byte i (one 24-bit multiply:
+// the four shifted copies n, n << 7, n << 14, n << 21 do not overlap).
+__device__ __forceinline__ uint32_t spread4(uint32_t nib)
 {
-    uint64_t t = (bits8 & 0xFFull) * 0x0101010101010101ull;
-    t &= 0x8040201008040201ull;
-    t = ((t + 0x7F7F7F7F7F7F7F7Full) & 0x8080808080808080ull) >> 7;
-    return t;
+    return __umul24(nib & 0xFu, 0x00204081u) & 0x01010101u;
 }
+
+// Hop bytes of vertices 8c .. 8c + 7 of a transposed tile: byte i is 0xFF
+// where the vertex is not visited, else the hop whose bit b is plane b
+// (planes past the ones in use are zero).
+template <int PL>
+__device__ __forceinline__ uint64_t hop_bytes8(uint64_t vis, const uint64_t *pl, int c)
+{
+    uint32_t half[2];
+#pragma unroll
+    for (int nib = 0; nib < 2; ++nib) {
+        const int sh = 8 * c + 4 * nib;
+        const uint32_t nv = spread4((uint32_t)(~vis >> sh));
+        uint32_t r = (nv << 8) - nv;   // 0xFF in the bytes of unvisited vertices
+#pragma unroll
+        for (int b = 0; b < PL; ++b) r |= spread4((uint32_t)(pl[b] >> sh)) << b;
+        half[nib] = r;
+    }
+    return (uint64_t)half[0] | ((uint64_t)half[1] << 32);
+}
+
 
 // Block: one wave per word of a group, all on the same vertex tiles, so the
 // waves of a block together read whole 64-byte state rows.  Wave w walks
@@ -912,13 +930,7 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
                 cnt[h - 1] += __popcll(m);
             }
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                uint64_t by = spread8(~vis >> (8 * c)) * 0xFFull;
-#pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    if (b < planes_used) by |= spread8(pl[b] >> (8 * c)) << b;
-                outw[half][c] = by;
-            }
+            for (int c = 0; c < 8; ++c) outw[half][c] = hop_bytes8<8>(vis, pl, c);
         }
         if (slot_ok) {
             const int32_t v0 = tile * 64;
@@ -1009,13 +1021,7 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
             }
             uint64_t *dst = (uint64_t *)(stage + (size_t)(64 * w + l) * PITCH + 64 * half);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                uint64_t by = spread8(~vis >> (8 * c)) * 0xFFull;
-#pragma unroll
-                for (int b = 0; b < PL; ++b)
-                    if (b < planes_used) by |= spread8(pl[b] >> (8 * c)) << b;
-                dst[c] = by;
-            }
+            for (int c = 0; c < 8; ++c) dst[c] = hop_bytes8<PL>(vis, pl, c);
         }
         __syncthreads();
         if (PREFETCH && tile + TILES < t_end) load_tiles(tile + TILES);
