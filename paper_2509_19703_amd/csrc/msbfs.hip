@@ -834,19 +834,68 @@ __global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int
 
 // Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
 // holds column j (bit i = old bit j of lane i).
+// x from lane (this lane) ^ S.  Strides 1 and 2 are quad permutations and 8
+// a rotation of the 16-lane row by 8, done by DPP moves on the VALU; 4, 16
+// and 32 go through ds_bpermute.
+template <int S>
+__device__ __forceinline__ uint64_t xor_lane(uint64_t x)
+{
+    if constexpr (S == 1 || S == 2 || S == 8) {
+        constexpr int ctrl = S == 1 ? 0xB1 : (S == 2 ? 0x4E : 0x128);   // quad_perm [1,0,3,2], [2,3,0,1]; row_ror:8
+        const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)x, ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), ctrl, 0xF, 0xF, false);
+        return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+    } else {
+        return __shfl_xor(x, S, GM_WAVE);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void transpose_stage(uint64_t &x, int l)
+{
+    constexpr int s = 32 >> K;
+    constexpr uint64_t M = K == 0 ? 0x00000000FFFFFFFFull
+                         : K == 1 ? 0x0000FFFF0000FFFFull
+                         : K == 2 ? 0x00FF00FF00FF00FFull
+                         : K == 3 ? 0x0F0F0F0F0F0F0F0Full
+                         : K == 4 ? 0x3333333333333333ull
+                                  : 0x5555555555555555ull;
+    const uint64_t y = xor_lane<s>(x);
+    if ((l & s) == 0) x = (x & M) | ((y & M) << s);
+    else x = (x & ~M) | ((y & ~M) >> s);
+}
+
 __device__ __forceinline__ uint64_t transpose64(uint64_t x)
 {
     const int l = lane();
-    const uint64_t M[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                           0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int s = 32 >> k;
-        const uint64_t y = __shfl_xor(x, s, GM_WAVE);
-        if ((l & s) == 0) x = (x & M[k]) | ((y & M[k]) << s);
-        else x = (x & ~M[k]) | ((y & ~M[k]) >> s);
-    }
+    transpose_stage<0>(x, l);
+    transpose_stage<1>(x, l);
+    transpose_stage<2>(x, l);
+    transpose_stage<3>(x, l);
+    transpose_stage<4>(x, l);
+    transpose_stage<5>(x, l);
     return x;
+}
+
+// Adds to cnt[h - 1] the vertices at hop h (1 <= h <= 16) among the 64 of a
+// transposed tile (bit i of pl[b] is bit b of vertex i's hop; planes 5..7
+// must be clear for a vertex to count), through a decision tree over the
+// planes: 29 ANDs for the 16 classes instead of 5 per class.
+__device__ __forceinline__ void count_hops(uint64_t vis, const uint64_t *pl, unsigned int *cnt)
+{
+    static_assert(kCountLevels == 16, "hops 1..16 are four planes plus the fifth");
+    const uint64_t low_ok = vis & ~(pl[5] | pl[6] | pl[7]);
+    const uint64_t base = low_ok & ~pl[4];   // hops 0..15
+    uint64_t t1[2], t2[4], t3[8];
+    t1[0] = base & ~pl[0];
+    t1[1] = base & pl[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t2[i] = t1[i & 1] & (((i >> 1) & 1) ? pl[1] : ~pl[1]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t3[i] = t2[i & 3] & (((i >> 2) & 1) ? pl[2] : ~pl[2]);
+#pragma unroll
+    for (int h = 1; h < 16; ++h) cnt[h - 1] += __popcll(t3[h & 7] & (((h >> 3) & 1) ? pl[3] : ~pl[3]));
+    cnt[15] += __popcll(low_ok & pl[4] & ~(pl[0] | pl[1] | pl[2] | pl[3]));
 }
 
 // 4 bits -> 4 bytes holding 0 or 1, bit i in byte i (one 24-bit multiply:
@@ -918,17 +967,7 @@ msbfs_hops_kernel(MsbfsArgs a, int planes_arg, uint8_t *__restrict__ hop_out,
             for (int b = 0; b < 8; ++b)
                 if (b < planes_used) pl[b] = transpose64(pl[b]);
             // counts of vertices at hops 1..16 (planes 5.. must be clear)
-            uint64_t high = 0;
-#pragma unroll
-            for (int b = 5; b < 8; ++b) high |= pl[b];
-            const uint64_t low_ok = vis & ~high;
-#pragma unroll
-            for (int h = 1; h <= kCountLevels; ++h) {
-                uint64_t m = low_ok;
-#pragma unroll
-                for (int b = 0; b < 5; ++b) m &= ((h >> b) & 1) ? pl[b] : ~pl[b];
-                cnt[h - 1] += __popcll(m);
-            }
+            count_hops(vis, pl, cnt);
 #pragma unroll
             for (int c = 0; c < 8; ++c) outw[half][c] = hop_bytes8<8>(vis, pl, c);
         }
@@ -1008,17 +1047,7 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
             uint64_t pl[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) pl[b] = (b < PL && b < planes_used) ? transpose64(wp[half][b < PL ? b : 0]) : 0ull;
-            uint64_t high = 0;
-#pragma unroll
-            for (int b = 5; b < 8; ++b) high |= pl[b];
-            const uint64_t low_ok = vis & ~high;
-#pragma unroll
-            for (int h = 1; h <= kCountLevels; ++h) {
-                uint64_t m = low_ok;
-#pragma unroll
-                for (int b = 0; b < 5; ++b) m &= ((h >> b) & 1) ? pl[b] : ~pl[b];
-                cnt[h - 1] += __popcll(m);
-            }
+            count_hops(vis, pl, cnt);
             uint64_t *dst = (uint64_t *)(stage + (size_t)(64 * w + l) * PITCH + 64 * half);
 #pragma unroll
             for (int c = 0; c < 8; ++c) dst[c] = hop_bytes8<PL>(vis, pl, c);
