@@ -125,7 +125,7 @@ constexpr int kHistBatch = 2;   // frontier hops loaded together per tile
 template <int WORDS, int PL, int TILES>
 __device__ __forceinline__ void load_tile_state(const MsbfsArgs &a, int32_t g, int w, int32_t tile, int32_t t_end,
                                                 int planes_used, int depth, uint64_t (&wv)[TILES],
-                                                uint64_t (&wp)[TILES][PL])
+                                                uint64_t (&wp)[TILES][PL], bool want_vis = true)
 {
     constexpr int LW = WORDS == 1 ? 0 : (WORDS == 2 ? 1 : (WORDS == 4 ? 2 : 3));
     const size_t gbase = (size_t)g * a.n * WORDS + w;
@@ -151,6 +151,8 @@ __device__ __forceinline__ void load_tile_state(const MsbfsArgs &a, int32_t g, i
     }
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
+        wv[t] = 0ull;
+        if (!want_vis) continue;   // the caller rebuilds it from the planes
         const int32_t v = (tile + t) * 64 + lane();
         const int32_t ls = (in[t] ? a.slot_of[v] : -1) - a.slot0;
         const int32_t bit = ls - (g * 64 * WORDS + 64 * w);
@@ -169,7 +171,7 @@ __device__ __forceinline__ void load_tile_state(const MsbfsArgs &a, int32_t g, i
             const int h = h0 + u;
 #pragma unroll
             for (int t = 0; t < TILES; ++t) {
-                wv[t] |= f[t][u];
+                if (want_vis) wv[t] |= f[t][u];
 #pragma unroll
                 for (int b = 0; b < PL; ++b)
                     if ((h >> b) & 1) wp[t][b] |= f[t][u];
@@ -184,7 +186,7 @@ __device__ __forceinline__ void load_tile_state(const MsbfsArgs &a, int32_t g, i
                 if (b < planes_used && in[t]) {
                     const uint64_t x = a.planes[(size_t)b * a.plane_stride + me[t]];
                     wp[t][b] |= x;
-                    wv[t] |= x;
+                    if (want_vis) wv[t] |= x;
                 }
     }
 }
@@ -1035,18 +1037,32 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
     const int32_t t_begin = (int32_t)((int64_t)blockIdx.x * ntiles / gridDim.x);
     const int32_t t_end = (int32_t)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     uint64_t wv[TILES], wp[TILES][PL];   // visited and plane words of the tiles being (or next to be) transposed
+    // With the frontier history and every hop <= 15 a vertex is visited iff it
+    // is the row's own source or one of the four planes holds it: the visited
+    // word is then rebuilt after the transpose instead of loaded and
+    // transposed (the source's vertex is read once per lane).
+    constexpr bool kPlanesGiveVis = PL <= 4 && !STRESS;
+    const bool derive_vis = kPlanesGiveVis && a.hist_levels > 0;
+    const int32_t self_v = (derive_vis && slot_ok) ? a.usrc[a.slot0 + local_slot] : -1;
     auto load_tiles = [&](int32_t tile) {
-        load_tile_state<WORDS, PL, TILES>(a, g, w, tile, t_end, planes_used, depth, wv, wp);
+        load_tile_state<WORDS, PL, TILES>(a, g, w, tile, t_end, planes_used, depth, wv, wp, !derive_vis);
     };
     if (PREFETCH && t_begin < t_end) load_tiles(t_begin);
     for (int32_t tile = t_begin; tile < t_end; tile += TILES) {
         if (!PREFETCH) load_tiles(tile);
 #pragma unroll
         for (int half = 0; half < TILES; ++half) {
-            const uint64_t vis = transpose64(wv[half]);
             uint64_t pl[8];
 #pragma unroll
             for (int b = 0; b < 8; ++b) pl[b] = (b < PL && b < planes_used) ? transpose64(wp[half][b < PL ? b : 0]) : 0ull;
+            uint64_t vis;
+            if (kPlanesGiveVis && derive_vis) {
+                const int32_t tt = tile + half;
+                vis = pl[0] | pl[1] | pl[2] | pl[3] |
+                      ((self_v >= 0 && (self_v >> 6) == tt) ? 1ull << (self_v & 63) : 0ull);
+            } else {
+                vis = transpose64(wv[half]);
+            }
             count_hops(vis, pl, cnt);
             uint64_t *dst = (uint64_t *)(stage + (size_t)(64 * w + l) * PITCH + 64 * half);
 #pragma unroll
