@@ -834,8 +834,6 @@ __global__ void heavy_list_kernel(int32_t n, const int32_t *__restrict__ rp, int
         }
 }
 
-// Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
-// holds column j (bit i = old bit j of lane i).
 // x from lane (this lane) ^ S.  Strides 1 and 2 are quad permutations and 8
 // a rotation of the 16-lane row by 8, done by DPP moves on the VALU; 4, 16
 // and 32 go through ds_bpermute.
@@ -867,6 +865,9 @@ __device__ __forceinline__ void transpose_stage(uint64_t &x, int l)
     else x = (x & ~M) | ((y & ~M) >> s);
 }
 
+// Transpose of a 64 x 64 bit matrix held one row per lane: afterwards lane j
+// holds column j (bit i = old bit j of lane i).  Six butterfly stages; in
+// stage K lanes l and l ^ (32 >> K) swap blocks of 32 >> K bits.
 __device__ __forceinline__ uint64_t transpose64(uint64_t x)
 {
     const int l = lane();
