@@ -317,10 +317,14 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
             if ((st = scratch_get(kSlotCount, (size_t)n * sizeof(int32_t), (void **)&count))) return st;
             if ((st = scratch_get(kSlotMult, (size_t)n * sizeof(int32_t), (void **)&mult))) return st;
         }
-        if (sources_ranked_small(rows, n))
+        if (sources_ranked_small(rows, n)) {
+            // the ranking kernel stores the final info words into pinned host
+            // memory itself (taken now: the read below gets the same buffer)
+            void *hv = nullptr;
+            if ((st = host_scratch_get(256, &hv))) return st;
             e = prepare_sources_small(sources, rows, n, c.row_ptr, heavy_forced, heavy,
-                                      first_row, count, usrc, slot_row, slot_of, mult, info, s);
-        else
+                                      first_row, count, usrc, slot_row, slot_of, mult, info, s, (int32_t *)hv);
+        } else
             e = prepare_sources(sources, rows, n, first_row, count, marks, pos, scan_tmp, usrc, slot_row, slot_of,
                                 mult, info, s);
     }
@@ -339,7 +343,8 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     if (!setup_known) {
         void *hv = nullptr;
         if ((st = host_scratch_get(256, &hv))) return st;
-        e = hipMemcpyAsync(hv, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        const bool published = !all_sources && sources_ranked_small(rows, n);
+        if (!published) e = hipMemcpyAsync(hv, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_status(e, "source setup");
         std::memcpy(hinfo, hv, sizeof(hinfo));
@@ -872,9 +877,14 @@ int csr_canonicalize(const gumap_graph *g, int32_t *out_rp, int32_t *out_col, in
     }
     void *tmp = nullptr;
     if ((st = scratch_get(kSlotCanonTmp, canon_scratch_bytes(g->n, g->nnz), &tmp))) return st;
+    // the scan stores the kept-entry count straight into pinned host memory
+    // (at byte 32: read_flag below uses the first bytes of the same buffer)
+    void *h = nullptr;
+    if ((st = host_scratch_get(64, &h))) return st;
+    int32_t *h_total = (int32_t *)h + 8;
     hipError_t e;
     GM_PROF("canonicalize", 2.0 * ((double)g->n * 4 + (double)g->nnz * 4),
-            launch_canonicalize(g->n, g->nnz, g->row_ptr, g->col_idx, out_rp, out_col, tmp, s));
+            launch_canonicalize(g->n, g->nnz, g->row_ptr, g->col_idx, out_rp, out_col, tmp, s, h_total));
     if (e != hipSuccess) return hip_status(e, "canonicalize");
     if (g->flags & GUMAP_VALIDATE) {
         int *err = nullptr;
@@ -886,12 +896,8 @@ int csr_canonicalize(const gumap_graph *g, int32_t *out_rp, int32_t *out_col, in
         if ((st = read_flag(err, &bad, s))) return st;
         if (bad) return set_error(GUMAP_EGRAPH, "CSR is not symmetric");
     }
-    void *h = nullptr;
-    if ((st = host_scratch_get(64, &h))) return st;
-    e = hipMemcpyAsync(h, out_rp + g->n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_status(e, "canonicalize");
     if ((st = finish(s, "gumap_csr_canonicalize"))) return st;
-    *out_nnz = *(int32_t *)h;
+    *out_nnz = *(volatile int32_t *)h_total;
     if (*out_nnz < 0) return set_error(GUMAP_EDEVICE, "canonicalisation scan did not complete");
     return GUMAP_OK;
 }

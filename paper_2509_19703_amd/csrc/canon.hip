@@ -588,7 +588,7 @@ constexpr int kSpinLimit = 1 << 22;
 __global__ void __launch_bounds__(kScanThreads)
 canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restrict__ out_row_ptr,
                   unsigned long long *flags, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ stg,
-                  int32_t *__restrict__ out_col)
+                  int32_t *__restrict__ out_col, int32_t *host_total)
 {
     __shared__ int32_t s_wave[kScanThreads / GM_WAVE];
     __shared__ int64_t s_excl;
@@ -662,7 +662,10 @@ canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restric
     }
     __syncthreads();
     if (s_fail) {
-        if (t == 0) out_row_ptr[n] = -1;
+        if (t == 0) {
+            out_row_ptr[n] = -1;
+            if (host_total) *host_total = -1;
+        }
         return;
     }
     const int off0 = (int)s_excl + before + inc - mine;
@@ -673,7 +676,10 @@ canon_scan_kernel(int32_t n, const int32_t *__restrict__ cnt, int32_t *__restric
         if (r < rows) out_row_ptr[v0 + r] = off;
         off += c[q];
     }
-    if (v0 + rows == n && t == kScanThreads - 1) out_row_ptr[n] = off;
+    if (v0 + rows == n && t == kScanThreads - 1) {
+        out_row_ptr[n] = off;
+        if (host_total) *host_total = off;
+    }
     // The sorted rows sit at their input offsets (kept entries first, also
     // in the staged copy).  A row moves to its output offset when an entry
     // was dropped before it: nothing moves in a tile that starts where its
@@ -864,7 +870,7 @@ size_t canon_scratch_bytes(int32_t n, int32_t nnz)
 
 hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                                const int32_t *col_idx, int32_t *out_row_ptr, int32_t *out_col,
-                               void *scratch, hipStream_t s)
+                               void *scratch, hipStream_t s, int32_t *host_total)
 {
     if (n <= 0) {
         hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, out_row_ptr, (int64_t)1, 0);
@@ -889,7 +895,7 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
     if (e != hipSuccess) return e;
     if (n <= 32 * kRowBitmapWords) {   // the row kernel sorted every row
         hipLaunchKernelGGL(canon_scan_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, (const int32_t *)cnt,
-                           out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col);
+                           out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col, host_total);
         return hipGetLastError();
     }
     const size_t big_lds = (kBigRow + kBigBlock) * sizeof(int32_t);
@@ -907,7 +913,7 @@ hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                        col_idx, out_col, stg, cnt, list_big, n_big, bitmaps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(canon_scan_kernel, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, n, (const int32_t *)cnt,
-                       out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col);
+                       out_row_ptr, flags, row_ptr, (const int32_t *)stg, out_col, host_total);
     return hipGetLastError();
 }
 

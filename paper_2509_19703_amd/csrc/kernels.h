@@ -22,10 +22,12 @@ hipError_t launch_check_symmetric(int32_t n, const int32_t *row_ptr, const int32
 size_t canon_scratch_bytes(int32_t n, int32_t nnz);
 // Canonical CSR (rows sorted, unique, no self-loops) of an arbitrary one.
 // out_row_ptr: n + 1 entries; out_col: nnz entries (capacity).  The number of
-// kept entries ends up in out_row_ptr[n].
+// kept entries ends up in out_row_ptr[n], and also in *host_total when that
+// is given (pinned host memory the kernel stores into; read it once the
+// stream has finished; n > 0).
 hipError_t launch_canonicalize(int32_t n, int32_t nnz, const int32_t *row_ptr,
                                const int32_t *col_idx, int32_t *out_row_ptr, int32_t *out_col,
-                               void *scratch, hipStream_t s);
+                               void *scratch, hipStream_t s, int32_t *host_total = nullptr);
 
 // Exclusive prefix sum of int32 `in` (len values) into `out` (len + 1 values,
 // out[len] = total).  scratch: exclusive_scan_scratch_bytes(len).

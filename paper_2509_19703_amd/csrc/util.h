@@ -27,12 +27,14 @@ hipError_t prepare_sources(const int32_t *src, int64_t rows, int32_t n, int32_t 
 // The same for at most 4,096 rows on at most 131,072 vertices in two launches
 // (a per-vertex pass that also lists the heavy vertices of the level kernel
 // as launch_heavy_list does, then one workgroup ranking the listed vertices
-// with a bit set in LDS); info[1] must be zero.
+// with a bit set in LDS); info[1] must be zero.  With host_info (pinned host
+// memory, 8 ints; rows > 0) the ranking kernel also stores the final
+// info[0..7] there, read once the stream has finished.
 bool sources_ranked_small(int64_t rows, int32_t n);
 hipError_t prepare_sources_small(const int32_t *src, int64_t rows, int32_t n, const int32_t *row_ptr,
                                  int32_t heavy_forced, int32_t *heavy, int32_t *first, int32_t *count,
                                  int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info,
-                                 hipStream_t s);
+                                 hipStream_t s, int32_t *host_info = nullptr);
 // Rows r with first[src[r]] != r copy row first[src[r]] of ids/hops (k wide)
 // and of the hop matrix (n wide, when not NULL).
 hipError_t copy_dup_rows(const int32_t *src, int64_t rows, const int32_t *first, int32_t k, int32_t n, int32_t *ids,

@@ -125,7 +125,8 @@ __device__ __forceinline__ int32_t rank_of(const uint64_t *bits, const int32_t *
 
 __global__ void __launch_bounds__(kRankThreads)
 source_rank_small_k(const int32_t *__restrict__ src, int32_t rows, int32_t n, int32_t *first, int32_t *count,
-                    int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info)
+                    int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info,
+                    int32_t *host_info)
 {
     __shared__ uint64_t bits[kRankWords];
     __shared__ int32_t prefix[kRankWords];
@@ -205,6 +206,17 @@ source_rank_small_k(const int32_t *__restrict__ src, int32_t rows, int32_t n, in
         }
     }
     if (t == 0) info[3] = total;
+    if (host_info) {
+        // the info words are final here (the vertex pass ran before this
+        // launch, this block's atomics before its barriers): publish them to
+        // pinned host memory, so that no copy follows
+        __syncthreads();
+        if (t == 0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                host_info[i] = i == 3 ? total : __hip_atomic_load(&info[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // Rows naming a source listed earlier copy that row's results.
@@ -426,7 +438,7 @@ bool sources_ranked_small(int64_t rows, int32_t n) { return rows <= kRankMax && 
 hipError_t prepare_sources_small(const int32_t *src, int64_t rows, int32_t n, const int32_t *row_ptr,
                                  int32_t heavy_forced, int32_t *heavy, int32_t *first, int32_t *count,
                                  int32_t *usrc, int64_t *slot_row, int32_t *slot_of, int32_t *mult, int32_t *info,
-                                 hipStream_t s)
+                                 hipStream_t s, int32_t *host_info)
 {
     if (!sources_ranked_small(rows, n)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(source_vertex_prep_k, dim3(blocks_for(n)), dim3(256), 0, s, n, row_ptr, heavy_forced, first,
@@ -434,7 +446,7 @@ hipError_t prepare_sources_small(const int32_t *src, int64_t rows, int32_t n, co
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || rows <= 0) return e;
     hipLaunchKernelGGL(source_rank_small_k, dim3(1), dim3(kRankThreads), 0, s, src, (int32_t)rows, n, first, count,
-                       usrc, slot_row, slot_of, mult, info);
+                       usrc, slot_row, slot_of, mult, info, host_info);
     return hipGetLastError();
 }
 
