@@ -453,14 +453,26 @@ __global__ void __launch_bounds__(256) msbfs_first_scatter_kernel(MsbfsArgs a)
     const int32_t e0 = a.row_ptr[v], e1 = a.row_ptr[v + 1];
     unsigned long long *fr = (unsigned long long *)front_of(a, 1) + (size_t)g * a.n * WORDS + w;
     unsigned long long nb = 0, fe = 0;
-    for (int32_t e = e0 + l; e < e1; e += GM_WAVE) {
-        const int32_t u = a.col[e];
-        const unsigned long long old = atomicOr(fr + ((size_t)u << LW), bit);
-        nb += (old & bit) ? 0ull : 1ull;
-        if (old == 0ull) fe += (unsigned long long)(a.row_ptr[u + 1] - a.row_ptr[u]);   // item newly in the frontier
+    if (a.push_levels >= 2) {
+        // level 2 may run top-down: it needs the edges of the items newly in
+        // the frontier, so each OR returns the word it found
+        for (int32_t e = e0 + l; e < e1; e += GM_WAVE) {
+            const int32_t u = a.col[e];
+            const unsigned long long old = atomicOr(fr + ((size_t)u << LW), bit);
+            nb += (old & bit) ? 0ull : 1ull;
+            if (old == 0ull) fe += (unsigned long long)(a.row_ptr[u + 1] - a.row_ptr[u]);   // item newly in the frontier
+        }
+        nb = wave_sum_u64(nb);
+        fe = wave_sum_u64(fe);
+    } else {
+        // the ORs return nothing (no wait per batch of 64 neighbours): on the
+        // canonical CSR each neighbour gets this source's bit exactly once,
+        // so the new bits are the degree
+        for (int32_t e = e0 + l; e < e1; e += GM_WAVE)
+            (void)__hip_atomic_fetch_or(fr + ((size_t)a.col[e] << LW), bit, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        nb = (unsigned long long)(e1 - e0);
     }
-    nb = wave_sum_u64(nb);
-    fe = wave_sum_u64(fe);
     if (l == 0) {
         unsigned long long *st = a.stats + ((size_t)(1 * a.stats_groups + g) * kSpread + (slot & (kSpread - 1))) * kStatFields;
         if (nb) atomicAdd(st + kFieldNewBits, nb);
