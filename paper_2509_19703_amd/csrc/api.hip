@@ -63,6 +63,8 @@ struct DeviceScratch {
     size_t size[kScratchSlots] = {};
     void *host = nullptr;
     size_t host_size = 0;
+    hipStream_t side = nullptr;          // default priority; copies that overlap the caller's kernels
+    hipEvent_t ev_ready = nullptr, ev_copied = nullptr;
 };
 
 DeviceScratch &scratch_of(int dev)
@@ -97,6 +99,35 @@ int scratch_get(int slot, size_t bytes, void **out)
         d.size[slot] = want;
     }
     *out = d.ptr[slot];
+    return GUMAP_OK;
+}
+
+// The current device's side stream and its two events (created on first use).
+int side_stream_get(hipStream_t *side, hipEvent_t *ready, hipEvent_t *copied)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+    DeviceScratch &d = scratch_of(dev);
+    if (!d.side) {
+        hipStream_t st = nullptr;
+        hipEvent_t a = nullptr, b = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (b) (void)hipEventDestroy(b);
+            if (a) (void)hipEventDestroy(a);
+            if (st) (void)hipStreamDestroy(st);
+            return hip_status(e, "side stream");
+        }
+        d.side = st;
+        d.ev_ready = a;
+        d.ev_copied = b;
+    }
+    *side = d.side;
+    *ready = d.ev_ready;
+    *copied = d.ev_copied;
     return GUMAP_OK;
 }
 
@@ -402,6 +433,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
     void *hstats_v = nullptr;
     if ((st = host_scratch_get((size_t)(L_cap + 2) * stats_per_level * 8 + 256, &hstats_v))) return st;
     unsigned long long *hstats = (unsigned long long *)hstats_v;
+    // the level counters are copied back on a side stream, beside the
+    // transpose and selection that follow the levels on `s`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_ready = nullptr, ev_copied = nullptr;
+    if ((st = side_stream_get(&side, &ev_ready, &ev_copied))) return st;
     for (int32_t gs = 0; gs < groups_total; gs += groups_round) {
         MsbfsArgs a;
         a.planes_dev = nullptr;
@@ -638,8 +674,12 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 ran[L] = 1;
                 if (e != hipSuccess) return hip_status(e, "bfs level");
             }
-            e = hipMemcpyAsync(hstats + (size_t)first * spl, stats + (size_t)first * spl,
-                               (size_t)(L - first) * spl * 8, hipMemcpyDeviceToHost, s);
+            e = hipEventRecord(ev_ready, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_ready, 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hstats + (size_t)first * spl, stats + (size_t)first * spl,
+                                   (size_t)(L - first) * spl * 8, hipMemcpyDeviceToHost, side);
+            if (e == hipSuccess) e = hipEventRecord(ev_copied, side);
             bool spec = false;
             a.levels_run = L - 1;
             if (e == hipSuccess && !so) {
@@ -659,6 +699,11 @@ int knn_build(const gumap_graph *g, int32_t k, const int32_t *sources, int32_t n
                 spec = true;
             }
             if (e == hipSuccess) e = hipStreamSynchronize(s);
+            {
+                // always waited for: the copy writes host memory this call owns
+                const hipError_t ec = hipEventSynchronize(ev_copied);
+                if (e == hipSuccess) e = ec;
+            }
             if (e != hipSuccess) return hip_status(e, "bfs stats");
             for (int lv = first; lv < L; ++lv) {
                 prof_set_bytes(marks[lv], level_bytes(lv, false));
