@@ -175,3 +175,14 @@ def test_neighborhood_ba100k_sampled(gumap):
     verts = G.config_ba_sources()[::16].copy()
     print("ba100k neighborhood", len(verts), flush=True)
     _np_check(gumap, g, _layout(g.n, 91, scale=100.0), vertices=verts)
+
+
+def test_stress_in_rounds(gumap, monkeypatch):
+    """A BFS memory budget below one source group's state makes every group a
+    round of its own; the stress sums of all rounds equal the oracle's."""
+    monkeypatch.setenv("GUMAP_BFS_BUDGET_MB", "1")
+    monkeypatch.setenv("GUMAP_FUSED", "0")
+    for g, words, src in ((G.ba(3001, 4, 61), 8, None), (G.rgg(2500, 8, 62), 2, G.sample_sources(2500, 700, 63))):
+        monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+        print("stress in rounds", g.n, words, flush=True)
+        _check(gumap, g, _layout(g.n, 64), sources=src)

@@ -256,6 +256,21 @@ def test_canonicalize_degenerate(gumap):
         assert np.array_equal(out_col.cpu().numpy(), want_col)
 
 
+def test_build_in_rounds(gumap, monkeypatch):
+    """A BFS memory budget below one source group's state makes every group a
+    round of its own: each round reuses the search state, the level counters
+    (copied back beside the transpose) and the hop-count buffers.  Rows, hops
+    and hop matrices equal the oracle's for all and for listed sources, at
+    several bitset widths and depths."""
+    monkeypatch.setenv("GUMAP_BFS_BUDGET_MB", "1")
+    monkeypatch.setenv("GUMAP_FUSED", "0")
+    for g, words in ((G.ba(3001, 4, 31), 8), (G.rgg(2000, 8, 32), 2), (G.path(200), 1)):
+        monkeypatch.setenv("GUMAP_FORCE_WORDS", str(words))
+        print("rounds", g.n, words, flush=True)
+        _check_build(gumap, g, 15, hop_matrix=True)
+        _check_build(gumap, g, 6, sources=G.sample_sources(g.n, 700, 33), hop_matrix=False)
+
+
 def test_hop_range_error(gumap):
     import torch
     g = G.path(300)
