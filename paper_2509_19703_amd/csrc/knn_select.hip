@@ -428,13 +428,15 @@ hipError_t launch_knn_select_counted(int32_t n, int32_t k, int32_t rows, const u
                            src_of, ids, hops);
     } else {
         const size_t lds = ((size_t)(k + 1) * GM_WAVE + 256) * sizeof(unsigned int);
-        static bool lds_set = false;
-        if (!lds_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)knn_select_hist_kernel,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(((size_t)(kMaxK + 1) * GM_WAVE + 256) * sizeof(unsigned int)));
+        static bool lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= 64 || !lds_set[dev]) {
+            e = hipFuncSetAttribute((const void *)knn_select_hist_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(((size_t)(kMaxK + 1) * GM_WAVE + 256) * sizeof(unsigned int)));
             if (e != hipSuccess) return e;
-            lds_set = true;
+            if (dev >= 0 && dev < 64) lds_set[dev] = true;
         }
         const int blocks = rows > 65536 ? 65536 : rows;
         hipLaunchKernelGGL(knn_select_hist_kernel, dim3(blocks), dim3(GM_WAVE), lds, s, n, k, rows, hop_rows,
