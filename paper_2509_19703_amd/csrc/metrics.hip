@@ -252,16 +252,17 @@ hipError_t launch_neighborhood(int32_t n, const int32_t *row_ptr, const int32_t 
 {
     if (n_verts <= 0) return hipSuccess;
     const size_t lds = neighborhood_lds_bytes(n);
-    static size_t lds_set = 0;
-    if (lds > 48 * 1024 && lds > lds_set) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    static size_t lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (lds > 48 * 1024 && lds > lds_set[dev]) {
         hipError_t e = hipFuncSetAttribute((const void *)neighborhood_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        lds_set = lds;
+        lds_set[dev] = lds;
     }
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
         (void)hipGetLastError();
         cus = 256;
     }

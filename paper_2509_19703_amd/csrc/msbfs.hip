@@ -1317,12 +1317,15 @@ hipError_t launch_msbfs_fused(const MsbfsArgs &a, int L_cap, bool full_hops, int
 {
     if (a.words != 1 || a.groups <= 0) return hipErrorInvalidValue;
     const size_t lds = msbfs_fused_lds_bytes(a.n);
-    static size_t lds_set = 0;
-    if (lds > 48 * 1024 && lds > lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)msbfs_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static size_t lds_set[64] = {};   // the LDS limit is an attribute of the kernel on each device
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (lds > 48 * 1024 && lds > lds_set[dev]) {
+        e = hipFuncSetAttribute((const void *)msbfs_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        lds_set = lds;
+        lds_set[dev] = lds;
     }
     hipLaunchKernelGGL(msbfs_fused_kernel, dim3(a.groups), dim3(kFusedBlock), lds, s, a, L_cap, full_hops ? 1 : 0,
                        group_out);
