@@ -1054,7 +1054,7 @@ __device__ __forceinline__ void hops_staged_body(const MsbfsArgs &a, int planes_
     // is the row's own source or one of the four planes holds it: the visited
     // word is then rebuilt after the transpose instead of loaded and
     // transposed (the source's vertex is read once per lane).
-    constexpr bool kPlanesGiveVis = PL <= 4 && !STRESS;
+    constexpr bool kPlanesGiveVis = PL <= 4;
     const bool derive_vis = kPlanesGiveVis && a.hist_levels > 0;
     const int32_t self_v = (derive_vis && slot_ok) ? a.usrc[a.slot0 + local_slot] : -1;
     auto load_tiles = [&](int32_t tile) {
